@@ -1,0 +1,202 @@
+"""Benchmark: complex TFLOP/s of path execution on one MI355X.
+
+Workload (default): single large pairwise contractions, complex64, all mode
+extents 2, i.i.d. complex Gaussian entries --
+  * A with 30 modes x B with 28 modes, 14 shared (output 2^30 entries), both
+    stored in seeded random mode orders so that the operand permutations
+    precede the GEMM (m = 2^16, n = 2^14, k = 2^14);
+  * a batch of 64 contractions with 20 / 18 modes, 10 shared
+    (h = 64, m = 2^10, n = 2^8, k = 2^10).
+One step = one execution of both paths (all operand permutations, the
+batched complex GEMMs on MFMA, results written to HBM).  Inputs are resident
+in HBM before timing starts.  FLOPs follow the paper's convention of 8 real
+FLOPs per complex multiply-add.
+
+Prints one JSON line.  ``roofline`` is for the dominant kernel (the large
+GEMM), its launch time measured with HIP events on its own stream over the
+timed steps; ``cpu_baseline`` times the FP64 oracle on a bounded sample of
+the same workload on this host's cores.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+PEAK_FP32_MFMA = 157.3   # TFLOP/s, MI355X dense FP32 matrix
+PEAK_BF16_MFMA = 2516.6  # TFLOP/s, MI355X dense bf16 matrix
+PEAK_HBM = 8000.0        # GB/s
+
+# HBM traffic per launch of the dominant kernel, from rocprofv3 --pmc
+# FETCH_SIZE / WRITE_SIZE (KiB per dispatch) scaled by the same counters on
+# a copy kernel of known size; None until measured for the current kernel.
+GEMM_TRAFFIC_BYTES = None
+
+
+def log(msg: str) -> None:
+    print(msg, file=sys.stderr, flush=True)
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--form", choices=["4M", "3M"], default="4M")
+    ap.add_argument("--prec", choices=["c64", "bf16x3"], default="c64")
+    ap.add_argument("--scale", type=int, default=0, help="drop this many modes from each group (smaller run)")
+    ap.add_argument("--no-cpu", action="store_true")
+    return ap.parse_args()
+
+
+def cpu_baseline(net_a, path_a, net_b, path_b, budget_s: float = 20.0):
+    """The oracle (complex128 numpy) on a bounded sample: the big contraction
+    with its 8 leading M labels fixed to one value (1/256 of the rows) and 4
+    of the 64 batch entries.  Rate = sample FLOPs (8 per complex MAC) / time."""
+    from threadpoolctl import threadpool_info
+
+    from oracle import contract as oc
+    from workloads.network import Network, Path
+
+    t_total, flops_total = 0.0, 0.0
+    # big pair: fix M labels 0..7 (open labels; taken as a sub-network)
+    a, b = net_a.leaves
+    la, lb = net_a.labels
+    fix = {l: 0 for l in range(8)}
+    idx = tuple(0 if l in fix else slice(None) for l in la)
+    sub_a = np.ascontiguousarray(a[idx])
+    sub_la = tuple(l for l in la if l not in fix)
+    sub = Network([sub_a, b], [sub_la, lb], net_a.extents, tuple(l for l in net_a.open if l not in fix))
+    t0 = time.perf_counter()
+    oc.contract(sub, Path(path_a.pairs, ()))
+    dt = time.perf_counter() - t0
+    m_sub = int(np.prod([net_a.extents[l] for l in sub_la])) // (2 ** 14)
+    t_total += dt
+    flops_total += 8.0 * m_sub * 2 ** 14 * 2 ** 14
+    # batch pair: 4 of the 64 entries
+    a2, b2 = net_b.leaves
+    sub2 = Network([a2[:4], b2[:4]], net_b.labels, net_b.extents.copy(), net_b.open)
+    sub2.extents[net_b.open[0]] = 4
+    t0 = time.perf_counter()
+    oc.contract(sub2, path_b)
+    dt2 = time.perf_counter() - t0
+    t_total += dt2
+    flops_total += 8.0 * 4 * 1024 * 256 * 1024
+    threads = max((i.get("num_threads", 1) for i in threadpool_info()), default=1)
+    return {"value": flops_total / t_total / 1e12, "unit": "complex TFLOP/s", "cores": int(threads),
+            "kind": "oracle",
+            "sample": f"pair30 rows with 8 leading M labels fixed (1/256 of the work, {dt:.1f} s) + 4 of 64 "
+                      f"batch entries ({dt2:.1f} s); numpy complex128 tensordot incl. operand transposes"}
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(json.dumps({"error": "this build runs on one GPU; multi-GPU execution is not part of it",
+                          "n_gpus": args.gpus}))
+        sys.exit(2)
+    import torch
+
+    from paper_2606_01852_amd import tnc
+    from workloads import configs
+
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    dev = torch.device("cuda:0")
+    log("generating inputs")
+    t0 = time.time()
+    net_a, path_a = configs.pair30(scale=args.scale)
+    net_b, path_b = configs.pair_batch(64, scale=args.scale)
+    log(f"inputs ready in {time.time() - t0:.1f} s")
+    stream = torch.cuda.current_stream()
+    prec = tnc.PREC_BF16X3 if args.prec == "bf16x3" else tnc.PREC_C64
+    form = tnc.GEMM_3M if args.form == "3M" else tnc.GEMM_4M
+
+    # plan on the host first to size the arena
+    hctx = tnc.Context(-1)
+    sizes = []
+    for net, path in ((net_a, path_a), (net_b, path_b)):
+        tn = tnc.Network(hctx, net.labels, net.extents, net.open)
+        p = tnc.Plan(tn, path.pairs, (), prec, form)
+        sizes.append(p.info.peak_bytes)
+        p.close()
+        tn.close()
+    arena_bytes = max(sizes) + (64 << 20)
+    arena = torch.empty(arena_bytes, dtype=torch.uint8, device=dev)
+    ctx = tnc.Context(0, arena_bytes=arena_bytes, arena_ptr=arena.data_ptr(), stream=stream.cuda_stream)
+    log("uploading leaves")
+    tn_a = tnc.Network(ctx, net_a.labels, net_a.extents, net_a.open, net_a.leaves)
+    tn_b = tnc.Network(ctx, net_b.labels, net_b.extents, net_b.open, net_b.leaves)
+    plan_a = tnc.Plan(tn_a, path_a.pairs, (), prec, form)
+    plan_b = tnc.Plan(tn_b, path_b.pairs, (), prec, form)
+    out_a = torch.empty(plan_a.info.n_result, dtype=torch.complex64, device=dev)
+    out_b = torch.empty(plan_b.info.n_result, dtype=torch.complex64, device=dev)
+    flops_step = plan_a.info.flops_per_slice + plan_b.info.flops_per_slice
+
+    def step():
+        tnc.tnc_contract_async(plan_a.handle, 0, 1, out_a.data_ptr(), tnc.OUT_C64)
+        tnc.tnc_contract_async(plan_b.handle, 0, 1, out_b.data_ptr(), tnc.OUT_C64)
+
+    log("warmup")
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    tnc.tnc_plan_set_profile(plan_a.handle, True)
+    tnc.tnc_plan_set_profile(plan_b.handle, True)
+    log("timing")
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        step()
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    gemm_ms, gemm_n = tnc.tnc_plan_get_profile(plan_a.handle, 0)
+    perm_ms, perm_n = tnc.tnc_plan_get_profile(plan_a.handle, -1)
+    bgemm_ms, bgemm_n = tnc.tnc_plan_get_profile(plan_b.handle, 0)
+    bperm_ms, bperm_n = tnc.tnc_plan_get_profile(plan_b.handle, -1)
+    gemm_avg_s = gemm_ms / max(gemm_n, 1) / 1e3
+    achieved = plan_a.info.flops_per_slice / gemm_avg_s / 1e12
+    peak = PEAK_BF16_MFMA / 3 if prec == tnc.PREC_BF16X3 else PEAK_FP32_MFMA
+    value = flops_step * args.steps / dt / 1e12
+    perm_bytes = plan_a.info.transpose_bytes
+    perm_gbs = perm_bytes / (perm_ms / max(perm_n, 1) * 2 / 1e3) / 1e9 if perm_n else None
+    log(f"step {dt / args.steps * 1e3:.1f} ms; big GEMM {gemm_avg_s * 1e3:.1f} ms = {achieved:.1f} TF; "
+        f"permutes {perm_ms / max(perm_n, 1):.2f} ms/launch ({perm_gbs} GB/s avg over A,B); "
+        f"batch GEMM {bgemm_ms / max(bgemm_n, 1):.3f} ms, batch permutes {bperm_ms / max(bperm_n, 1):.3f} ms")
+    res = {
+        "metric": "complex TFLOP/s of path execution (% MFMA peak) + p50/p99 request latency",
+        "value": round(value, 3),
+        "unit": "complex TFLOP/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(dt / args.steps * 1e3, 3),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "c64/fp32" if prec == tnc.PREC_C64 else "c64/bf16x3",
+        "data": "synthetic",
+        "config": {"workload": "pair30+pair_batch64: A 30 modes x B 28 modes (14 shared, 2^30 outputs) and "
+                               "64 x (20 x 18 modes, 10 shared); extents 2; random stored mode orders",
+                   "form": args.form, "prec": args.prec, "scale": args.scale,
+                   "pct_fp32_mfma_peak": round(100 * value / PEAK_FP32_MFMA, 1)},
+        "roofline": {"bound": "mfma", "achieved": round(achieved, 3), "peak": round(peak, 1),
+                     "unit": "TFLOP/s", "frac": round(achieved / peak, 4), "traffic": GEMM_TRAFFIC_BYTES},
+        "kernels": {"gemm_ms": round(gemm_avg_s * 1e3, 3),
+                    "permute_ms_per_launch": round(perm_ms / max(perm_n, 1), 3),
+                    "batch_gemm_ms": round(bgemm_ms / max(bgemm_n, 1), 3)},
+    }
+    if not args.no_cpu:
+        log("cpu baseline (oracle on a bounded sample)")
+        res["cpu_baseline"] = cpu_baseline(net_a, path_a, net_b, path_b)
+    print(json.dumps(res), flush=True)
+
+
+if __name__ == "__main__":
+    main()

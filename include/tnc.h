@@ -1,0 +1,223 @@
+/*
+ * tnc.h -- C ABI of the MI355X (gfx950) tensor-network path executor.
+ *
+ * The library executes a fixed pairwise contraction path over a complex
+ * tensor network on one GPU (arXiv 2606.01852, Sec. IV: "the input is a
+ * contraction-path descriptor ... initial tensors, the pairwise contraction
+ * sequence, and any slicing metadata").  Every step is put into GEMM form by
+ * the GEMM-oriented mode reordering of Sec. IV-A and runs as a batched
+ * complex GEMM on MFMA; operands whose stored order differs from the order
+ * the step needs are permuted by an LDS-tiled transpose.
+ *
+ * Conventions shared by every call
+ *   - Tensors are row-major, mode 0 outermost (Sec. IV-B: leading modes are
+ *     the outermost memory dimensions).  Complex values are interleaved
+ *     (re, im): complex64 = 2 x float32, complex128 = 2 x float64.
+ *   - A label is a non-negative int32 below n_labels; extent_of_label[l] >= 1.
+ *     A closed label joins exactly two tensors and is summed (Sec. II-A); an
+ *     open label survives into the result, in the order of open_labels.  An
+ *     open label carried by two or more tensors is a batch label: kept, not
+ *     summed, wherever two operands share it.  A closed label held by one
+ *     tensor or by three or more is rejected (TNC_E_ARG).
+ *   - Path: SSA pairs.  Ids below n_tensors are the leaves; step s creates id
+ *     n_tensors + s.  Every id is consumed exactly once and the last step
+ *     yields the root (TNC_E_PATH otherwise).  A one-leaf network has no steps.
+ *   - Slicing (Sec. II-C): sliced labels must be closed.  Slice s fixes them
+ *     to the digits of s, row-major over sliced_labels (first most
+ *     significant); a result is the sum over the requested slices.
+ *   - Errors: every call returns a tnc_status; nothing throws or aborts
+ *     across the ABI.  On error, outputs are left untouched and
+ *     tnc_last_error() (thread-local) says why.  Asynchronous device faults
+ *     surface as TNC_E_DEVICE at the next synchronising call.
+ *   - Threads: tnc_submit / tnc_poll / tnc_wait are thread-safe; every other
+ *     call is single-threaded per context.
+ *   - "Device pointer" means memory on the context's GPU (e.g. a torch CUDA
+ *     tensor's data_ptr()); "host pointer" means ordinary host memory.
+ */
+#ifndef TNC_H
+#define TNC_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  TNC_OK = 0,
+  TNC_E_ARG = 1,          /* malformed argument or network            */
+  TNC_E_PATH = 2,         /* path is not a full binary tree            */
+  TNC_E_NOMEM = 3,        /* planned peak exceeds the arena            */
+  TNC_E_DEVICE = 4,       /* HIP runtime or kernel error               */
+  TNC_E_BUSY = 5,         /* serving queue full                        */
+  TNC_E_UNSUPPORTED = 6   /* request needs something not built here    */
+} tnc_status;
+
+/* Arithmetic of the GEMMs.  C64: complex64 operands, FP32 MFMA, FP32
+ * accumulate (the paper's setting, Sec. V).  BF16X3: each float32 operand
+ * plane is split into bf16 hi + lo (round to nearest even) and every real
+ * product is a_hi*b_hi + a_hi*b_lo + a_lo*b_hi on bf16 MFMA with FP32
+ * accumulate (an extension, not in the paper). */
+typedef enum { TNC_PREC_C64 = 0, TNC_PREC_BF16X3 = 1 } tnc_prec;
+
+/* Complex-GEMM form.  4M: four real products (re = ar*br - ai*bi,
+ * im = ar*bi + ai*br), 8 real FLOPs per complex MAC.  3M: three real
+ * products (T1 = ar*br, T2 = ai*bi, T3 = (ar+ai)(br+bi); re = T1 - T2,
+ * im = T3 - T1 - T2), 6 executed FLOPs per complex MAC. */
+typedef enum { TNC_GEMM_4M = 0, TNC_GEMM_3M = 1 } tnc_cgemm;
+
+/* Element type of host leaf data handed to the library. */
+typedef enum { TNC_IN_C64 = 0, TNC_IN_C128 = 1 } tnc_in;
+
+typedef struct tnc_ctx_s* tnc_ctx;
+typedef struct tnc_net_s* tnc_net;
+typedef struct tnc_plan_s* tnc_plan;
+typedef uint64_t tnc_req;
+
+/* Last error message of the calling thread ("" if none).  Owned by the
+ * library; valid until the thread's next tnc_* call. */
+const char* tnc_last_error(void);
+
+/* Library version string (static storage). */
+const char* tnc_version(void);
+
+/* ---------------------------------------------------------------- context
+ * device      : HIP device ordinal, or -1 for a host-only context that can
+ *               validate networks and build plans but runs nothing.
+ * arena       : device pointer to caller-owned scratch for intermediates,
+ *               or NULL to let the library allocate arena_bytes itself.
+ * arena_bytes : arena size; all intermediates of a contraction live in it
+ *               (plans whose planned peak exceeds it fail with TNC_E_NOMEM).
+ * stream      : hipStream_t to launch on, or NULL for a library-owned
+ *               stream.  Caller-owned arena/stream must outlive the context. */
+tnc_status tnc_ctx_create(int device, void* arena, size_t arena_bytes, void* stream, tnc_ctx* out);
+tnc_status tnc_ctx_destroy(tnc_ctx ctx);
+/* Number of HIP devices visible (0 when none); never fails. */
+int tnc_device_count(void);
+
+/* ---------------------------------------------------------------- network
+ * ranks[n_tensors]; labels = concatenated mode labels of every tensor in its
+ * stored order; extent_of_label[n_labels]; open_labels[n_open] = result mode
+ * order.  host_data[t] = host pointer to tensor t (row-major, stored order,
+ * element type `in`); the library copies every leaf to device memory it owns
+ * (complex64), where it stays resident until tnc_net_destroy.  host_data may
+ * be NULL on a host-only context (structure only).  All checks of Sec. II-A
+ * happen here, on the host, before any device work. */
+tnc_status tnc_net_create(tnc_ctx ctx, int32_t n_tensors, const int32_t* ranks,
+                          const int32_t* labels, int32_t n_labels,
+                          const int64_t* extent_of_label, int32_t n_open,
+                          const int32_t* open_labels, const void* const* host_data,
+                          tnc_in in, tnc_net* out);
+/* Replace leaf `tensor`'s values (same shape), e.g. a new bitstring's
+ * projectors.  Synchronous host-to-device copy. */
+tnc_status tnc_net_set_tensor(tnc_net net, int32_t tensor, const void* host_data, tnc_in in);
+/* Replace leaf `tensor`'s values from a device pointer (complex64, stored
+ * order).  Device-to-device copy on the context's stream. */
+tnc_status tnc_net_set_tensor_device(tnc_net net, int32_t tensor, const void* dev_data);
+tnc_status tnc_net_destroy(tnc_net net);
+
+/* ---------------------------------------------------------------- plan
+ * Builds the execution plan of a path (Sec. IV-A reordering, per-step GEMM
+ * groups, permutations, memory plan).  ssa_pairs[2*n_steps].  A plan borrows
+ * its network: destroy plans first. */
+tnc_status tnc_plan_create(tnc_net net, int32_t n_steps, const int32_t* ssa_pairs,
+                           int32_t n_sliced, const int32_t* sliced_labels,
+                           tnc_prec prec, tnc_cgemm cgemm, tnc_plan* out);
+tnc_status tnc_plan_destroy(tnc_plan plan);
+
+typedef struct {
+  double flops_per_slice;        /* 8 * sum_a h m n k (Sec. II-B convention)   */
+  double bytes_per_slice;        /* 8 * sum_a C_m^(a): operands + result bytes */
+  double transpose_bytes;        /* 16 * elements permuted per slice           */
+  int64_t n_slices;              /* product of the sliced extents              */
+  int64_t max_intermediate;      /* C_s: largest tensor, elements, one slice   */
+  int64_t peak_bytes;            /* arena bytes of one slice                   */
+  int64_t max_chunk;             /* slices executed together (batch)           */
+  int64_t chunk_peak_bytes;      /* arena bytes of a max_chunk batch           */
+  int32_t n_steps;
+  int32_t n_permutes;            /* leaves permuted before use                 */
+  int32_t n_permuted_stores;     /* steps whose output order interleaves M, N  */
+  int32_t n_result;              /* elements of the result tensor              */
+} tnc_plan_info;
+tnc_status tnc_plan_get_info(tnc_plan plan, tnc_plan_info* out);
+
+/* Per-step view of the plan for one slice (chunk of 1).  A, B, C are tensor
+ * ids (A is the GEMM's M side); h, m, n, k are the products of the extents
+ * of the H (batch), M, N, K groups; natural = 1 if C is stored [H|M|N]. */
+typedef struct {
+  int32_t A, B, C;
+  int32_t nH, nM, nN, nK;
+  int64_t h, m, n, k;
+  int32_t natural;
+  int32_t kernel;                /* 0 = MFMA tiles, 1 = small-shape VALU kernel */
+} tnc_step_info;
+tnc_status tnc_plan_get_step(tnc_plan plan, int32_t step, tnc_step_info* out);
+/* Mode order (labels) tensor `id` is stored in when the plan runs one slice:
+ * the target order of the Sec. IV-A backward pass.  Writes min(cap, rank)
+ * labels, sets *rank. */
+tnc_status tnc_plan_get_order(tnc_plan plan, int32_t id, int32_t* labels, int32_t cap, int32_t* rank);
+
+/* Upper bound on slices per device batch (default: as many as fit the arena). */
+tnc_status tnc_plan_set_max_chunk(tnc_plan plan, int64_t max_chunk);
+/* 1 = capture each chunk's launches in a hipGraph and replay it. */
+tnc_status tnc_plan_set_graph(tnc_plan plan, int32_t enable);
+/* 1 = time every kernel with HIP events on the launch stream. */
+tnc_status tnc_plan_set_profile(tnc_plan plan, int32_t enable);
+/* Per-step accumulated kernel time (ms) and launch count since profiling was
+ * enabled; step = -1 gives the leaf permutations, -2 the FP64 reductions. */
+tnc_status tnc_plan_get_profile(tnc_plan plan, int32_t step, double* ms, int64_t* launches);
+
+/* ---------------------------------------------------------------- contract
+ * Sum over slices [first_slice, first_slice + n_slices) of the sliced
+ * contractions, accumulated in FP64 on the device; out_c128 (host pointer,
+ * n_result complex128 values, open-label order) receives the result.  A
+ * closed network (n_open = 0) yields one amplitude.  Synchronous. */
+tnc_status tnc_contract(tnc_plan plan, int64_t first_slice, int64_t n_slices, double* out_c128);
+/* Same, but leaves the result on the device and does not synchronise.
+ * out_dev: n_result elements of complex128 (TNC_OUT_C128) or complex64
+ * (TNC_OUT_C64).  A single-slice complex64 request whose root order equals
+ * the open-label order is written by the last GEMM directly (no FP64 pass);
+ * otherwise the FP64 sum is rounded to complex64 at the end. */
+typedef enum { TNC_OUT_C128 = 0, TNC_OUT_C64 = 1 } tnc_out;
+tnc_status tnc_contract_async(tnc_plan plan, int64_t first_slice, int64_t n_slices, void* out_dev,
+                              tnc_out out_type);
+/* Sum of |R|^2 over the last result of this plan, in FP64 on the device. */
+tnc_status tnc_plan_result_norm2(tnc_plan plan, double* out);
+
+/* ---------------------------------------------------------------- kernels
+ * Operand permutation (a bit copy): out[pi(idx)] = in[idx] for a complex64
+ * tensor of `rank` modes with extents in[rank] (input order); perm[j] = the
+ * input mode that becomes output mode j.  in/out: device pointers, must not
+ * overlap.  Asynchronous on the context's stream. */
+tnc_status tnc_permute(tnc_ctx ctx, const void* in, void* out, int32_t rank,
+                       const int64_t* extents, const int32_t* perm);
+/* Batched complex GEMM with both operands K-contiguous:
+ *   C[b, i, j] = sum_l A[b, i, l] * B[b, j, l]     (no conjugation)
+ * A: h*m*k, B: h*n*k, C: h*m*n complex64 (device pointers, contiguous; a
+ * batch stride of 0 for A or B broadcasts it).  Asynchronous. */
+tnc_status tnc_batched_cgemm(tnc_ctx ctx, int64_t h, int64_t m, int64_t n, int64_t k,
+                             const void* A, int64_t stride_a, const void* B, int64_t stride_b,
+                             void* C, tnc_prec prec, tnc_cgemm form);
+/* Synchronise the context's stream; TNC_E_DEVICE if a kernel failed. */
+tnc_status tnc_ctx_sync(tnc_ctx ctx);
+
+/* ---------------------------------------------------------------- serving
+ * Continuous batching: requests are admitted while others run, as soon as a
+ * slot and enough arena for the plan's planned peak are free; admitted
+ * requests run concurrently on separate streams.  out_c128 (host pointer)
+ * must stay valid until the request is done.  TNC_E_BUSY if the queue is
+ * full; TNC_E_NOMEM if the request can never fit. */
+tnc_status tnc_serve_start(tnc_ctx ctx, int32_t max_inflight, int32_t queue_cap);
+tnc_status tnc_serve_stop(tnc_ctx ctx);
+tnc_status tnc_submit(tnc_ctx ctx, tnc_plan plan, int64_t first_slice, int64_t n_slices,
+                      double* out_c128, tnc_req* id);
+/* done = 1 when finished; latency_s = submit-to-done wall time (else 0);
+ * status of the request's execution is returned once done. */
+tnc_status tnc_poll(tnc_ctx ctx, tnc_req id, int32_t* done, double* latency_s);
+tnc_status tnc_wait(tnc_ctx ctx, tnc_req id, double* latency_s);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* TNC_H */

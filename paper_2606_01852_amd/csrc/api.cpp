@@ -1,0 +1,607 @@
+// C ABI of the path executor.  Every entry point converts internal errors
+// into a status code and a thread-local message; nothing throws across it.
+#include <algorithm>
+#include <chrono>
+#include <cstring>
+#include <new>
+
+#include "core.hpp"
+#include "serve.hpp"
+
+namespace tnc {
+
+void fail(tnc_status code, const std::string& msg) { throw Error{code, msg}; }
+
+void check_hip(hipError_t e, const char* what) {
+  if (e != hipSuccess) fail(TNC_E_DEVICE, std::string(what) + ": " + hipGetErrorString(e));
+}
+
+DeviceBuf::~DeviceBuf() { reset(); }
+
+void DeviceBuf::alloc(size_t n) {
+  reset();
+  if (n == 0) return;
+  void* p = nullptr;
+  const hipError_t e = hipMalloc(&p, n);
+  if (e != hipSuccess) {
+    (void)hipGetLastError();
+    fail(e == hipErrorOutOfMemory ? TNC_E_NOMEM : TNC_E_DEVICE,
+         "hipMalloc of " + std::to_string(n) + " bytes: " + hipGetErrorString(e));
+  }
+  ptr = p;
+  bytes = n;
+}
+
+void DeviceBuf::reset() {
+  if (ptr) (void)hipFree(ptr);
+  ptr = nullptr;
+  bytes = 0;
+}
+
+Ctx::~Ctx() {
+  server.reset();
+  if (!host_only) {
+    (void)hipSetDevice(device);
+    if (stream) (void)hipStreamSynchronize(stream);
+    scratch.reset();
+    if (own_arena && arena) (void)hipFree(arena);
+    if (own_stream && stream) (void)hipStreamDestroy(stream);
+  }
+}
+
+void set_device(const Ctx& c) {
+  if (c.host_only) fail(TNC_E_UNSUPPORTED, "host-only context cannot run device work");
+  check_hip(hipSetDevice(c.device), "hipSetDevice");
+}
+
+}  // namespace tnc
+
+using namespace tnc;
+
+#define TNC_TRY            \
+  tnc::g_error_clear();    \
+  try {
+#define TNC_CATCH                                   \
+  }                                                 \
+  catch (const tnc::Error& e) {                     \
+    tnc::g_error_set(e.msg);                        \
+    return e.code;                                  \
+  }                                                 \
+  catch (const std::bad_alloc&) {                   \
+    tnc::g_error_set("host allocation failed");     \
+    return TNC_E_NOMEM;                             \
+  }                                                 \
+  catch (const std::exception& e) {                 \
+    tnc::g_error_set(e.what());                     \
+    return TNC_E_ARG;                               \
+  }                                                 \
+  return TNC_OK;
+
+namespace tnc {
+namespace {
+thread_local std::string g_msg;
+}
+void g_error_clear() { g_msg.clear(); }
+void g_error_set(const std::string& m) { g_msg = m; }
+const char* g_error_get() { return g_msg.c_str(); }
+}  // namespace tnc
+
+extern "C" {
+
+const char* tnc_last_error(void) { return tnc::g_error_get(); }
+
+const char* tnc_version(void) { return "tnc 0.1 (gfx950)"; }
+
+int tnc_device_count(void) {
+  int n = 0;
+  if (hipGetDeviceCount(&n) != hipSuccess) {
+    (void)hipGetLastError();
+    return 0;
+  }
+  return n;
+}
+
+tnc_status tnc_ctx_create(int device, void* arena, size_t arena_bytes, void* stream, tnc_ctx* out) {
+  TNC_TRY
+  if (!out) fail(TNC_E_ARG, "out is NULL");
+  auto h = std::make_unique<tnc_ctx_s>();
+  Ctx& c = h->c;
+  c.device = device;
+  c.host_only = device < 0;
+  c.arena_bytes = arena_bytes;
+  if (!c.host_only) {
+    const int nd = tnc_device_count();
+    if (device >= nd) fail(TNC_E_DEVICE, "device " + std::to_string(device) + " not present");
+    check_hip(hipSetDevice(device), "hipSetDevice");
+    if (arena) {
+      c.arena = static_cast<char*>(arena);
+    } else if (arena_bytes) {
+      void* p = nullptr;
+      const hipError_t e = hipMalloc(&p, arena_bytes);
+      if (e != hipSuccess) {
+        (void)hipGetLastError();
+        fail(TNC_E_NOMEM, "arena hipMalloc failed: " + std::string(hipGetErrorString(e)));
+      }
+      c.arena = static_cast<char*>(p);
+      c.own_arena = true;
+    }
+    if (stream) {
+      c.stream = static_cast<hipStream_t>(stream);
+    } else {
+      check_hip(hipStreamCreate(&c.stream), "hipStreamCreate");
+      c.own_stream = true;
+    }
+  } else if (arena) {
+    fail(TNC_E_ARG, "a host-only context takes no arena");
+  }
+  *out = h.release();
+  TNC_CATCH
+}
+
+tnc_status tnc_ctx_destroy(tnc_ctx ctx) {
+  TNC_TRY
+  delete ctx;
+  TNC_CATCH
+}
+
+tnc_status tnc_ctx_sync(tnc_ctx ctx) {
+  TNC_TRY
+  if (!ctx) fail(TNC_E_ARG, "ctx is NULL");
+  set_device(ctx->c);
+  check_hip(hipStreamSynchronize(ctx->c.stream), "stream synchronize");
+  TNC_CATCH
+}
+
+static void upload_leaf(Net& net, int t, const void* host, tnc_in in) {
+  DeviceBuf& d = net.leaf[t];
+  const int64_t n = net.numel[t];
+  if (!d.ptr) d.alloc(static_cast<size_t>(n) * 8);
+  if (in == TNC_IN_C64) {
+    check_hip(hipMemcpy(d.ptr, host, n * 8, hipMemcpyHostToDevice), "leaf upload");
+  } else if (in == TNC_IN_C128) {
+    const double* src = static_cast<const double*>(host);
+    std::vector<float> tmp(static_cast<size_t>(2 * n));
+    for (int64_t i = 0; i < 2 * n; ++i) tmp[i] = static_cast<float>(src[i]);
+    check_hip(hipMemcpy(d.ptr, tmp.data(), n * 8, hipMemcpyHostToDevice), "leaf upload");
+  } else {
+    fail(TNC_E_ARG, "unknown input element type");
+  }
+}
+
+tnc_status tnc_net_create(tnc_ctx ctx, int32_t n_tensors, const int32_t* ranks, const int32_t* labels,
+                          int32_t n_labels, const int64_t* extent_of_label, int32_t n_open,
+                          const int32_t* open_labels, const void* const* host_data, tnc_in in, tnc_net* out) {
+  TNC_TRY
+  if (!ctx || !out) fail(TNC_E_ARG, "ctx/out is NULL");
+  if (n_tensors < 1 || !ranks || n_labels < 0 || (n_labels && !extent_of_label) || n_open < 0 ||
+      (n_open && !open_labels))
+    fail(TNC_E_ARG, "bad network arguments");
+  auto h = std::make_unique<tnc_net_s>();
+  Net& net = h->n;
+  net.ctx = &ctx->c;
+  net.n_tensors = n_tensors;
+  net.labels.resize(n_tensors);
+  int64_t pos = 0;
+  for (int t = 0; t < n_tensors; ++t) {
+    if (ranks[t] < 0) fail(TNC_E_ARG, "negative rank");
+    if (ranks[t] && !labels) fail(TNC_E_ARG, "labels is NULL");
+    net.labels[t].assign(labels + pos, labels + pos + ranks[t]);
+    pos += ranks[t];
+  }
+  net.extents.assign(extent_of_label, extent_of_label + n_labels);
+  net.open.assign(open_labels, open_labels + n_open);
+  validate_net(net);
+  net.leaf.resize(n_tensors);
+  if (!ctx->c.host_only) {
+    if (!host_data) fail(TNC_E_ARG, "host_data is NULL");
+    set_device(ctx->c);
+    for (int t = 0; t < n_tensors; ++t) {
+      if (!host_data[t]) fail(TNC_E_ARG, "host_data[" + std::to_string(t) + "] is NULL");
+      upload_leaf(net, t, host_data[t], in);
+    }
+  }
+  *out = h.release();
+  TNC_CATCH
+}
+
+tnc_status tnc_net_set_tensor(tnc_net net, int32_t tensor, const void* host_data, tnc_in in) {
+  TNC_TRY
+  if (!net || !host_data) fail(TNC_E_ARG, "net/host_data is NULL");
+  Net& n = net->n;
+  if (tensor < 0 || tensor >= n.n_tensors) fail(TNC_E_ARG, "tensor out of range");
+  set_device(*n.ctx);
+  check_hip(hipStreamSynchronize(n.ctx->stream), "stream synchronize");
+  upload_leaf(n, tensor, host_data, in);
+  TNC_CATCH
+}
+
+tnc_status tnc_net_set_tensor_device(tnc_net net, int32_t tensor, const void* dev_data) {
+  TNC_TRY
+  if (!net || !dev_data) fail(TNC_E_ARG, "net/dev_data is NULL");
+  Net& n = net->n;
+  if (tensor < 0 || tensor >= n.n_tensors) fail(TNC_E_ARG, "tensor out of range");
+  set_device(*n.ctx);
+  check_hip(hipMemcpyAsync(n.leaf[tensor].ptr, dev_data, n.numel[tensor] * 8, hipMemcpyDeviceToDevice, n.ctx->stream),
+            "leaf copy");
+  TNC_CATCH
+}
+
+tnc_status tnc_net_destroy(tnc_net net) {
+  TNC_TRY
+  if (net && !net->n.ctx->host_only) {
+    (void)hipSetDevice(net->n.ctx->device);
+    (void)hipStreamSynchronize(net->n.ctx->stream);
+  }
+  delete net;
+  TNC_CATCH
+}
+
+tnc_status tnc_plan_create(tnc_net net, int32_t n_steps, const int32_t* ssa_pairs, int32_t n_sliced,
+                           const int32_t* sliced_labels, tnc_prec prec, tnc_cgemm cgemm, tnc_plan* out) {
+  TNC_TRY
+  if (!net || !out) fail(TNC_E_ARG, "net/out is NULL");
+  if (n_steps < 0 || (n_steps && !ssa_pairs) || n_sliced < 0 || (n_sliced && !sliced_labels))
+    fail(TNC_E_ARG, "bad plan arguments");
+  if (prec != TNC_PREC_C64 && prec != TNC_PREC_BF16X3) fail(TNC_E_ARG, "unknown precision");
+  if (cgemm != TNC_GEMM_4M && cgemm != TNC_GEMM_3M) fail(TNC_E_ARG, "unknown GEMM form");
+  if (prec == TNC_PREC_BF16X3 && cgemm == TNC_GEMM_3M)
+    fail(TNC_E_UNSUPPORTED, "split precision runs in the 4M form only");
+  Net& n = net->n;
+  auto h = std::make_unique<tnc_plan_s>();
+  Plan& p = h->p;
+  p.net = &n;
+  p.prec = prec;
+  p.form = cgemm;
+  for (int s = 0; s < n_steps; ++s) p.pairs.push_back({ssa_pairs[2 * s], ssa_pairs[2 * s + 1]});
+  validate_path(n, p.pairs);
+  std::vector<char> seen(n.extents.size(), 0);
+  for (int i = 0; i < n_sliced; ++i) {
+    const int l = sliced_labels[i];
+    if (l < 0 || l >= static_cast<int>(n.extents.size())) fail(TNC_E_ARG, "sliced label out of range");
+    if (n.kind[l] != LabelKind::Closed) fail(TNC_E_ARG, "sliced label " + std::to_string(l) + " is not closed");
+    if (seen[l]) fail(TNC_E_ARG, "sliced label repeated");
+    seen[l] = 1;
+    p.sliced.push_back(l);
+  }
+  p.suffix_prod.assign(n_sliced + 1, 1);
+  for (int j = 1; j <= n_sliced; ++j) {
+    p.suffix_prod[j] = p.suffix_prod[j - 1] * n.extents[p.sliced[n_sliced - j]];
+    if (p.suffix_prod[j] > (int64_t{1} << 40)) fail(TNC_E_ARG, "too many slices");
+  }
+  p.n_slices = p.suffix_prod[n_sliced];
+  choose_chunking(p, n.ctx->arena_bytes);
+  const ChunkPlan& c0 = *p.chunks[0];
+  if (n.ctx->arena_bytes && static_cast<size_t>(c0.peak) + run_extra_bytes(c0, 1) > n.ctx->arena_bytes)
+    fail(TNC_E_NOMEM, "planned peak of one slice (" + std::to_string(c0.peak) + " B) exceeds the arena (" +
+                          std::to_string(n.ctx->arena_bytes) + " B)");
+  if (!n.ctx->host_only) {
+    set_device(*n.ctx);
+    p.acc.alloc(static_cast<size_t>(std::max<int64_t>(1, c0.R)) * 16);
+    p.norm.alloc(256);
+  }
+  *out = h.release();
+  TNC_CATCH
+}
+
+tnc_status tnc_plan_destroy(tnc_plan plan) {
+  TNC_TRY
+  if (plan) {
+    Plan& p = plan->p;
+    if (!p.net->ctx->host_only) {
+      (void)hipSetDevice(p.net->ctx->device);
+      (void)hipStreamSynchronize(p.net->ctx->stream);
+      for (auto& e : p.pending) {
+        (void)hipEventDestroy(e.first.first);
+        (void)hipEventDestroy(e.first.second);
+      }
+    }
+  }
+  delete plan;
+  TNC_CATCH
+}
+
+tnc_status tnc_plan_get_info(tnc_plan plan, tnc_plan_info* out) {
+  TNC_TRY
+  if (!plan || !out) fail(TNC_E_ARG, "plan/out is NULL");
+  Plan& p = plan->p;
+  const ChunkPlan& c0 = *p.chunks[0];
+  const ChunkPlan& cm = p.chunk(p.j_max);
+  tnc_plan_info info{};
+  info.flops_per_slice = c0.flops;
+  info.bytes_per_slice = c0.bytes;
+  info.transpose_bytes = c0.transpose_bytes;
+  info.n_slices = p.n_slices;
+  info.max_intermediate = c0.max_tensor;
+  info.peak_bytes = c0.peak;
+  info.max_chunk = p.suffix_prod[p.j_max];
+  info.chunk_peak_bytes = cm.peak;
+  info.n_steps = static_cast<int32_t>(p.pairs.size());
+  info.n_permutes = c0.n_permutes;
+  info.n_permuted_stores = c0.n_perm_stores;
+  info.n_result = static_cast<int32_t>(std::min<int64_t>(c0.R, INT32_MAX));
+  *out = info;
+  TNC_CATCH
+}
+
+tnc_status tnc_plan_get_step(tnc_plan plan, int32_t step, tnc_step_info* out) {
+  TNC_TRY
+  if (!plan || !out) fail(TNC_E_ARG, "plan/out is NULL");
+  const ChunkPlan& c0 = *plan->p.chunks[0];
+  if (step < 0 || step >= static_cast<int32_t>(c0.steps.size())) fail(TNC_E_ARG, "step out of range");
+  const StepPlan& s = c0.steps[step];
+  tnc_step_info i{};
+  i.A = s.A;
+  i.B = s.B;
+  i.C = s.C;
+  i.nH = static_cast<int32_t>(s.H.size());
+  i.nM = static_cast<int32_t>(s.M.size());
+  i.nN = static_cast<int32_t>(s.N.size());
+  i.nK = static_cast<int32_t>(s.K.size());
+  i.h = s.h;
+  i.m = s.m;
+  i.n = s.n;
+  i.k = s.k;
+  i.natural = s.natural ? 1 : 0;
+  i.kernel = static_cast<int32_t>(s.kind);
+  *out = i;
+  TNC_CATCH
+}
+
+tnc_status tnc_plan_get_order(tnc_plan plan, int32_t id, int32_t* labels, int32_t cap, int32_t* rank) {
+  TNC_TRY
+  if (!plan || !rank || (cap > 0 && !labels)) fail(TNC_E_ARG, "bad arguments");
+  const ChunkPlan& c0 = *plan->p.chunks[0];
+  if (id < 0 || id >= static_cast<int32_t>(c0.order.size())) fail(TNC_E_ARG, "tensor id out of range");
+  const auto& o = c0.order[id];
+  for (int q = 0; q < std::min<int>(cap, static_cast<int>(o.size())); ++q) labels[q] = o[q];
+  *rank = static_cast<int32_t>(o.size());
+  TNC_CATCH
+}
+
+tnc_status tnc_plan_set_max_chunk(tnc_plan plan, int64_t max_chunk) {
+  TNC_TRY
+  if (!plan) fail(TNC_E_ARG, "plan is NULL");
+  Plan& p = plan->p;
+  p.max_chunk_user = max_chunk;
+  int j = 0;
+  for (int q = 1; q < static_cast<int>(p.suffix_prod.size()); ++q) {
+    if (max_chunk > 0 && p.suffix_prod[q] > max_chunk) break;
+    if (!p.chunks[q]) {
+      auto cp = build_chunk(p, q);
+      const size_t need = static_cast<size_t>(cp->peak) + run_extra_bytes(*cp, 1);
+      if (p.net->ctx->arena_bytes && need > p.net->ctx->arena_bytes) break;
+      p.chunks[q] = std::move(cp);
+    } else {
+      const size_t need = static_cast<size_t>(p.chunks[q]->peak) + run_extra_bytes(*p.chunks[q], 1);
+      if (p.net->ctx->arena_bytes && need > p.net->ctx->arena_bytes) break;
+    }
+    j = q;
+  }
+  p.j_max = j;
+  TNC_CATCH
+}
+
+tnc_status tnc_plan_set_graph(tnc_plan plan, int32_t enable) {
+  TNC_TRY
+  if (!plan) fail(TNC_E_ARG, "plan is NULL");
+  plan->p.graph = enable ? 1 : 0;
+  TNC_CATCH
+}
+
+tnc_status tnc_plan_set_profile(tnc_plan plan, int32_t enable) {
+  TNC_TRY
+  if (!plan) fail(TNC_E_ARG, "plan is NULL");
+  Plan& p = plan->p;
+  if (!p.net->ctx->host_only) drain_profile(p);
+  p.profile = enable ? 1 : 0;
+  p.timers.assign(p.pairs.size() + 2, StepTimer{});
+  TNC_CATCH
+}
+
+tnc_status tnc_plan_get_profile(tnc_plan plan, int32_t step, double* ms, int64_t* launches) {
+  TNC_TRY
+  if (!plan || !ms || !launches) fail(TNC_E_ARG, "bad arguments");
+  Plan& p = plan->p;
+  set_device(*p.net->ctx);
+  drain_profile(p);
+  const int ns = static_cast<int>(p.pairs.size());
+  int idx = step;
+  if (step == -1) idx = ns;
+  if (step == -2) idx = ns + 1;
+  if (idx < 0 || idx >= ns + 2) fail(TNC_E_ARG, "step out of range");
+  if (p.timers.size() < static_cast<size_t>(ns + 2)) p.timers.resize(ns + 2);
+  *ms = p.timers[idx].ms;
+  *launches = p.timers[idx].launches;
+  TNC_CATCH
+}
+
+static void check_range(const Plan& p, int64_t first, int64_t count) {
+  if (first < 0 || count < 1 || first + count > p.n_slices)
+    fail(TNC_E_ARG, "slice range [" + std::to_string(first) + ", " + std::to_string(first + count) +
+                        ") outside [0, " + std::to_string(p.n_slices) + ")");
+}
+
+tnc_status tnc_contract(tnc_plan plan, int64_t first_slice, int64_t n_slices, double* out_c128) {
+  TNC_TRY
+  if (!plan || !out_c128) fail(TNC_E_ARG, "plan/out is NULL");
+  Plan& p = plan->p;
+  Ctx& c = *p.net->ctx;
+  set_device(c);
+  check_range(p, first_slice, n_slices);
+  const ChunkPlan& c0 = *p.chunks[0];
+  RunArgs a;
+  a.first = first_slice;
+  a.count = n_slices;
+  a.arena = c.arena;
+  a.arena_bytes = c.arena_bytes;
+  a.acc = static_cast<double2*>(p.acc.ptr);
+  a.stream = c.stream;
+  check_hip(launch_fill_zero(a.acc, c0.R * 16, c.stream), "zero accumulator");
+  run_plan(p, a);
+  std::vector<double> tmp(static_cast<size_t>(2 * c0.R));
+  check_hip(hipMemcpyAsync(tmp.data(), a.acc, c0.R * 16, hipMemcpyDeviceToHost, c.stream), "result copy");
+  check_hip(hipStreamSynchronize(c.stream), "stream synchronize");
+  if (c0.result_perm.empty()) {
+    std::memcpy(out_c128, tmp.data(), tmp.size() * sizeof(double));
+  } else {
+    for (int64_t u = 0; u < c0.R; ++u) {
+      out_c128[2 * u] = tmp[2 * c0.result_perm[u]];
+      out_c128[2 * u + 1] = tmp[2 * c0.result_perm[u] + 1];
+    }
+  }
+  TNC_CATCH
+}
+
+tnc_status tnc_contract_async(tnc_plan plan, int64_t first_slice, int64_t n_slices, void* out_dev,
+                              tnc_out out_type) {
+  TNC_TRY
+  if (!plan || !out_dev) fail(TNC_E_ARG, "plan/out is NULL");
+  Plan& p = plan->p;
+  Ctx& c = *p.net->ctx;
+  set_device(c);
+  check_range(p, first_slice, n_slices);
+  const ChunkPlan& c0 = *p.chunks[0];
+  if (!c0.result_perm.empty()) fail(TNC_E_UNSUPPORTED, "device results need batch labels leading the open order");
+  RunArgs a;
+  a.first = first_slice;
+  a.count = n_slices;
+  a.arena = c.arena;
+  a.arena_bytes = c.arena_bytes;
+  a.stream = c.stream;
+  if (out_type == TNC_OUT_C64 && n_slices == 1 && !p.pairs.empty()) {
+    a.direct_out = static_cast<float2*>(out_dev);
+    run_plan(p, a);
+  } else if (out_type == TNC_OUT_C64) {
+    a.acc = static_cast<double2*>(p.acc.ptr);
+    check_hip(launch_fill_zero(a.acc, c0.R * 16, c.stream), "zero accumulator");
+    run_plan(p, a);
+    check_hip(launch_c128_to_c64(a.acc, static_cast<float2*>(out_dev), c0.R, c.stream), "result conversion");
+  } else if (out_type == TNC_OUT_C128) {
+    a.acc = static_cast<double2*>(out_dev);
+    check_hip(launch_fill_zero(a.acc, c0.R * 16, c.stream), "zero accumulator");
+    run_plan(p, a);
+  } else {
+    fail(TNC_E_ARG, "unknown output type");
+  }
+  TNC_CATCH
+}
+
+tnc_status tnc_plan_result_norm2(tnc_plan plan, double* out) {
+  TNC_TRY
+  if (!plan || !out) fail(TNC_E_ARG, "plan/out is NULL");
+  Plan& p = plan->p;
+  Ctx& c = *p.net->ctx;
+  set_device(c);
+  const ChunkPlan& c0 = *p.chunks[0];
+  check_hip(launch_norm2(static_cast<double2*>(p.acc.ptr), c0.R, static_cast<double*>(p.norm.ptr), c.stream), "norm");
+  double v = 0;
+  check_hip(hipMemcpyAsync(&v, p.norm.ptr, sizeof(double), hipMemcpyDeviceToHost, c.stream), "norm copy");
+  check_hip(hipStreamSynchronize(c.stream), "stream synchronize");
+  *out = v;
+  TNC_CATCH
+}
+
+tnc_status tnc_permute(tnc_ctx ctx, const void* in, void* out, int32_t rank, const int64_t* extents,
+                       const int32_t* perm) {
+  TNC_TRY
+  if (!ctx || !in || !out || rank < 0 || (rank && (!extents || !perm))) fail(TNC_E_ARG, "bad arguments");
+  Ctx& c = ctx->c;
+  set_device(c);
+  std::vector<int64_t> ist(rank);
+  int64_t s = 1;
+  for (int q = rank - 1; q >= 0; --q) {
+    if (extents[q] < 1) fail(TNC_E_ARG, "extent < 1");
+    ist[q] = s;
+    s *= extents[q];
+  }
+  std::vector<char> seen(rank, 0);
+  std::vector<int64_t> ext(rank), st(rank);
+  for (int q = 0; q < rank; ++q) {
+    const int p = perm[q];
+    if (p < 0 || p >= rank || seen[p]) fail(TNC_E_ARG, "perm is not a permutation");
+    seen[p] = 1;
+    ext[q] = extents[p];
+    st[q] = ist[p];
+  }
+  PermuteHost ph = build_permute(ext, st);
+  if (!ph.tiled) {
+    GatherDesc g = ph.plain;
+    g.in = static_cast<const float2*>(in);
+    g.out = static_cast<float2*>(out);
+    check_hip(launch_gather(g, c.stream), "gather launch");
+  } else {
+    std::vector<uint8_t> blob;
+    auto put = [&](const void* src, size_t bytes) {
+      const size_t off = (blob.size() + 255) / 256 * 256;
+      blob.resize(off + bytes);
+      std::memcpy(blob.data() + off, src, bytes);
+      return off;
+    };
+    const size_t o1 = put(ph.tile_in.data(), ph.tile_in.size() * 4);
+    const size_t o2 = put(ph.tile_slot_r.data(), ph.tile_slot_r.size() * 4);
+    const size_t o3 = put(ph.tile_out.data(), ph.tile_out.size() * 4);
+    const size_t o4 = put(ph.tile_slot_w.data(), ph.tile_slot_w.size() * 4);
+    const size_t o5 = put(ph.lo_tab.data(), ph.lo_tab.size() * 8);
+    const size_t o6 = put(ph.hi_tab.data(), ph.hi_tab.size() * 8);
+    check_hip(hipStreamSynchronize(c.stream), "stream synchronize");
+    if (c.scratch.bytes < blob.size()) c.scratch.alloc(blob.size());
+    check_hip(hipMemcpy(c.scratch.ptr, blob.data(), blob.size(), hipMemcpyHostToDevice), "table upload");
+    const char* b = static_cast<const char*>(c.scratch.ptr);
+    PermuteDesc d{};
+    d.in = static_cast<const float2*>(in);
+    d.out = static_cast<float2*>(out);
+    d.tile_in = reinterpret_cast<const int32_t*>(b + o1);
+    d.tile_slot_r = reinterpret_cast<const int32_t*>(b + o2);
+    d.tile_out = reinterpret_cast<const int32_t*>(b + o3);
+    d.tile_slot_w = reinterpret_cast<const int32_t*>(b + o4);
+    d.lo_tab = reinterpret_cast<const int64_t*>(b + o5);
+    d.hi_tab = reinterpret_cast<const int64_t*>(b + o6);
+    d.n_tiles = ph.n_tiles;
+    d.L = ph.L;
+    d.T = ph.T;
+    d.slots = ph.slots;
+    check_hip(launch_permute(d, c.stream), "permute launch");
+  }
+  TNC_CATCH
+}
+
+tnc_status tnc_batched_cgemm(tnc_ctx ctx, int64_t h, int64_t m, int64_t n, int64_t k, const void* A,
+                             int64_t stride_a, const void* B, int64_t stride_b, void* C, tnc_prec prec,
+                             tnc_cgemm form) {
+  TNC_TRY
+  if (!ctx || !A || !B || !C || h < 1 || m < 1 || n < 1 || k < 1 || stride_a < 0 || stride_b < 0)
+    fail(TNC_E_ARG, "bad arguments");
+  if (prec == TNC_PREC_BF16X3 && form == TNC_GEMM_3M) fail(TNC_E_UNSUPPORTED, "split precision runs in 4M form");
+  Ctx& c = ctx->c;
+  set_device(c);
+  GemmDesc d;
+  std::memset(&d, 0, sizeof(d));
+  d.A = static_cast<const float2*>(A);
+  d.B = static_cast<const float2*>(B);
+  d.C = static_cast<float2*>(C);
+  d.m = m;
+  d.n = n;
+  d.k = k;
+  d.h = h;
+  d.pow2 = 0;
+  if (h > 1) {
+    if (h > INT32_MAX) fail(TNC_E_ARG, "batch too large");
+    d.nbd = 1;
+    d.bext[0] = static_cast<int32_t>(h);
+    d.bsA[0] = stride_a;
+    d.bsB[0] = stride_b;
+    if ((h & (h - 1)) == 0) {
+      d.pow2 = 1;
+      int sh = 0;
+      while ((int64_t{1} << sh) < h) ++sh;
+      d.bshift[0] = sh;
+    }
+  }
+  const GemmKernel kind = (m >= 64 && n >= 32 && k >= 16) ? GemmKernel::MFMA : GemmKernel::SMALL;
+  check_hip(launch_gemm(d, kind, form == TNC_GEMM_3M ? Form::M3 : Form::M4,
+                        prec == TNC_PREC_BF16X3 ? Prec::BF16X3 : Prec::C64, c.stream),
+            "gemm launch");
+  TNC_CATCH
+}
+
+}  // extern "C"

@@ -1,0 +1,197 @@
+// Host-side structures of the path executor (internal).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <array>
+#include <atomic>
+#include <cstdint>
+#include <memory>
+#include <mutex>
+#include <string>
+#include <vector>
+
+#include "../../include/tnc.h"
+#include "kernels.hpp"
+
+namespace tnc {
+
+// Error carrying a status code; caught at the ABI boundary.
+struct Error {
+  tnc_status code;
+  std::string msg;
+};
+[[noreturn]] void fail(tnc_status code, const std::string& msg);
+void check_hip(hipError_t e, const char* what);
+struct Ctx;
+void set_device(const Ctx& c);
+void g_error_clear();
+void g_error_set(const std::string& m);
+const char* g_error_get();
+
+// Device allocation owned by the library.
+struct DeviceBuf {
+  void* ptr = nullptr;
+  size_t bytes = 0;
+  DeviceBuf() = default;
+  DeviceBuf(const DeviceBuf&) = delete;
+  DeviceBuf& operator=(const DeviceBuf&) = delete;
+  DeviceBuf(DeviceBuf&& o) noexcept : ptr(o.ptr), bytes(o.bytes) {
+    o.ptr = nullptr;
+    o.bytes = 0;
+  }
+  ~DeviceBuf();
+  void alloc(size_t n);
+  void reset();
+};
+
+struct Server;
+
+struct Ctx {
+  int device = -1;
+  bool host_only = true;
+  char* arena = nullptr;
+  size_t arena_bytes = 0;
+  bool own_arena = false;
+  hipStream_t stream = nullptr;
+  bool own_stream = false;
+  DeviceBuf scratch;   // tables of stand-alone permutes
+  std::shared_ptr<Server> server;
+  ~Ctx();
+};
+
+enum class LabelKind : uint8_t { Unused = 0, Closed, Open, Batch };
+
+struct Net {
+  Ctx* ctx = nullptr;
+  int n_tensors = 0;
+  std::vector<std::vector<int>> labels;   // stored order per leaf
+  std::vector<int64_t> extents;           // per label
+  std::vector<int> open;                  // result order
+  std::vector<LabelKind> kind;            // per label
+  std::vector<int> user_batch;            // batch labels in open order
+  std::vector<int64_t> numel;             // per leaf
+  std::vector<DeviceBuf> leaf;            // resident complex64 leaves
+  std::vector<std::vector<int64_t>> stride;  // per leaf, per stored mode
+};
+
+// A tile decomposition of one gather-permute (host copy of the tables).
+struct PermuteHost {
+  bool tiled = false;
+  int32_t T = 0, slots = 0, L = 1;
+  int64_t n_tiles = 0;
+  std::vector<int32_t> tile_in, tile_slot_r, tile_out, tile_slot_w;
+  std::vector<int64_t> lo_tab, hi_tab;
+  GatherDesc plain{};
+  // offsets of the tables inside the plan's device blob
+  int64_t off_tile_in = -1, off_slot_r = -1, off_tile_out = -1, off_slot_w = -1, off_lo = -1, off_hi = -1;
+};
+
+// Build the gather-permute out[w] = in[base + sum_d digit_d(w) * in_stride[d]]
+// for row-major output dims ext[].
+PermuteHost build_permute(const std::vector<int64_t>& ext, const std::vector<int64_t>& in_stride);
+
+struct LeafPrep {
+  int leaf = -1;
+  bool direct = true;        // use the resident leaf as is
+  int buf = -1;              // arena buffer when prepared
+  int base_slot = -1;        // slot of its per-chunk base offset (-1: none)
+  std::vector<std::pair<int, int64_t>> fixed;  // (sliced label, stride) fixed per chunk
+  PermuteHost perm;
+  int step = -1;             // step that consumes it
+};
+
+struct StepPlan {
+  int A = -1, B = -1, C = -1;                 // tensor ids (A = M side)
+  std::vector<int> H, M, N, K;
+  int64_t h = 1, m = 1, n = 1, k = 1, hA = 1, hB = 1;
+  bool natural = true;
+  GemmKernel kind = GemmKernel::SMALL;
+  GemmDesc desc{};                            // pointers filled at run time
+  int64_t off_offM = -1, off_offN = -1;       // in the device blob
+  std::vector<int64_t> offM, offN;            // host copies (permuted store)
+  std::vector<int> preps;                     // leaf preps launched before the GEMM
+};
+
+struct ChunkPlan {
+  int j = 0;                       // number of trailing sliced labels batched
+  int64_t hs = 1;                  // slices per chunk
+  std::vector<int> batch;          // canonical batch labels
+  std::vector<std::vector<int>> order;   // per tensor id
+  std::vector<int64_t> numel;            // per tensor id
+  std::vector<LeafPrep> leaf;            // per leaf
+  std::vector<StepPlan> steps;
+  std::vector<int64_t> buf_bytes, buf_off;  // arena buffers
+  std::vector<int> tensor_buf;              // per tensor id: arena buffer or -1
+  int64_t peak = 0;                          // arena bytes
+  int root_id = -1;
+  int64_t R = 1;                             // result elements
+  int n_base_slots = 0;
+  std::vector<int64_t> result_perm;          // user index -> reduced-root index
+  // device side (built on first use)
+  bool materialized = false;
+  DeviceBuf blob;
+  std::vector<uint8_t> host_blob;
+  double flops = 0, bytes = 0, transpose_bytes = 0;
+  int64_t max_tensor = 0;
+  int n_permutes = 0, n_perm_stores = 0;
+};
+
+struct StepTimer {
+  double ms = 0;
+  int64_t launches = 0;
+};
+
+struct Plan {
+  Net* net = nullptr;
+  std::vector<std::array<int, 2>> pairs;
+  std::vector<int> sliced;
+  std::vector<int64_t> suffix_prod;   // suffix_prod[j] = slices per chunk with j batched labels
+  int64_t n_slices = 1;
+  tnc_prec prec = TNC_PREC_C64;
+  tnc_cgemm form = TNC_GEMM_4M;
+  int64_t max_chunk_user = -1;
+  int graph = 0;
+  int profile = 0;
+  int j_max = 0;
+  std::vector<std::unique_ptr<ChunkPlan>> chunks;   // index j
+  std::vector<StepTimer> timers;                    // per step, then preps, reductions
+  std::vector<std::pair<std::pair<hipEvent_t, hipEvent_t>, int>> pending;  // profiling events
+  DeviceBuf acc;         // complex128 result accumulator (synchronous calls)
+  DeviceBuf norm;        // one double
+  std::mutex mu;         // guards lazy chunk building
+  ChunkPlan& chunk(int j);
+};
+
+// planner.cpp
+void validate_net(Net& net);
+void validate_path(const Net& net, const std::vector<std::array<int, 2>>& pairs);
+std::unique_ptr<ChunkPlan> build_chunk(const Plan& plan, int j);
+void choose_chunking(Plan& plan, size_t budget);
+size_t run_extra_bytes(const ChunkPlan& cp, int64_t n_chunks);
+
+// executor.cpp
+void materialize(ChunkPlan& cp);
+struct RunArgs {
+  int64_t first = 0, count = 1;
+  char* arena = nullptr;        // workspace (peak + extras)
+  size_t arena_bytes = 0;
+  double2* acc = nullptr;       // device accumulator (n_result complex128)
+  float2* direct_out = nullptr; // single-slice runs: the last step writes here, no reduction
+  hipStream_t stream = nullptr;
+};
+void run_plan(Plan& plan, const RunArgs& a);
+void drain_profile(Plan& plan);
+std::vector<std::pair<int, int64_t>> decompose(const Plan& plan, int64_t first, int64_t count);
+
+}  // namespace tnc
+
+struct tnc_ctx_s {
+  tnc::Ctx c;
+};
+struct tnc_net_s {
+  tnc::Net n;
+};
+struct tnc_plan_s {
+  tnc::Plan p;
+};

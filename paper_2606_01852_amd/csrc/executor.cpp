@@ -1,0 +1,226 @@
+// Path executor: uploads a chunk plan's tables once, then replays the path
+// for each chunk of slices -- leaf permutations, one batched complex GEMM
+// per step, FP64 accumulation of the root -- on one stream with no
+// allocation inside the loop (paper Sec. IV: the executor replays the
+// planned schedule; slicing, Sec. II-C, becomes a batch dimension).
+#include <algorithm>
+#include <cstring>
+
+#include "core.hpp"
+
+namespace tnc {
+
+namespace {
+
+int64_t align_up(int64_t x) { return (x + 255) / 256 * 256; }
+
+template <typename T>
+int64_t put(std::vector<uint8_t>& blob, const std::vector<T>& v) {
+  if (v.empty()) return -1;
+  const int64_t off = align_up(static_cast<int64_t>(blob.size()));
+  blob.resize(off + v.size() * sizeof(T));
+  std::memcpy(blob.data() + off, v.data(), v.size() * sizeof(T));
+  return off;
+}
+
+}  // namespace
+
+void materialize(ChunkPlan& cp) {
+  if (cp.materialized) return;
+  std::vector<uint8_t>& blob = cp.host_blob;
+  blob.clear();
+  for (LeafPrep& lp : cp.leaf) {
+    if (lp.direct || !lp.perm.tiled) continue;
+    PermuteHost& p = lp.perm;
+    p.off_tile_in = put(blob, p.tile_in);
+    p.off_slot_r = put(blob, p.tile_slot_r);
+    p.off_tile_out = put(blob, p.tile_out);
+    p.off_slot_w = put(blob, p.tile_slot_w);
+    p.off_lo = put(blob, p.lo_tab);
+    p.off_hi = put(blob, p.hi_tab);
+  }
+  for (StepPlan& sp : cp.steps) {
+    if (sp.natural) continue;
+    sp.off_offM = put(blob, sp.offM);
+    sp.off_offN = put(blob, sp.offN);
+  }
+  if (!blob.empty()) {
+    cp.blob.alloc(blob.size());
+    check_hip(hipMemcpy(cp.blob.ptr, blob.data(), blob.size(), hipMemcpyHostToDevice), "upload plan tables");
+  }
+  char* base = static_cast<char*>(cp.blob.ptr);
+  for (StepPlan& sp : cp.steps) {
+    if (sp.natural) continue;
+    sp.desc.offM = reinterpret_cast<const int64_t*>(base + sp.off_offM);
+    sp.desc.offN = reinterpret_cast<const int64_t*>(base + sp.off_offN);
+  }
+  cp.materialized = true;
+}
+
+std::vector<std::pair<int, int64_t>> decompose(const Plan& plan, int64_t first, int64_t count) {
+  std::vector<std::pair<int, int64_t>> out;
+  int64_t s = first;
+  const int64_t end = first + count;
+  while (s < end) {
+    int j = plan.j_max;
+    while (j > 0 && (s % plan.suffix_prod[j] != 0 || s + plan.suffix_prod[j] > end)) --j;
+    out.emplace_back(j, s);
+    s += plan.suffix_prod[j];
+  }
+  return out;
+}
+
+namespace {
+
+ChunkPlan& ready(Plan& plan, int j) {
+  std::lock_guard<std::mutex> g(plan.mu);
+  if (!plan.chunks[j]) plan.chunks[j] = build_chunk(plan, j);
+  materialize(*plan.chunks[j]);
+  return *plan.chunks[j];
+}
+
+struct Launcher {
+  Plan& plan;
+  hipStream_t stream;
+  std::vector<std::pair<std::pair<hipEvent_t, hipEvent_t>, int>>* events;
+
+  template <typename F>
+  void run(int timer, F&& f) {
+    hipEvent_t a = nullptr, b = nullptr;
+    if (events) {
+      check_hip(hipEventCreate(&a), "event");
+      check_hip(hipEventCreate(&b), "event");
+      check_hip(hipEventRecord(a, stream), "event record");
+    }
+    check_hip(f(), "kernel launch");
+    if (events) {
+      check_hip(hipEventRecord(b, stream), "event record");
+      events->push_back({{a, b}, timer});
+    }
+  }
+};
+
+}  // namespace
+
+void run_plan(Plan& plan, const RunArgs& a) {
+  Net& net = *plan.net;
+  const int n = net.n_tensors;
+  const int ns = static_cast<int>(plan.pairs.size());
+  const auto chunks = decompose(plan, a.first, a.count);
+  if (chunks.empty()) fail(TNC_E_ARG, "empty slice range");
+  // per-chunk base offsets of leaves that carry fixed sliced labels
+  int slots = 1;
+  for (auto& c : chunks) slots = std::max(slots, ready(plan, c.first).n_base_slots);
+  const int64_t nS = static_cast<int64_t>(plan.sliced.size());
+  std::vector<int64_t> bases(chunks.size() * slots, 0);
+  int64_t peak = 0;
+  for (size_t c = 0; c < chunks.size(); ++c) {
+    ChunkPlan& cp = ready(plan, chunks[c].first);
+    peak = std::max(peak, cp.peak);
+    if (!cp.n_base_slots) continue;
+    std::vector<int64_t> val(net.extents.size(), 0);
+    int64_t rest = chunks[c].second;
+    for (int64_t q = nS - 1; q >= 0; --q) {
+      const int l = plan.sliced[q];
+      val[l] = rest % net.extents[l];
+      rest /= net.extents[l];
+    }
+    for (const LeafPrep& lp : cp.leaf) {
+      if (lp.base_slot < 0) continue;
+      int64_t off = 0;
+      for (auto& f : lp.fixed) off += val[f.first] * f.second;
+      bases[c * slots + lp.base_slot] = off;
+    }
+  }
+  const int64_t bases_off = align_up(peak);
+  const size_t need = static_cast<size_t>(bases_off) + bases.size() * sizeof(int64_t);
+  if (need > a.arena_bytes)
+    fail(TNC_E_NOMEM, "run needs " + std::to_string(need) + " arena bytes, have " + std::to_string(a.arena_bytes));
+  int64_t* bases_dev = reinterpret_cast<int64_t*>(a.arena + bases_off);
+  check_hip(hipMemcpyAsync(bases_dev, bases.data(), bases.size() * sizeof(int64_t), hipMemcpyHostToDevice, a.stream),
+            "upload chunk bases");
+
+  std::vector<std::pair<std::pair<hipEvent_t, hipEvent_t>, int>> ev;
+  Launcher L{plan, a.stream, plan.profile ? &ev : nullptr};
+  const int t_prep = ns, t_red = ns + 1;
+  if (plan.timers.size() < static_cast<size_t>(ns + 2)) plan.timers.resize(ns + 2);
+
+  for (size_t c = 0; c < chunks.size(); ++c) {
+    ChunkPlan& cp = ready(plan, chunks[c].first);
+    const char* blob = static_cast<const char*>(cp.blob.ptr);
+    auto ptr = [&](int id) -> float2* {
+      if (id < n && cp.leaf[id].direct) return static_cast<float2*>(net.leaf[id].ptr);
+      if (id == cp.root_id && a.direct_out) return a.direct_out;
+      return reinterpret_cast<float2*>(a.arena + cp.buf_off[cp.tensor_buf[id]]);
+    };
+    auto prep = [&](int t) {
+      const LeafPrep& lp = cp.leaf[t];
+      const float2* in = static_cast<const float2*>(net.leaf[t].ptr);
+      float2* out = ptr(t);
+      const int64_t* bd = lp.base_slot >= 0 ? bases_dev + c * slots + lp.base_slot : nullptr;
+      if (lp.perm.tiled) {
+        const PermuteHost& p = lp.perm;
+        PermuteDesc d{};
+        d.in = in;
+        d.out = out;
+        d.tile_in = reinterpret_cast<const int32_t*>(blob + p.off_tile_in);
+        d.tile_slot_r = reinterpret_cast<const int32_t*>(blob + p.off_slot_r);
+        d.tile_out = reinterpret_cast<const int32_t*>(blob + p.off_tile_out);
+        d.tile_slot_w = reinterpret_cast<const int32_t*>(blob + p.off_slot_w);
+        d.lo_tab = reinterpret_cast<const int64_t*>(blob + p.off_lo);
+        d.hi_tab = reinterpret_cast<const int64_t*>(blob + p.off_hi);
+        d.n_tiles = p.n_tiles;
+        d.L = p.L;
+        d.T = p.T;
+        d.slots = p.slots;
+        d.base = 0;
+        d.base_dev = bd;
+        L.run(t_prep, [&] { return launch_permute(d, a.stream); });
+      } else {
+        GatherDesc g = lp.perm.plain;
+        g.in = in;
+        g.out = out;
+        g.base = 0;
+        g.base_dev = bd;
+        L.run(t_prep, [&] { return launch_gather(g, a.stream); });
+      }
+    };
+    if (ns == 0 && !cp.leaf[0].direct) prep(0);
+    for (int s = 0; s < ns; ++s) {
+      StepPlan& sp = cp.steps[s];
+      for (int t : sp.preps) prep(t);
+      GemmDesc d = sp.desc;
+      d.A = ptr(sp.A);
+      d.B = ptr(sp.B);
+      d.C = ptr(sp.C);
+      const Form form = plan.form == TNC_GEMM_3M ? Form::M3 : Form::M4;
+      const Prec prec = plan.prec == TNC_PREC_BF16X3 ? Prec::BF16X3 : Prec::C64;
+      L.run(s, [&] { return launch_gemm(d, sp.kind, form, prec, a.stream); });
+    }
+    if (!a.direct_out) {
+      const float2* root = ptr(cp.root_id);
+      L.run(t_red, [&] { return launch_reduce_fp64(root, a.acc, cp.hs, cp.R, a.stream); });
+    }
+  }
+  if (!ev.empty()) {
+    std::lock_guard<std::mutex> g(plan.mu);
+    for (auto& e : ev) plan.pending.push_back(e);
+  }
+}
+
+void drain_profile(Plan& plan) {
+  std::lock_guard<std::mutex> g(plan.mu);
+  for (auto& e : plan.pending) {
+    check_hip(hipEventSynchronize(e.first.second), "event sync");
+    float ms = 0.f;
+    check_hip(hipEventElapsedTime(&ms, e.first.first, e.first.second), "event time");
+    StepTimer& t = plan.timers[e.second];
+    t.ms += ms;
+    t.launches += 1;
+    (void)hipEventDestroy(e.first.first);
+    (void)hipEventDestroy(e.first.second);
+  }
+  plan.pending.clear();
+}
+
+}  // namespace tnc

@@ -1,0 +1,111 @@
+// Operand permutation kernels (complex64 bit copies).
+//
+// A step's operand must be stored [retained || reduced] (paper Sec. IV-A);
+// leaves whose stored order differs, and leaves of a slice batch, are
+// rewritten once before the step that reads them.  The tiled kernel moves
+// one tile per iteration through LDS: it reads a tile whose innermost modes
+// are the input's innermost ones (contiguous runs) and writes it back with
+// the output's innermost modes innermost (contiguous runs), so both sides of
+// HBM traffic are coalesced.  All index arithmetic is precomputed on the
+// host into small tables; the kernel only adds offsets.
+#include "kernels.hpp"
+
+namespace tnc {
+
+namespace {
+
+constexpr int kPermThreads = 256;
+
+template <int EPT>
+__global__ __launch_bounds__(kPermThreads) void permute_tiled(PermuteDesc d) {
+  extern __shared__ float2 lds[];
+  const int t = threadIdx.x;
+  int32_t in_off[EPT], slot_r[EPT], out_off[EPT], slot_w[EPT];
+#pragma unroll
+  for (int e = 0; e < EPT; ++e) {
+    const int idx = e * kPermThreads + t;
+    const bool ok = idx < d.T;
+    in_off[e] = ok ? d.tile_in[idx] : -1;
+    slot_r[e] = ok ? d.tile_slot_r[idx] : 0;
+    out_off[e] = ok ? d.tile_out[idx] : -1;
+    slot_w[e] = ok ? d.tile_slot_w[idx] : 0;
+  }
+  const int64_t base = d.base + (d.base_dev ? d.base_dev[0] : 0);
+  const uint32_t L = static_cast<uint32_t>(d.L);
+  int64_t tile = blockIdx.x;
+  if (tile >= d.n_tiles) return;
+  float2 v[EPT];
+  auto load = [&](int64_t tl) {
+    const uint32_t hi = static_cast<uint32_t>(tl / L);
+    const uint32_t lo = static_cast<uint32_t>(tl - static_cast<int64_t>(hi) * L);
+    const int64_t ib = base + d.lo_tab[2 * lo] + d.hi_tab[2 * hi];
+#pragma unroll
+    for (int e = 0; e < EPT; ++e)
+      if (in_off[e] >= 0) v[e] = d.in[ib + in_off[e]];
+  };
+  load(tile);
+  for (; tile < d.n_tiles; tile += gridDim.x) {
+#pragma unroll
+    for (int e = 0; e < EPT; ++e)
+      if (in_off[e] >= 0) lds[slot_r[e]] = v[e];
+    __syncthreads();
+    const int64_t next = tile + gridDim.x;
+    const uint32_t hi = static_cast<uint32_t>(tile / L);
+    const uint32_t lo = static_cast<uint32_t>(tile - static_cast<int64_t>(hi) * L);
+    const int64_t ob = d.lo_tab[2 * lo + 1] + d.hi_tab[2 * hi + 1];
+    if (next < d.n_tiles) load(next);
+#pragma unroll
+    for (int e = 0; e < EPT; ++e)
+      if (out_off[e] >= 0) d.out[ob + out_off[e]] = lds[slot_w[e]];
+    __syncthreads();
+  }
+}
+
+__global__ __launch_bounds__(256) void gather_plain(GatherDesc d) {
+  const int64_t base = d.base + (d.base_dev ? d.base_dev[0] : 0);
+  for (int64_t w = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x; w < d.total;
+       w += static_cast<int64_t>(gridDim.x) * blockDim.x) {
+    int64_t rest = w, off = base;
+    for (int j = d.rank - 1; j >= 0; --j) {
+      const int64_t e = d.ext[j];
+      const int64_t q = rest / e;
+      off += (rest - q * e) * d.in_stride[j];
+      rest = q;
+    }
+    d.out[w] = d.in[off];
+  }
+}
+
+}  // namespace
+
+hipError_t launch_permute(const PermuteDesc& d, hipStream_t s) {
+  if (d.n_tiles <= 0) return hipSuccess;
+  int ept = 1;
+  while (ept * kPermThreads < d.T) ept *= 2;
+  const size_t lds = static_cast<size_t>(d.slots) * sizeof(float2);
+  // enough blocks to fill 256 CUs several times over; each loops over tiles
+  const int64_t grid = d.n_tiles < 8192 ? d.n_tiles : 8192;
+  switch (ept) {
+#define TNC_PERM_CASE(E) \
+  case E: hipLaunchKernelGGL(permute_tiled<E>, dim3(grid), dim3(kPermThreads), lds, s, d); break;
+    TNC_PERM_CASE(1)
+    TNC_PERM_CASE(2)
+    TNC_PERM_CASE(4)
+    TNC_PERM_CASE(8)
+    TNC_PERM_CASE(16)
+#undef TNC_PERM_CASE
+    default:
+      return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_gather(const GatherDesc& d, hipStream_t s) {
+  if (d.total <= 0) return hipSuccess;
+  int64_t grid = (d.total + 255) / 256;
+  if (grid > 65536) grid = 65536;
+  hipLaunchKernelGGL(gather_plain, dim3(grid), dim3(256), 0, s, d);
+  return hipGetLastError();
+}
+
+}  // namespace tnc

@@ -1,0 +1,86 @@
+// Internal kernel interface: descriptors built by the host planner and the
+// launchers that run them.  Nothing here is part of the public C ABI.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <cstdint>
+
+namespace tnc {
+
+constexpr int kMaxBatchDims = 24;
+
+// Batched complex GEMM  C[b, i, j] = sum_l A[b, i, l] * B[b, j, l].
+// A, B are K-contiguous ([.. | M | K] and [.. | N | K] storage, row stride
+// k).  The batch index b (0 <= b < h) is row-major over nbd batch dims; the
+// operands' offsets are sum_d digit_d * bs{A,B}[d] (0 = broadcast), C's is
+// b * m * n.  Within one batch entry C is natural row-major [m, n] when offM
+// is null, else element (i, j) sits at offM[i] + offN[j].
+struct GemmDesc {
+  const float2* A;
+  const float2* B;
+  float2* C;
+  int64_t m, n, k, h;
+  int32_t nbd;
+  int32_t pow2;                    // every batch extent a power of two
+  int32_t bext[kMaxBatchDims];
+  int32_t bshift[kMaxBatchDims];   // log2(bext) when pow2
+  int64_t bsA[kMaxBatchDims];
+  int64_t bsB[kMaxBatchDims];
+  const int64_t* offM;
+  const int64_t* offN;
+};
+
+enum class Form : int { M4 = 0, M3 = 1 };
+enum class Prec : int { C64 = 0, BF16X3 = 1 };
+enum class GemmKernel : int { MFMA = 0, SMALL = 1 };
+
+// Tiled gather-permute of complex64: out (contiguous) gets, for every tile
+// t < n_tiles and element e < T of the tile,
+//   out[tile_out_base(t) + tile_out[e]] = in[base + tile_in_base(t) + tile_in[e']]
+// where the per-tile bases come from two host-built tables (outer tile index
+// split row-major into hi * L + lo) and the in-tile offsets and LDS slots
+// from per-element tables (read order r and write order w).
+struct PermuteDesc {
+  const float2* in;
+  float2* out;
+  const int32_t* tile_in;      // [T] input offset of read-order element r
+  const int32_t* tile_slot_r;  // [T] LDS slot of read-order element r
+  const int32_t* tile_out;     // [T] output offset of write-order element w
+  const int32_t* tile_slot_w;  // [T] LDS slot of write-order element w
+  const int64_t* lo_tab;       // [L * 2] (in, out) offsets of the low outer digits
+  const int64_t* hi_tab;       // [Hn * 2] (in, out) offsets of the high outer digits
+  int64_t n_tiles;
+  int32_t L;
+  int32_t T;
+  int32_t slots;               // LDS slots used (>= T, padding included)
+  int64_t base;                // constant input offset
+  const int64_t* base_dev;     // optional extra input offset read on device
+};
+
+// Plain gather: out[w] = in[base + sum_d digit_d(w) * in_stride[d]] over
+// row-major output dims (any shape; used for small tensors).
+constexpr int kMaxRank = 64;
+struct GatherDesc {
+  const float2* in;
+  float2* out;
+  int64_t total;
+  int32_t rank;
+  int64_t ext[kMaxRank];
+  int64_t in_stride[kMaxRank];
+  int64_t base;
+  const int64_t* base_dev;
+};
+
+hipError_t launch_gemm(const GemmDesc& d, GemmKernel kind, Form form, Prec prec, hipStream_t s);
+hipError_t launch_permute(const PermuteDesc& d, hipStream_t s);
+hipError_t launch_gather(const GatherDesc& d, hipStream_t s);
+// acc[i] += sum_s root[s * R + i] (complex64 in, complex128 out), pairwise
+// over s in a fixed tree; hs = number of s.
+hipError_t launch_reduce_fp64(const float2* root, double2* acc, int64_t hs, int64_t R, hipStream_t s);
+// out = sum_i |acc[i]|^2 in FP64 (one value written to *out, device pointer).
+hipError_t launch_norm2(const double2* acc, int64_t R, double* out, hipStream_t s);
+hipError_t launch_fill_zero(void* p, int64_t bytes, hipStream_t s);
+// complex128 -> complex64 conversion (leaf upload).
+hipError_t launch_c128_to_c64(const double2* in, float2* out, int64_t n, hipStream_t s);
+
+}  // namespace tnc

@@ -1,0 +1,156 @@
+"""GPU parity of the two kernels on the hot path, called through the C ABI.
+
+a3 (operand permutation): a bit copy, so the result must be bit-exact with
+numpy.transpose; applying the inverse permutation must give back the input.
+a4 (batched complex GEMM): compared with a complex128 numpy product; the
+tolerance follows from float32 accumulation (unit roundoff 2**-24 times
+~sqrt(k) for random data) and is the 1e-5 relative Frobenius bound of the
+complex64 path.  The split-bf16 form is compared with the FP64 emulation of
+the same three-product arithmetic (exact products, so only float32
+accumulation separates them) and with the exact product (a-priori bound
+3 * 2**-16 per real product).
+"""
+import zlib
+
+import numpy as np
+import pytest
+
+from tests.gpu_util import from_dev, rel_fro, to_dev
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+from oracle import split as osp  # noqa: E402
+from paper_2606_01852_amd import tnc  # noqa: E402
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    assert torch.cuda.is_available()
+    arena = torch.empty(256 << 20, dtype=torch.uint8, device="cuda")
+    c = tnc.Context(0, arena_bytes=arena.numel(), arena_ptr=arena.data_ptr(),
+                    stream=torch.cuda.current_stream().cuda_stream)
+    c._arena = arena
+    yield c
+    c.close()
+
+
+def cn(rng, shape):
+    z = rng.standard_normal(shape + (2,), dtype=np.float32) * np.float32(np.sqrt(0.5))
+    return z.view(np.complex64).reshape(shape)
+
+
+PERM_CASES = [
+    ("binary20", (2,) * 20, None),
+    ("mixed", (3, 4, 5, 2, 7, 6, 2), None),
+    ("tiny", (2, 3, 4), (2, 0, 1)),
+    ("common_inner", (2,) * 16 + (8,), "keep_last"),
+    ("split_large", (64, 96, 2, 50), (3, 1, 0, 2)),
+    ("unit_dims", (1, 2, 1, 2048, 3), (3, 0, 4, 2, 1)),
+    ("identity", (4, 4, 4, 4, 4, 4), (0, 1, 2, 3, 4, 5)),
+    ("binary24_ragged_tile", (2,) * 12 + (3,) + (2,) * 9, None),
+]
+
+
+@pytest.mark.parametrize("name,ext,perm", PERM_CASES, ids=[c[0] for c in PERM_CASES])
+def test_permute_bit_exact(ctx, name, ext, perm):
+    rng = np.random.Generator(np.random.PCG64(zlib.crc32(name.encode())))
+    r = len(ext)
+    if perm is None:
+        perm = tuple(int(x) for x in rng.permutation(r))
+    elif perm == "keep_last":
+        perm = tuple(int(x) for x in rng.permutation(r - 1)) + (r - 1,)
+    x = cn(rng, ext)
+    print(f"permute {name} ext={ext} perm={perm}", flush=True)
+    xd = to_dev(torch, x)
+    yd = torch.empty(x.size, dtype=torch.complex64, device="cuda")
+    tnc.tnc_permute(ctx.handle, xd.data_ptr(), yd.data_ptr(), ext, perm)
+    torch.cuda.synchronize()
+    ref = np.ascontiguousarray(np.transpose(x, perm))
+    got = from_dev(yd).reshape(ref.shape)
+    assert np.array_equal(got.view(np.uint64), ref.view(np.uint64))
+    # the inverse permutation restores the input exactly
+    inv = tuple(int(i) for i in np.argsort(perm))
+    zd = torch.empty_like(yd)
+    tnc.tnc_permute(ctx.handle, yd.data_ptr(), zd.data_ptr(), ref.shape, inv)
+    torch.cuda.synchronize()
+    assert np.array_equal(from_dev(zd).reshape(x.shape).view(np.uint64), x.view(np.uint64))
+
+
+GEMM_SHAPES = [
+    (1, 128, 64, 16),      # exactly one tile
+    (1, 200, 100, 50),     # ragged m, n, k
+    (2, 300, 70, 33),      # odd k: 8-byte loads
+    (3, 1000, 500, 600),   # many tiles, batch
+    (1, 4096, 1024, 256),
+    (5, 10, 3, 4),         # small-shape kernel
+    (7, 64, 32, 16),       # smallest MFMA shape
+    (1, 1, 1, 1),
+]
+
+
+def ref_gemm(A, B):
+    return np.einsum("bik,bjk->bij", A.astype(np.complex128), B.astype(np.complex128))
+
+
+@pytest.mark.parametrize("form", [tnc.GEMM_4M, tnc.GEMM_3M], ids=["4M", "3M"])
+@pytest.mark.parametrize("shape", GEMM_SHAPES, ids=[str(s) for s in GEMM_SHAPES])
+def test_cgemm_matches_numpy(ctx, shape, form):
+    h, m, n, k = shape
+    rng = np.random.Generator(np.random.PCG64(h * 1000003 + m * 1009 + n * 17 + k))
+    A, B = cn(rng, (h, m, k)), cn(rng, (h, n, k))
+    print(f"cgemm form={form} shape={shape}", flush=True)
+    Ad, Bd = to_dev(torch, A), to_dev(torch, B)
+    Cd = torch.empty((h, m, n), dtype=torch.complex64, device="cuda")
+    torch.view_as_real(Cd).fill_(float("nan"))
+    tnc.tnc_batched_cgemm(ctx.handle, h, m, n, k, Ad.data_ptr(), m * k, Bd.data_ptr(), n * k, Cd.data_ptr(),
+                          tnc.PREC_C64, form)
+    torch.cuda.synchronize()
+    got = from_dev(Cd)
+    assert np.all(np.isfinite(got.view(np.float32)))
+    err = rel_fro(got, ref_gemm(A, B))
+    assert err <= 1e-5, err
+
+
+def test_cgemm_broadcast_operand(ctx):
+    h, m, n, k = 4, 256, 96, 40
+    rng = np.random.Generator(np.random.PCG64(77))
+    A, B = cn(rng, (h, m, k)), cn(rng, (1, n, k))
+    Ad, Bd = to_dev(torch, A), to_dev(torch, B)
+    Cd = torch.empty((h, m, n), dtype=torch.complex64, device="cuda")
+    tnc.tnc_batched_cgemm(ctx.handle, h, m, n, k, Ad.data_ptr(), m * k, Bd.data_ptr(), 0, Cd.data_ptr())
+    torch.cuda.synchronize()
+    ref = ref_gemm(A, np.broadcast_to(B, (h, n, k)))
+    assert rel_fro(from_dev(Cd), ref) <= 1e-5
+
+
+def split_emulated_gemm(A, B):
+    def prod3(x, y):
+        xh, xl = osp.split(x)
+        yh, yl = osp.split(y)
+        e = lambda p, q: np.einsum("bik,bjk->bij", p, q)
+        return e(xh, yh) + e(xh, yl) + e(xl, yh)
+    ar, ai = A.real, A.imag
+    br, bi = B.real, B.imag
+    return (prod3(ar, br) - prod3(ai, bi)) + 1j * (prod3(ar, bi) + prod3(ai, br))
+
+
+@pytest.mark.parametrize("shape", [(1, 256, 128, 64), (2, 130, 70, 33), (3, 20, 5, 7)],
+                         ids=["tiles", "ragged", "small"])
+def test_cgemm_bf16x3_matches_split_emulation(ctx, shape):
+    h, m, n, k = shape
+    rng = np.random.Generator(np.random.PCG64(m + n + k))
+    A, B = cn(rng, (h, m, k)), cn(rng, (h, n, k))
+    print(f"cgemm bf16x3 shape={shape}", flush=True)
+    Ad, Bd = to_dev(torch, A), to_dev(torch, B)
+    Cd = torch.empty((h, m, n), dtype=torch.complex64, device="cuda")
+    tnc.tnc_batched_cgemm(ctx.handle, h, m, n, k, Ad.data_ptr(), m * k, Bd.data_ptr(), n * k, Cd.data_ptr(),
+                          tnc.PREC_BF16X3, tnc.GEMM_4M)
+    torch.cuda.synchronize()
+    got = from_dev(Cd)
+    emu = split_emulated_gemm(A, B)
+    exact = ref_gemm(A, B)
+    assert rel_fro(got, emu) <= 1e-5
+    # against the exact product: a-priori bound of the split (3 * 2**-16 per
+    # real product), far looser than the emulation match above
+    assert rel_fro(got, exact) <= 3 * 2.0 ** -16 * 4

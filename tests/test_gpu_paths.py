@@ -1,0 +1,246 @@
+"""GPU parity of whole path executions (C ABI) against the FP64 oracle.
+
+Each case runs the plan on the GPU and compares with the oracle on the same
+seeded inputs (complex64 leaves upcast to complex128):
+  * scalars: |z - z_ref| / |z_ref| <= 1e-5; tensors: relative Frobenius
+    error <= 1e-5 (complex64 path);
+  * split-bf16 paths: against the oracle's split emulation (same products,
+    FP64 sums, complex64 storage per step) within 1e-5: only float32
+    accumulation separates them, the same error class as the complex64 path;
+    against the exact value within max(1e-5, 4 * 2**-16 * D), the a-priori
+    split bound (3 * 2**-16 per real product) compounded once per level of
+    the contraction tree (depth D of the root);
+  * circuit amplitudes also against the brute-force state vector.
+"""
+import numpy as np
+import pytest
+
+from tests.gpu_util import rel_fro
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+from oracle import contract as oc  # noqa: E402
+from oracle import split as osp  # noqa: E402
+from oracle import statevector as osv  # noqa: E402
+from paper_2606_01852_amd import tnc  # noqa: E402
+from workloads import configs  # noqa: E402
+from workloads.circuits import circuit_network, random_circuit  # noqa: E402
+from workloads.grids import prescale_log2, random_grid_network  # noqa: E402
+from workloads.network import Network, Path  # noqa: E402
+from workloads.pairs import pair_network  # noqa: E402
+from workloads.paths import greedy_path, greedy_slice  # noqa: E402
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    assert torch.cuda.is_available()
+    arena = torch.empty(2 << 30, dtype=torch.uint8, device="cuda")
+    c = tnc.Context(0, arena_bytes=arena.numel(), arena_ptr=arena.data_ptr(),
+                    stream=torch.cuda.current_stream().cuda_stream)
+    c._arena = arena
+    yield c
+    c.close()
+
+
+def tree_depth(n_leaves, pairs):
+    depth = [0] * n_leaves
+    for a, b in pairs:
+        depth.append(1 + max(depth[int(a)], depth[int(b)]))
+    return depth[-1]
+
+
+def split_tols(net, path):
+    D = tree_depth(net.n_leaves, path.pairs)
+    return 1e-5, max(1e-5, 4 * 2.0 ** -16 * D)
+
+
+def run(ctx, net, path, prec=tnc.PREC_C64, form=tnc.GEMM_4M, first=0, count=None, max_chunk=None):
+    tn = tnc.Network(ctx, net.labels, net.extents, net.open, net.c64().leaves)
+    plan = tnc.Plan(tn, path.pairs, path.sliced, prec, form)
+    if max_chunk is not None:
+        tnc.tnc_plan_set_max_chunk(plan.handle, max_chunk)
+        plan.info = tnc.tnc_plan_get_info(plan.handle)
+    out = plan.contract(first, count)
+    shape = tuple(int(net.extents[l]) for l in net.open)
+    return out.reshape(shape) if shape else complex(out[0]), plan, tn
+
+
+@pytest.mark.parametrize("form", [tnc.GEMM_4M, tnc.GEMM_3M], ids=["4M", "3M"])
+def test_circuit12_amplitude(ctx, form):
+    circ = configs.circuit12_circuit()
+    net, path = configs.circuit12()
+    print("circuit12 amplitude", form, flush=True)
+    z, _, _ = run(ctx, net, path, form=form)
+    ref = complex(oc.contract(net, path))
+    sv = osv.amplitude(circ.n_qubits, circ.gates, circ.bitstring)
+    print(f"circuit12 {form}: err vs oracle {abs(z - ref) / abs(ref):.2e}")
+    assert abs(z - ref) <= 1e-5 * abs(ref)
+    assert abs(z - sv) <= 1e-5 * abs(sv)
+
+
+def test_circuit12_all_amplitudes_unitarity(ctx):
+    circ = configs.circuit12_circuit()
+    net = circuit_network(circ, open_qubits=range(12))
+    path = greedy_path(net)
+    print("circuit12 all amplitudes", flush=True)
+    amps, plan, _ = run(ctx, net, path)
+    ref = osv.run(12, circ.gates)
+    assert rel_fro(amps, ref) <= 1e-5
+    norm2 = tnc.tnc_plan_result_norm2(plan.handle)
+    assert abs(norm2 - 1.0) <= 1e-5
+    assert abs(norm2 - float(np.sum(np.abs(amps) ** 2))) <= 1e-12
+
+
+def test_circuit12_sliced_and_chunking_invariance(ctx):
+    net, path = configs.circuit12()
+    sl = greedy_slice(net, path.pairs, n_sliced=4)
+    p = Path(path.pairs, sl)
+    ref = complex(oc.contract(net, p))
+    vals = []
+    for mc in (1, 2, 16):
+        print("circuit12 sliced, max_chunk", mc, flush=True)
+        z, plan, _ = run(ctx, net, p, max_chunk=mc)
+        assert plan.info.max_chunk == mc
+        vals.append(z)
+        assert abs(z - ref) <= 1e-5 * abs(ref)
+    assert max(abs(v - vals[0]) for v in vals) <= 1e-13 * abs(vals[0])
+    # partial ranges and single slices
+    z3, _, _ = run(ctx, net, p, first=3, count=9)
+    ref3 = complex(oc.contract(net, p, slices=range(3, 12)))
+    assert abs(z3 - ref3) <= 1e-5 * abs(ref3)
+    z7, _, _ = run(ctx, net, p, first=7, count=1)
+    ref7 = complex(oc.contract(net, p, slices=[7]))
+    assert abs(z7 - ref7) <= 1e-5 * abs(ref7)
+
+
+def test_circuit12_split_precision(ctx):
+    net, path = configs.circuit12()
+    print("circuit12 bf16x3", flush=True)
+    z, _, _ = run(ctx, net, path, prec=tnc.PREC_BF16X3)
+    emu = complex(oc.contract(net, path, step=osp.split_step))
+    exact = complex(oc.contract(net, path))
+    t_emu, t_exact = split_tols(net, path)
+    print(f"depth {tree_depth(net.n_leaves, path.pairs)}: err vs emulation {abs(z - emu) / abs(emu):.2e} "
+          f"(tol {t_emu:.1e}), vs exact {abs(z - exact) / abs(exact):.2e} (tol {t_exact:.1e})")
+    assert abs(z - emu) <= t_emu * abs(emu)
+    assert abs(z - exact) <= t_exact * abs(exact)
+
+
+def test_circuit20_sliced_sum_matches_statevector(ctx):
+    circ = random_circuit(4, 5, 10, seed=77)
+    net = circuit_network(circ)
+    path = greedy_path(net)
+    sl = greedy_slice(net, path.pairs, n_sliced=6)
+    p = Path(path.pairs, sl)
+    print("circuit20 sliced", sl, flush=True)
+    z, plan, _ = run(ctx, net, p)
+    # the state vector with the same complex64-rounded gates the GPU uses,
+    # so that only the arithmetic differs
+    gates64 = [(q, u.astype(np.complex64).astype(np.complex128)) for q, u in circ.gates]
+    sv = osv.amplitude(20, gates64, circ.bitstring)
+    ref = complex(oc.contract(net, p))
+    assert plan.info.n_slices == 64
+    print(f"circuit20 sliced: err vs state vector {abs(z - sv) / abs(sv):.2e}, vs oracle {abs(z - ref) / abs(ref):.2e}")
+    assert abs(ref - sv) <= 1e-12 * abs(sv)
+    assert abs(z - sv) <= 1e-5 * abs(sv)
+    for s in (0, 17, 63):
+        zs, _, _ = run(ctx, net, p, first=s, count=1)
+        rs = complex(oc.contract(net, p, slices=[s]))
+        assert abs(zs - rs) <= 1e-5 * abs(rs)
+
+
+def prescaled_grid(rows, cols, bond, seed):
+    g = random_grid_network(rows, cols, bond, seed=seed)
+    e = prescale_log2(g.labels)
+    leaves = [x * 2.0 ** int(k) for x, k in zip(g.leaves, e)]
+    return Network(leaves, g.labels, g.extents, ()), int(e.sum())
+
+
+@pytest.mark.parametrize("prec", [tnc.PREC_C64, tnc.PREC_BF16X3], ids=["c64", "bf16x3"])
+def test_grid8_bond4(ctx, prec):
+    net, shift = prescaled_grid(8, 8, 4, seed=1002)
+    path = greedy_path(net)
+    print("grid8 prec", prec, flush=True)
+    z, plan, _ = run(ctx, net, path, prec=prec)
+    exact = complex(oc.contract(net, path))
+    if prec == tnc.PREC_C64:
+        print(f"grid8 c64: err vs oracle {abs(z - exact) / abs(exact):.2e}")
+        assert abs(z - exact) <= 1e-5 * abs(exact)
+    else:
+        emu = complex(oc.contract(net, path, step=osp.split_step))
+        t_emu, t_exact = split_tols(net, path)
+        print(f"grid8 bf16x3: err vs emulation {abs(z - emu) / abs(emu):.2e} (tol {t_emu:.1e}), "
+              f"vs exact {abs(z - exact) / abs(exact):.2e} (tol {t_exact:.1e})")
+        assert abs(z - emu) <= t_emu * abs(emu)
+        assert abs(z - exact) <= t_exact * abs(exact)
+    # the unscaled value is tiny but representable in FP64
+    assert 0 < abs(z) * 2.0 ** -shift < 1e-20
+
+
+def test_pair_permuted_operands(ctx):
+    net, path = pair_network(10, 9, 8, seed=3)
+    print("pair 10/9/8", flush=True)
+    got, plan, _ = run(ctx, net, path)
+    assert plan.info.n_permutes == 2
+    ref = oc.contract(net, path)
+    assert rel_fro(got, ref) <= 1e-5
+
+
+def test_pair_batch(ctx):
+    net, path = pair_network(8, 7, 6, seed=4, batch=8)
+    print("pair batch", flush=True)
+    got, plan, _ = run(ctx, net, path)
+    assert plan.step(0).h == 8
+    assert rel_fro(got, oc.contract(net, path)) <= 1e-5
+
+
+def test_direct_device_output_single_contraction(ctx):
+    net, path = pair_network(9, 8, 7, seed=5)
+    tn = tnc.Network(ctx, net.labels, net.extents, net.open, net.c64().leaves)
+    plan = tnc.Plan(tn, path.pairs)
+    out = torch.empty(plan.info.n_result, dtype=torch.complex64, device="cuda")
+    tnc.tnc_contract_async(plan.handle, 0, 1, out.data_ptr(), tnc.OUT_C64)
+    torch.cuda.synchronize()
+    ref = oc.contract(net, path)
+    assert rel_fro(out.cpu().numpy().reshape(ref.shape), ref) <= 1e-5
+
+
+def test_degenerate_networks(ctx):
+    rng = np.random.Generator(np.random.PCG64(8))
+    # one leaf, no steps, result in a permuted order
+    x = (rng.standard_normal((2, 3, 4)) + 1j * rng.standard_normal((2, 3, 4))).astype(np.complex64)
+    net = Network([x], [(0, 1, 2)], np.array([2, 3, 4]), (2, 0, 1))
+    got, _, _ = run(ctx, net, Path(np.zeros((0, 2), dtype=np.int32)))
+    assert np.array_equal(got, np.transpose(x, (2, 0, 1)).astype(np.complex128))
+    # outer product (no shared label, k = 1) and an extent-1 label
+    a = (rng.standard_normal((5, 1)) + 0j).astype(np.complex64)
+    b = (rng.standard_normal((1, 7)) + 0j).astype(np.complex64)
+    c = (rng.standard_normal((3,)) + 0j).astype(np.complex64)
+    net = Network([a, b, c], [(0, 1), (1, 2), (3,)], np.array([5, 1, 7, 3]), (3, 2, 0))
+    path = Path(np.array([[0, 1], [3, 2]], dtype=np.int32))
+    got, _, _ = run(ctx, net, path)
+    assert rel_fro(got, oc.contract(net, path)) <= 1e-6
+    # closed scalar network of two vectors
+    u = (rng.standard_normal(6) + 1j * rng.standard_normal(6)).astype(np.complex64)
+    v = (rng.standard_normal(6) + 1j * rng.standard_normal(6)).astype(np.complex64)
+    net = Network([u, v], [(0,), (0,)], np.array([6]), ())
+    got, _, _ = run(ctx, net, Path(np.array([[0, 1]], dtype=np.int32)))
+    ref = complex(np.sum(u.astype(np.complex128) * v.astype(np.complex128)))
+    assert abs(got - ref) <= 1e-6 * abs(ref)
+
+
+def test_device_errors_are_status_codes(ctx):
+    net, path = configs.circuit12()
+    tn = tnc.Network(ctx, net.labels, net.extents, net.open, net.c64().leaves)
+    plan = tnc.Plan(tn, path.pairs)
+    with pytest.raises(tnc.TncError) as e:
+        tnc.tnc_contract(plan.handle, 0, 2, 1)      # only one slice exists
+    assert e.value.status == tnc.E_ARG
+    small = tnc.Context(0, arena_bytes=4096)
+    tn2 = tnc.Network(small, net.labels, net.extents, net.open, net.c64().leaves)
+    with pytest.raises(tnc.TncError) as e:
+        tnc.Plan(tn2, path.pairs)
+    assert e.value.status == tnc.E_NOMEM
+    # the context still works afterwards
+    assert abs(plan.contract()[0]) > 0

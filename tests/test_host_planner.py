@@ -1,0 +1,207 @@
+"""Host-side tests of the C ABI library (no GPU needed).
+
+The library is loaded and every symbol the header declares must be exported.
+Plans built on a host-only context are compared with the oracle's reordering
+pass (paper Sec. IV-A) and cost model (Sec. II-B): orders and step groups are
+integer data and must match exactly.
+"""
+import json
+import os
+import re
+
+import numpy as np
+import pytest
+
+from oracle import costs as ocost
+from oracle import reorder as orr
+from paper_2606_01852_amd import tnc
+from workloads import configs
+from workloads.grids import random_grid_network
+from workloads.network import Network
+from workloads.paths import greedy_path, greedy_slice, random_greedy_path
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def header_functions():
+    text = open(os.path.join(ROOT, "include", "tnc.h")).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(tnc_[a-z0-9_]+)\s*\(", text)))
+
+
+def test_library_exports_every_declared_symbol():
+    L = tnc.lib()
+    names = header_functions()
+    assert len(names) >= 25
+    for name in names:
+        assert hasattr(L, name), name
+    assert set(names) == set(tnc.exported_symbols())
+    assert "gfx950" in tnc.tnc_version()
+
+
+@pytest.fixture(scope="module")
+def hctx():
+    return tnc.Context(-1)
+
+
+def plan_for(hctx, net, path, sliced=()):
+    tn = tnc.Network(hctx, net.labels, net.extents, net.open)
+    return tn, tnc.Plan(tn, path.pairs, sliced)
+
+
+def compare_with_oracle(plan, net, path, sliced=()):
+    rm = set(sliced)
+    labels = [tuple(l for l in lab if l not in rm) for lab in net.labels]
+    target, steps = orr.reorder(labels, path.pairs, net.open)
+    n_ids = net.n_leaves + len(path.pairs)
+    for i in range(n_ids):
+        assert plan.order(i) == target[i], i
+    costs = ocost.step_costs(steps, target, net.extents)
+    for s, (st, c) in enumerate(zip(steps, costs)):
+        si = plan.step(s)
+        assert (si.A, si.B, si.C) == (st["A"], st["B"], st["C"]), s
+        assert (si.nH, si.nM, si.nN, si.nK) == tuple(len(st[g]) for g in "HMNK"), s
+        assert (si.h, si.m, si.n, si.k) == (c["h"], c["m"], c["n"], c["k"]), s
+        assert bool(si.natural) == st["natural"], s
+    tot = ocost.path_totals(costs)
+    assert plan.info.flops_per_slice == pytest.approx(tot["flops"], rel=1e-12)
+    assert plan.info.bytes_per_slice == pytest.approx(8 * tot["Cm"], rel=1e-12)
+    return target, steps
+
+
+def test_fig3_example_through_the_library(hctx, golden_dir):
+    d = json.load(open(os.path.join(golden_dir, "fig3_reorder.json")))
+    L = d["labels"]
+    lab = lambda s: tuple(L[c] for c in s)
+    labels = [lab(d["leaves"][n]) for n in ("I1", "I2", "I3")]
+    ids = {"I1": 0, "I2": 1, "I3": 2, "I4": 3, "I5": 4}
+    pairs = np.array([[ids[a], ids[b]] for a, b in d["pairs"]], dtype=np.int32)
+    tn = tnc.Network(hctx, labels, np.full(8, 2), lab(d["root_order"]))
+    plan = tnc.Plan(tn, pairs)
+    for name, want in d["expected"].items():
+        assert tuple(plan.order(ids[name])) == lab(want), name
+    assert plan.step(0).natural == 0 and plan.step(1).natural == 0
+    assert plan.info.n_permuted_stores == 2
+
+
+def _random_tree_network(rng, n_leaves, n_open):
+    labels = [[] for _ in range(n_leaves)]
+    nxt = 0
+    for t in range(1, n_leaves):
+        s = int(rng.integers(0, t))
+        labels[s].append(nxt); labels[t].append(nxt); nxt += 1
+    for _ in range(n_leaves):
+        s, t = rng.choice(n_leaves, 2, replace=False)
+        labels[s].append(nxt); labels[t].append(nxt); nxt += 1
+    opn = []
+    for _ in range(n_open):
+        t = int(rng.integers(0, n_leaves))
+        labels[t].append(nxt); opn.append(nxt); nxt += 1
+    labels = [tuple(int(x) for x in rng.permutation(l)) for l in labels]
+    ext = rng.integers(1, 4, size=nxt).astype(np.int64)
+    return Network([None] * n_leaves, labels, ext, tuple(opn))
+
+
+@pytest.mark.parametrize("seed", range(20))
+def test_planner_matches_oracle_on_random_trees(hctx, seed):
+    rng = np.random.Generator(np.random.PCG64(500 + seed))
+    net = _random_tree_network(rng, int(rng.integers(2, 24)), int(rng.integers(0, 5)))
+    path = random_greedy_path(net, seed=seed)
+    tn, plan = plan_for(hctx, net, path)
+    compare_with_oracle(plan, net, path)
+
+
+def test_planner_matches_oracle_on_workloads(hctx):
+    net, path = configs.circuit12()
+    tn, plan = plan_for(hctx, net, path)
+    compare_with_oracle(plan, net, path)
+    assert plan.info.n_steps == 153 and plan.info.n_result == 1
+    g = random_grid_network(8, 8, 4, seed=1002)
+    gp = greedy_path(g)
+    tn2, plan2 = plan_for(hctx, g, gp)
+    compare_with_oracle(plan2, g, gp)
+
+
+def test_planner_with_slices_matches_sliced_oracle(hctx):
+    net, path = configs.circuit12()
+    sl = greedy_slice(net, path.pairs, n_sliced=3)
+    tn, plan = plan_for(hctx, net, path, sl)
+    compare_with_oracle(plan, net, path, sl)
+    assert plan.info.n_slices == 8
+
+
+def test_pair_batch_structure(hctx):
+    net, path = configs.pair_batch(batch=64)
+    tn, plan = plan_for(hctx, net, path)
+    s = plan.step(0)
+    assert (s.h, s.m, s.n, s.k) == (64, 1024, 256, 1024)
+    assert s.natural == 1 and plan.info.n_permutes == 2
+    assert plan.info.flops_per_slice == 8 * 64 * 1024 * 256 * 1024
+
+
+def test_pair30_structure(hctx):
+    net, path = configs.pair30.__wrapped__() if hasattr(configs.pair30, "__wrapped__") else (None, None)
+    # structure only: labels without data (the 2^30 entries are not generated here)
+    M, K, N = list(range(16)), list(range(16, 30)), list(range(30, 44))
+    rng = np.random.Generator(np.random.PCG64(1))
+    labels = [tuple(int(x) for x in rng.permutation(M + K)), tuple(int(x) for x in rng.permutation(N + K))]
+    tn = tnc.Network(hctx, labels, np.full(44, 2), M + N)
+    plan = tnc.Plan(tn, np.array([[0, 1]], dtype=np.int32))
+    s = plan.step(0)
+    assert (s.m, s.n, s.k) == (2 ** 16, 2 ** 14, 2 ** 14) and s.kernel == 0
+    assert plan.order(0) == M + K and plan.order(1) == N + K
+    assert plan.info.flops_per_slice == 8.0 * 2 ** 44
+    assert plan.info.transpose_bytes == 16.0 * (2 ** 30 + 2 ** 28)
+
+
+def test_errors_are_reported_not_raised_across_the_abi(hctx):
+    with pytest.raises(tnc.TncError) as e:       # closed hyperedge
+        tnc.Network(hctx, [(0, 1), (1, 2), (1, 3)], [2, 2, 2, 2], [0, 2, 3])
+    assert e.value.status == tnc.E_ARG and "joins exactly two" in str(e.value)
+    with pytest.raises(tnc.TncError) as e:       # dangling closed label
+        tnc.Network(hctx, [(0, 1), (1,)], [2, 2], [])
+    assert e.value.status == tnc.E_ARG
+    tn = tnc.Network(hctx, [(0, 1), (1, 2), (2,)], [2, 2, 2], [0])
+    with pytest.raises(tnc.TncError) as e:       # id consumed twice
+        tnc.Plan(tn, np.array([[0, 1], [0, 2]]))
+    assert e.value.status == tnc.E_PATH
+    with pytest.raises(tnc.TncError) as e:       # not a full tree
+        tnc.Plan(tn, np.array([[0, 1]]))
+    assert e.value.status == tnc.E_PATH
+    with pytest.raises(tnc.TncError) as e:       # slicing an open label
+        tnc.Plan(tn, np.array([[0, 1], [3, 2]]), sliced=[0])
+    assert e.value.status == tnc.E_ARG
+    # a host-only context with a budget reports planned peaks above it
+    small = tnc.Context(-1, arena_bytes=1024)
+    net, path = configs.circuit12()
+    tn2 = tnc.Network(small, net.labels, net.extents, net.open)
+    with pytest.raises(tnc.TncError) as e:
+        tnc.Plan(tn2, path.pairs)
+    assert e.value.status == tnc.E_NOMEM
+    assert tnc.lib().tnc_last_error().decode()
+
+
+def test_memory_plan_and_chunking(hctx):
+    net, path = configs.circuit40(n_sliced=16)
+    tn = tnc.Network(tnc.Context(-1, arena_bytes=8 << 30), net.labels, net.extents, net.open)
+    plan = tnc.Plan(tn, path.pairs, path.sliced)
+    info = plan.info
+    assert info.n_slices == 2 ** 16
+    assert info.max_intermediate <= 2 ** 19
+    # first-fit placement stays close to the live-bytes lower bound: at each
+    # step the tensors alive (intermediates not yet consumed, the step's
+    # operands and result) must all be resident
+    from workloads.paths import path_tensors
+    tens, _ = path_tensors(net, path.pairs, path.sliced)
+    size = [int(np.prod([net.extents[l] for l in t])) * 8 for t in tens]
+    n = net.n_leaves
+    consumer = {}
+    for s_, (a, b) in enumerate(path.pairs):
+        consumer[int(a)] = consumer[int(b)] = s_
+    ns = len(path.pairs)
+    lb = 0
+    for s_ in range(ns):
+        live = sum(size[n + q] for q in range(ns) if q <= s_ <= consumer.get(n + q, ns))
+        lb = max(lb, live)
+    assert lb <= info.peak_bytes <= 1.5 * lb + (1 << 20)
+    assert info.max_chunk >= 64 and info.chunk_peak_bytes <= 8 << 30
