@@ -53,6 +53,13 @@ def parse():
     ap.add_argument("--prec", choices=["c64", "bf16x3"], default="c64")
     ap.add_argument("--scale", type=int, default=0, help="drop this many modes from each group (smaller run)")
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--workload", choices=["pair30", "circuit40"], default="pair30")
+    ap.add_argument("--slices", type=int, default=0, help="circuit40: slices per run (0 = all)")
+    ap.add_argument("--arena-gib", type=float, default=64.0, help="circuit40: arena size")
+    ap.add_argument("--max-chunk", type=int, default=0, help="circuit40: cap on slices per batch")
+    ap.add_argument("--graph", action="store_true", help="circuit40: replay chunks as hipGraphs")
+    ap.add_argument("--probe-copy", action="store_true",
+                    help="after timing, run one 4 GiB device-to-device copy (calibrates HBM counters)")
     return ap.parse_args()
 
 
@@ -96,12 +103,76 @@ def cpu_baseline(net_a, path_a, net_b, path_b, budget_s: float = 20.0):
                       f"batch entries ({dt2:.1f} s); numpy complex128 tensordot incl. operand transposes"}
 
 
+def bench_circuit40(args):
+    """Sliced 40-qubit circuit (5x8 grid, depth 12, 16 sliced labels = 65,536
+    slices): the slices run as a batch dimension of every step, summed in FP64."""
+    import torch
+
+    from paper_2606_01852_amd import tnc
+    from workloads import configs
+
+    log("building circuit40 network, path and slices")
+    net, path = configs.circuit40()
+    stream = torch.cuda.current_stream()
+    arena_bytes = int(args.arena_gib * (1 << 30))
+    arena = torch.empty(arena_bytes, dtype=torch.uint8, device="cuda")
+    ctx = tnc.Context(0, arena_bytes=arena_bytes, arena_ptr=arena.data_ptr(), stream=stream.cuda_stream)
+    prec = tnc.PREC_BF16X3 if args.prec == "bf16x3" else tnc.PREC_C64
+    form = tnc.GEMM_3M if args.form == "3M" else tnc.GEMM_4M
+    tn = tnc.Network(ctx, net.labels, net.extents, net.open, net.c64().leaves)
+    plan = tnc.Plan(tn, path.pairs, path.sliced, prec, form)
+    if args.max_chunk:
+        tnc.tnc_plan_set_max_chunk(plan.handle, args.max_chunk)
+    if args.graph:
+        tnc.tnc_plan_set_graph(plan.handle, True)
+    info = tnc.tnc_plan_get_info(plan.handle)
+    n = args.slices or info.n_slices
+    log(f"slices {n} of {info.n_slices}; chunk {info.max_chunk}; chunk peak {info.chunk_peak_bytes / 2**30:.1f} GiB; "
+        f"{info.flops_per_slice:.3e} FLOP per slice")
+    for _ in range(args.warmup):
+        plan.contract(0, n)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        z = plan.contract(0, n)
+    dt = (time.perf_counter() - t0) / args.steps
+    tnc.tnc_plan_set_profile(plan.handle, True)
+    plan.contract(0, n)
+    per_step = []
+    for s in range(info.n_steps):
+        ms, cnt = tnc.tnc_plan_get_profile(plan.handle, s)
+        per_step.append((ms, s))
+    perm_ms, perm_n = tnc.tnc_plan_get_profile(plan.handle, -1)
+    red_ms, red_n = tnc.tnc_plan_get_profile(plan.handle, -2)
+    per_step.sort(reverse=True)
+    tot = sum(x[0] for x in per_step)
+    log(f"profiled run: GEMMs {tot:.1f} ms, leaf permutes {perm_ms:.1f} ms ({perm_n}), reductions {red_ms:.2f} ms")
+    for ms, s in per_step[:12]:
+        st = tnc.tnc_plan_get_step(plan.handle, s)
+        log(f"  step {s:4d}: {ms:8.2f} ms  m {st.m} n {st.n} k {st.k} kernel {st.kernel} natural {st.natural}")
+    n_chunks = max(1, n // info.max_chunk)
+    exec_flops = info.chunk_flops * n_chunks if n % info.max_chunk == 0 else info.flops_per_slice * n
+    value = exec_flops / dt / 1e12
+    log(f"executed {exec_flops:.3e} FLOP ({info.flops_per_slice * n:.3e} without hoisting slice-invariant steps)")
+    res = {"metric": "complex TFLOP/s of path execution (% MFMA peak) + p50/p99 request latency",
+           "value": round(value, 3), "unit": "complex TFLOP/s", "n_gpus": 1, "steps": args.steps,
+           "warmup": args.warmup, "ms_per_step": round(dt * 1e3, 3), "higher_is_better": True,
+           "scaling": "weak", "vs_baseline": None, "dtype": "c64/fp32" if prec == tnc.PREC_C64 else "c64/bf16x3",
+           "data": "synthetic",
+           "config": {"workload": "circuit40: 5x8 grid, depth 12, 16 sliced labels", "slices": n,
+                      "chunk": info.max_chunk, "amplitude": [z[0].real, z[0].imag],
+                      "per_slice_equivalent_tflops": round(info.flops_per_slice * n / dt / 1e12, 3)}}
+    print(json.dumps(res), flush=True)
+
+
 def main():
     args = parse()
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU; multi-GPU execution is not part of it",
                           "n_gpus": args.gpus}))
         sys.exit(2)
+    if args.workload == "circuit40":
+        return bench_circuit40(args)
     import torch
 
     from paper_2606_01852_amd import tnc
@@ -192,6 +263,14 @@ def main():
                     "permute_ms_per_launch": round(perm_ms / max(perm_n, 1), 3),
                     "batch_gemm_ms": round(bgemm_ms / max(bgemm_n, 1), 3)},
     }
+    if args.probe_copy:
+        src = torch.empty(4 << 30, dtype=torch.uint8, device=dev)
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        log("copy probe: 4 GiB read + 4 GiB written")
+        del src, dst
     if not args.no_cpu:
         log("cpu baseline (oracle on a bounded sample)")
         res["cpu_baseline"] = cpu_baseline(net_a, path_a, net_b, path_b)

@@ -135,6 +135,8 @@ typedef struct {
   int64_t peak_bytes;            /* arena bytes of one slice                   */
   int64_t max_chunk;             /* slices executed together (batch)           */
   int64_t chunk_peak_bytes;      /* arena bytes of a max_chunk batch           */
+  double chunk_flops;            /* FLOPs executed by one max_chunk batch: the
+                                    slice-invariant steps run once per batch  */
   int32_t n_steps;
   int32_t n_permutes;            /* leaves permuted before use                 */
   int32_t n_permuted_stores;     /* steps whose output order interleaves M, N  */
@@ -150,7 +152,8 @@ typedef struct {
   int32_t nH, nM, nN, nK;
   int64_t h, m, n, k;
   int32_t natural;
-  int32_t kernel;                /* 0 = MFMA tiles, 1 = small-shape VALU kernel */
+  int32_t kernel;                /* 0 = MFMA tiles, 1 = small-shape VALU kernel,
+                                    2 = long-K dot kernel (k large, m*n tiny)  */
 } tnc_step_info;
 tnc_status tnc_plan_get_step(tnc_plan plan, int32_t step, tnc_step_info* out);
 /* Mode order (labels) tensor `id` is stored in when the plan runs one slice:

@@ -315,6 +315,7 @@ tnc_status tnc_plan_get_info(tnc_plan plan, tnc_plan_info* out) {
   info.peak_bytes = c0.peak;
   info.max_chunk = p.suffix_prod[p.j_max];
   info.chunk_peak_bytes = cm.peak;
+  info.chunk_flops = cm.flops;
   info.n_steps = static_cast<int32_t>(p.pairs.size());
   info.n_permutes = c0.n_permutes;
   info.n_permuted_stores = c0.n_perm_stores;
@@ -597,7 +598,7 @@ tnc_status tnc_batched_cgemm(tnc_ctx ctx, int64_t h, int64_t m, int64_t n, int64
       d.bshift[0] = sh;
     }
   }
-  const GemmKernel kind = (m >= 64 && n >= 32 && k >= 16) ? GemmKernel::MFMA : GemmKernel::SMALL;
+  const GemmKernel kind = choose_gemm_kernel(h, m, n, k);
   check_hip(launch_gemm(d, kind, form == TNC_GEMM_3M ? Form::M3 : Form::M4,
                         prec == TNC_PREC_BF16X3 ? Prec::BF16X3 : Prec::C64, c.stream),
             "gemm launch");

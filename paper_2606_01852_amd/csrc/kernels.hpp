@@ -32,7 +32,16 @@ struct GemmDesc {
 
 enum class Form : int { M4 = 0, M3 = 1 };
 enum class Prec : int { C64 = 0, BF16X3 = 1 };
-enum class GemmKernel : int { MFMA = 0, SMALL = 1 };
+enum class GemmKernel : int { MFMA = 0, SMALL = 1, DOT = 2 };
+
+// Kernel choice for one step's shape (shared by the planner and the
+// stand-alone GEMM entry point).
+inline GemmKernel choose_gemm_kernel(int64_t h, int64_t m, int64_t n, int64_t k) {
+  const int64_t tiles = ((m + 127) / 128) * ((n + 63) / 64) * h;
+  if (m >= 64 && n >= 32 && k >= 16 && tiles < (int64_t{1} << 24)) return GemmKernel::MFMA;
+  if (k >= 256 && m * n <= 64 && (h * m * n + 3) / 4 < 0x7FFFFF) return GemmKernel::DOT;
+  return GemmKernel::SMALL;
+}
 
 // Tiled gather-permute of complex64: out (contiguous) gets, for every tile
 // t < n_tiles and element e < T of the tile,

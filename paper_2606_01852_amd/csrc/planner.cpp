@@ -529,9 +529,7 @@ std::unique_ptr<ChunkPlan> build_chunk(const Plan& plan, int j) {
       fill(sp.N, sp.offN);
       cp->n_perm_stores++;
     }
-    bool big = sp.m >= 64 && sp.n >= 32 && sp.k >= 16;
-    if (big && ((sp.m + 127) / 128) * ((sp.n + 63) / 64) * sp.h >= (int64_t{1} << 24)) big = false;
-    sp.kind = big ? GemmKernel::MFMA : GemmKernel::SMALL;
+    sp.kind = choose_gemm_kernel(sp.h, sp.m, sp.n, sp.k);
     cp->flops += 8.0 * static_cast<double>(sp.h) * sp.m * sp.n * sp.k;
     cp->bytes += 8.0 * (static_cast<double>(sp.hA) * sp.m * sp.k + static_cast<double>(sp.hB) * sp.n * sp.k +
                         static_cast<double>(sp.h) * sp.m * sp.n);

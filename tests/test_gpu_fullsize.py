@@ -1,0 +1,126 @@
+"""Parity at the benchmark sizes, in the launch configuration bench.py times.
+
+pair30 (A 2^30, B 2^28, C 2^30 complex64): the oracle cannot hold the whole
+product, so the result is checked
+  * everywhere at once by Freivalds' test: ||C r - A (B^T r)|| / (||A|| ||B^T r||)
+    for a random complex vector r (float32 accumulation bounds it by a few
+    times sqrt(k) * 2^-24; 1e-5 is used), and
+  * exactly on sampled full rows, each computed by the oracle's tensordot
+    from the same leaves (relative Frobenius error <= 1e-5).
+pair_batch (64 x 20/18 modes): the whole result against the oracle.
+circuit40 (65,536 slices): single seeded slices and a batched chunk of 256
+slices against the oracle's per-slice contraction.
+"""
+import numpy as np
+import pytest
+
+from tests.gpu_util import rel_fro
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+from oracle import contract as oc  # noqa: E402
+from paper_2606_01852_amd import tnc  # noqa: E402
+from workloads import configs  # noqa: E402
+from workloads.network import Network, Path  # noqa: E402
+
+
+def make_ctx(gib):
+    arena = torch.empty(int(gib * (1 << 30)), dtype=torch.uint8, device="cuda")
+    c = tnc.Context(0, arena_bytes=arena.numel(), arena_ptr=arena.data_ptr(),
+                    stream=torch.cuda.current_stream().cuda_stream)
+    c._arena = arena
+    return c
+
+
+def test_pair30_full_size_freivalds_and_rows():
+    print("pair30: generating inputs", flush=True)
+    net, path = configs.pair30()
+    a, b = net.leaves
+    la, lb = net.labels
+    M, K, N = list(range(16)), list(range(16, 30)), list(range(30, 44))
+    ctx = make_ctx(18.5)
+    tn = tnc.Network(ctx, net.labels, net.extents, net.open, net.leaves)
+    plan = tnc.Plan(tn, path.pairs)
+    out = torch.empty(plan.info.n_result, dtype=torch.complex64, device="cuda")
+    print("pair30: contracting", flush=True)
+    tnc.tnc_contract_async(plan.handle, 0, 1, out.data_ptr(), tnc.OUT_C64)
+    torch.cuda.synchronize()
+    C = out.cpu().numpy().reshape(2 ** 16, 2 ** 14)
+    del out
+    print("pair30: Freivalds", flush=True)
+    Am = np.transpose(a, [la.index(l) for l in M + K]).reshape(2 ** 16, 2 ** 14)
+    Bm = np.transpose(b, [lb.index(l) for l in N + K]).reshape(2 ** 14, 2 ** 14)
+    rng = np.random.Generator(np.random.PCG64(31))
+    r = (rng.standard_normal(2 ** 14) + 1j * rng.standard_normal(2 ** 14)) / np.sqrt(2)
+    Btr = Bm.astype(np.complex128).T @ r                      # sum_j B[j, l] r[j]
+    lhs = np.empty(2 ** 16, dtype=np.complex128)
+    rhs = np.empty(2 ** 16, dtype=np.complex128)
+    for i0 in range(0, 2 ** 16, 4096):
+        lhs[i0:i0 + 4096] = C[i0:i0 + 4096].astype(np.complex128) @ r
+        rhs[i0:i0 + 4096] = Am[i0:i0 + 4096].astype(np.complex128) @ Btr
+    normA = np.sqrt(sum(float(np.sum(np.abs(Am[i0:i0 + 4096].astype(np.complex128)) ** 2))
+                        for i0 in range(0, 2 ** 16, 4096)))
+    frei = np.linalg.norm(lhs - rhs) / (normA * np.linalg.norm(Btr))
+    print(f"pair30: Freivalds ratio {frei:.2e}", flush=True)
+    assert frei <= 1e-5
+    # sampled rows through the oracle's own contraction of the sub-network
+    rows = rng.choice(2 ** 16, 8, replace=False)
+    for i in rows:
+        digits = [(int(i) >> (15 - q)) & 1 for q in range(16)]
+        fix = dict(zip(M, digits))
+        idx = tuple(fix[l] if l in fix else slice(None) for l in la)
+        sub = Network([np.ascontiguousarray(a[idx]), b], [tuple(l for l in la if l not in fix), lb],
+                      net.extents, tuple(N))
+        ref = oc.contract(sub, Path(path.pairs, ())).reshape(-1)
+        err = rel_fro(C[i], ref)
+        assert err <= 1e-5, (i, err)
+    plan.close()
+    tn.close()
+    ctx.close()
+
+
+def test_pair_batch_full_size():
+    net, path = configs.pair_batch(64)
+    ctx = make_ctx(2)
+    tn = tnc.Network(ctx, net.labels, net.extents, net.open, net.leaves)
+    plan = tnc.Plan(tn, path.pairs)
+    out = torch.empty(plan.info.n_result, dtype=torch.complex64, device="cuda")
+    tnc.tnc_contract_async(plan.handle, 0, 1, out.data_ptr(), tnc.OUT_C64)
+    torch.cuda.synchronize()
+    got = out.cpu().numpy()
+    ref = oc.contract(net, path).reshape(-1)
+    err = rel_fro(got, ref)
+    print(f"pair_batch: err {err:.2e}", flush=True)
+    assert err <= 1e-5
+
+
+def test_circuit40_sampled_slices():
+    """Per-slice amplitudes of a random circuit are Porter-Thomas distributed:
+    many slices sit far below the typical magnitude, where float32
+    cancellation alone exceeds 1e-5 of |z| (the oracle's own complex64
+    evaluation along this path does).  Errors are therefore bounded by 1e-5
+    of the root-mean-square amplitude of the sampled ensemble, and the
+    relative errors are printed as the measured distribution."""
+    net, path = configs.circuit40()
+    ctx = make_ctx(16)
+    tn = tnc.Network(ctx, net.labels, net.extents, net.open, net.c64().leaves)
+    plan = tnc.Plan(tn, path.pairs, path.sliced)
+    assert plan.info.n_slices == 65536
+    rng = np.random.Generator(np.random.PCG64(1003))
+    sample = [int(x) for x in rng.choice(65536, 24, replace=False)]
+    got = np.array([complex(plan.contract(s, 1)[0]) for s in sample])
+    ref = np.array([complex(oc.contract(net, path, slices=[s])) for s in sample])
+    rms = np.sqrt(np.mean(np.abs(ref) ** 2))
+    rel = np.abs(got - ref) / np.abs(ref)
+    print(f"circuit40 slices: relative errors median {np.median(rel):.2e} max {rel.max():.2e}; "
+          f"max error / rms amplitude {np.max(np.abs(got - ref)) / rms:.2e}", flush=True)
+    assert np.max(np.abs(got - ref)) <= 1e-5 * rms
+    # a batched chunk of 256 slices, summed in FP64 on the device
+    refs = np.array([complex(oc.contract(net, path, slices=[s])) for s in range(256, 512)])
+    tot = complex(plan.contract(256, 256)[0])
+    scale = np.sqrt(np.sum(np.abs(refs) ** 2))
+    err = abs(tot - refs.sum())
+    print(f"circuit40 slices [256, 512): |err| / |sum| {err / abs(refs.sum()):.2e}, "
+          f"|err| / sqrt(sum |z_s|^2) {err / scale:.2e}", flush=True)
+    assert err <= 1e-5 * scale

@@ -86,6 +86,8 @@ GEMM_SHAPES = [
     (5, 10, 3, 4),         # small-shape kernel
     (7, 64, 32, 16),       # smallest MFMA shape
     (1, 1, 1, 1),
+    (3, 1, 1, 5000),       # long-K dot kernel
+    (2, 4, 8, 1024),       # long-K dot kernel, several outputs
 ]
 
 
@@ -135,8 +137,8 @@ def split_emulated_gemm(A, B):
     return (prod3(ar, br) - prod3(ai, bi)) + 1j * (prod3(ar, bi) + prod3(ai, br))
 
 
-@pytest.mark.parametrize("shape", [(1, 256, 128, 64), (2, 130, 70, 33), (3, 20, 5, 7)],
-                         ids=["tiles", "ragged", "small"])
+@pytest.mark.parametrize("shape", [(1, 256, 128, 64), (2, 130, 70, 33), (3, 20, 5, 7), (2, 2, 3, 700)],
+                         ids=["tiles", "ragged", "small", "dot"])
 def test_cgemm_bf16x3_matches_split_emulation(ctx, shape):
     h, m, n, k = shape
     rng = np.random.Generator(np.random.PCG64(m + n + k))
