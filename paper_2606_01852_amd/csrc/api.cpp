@@ -428,6 +428,7 @@ tnc_status tnc_contract(tnc_plan plan, int64_t first_slice, int64_t n_slices, do
   Plan& p = plan->p;
   Ctx& c = *p.net->ctx;
   set_device(c);
+  if (c.server) fail(TNC_E_BUSY, "the context is serving: submit requests instead");
   check_range(p, first_slice, n_slices);
   const ChunkPlan& c0 = *p.chunks[0];
   RunArgs a;
@@ -460,6 +461,7 @@ tnc_status tnc_contract_async(tnc_plan plan, int64_t first_slice, int64_t n_slic
   Plan& p = plan->p;
   Ctx& c = *p.net->ctx;
   set_device(c);
+  if (c.server) fail(TNC_E_BUSY, "the context is serving: submit requests instead");
   check_range(p, first_slice, n_slices);
   const ChunkPlan& c0 = *p.chunks[0];
   if (!c0.result_perm.empty()) fail(TNC_E_UNSUPPORTED, "device results need batch labels leading the open order");

@@ -171,7 +171,7 @@ void choose_chunking(Plan& plan, size_t budget);
 size_t run_extra_bytes(const ChunkPlan& cp, int64_t n_chunks);
 
 // executor.cpp
-void materialize(ChunkPlan& cp);
+void materialize(ChunkPlan& cp, hipStream_t stream);
 struct RunArgs {
   int64_t first = 0, count = 1;
   char* arena = nullptr;        // workspace (peak + extras)

@@ -25,7 +25,7 @@ int64_t put(std::vector<uint8_t>& blob, const std::vector<T>& v) {
 
 }  // namespace
 
-void materialize(ChunkPlan& cp) {
+void materialize(ChunkPlan& cp, hipStream_t stream) {
   if (cp.materialized) return;
   std::vector<uint8_t>& blob = cp.host_blob;
   blob.clear();
@@ -46,7 +46,11 @@ void materialize(ChunkPlan& cp) {
   }
   if (!blob.empty()) {
     cp.blob.alloc(blob.size());
-    check_hip(hipMemcpy(cp.blob.ptr, blob.data(), blob.size(), hipMemcpyHostToDevice), "upload plan tables");
+    // upload on the caller's stream and wait for it alone: other requests
+    // keep running, and nobody sees the tables before they are complete
+    check_hip(hipMemcpyAsync(cp.blob.ptr, blob.data(), blob.size(), hipMemcpyHostToDevice, stream),
+              "upload plan tables");
+    check_hip(hipStreamSynchronize(stream), "upload plan tables");
   }
   char* base = static_cast<char*>(cp.blob.ptr);
   for (StepPlan& sp : cp.steps) {
@@ -72,10 +76,10 @@ std::vector<std::pair<int, int64_t>> decompose(const Plan& plan, int64_t first, 
 
 namespace {
 
-ChunkPlan& ready(Plan& plan, int j) {
+ChunkPlan& ready(Plan& plan, int j, hipStream_t stream) {
   std::lock_guard<std::mutex> g(plan.mu);
   if (!plan.chunks[j]) plan.chunks[j] = build_chunk(plan, j);
-  materialize(*plan.chunks[j]);
+  materialize(*plan.chunks[j], stream);
   return *plan.chunks[j];
 }
 
@@ -110,12 +114,12 @@ void run_plan(Plan& plan, const RunArgs& a) {
   if (chunks.empty()) fail(TNC_E_ARG, "empty slice range");
   // per-chunk base offsets of leaves that carry fixed sliced labels
   int slots = 1;
-  for (auto& c : chunks) slots = std::max(slots, ready(plan, c.first).n_base_slots);
+  for (auto& c : chunks) slots = std::max(slots, ready(plan, c.first, a.stream).n_base_slots);
   const int64_t nS = static_cast<int64_t>(plan.sliced.size());
   std::vector<int64_t> bases(chunks.size() * slots, 0);
   int64_t peak = 0;
   for (size_t c = 0; c < chunks.size(); ++c) {
-    ChunkPlan& cp = ready(plan, chunks[c].first);
+    ChunkPlan& cp = ready(plan, chunks[c].first, a.stream);
     peak = std::max(peak, cp.peak);
     if (!cp.n_base_slots) continue;
     std::vector<int64_t> val(net.extents.size(), 0);
@@ -143,10 +147,9 @@ void run_plan(Plan& plan, const RunArgs& a) {
   std::vector<std::pair<std::pair<hipEvent_t, hipEvent_t>, int>> ev;
   Launcher L{plan, a.stream, plan.profile ? &ev : nullptr};
   const int t_prep = ns, t_red = ns + 1;
-  if (plan.timers.size() < static_cast<size_t>(ns + 2)) plan.timers.resize(ns + 2);
 
   for (size_t c = 0; c < chunks.size(); ++c) {
-    ChunkPlan& cp = ready(plan, chunks[c].first);
+    ChunkPlan& cp = ready(plan, chunks[c].first, a.stream);
     const char* blob = static_cast<const char*>(cp.blob.ptr);
     auto ptr = [&](int id) -> float2* {
       if (id < n && cp.leaf[id].direct) return static_cast<float2*>(net.leaf[id].ptr);
@@ -204,6 +207,7 @@ void run_plan(Plan& plan, const RunArgs& a) {
   }
   if (!ev.empty()) {
     std::lock_guard<std::mutex> g(plan.mu);
+    if (plan.timers.size() < static_cast<size_t>(ns + 2)) plan.timers.resize(ns + 2);
     for (auto& e : ev) plan.pending.push_back(e);
   }
 }

@@ -1,29 +1,322 @@
-// Continuous-batching server: placeholder until the scheduler lands.
+// Continuous-batching server.
+//
+// Requests (plan, slice range, host output) are queued by tnc_submit.  A
+// request is admitted -- while others are still running -- as soon as a
+// slot is free and the arena has room for its planned peak (intermediates of
+// its largest chunk, per-chunk base offsets and its FP64 accumulator).
+// Every slot owns a worker thread and a HIP stream (default priority), so
+// the kernels of admitted requests overlap on the device.  A request's work
+// and its chunking depend only on its plan and slice range, so its result is
+// the same alone or in a mix.
+#include <chrono>
+#include <condition_variable>
+#include <cstring>
+#include <deque>
+#include <map>
+#include <thread>
+#include <unordered_map>
+
 #include "serve.hpp"
 
 namespace tnc {
-struct Server {};
-std::shared_ptr<Server> make_server(Ctx&, int, int) { fail(TNC_E_UNSUPPORTED, "serving not built"); }
+
+namespace {
+
+constexpr int64_t kAlign = 256;
+int64_t align_up(int64_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
+
+using Clock = std::chrono::steady_clock;
+
+// First-fit allocator over [0, size) of the context arena.
+class ArenaAllocator {
+ public:
+  explicit ArenaAllocator(int64_t size) { free_[0] = size; }
+  int64_t alloc(int64_t bytes) {
+    bytes = align_up(bytes);
+    for (auto it = free_.begin(); it != free_.end(); ++it) {
+      if (it->second >= bytes) {
+        const int64_t off = it->first;
+        const int64_t rest = it->second - bytes;
+        free_.erase(it);
+        if (rest > 0) free_[off + bytes] = rest;
+        return off;
+      }
+    }
+    return -1;
+  }
+  void release(int64_t off, int64_t bytes) {
+    bytes = align_up(bytes);
+    auto it = free_.emplace(off, bytes).first;
+    auto next = std::next(it);
+    if (next != free_.end() && it->first + it->second == next->first) {
+      it->second += next->second;
+      free_.erase(next);
+    }
+    if (it != free_.begin()) {
+      auto prev = std::prev(it);
+      if (prev->first + prev->second == it->first) {
+        prev->second += it->second;
+        free_.erase(it);
+      }
+    }
+  }
+  bool fits(int64_t bytes) const {
+    bytes = align_up(bytes);
+    for (auto& f : free_)
+      if (f.second >= bytes) return true;
+    return false;
+  }
+
+ private:
+  std::map<int64_t, int64_t> free_;
+};
+
+struct Request {
+  uint64_t id = 0;
+  Plan* plan = nullptr;
+  int64_t first = 0, count = 0;
+  double* out = nullptr;
+  int64_t need = 0, work_bytes = 0, acc_off = 0;
+  int64_t arena_off = -1;
+  Clock::time_point t_submit, t_done;
+  bool done = false;
+  tnc_status status = TNC_OK;
+  std::string err;
+};
+
+}  // namespace
+
+struct Server {
+  Ctx& ctx;
+  int max_inflight;
+  size_t queue_cap;
+  std::mutex mu;
+  std::condition_variable cv_work, cv_done;
+  std::deque<std::shared_ptr<Request>> queue;
+  std::unordered_map<uint64_t, std::shared_ptr<Request>> reqs;
+  std::vector<std::thread> workers;
+  std::vector<hipStream_t> streams;
+  ArenaAllocator arena;
+  bool stop = false;
+  uint64_t next_id = 1;
+  int inflight = 0;
+
+  Server(Ctx& c, int slots, int cap)
+      : ctx(c), max_inflight(slots), queue_cap(cap), arena(static_cast<int64_t>(c.arena_bytes)) {}
+
+  ~Server() {
+    {
+      std::lock_guard<std::mutex> g(mu);
+      stop = true;
+    }
+    cv_work.notify_all();
+    for (auto& t : workers) t.join();
+    for (hipStream_t s : streams) (void)hipStreamDestroy(s);
+  }
+
+  void start() {
+    (void)hipSetDevice(ctx.device);
+    for (int i = 0; i < max_inflight; ++i) {
+      hipStream_t s = nullptr;
+      check_hip(hipStreamCreate(&s), "hipStreamCreate");
+      streams.push_back(s);
+    }
+    for (int i = 0; i < max_inflight; ++i) workers.emplace_back([this, i] { loop(i); });
+  }
+
+  void loop(int slot) {
+    (void)hipSetDevice(ctx.device);
+    hipStream_t stream = streams[slot];
+    for (;;) {
+      std::shared_ptr<Request> r;
+      {
+        std::unique_lock<std::mutex> g(mu);
+        // drain on stop: keep admitting until the queue is empty
+        cv_work.wait(g, [&] { return (stop && queue.empty()) || (!queue.empty() && arena.fits(queue.front()->need)); });
+        if (queue.empty()) return;
+        r = queue.front();
+        queue.pop_front();
+        r->arena_off = arena.alloc(r->need);
+        ++inflight;
+      }
+      execute(*r, stream);
+      {
+        std::lock_guard<std::mutex> g(mu);
+        arena.release(r->arena_off, r->need);
+        r->t_done = Clock::now();
+        r->done = true;
+        --inflight;
+      }
+      cv_work.notify_all();
+      cv_done.notify_all();
+    }
+  }
+
+  void execute(Request& r, hipStream_t stream) {
+    try {
+      Plan& p = *r.plan;
+      const ChunkPlan& c0 = *p.chunks[0];
+      RunArgs a;
+      a.first = r.first;
+      a.count = r.count;
+      a.arena = ctx.arena + r.arena_off;
+      a.arena_bytes = static_cast<size_t>(r.work_bytes);
+      a.acc = reinterpret_cast<double2*>(ctx.arena + r.arena_off + r.acc_off);
+      a.stream = stream;
+      check_hip(launch_fill_zero(a.acc, c0.R * 16, stream), "zero accumulator");
+      run_plan(p, a);
+      std::vector<double> tmp(static_cast<size_t>(2 * c0.R));
+      check_hip(hipMemcpyAsync(tmp.data(), a.acc, c0.R * 16, hipMemcpyDeviceToHost, stream), "result copy");
+      check_hip(hipStreamSynchronize(stream), "stream synchronize");
+      if (c0.result_perm.empty()) {
+        std::memcpy(r.out, tmp.data(), tmp.size() * sizeof(double));
+      } else {
+        for (int64_t u = 0; u < c0.R; ++u) {
+          r.out[2 * u] = tmp[2 * c0.result_perm[u]];
+          r.out[2 * u + 1] = tmp[2 * c0.result_perm[u] + 1];
+        }
+      }
+    } catch (const Error& e) {
+      r.status = e.code;
+      r.err = e.msg;
+    } catch (const std::exception& e) {
+      r.status = TNC_E_DEVICE;
+      r.err = e.what();
+    }
+  }
+};
+
+std::shared_ptr<Server> make_server(Ctx& ctx, int max_inflight, int queue_cap) {
+  auto s = std::make_shared<Server>(ctx, max_inflight, queue_cap);
+  s->start();
+  return s;
+}
+
 }  // namespace tnc
 
 using namespace tnc;
 
 extern "C" {
-tnc_status tnc_serve_start(tnc_ctx, int32_t, int32_t) {
-  g_error_set("serving not built");
-  return TNC_E_UNSUPPORTED;
+
+tnc_status tnc_serve_start(tnc_ctx ctx, int32_t max_inflight, int32_t queue_cap) {
+  g_error_clear();
+  try {
+    if (!ctx) fail(TNC_E_ARG, "ctx is NULL");
+    Ctx& c = ctx->c;
+    set_device(c);
+    if (!c.arena || !c.arena_bytes) fail(TNC_E_ARG, "serving needs an arena");
+    if (max_inflight < 1 || max_inflight > 64 || queue_cap < 1) fail(TNC_E_ARG, "bad serving limits");
+    if (c.server) fail(TNC_E_BUSY, "server already running");
+    c.server = make_server(c, max_inflight, queue_cap);
+  } catch (const Error& e) {
+    g_error_set(e.msg);
+    return e.code;
+  }
+  return TNC_OK;
 }
-tnc_status tnc_serve_stop(tnc_ctx) { return TNC_OK; }
-tnc_status tnc_submit(tnc_ctx, tnc_plan, int64_t, int64_t, double*, tnc_req*) {
-  g_error_set("serving not built");
-  return TNC_E_UNSUPPORTED;
+
+tnc_status tnc_serve_stop(tnc_ctx ctx) {
+  g_error_clear();
+  if (!ctx) {
+    g_error_set("ctx is NULL");
+    return TNC_E_ARG;
+  }
+  ctx->c.server.reset();  // drains the queue: workers finish every request first
+  return TNC_OK;
 }
-tnc_status tnc_poll(tnc_ctx, tnc_req, int32_t*, double*) {
-  g_error_set("serving not built");
-  return TNC_E_UNSUPPORTED;
+
+tnc_status tnc_submit(tnc_ctx ctx, tnc_plan plan, int64_t first_slice, int64_t n_slices, double* out_c128,
+                      tnc_req* id) {
+  g_error_clear();
+  try {
+    if (!ctx || !plan || !out_c128 || !id) fail(TNC_E_ARG, "NULL argument");
+    Ctx& c = ctx->c;
+    Server* s = c.server.get();
+    if (!s) fail(TNC_E_ARG, "server not started");
+    Plan& p = plan->p;
+    if (p.net->ctx != &c) fail(TNC_E_ARG, "plan belongs to another context");
+    if (first_slice < 0 || n_slices < 1 || first_slice + n_slices > p.n_slices) fail(TNC_E_ARG, "bad slice range");
+    auto r = std::make_shared<Request>();
+    r->plan = &p;
+    r->first = first_slice;
+    r->count = n_slices;
+    r->out = out_c128;
+    // workspace: intermediates of the largest chunk, chunk base offsets, accumulator
+    const auto chunks = decompose(p, first_slice, n_slices);
+    int64_t peak = 0;
+    int slots = 1;
+    for (auto& ch : chunks) {
+      ChunkPlan& cp = p.chunk(ch.first);
+      peak = std::max(peak, cp.peak);
+      slots = std::max(slots, cp.n_base_slots);
+    }
+    r->work_bytes = align_up(peak) + align_up(static_cast<int64_t>(chunks.size()) * slots * 8);
+    r->acc_off = r->work_bytes;
+    r->need = r->work_bytes + align_up(p.chunks[0]->R * 16);
+    if (r->need > static_cast<int64_t>(c.arena_bytes))
+      fail(TNC_E_NOMEM, "request needs " + std::to_string(r->need) + " arena bytes, the arena has " +
+                            std::to_string(c.arena_bytes));
+    {
+      std::lock_guard<std::mutex> g(s->mu);
+      if (s->queue.size() >= s->queue_cap) fail(TNC_E_BUSY, "serving queue full");
+      r->id = s->next_id++;
+      r->t_submit = Clock::now();
+      s->queue.push_back(r);
+      s->reqs[r->id] = r;
+    }
+    s->cv_work.notify_all();
+    *id = r->id;
+  } catch (const Error& e) {
+    g_error_set(e.msg);
+    return e.code;
+  }
+  return TNC_OK;
 }
-tnc_status tnc_wait(tnc_ctx, tnc_req, double*) {
-  g_error_set("serving not built");
-  return TNC_E_UNSUPPORTED;
+
+static tnc_status finish(Request& r, double* latency_s) {
+  if (latency_s) *latency_s = std::chrono::duration<double>(r.t_done - r.t_submit).count();
+  if (r.status != TNC_OK) g_error_set(r.err);
+  return r.status;
 }
+
+tnc_status tnc_poll(tnc_ctx ctx, tnc_req id, int32_t* done, double* latency_s) {
+  g_error_clear();
+  if (!ctx || !done || !ctx->c.server) {
+    g_error_set("bad arguments or server not started");
+    return TNC_E_ARG;
+  }
+  Server& s = *ctx->c.server;
+  std::lock_guard<std::mutex> g(s.mu);
+  auto it = s.reqs.find(id);
+  if (it == s.reqs.end()) {
+    g_error_set("unknown request id");
+    return TNC_E_ARG;
+  }
+  *done = it->second->done ? 1 : 0;
+  if (!it->second->done) {
+    if (latency_s) *latency_s = 0;
+    return TNC_OK;
+  }
+  return finish(*it->second, latency_s);
 }
+
+tnc_status tnc_wait(tnc_ctx ctx, tnc_req id, double* latency_s) {
+  g_error_clear();
+  if (!ctx || !ctx->c.server) {
+    g_error_set("bad arguments or server not started");
+    return TNC_E_ARG;
+  }
+  Server& s = *ctx->c.server;
+  std::unique_lock<std::mutex> g(s.mu);
+  auto it = s.reqs.find(id);
+  if (it == s.reqs.end()) {
+    g_error_set("unknown request id");
+    return TNC_E_ARG;
+  }
+  std::shared_ptr<Request> r = it->second;
+  s.cv_done.wait(g, [&] { return r->done; });
+  s.reqs.erase(id);
+  return finish(*r, latency_s);
+}
+
+}  // extern "C"

@@ -1,0 +1,136 @@
+"""Continuous-batching server (C ABI): results alone vs in a mix, admission
+by planned memory, queue limits, and parity of served amplitudes with the
+oracle."""
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+from oracle import contract as oc  # noqa: E402
+from paper_2606_01852_amd import tnc  # noqa: E402
+from workloads.circuits import circuit_network, random_circuit  # noqa: E402
+from workloads.network import Path  # noqa: E402
+from workloads.paths import greedy_path, greedy_slice  # noqa: E402
+
+
+def request_pool(n):
+    """Small synthetic mix: grid circuits of 12..30 qubits, 1..64 slices."""
+    rng = np.random.Generator(np.random.PCG64(4242))
+    pool = []
+    for i in range(n):
+        rows, cols = [(3, 4), (4, 5), (4, 6), (5, 6), (4, 4)][i % 5]
+        depth = int(rng.integers(6, 11))
+        circ = random_circuit(rows, cols, depth, seed=7000 + i)
+        net = circuit_network(circ)
+        path = greedy_path(net)
+        n_sl = int(rng.integers(0, 4)) * 2
+        sl = greedy_slice(net, path.pairs, n_sliced=n_sl) if n_sl else ()
+        pool.append((net, Path(path.pairs, sl)))
+    return pool
+
+
+@pytest.fixture(scope="module")
+def served():
+    arena = torch.empty(4 << 30, dtype=torch.uint8, device="cuda")
+    ctx = tnc.Context(0, arena_bytes=arena.numel(), arena_ptr=arena.data_ptr())
+    ctx._arena = arena
+    pool = request_pool(10)
+    nets, plans = [], []
+    for net, path in pool:
+        tn = tnc.Network(ctx, net.labels, net.extents, net.open, net.c64().leaves)
+        nets.append(tn)
+        plans.append(tnc.Plan(tn, path.pairs, path.sliced))
+    yield ctx, pool, nets, plans
+    for p in plans:
+        p.close()
+    for n in nets:
+        n.close()
+    ctx.close()
+
+
+def run_all(ctx, plans, order, max_inflight):
+    tnc.tnc_serve_start(ctx.handle, max_inflight, 1024)
+    outs, ids = {}, {}
+    for i in order:
+        outs[i] = np.zeros(1, dtype=np.complex128)
+        ids[i] = tnc.tnc_submit(ctx.handle, plans[i].handle, 0, plans[i].info.n_slices, outs[i])
+    lat = {i: tnc.tnc_wait(ctx.handle, ids[i]) for i in order}
+    tnc.tnc_serve_stop(ctx.handle)
+    return outs, lat
+
+
+def test_alone_equals_mix_and_matches_oracle(served):
+    ctx, pool, nets, plans = served
+    order = list(range(len(plans)))
+    alone = {}
+    for i in order:                       # one request at a time
+        o, _ = run_all(ctx, plans, [i], 1)
+        alone[i] = o[i]
+    rng = np.random.Generator(np.random.PCG64(5))
+    mixed_order = [int(x) for x in rng.permutation(order)] * 3   # repeats overlap each other
+    tnc.tnc_serve_start(ctx.handle, 6, 1024)
+    outs, ids = [], []
+    for i in mixed_order:
+        out = np.zeros(1, dtype=np.complex128)
+        outs.append((i, out))
+        ids.append(tnc.tnc_submit(ctx.handle, plans[i].handle, 0, plans[i].info.n_slices, out))
+    for rid in ids:
+        tnc.tnc_wait(ctx.handle, rid)
+    tnc.tnc_serve_stop(ctx.handle)
+    for i, out in outs:
+        assert np.array_equal(out.view(np.uint64), alone[i].view(np.uint64)), i   # bitwise
+    for i in order[:4]:
+        net, path = pool[i]
+        ref = complex(oc.contract(net, path))
+        z = complex(alone[i][0])
+        assert abs(z - ref) <= 1e-5 * abs(ref), (i, abs(z - ref) / abs(ref))
+
+
+def test_admission_by_memory_queues_instead_of_failing(served):
+    _, pool, _, _ = served
+    net, path = pool[3]
+    # an arena that holds exactly one request at a time
+    probe = tnc.Context(-1)
+    tp = tnc.Network(probe, net.labels, net.extents, net.open)
+    pp = tnc.Plan(tp, path.pairs, path.sliced)
+    need = pp.info.chunk_peak_bytes + (1 << 20)
+    arena = torch.empty(int(need * 1.5), dtype=torch.uint8, device="cuda")
+    ctx = tnc.Context(0, arena_bytes=arena.numel(), arena_ptr=arena.data_ptr())
+    tn = tnc.Network(ctx, net.labels, net.extents, net.open, net.c64().leaves)
+    plan = tnc.Plan(tn, path.pairs, path.sliced)
+    tnc.tnc_serve_start(ctx.handle, 4, 64)
+    outs = [np.zeros(1, dtype=np.complex128) for _ in range(8)]
+    ids = [tnc.tnc_submit(ctx.handle, plan.handle, 0, plan.info.n_slices, o) for o in outs]
+    for rid in ids:
+        tnc.tnc_wait(ctx.handle, rid)
+    tnc.tnc_serve_stop(ctx.handle)
+    for o in outs[1:]:
+        assert np.array_equal(o, outs[0])
+    # a full queue is refused with TNC_E_BUSY (one slot, queue of one)
+    tnc.tnc_serve_start(ctx.handle, 1, 1)
+    accepted, busy = [], 0
+    keep = [np.zeros(1, dtype=np.complex128) for _ in range(6)]   # outputs must outlive the requests
+    for o in keep:
+        try:
+            accepted.append(tnc.tnc_submit(ctx.handle, plan.handle, 0, plan.info.n_slices, o))
+        except tnc.TncError as e:
+            assert e.status == tnc.E_BUSY
+            busy += 1
+    assert busy >= 1 and len(accepted) >= 1
+    for rid in accepted:
+        tnc.tnc_wait(ctx.handle, rid)
+    tnc.tnc_serve_stop(ctx.handle)
+    with pytest.raises(tnc.TncError) as e:     # no server any more
+        tnc.tnc_submit(ctx.handle, plan.handle, 0, 1, np.zeros(1, dtype=np.complex128))
+    assert e.value.status == tnc.E_ARG
+
+
+def test_contract_is_refused_while_serving(served):
+    ctx, _, _, plans = served
+    tnc.tnc_serve_start(ctx.handle, 2, 16)
+    with pytest.raises(tnc.TncError) as e:
+        plans[0].contract()
+    assert e.value.status == tnc.E_BUSY
+    tnc.tnc_serve_stop(ctx.handle)
+    assert plans[0].contract().shape == (1,)

@@ -205,3 +205,9 @@ def test_memory_plan_and_chunking(hctx):
         lb = max(lb, live)
     assert lb <= info.peak_bytes <= 1.5 * lb + (1 << 20)
     assert info.max_chunk >= 64 and info.chunk_peak_bytes <= 8 << 30
+
+
+def test_serving_needs_a_device_arena(hctx):
+    with pytest.raises(tnc.TncError) as e:
+        tnc.tnc_serve_start(hctx.handle, 2, 8)
+    assert e.value.status in (tnc.E_ARG, tnc.E_UNSUPPORTED)
