@@ -53,7 +53,12 @@ def parse():
     ap.add_argument("--prec", choices=["c64", "bf16x3"], default="c64")
     ap.add_argument("--scale", type=int, default=0, help="drop this many modes from each group (smaller run)")
     ap.add_argument("--no-cpu", action="store_true")
-    ap.add_argument("--workload", choices=["pair30", "circuit40"], default="pair30")
+    ap.add_argument("--workload", choices=["pair30", "circuit40", "serve"], default="pair30")
+    ap.add_argument("--no-serve", action="store_true", help="skip the serving-latency leg")
+    ap.add_argument("--serve-pool", type=int, default=12)
+    ap.add_argument("--serve-requests", type=int, default=150)
+    ap.add_argument("--serve-load", type=float, default=0.8)
+    ap.add_argument("--serve-slots", type=int, default=8)
     ap.add_argument("--slices", type=int, default=0, help="circuit40: slices per run (0 = all)")
     ap.add_argument("--arena-gib", type=float, default=64.0, help="circuit40: arena size")
     ap.add_argument("--max-chunk", type=int, default=0, help="circuit40: cap on slices per batch")
@@ -101,6 +106,85 @@ def cpu_baseline(net_a, path_a, net_b, path_b, budget_s: float = 20.0):
             "kind": "oracle",
             "sample": f"pair30 rows with 8 leading M labels fixed (1/256 of the work, {dt:.1f} s) + 4 of 64 "
                       f"batch entries ({dt2:.1f} s); numpy complex128 tensordot incl. operand transposes"}
+
+
+def serving_leg(args):
+    """Serving mix: a pool of random grid circuits (20..48 qubits, depth 8..14,
+    4^j slices, complex64 or split-bf16, planned work capped at 2^43 FLOP),
+    Poisson arrivals at ``load`` x the measured saturation throughput of the
+    continuous-batching server; the same arrival trace is replayed through
+    the server with one slot (one request at a time).  Latency is submit to
+    done, measured by the library."""
+    import threading
+
+    import torch
+
+    from paper_2606_01852_amd import tnc
+    from workloads import configs
+
+    log(f"serving: building a pool of {args.serve_pool} circuits")
+    t0 = time.time()
+    pool = [configs.serve_request(i) for i in range(args.serve_pool)]
+    log(f"serving: pool ready in {time.time() - t0:.1f} s")
+    arena_bytes = 64 << 30
+    arena = torch.empty(arena_bytes, dtype=torch.uint8, device="cuda")
+    ctx = tnc.Context(0, arena_bytes=arena_bytes, arena_ptr=arena.data_ptr())
+    nets, plans, flops = [], [], []
+    for net, path, prec in pool:
+        tn = tnc.Network(ctx, net.labels, net.extents, net.open, net.c64().leaves)
+        p = tnc.Plan(tn, path.pairs, path.sliced, tnc.PREC_BF16X3 if prec else tnc.PREC_C64, tnc.GEMM_4M)
+        tnc.tnc_plan_set_max_chunk(p.handle, 256)
+        p.info = tnc.tnc_plan_get_info(p.handle)
+        nets.append(tn)
+        plans.append(p)
+        flops.append(p.info.chunk_flops * (p.info.n_slices // p.info.max_chunk))
+    rng = np.random.Generator(np.random.PCG64(99))
+    which = [int(x) for x in rng.integers(0, len(plans), args.serve_requests)]
+    gaps = rng.exponential(1.0, args.serve_requests)
+    outs = [np.zeros(1, dtype=np.complex128) for _ in which]
+
+    def replay(slots, arrivals):
+        tnc.tnc_serve_start(ctx.handle, slots, 1 << 16)
+        t_start = time.perf_counter()
+        ids = []
+        for i, (w, at) in enumerate(zip(which, arrivals)):
+            delay = t_start + at - time.perf_counter()
+            if delay > 0:
+                time.sleep(delay)
+            ids.append(tnc.tnc_submit(ctx.handle, plans[w].handle, 0, plans[w].info.n_slices, outs[i]))
+        lat = [tnc.tnc_wait(ctx.handle, r) for r in ids]
+        t_end = time.perf_counter()
+        tnc.tnc_serve_stop(ctx.handle)
+        return np.array(lat), t_end - t_start
+
+    # warm up every plan once (tables, kernels)
+    replay(args.serve_slots, np.zeros(len(which)))
+    lat_sat, t_sat = replay(args.serve_slots, np.zeros(len(which)))
+    sat = len(which) / t_sat
+    rate = args.serve_load * sat
+    arrivals = np.cumsum(gaps) / rate
+    log(f"serving: saturation {sat:.1f} req/s; replaying {len(which)} Poisson arrivals at {rate:.1f} req/s")
+    res = {}
+    for name, slots in (("continuous_batching", args.serve_slots), ("one_at_a_time", 1)):
+        lat, wall = replay(slots, arrivals)
+        tot_flops = sum(flops[w] for w in which)
+        res[name] = {"slots": slots, "p50_ms": round(float(np.percentile(lat, 50)) * 1e3, 3),
+                     "p99_ms": round(float(np.percentile(lat, 99)) * 1e3, 3),
+                     "req_per_s": round(len(which) / wall, 2),
+                     "tflops": round(tot_flops / wall / 1e12, 3)}
+        log(f"serving {name}: {res[name]}")
+    res["arrival_rate_req_per_s"] = round(rate, 2)
+    res["saturation_req_per_s"] = round(sat, 2)
+    res["requests"] = len(which)
+    res["pool"] = len(plans)
+    for p in plans:
+        p.close()
+    for n in nets:
+        n.close()
+    ctx.close()
+    del arena
+    torch.cuda.empty_cache()
+    return res
 
 
 def bench_circuit40(args):
@@ -173,6 +257,9 @@ def main():
         sys.exit(2)
     if args.workload == "circuit40":
         return bench_circuit40(args)
+    if args.workload == "serve":
+        print(json.dumps({"serving": serving_leg(args)}), flush=True)
+        return
     import torch
 
     from paper_2606_01852_amd import tnc
@@ -271,6 +358,15 @@ def main():
         torch.cuda.synchronize()
         log("copy probe: 4 GiB read + 4 GiB written")
         del src, dst
+    if not args.no_serve:
+        plan_a.close()
+        plan_b.close()
+        tn_a.close()
+        tn_b.close()
+        ctx.close()
+        del arena
+        torch.cuda.empty_cache()
+        res["latency"] = serving_leg(args)
     if not args.no_cpu:
         log("cpu baseline (oracle on a bounded sample)")
         res["cpu_baseline"] = cpu_baseline(net_a, path_a, net_b, path_b)
