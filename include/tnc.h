@@ -90,7 +90,8 @@ const char* tnc_version(void);
  * arena_bytes : arena size; all intermediates of a contraction live in it
  *               (plans whose planned peak exceeds it fail with TNC_E_NOMEM).
  * stream      : hipStream_t to launch on, or NULL for a library-owned
- *               stream.  Caller-owned arena/stream must outlive the context. */
+ *               stream.  Caller-owned arena/stream must outlive the context
+ *               and every network and plan made from it. */
 tnc_status tnc_ctx_create(int device, void* arena, size_t arena_bytes, void* stream, tnc_ctx* out);
 tnc_status tnc_ctx_destroy(tnc_ctx ctx);
 /* Number of HIP devices visible (0 when none); never fails. */
@@ -119,8 +120,10 @@ tnc_status tnc_net_destroy(tnc_net net);
 
 /* ---------------------------------------------------------------- plan
  * Builds the execution plan of a path (Sec. IV-A reordering, per-step GEMM
- * groups, permutations, memory plan).  ssa_pairs[2*n_steps].  A plan borrows
- * its network: destroy plans first. */
+ * groups, permutations, memory plan).  ssa_pairs[2*n_steps].  A plan keeps
+ * its network (and the network its context) alive: handles may be destroyed
+ * in any order, and a destroyed plan's queued or running served requests
+ * still complete. */
 tnc_status tnc_plan_create(tnc_net net, int32_t n_steps, const int32_t* ssa_pairs,
                            int32_t n_sliced, const int32_t* sliced_labels,
                            tnc_prec prec, tnc_cgemm cgemm, tnc_plan* out);

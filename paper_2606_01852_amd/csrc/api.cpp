@@ -38,6 +38,13 @@ void DeviceBuf::reset() {
   bytes = 0;
 }
 
+Net::~Net() {
+  if (ctx && !ctx->host_only) {
+    (void)hipSetDevice(ctx->device);
+    (void)hipStreamSynchronize(ctx->stream);
+  }
+}
+
 Ctx::~Ctx() {
   server.reset();
   if (!host_only) {
@@ -105,7 +112,8 @@ tnc_status tnc_ctx_create(int device, void* arena, size_t arena_bytes, void* str
   TNC_TRY
   if (!out) fail(TNC_E_ARG, "out is NULL");
   auto h = std::make_unique<tnc_ctx_s>();
-  Ctx& c = h->c;
+  h->c = std::make_shared<Ctx>();
+  Ctx& c = *h->c;
   c.device = device;
   c.host_only = device < 0;
   c.arena_bytes = arena_bytes;
@@ -140,6 +148,8 @@ tnc_status tnc_ctx_create(int device, void* arena, size_t arena_bytes, void* str
 
 tnc_status tnc_ctx_destroy(tnc_ctx ctx) {
   TNC_TRY
+  // stop serving first: queued requests hold plans, which hold this context
+  if (ctx && ctx->c) ctx->c->server.reset();
   delete ctx;
   TNC_CATCH
 }
@@ -147,8 +157,8 @@ tnc_status tnc_ctx_destroy(tnc_ctx ctx) {
 tnc_status tnc_ctx_sync(tnc_ctx ctx) {
   TNC_TRY
   if (!ctx) fail(TNC_E_ARG, "ctx is NULL");
-  set_device(ctx->c);
-  check_hip(hipStreamSynchronize(ctx->c.stream), "stream synchronize");
+  set_device(*ctx->c);
+  check_hip(hipStreamSynchronize(ctx->c->stream), "stream synchronize");
   TNC_CATCH
 }
 
@@ -177,8 +187,10 @@ tnc_status tnc_net_create(tnc_ctx ctx, int32_t n_tensors, const int32_t* ranks, 
       (n_open && !open_labels))
     fail(TNC_E_ARG, "bad network arguments");
   auto h = std::make_unique<tnc_net_s>();
-  Net& net = h->n;
-  net.ctx = &ctx->c;
+  h->n = std::make_shared<Net>();
+  Net& net = *h->n;
+  net.ctx_ref = ctx->c;
+  net.ctx = ctx->c.get();
   net.n_tensors = n_tensors;
   net.labels.resize(n_tensors);
   int64_t pos = 0;
@@ -192,9 +204,9 @@ tnc_status tnc_net_create(tnc_ctx ctx, int32_t n_tensors, const int32_t* ranks, 
   net.open.assign(open_labels, open_labels + n_open);
   validate_net(net);
   net.leaf.resize(n_tensors);
-  if (!ctx->c.host_only) {
+  if (!ctx->c->host_only) {
     if (!host_data) fail(TNC_E_ARG, "host_data is NULL");
-    set_device(ctx->c);
+    set_device(*ctx->c);
     for (int t = 0; t < n_tensors; ++t) {
       if (!host_data[t]) fail(TNC_E_ARG, "host_data[" + std::to_string(t) + "] is NULL");
       upload_leaf(net, t, host_data[t], in);
@@ -207,7 +219,7 @@ tnc_status tnc_net_create(tnc_ctx ctx, int32_t n_tensors, const int32_t* ranks, 
 tnc_status tnc_net_set_tensor(tnc_net net, int32_t tensor, const void* host_data, tnc_in in) {
   TNC_TRY
   if (!net || !host_data) fail(TNC_E_ARG, "net/host_data is NULL");
-  Net& n = net->n;
+  Net& n = *net->n;
   if (tensor < 0 || tensor >= n.n_tensors) fail(TNC_E_ARG, "tensor out of range");
   set_device(*n.ctx);
   check_hip(hipStreamSynchronize(n.ctx->stream), "stream synchronize");
@@ -218,7 +230,7 @@ tnc_status tnc_net_set_tensor(tnc_net net, int32_t tensor, const void* host_data
 tnc_status tnc_net_set_tensor_device(tnc_net net, int32_t tensor, const void* dev_data) {
   TNC_TRY
   if (!net || !dev_data) fail(TNC_E_ARG, "net/dev_data is NULL");
-  Net& n = net->n;
+  Net& n = *net->n;
   if (tensor < 0 || tensor >= n.n_tensors) fail(TNC_E_ARG, "tensor out of range");
   set_device(*n.ctx);
   check_hip(hipMemcpyAsync(n.leaf[tensor].ptr, dev_data, n.numel[tensor] * 8, hipMemcpyDeviceToDevice, n.ctx->stream),
@@ -228,11 +240,7 @@ tnc_status tnc_net_set_tensor_device(tnc_net net, int32_t tensor, const void* de
 
 tnc_status tnc_net_destroy(tnc_net net) {
   TNC_TRY
-  if (net && !net->n.ctx->host_only) {
-    (void)hipSetDevice(net->n.ctx->device);
-    (void)hipStreamSynchronize(net->n.ctx->stream);
-  }
-  delete net;
+  delete net;  // the network itself goes when its last plan does
   TNC_CATCH
 }
 
@@ -246,9 +254,11 @@ tnc_status tnc_plan_create(tnc_net net, int32_t n_steps, const int32_t* ssa_pair
   if (cgemm != TNC_GEMM_4M && cgemm != TNC_GEMM_3M) fail(TNC_E_ARG, "unknown GEMM form");
   if (prec == TNC_PREC_BF16X3 && cgemm == TNC_GEMM_3M)
     fail(TNC_E_UNSUPPORTED, "split precision runs in the 4M form only");
-  Net& n = net->n;
+  Net& n = *net->n;
   auto h = std::make_unique<tnc_plan_s>();
-  Plan& p = h->p;
+  h->p = std::make_shared<Plan>();
+  Plan& p = *h->p;
+  p.net_ref = net->n;
   p.net = &n;
   p.prec = prec;
   p.form = cgemm;
@@ -285,25 +295,14 @@ tnc_status tnc_plan_create(tnc_net net, int32_t n_steps, const int32_t* ssa_pair
 
 tnc_status tnc_plan_destroy(tnc_plan plan) {
   TNC_TRY
-  if (plan) {
-    Plan& p = plan->p;
-    if (!p.net->ctx->host_only) {
-      (void)hipSetDevice(p.net->ctx->device);
-      (void)hipStreamSynchronize(p.net->ctx->stream);
-      for (auto& e : p.pending) {
-        (void)hipEventDestroy(e.first.first);
-        (void)hipEventDestroy(e.first.second);
-      }
-    }
-  }
-  delete plan;
+  delete plan;  // in-flight served requests keep the plan until they finish
   TNC_CATCH
 }
 
 tnc_status tnc_plan_get_info(tnc_plan plan, tnc_plan_info* out) {
   TNC_TRY
   if (!plan || !out) fail(TNC_E_ARG, "plan/out is NULL");
-  Plan& p = plan->p;
+  Plan& p = *plan->p;
   const ChunkPlan& c0 = *p.chunks[0];
   const ChunkPlan& cm = p.chunk(p.j_max);
   tnc_plan_info info{};
@@ -327,7 +326,7 @@ tnc_status tnc_plan_get_info(tnc_plan plan, tnc_plan_info* out) {
 tnc_status tnc_plan_get_step(tnc_plan plan, int32_t step, tnc_step_info* out) {
   TNC_TRY
   if (!plan || !out) fail(TNC_E_ARG, "plan/out is NULL");
-  const ChunkPlan& c0 = *plan->p.chunks[0];
+  const ChunkPlan& c0 = *plan->p->chunks[0];
   if (step < 0 || step >= static_cast<int32_t>(c0.steps.size())) fail(TNC_E_ARG, "step out of range");
   const StepPlan& s = c0.steps[step];
   tnc_step_info i{};
@@ -351,7 +350,7 @@ tnc_status tnc_plan_get_step(tnc_plan plan, int32_t step, tnc_step_info* out) {
 tnc_status tnc_plan_get_order(tnc_plan plan, int32_t id, int32_t* labels, int32_t cap, int32_t* rank) {
   TNC_TRY
   if (!plan || !rank || (cap > 0 && !labels)) fail(TNC_E_ARG, "bad arguments");
-  const ChunkPlan& c0 = *plan->p.chunks[0];
+  const ChunkPlan& c0 = *plan->p->chunks[0];
   if (id < 0 || id >= static_cast<int32_t>(c0.order.size())) fail(TNC_E_ARG, "tensor id out of range");
   const auto& o = c0.order[id];
   for (int q = 0; q < std::min<int>(cap, static_cast<int>(o.size())); ++q) labels[q] = o[q];
@@ -362,7 +361,7 @@ tnc_status tnc_plan_get_order(tnc_plan plan, int32_t id, int32_t* labels, int32_
 tnc_status tnc_plan_set_max_chunk(tnc_plan plan, int64_t max_chunk) {
   TNC_TRY
   if (!plan) fail(TNC_E_ARG, "plan is NULL");
-  Plan& p = plan->p;
+  Plan& p = *plan->p;
   p.max_chunk_user = max_chunk;
   int j = 0;
   for (int q = 1; q < static_cast<int>(p.suffix_prod.size()); ++q) {
@@ -385,14 +384,14 @@ tnc_status tnc_plan_set_max_chunk(tnc_plan plan, int64_t max_chunk) {
 tnc_status tnc_plan_set_graph(tnc_plan plan, int32_t enable) {
   TNC_TRY
   if (!plan) fail(TNC_E_ARG, "plan is NULL");
-  plan->p.graph = enable ? 1 : 0;
+  plan->p->graph = enable ? 1 : 0;
   TNC_CATCH
 }
 
 tnc_status tnc_plan_set_profile(tnc_plan plan, int32_t enable) {
   TNC_TRY
   if (!plan) fail(TNC_E_ARG, "plan is NULL");
-  Plan& p = plan->p;
+  Plan& p = *plan->p;
   if (!p.net->ctx->host_only) drain_profile(p);
   p.profile = enable ? 1 : 0;
   p.timers.assign(p.pairs.size() + 2, StepTimer{});
@@ -402,7 +401,7 @@ tnc_status tnc_plan_set_profile(tnc_plan plan, int32_t enable) {
 tnc_status tnc_plan_get_profile(tnc_plan plan, int32_t step, double* ms, int64_t* launches) {
   TNC_TRY
   if (!plan || !ms || !launches) fail(TNC_E_ARG, "bad arguments");
-  Plan& p = plan->p;
+  Plan& p = *plan->p;
   set_device(*p.net->ctx);
   drain_profile(p);
   const int ns = static_cast<int>(p.pairs.size());
@@ -425,7 +424,7 @@ static void check_range(const Plan& p, int64_t first, int64_t count) {
 tnc_status tnc_contract(tnc_plan plan, int64_t first_slice, int64_t n_slices, double* out_c128) {
   TNC_TRY
   if (!plan || !out_c128) fail(TNC_E_ARG, "plan/out is NULL");
-  Plan& p = plan->p;
+  Plan& p = *plan->p;
   Ctx& c = *p.net->ctx;
   set_device(c);
   if (c.server) fail(TNC_E_BUSY, "the context is serving: submit requests instead");
@@ -458,7 +457,7 @@ tnc_status tnc_contract_async(tnc_plan plan, int64_t first_slice, int64_t n_slic
                               tnc_out out_type) {
   TNC_TRY
   if (!plan || !out_dev) fail(TNC_E_ARG, "plan/out is NULL");
-  Plan& p = plan->p;
+  Plan& p = *plan->p;
   Ctx& c = *p.net->ctx;
   set_device(c);
   if (c.server) fail(TNC_E_BUSY, "the context is serving: submit requests instead");
@@ -492,7 +491,7 @@ tnc_status tnc_contract_async(tnc_plan plan, int64_t first_slice, int64_t n_slic
 tnc_status tnc_plan_result_norm2(tnc_plan plan, double* out) {
   TNC_TRY
   if (!plan || !out) fail(TNC_E_ARG, "plan/out is NULL");
-  Plan& p = plan->p;
+  Plan& p = *plan->p;
   Ctx& c = *p.net->ctx;
   set_device(c);
   const ChunkPlan& c0 = *p.chunks[0];
@@ -508,7 +507,7 @@ tnc_status tnc_permute(tnc_ctx ctx, const void* in, void* out, int32_t rank, con
                        const int32_t* perm) {
   TNC_TRY
   if (!ctx || !in || !out || rank < 0 || (rank && (!extents || !perm))) fail(TNC_E_ARG, "bad arguments");
-  Ctx& c = ctx->c;
+  Ctx& c = *ctx->c;
   set_device(c);
   std::vector<int64_t> ist(rank);
   int64_t s = 1;
@@ -575,7 +574,7 @@ tnc_status tnc_batched_cgemm(tnc_ctx ctx, int64_t h, int64_t m, int64_t n, int64
   if (!ctx || !A || !B || !C || h < 1 || m < 1 || n < 1 || k < 1 || stride_a < 0 || stride_b < 0)
     fail(TNC_E_ARG, "bad arguments");
   if (prec == TNC_PREC_BF16X3 && form == TNC_GEMM_3M) fail(TNC_E_UNSUPPORTED, "split precision runs in 4M form");
-  Ctx& c = ctx->c;
+  Ctx& c = *ctx->c;
   set_device(c);
   GemmDesc d;
   std::memset(&d, 0, sizeof(d));

@@ -5,6 +5,7 @@
 
 #include <array>
 #include <atomic>
+#include <map>
 #include <cstdint>
 #include <memory>
 #include <mutex>
@@ -63,6 +64,7 @@ struct Ctx {
 enum class LabelKind : uint8_t { Unused = 0, Closed, Open, Batch };
 
 struct Net {
+  std::shared_ptr<Ctx> ctx_ref;           // keeps the context alive (destroyed last)
   Ctx* ctx = nullptr;
   int n_tensors = 0;
   std::vector<std::vector<int>> labels;   // stored order per leaf
@@ -73,6 +75,7 @@ struct Net {
   std::vector<int64_t> numel;             // per leaf
   std::vector<DeviceBuf> leaf;            // resident complex64 leaves
   std::vector<std::vector<int64_t>> stride;  // per leaf, per stored mode
+  ~Net();
 };
 
 // A tile decomposition of one gather-permute (host copy of the tables).
@@ -142,7 +145,23 @@ struct StepTimer {
   int64_t launches = 0;
 };
 
+struct GraphKey {
+  int j;
+  const void* arena;
+  const void* acc;
+  const void* out;
+  const void* bases;
+  bool operator<(const GraphKey& o) const {
+    if (j != o.j) return j < o.j;
+    if (arena != o.arena) return arena < o.arena;
+    if (acc != o.acc) return acc < o.acc;
+    if (out != o.out) return out < o.out;
+    return bases < o.bases;
+  }
+};
+
 struct Plan {
+  std::shared_ptr<Net> net_ref;       // keeps the network alive (destroyed last)
   Net* net = nullptr;
   std::vector<std::array<int, 2>> pairs;
   std::vector<int> sliced;
@@ -160,6 +179,10 @@ struct Plan {
   DeviceBuf acc;         // complex128 result accumulator (synchronous calls)
   DeviceBuf norm;        // one double
   std::mutex mu;         // guards lazy chunk building
+  std::mutex graph_mu;   // guards the graph cache
+  std::map<GraphKey, hipGraphExec_t> graphs;
+  hipStream_t capture_stream = nullptr;
+  ~Plan();
   ChunkPlan& chunk(int j);
 };
 
@@ -181,17 +204,22 @@ struct RunArgs {
   hipStream_t stream = nullptr;
 };
 void run_plan(Plan& plan, const RunArgs& a);
+// Arena bytes run_plan needs for a slice range (intermediates of the largest
+// chunk, the current chunk's leaf bases, every chunk's leaf bases).
+int64_t run_workspace_bytes(Plan& plan, int64_t first, int64_t count);
 void drain_profile(Plan& plan);
 std::vector<std::pair<int, int64_t>> decompose(const Plan& plan, int64_t first, int64_t count);
 
 }  // namespace tnc
 
+// Handles own a reference each: a plan keeps its network alive and a network
+// its context, so handles may be destroyed in any order.
 struct tnc_ctx_s {
-  tnc::Ctx c;
+  std::shared_ptr<tnc::Ctx> c;
 };
 struct tnc_net_s {
-  tnc::Net n;
+  std::shared_ptr<tnc::Net> n;
 };
 struct tnc_plan_s {
-  tnc::Plan p;
+  std::shared_ptr<tnc::Plan> p;
 };

@@ -85,11 +85,10 @@ ChunkPlan& ready(Plan& plan, int j, hipStream_t stream) {
 
 struct Launcher {
   Plan& plan;
-  hipStream_t stream;
   std::vector<std::pair<std::pair<hipEvent_t, hipEvent_t>, int>>* events;
 
   template <typename F>
-  void run(int timer, F&& f) {
+  void run(int timer, hipStream_t stream, F&& f) {
     hipEvent_t a = nullptr, b = nullptr;
     if (events) {
       check_hip(hipEventCreate(&a), "event");
@@ -106,9 +105,115 @@ struct Launcher {
 
 }  // namespace
 
-void run_plan(Plan& plan, const RunArgs& a) {
+namespace {
+
+// Enqueue one chunk: leaf permutations, one GEMM per step, the FP64
+// reduction of the root.  `bases` points at this chunk's leaf base offsets.
+void enqueue_chunk(Plan& plan, ChunkPlan& cp, const RunArgs& a, const int64_t* bases, hipStream_t stream,
+                   Launcher& L) {
   Net& net = *plan.net;
   const int n = net.n_tensors;
+  const int ns = static_cast<int>(plan.pairs.size());
+  const int t_prep = ns, t_red = ns + 1;
+  const char* blob = static_cast<const char*>(cp.blob.ptr);
+  auto ptr = [&](int id) -> float2* {
+    if (id < n && cp.leaf[id].direct) return static_cast<float2*>(net.leaf[id].ptr);
+    if (id == cp.root_id && a.direct_out) return a.direct_out;
+    return reinterpret_cast<float2*>(a.arena + cp.buf_off[cp.tensor_buf[id]]);
+  };
+  auto prep = [&](int t) {
+    const LeafPrep& lp = cp.leaf[t];
+    const float2* in = static_cast<const float2*>(net.leaf[t].ptr);
+    float2* out = ptr(t);
+    const int64_t* bd = lp.base_slot >= 0 ? bases + lp.base_slot : nullptr;
+    if (lp.perm.tiled) {
+      const PermuteHost& p = lp.perm;
+      PermuteDesc d{};
+      d.in = in;
+      d.out = out;
+      d.tile_in = reinterpret_cast<const int32_t*>(blob + p.off_tile_in);
+      d.tile_slot_r = reinterpret_cast<const int32_t*>(blob + p.off_slot_r);
+      d.tile_out = reinterpret_cast<const int32_t*>(blob + p.off_tile_out);
+      d.tile_slot_w = reinterpret_cast<const int32_t*>(blob + p.off_slot_w);
+      d.lo_tab = reinterpret_cast<const int64_t*>(blob + p.off_lo);
+      d.hi_tab = reinterpret_cast<const int64_t*>(blob + p.off_hi);
+      d.n_tiles = p.n_tiles;
+      d.L = p.L;
+      d.T = p.T;
+      d.slots = p.slots;
+      d.base = 0;
+      d.base_dev = bd;
+      L.run(t_prep, stream, [&] { return launch_permute(d, stream); });
+    } else {
+      GatherDesc g = lp.perm.plain;
+      g.in = in;
+      g.out = out;
+      g.base = 0;
+      g.base_dev = bd;
+      L.run(t_prep, stream, [&] { return launch_gather(g, stream); });
+    }
+  };
+  if (ns == 0 && !cp.leaf[0].direct) prep(0);
+  const Form form = plan.form == TNC_GEMM_3M ? Form::M3 : Form::M4;
+  const Prec prec = plan.prec == TNC_PREC_BF16X3 ? Prec::BF16X3 : Prec::C64;
+  for (int s = 0; s < ns; ++s) {
+    StepPlan& sp = cp.steps[s];
+    for (int t : sp.preps) prep(t);
+    GemmDesc d = sp.desc;
+    d.A = ptr(sp.A);
+    d.B = ptr(sp.B);
+    d.C = ptr(sp.C);
+    L.run(s, stream, [&] { return launch_gemm(d, sp.kind, form, prec, stream); });
+  }
+  if (!a.direct_out) {
+    const float2* root = ptr(cp.root_id);
+    L.run(t_red, stream, [&] { return launch_reduce_fp64(root, a.acc, cp.hs, cp.R, stream); });
+  }
+}
+
+// The captured graph of one chunk plan for one set of buffers (created on
+// first use, replayed afterwards).
+hipGraphExec_t chunk_graph(Plan& plan, ChunkPlan& cp, const RunArgs& a, const int64_t* cur_bases) {
+  const GraphKey key{cp.j, a.arena, a.acc, a.direct_out, cur_bases};
+  std::lock_guard<std::mutex> g(plan.graph_mu);
+  auto it = plan.graphs.find(key);
+  if (it != plan.graphs.end()) return it->second;
+  if (!plan.capture_stream) check_hip(hipStreamCreate(&plan.capture_stream), "hipStreamCreate");
+  hipGraph_t graph = nullptr;
+  check_hip(hipStreamBeginCapture(plan.capture_stream, hipStreamCaptureModeThreadLocal), "begin capture");
+  Launcher none{plan, nullptr};
+  try {
+    enqueue_chunk(plan, cp, a, cur_bases, plan.capture_stream, none);
+  } catch (...) {
+    (void)hipStreamEndCapture(plan.capture_stream, &graph);
+    if (graph) (void)hipGraphDestroy(graph);
+    throw;
+  }
+  check_hip(hipStreamEndCapture(plan.capture_stream, &graph), "end capture");
+  hipGraphExec_t exec = nullptr;
+  const hipError_t e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+  (void)hipGraphDestroy(graph);
+  check_hip(e, "graph instantiate");
+  plan.graphs.emplace(key, exec);
+  return exec;
+}
+
+}  // namespace
+
+int64_t run_workspace_bytes(Plan& plan, int64_t first, int64_t count) {
+  const auto chunks = decompose(plan, first, count);
+  int64_t peak = 0;
+  int slots = 1;
+  for (auto& c : chunks) {
+    ChunkPlan& cp = plan.chunk(c.first);
+    peak = std::max(peak, cp.peak);
+    slots = std::max(slots, cp.n_base_slots);
+  }
+  return align_up(peak) + align_up(slots * 8) + align_up(static_cast<int64_t>(chunks.size()) * slots * 8);
+}
+
+void run_plan(Plan& plan, const RunArgs& a) {
+  Net& net = *plan.net;
   const int ns = static_cast<int>(plan.pairs.size());
   const auto chunks = decompose(plan, a.first, a.count);
   if (chunks.empty()) fail(TNC_E_ARG, "empty slice range");
@@ -136,73 +241,29 @@ void run_plan(Plan& plan, const RunArgs& a) {
       bases[c * slots + lp.base_slot] = off;
     }
   }
-  const int64_t bases_off = align_up(peak);
+  // workspace: [intermediates | current chunk's bases | all chunks' bases]
+  const int64_t cur_off = align_up(peak);
+  const int64_t bases_off = cur_off + align_up(slots * 8);
   const size_t need = static_cast<size_t>(bases_off) + bases.size() * sizeof(int64_t);
   if (need > a.arena_bytes)
     fail(TNC_E_NOMEM, "run needs " + std::to_string(need) + " arena bytes, have " + std::to_string(a.arena_bytes));
+  int64_t* cur_dev = reinterpret_cast<int64_t*>(a.arena + cur_off);
   int64_t* bases_dev = reinterpret_cast<int64_t*>(a.arena + bases_off);
   check_hip(hipMemcpyAsync(bases_dev, bases.data(), bases.size() * sizeof(int64_t), hipMemcpyHostToDevice, a.stream),
             "upload chunk bases");
 
   std::vector<std::pair<std::pair<hipEvent_t, hipEvent_t>, int>> ev;
-  Launcher L{plan, a.stream, plan.profile ? &ev : nullptr};
-  const int t_prep = ns, t_red = ns + 1;
-
+  Launcher L{plan, plan.profile && !plan.graph ? &ev : nullptr};
   for (size_t c = 0; c < chunks.size(); ++c) {
     ChunkPlan& cp = ready(plan, chunks[c].first, a.stream);
-    const char* blob = static_cast<const char*>(cp.blob.ptr);
-    auto ptr = [&](int id) -> float2* {
-      if (id < n && cp.leaf[id].direct) return static_cast<float2*>(net.leaf[id].ptr);
-      if (id == cp.root_id && a.direct_out) return a.direct_out;
-      return reinterpret_cast<float2*>(a.arena + cp.buf_off[cp.tensor_buf[id]]);
-    };
-    auto prep = [&](int t) {
-      const LeafPrep& lp = cp.leaf[t];
-      const float2* in = static_cast<const float2*>(net.leaf[t].ptr);
-      float2* out = ptr(t);
-      const int64_t* bd = lp.base_slot >= 0 ? bases_dev + c * slots + lp.base_slot : nullptr;
-      if (lp.perm.tiled) {
-        const PermuteHost& p = lp.perm;
-        PermuteDesc d{};
-        d.in = in;
-        d.out = out;
-        d.tile_in = reinterpret_cast<const int32_t*>(blob + p.off_tile_in);
-        d.tile_slot_r = reinterpret_cast<const int32_t*>(blob + p.off_slot_r);
-        d.tile_out = reinterpret_cast<const int32_t*>(blob + p.off_tile_out);
-        d.tile_slot_w = reinterpret_cast<const int32_t*>(blob + p.off_slot_w);
-        d.lo_tab = reinterpret_cast<const int64_t*>(blob + p.off_lo);
-        d.hi_tab = reinterpret_cast<const int64_t*>(blob + p.off_hi);
-        d.n_tiles = p.n_tiles;
-        d.L = p.L;
-        d.T = p.T;
-        d.slots = p.slots;
-        d.base = 0;
-        d.base_dev = bd;
-        L.run(t_prep, [&] { return launch_permute(d, a.stream); });
-      } else {
-        GatherDesc g = lp.perm.plain;
-        g.in = in;
-        g.out = out;
-        g.base = 0;
-        g.base_dev = bd;
-        L.run(t_prep, [&] { return launch_gather(g, a.stream); });
-      }
-    };
-    if (ns == 0 && !cp.leaf[0].direct) prep(0);
-    for (int s = 0; s < ns; ++s) {
-      StepPlan& sp = cp.steps[s];
-      for (int t : sp.preps) prep(t);
-      GemmDesc d = sp.desc;
-      d.A = ptr(sp.A);
-      d.B = ptr(sp.B);
-      d.C = ptr(sp.C);
-      const Form form = plan.form == TNC_GEMM_3M ? Form::M3 : Form::M4;
-      const Prec prec = plan.prec == TNC_PREC_BF16X3 ? Prec::BF16X3 : Prec::C64;
-      L.run(s, [&] { return launch_gemm(d, sp.kind, form, prec, a.stream); });
-    }
-    if (!a.direct_out) {
-      const float2* root = ptr(cp.root_id);
-      L.run(t_red, [&] { return launch_reduce_fp64(root, a.acc, cp.hs, cp.R, a.stream); });
+    if (plan.graph) {
+      hipGraphExec_t exec = chunk_graph(plan, cp, a, cur_dev);
+      check_hip(hipMemcpyAsync(cur_dev, bases_dev + c * slots, slots * sizeof(int64_t), hipMemcpyDeviceToDevice,
+                               a.stream),
+                "chunk bases");
+      check_hip(hipGraphLaunch(exec, a.stream), "graph launch");
+    } else {
+      enqueue_chunk(plan, cp, a, bases_dev + c * slots, a.stream, L);
     }
   }
   if (!ev.empty()) {
@@ -210,6 +271,19 @@ void run_plan(Plan& plan, const RunArgs& a) {
     if (plan.timers.size() < static_cast<size_t>(ns + 2)) plan.timers.resize(ns + 2);
     for (auto& e : ev) plan.pending.push_back(e);
   }
+}
+
+Plan::~Plan() {
+  if (net && !net->ctx->host_only) {
+    (void)hipSetDevice(net->ctx->device);
+    (void)hipStreamSynchronize(net->ctx->stream);
+  }
+  for (auto& e : pending) {
+    (void)hipEventDestroy(e.first.first);
+    (void)hipEventDestroy(e.first.second);
+  }
+  for (auto& g : graphs) (void)hipGraphExecDestroy(g.second);
+  if (capture_stream) (void)hipStreamDestroy(capture_stream);
 }
 
 void drain_profile(Plan& plan) {

@@ -73,6 +73,7 @@ class ArenaAllocator {
 
 struct Request {
   uint64_t id = 0;
+  std::shared_ptr<Plan> plan_ref;   // keeps the plan alive while queued or running
   Plan* plan = nullptr;
   int64_t first = 0, count = 0;
   double* out = nullptr;
@@ -202,7 +203,7 @@ tnc_status tnc_serve_start(tnc_ctx ctx, int32_t max_inflight, int32_t queue_cap)
   g_error_clear();
   try {
     if (!ctx) fail(TNC_E_ARG, "ctx is NULL");
-    Ctx& c = ctx->c;
+    Ctx& c = *ctx->c;
     set_device(c);
     if (!c.arena || !c.arena_bytes) fail(TNC_E_ARG, "serving needs an arena");
     if (max_inflight < 1 || max_inflight > 64 || queue_cap < 1) fail(TNC_E_ARG, "bad serving limits");
@@ -221,7 +222,7 @@ tnc_status tnc_serve_stop(tnc_ctx ctx) {
     g_error_set("ctx is NULL");
     return TNC_E_ARG;
   }
-  ctx->c.server.reset();  // drains the queue: workers finish every request first
+  ctx->c->server.reset();  // drains the queue: workers finish every request first
   return TNC_OK;
 }
 
@@ -230,27 +231,20 @@ tnc_status tnc_submit(tnc_ctx ctx, tnc_plan plan, int64_t first_slice, int64_t n
   g_error_clear();
   try {
     if (!ctx || !plan || !out_c128 || !id) fail(TNC_E_ARG, "NULL argument");
-    Ctx& c = ctx->c;
+    Ctx& c = *ctx->c;
     Server* s = c.server.get();
     if (!s) fail(TNC_E_ARG, "server not started");
-    Plan& p = plan->p;
+    Plan& p = *plan->p;
     if (p.net->ctx != &c) fail(TNC_E_ARG, "plan belongs to another context");
     if (first_slice < 0 || n_slices < 1 || first_slice + n_slices > p.n_slices) fail(TNC_E_ARG, "bad slice range");
     auto r = std::make_shared<Request>();
+    r->plan_ref = plan->p;
     r->plan = &p;
     r->first = first_slice;
     r->count = n_slices;
     r->out = out_c128;
     // workspace: intermediates of the largest chunk, chunk base offsets, accumulator
-    const auto chunks = decompose(p, first_slice, n_slices);
-    int64_t peak = 0;
-    int slots = 1;
-    for (auto& ch : chunks) {
-      ChunkPlan& cp = p.chunk(ch.first);
-      peak = std::max(peak, cp.peak);
-      slots = std::max(slots, cp.n_base_slots);
-    }
-    r->work_bytes = align_up(peak) + align_up(static_cast<int64_t>(chunks.size()) * slots * 8);
+    r->work_bytes = run_workspace_bytes(p, first_slice, n_slices);
     r->acc_off = r->work_bytes;
     r->need = r->work_bytes + align_up(p.chunks[0]->R * 16);
     if (r->need > static_cast<int64_t>(c.arena_bytes))
@@ -281,11 +275,11 @@ static tnc_status finish(Request& r, double* latency_s) {
 
 tnc_status tnc_poll(tnc_ctx ctx, tnc_req id, int32_t* done, double* latency_s) {
   g_error_clear();
-  if (!ctx || !done || !ctx->c.server) {
+  if (!ctx || !done || !ctx->c->server) {
     g_error_set("bad arguments or server not started");
     return TNC_E_ARG;
   }
-  Server& s = *ctx->c.server;
+  Server& s = *ctx->c->server;
   std::lock_guard<std::mutex> g(s.mu);
   auto it = s.reqs.find(id);
   if (it == s.reqs.end()) {
@@ -302,11 +296,11 @@ tnc_status tnc_poll(tnc_ctx ctx, tnc_req id, int32_t* done, double* latency_s) {
 
 tnc_status tnc_wait(tnc_ctx ctx, tnc_req id, double* latency_s) {
   g_error_clear();
-  if (!ctx || !ctx->c.server) {
+  if (!ctx || !ctx->c->server) {
     g_error_set("bad arguments or server not started");
     return TNC_E_ARG;
   }
-  Server& s = *ctx->c.server;
+  Server& s = *ctx->c->server;
   std::unique_lock<std::mutex> g(s.mu);
   auto it = s.reqs.find(id);
   if (it == s.reqs.end()) {

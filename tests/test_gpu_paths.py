@@ -244,3 +244,40 @@ def test_device_errors_are_status_codes(ctx):
     assert e.value.status == tnc.E_NOMEM
     # the context still works afterwards
     assert abs(plan.contract()[0]) > 0
+
+
+def test_graph_replay_matches_eager(ctx):
+    """Chunks replayed as captured hipGraphs give bitwise the eager result,
+    replay after replay, with other eager work on the stream in between."""
+    net, path = configs.circuit12()
+    sl = greedy_slice(net, path.pairs, n_sliced=4)
+    p = Path(path.pairs, sl)
+    tn = tnc.Network(ctx, net.labels, net.extents, net.open, net.c64().leaves)
+    eager = tnc.Plan(tn, p.pairs, p.sliced)
+    tnc.tnc_plan_set_max_chunk(eager.handle, 4)
+    graph = tnc.Plan(tn, p.pairs, p.sliced)
+    tnc.tnc_plan_set_max_chunk(graph.handle, 4)
+    tnc.tnc_plan_set_graph(graph.handle, True)
+    ref = eager.contract()
+    other_net, other_path = configs.grid8(4, 4, 3)
+    other = tnc.Plan(tnc.Network(ctx, other_net.labels, other_net.extents, other_net.open,
+                                 other_net.c64().leaves), other_path.pairs)
+    for rep in range(4):
+        got = graph.contract()
+        assert np.array_equal(got.view(np.uint64), ref.view(np.uint64)), rep
+        other.contract()                          # eager work between replays
+        part = graph.contract(3, 9)               # partial range: other chunk plans, same graphs
+        assert np.array_equal(part.view(np.uint64), eager.contract(3, 9).view(np.uint64)), rep
+    # single-slice direct device output through a graph
+    net2, path2 = pair_network(9, 8, 7, seed=6)
+    tn2 = tnc.Network(ctx, net2.labels, net2.extents, net2.open, net2.c64().leaves)
+    pe, pg = tnc.Plan(tn2, path2.pairs), tnc.Plan(tn2, path2.pairs)
+    tnc.tnc_plan_set_graph(pg.handle, True)
+    oe = torch.empty(pe.info.n_result, dtype=torch.complex64, device="cuda")
+    og = torch.empty_like(oe)
+    tnc.tnc_contract_async(pe.handle, 0, 1, oe.data_ptr(), tnc.OUT_C64)
+    for _ in range(3):
+        og.zero_()
+        tnc.tnc_contract_async(pg.handle, 0, 1, og.data_ptr(), tnc.OUT_C64)
+        torch.cuda.synchronize()
+        assert torch.equal(torch.view_as_real(oe), torch.view_as_real(og))

@@ -211,3 +211,24 @@ def test_serving_needs_a_device_arena(hctx):
     with pytest.raises(tnc.TncError) as e:
         tnc.tnc_serve_start(hctx.handle, 2, 8)
     assert e.value.status in (tnc.E_ARG, tnc.E_UNSUPPORTED)
+
+
+def test_handles_can_be_destroyed_in_any_order():
+    net, path = configs.circuit12()
+    for order in ("ctx_first", "net_first", "plan_first"):
+        ctx = tnc.tnc_ctx_create(-1)
+        n = tnc.tnc_net_create(ctx, net.labels, net.extents, net.open, None)
+        p = tnc.tnc_plan_create(n, path.pairs)
+        if order == "ctx_first":
+            tnc.tnc_ctx_destroy(ctx)
+            tnc.tnc_net_destroy(n)
+            assert tnc.tnc_plan_get_info(p).n_steps == 153   # still usable
+            tnc.tnc_plan_destroy(p)
+        elif order == "net_first":
+            tnc.tnc_net_destroy(n)
+            tnc.tnc_plan_destroy(p)
+            tnc.tnc_ctx_destroy(ctx)
+        else:
+            tnc.tnc_plan_destroy(p)
+            tnc.tnc_net_destroy(n)
+            tnc.tnc_ctx_destroy(ctx)
