@@ -134,6 +134,7 @@ def serving_leg(args):
         tn = tnc.Network(ctx, net.labels, net.extents, net.open, net.c64().leaves)
         p = tnc.Plan(tn, path.pairs, path.sliced, tnc.PREC_BF16X3 if prec else tnc.PREC_C64, tnc.GEMM_4M)
         tnc.tnc_plan_set_max_chunk(p.handle, 256)
+        tnc.tnc_plan_autotune(p.handle)
         p.info = tnc.tnc_plan_get_info(p.handle)
         nets.append(tn)
         plans.append(p)
@@ -209,6 +210,9 @@ def bench_circuit40(args):
         tnc.tnc_plan_set_max_chunk(plan.handle, args.max_chunk)
     if args.graph:
         tnc.tnc_plan_set_graph(plan.handle, True)
+    t_tune = time.time()
+    tnc.tnc_plan_autotune(plan.handle)
+    log(f"autotuned in {time.time() - t_tune:.1f} s")
     info = tnc.tnc_plan_get_info(plan.handle)
     n = args.slices or info.n_slices
     log(f"slices {n} of {info.n_slices}; chunk {info.max_chunk}; chunk peak {info.chunk_peak_bytes / 2**30:.1f} GiB; "
@@ -293,6 +297,12 @@ def main():
     tn_b = tnc.Network(ctx, net_b.labels, net_b.extents, net_b.open, net_b.leaves)
     plan_a = tnc.Plan(tn_a, path_a.pairs, (), prec, form)
     plan_b = tnc.Plan(tn_b, path_b.pairs, (), prec, form)
+    log("autotuning tile shapes")
+    t_tune = time.time()
+    tnc.tnc_plan_autotune(plan_a.handle)
+    tnc.tnc_plan_autotune(plan_b.handle)
+    log(f"autotuned in {time.time() - t_tune:.1f} s: big GEMM variant {tnc.tnc_plan_get_step(plan_a.handle, 0).variant}, "
+        f"batch GEMM variant {tnc.tnc_plan_get_step(plan_b.handle, 0).variant}")
     out_a = torch.empty(plan_a.info.n_result, dtype=torch.complex64, device=dev)
     out_b = torch.empty(plan_b.info.n_result, dtype=torch.complex64, device=dev)
     flops_step = plan_a.info.flops_per_slice + plan_b.info.flops_per_slice

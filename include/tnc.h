@@ -157,6 +157,7 @@ typedef struct {
   int32_t natural;
   int32_t kernel;                /* 0 = MFMA tiles, 1 = small-shape VALU kernel,
                                     2 = long-K dot kernel (k large, m*n tiny)  */
+  int32_t variant;               /* MFMA workgroup shape (autotuned)           */
 } tnc_step_info;
 tnc_status tnc_plan_get_step(tnc_plan plan, int32_t step, tnc_step_info* out);
 /* Mode order (labels) tensor `id` is stored in when the plan runs one slice:
@@ -166,6 +167,11 @@ tnc_status tnc_plan_get_order(tnc_plan plan, int32_t id, int32_t* labels, int32_
 
 /* Upper bound on slices per device batch (default: as many as fit the arena). */
 tnc_status tnc_plan_set_max_chunk(tnc_plan plan, int64_t max_chunk);
+/* Time the candidate MFMA workgroup shapes of every GEMM step shape of the
+ * plan on the device and keep the fastest (cached per context, and in the
+ * file named by the environment variable TNC_AUTOTUNE_CACHE if set).
+ * Untuned steps use a shape-based default.  Synchronous. */
+tnc_status tnc_plan_autotune(tnc_plan plan);
 /* 1 = capture each chunk's launches in a hipGraph and replay it. */
 tnc_status tnc_plan_set_graph(tnc_plan plan, int32_t enable);
 /* 1 = time every kernel with HIP events on the launch stream. */
@@ -205,6 +211,11 @@ tnc_status tnc_permute(tnc_ctx ctx, const void* in, void* out, int32_t rank,
 tnc_status tnc_batched_cgemm(tnc_ctx ctx, int64_t h, int64_t m, int64_t n, int64_t k,
                              const void* A, int64_t stride_a, const void* B, int64_t stride_b,
                              void* C, tnc_prec prec, tnc_cgemm form);
+/* Force the MFMA tile variant of every complex GEMM this context launches
+ * (0 .. tnc_gemm_variant_count()-1; -1 = the plan's autotuned choice).  For
+ * tests and tuning sweeps. */
+tnc_status tnc_ctx_set_gemm_variant(tnc_ctx ctx, int32_t variant);
+int tnc_gemm_variant_count(void);
 /* Synchronise the context's stream; TNC_E_DEVICE if a kernel failed. */
 tnc_status tnc_ctx_sync(tnc_ctx ctx);
 

@@ -133,6 +133,7 @@ tnc_status tnc_ctx_create(int device, void* arena, size_t arena_bytes, void* str
       c.arena = static_cast<char*>(p);
       c.own_arena = true;
     }
+    load_tune_cache(c);
     if (stream) {
       c.stream = static_cast<hipStream_t>(stream);
     } else {
@@ -153,6 +154,16 @@ tnc_status tnc_ctx_destroy(tnc_ctx ctx) {
   delete ctx;
   TNC_CATCH
 }
+
+tnc_status tnc_ctx_set_gemm_variant(tnc_ctx ctx, int32_t variant) {
+  TNC_TRY
+  if (!ctx) fail(TNC_E_ARG, "ctx is NULL");
+  if (variant < -1 || variant >= kGemmVariants) fail(TNC_E_ARG, "variant out of range");
+  ctx->c->gemm_variant = variant;
+  TNC_CATCH
+}
+
+int tnc_gemm_variant_count(void) { return kGemmVariants; }
 
 tnc_status tnc_ctx_sync(tnc_ctx ctx) {
   TNC_TRY
@@ -343,6 +354,7 @@ tnc_status tnc_plan_get_step(tnc_plan plan, int32_t step, tnc_step_info* out) {
   i.k = s.k;
   i.natural = s.natural ? 1 : 0;
   i.kernel = static_cast<int32_t>(s.kind);
+  i.variant = s.variant;
   *out = i;
   TNC_CATCH
 }
@@ -378,6 +390,17 @@ tnc_status tnc_plan_set_max_chunk(tnc_plan plan, int64_t max_chunk) {
     j = q;
   }
   p.j_max = j;
+  TNC_CATCH
+}
+
+tnc_status tnc_plan_autotune(tnc_plan plan) {
+  TNC_TRY
+  if (!plan) fail(TNC_E_ARG, "plan is NULL");
+  Plan& p = *plan->p;
+  set_device(*p.net->ctx);
+  std::lock_guard<std::mutex> g(p.mu);
+  for (auto& cp : p.chunks)
+    if (cp) assign_variants(p, *cp, true);
   TNC_CATCH
 }
 
@@ -600,7 +623,7 @@ tnc_status tnc_batched_cgemm(tnc_ctx ctx, int64_t h, int64_t m, int64_t n, int64
     }
   }
   const GemmKernel kind = choose_gemm_kernel(h, m, n, k);
-  check_hip(launch_gemm(d, kind, form == TNC_GEMM_3M ? Form::M3 : Form::M4,
+  check_hip(launch_gemm(d, kind, c.gemm_variant < 0 ? 0 : c.gemm_variant, form == TNC_GEMM_3M ? Form::M3 : Form::M4,
                         prec == TNC_PREC_BF16X3 ? Prec::BF16X3 : Prec::C64, c.stream),
             "gemm launch");
   TNC_CATCH

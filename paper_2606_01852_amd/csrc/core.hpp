@@ -48,6 +48,22 @@ struct DeviceBuf {
 
 struct Server;
 
+// Autotuning key: one GEMM step shape.
+struct TuneKey {
+  int prec = 0, form = 0, perm = 0;
+  int64_t h = 0, m = 0, n = 0, k = 0;
+  bool operator<(const TuneKey& o) const {
+    if (prec != o.prec) return prec < o.prec;
+    if (form != o.form) return form < o.form;
+    if (perm != o.perm) return perm < o.perm;
+    if (h != o.h) return h < o.h;
+    if (m != o.m) return m < o.m;
+    if (n != o.n) return n < o.n;
+    return k < o.k;
+  }
+  std::string str() const;
+};
+
 struct Ctx {
   int device = -1;
   bool host_only = true;
@@ -57,6 +73,9 @@ struct Ctx {
   hipStream_t stream = nullptr;
   bool own_stream = false;
   DeviceBuf scratch;   // tables of stand-alone permutes
+  int gemm_variant = -1; // forced MFMA tile variant (-1: autotuned / default)
+  std::mutex tune_mu;
+  std::map<TuneKey, int> tune_cache;  // autotuned tile variant per step shape
   std::shared_ptr<Server> server;
   ~Ctx();
 };
@@ -110,6 +129,7 @@ struct StepPlan {
   int64_t h = 1, m = 1, n = 1, k = 1, hA = 1, hB = 1;
   bool natural = true;
   GemmKernel kind = GemmKernel::SMALL;
+  int variant = 0;                            // MFMA tile variant (autotuned)
   GemmDesc desc{};                            // pointers filled at run time
   int64_t off_offM = -1, off_offN = -1;       // in the device blob
   std::vector<int64_t> offM, offN;            // host copies (permuted store)
@@ -192,6 +212,11 @@ void validate_path(const Net& net, const std::vector<std::array<int, 2>>& pairs)
 std::unique_ptr<ChunkPlan> build_chunk(const Plan& plan, int j);
 void choose_chunking(Plan& plan, size_t budget);
 size_t run_extra_bytes(const ChunkPlan& cp, int64_t n_chunks);
+
+// autotune.cpp
+int default_variant(tnc_prec prec, tnc_cgemm form, int64_t h, int64_t m, int64_t n);
+void load_tune_cache(Ctx& c);
+void assign_variants(const Plan& plan, ChunkPlan& cp, bool tune);
 
 // executor.cpp
 void materialize(ChunkPlan& cp, hipStream_t stream);

@@ -163,7 +163,8 @@ void enqueue_chunk(Plan& plan, ChunkPlan& cp, const RunArgs& a, const int64_t* b
     d.A = ptr(sp.A);
     d.B = ptr(sp.B);
     d.C = ptr(sp.C);
-    L.run(s, stream, [&] { return launch_gemm(d, sp.kind, form, prec, stream); });
+    const int variant = net.ctx->gemm_variant >= 0 ? net.ctx->gemm_variant : sp.variant;
+    L.run(s, stream, [&] { return launch_gemm(d, sp.kind, variant, form, prec, stream); });
   }
   if (!a.direct_out) {
     const float2* root = ptr(cp.root_id);

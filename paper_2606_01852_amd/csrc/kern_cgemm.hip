@@ -1,4 +1,4 @@
-// Batched complex GEMM kernels for gfx950:  C[b,i,j] = sum_l A[b,i,l] B[b,j,l].
+// Batched complex GEMM on MFMA for gfx950:  C[b,i,j] = sum_l A[b,i,l] B[b,j,l].
 //
 // Every contraction step of the path is one such GEMM once the operands are
 // in [retained || reduced] order (paper Sec. II-B: A_MK x B_KN -> C_MN;
@@ -21,16 +21,21 @@
 //
 // BF16x3: each float32 plane is split into bf16 hi/lo (round to nearest
 // even) while it is staged into LDS; every real product becomes
-// a_hi b_hi + a_hi b_lo + a_lo b_hi on bf16 MFMA with FP32 accumulation.
+// a_hi b_hi + (a_hi b_lo + a_lo b_hi) on bf16 MFMA with FP32 accumulation
+// (hi and cross terms in separate accumulators).
 //
-// Tiling: a 256-thread workgroup (4 wave64) owns a 128 x 64 complex tile of
-// C; each wave owns 64 x 32 complex.  K advances 16 complex per stage
-// through double-buffered LDS (rows padded to 144 B so the 16-byte fragment
-// reads of 16 lanes hit 16 distinct 4-bank groups).  Workgroups are remapped
-// so that consecutive tiles land on one XCD (the hardware deals workgroups
-// round-robin over the 8 XCDs, each with its own L2) and tiles sweep the
-// N dimension in groups of 8 M-tiles for L2 reuse.
-#include "kernels.hpp"
+// Tiling.  A wave64 always owns a 64 x 32 complex tile of C (2x2 MFMA
+// 32x32 blocks of the real view, or 2x1 complex blocks in 3M); a workgroup
+// is WM x WN waves, so its tile is 64*WM x 32*WN complex.  K advances 16
+// complex per stage through double-buffered LDS (rows padded to 144 B: the
+// 16-byte fragment reads of 16 lanes hit 16 distinct 4-bank groups).  Each
+// lane reads 4 consecutive real k and feeds them to 4 successive MFMAs; the
+// K order inside a stage is permuted the same way for A and B.  Interior
+// tiles run a copy of the main loop without bounds checks.  Workgroups are
+// remapped so that consecutive tiles land on one XCD (the hardware deals
+// workgroups round-robin over the 8 XCDs, each with its own L2) and tiles
+// sweep N in groups of 8 M-tiles for L2 reuse.
+#include "gemm_common.hpp"
 
 namespace tnc {
 
@@ -41,38 +46,25 @@ typedef float f16v __attribute__((ext_vector_type(16)));
 typedef __bf16 bf8 __attribute__((ext_vector_type(8)));
 typedef short s8v __attribute__((ext_vector_type(8)));
 
-constexpr int BM = 128;    // rows of C per workgroup
-constexpr int BNC = 64;    // complex columns of C per workgroup
-constexpr int BKC = 16;    // complex k per LDS stage
-constexpr int PITCH = 36;  // floats per LDS row (32 data + 4 pad)
+constexpr int BKC = 16;     // complex k per LDS stage
+constexpr int PITCH = 36;   // floats per LDS row (32 data + 4 pad)
+constexpr int SPITCH = 40;  // uint16 per LDS row of a bf16 plane (32 data + 8 pad)
 constexpr int GROUP_M = 8;
 
-__device__ __forceinline__ void batch_offsets(const GemmDesc& d, int64_t b, int64_t& oa, int64_t& ob) {
-  oa = 0;
-  ob = 0;
-  if (d.pow2) {
-    for (int j = d.nbd - 1; j >= 0; --j) {
-      const int64_t dig = b & (static_cast<int64_t>(d.bext[j]) - 1);
-      b >>= d.bshift[j];
-      oa += dig * d.bsA[j];
-      ob += dig * d.bsB[j];
-    }
-  } else {
-    for (int j = d.nbd - 1; j >= 0; --j) {
-      const int64_t e = d.bext[j];
-      const int64_t q = b / e;
-      const int64_t dig = b - q * e;
-      b = q;
-      oa += dig * d.bsA[j];
-      ob += dig * d.bsB[j];
-    }
-  }
-}
+template <int WM, int WN>
+struct Shape {
+  static constexpr int BM = 64 * WM;   // rows of C per workgroup
+  static constexpr int BNC = 32 * WN;  // complex columns of C per workgroup
+  static constexpr int NT = 64 * WM * WN;
+  static constexpr size_t lds_f32 = 2 * (BM + BNC) * PITCH * sizeof(float);
+  static constexpr size_t lds_bf16 = 2 * 2 * (BM + BNC) * SPITCH * sizeof(uint16_t);
+};
 
 struct TileCoord {
   int64_t b, row0, col0;
 };
 
+template <int BM, int BNC>
 __device__ __forceinline__ TileCoord map_tile(int64_t tiles_m, int64_t tiles_n, int64_t total) {
   int64_t wg = blockIdx.x;
   const int64_t per = total >> 3;
@@ -94,84 +86,92 @@ __device__ __forceinline__ TileCoord map_tile(int64_t tiles_m, int64_t tiles_n, 
 }
 
 // Global -> register staging of one K stage (VW complex per load).
-template <int VW>
+template <int WM, int WN, int VW>
 struct Stage {
-  static constexpr int A_LOADS = BM * BKC / VW / 256;
-  static constexpr int B_LOADS = BNC * BKC / VW / 256;
+  using S = Shape<WM, WN>;
   static constexpr int PER_ROW = BKC / VW;
-  f4 a[A_LOADS > 0 ? A_LOADS : 1];
-  f4 b[B_LOADS > 0 ? B_LOADS : 1];
+  static constexpr int A_LOADS = S::BM * PER_ROW / S::NT;
+  static constexpr int B_LOADS = S::BNC * PER_ROW / S::NT;
+  static_assert(A_LOADS >= 1 && A_LOADS * S::NT == S::BM * PER_ROW, "A staging must tile evenly");
+  static_assert(B_LOADS >= 1 && B_LOADS * S::NT == S::BNC * PER_ROW, "B staging must tile evenly");
+  f4 a[A_LOADS];
+  f4 b[B_LOADS];
 
-  __device__ __forceinline__ void load(const float2* __restrict__ A, const float2* __restrict__ B,
-                                       int64_t m, int64_t n, int64_t k, int64_t row0, int64_t col0,
-                                       int64_t kk, int tid) {
+  template <bool CHECK>
+  __device__ __forceinline__ static f4 fetch(const float2* __restrict__ X, int64_t gr, int64_t gk, int64_t rows,
+                                             int64_t k) {
+    f4 v = {0.f, 0.f, 0.f, 0.f};
+    if (!CHECK || (gr < rows && gk < k)) {
+      const float2* p = X + gr * k + gk;
+      if constexpr (VW == 2) {
+        v = *reinterpret_cast<const f4*>(p);
+      } else {
+        const float2 x = *p;
+        v.x = x.x;
+        v.y = x.y;
+      }
+    }
+    return v;
+  }
+
+  template <bool CHECK>
+  __device__ __forceinline__ void load(const float2* __restrict__ A, const float2* __restrict__ B, int64_t m,
+                                       int64_t n, int64_t k, int64_t row0, int64_t col0, int64_t kk, int tid) {
 #pragma unroll
     for (int i = 0; i < A_LOADS; ++i) {
-      const int idx = tid + 256 * i;
-      const int r = idx / PER_ROW;
-      const int c = (idx % PER_ROW) * VW;
-      const int64_t gr = row0 + r, gk = kk + c;
-      f4 v = {0.f, 0.f, 0.f, 0.f};
-      if (gr < m && gk < k) {
-        const float2* p = A + gr * k + gk;
-        if constexpr (VW == 2) {
-          v = *reinterpret_cast<const f4*>(p);
-        } else {
-          const float2 x = *p;
-          v.x = x.x;
-          v.y = x.y;
-        }
-      }
-      a[i] = v;
+      const int idx = tid + S::NT * i;
+      a[i] = fetch<CHECK>(A, row0 + idx / PER_ROW, kk + (idx % PER_ROW) * VW, m, k);
     }
 #pragma unroll
     for (int i = 0; i < B_LOADS; ++i) {
-      const int idx = tid + 256 * i;
-      const int r = idx / PER_ROW;
-      const int c = (idx % PER_ROW) * VW;
-      const int64_t gr = col0 + r, gk = kk + c;
-      f4 v = {0.f, 0.f, 0.f, 0.f};
-      if (gr < n && gk < k) {
-        const float2* p = B + gr * k + gk;
-        if constexpr (VW == 2) {
-          v = *reinterpret_cast<const f4*>(p);
-        } else {
-          const float2 x = *p;
-          v.x = x.x;
-          v.y = x.y;
-        }
-      }
-      b[i] = v;
+      const int idx = tid + S::NT * i;
+      b[i] = fetch<CHECK>(B, col0 + idx / PER_ROW, kk + (idx % PER_ROW) * VW, n, k);
     }
   }
 
-  __device__ __forceinline__ void store(float* As, float* Bs, int tid) const {
-#pragma unroll
-    for (int i = 0; i < A_LOADS; ++i) {
-      const int idx = tid + 256 * i;
-      const int r = idx / PER_ROW;
-      const int c = (idx % PER_ROW) * VW;
-      float* p = As + r * PITCH + 2 * c;
-      if constexpr (VW == 2) {
-        *reinterpret_cast<f4*>(p) = a[i];
-      } else {
-        p[0] = a[i].x;
-        p[1] = a[i].y;
-      }
+  __device__ __forceinline__ static void put_f32(float* base, int idx, const f4& v) {
+    float* p = base + (idx / PER_ROW) * PITCH + 2 * (idx % PER_ROW) * VW;
+    if constexpr (VW == 2) {
+      *reinterpret_cast<f4*>(p) = v;
+    } else {
+      p[0] = v.x;
+      p[1] = v.y;
     }
+  }
+
+  __device__ __forceinline__ void store_f32(float* As, float* Bs, int tid) const {
 #pragma unroll
-    for (int i = 0; i < B_LOADS; ++i) {
-      const int idx = tid + 256 * i;
-      const int r = idx / PER_ROW;
-      const int c = (idx % PER_ROW) * VW;
-      float* p = Bs + r * PITCH + 2 * c;
-      if constexpr (VW == 2) {
-        *reinterpret_cast<f4*>(p) = b[i];
-      } else {
-        p[0] = b[i].x;
-        p[1] = b[i].y;
-      }
+    for (int i = 0; i < A_LOADS; ++i) put_f32(As, tid + S::NT * i, a[i]);
+#pragma unroll
+    for (int i = 0; i < B_LOADS; ++i) put_f32(Bs, tid + S::NT * i, b[i]);
+  }
+
+  // bf16 planes: the hi and lo halves of every float go to separate planes
+  // at the same position (real k index = 2 * complex k + re/im).
+  __device__ __forceinline__ static void put_split(uint16_t* hi, uint16_t* lo, int idx, const f4& v) {
+    const int pos = (idx / PER_ROW) * SPITCH + 2 * (idx % PER_ROW) * VW;
+    uint16_t h[4], l[4];
+    split_bf16(v.x, h[0], l[0]);
+    split_bf16(v.y, h[1], l[1]);
+    split_bf16(v.z, h[2], l[2]);
+    split_bf16(v.w, h[3], l[3]);
+    if constexpr (VW == 2) {
+      *reinterpret_cast<uint2*>(hi + pos) =
+          make_uint2(h[0] | (uint32_t(h[1]) << 16), h[2] | (uint32_t(h[3]) << 16));
+      *reinterpret_cast<uint2*>(lo + pos) =
+          make_uint2(l[0] | (uint32_t(l[1]) << 16), l[2] | (uint32_t(l[3]) << 16));
+    } else {
+      *reinterpret_cast<uint32_t*>(hi + pos) = h[0] | (uint32_t(h[1]) << 16);
+      *reinterpret_cast<uint32_t*>(lo + pos) = l[0] | (uint32_t(l[1]) << 16);
     }
+  }
+
+  __device__ __forceinline__ void store_split(uint16_t* Ah, uint16_t* Al, uint16_t* Bh, uint16_t* Bl,
+                                              int tid) const {
+#pragma unroll
+    for (int i = 0; i < A_LOADS; ++i) put_split(Ah, Al, tid + S::NT * i, a[i]);
+#pragma unroll
+    for (int i = 0; i < B_LOADS; ++i) put_split(Bh, Bl, tid + S::NT * i, b[i]);
   }
 };
 
@@ -180,39 +180,29 @@ __device__ __forceinline__ int64_t c_index(const GemmDesc& d, bool perm, int64_t
 }
 
 // ------------------------------------------------------------------ 4M, FP32 MFMA
-template <int VW, bool PERM>
-__global__ __launch_bounds__(256) void cgemm_4m_mfma(GemmDesc d, int64_t tiles_m, int64_t tiles_n,
-                                                      int64_t total) {
-  __shared__ __attribute__((aligned(16))) float As[2][BM * PITCH];
-  __shared__ __attribute__((aligned(16))) float Bs[2][BNC * PITCH];
-  const int tid = threadIdx.x;
-  const int lane = tid & 63, wave = tid >> 6;
-  const int wm = wave >> 1, wn = wave & 1;
-  const int h = lane >> 5, l32 = lane & 31, p = lane & 1;
-  const TileCoord tc = map_tile(tiles_m, tiles_n, total);
-  int64_t oa, ob;
-  batch_offsets(d, tc.b, oa, ob);
-  const float2* __restrict__ A = d.A + oa;
-  const float2* __restrict__ B = d.B + ob;
-
+template <int WM, int WN, int VW>
+struct Ops4M {
+  using S = Shape<WM, WN>;
   f16v acc[2][2];
-#pragma unroll
-  for (int i = 0; i < 2; ++i)
-#pragma unroll
-    for (int j = 0; j < 2; ++j)
-#pragma unroll
-      for (int v = 0; v < 16; ++v) acc[i][j][v] = 0.f;
 
-  const int64_t nk = (d.k + BKC - 1) / BKC;
-  Stage<VW> st;
-  st.load(A, B, d.m, d.n, d.k, tc.row0, tc.col0, 0, tid);
-  st.store(As[0], Bs[0], tid);
-  __syncthreads();
-  for (int64_t kt = 0; kt < nk; ++kt) {
-    const int buf = kt & 1;
-    if (kt + 1 < nk) st.load(A, B, d.m, d.n, d.k, tc.row0, tc.col0, (kt + 1) * BKC, tid);
-    const float* as = As[buf];
-    const float* bs = Bs[buf];
+  __device__ __forceinline__ void init() {
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+      for (int j = 0; j < 2; ++j)
+#pragma unroll
+        for (int v = 0; v < 16; ++v) acc[i][j][v] = 0.f;
+  }
+
+  __device__ __forceinline__ void stage(const Stage<WM, WN, VW>& st, char* lds, int buf, int tid) const {
+    float* As = reinterpret_cast<float*>(lds) + buf * (S::BM + S::BNC) * PITCH;
+    st.store_f32(As, As + S::BM * PITCH, tid);
+  }
+
+  __device__ __forceinline__ void compute(const char* lds, int buf, int wm, int wn, int lane) {
+    const float* as = reinterpret_cast<const float*>(lds) + buf * (S::BM + S::BNC) * PITCH;
+    const float* bs = as + S::BM * PITCH;
+    const int h = lane >> 5, l32 = lane & 31, p = lane & 1;
 #pragma unroll
     for (int g = 0; g < BKC / 4; ++g) {
       const int koff = (4 * g + 2 * h) * 2;
@@ -240,82 +230,74 @@ __global__ __launch_bounds__(256) void cgemm_4m_mfma(GemmDesc d, int64_t tiles_m
           acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x2f32(a[i].w, bt[j].w, acc[i][j], 0, 0, 0);
         }
     }
-    if (kt + 1 < nk) st.store(As[buf ^ 1], Bs[buf ^ 1], tid);
-    __syncthreads();
   }
 
-  float* C = reinterpret_cast<float*>(d.C);
+  __device__ __forceinline__ void store(const GemmDesc& d, bool perm, const TileCoord& tc, int wm, int wn,
+                                        int lane) const {
+    const int h = lane >> 5, l32 = lane & 31;
+    float* C = reinterpret_cast<float*>(d.C);
 #pragma unroll
-  for (int i = 0; i < 2; ++i)
+    for (int i = 0; i < 2; ++i)
 #pragma unroll
-    for (int j = 0; j < 2; ++j) {
-      const int64_t ncr = tc.col0 * 2 + wn * 64 + j * 32 + l32;  // real column
-      const int64_t col = ncr >> 1;
-      if (col >= d.n) continue;
+      for (int j = 0; j < 2; ++j) {
+        const int64_t ncr = tc.col0 * 2 + wn * 64 + j * 32 + l32;  // real column
+        const int64_t col = ncr >> 1;
+        if (col >= d.n) continue;
 #pragma unroll
-      for (int v = 0; v < 16; ++v) {
-        const int64_t row = tc.row0 + wm * 64 + i * 32 + 8 * (v >> 2) + 4 * h + (v & 3);
-        if (row < d.m) C[2 * c_index(d, PERM, tc.b, row, col) + (ncr & 1)] = acc[i][j][v];
+        for (int v = 0; v < 16; ++v) {
+          const int64_t row = tc.row0 + wm * 64 + i * 32 + 8 * (v >> 2) + 4 * h + (v & 3);
+          if (row < d.m) C[2 * c_index(d, perm, tc.b, row, col) + (ncr & 1)] = acc[i][j][v];
+        }
       }
-    }
-}
+  }
+};
 
 // ------------------------------------------------------------------ 3M, FP32 MFMA
-template <int VW, bool PERM>
-__global__ __launch_bounds__(256) void cgemm_3m_mfma(GemmDesc d, int64_t tiles_m, int64_t tiles_n,
-                                                      int64_t total) {
-  __shared__ __attribute__((aligned(16))) float As[2][BM * PITCH];
-  __shared__ __attribute__((aligned(16))) float Bs[2][BNC * PITCH];
-  const int tid = threadIdx.x;
-  const int lane = tid & 63, wave = tid >> 6;
-  const int wm = wave >> 1, wn = wave & 1;
-  const int h = lane >> 5, l32 = lane & 31;
-  const TileCoord tc = map_tile(tiles_m, tiles_n, total);
-  int64_t oa, ob;
-  batch_offsets(d, tc.b, oa, ob);
-  const float2* __restrict__ A = d.A + oa;
-  const float2* __restrict__ B = d.B + ob;
-
+template <int WM, int WN, int VW>
+struct Ops3M {
+  using S = Shape<WM, WN>;
   f16v t1[2], t2[2], t3[2];
-#pragma unroll
-  for (int i = 0; i < 2; ++i)
-#pragma unroll
-    for (int v = 0; v < 16; ++v) t1[i][v] = t2[i][v] = t3[i][v] = 0.f;
 
-  const int64_t nk = (d.k + BKC - 1) / BKC;
-  Stage<VW> st;
-  st.load(A, B, d.m, d.n, d.k, tc.row0, tc.col0, 0, tid);
-  st.store(As[0], Bs[0], tid);
-  __syncthreads();
-  for (int64_t kt = 0; kt < nk; ++kt) {
-    const int buf = kt & 1;
-    if (kt + 1 < nk) st.load(A, B, d.m, d.n, d.k, tc.row0, tc.col0, (kt + 1) * BKC, tid);
-    const float* as = As[buf];
-    const float* bs = Bs[buf];
+  __device__ __forceinline__ void init() {
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+      for (int v = 0; v < 16; ++v) t1[i][v] = t2[i][v] = t3[i][v] = 0.f;
+  }
+
+  __device__ __forceinline__ void stage(const Stage<WM, WN, VW>& st, char* lds, int buf, int tid) const {
+    float* As = reinterpret_cast<float*>(lds) + buf * (S::BM + S::BNC) * PITCH;
+    st.store_f32(As, As + S::BM * PITCH, tid);
+  }
+
+  __device__ __forceinline__ void compute(const char* lds, int buf, int wm, int wn, int lane) {
+    const float* as = reinterpret_cast<const float*>(lds) + buf * (S::BM + S::BNC) * PITCH;
+    const float* bs = as + S::BM * PITCH;
+    const int h = lane >> 5, l32 = lane & 31;
 #pragma unroll
     for (int g = 0; g < BKC / 4; ++g) {
       const int koff = (4 * g + 2 * h) * 2;
       const f4 rb = *reinterpret_cast<const f4*>(bs + (wn * 32 + l32) * PITCH + koff);
-      const float br0 = rb.x, bi0 = rb.y, br1 = rb.z, bi1 = rb.w;
-      const float bs0 = br0 + bi0, bs1 = br1 + bi1;
+      const float bs0 = rb.x + rb.y, bs1 = rb.z + rb.w;
 #pragma unroll
       for (int i = 0; i < 2; ++i) {
         const f4 ra = *reinterpret_cast<const f4*>(as + (wm * 64 + i * 32 + l32) * PITCH + koff);
         const float as0 = ra.x + ra.y, as1 = ra.z + ra.w;
-        t1[i] = __builtin_amdgcn_mfma_f32_32x32x2f32(ra.x, br0, t1[i], 0, 0, 0);
-        t2[i] = __builtin_amdgcn_mfma_f32_32x32x2f32(ra.y, bi0, t2[i], 0, 0, 0);
+        t1[i] = __builtin_amdgcn_mfma_f32_32x32x2f32(ra.x, rb.x, t1[i], 0, 0, 0);
+        t2[i] = __builtin_amdgcn_mfma_f32_32x32x2f32(ra.y, rb.y, t2[i], 0, 0, 0);
         t3[i] = __builtin_amdgcn_mfma_f32_32x32x2f32(as0, bs0, t3[i], 0, 0, 0);
-        t1[i] = __builtin_amdgcn_mfma_f32_32x32x2f32(ra.z, br1, t1[i], 0, 0, 0);
-        t2[i] = __builtin_amdgcn_mfma_f32_32x32x2f32(ra.w, bi1, t2[i], 0, 0, 0);
+        t1[i] = __builtin_amdgcn_mfma_f32_32x32x2f32(ra.z, rb.z, t1[i], 0, 0, 0);
+        t2[i] = __builtin_amdgcn_mfma_f32_32x32x2f32(ra.w, rb.w, t2[i], 0, 0, 0);
         t3[i] = __builtin_amdgcn_mfma_f32_32x32x2f32(as1, bs1, t3[i], 0, 0, 0);
       }
     }
-    if (kt + 1 < nk) st.store(As[buf ^ 1], Bs[buf ^ 1], tid);
-    __syncthreads();
   }
 
-  const int64_t col = tc.col0 + wn * 32 + l32;
-  if (col < d.n) {
+  __device__ __forceinline__ void store(const GemmDesc& d, bool perm, const TileCoord& tc, int wm, int wn,
+                                        int lane) const {
+    const int h = lane >> 5, l32 = lane & 31;
+    const int64_t col = tc.col0 + wn * 32 + l32;
+    if (col >= d.n) return;
 #pragma unroll
     for (int i = 0; i < 2; ++i)
 #pragma unroll
@@ -325,105 +307,51 @@ __global__ __launch_bounds__(256) void cgemm_3m_mfma(GemmDesc d, int64_t tiles_m
           float2 o;
           o.x = t1[i][v] - t2[i][v];
           o.y = t3[i][v] - t1[i][v] - t2[i][v];
-          d.C[c_index(d, PERM, tc.b, row, col)] = o;
+          d.C[c_index(d, perm, tc.b, row, col)] = o;
         }
       }
   }
-}
+};
 
 // ------------------------------------------------------------------ split BF16x3, 4M form
-__device__ __forceinline__ uint32_t bf16_rne_bits(float x) {
-  uint32_t u = __float_as_uint(x);
-  u += 0x7FFFu + ((u >> 16) & 1u);
-  return u & 0xFFFF0000u;
-}
-
-// hi/lo bf16 halves (as 16-bit patterns) of one float32.
-__device__ __forceinline__ void split_bf16(float x, uint16_t& hi, uint16_t& lo) {
-  const uint32_t h = bf16_rne_bits(x);
-  const float r = x - __uint_as_float(h);
-  hi = static_cast<uint16_t>(h >> 16);
-  lo = static_cast<uint16_t>(bf16_rne_bits(r) >> 16);
-}
-
-// LDS layout for the split kernel: for each of A and B, a hi plane and a lo
-// plane, each row = 2*BKC bf16 of the real-expanded K (32 values = 64 B)
-// padded to 80 B.  Rows of B hold B's interleaved values unexpanded; the
-// re/im select and sign flip are applied to the bf16 fragments.
-constexpr int SPITCH = 40;  // uint16 per LDS row (32 data + 8 pad)
-
-template <int VW, bool PERM>
-__global__ __launch_bounds__(256) void cgemm_4m_bf16x3(GemmDesc d, int64_t tiles_m, int64_t tiles_n,
-                                                        int64_t total) {
-  __shared__ __attribute__((aligned(16))) uint16_t Ah[2][BM * SPITCH];
-  __shared__ __attribute__((aligned(16))) uint16_t Al[2][BM * SPITCH];
-  __shared__ __attribute__((aligned(16))) uint16_t Bh[2][BNC * SPITCH];
-  __shared__ __attribute__((aligned(16))) uint16_t Bl[2][BNC * SPITCH];
-  const int tid = threadIdx.x;
-  const int lane = tid & 63, wave = tid >> 6;
-  const int wm = wave >> 1, wn = wave & 1;
-  const int h = lane >> 5, l32 = lane & 31, p = lane & 1;
-  const TileCoord tc = map_tile(tiles_m, tiles_n, total);
-  int64_t oa, ob;
-  batch_offsets(d, tc.b, oa, ob);
-  const float2* __restrict__ A = d.A + oa;
-  const float2* __restrict__ B = d.B + ob;
-
+template <int WM, int WN, int VW>
+struct OpsBF16x3 {
+  using S = Shape<WM, WN>;
   // hi*hi products and the two cross products accumulate separately: the
   // cross terms are ~2^-8 smaller, so their rounding barely adds to that of
   // the main sum
   f16v acc[2][2], accx[2][2];
-#pragma unroll
-  for (int i = 0; i < 2; ++i)
-#pragma unroll
-    for (int j = 0; j < 2; ++j)
-#pragma unroll
-      for (int v = 0; v < 16; ++v) acc[i][j][v] = accx[i][j][v] = 0.f;
 
-  auto store_split = [&](const Stage<VW>& st, int buf) {
+  __device__ __forceinline__ void init() {
 #pragma unroll
-    for (int i = 0; i < Stage<VW>::A_LOADS; ++i) {
-      const int idx = tid + 256 * i;
-      const int r = idx / Stage<VW>::PER_ROW;
-      const int c = (idx % Stage<VW>::PER_ROW) * VW;
-      uint16_t hi[4], lo[4];
-      split_bf16(st.a[i].x, hi[0], lo[0]);
-      split_bf16(st.a[i].y, hi[1], lo[1]);
-      split_bf16(st.a[i].z, hi[2], lo[2]);
-      split_bf16(st.a[i].w, hi[3], lo[3]);
-      for (int e = 0; e < 2 * VW; ++e) {
-        Ah[buf][r * SPITCH + 2 * c + e] = hi[e];
-        Al[buf][r * SPITCH + 2 * c + e] = lo[e];
-      }
-    }
+    for (int i = 0; i < 2; ++i)
 #pragma unroll
-    for (int i = 0; i < Stage<VW>::B_LOADS; ++i) {
-      const int idx = tid + 256 * i;
-      const int r = idx / Stage<VW>::PER_ROW;
-      const int c = (idx % Stage<VW>::PER_ROW) * VW;
-      uint16_t hi[4], lo[4];
-      split_bf16(st.b[i].x, hi[0], lo[0]);
-      split_bf16(st.b[i].y, hi[1], lo[1]);
-      split_bf16(st.b[i].z, hi[2], lo[2]);
-      split_bf16(st.b[i].w, hi[3], lo[3]);
-      for (int e = 0; e < 2 * VW; ++e) {
-        Bh[buf][r * SPITCH + 2 * c + e] = hi[e];
-        Bl[buf][r * SPITCH + 2 * c + e] = lo[e];
-      }
-    }
-  };
+      for (int j = 0; j < 2; ++j)
+#pragma unroll
+        for (int v = 0; v < 16; ++v) acc[i][j][v] = accx[i][j][v] = 0.f;
+  }
 
-  // The bf16 MFMA 32x32x16: lane (h, r) supplies 8 consecutive K values of
-  // row r; here K = the 32 real k' of one stage, lane half h taking
-  // k' = 8*(2s + h) .. +7 for sub-step s in {0, 1}.
-  const int64_t nk = (d.k + BKC - 1) / BKC;
-  Stage<VW> st;
-  st.load(A, B, d.m, d.n, d.k, tc.row0, tc.col0, 0, tid);
-  store_split(st, 0);
-  __syncthreads();
-  for (int64_t kt = 0; kt < nk; ++kt) {
-    const int buf = kt & 1;
-    if (kt + 1 < nk) st.load(A, B, d.m, d.n, d.k, tc.row0, tc.col0, (kt + 1) * BKC, tid);
+  __device__ __forceinline__ static const uint16_t* planes(const char* lds, int buf) {
+    return reinterpret_cast<const uint16_t*>(lds) + buf * 2 * (S::BM + S::BNC) * SPITCH;
+  }
+
+  __device__ __forceinline__ void stage(const Stage<WM, WN, VW>& st, char* lds, int buf, int tid) const {
+    uint16_t* Ah = const_cast<uint16_t*>(planes(lds, buf));
+    uint16_t* Al = Ah + S::BM * SPITCH;
+    uint16_t* Bh = Al + S::BM * SPITCH;
+    uint16_t* Bl = Bh + S::BNC * SPITCH;
+    st.store_split(Ah, Al, Bh, Bl, tid);
+  }
+
+  // bf16 MFMA 32x32x16: lane (h, r) supplies 8 consecutive K values of row
+  // r; the stage's 32 real k are two sub-steps, lane half h taking
+  // k = 8 * (2s + h) .. +7.
+  __device__ __forceinline__ void compute(const char* lds, int buf, int wm, int wn, int lane) {
+    const uint16_t* Ah = planes(lds, buf);
+    const uint16_t* Al = Ah + S::BM * SPITCH;
+    const uint16_t* Bh = Al + S::BM * SPITCH;
+    const uint16_t* Bl = Bh + S::BNC * SPITCH;
+    const int h = lane >> 5, l32 = lane & 31, p = lane & 1;
 #pragma unroll
     for (int s = 0; s < 2; ++s) {
       const int koff = 8 * (2 * s + h);
@@ -431,14 +359,14 @@ __global__ __launch_bounds__(256) void cgemm_4m_bf16x3(GemmDesc d, int64_t tiles
 #pragma unroll
       for (int i = 0; i < 2; ++i) {
         const int row = wm * 64 + i * 32 + l32;
-        ah[i] = *reinterpret_cast<const s8v*>(&Ah[buf][row * SPITCH + koff]);
-        al[i] = *reinterpret_cast<const s8v*>(&Al[buf][row * SPITCH + koff]);
+        ah[i] = *reinterpret_cast<const s8v*>(Ah + row * SPITCH + koff);
+        al[i] = *reinterpret_cast<const s8v*>(Al + row * SPITCH + koff);
       }
 #pragma unroll
       for (int j = 0; j < 2; ++j) {
         const int row = wn * 32 + j * 16 + (l32 >> 1);
-        const s8v rh = *reinterpret_cast<const s8v*>(&Bh[buf][row * SPITCH + koff]);
-        const s8v rl = *reinterpret_cast<const s8v*>(&Bl[buf][row * SPITCH + koff]);
+        const s8v rh = *reinterpret_cast<const s8v*>(Bh + row * SPITCH + koff);
+        const s8v rl = *reinterpret_cast<const s8v*>(Bl + row * SPITCH + koff);
         s8v th, tl;
 #pragma unroll
         for (int e = 0; e < 8; e += 2) {
@@ -464,187 +392,132 @@ __global__ __launch_bounds__(256) void cgemm_4m_bf16x3(GemmDesc d, int64_t tiles
                                                               __builtin_bit_cast(bf8, bh[j]), acc[i][j], 0, 0, 0);
         }
     }
-    if (kt + 1 < nk) store_split(st, buf ^ 1);
+  }
+
+  __device__ __forceinline__ void store(const GemmDesc& d, bool perm, const TileCoord& tc, int wm, int wn,
+                                        int lane) const {
+    const int h = lane >> 5, l32 = lane & 31;
+    float* C = reinterpret_cast<float*>(d.C);
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+      for (int j = 0; j < 2; ++j) {
+        const int64_t ncr = tc.col0 * 2 + wn * 64 + j * 32 + l32;
+        const int64_t col = ncr >> 1;
+        if (col >= d.n) continue;
+#pragma unroll
+        for (int v = 0; v < 16; ++v) {
+          const int64_t row = tc.row0 + wm * 64 + i * 32 + 8 * (v >> 2) + 4 * h + (v & 3);
+          if (row < d.m) C[2 * c_index(d, perm, tc.b, row, col) + (ncr & 1)] = acc[i][j][v] + accx[i][j][v];
+        }
+      }
+  }
+};
+
+// ------------------------------------------------------------------ driver
+template <int WM, int WN, int VW, bool CHECK, class Ops>
+__device__ __forceinline__ void main_loop(const GemmDesc& d, const float2* A, const float2* B, const TileCoord& tc,
+                                          char* lds, Ops& ops, int tid, int wm, int wn, int lane) {
+  const int64_t nk = (d.k + BKC - 1) / BKC;
+  Stage<WM, WN, VW> st;
+  st.template load<CHECK>(A, B, d.m, d.n, d.k, tc.row0, tc.col0, 0, tid);
+  ops.stage(st, lds, 0, tid);
+  __syncthreads();
+  for (int64_t kt = 0; kt < nk; ++kt) {
+    const int buf = kt & 1;
+    if (kt + 1 < nk) st.template load<CHECK>(A, B, d.m, d.n, d.k, tc.row0, tc.col0, (kt + 1) * BKC, tid);
+    ops.compute(lds, buf, wm, wn, lane);
+    if (kt + 1 < nk) ops.stage(st, lds, buf ^ 1, tid);
     __syncthreads();
   }
-
-  float* C = reinterpret_cast<float*>(d.C);
-#pragma unroll
-  for (int i = 0; i < 2; ++i)
-#pragma unroll
-    for (int j = 0; j < 2; ++j) {
-      const int64_t ncr = tc.col0 * 2 + wn * 64 + j * 32 + l32;
-      const int64_t col = ncr >> 1;
-      if (col >= d.n) continue;
-#pragma unroll
-      for (int v = 0; v < 16; ++v) {
-        const int64_t row = tc.row0 + wm * 64 + i * 32 + 8 * (v >> 2) + 4 * h + (v & 3);
-        if (row < d.m) C[2 * c_index(d, PERM, tc.b, row, col) + (ncr & 1)] = acc[i][j][v] + accx[i][j][v];
-      }
-    }
 }
 
-// ------------------------------------------------------------------ small shapes (VALU)
-__device__ __forceinline__ float bf16_round(float x) { return __uint_as_float(bf16_rne_bits(x)); }
-
-// a*b with both factors split: hi = a_hi b_hi, cross = a_hi b_lo + a_lo b_hi
-// (each product exact in FP32).
-__device__ __forceinline__ void split_mul(float a, float b, float& hi, float& cross) {
-  const float ah = bf16_round(a), al = bf16_round(a - ah);
-  const float bh = bf16_round(b), bl = bf16_round(b - bh);
-  hi = ah * bh;
-  cross = ah * bl + al * bh;
-}
-
-template <bool SPLIT>
-__global__ __launch_bounds__(256) void cgemm_small(GemmDesc d) {
-  const int64_t mn = d.m * d.n;
-  const int64_t total = d.h * mn;
-  for (int64_t idx = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x; idx < total;
-       idx += static_cast<int64_t>(gridDim.x) * blockDim.x) {
-    const int64_t b = idx / mn;
-    const int64_t r = idx - b * mn;
-    const int64_t i = r / d.n;
-    const int64_t j = r - i * d.n;
-    int64_t oa, ob;
-    batch_offsets(d, b, oa, ob);
-    const float2* a = d.A + oa + i * d.k;
-    const float2* bb = d.B + ob + j * d.k;
-    float cr = 0.f, ci = 0.f, crx = 0.f, cix = 0.f;
-    for (int64_t l = 0; l < d.k; ++l) {
-      const float2 x = a[l];
-      const float2 y = bb[l];
-      if constexpr (SPLIT) {
-        float h1, x1, h2, x2, h3, x3, h4, x4;
-        split_mul(x.x, y.x, h1, x1);
-        split_mul(x.y, y.y, h2, x2);
-        split_mul(x.x, y.y, h3, x3);
-        split_mul(x.y, y.x, h4, x4);
-        cr += h1;
-        cr -= h2;
-        ci += h3;
-        ci += h4;
-        crx += x1 - x2;
-        cix += x3 + x4;
-      } else {
-        cr = fmaf(x.x, y.x, cr);
-        cr = fmaf(-x.y, y.y, cr);
-        ci = fmaf(x.x, y.y, ci);
-        ci = fmaf(x.y, y.x, ci);
-      }
-    }
-    const int64_t c = b * mn + (d.offM ? d.offM[i] + d.offN[j] : r);
-    d.C[c] = make_float2(cr + crx, ci + cix);
-  }
-}
-
-// Long reductions with few outputs (k large, m*n tiny): one wave64 per output
-// element; lanes stride over k with coalesced reads and the 64 partial sums
-// are combined by a fixed butterfly, so the summation error grows like
-// (k/64 + 6) roundings instead of k.
-template <bool SPLIT>
-__global__ __launch_bounds__(256) void cgemm_dot(GemmDesc d) {
-  const int lane = threadIdx.x & 63;
-  const int64_t mn = d.m * d.n;
-  const int64_t total = d.h * mn;
-  const int64_t out = static_cast<int64_t>(blockIdx.x) * 4 + (threadIdx.x >> 6);
-  if (out >= total) return;  // uniform per wave
-  const int64_t b = out / mn;
-  const int64_t r = out - b * mn;
-  const int64_t i = r / d.n;
-  const int64_t j = r - i * d.n;
+template <template <int, int, int> class OpsT, int WM, int WN, int VW, bool PERM>
+__global__ __launch_bounds__(64 * WM * WN) void cgemm_mfma(GemmDesc d, int64_t tiles_m, int64_t tiles_n,
+                                                           int64_t total) {
+  using S = Shape<WM, WN>;
+  extern __shared__ __attribute__((aligned(16))) char lds[];
+  const int tid = threadIdx.x;
+  const int lane = tid & 63, wave = tid >> 6;
+  const int wm = wave / WN, wn = wave % WN;
+  const TileCoord tc = map_tile<S::BM, S::BNC>(tiles_m, tiles_n, total);
   int64_t oa, ob;
-  batch_offsets(d, b, oa, ob);
-  const float2* a = d.A + oa + i * d.k;
-  const float2* bb = d.B + ob + j * d.k;
-  float cr = 0.f, ci = 0.f, crx = 0.f, cix = 0.f;
-  for (int64_t l = lane; l < d.k; l += 64) {
-    const float2 x = a[l];
-    const float2 y = bb[l];
-    if constexpr (SPLIT) {
-      float h1, x1, h2, x2, h3, x3, h4, x4;
-      split_mul(x.x, y.x, h1, x1);
-      split_mul(x.y, y.y, h2, x2);
-      split_mul(x.x, y.y, h3, x3);
-      split_mul(x.y, y.x, h4, x4);
-      cr += h1;
-      cr -= h2;
-      ci += h3;
-      ci += h4;
-      crx += x1 - x2;
-      cix += x3 + x4;
-    } else {
-      cr = fmaf(x.x, y.x, cr);
-      cr = fmaf(-x.y, y.y, cr);
-      ci = fmaf(x.x, y.y, ci);
-      ci = fmaf(x.y, y.x, ci);
-    }
+  batch_offsets(d, tc.b, oa, ob);
+  const float2* __restrict__ A = d.A + oa;
+  const float2* __restrict__ B = d.B + ob;
+  OpsT<WM, WN, VW> ops;
+  ops.init();
+  const bool interior = tc.row0 + S::BM <= d.m && tc.col0 + S::BNC <= d.n && d.k % BKC == 0;
+  if (interior)
+    main_loop<WM, WN, VW, false>(d, A, B, tc, lds, ops, tid, wm, wn, lane);
+  else
+    main_loop<WM, WN, VW, true>(d, A, B, tc, lds, ops, tid, wm, wn, lane);
+  ops.store(d, PERM, tc, wm, wn, lane);
+}
+
+template <template <int, int, int> class OpsT, int WM, int WN, int VW, bool PERM>
+hipError_t launch_one(const GemmDesc& d, size_t lds, hipStream_t s) {
+  using S = Shape<WM, WN>;
+  const int64_t tiles_m = (d.m + S::BM - 1) / S::BM;
+  const int64_t tiles_n = (d.n + S::BNC - 1) / S::BNC;
+  const int64_t total = tiles_m * tiles_n * d.h;
+  // one workgroup per tile; the grid's work-items must fit 32 bits
+  if (total * S::NT > 0xFFFFFFFFLL) return hipErrorInvalidValue;
+  auto kern = cgemm_mfma<OpsT, WM, WN, VW, PERM>;
+  static bool attr_set = false;
+  if (!attr_set && lds > 65536) {
+    const hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(kern),
+                                             hipFuncAttributeMaxDynamicSharedMemorySize, static_cast<int>(lds));
+    if (e != hipSuccess) return e;
+    attr_set = true;
   }
-  cr += crx;
-  ci += cix;
-#pragma unroll
-  for (int off = 32; off > 0; off >>= 1) {
-    cr += __shfl_xor(cr, off, 64);
-    ci += __shfl_xor(ci, off, 64);
+  hipLaunchKernelGGL(kern, dim3(static_cast<unsigned>(total)), dim3(S::NT), lds, s, d, tiles_m, tiles_n, total);
+  return hipGetLastError();
+}
+
+template <template <int, int, int> class OpsT, int WM, int WN>
+hipError_t launch_shape(const GemmDesc& d, bool bf16, hipStream_t s) {
+  using S = Shape<WM, WN>;
+  const size_t lds = bf16 ? S::lds_bf16 : S::lds_f32;
+  const bool perm = d.offM != nullptr;
+  return perm ? launch_one<OpsT, WM, WN, 2, true>(d, lds, s) : launch_one<OpsT, WM, WN, 2, false>(d, lds, s);
+}
+
+template <template <int, int, int> class OpsT>
+hipError_t launch_variant(const GemmDesc& d, int variant, bool bf16, hipStream_t s) {
+  if (d.k % 2 != 0) {  // odd k: 8-byte loads, default shape only
+    const size_t lds = bf16 ? Shape<2, 2>::lds_bf16 : Shape<2, 2>::lds_f32;
+    return d.offM ? launch_one<OpsT, 2, 2, 1, true>(d, lds, s) : launch_one<OpsT, 2, 2, 1, false>(d, lds, s);
   }
-  if (lane == 0) {
-    const int64_t c = b * mn + (d.offM ? d.offM[i] + d.offN[j] : r);
-    d.C[c] = make_float2(cr, ci);
+  switch (variant) {
+    case 0: return launch_shape<OpsT, 2, 2>(d, bf16, s);
+    case 1: return launch_shape<OpsT, 4, 2>(d, bf16, s);
+    case 2: return launch_shape<OpsT, 2, 4>(d, bf16, s);
+    case 3: return launch_shape<OpsT, 4, 4>(d, bf16, s);
+    case 4: return launch_shape<OpsT, 1, 2>(d, bf16, s);
+    case 5: return launch_shape<OpsT, 2, 1>(d, bf16, s);
+    case 6: return launch_shape<OpsT, 1, 1>(d, bf16, s);
+    default: return hipErrorInvalidValue;
   }
 }
 
 }  // namespace
 
-hipError_t launch_gemm(const GemmDesc& d, GemmKernel kind, Form form, Prec prec, hipStream_t s) {
+void gemm_variant_tile(int variant, int* bm, int* bnc) {
+  static const int wm[kGemmVariants] = {2, 4, 2, 4, 1, 2, 1};
+  static const int wn[kGemmVariants] = {2, 2, 4, 4, 2, 1, 1};
+  if (variant < 0 || variant >= kGemmVariants) variant = 0;
+  *bm = 64 * wm[variant];
+  *bnc = 32 * wn[variant];
+}
+
+hipError_t launch_gemm(const GemmDesc& d, GemmKernel kind, int variant, Form form, Prec prec, hipStream_t s) {
   if (d.h <= 0 || d.m <= 0 || d.n <= 0) return hipSuccess;
   if (d.k <= 0) return hipErrorInvalidValue;
-  if (kind == GemmKernel::DOT) {
-    const int64_t total = d.h * d.m * d.n;
-    const int64_t grid = (total + 3) / 4;
-    if (grid > 0x7FFFFFLL) return hipErrorInvalidValue;
-    if (prec == Prec::BF16X3)
-      hipLaunchKernelGGL(cgemm_dot<true>, dim3(grid), dim3(256), 0, s, d);
-    else
-      hipLaunchKernelGGL(cgemm_dot<false>, dim3(grid), dim3(256), 0, s, d);
-    return hipGetLastError();
-  }
-  if (kind == GemmKernel::SMALL) {
-    const int64_t total = d.h * d.m * d.n;
-    int64_t grid = (total + 255) / 256;
-    if (grid > 1048576) grid = 1048576;
-    if (prec == Prec::BF16X3)
-      hipLaunchKernelGGL(cgemm_small<true>, dim3(grid), dim3(256), 0, s, d);
-    else
-      hipLaunchKernelGGL(cgemm_small<false>, dim3(grid), dim3(256), 0, s, d);
-    return hipGetLastError();
-  }
-  const int64_t tiles_m = (d.m + BM - 1) / BM;
-  const int64_t tiles_n = (d.n + BNC - 1) / BNC;
-  const int64_t total = tiles_m * tiles_n * d.h;
-  // one workgroup per tile; the grid's x extent times 256 must fit 32 bits
-  if (total > (1LL << 24) - 1) return hipErrorInvalidValue;
-  const bool vec2 = (d.k % 2) == 0;
-  const bool perm = d.offM != nullptr;
-  const dim3 grid(static_cast<unsigned>(total)), block(256);
-#define TNC_GEMM_LAUNCH(KERN)                                                                 \
-  do {                                                                                        \
-    if (vec2 && perm)                                                                         \
-      hipLaunchKernelGGL((KERN<2, true>), grid, block, 0, s, d, tiles_m, tiles_n, total);     \
-    else if (vec2)                                                                            \
-      hipLaunchKernelGGL((KERN<2, false>), grid, block, 0, s, d, tiles_m, tiles_n, total);    \
-    else if (perm)                                                                            \
-      hipLaunchKernelGGL((KERN<1, true>), grid, block, 0, s, d, tiles_m, tiles_n, total);     \
-    else                                                                                      \
-      hipLaunchKernelGGL((KERN<1, false>), grid, block, 0, s, d, tiles_m, tiles_n, total);    \
-  } while (0)
-  if (prec == Prec::BF16X3)
-    TNC_GEMM_LAUNCH(cgemm_4m_bf16x3);
-  else if (form == Form::M3)
-    TNC_GEMM_LAUNCH(cgemm_3m_mfma);
-  else
-    TNC_GEMM_LAUNCH(cgemm_4m_mfma);
-#undef TNC_GEMM_LAUNCH
-  return hipGetLastError();
+  if (kind != GemmKernel::MFMA) return launch_gemm_valu(d, kind, prec, s);
+  if (prec == Prec::BF16X3) return launch_variant<OpsBF16x3>(d, variant, true, s);
+  if (form == Form::M3) return launch_variant<Ops3M>(d, variant, false, s);
+  return launch_variant<Ops4M>(d, variant, false, s);
 }
 
 }  // namespace tnc

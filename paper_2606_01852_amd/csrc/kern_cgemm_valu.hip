@@ -1,0 +1,141 @@
+// Complex GEMM kernels for shapes that do not fill MFMA tiles (VALU).
+//
+// cgemm_small: one thread per output element, k looped in order; used for
+// the many tiny steps of circuit networks (m, n or k of a few elements).
+// cgemm_dot:   one wave64 per output element for long reductions with few
+// outputs (k large, m*n tiny); the 64 partial sums are combined by a fixed
+// butterfly, so the summation error grows like k/64 + 6 roundings, not k.
+// Both honour the split-bf16 precision with the same products as the MFMA
+// kernel (hi*hi and the two cross products accumulated separately).
+#include "gemm_common.hpp"
+
+namespace tnc {
+
+namespace {
+
+template <bool SPLIT>
+__global__ __launch_bounds__(256) void cgemm_small(GemmDesc d) {
+  const int64_t mn = d.m * d.n;
+  const int64_t total = d.h * mn;
+  for (int64_t idx = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x; idx < total;
+       idx += static_cast<int64_t>(gridDim.x) * blockDim.x) {
+    const int64_t b = idx / mn;
+    const int64_t r = idx - b * mn;
+    const int64_t i = r / d.n;
+    const int64_t j = r - i * d.n;
+    int64_t oa, ob;
+    batch_offsets(d, b, oa, ob);
+    const float2* a = d.A + oa + i * d.k;
+    const float2* bb = d.B + ob + j * d.k;
+    float cr = 0.f, ci = 0.f, crx = 0.f, cix = 0.f;
+    for (int64_t l = 0; l < d.k; ++l) {
+      const float2 x = a[l];
+      const float2 y = bb[l];
+      if constexpr (SPLIT) {
+        float h1, x1, h2, x2, h3, x3, h4, x4;
+        split_mul(x.x, y.x, h1, x1);
+        split_mul(x.y, y.y, h2, x2);
+        split_mul(x.x, y.y, h3, x3);
+        split_mul(x.y, y.x, h4, x4);
+        cr += h1;
+        cr -= h2;
+        ci += h3;
+        ci += h4;
+        crx += x1 - x2;
+        cix += x3 + x4;
+      } else {
+        cr = fmaf(x.x, y.x, cr);
+        cr = fmaf(-x.y, y.y, cr);
+        ci = fmaf(x.x, y.y, ci);
+        ci = fmaf(x.y, y.x, ci);
+      }
+    }
+    const int64_t c = b * mn + (d.offM ? d.offM[i] + d.offN[j] : r);
+    d.C[c] = make_float2(cr + crx, ci + cix);
+  }
+}
+
+// Long reductions with few outputs (k large, m*n tiny): one wave64 per output
+// element; lanes stride over k with coalesced reads and the 64 partial sums
+// are combined by a fixed butterfly, so the summation error grows like
+// (k/64 + 6) roundings instead of k.
+template <bool SPLIT>
+__global__ __launch_bounds__(256) void cgemm_dot(GemmDesc d) {
+  const int lane = threadIdx.x & 63;
+  const int64_t mn = d.m * d.n;
+  const int64_t total = d.h * mn;
+  const int64_t out = static_cast<int64_t>(blockIdx.x) * 4 + (threadIdx.x >> 6);
+  if (out >= total) return;  // uniform per wave
+  const int64_t b = out / mn;
+  const int64_t r = out - b * mn;
+  const int64_t i = r / d.n;
+  const int64_t j = r - i * d.n;
+  int64_t oa, ob;
+  batch_offsets(d, b, oa, ob);
+  const float2* a = d.A + oa + i * d.k;
+  const float2* bb = d.B + ob + j * d.k;
+  float cr = 0.f, ci = 0.f, crx = 0.f, cix = 0.f;
+  for (int64_t l = lane; l < d.k; l += 64) {
+    const float2 x = a[l];
+    const float2 y = bb[l];
+    if constexpr (SPLIT) {
+      float h1, x1, h2, x2, h3, x3, h4, x4;
+      split_mul(x.x, y.x, h1, x1);
+      split_mul(x.y, y.y, h2, x2);
+      split_mul(x.x, y.y, h3, x3);
+      split_mul(x.y, y.x, h4, x4);
+      cr += h1;
+      cr -= h2;
+      ci += h3;
+      ci += h4;
+      crx += x1 - x2;
+      cix += x3 + x4;
+    } else {
+      cr = fmaf(x.x, y.x, cr);
+      cr = fmaf(-x.y, y.y, cr);
+      ci = fmaf(x.x, y.y, ci);
+      ci = fmaf(x.y, y.x, ci);
+    }
+  }
+  cr += crx;
+  ci += cix;
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) {
+    cr += __shfl_xor(cr, off, 64);
+    ci += __shfl_xor(ci, off, 64);
+  }
+  if (lane == 0) {
+    const int64_t c = b * mn + (d.offM ? d.offM[i] + d.offN[j] : r);
+    d.C[c] = make_float2(cr, ci);
+  }
+}
+
+}  // namespace
+
+hipError_t launch_gemm_valu(const GemmDesc& d, GemmKernel kind, Prec prec, hipStream_t s) {
+  if (d.h <= 0 || d.m <= 0 || d.n <= 0) return hipSuccess;
+  if (d.k <= 0) return hipErrorInvalidValue;
+  if (kind == GemmKernel::DOT) {
+    const int64_t total = d.h * d.m * d.n;
+    const int64_t grid = (total + 3) / 4;
+    if (grid > 0x7FFFFFLL) return hipErrorInvalidValue;
+    if (prec == Prec::BF16X3)
+      hipLaunchKernelGGL(cgemm_dot<true>, dim3(grid), dim3(256), 0, s, d);
+    else
+      hipLaunchKernelGGL(cgemm_dot<false>, dim3(grid), dim3(256), 0, s, d);
+    return hipGetLastError();
+  }
+  if (kind == GemmKernel::SMALL) {
+    const int64_t total = d.h * d.m * d.n;
+    int64_t grid = (total + 255) / 256;
+    if (grid > 1048576) grid = 1048576;
+    if (prec == Prec::BF16X3)
+      hipLaunchKernelGGL(cgemm_small<true>, dim3(grid), dim3(256), 0, s, d);
+    else
+      hipLaunchKernelGGL(cgemm_small<false>, dim3(grid), dim3(256), 0, s, d);
+    return hipGetLastError();
+  }
+  return hipErrorInvalidValue;
+}
+
+}  // namespace tnc

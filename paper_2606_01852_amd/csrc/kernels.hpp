@@ -80,7 +80,12 @@ struct GatherDesc {
   const int64_t* base_dev;
 };
 
-hipError_t launch_gemm(const GemmDesc& d, GemmKernel kind, Form form, Prec prec, hipStream_t s);
+// MFMA tile variants: variant v uses workgroups of WM x WN wave64, each
+// wave owning 64 x 32 complex of C (gemm_variant_tile gives the block tile).
+constexpr int kGemmVariants = 7;
+void gemm_variant_tile(int variant, int* bm, int* bnc);
+hipError_t launch_gemm(const GemmDesc& d, GemmKernel kind, int variant, Form form, Prec prec, hipStream_t s);
+hipError_t launch_gemm_valu(const GemmDesc& d, GemmKernel kind, Prec prec, hipStream_t s);
 hipError_t launch_permute(const PermuteDesc& d, hipStream_t s);
 hipError_t launch_gather(const GatherDesc& d, hipStream_t s);
 // acc[i] += sum_s root[s * R + i] (complex64 in, complex128 out), pairwise

@@ -602,6 +602,7 @@ std::unique_ptr<ChunkPlan> build_chunk(const Plan& plan, int j) {
       cp->result_perm[u] = o;
     }
   }
+  assign_variants(plan, *cp, false);
   return cp;
 }
 

@@ -43,7 +43,7 @@ class PlanInfo(C.Structure):
 class StepInfo(C.Structure):
     _fields_ = [("A", C.c_int32), ("B", C.c_int32), ("C", C.c_int32), ("nH", C.c_int32), ("nM", C.c_int32),
                 ("nN", C.c_int32), ("nK", C.c_int32), ("h", C.c_int64), ("m", C.c_int64), ("n", C.c_int64),
-                ("k", C.c_int64), ("natural", C.c_int32), ("kernel", C.c_int32)]
+                ("k", C.c_int64), ("natural", C.c_int32), ("kernel", C.c_int32), ("variant", C.c_int32)]
 
 
 _P = C.c_void_p
@@ -58,6 +58,8 @@ _SIGS = {
     "tnc_ctx_create": (C.c_int, [C.c_int, _P, C.c_size_t, _P, C.POINTER(_P)]),
     "tnc_ctx_destroy": (C.c_int, [_P]),
     "tnc_ctx_sync": (C.c_int, [_P]),
+    "tnc_ctx_set_gemm_variant": (C.c_int, [_P, C.c_int32]),
+    "tnc_gemm_variant_count": (C.c_int, []),
     "tnc_net_create": (C.c_int, [_P, C.c_int32, _I32P, _I32P, C.c_int32, _I64P, C.c_int32, _I32P,
                                  C.POINTER(_P), C.c_int, C.POINTER(_P)]),
     "tnc_net_set_tensor": (C.c_int, [_P, C.c_int32, _P, C.c_int]),
@@ -70,6 +72,7 @@ _SIGS = {
     "tnc_plan_get_order": (C.c_int, [_P, C.c_int32, _I32P, C.c_int32, _I32P]),
     "tnc_plan_set_max_chunk": (C.c_int, [_P, C.c_int64]),
     "tnc_plan_set_graph": (C.c_int, [_P, C.c_int32]),
+    "tnc_plan_autotune": (C.c_int, [_P]),
     "tnc_plan_set_profile": (C.c_int, [_P, C.c_int32]),
     "tnc_plan_get_profile": (C.c_int, [_P, C.c_int32, _DP, _I64P]),
     "tnc_contract": (C.c_int, [_P, C.c_int64, C.c_int64, _DP]),
@@ -143,6 +146,14 @@ def tnc_ctx_sync(ctx: int) -> None:
     _check(lib().tnc_ctx_sync(ctx))
 
 
+def tnc_ctx_set_gemm_variant(ctx: int, variant: int) -> None:
+    _check(lib().tnc_ctx_set_gemm_variant(ctx, variant))
+
+
+def tnc_gemm_variant_count() -> int:
+    return int(lib().tnc_gemm_variant_count())
+
+
 def tnc_net_create(ctx: int, labels: Sequence[Sequence[int]], extents: Sequence[int], open_labels: Sequence[int],
                    leaves: Optional[Sequence[np.ndarray]]) -> int:
     ranks = _i32([len(l) for l in labels])
@@ -210,6 +221,10 @@ def tnc_plan_get_order(plan: int, tensor_id: int) -> list:
 
 def tnc_plan_set_max_chunk(plan: int, max_chunk: int) -> None:
     _check(lib().tnc_plan_set_max_chunk(plan, max_chunk))
+
+
+def tnc_plan_autotune(plan: int) -> None:
+    _check(lib().tnc_plan_autotune(plan))
 
 
 def tnc_plan_set_graph(plan: int, enable: bool) -> None:

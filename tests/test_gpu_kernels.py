@@ -156,3 +156,53 @@ def test_cgemm_bf16x3_matches_split_emulation(ctx, shape):
     # against the exact product: a-priori bound of the split (3 * 2**-16 per
     # real product), far looser than the emulation match above
     assert rel_fro(got, exact) <= 3 * 2.0 ** -16 * 4
+
+
+@pytest.mark.parametrize("variant", range(7))
+@pytest.mark.parametrize("kind", ["4M", "3M", "bf16x3"])
+def test_every_tile_variant(ctx, variant, kind):
+    """Each MFMA workgroup shape on an interior-tile shape and a ragged one."""
+    prec = tnc.PREC_BF16X3 if kind == "bf16x3" else tnc.PREC_C64
+    form = tnc.GEMM_3M if kind == "3M" else tnc.GEMM_4M
+    tnc.tnc_ctx_set_gemm_variant(ctx.handle, variant)
+    try:
+        for (h, m, n, k) in ((2, 512, 256, 64), (3, 333, 111, 70)):
+            rng = np.random.Generator(np.random.PCG64(variant * 100 + m))
+            A, B = cn(rng, (h, m, k)), cn(rng, (h, n, k))
+            print(f"variant {variant} {kind} shape {(h, m, n, k)}", flush=True)
+            Ad, Bd = to_dev(torch, A), to_dev(torch, B)
+            Cd = torch.empty((h, m, n), dtype=torch.complex64, device="cuda")
+            torch.view_as_real(Cd).fill_(float("nan"))
+            tnc.tnc_batched_cgemm(ctx.handle, h, m, n, k, Ad.data_ptr(), m * k, Bd.data_ptr(), n * k,
+                                  Cd.data_ptr(), prec, form)
+            torch.cuda.synchronize()
+            got = from_dev(Cd)
+            ref = split_emulated_gemm(A, B) if kind == "bf16x3" else ref_gemm(A, B)
+            assert rel_fro(got, ref) <= 1e-5
+    finally:
+        tnc.tnc_ctx_set_gemm_variant(ctx.handle, -1)
+
+
+def test_autotune_keeps_results_and_persists(ctx, tmp_path, monkeypatch):
+    from workloads.pairs import pair_network
+    from oracle import contract as oc
+    cache = tmp_path / "tune.txt"
+    monkeypatch.setenv("TNC_AUTOTUNE_CACHE", str(cache))
+    c2 = tnc.Context(0, arena_bytes=512 << 20)
+    net, path = pair_network(11, 9, 9, seed=12)
+    tn = tnc.Network(c2, net.labels, net.extents, net.open, net.c64().leaves)
+    plan = tnc.Plan(tn, path.pairs)
+    before = plan.contract()
+    tnc.tnc_plan_autotune(plan.handle)
+    v = tnc.tnc_plan_get_step(plan.handle, 0).variant
+    assert 0 <= v < tnc.tnc_gemm_variant_count()
+    after = plan.contract()
+    ref = oc.contract(net, path).reshape(-1)
+    assert rel_fro(after, ref) <= 1e-5 and rel_fro(before, ref) <= 1e-5
+    lines = cache.read_text().split()
+    assert len(lines) == 8 and int(lines[-1]) == v
+    # a new context reads the cache back and assigns the same variant untimed
+    c3 = tnc.Context(0, arena_bytes=512 << 20)
+    tn3 = tnc.Network(c3, net.labels, net.extents, net.open, net.c64().leaves)
+    plan3 = tnc.Plan(tn3, path.pairs)
+    assert tnc.tnc_plan_get_step(plan3.handle, 0).variant == v

@@ -35,7 +35,7 @@ def test_library_exports_every_declared_symbol():
     assert len(names) >= 25
     for name in names:
         assert hasattr(L, name), name
-    assert set(names) == set(tnc.exported_symbols())
+    assert set(names) == set(tnc.exported_symbols()), set(names) ^ set(tnc.exported_symbols())
     assert "gfx950" in tnc.tnc_version()
 
 
