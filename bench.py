@@ -34,10 +34,11 @@ PEAK_FP32_MFMA = 157.3   # TFLOP/s, MI355X dense FP32 matrix
 PEAK_BF16_MFMA = 2516.6  # TFLOP/s, MI355X dense bf16 matrix
 PEAK_HBM = 8000.0        # GB/s
 
-# HBM traffic per launch of the dominant kernel, from rocprofv3 --pmc
-# FETCH_SIZE / WRITE_SIZE (KiB per dispatch) scaled by the same counters on
-# a copy kernel of known size; None until measured for the current kernel.
-GEMM_TRAFFIC_BYTES = None
+# HBM traffic per launch of the dominant kernel (4M GEMM, 4x4-wave tiles, the
+# 2^30-output contraction), from rocprofv3 --pmc FETCH_SIZE (212,037,464 KiB,
+# x2.0) and WRITE_SIZE (8,388,609 KiB, x1.0); the factors are what the same
+# counters read for a 4 GiB device copy.  Set to None when the kernel changes.
+GEMM_TRAFFIC_BYTES = 442.8e9
 
 
 def log(msg: str) -> None:
@@ -53,7 +54,7 @@ def parse():
     ap.add_argument("--prec", choices=["c64", "bf16x3"], default="c64")
     ap.add_argument("--scale", type=int, default=0, help="drop this many modes from each group (smaller run)")
     ap.add_argument("--no-cpu", action="store_true")
-    ap.add_argument("--workload", choices=["pair30", "circuit40", "serve"], default="pair30")
+    ap.add_argument("--workload", choices=["pair30", "circuit40", "serve", "small"], default="pair30")
     ap.add_argument("--no-serve", action="store_true", help="skip the serving-latency leg")
     ap.add_argument("--serve-pool", type=int, default=12)
     ap.add_argument("--serve-requests", type=int, default=150)
@@ -188,6 +189,66 @@ def serving_leg(args):
     return res
 
 
+def bench_small(args):
+    """Latency-bound and mixed workloads: the 12-qubit circuit amplitude
+    (153 tiny steps) eager vs hipGraph replay, all 4096 amplitudes with the
+    FP64 norm, and the closed 8x8 bond-4 grid in complex64, 3M and split-bf16."""
+    import torch
+
+    from paper_2606_01852_amd import tnc
+    from workloads import configs
+    from workloads.circuits import circuit_network
+    from workloads.grids import prescale_log2
+    from workloads.network import Network
+    from workloads.paths import greedy_path
+
+    ctx = tnc.Context(0, arena_bytes=8 << 30, stream=torch.cuda.current_stream().cuda_stream)
+    out = {}
+
+    def timed(fn, reps):
+        fn()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            fn()
+        torch.cuda.synchronize()
+        return (time.perf_counter() - t0) / reps
+
+    net, path = configs.circuit12()
+    tn = tnc.Network(ctx, net.labels, net.extents, net.open, net.c64().leaves)
+    for graph in (False, True):
+        p = tnc.Plan(tn, path.pairs)
+        tnc.tnc_plan_set_graph(p.handle, graph)
+        dt = timed(lambda: p.contract(), 200)
+        out[f"circuit12_amplitude_{'graph' if graph else 'eager'}_us"] = round(dt * 1e6, 1)
+        p.close()
+    circ = configs.circuit12_circuit()
+    netall = circuit_network(circ, open_qubits=range(12))
+    pathall = greedy_path(netall)
+    tna = tnc.Network(ctx, netall.labels, netall.extents, netall.open, netall.c64().leaves)
+    pa = tnc.Plan(tna, pathall.pairs)
+    tnc.tnc_plan_set_graph(pa.handle, True)
+    dt = timed(lambda: pa.contract(), 100)
+    out["circuit12_all_4096_amplitudes_us"] = round(dt * 1e6, 1)
+    out["circuit12_norm2_minus_1"] = tnc.tnc_plan_result_norm2(pa.handle) - 1.0
+
+    g, _ = configs.grid8()
+    e = prescale_log2(g.labels)
+    gs = Network([x * 2.0 ** int(k) for x, k in zip(g.leaves, e)], g.labels, g.extents, ())
+    gpath = greedy_path(gs)
+    tg = tnc.Network(ctx, gs.labels, gs.extents, gs.open, gs.c64().leaves)
+    for name, prec, form in (("c64_4M", tnc.PREC_C64, tnc.GEMM_4M), ("c64_3M", tnc.PREC_C64, tnc.GEMM_3M),
+                             ("bf16x3", tnc.PREC_BF16X3, tnc.GEMM_4M)):
+        p = tnc.Plan(tg, gpath.pairs, (), prec, form)
+        tnc.tnc_plan_autotune(p.handle)
+        tnc.tnc_plan_set_graph(p.handle, True)
+        dt = timed(lambda: p.contract(), 20)
+        out[f"grid8_{name}_ms"] = round(dt * 1e3, 3)
+        out[f"grid8_{name}_tflops"] = round(p.info.flops_per_slice / dt / 1e12, 3)
+        p.close()
+    print(json.dumps({"small_workloads": out}), flush=True)
+
+
 def bench_circuit40(args):
     """Sliced 40-qubit circuit (5x8 grid, depth 12, 16 sliced labels = 65,536
     slices): the slices run as a batch dimension of every step, summed in FP64."""
@@ -261,6 +322,8 @@ def main():
         sys.exit(2)
     if args.workload == "circuit40":
         return bench_circuit40(args)
+    if args.workload == "small":
+        return bench_small(args)
     if args.workload == "serve":
         print(json.dumps({"serving": serving_leg(args)}), flush=True)
         return
