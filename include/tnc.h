@@ -180,6 +180,37 @@ tnc_status tnc_plan_set_profile(tnc_plan plan, int32_t enable);
  * enabled; step = -1 gives the leaf permutations, -2 the FP64 reductions. */
 tnc_status tnc_plan_get_profile(tnc_plan plan, int32_t step, double* ms, int64_t* launches);
 
+/* ---------------------------------------------------------------- distribution plan
+ * Offline planning of a multi-GPU execution (Sec. IV-B), on the host; this
+ * build executes nothing across GPUs.  Steps whose operands or output reach
+ * large_bytes start use-chains (the tensor's consumers up the tree, to the
+ * last large step); along each chain a DP over the distributed modes
+ * (Eq. (4) prefixes, tracked by label) chooses keep or redistribute per
+ * equation under the cost model of Eq. (5)-(7), with forced redistribution
+ * when a distributed mode is about to be summed and a gather at the end. */
+typedef struct {
+  double hbm_bytes_per_s;   /* B_dev: device memory bandwidth              */
+  double flops_per_s;       /* F_dev: device peak FLOP rate                */
+  double net_bytes_per_s;   /* B_net: interconnect bandwidth per device    */
+  double latency_s;         /* lambda: per-message latency                 */
+} tnc_dist_hw;
+typedef struct {
+  int32_t chain;            /* use-chain index                             */
+  int32_t step;             /* path step (equation)                        */
+  int32_t state;            /* 0 activate, 1 keep, 2 redistribute          */
+  int32_t n_dist;           /* distributed modes of the step's output      */
+  int32_t dist[16];         /* their labels, in mode order                 */
+  double t_gemm_s;          /* Eq. (6) per-device GEMM time                */
+  double t_comm_s;          /* Eq. (7) redistribution time (0 if kept)     */
+  double out_bytes;         /* |C| of the step                             */
+} tnc_dist_step;
+/* Writes min(cap, n) chain steps to steps[] (host array), sets *n_steps to
+ * n, *total_s to the summed optimal chain time (gathers included) and
+ * *redistributed_bytes to the all-to-all volume. */
+tnc_status tnc_plan_distribute(tnc_plan plan, int32_t n_gpus, double large_bytes, const tnc_dist_hw* hw,
+                               tnc_dist_step* steps, int32_t cap, int32_t* n_steps, double* total_s,
+                               double* redistributed_bytes);
+
 /* ---------------------------------------------------------------- contract
  * Sum over slices [first_slice, first_slice + n_slices) of the sliced
  * contractions, accumulated in FP64 on the device; out_c128 (host pointer,

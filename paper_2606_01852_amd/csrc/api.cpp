@@ -393,6 +393,25 @@ tnc_status tnc_plan_set_max_chunk(tnc_plan plan, int64_t max_chunk) {
   TNC_CATCH
 }
 
+tnc_status tnc_plan_distribute(tnc_plan plan, int32_t n_gpus, double large_bytes, const tnc_dist_hw* hw,
+                               tnc_dist_step* steps, int32_t cap, int32_t* n_steps, double* total_s,
+                               double* redistributed_bytes) {
+  TNC_TRY
+  if (!plan || !hw || !n_steps || !total_s || !redistributed_bytes || cap < 0 || (cap && !steps))
+    fail(TNC_E_ARG, "bad arguments");
+  if (n_gpus < 2) fail(TNC_E_ARG, "distribution needs at least two GPUs");
+  if (!(hw->hbm_bytes_per_s > 0) || !(hw->flops_per_s > 0) || !(hw->net_bytes_per_s > 0) || hw->latency_s < 0)
+    fail(TNC_E_ARG, "hardware constants must be positive");
+  std::vector<tnc_dist_step> out;
+  double total = 0, moved = 0;
+  plan_distribution(*plan->p, n_gpus, large_bytes, *hw, out, total, moved);
+  for (int i = 0; i < std::min<int>(cap, static_cast<int>(out.size())); ++i) steps[i] = out[i];
+  *n_steps = static_cast<int32_t>(out.size());
+  *total_s = total;
+  *redistributed_bytes = moved;
+  TNC_CATCH
+}
+
 tnc_status tnc_plan_autotune(tnc_plan plan) {
   TNC_TRY
   if (!plan) fail(TNC_E_ARG, "plan is NULL");

@@ -213,6 +213,10 @@ std::unique_ptr<ChunkPlan> build_chunk(const Plan& plan, int j);
 void choose_chunking(Plan& plan, size_t budget);
 size_t run_extra_bytes(const ChunkPlan& cp, int64_t n_chunks);
 
+// distplan.cpp
+void plan_distribution(const Plan& plan, int P, double large_bytes, const tnc_dist_hw& hw,
+                       std::vector<tnc_dist_step>& out, double& total, double& moved);
+
 // autotune.cpp
 int default_variant(tnc_prec prec, tnc_cgemm form, int64_t h, int64_t m, int64_t n);
 void load_tune_cache(Ctx& c);

@@ -46,6 +46,17 @@ class StepInfo(C.Structure):
                 ("k", C.c_int64), ("natural", C.c_int32), ("kernel", C.c_int32), ("variant", C.c_int32)]
 
 
+class DistHW(C.Structure):
+    _fields_ = [("hbm_bytes_per_s", C.c_double), ("flops_per_s", C.c_double),
+                ("net_bytes_per_s", C.c_double), ("latency_s", C.c_double)]
+
+
+class DistStep(C.Structure):
+    _fields_ = [("chain", C.c_int32), ("step", C.c_int32), ("state", C.c_int32), ("n_dist", C.c_int32),
+                ("dist", C.c_int32 * 16), ("t_gemm_s", C.c_double), ("t_comm_s", C.c_double),
+                ("out_bytes", C.c_double)]
+
+
 _P = C.c_void_p
 _I32P = C.POINTER(C.c_int32)
 _I64P = C.POINTER(C.c_int64)
@@ -73,6 +84,8 @@ _SIGS = {
     "tnc_plan_set_max_chunk": (C.c_int, [_P, C.c_int64]),
     "tnc_plan_set_graph": (C.c_int, [_P, C.c_int32]),
     "tnc_plan_autotune": (C.c_int, [_P]),
+    "tnc_plan_distribute": (C.c_int, [_P, C.c_int32, C.c_double, C.POINTER(DistHW), C.POINTER(DistStep),
+                                      C.c_int32, _I32P, _DP, _DP]),
     "tnc_plan_set_profile": (C.c_int, [_P, C.c_int32]),
     "tnc_plan_get_profile": (C.c_int, [_P, C.c_int32, _DP, _I64P]),
     "tnc_contract": (C.c_int, [_P, C.c_int64, C.c_int64, _DP]),
@@ -221,6 +234,22 @@ def tnc_plan_get_order(plan: int, tensor_id: int) -> list:
 
 def tnc_plan_set_max_chunk(plan: int, max_chunk: int) -> None:
     _check(lib().tnc_plan_set_max_chunk(plan, max_chunk))
+
+
+def tnc_plan_distribute(plan: int, n_gpus: int, large_bytes: float, hbm: float, flops: float, net: float,
+                        latency: float):
+    """Returns (steps, total_s, redistributed_bytes); steps is a list of
+    DistStep records."""
+    hw = DistHW(hbm, flops, net, latency)
+    n = C.c_int32()
+    tot = C.c_double()
+    moved = C.c_double()
+    _check(lib().tnc_plan_distribute(plan, n_gpus, large_bytes, C.byref(hw), None, 0, C.byref(n), C.byref(tot),
+                                     C.byref(moved)))
+    arr = (DistStep * max(n.value, 1))()
+    _check(lib().tnc_plan_distribute(plan, n_gpus, large_bytes, C.byref(hw), arr, n.value, C.byref(n),
+                                     C.byref(tot), C.byref(moved)))
+    return list(arr[:n.value]), tot.value, moved.value
 
 
 def tnc_plan_autotune(plan: int) -> None:
