@@ -191,7 +191,8 @@ def serving_leg(args):
 
 def bench_small(args):
     """Latency-bound and mixed workloads: the 12-qubit circuit amplitude
-    (153 tiny steps) eager vs hipGraph replay, all 4096 amplitudes with the
+    (153 tiny steps, 13 tree levels) step by step or level-grouped, eager or
+    replayed as a hipGraph; all 4096 amplitudes with the
     FP64 norm, and the closed 8x8 bond-4 grid in complex64, 3M and split-bf16."""
     import torch
 
@@ -216,12 +217,15 @@ def bench_small(args):
 
     net, path = configs.circuit12()
     tn = tnc.Network(ctx, net.labels, net.extents, net.open, net.c64().leaves)
-    for graph in (False, True):
-        p = tnc.Plan(tn, path.pairs)
-        tnc.tnc_plan_set_graph(p.handle, graph)
-        dt = timed(lambda: p.contract(), 200)
-        out[f"circuit12_amplitude_{'graph' if graph else 'eager'}_us"] = round(dt * 1e6, 1)
-        p.close()
+    for grouping in (False, True):
+        for graph in (False, True):
+            p = tnc.Plan(tn, path.pairs)
+            tnc.tnc_plan_set_grouping(p.handle, grouping)
+            tnc.tnc_plan_set_graph(p.handle, graph)
+            dt = timed(lambda: p.contract(), 200)
+            key = f"circuit12_amplitude_{'grouped' if grouping else 'stepwise'}_{'graph' if graph else 'eager'}_us"
+            out[key] = round(dt * 1e6, 1)
+            p.close()
     circ = configs.circuit12_circuit()
     netall = circuit_network(circ, open_qubits=range(12))
     pathall = greedy_path(netall)

@@ -174,10 +174,18 @@ tnc_status tnc_plan_set_max_chunk(tnc_plan plan, int64_t max_chunk);
 tnc_status tnc_plan_autotune(tnc_plan plan);
 /* 1 = capture each chunk's launches in a hipGraph and replay it. */
 tnc_status tnc_plan_set_graph(tnc_plan plan, int32_t enable);
+/* 1 (default) = run the contraction tree level by level (a step's level is
+ * one more than the highest of its operands'): the small VALU GEMMs of one
+ * level go out as one launch, the plain leaf gathers of one level as another.
+ * Results are bitwise those of step-by-step launches (0).  Changing it
+ * re-plans the chunks (the arena layout follows the execution order) and
+ * drops captured graphs; refused with TNC_E_BUSY while the context serves. */
+tnc_status tnc_plan_set_grouping(tnc_plan plan, int32_t enable);
 /* 1 = time every kernel with HIP events on the launch stream. */
 tnc_status tnc_plan_set_profile(tnc_plan plan, int32_t enable);
 /* Per-step accumulated kernel time (ms) and launch count since profiling was
- * enabled; step = -1 gives the leaf permutations, -2 the FP64 reductions. */
+ * enabled; step = -1 gives the leaf permutations and gathers, -2 the FP64
+ * reductions, -3 the grouped small-GEMM launches (one per tree level). */
 tnc_status tnc_plan_get_profile(tnc_plan plan, int32_t step, double* ms, int64_t* launches);
 
 /* ---------------------------------------------------------------- distribution plan

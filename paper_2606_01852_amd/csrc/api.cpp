@@ -430,13 +430,36 @@ tnc_status tnc_plan_set_graph(tnc_plan plan, int32_t enable) {
   TNC_CATCH
 }
 
+tnc_status tnc_plan_set_grouping(tnc_plan plan, int32_t enable) {
+  TNC_TRY
+  if (!plan) fail(TNC_E_ARG, "plan is NULL");
+  Plan& p = *plan->p;
+  Ctx& c = *p.net->ctx;
+  if (c.server) fail(TNC_E_BUSY, "the context is serving: plans cannot change");
+  const int g = enable ? 1 : 0;
+  if (g == p.grouping) return TNC_OK;
+  if (!c.host_only) {
+    set_device(c);
+    check_hip(hipStreamSynchronize(c.stream), "sync before re-planning");
+    drain_profile(p);
+  }
+  {
+    std::lock_guard<std::mutex> lk(p.graph_mu);
+    for (auto& e : p.graphs) (void)hipGraphExecDestroy(e.second);
+    p.graphs.clear();
+  }
+  p.grouping = g;
+  choose_chunking(p, c.arena_bytes);
+  TNC_CATCH
+}
+
 tnc_status tnc_plan_set_profile(tnc_plan plan, int32_t enable) {
   TNC_TRY
   if (!plan) fail(TNC_E_ARG, "plan is NULL");
   Plan& p = *plan->p;
   if (!p.net->ctx->host_only) drain_profile(p);
   p.profile = enable ? 1 : 0;
-  p.timers.assign(p.pairs.size() + 2, StepTimer{});
+  p.timers.assign(p.pairs.size() + 3, StepTimer{});
   TNC_CATCH
 }
 
@@ -450,8 +473,9 @@ tnc_status tnc_plan_get_profile(tnc_plan plan, int32_t step, double* ms, int64_t
   int idx = step;
   if (step == -1) idx = ns;
   if (step == -2) idx = ns + 1;
-  if (idx < 0 || idx >= ns + 2) fail(TNC_E_ARG, "step out of range");
-  if (p.timers.size() < static_cast<size_t>(ns + 2)) p.timers.resize(ns + 2);
+  if (step == -3) idx = ns + 2;
+  if (idx < 0 || idx >= ns + 3) fail(TNC_E_ARG, "step out of range");
+  if (p.timers.size() < static_cast<size_t>(ns + 3)) p.timers.resize(ns + 3);
   *ms = p.timers[idx].ms;
   *launches = p.timers[idx].launches;
   TNC_CATCH

@@ -136,8 +136,21 @@ struct StepPlan {
   std::vector<int> preps;                     // leaf preps launched before the GEMM
 };
 
+// One level of the contraction tree: the steps whose operands are all
+// produced at lower levels.  Small steps and plain leaf gathers of a level
+// run as one grouped launch each; MFMA/long-K steps and tiled permutes run
+// alone.
+struct LevelPlan {
+  std::vector<int> group_leaves, single_leaves;
+  std::vector<int> group_steps, single_steps;
+  int64_t off_gemm = -1, off_gemm_prefix = -1, gemm_total = 0;
+  int64_t off_gather = -1, off_gather_prefix = -1, gather_total = 0;
+};
+
 struct ChunkPlan {
   int j = 0;                       // number of trailing sliced labels batched
+  bool grouped = false;            // execute level by level
+  std::vector<LevelPlan> levels;
   int64_t hs = 1;                  // slices per chunk
   std::vector<int> batch;          // canonical batch labels
   std::vector<std::vector<int>> order;   // per tensor id
@@ -190,6 +203,7 @@ struct Plan {
   tnc_prec prec = TNC_PREC_C64;
   tnc_cgemm form = TNC_GEMM_4M;
   int64_t max_chunk_user = -1;
+  int grouping = 1;                   // level-grouped launches
   int graph = 0;
   int profile = 0;
   int j_max = 0;
@@ -223,7 +237,7 @@ void load_tune_cache(Ctx& c);
 void assign_variants(const Plan& plan, ChunkPlan& cp, bool tune);
 
 // executor.cpp
-void materialize(ChunkPlan& cp, hipStream_t stream);
+void materialize(const Net& net, ChunkPlan& cp, hipStream_t stream);
 struct RunArgs {
   int64_t first = 0, count = 1;
   char* arena = nullptr;        // workspace (peak + extras)

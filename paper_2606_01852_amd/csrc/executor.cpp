@@ -25,7 +25,7 @@ int64_t put(std::vector<uint8_t>& blob, const std::vector<T>& v) {
 
 }  // namespace
 
-void materialize(ChunkPlan& cp, hipStream_t stream) {
+void materialize(const Net& net, ChunkPlan& cp, hipStream_t stream) {
   if (cp.materialized) return;
   std::vector<uint8_t>& blob = cp.host_blob;
   blob.clear();
@@ -44,19 +44,83 @@ void materialize(ChunkPlan& cp, hipStream_t stream) {
     sp.off_offM = put(blob, sp.offM);
     sp.off_offN = put(blob, sp.offN);
   }
-  if (!blob.empty()) {
-    cp.blob.alloc(blob.size());
-    // upload on the caller's stream and wait for it alone: other requests
-    // keep running, and nobody sees the tables before they are complete
-    check_hip(hipMemcpyAsync(cp.blob.ptr, blob.data(), blob.size(), hipMemcpyHostToDevice, stream),
-              "upload plan tables");
-    check_hip(hipStreamSynchronize(stream), "upload plan tables");
+  // grouped-launch tables reserve their space now and are filled once the
+  // blob's device address (for the offset tables they point to) is known
+  for (LevelPlan& L : cp.levels) {
+    if (!L.group_steps.empty()) {
+      L.off_gemm = put(blob, std::vector<GroupGemm>(L.group_steps.size()));
+      L.off_gemm_prefix = put(blob, std::vector<int64_t>(L.group_steps.size()));
+    }
+    if (!L.group_leaves.empty()) {
+      L.off_gather = put(blob, std::vector<GroupGather>(L.group_leaves.size()));
+      L.off_gather_prefix = put(blob, std::vector<int64_t>(L.group_leaves.size()));
+    }
   }
+  if (!blob.empty()) cp.blob.alloc(blob.size());
   char* base = static_cast<char*>(cp.blob.ptr);
   for (StepPlan& sp : cp.steps) {
     if (sp.natural) continue;
     sp.desc.offM = reinterpret_cast<const int64_t*>(base + sp.off_offM);
     sp.desc.offN = reinterpret_cast<const int64_t*>(base + sp.off_offN);
+  }
+  const int n = net.n_tensors;
+  for (LevelPlan& L : cp.levels) {
+    if (!L.group_steps.empty()) {
+      GroupGemm* tab = reinterpret_cast<GroupGemm*>(blob.data() + L.off_gemm);
+      int64_t* pre = reinterpret_cast<int64_t*>(blob.data() + L.off_gemm_prefix);
+      int64_t acc = 0;
+      for (size_t q = 0; q < L.group_steps.size(); ++q) {
+        const StepPlan& sp = cp.steps[L.group_steps[q]];
+        GroupGemm g;
+        std::memset(&g, 0, sizeof(g));
+        g.d = sp.desc;
+        auto operand = [&](int id, int32_t& rel) -> void* {
+          if (id < n && cp.leaf[id].direct) {
+            rel = 0;
+            return net.leaf[id].ptr;
+          }
+          rel = 1;
+          return reinterpret_cast<void*>(static_cast<intptr_t>(cp.buf_off[cp.tensor_buf[id]]));
+        };
+        g.d.A = static_cast<const float2*>(operand(sp.A, g.rel_a));
+        g.d.B = static_cast<const float2*>(operand(sp.B, g.rel_b));
+        g.d.C = static_cast<float2*>(operand(sp.C, g.rel_c));
+        tab[q] = g;
+        pre[q] = acc;
+        acc += sp.h * sp.m * sp.n;
+      }
+      L.gemm_total = acc;
+    }
+    if (!L.group_leaves.empty()) {
+      GroupGather* tab = reinterpret_cast<GroupGather*>(blob.data() + L.off_gather);
+      int64_t* pre = reinterpret_cast<int64_t*>(blob.data() + L.off_gather_prefix);
+      int64_t acc = 0;
+      for (size_t q = 0; q < L.group_leaves.size(); ++q) {
+        const int t = L.group_leaves[q];
+        const LeafPrep& lp = cp.leaf[t];
+        GroupGather g;
+        std::memset(&g, 0, sizeof(g));
+        g.in = static_cast<const float2*>(net.leaf[t].ptr);
+        g.out_off = cp.buf_off[cp.tensor_buf[t]];
+        g.rank = lp.perm.plain.rank;
+        g.base_slot = lp.base_slot;
+        for (int r = 0; r < g.rank; ++r) {
+          g.ext[r] = lp.perm.plain.ext[r];
+          g.in_stride[r] = lp.perm.plain.in_stride[r];
+        }
+        tab[q] = g;
+        pre[q] = acc;
+        acc += cp.numel[t];
+      }
+      L.gather_total = acc;
+    }
+  }
+  if (!blob.empty()) {
+    // upload on the caller's stream and wait for it alone: other requests
+    // keep running, and nobody sees the tables before they are complete
+    check_hip(hipMemcpyAsync(cp.blob.ptr, blob.data(), blob.size(), hipMemcpyHostToDevice, stream),
+              "upload plan tables");
+    check_hip(hipStreamSynchronize(stream), "upload plan tables");
   }
   cp.materialized = true;
 }
@@ -79,7 +143,7 @@ namespace {
 ChunkPlan& ready(Plan& plan, int j, hipStream_t stream) {
   std::lock_guard<std::mutex> g(plan.mu);
   if (!plan.chunks[j]) plan.chunks[j] = build_chunk(plan, j);
-  materialize(*plan.chunks[j], stream);
+  materialize(*plan.net, *plan.chunks[j], stream);
   return *plan.chunks[j];
 }
 
@@ -114,7 +178,7 @@ void enqueue_chunk(Plan& plan, ChunkPlan& cp, const RunArgs& a, const int64_t* b
   Net& net = *plan.net;
   const int n = net.n_tensors;
   const int ns = static_cast<int>(plan.pairs.size());
-  const int t_prep = ns, t_red = ns + 1;
+  const int t_prep = ns, t_red = ns + 1, t_group = ns + 2;
   const char* blob = static_cast<const char*>(cp.blob.ptr);
   auto ptr = [&](int id) -> float2* {
     if (id < n && cp.leaf[id].direct) return static_cast<float2*>(net.leaf[id].ptr);
@@ -156,15 +220,40 @@ void enqueue_chunk(Plan& plan, ChunkPlan& cp, const RunArgs& a, const int64_t* b
   if (ns == 0 && !cp.leaf[0].direct) prep(0);
   const Form form = plan.form == TNC_GEMM_3M ? Form::M3 : Form::M4;
   const Prec prec = plan.prec == TNC_PREC_BF16X3 ? Prec::BF16X3 : Prec::C64;
-  for (int s = 0; s < ns; ++s) {
+  auto step = [&](int s) {
     StepPlan& sp = cp.steps[s];
-    for (int t : sp.preps) prep(t);
     GemmDesc d = sp.desc;
     d.A = ptr(sp.A);
     d.B = ptr(sp.B);
     d.C = ptr(sp.C);
     const int variant = net.ctx->gemm_variant >= 0 ? net.ctx->gemm_variant : sp.variant;
     L.run(s, stream, [&] { return launch_gemm(d, sp.kind, variant, form, prec, stream); });
+  };
+  if (cp.grouped) {
+    // level by level: the level's plain leaf gathers in one launch, its small
+    // GEMMs in another, everything else one launch each
+    for (const LevelPlan& lv : cp.levels) {
+      if (!lv.group_leaves.empty())
+        L.run(t_prep, stream, [&] {
+          return launch_group_gather(reinterpret_cast<const GroupGather*>(blob + lv.off_gather),
+                                     reinterpret_cast<const int64_t*>(blob + lv.off_gather_prefix),
+                                     static_cast<int>(lv.group_leaves.size()), lv.gather_total, a.arena, bases,
+                                     stream);
+        });
+      for (int t : lv.single_leaves) prep(t);
+      if (!lv.group_steps.empty())
+        L.run(t_group, stream, [&] {
+          return launch_group_gemm(reinterpret_cast<const GroupGemm*>(blob + lv.off_gemm),
+                                   reinterpret_cast<const int64_t*>(blob + lv.off_gemm_prefix),
+                                   static_cast<int>(lv.group_steps.size()), lv.gemm_total, a.arena, prec, stream);
+        });
+      for (int s : lv.single_steps) step(s);
+    }
+  } else {
+    for (int s = 0; s < ns; ++s) {
+      for (int t : cp.steps[s].preps) prep(t);
+      step(s);
+    }
   }
   if (!a.direct_out) {
     const float2* root = ptr(cp.root_id);
@@ -269,7 +358,7 @@ void run_plan(Plan& plan, const RunArgs& a) {
   }
   if (!ev.empty()) {
     std::lock_guard<std::mutex> g(plan.mu);
-    if (plan.timers.size() < static_cast<size_t>(ns + 2)) plan.timers.resize(ns + 2);
+    if (plan.timers.size() < static_cast<size_t>(ns + 3)) plan.timers.resize(ns + 3);
     for (auto& e : ev) plan.pending.push_back(e);
   }
 }

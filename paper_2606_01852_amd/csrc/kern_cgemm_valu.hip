@@ -51,7 +51,10 @@ __global__ __launch_bounds__(256) void cgemm_small(GemmDesc d) {
       }
     }
     const int64_t c = b * mn + (d.offM ? d.offM[i] + d.offN[j] : r);
-    d.C[c] = make_float2(cr + crx, ci + cix);
+    if constexpr (SPLIT)
+      d.C[c] = make_float2(cr + crx, ci + cix);
+    else
+      d.C[c] = make_float2(cr, ci);
   }
 }
 

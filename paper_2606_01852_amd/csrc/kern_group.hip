@@ -1,0 +1,128 @@
+// Grouped launches: every small step (or leaf gather) of one level of the
+// contraction tree in a single kernel.
+//
+// Steps of one level depend only on lower levels, so they can run together.
+// Circuit and grid networks have hundreds of tiny steps but trees only
+// 10-20 levels deep; one launch per level instead of per step removes most
+// of the launch chain that otherwise bounds their latency.  Each thread
+// finds its step by binary search over the level's prefix sums of work items
+// and then does exactly what the one-step kernel does for that element, so
+// results are bitwise those of the per-step launches.
+#include "gemm_common.hpp"
+
+namespace tnc {
+
+namespace {
+
+__device__ __forceinline__ int find_item(const int64_t* prefix, int n, int64_t gt) {
+  int lo = 0, hi = n - 1;  // largest i with prefix[i] <= gt
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (prefix[mid] <= gt)
+      lo = mid;
+    else
+      hi = mid - 1;
+  }
+  return lo;
+}
+
+template <typename T>
+__device__ __forceinline__ T* reloc(const void* p, int flag, char* arena) {
+  return flag ? reinterpret_cast<T*>(arena + reinterpret_cast<intptr_t>(p)) : (T*)p;
+}
+
+template <bool SPLIT>
+__global__ __launch_bounds__(256) void group_small_gemm(const GroupGemm* __restrict__ g, const int64_t* __restrict__ prefix,
+                                                        int n, int64_t total, char* arena) {
+  for (int64_t gt = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x; gt < total;
+       gt += static_cast<int64_t>(gridDim.x) * blockDim.x) {
+    const int s = find_item(prefix, n, gt);
+    const GroupGemm& e = g[s];
+    const GemmDesc& d = e.d;
+    const int64_t idx = gt - prefix[s];
+    const int64_t mn = d.m * d.n;
+    const int64_t b = idx / mn;
+    const int64_t r = idx - b * mn;
+    const int64_t i = r / d.n;
+    const int64_t j = r - i * d.n;
+    int64_t oa, ob;
+    batch_offsets(d, b, oa, ob);
+    const float2* A = reloc<const float2>(d.A, e.rel_a, arena) + oa + i * d.k;
+    const float2* B = reloc<const float2>(d.B, e.rel_b, arena) + ob + j * d.k;
+    float2* C = reloc<float2>(d.C, e.rel_c, arena);
+    float cr = 0.f, ci = 0.f, crx = 0.f, cix = 0.f;
+    for (int64_t l = 0; l < d.k; ++l) {
+      const float2 x = A[l];
+      const float2 y = B[l];
+      if constexpr (SPLIT) {
+        float h1, x1, h2, x2, h3, x3, h4, x4;
+        split_mul(x.x, y.x, h1, x1);
+        split_mul(x.y, y.y, h2, x2);
+        split_mul(x.x, y.y, h3, x3);
+        split_mul(x.y, y.x, h4, x4);
+        cr += h1;
+        cr -= h2;
+        ci += h3;
+        ci += h4;
+        crx += x1 - x2;
+        cix += x3 + x4;
+      } else {
+        cr = fmaf(x.x, y.x, cr);
+        cr = fmaf(-x.y, y.y, cr);
+        ci = fmaf(x.x, y.y, ci);
+        ci = fmaf(x.y, y.x, ci);
+      }
+    }
+    const int64_t c = b * mn + (d.offM ? d.offM[i] + d.offN[j] : r);
+    if constexpr (SPLIT)
+      C[c] = make_float2(cr + crx, ci + cix);
+    else
+      C[c] = make_float2(cr, ci);
+  }
+}
+
+__global__ __launch_bounds__(256) void group_gather(const GroupGather* __restrict__ g, const int64_t* __restrict__ prefix,
+                                                    int n, int64_t total, char* arena, const int64_t* bases) {
+  for (int64_t gt = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x; gt < total;
+       gt += static_cast<int64_t>(gridDim.x) * blockDim.x) {
+    const int s = find_item(prefix, n, gt);
+    const GroupGather& e = g[s];
+    int64_t rest = gt - prefix[s];
+    int64_t off = e.base_slot >= 0 ? bases[e.base_slot] : 0;
+    for (int j = e.rank - 1; j >= 0; --j) {
+      const int64_t x = e.ext[j];
+      const int64_t q = rest / x;
+      off += (rest - q * x) * e.in_stride[j];
+      rest = q;
+    }
+    float2* out = reinterpret_cast<float2*>(arena + e.out_off);
+    out[gt - prefix[s]] = e.in[off];
+  }
+}
+
+int64_t grid_for(int64_t total) {
+  int64_t g = (total + 255) / 256;
+  if (g < 1) g = 1;
+  return g > 1048576 ? 1048576 : g;
+}
+
+}  // namespace
+
+hipError_t launch_group_gemm(const GroupGemm* table, const int64_t* prefix, int n, int64_t total, char* arena,
+                             Prec prec, hipStream_t s) {
+  if (n <= 0 || total <= 0) return hipSuccess;
+  if (prec == Prec::BF16X3)
+    hipLaunchKernelGGL(group_small_gemm<true>, dim3(grid_for(total)), dim3(256), 0, s, table, prefix, n, total, arena);
+  else
+    hipLaunchKernelGGL(group_small_gemm<false>, dim3(grid_for(total)), dim3(256), 0, s, table, prefix, n, total, arena);
+  return hipGetLastError();
+}
+
+hipError_t launch_group_gather(const GroupGather* table, const int64_t* prefix, int n, int64_t total, char* arena,
+                               const int64_t* bases, hipStream_t s) {
+  if (n <= 0 || total <= 0) return hipSuccess;
+  hipLaunchKernelGGL(group_gather, dim3(grid_for(total)), dim3(256), 0, s, table, prefix, n, total, arena, bases);
+  return hipGetLastError();
+}
+
+}  // namespace tnc

@@ -86,6 +86,28 @@ constexpr int kGemmVariants = 7;
 void gemm_variant_tile(int variant, int* bm, int* bnc);
 hipError_t launch_gemm(const GemmDesc& d, GemmKernel kind, int variant, Form form, Prec prec, hipStream_t s);
 hipError_t launch_gemm_valu(const GemmDesc& d, GemmKernel kind, Prec prec, hipStream_t s);
+// Grouped launches (one per tree level).  Operand pointers flagged rel_*
+// hold arena offsets, relocated against the arena base at run time, so the
+// tables stay valid for any arena.
+struct GroupGemm {
+  GemmDesc d;
+  int32_t rel_a, rel_b, rel_c, pad;
+};
+constexpr int kGroupRank = 32;
+struct GroupGather {
+  const float2* in;     // resident leaf
+  int64_t out_off;      // arena offset of the gathered copy
+  int32_t rank;
+  int32_t base_slot;    // slot of the chunk's base offset (-1: none)
+  int64_t ext[kGroupRank];
+  int64_t in_stride[kGroupRank];
+};
+// prefix[i] = first work item of entry i (work items: output elements).
+hipError_t launch_group_gemm(const GroupGemm* table, const int64_t* prefix, int n, int64_t total, char* arena,
+                             Prec prec, hipStream_t s);
+hipError_t launch_group_gather(const GroupGather* table, const int64_t* prefix, int n, int64_t total, char* arena,
+                               const int64_t* bases, hipStream_t s);
+
 hipError_t launch_permute(const PermuteDesc& d, hipStream_t s);
 hipError_t launch_gather(const GatherDesc& d, hipStream_t s);
 // acc[i] += sum_s root[s * R + i] (complex64 in, complex128 out), pairwise

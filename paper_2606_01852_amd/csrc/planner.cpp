@@ -535,7 +535,34 @@ std::unique_ptr<ChunkPlan> build_chunk(const Plan& plan, int j) {
                         static_cast<double>(sp.h) * sp.m * sp.n);
   }
 
-  // arena buffers: live ranges in step time, first fit by decreasing size
+  // execution order: step by step, or level by level of the tree (a step's
+  // level is one more than its operands'; all steps of a level are
+  // independent and run together)
+  std::vector<int> lvl(n_ids, 0);
+  for (int s = 0; s < ns; ++s) lvl[n + s] = 1 + std::max(lvl[plan.pairs[s][0]], lvl[plan.pairs[s][1]]);
+  cp->grouped = plan.grouping != 0 && ns > 0;
+  auto when = [&](int s) { return cp->grouped ? lvl[n + s] : s; };
+  const int t_end = ns == 0 ? 0 : (cp->grouped ? lvl[root] + 1 : ns);
+  if (cp->grouped) {
+    cp->levels.assign(lvl[root] + 1, LevelPlan{});
+    for (int s = 0; s < ns; ++s) {
+      LevelPlan& L = cp->levels[lvl[n + s]];
+      const StepPlan& sp = cp->steps[s];
+      if (sp.kind == GemmKernel::SMALL && n + s != root)
+        L.group_steps.push_back(s);
+      else
+        L.single_steps.push_back(s);
+      for (int t : sp.preps) {
+        const LeafPrep& lp = cp->leaf[t];
+        if (!lp.perm.tiled && lp.perm.plain.rank <= kGroupRank)
+          L.group_leaves.push_back(t);
+        else
+          L.single_leaves.push_back(t);
+      }
+    }
+  }
+
+  // arena buffers: live ranges in execution time, first fit by decreasing size
   struct Iv {
     int64_t bytes;
     int t0, t1;
@@ -544,12 +571,12 @@ std::unique_ptr<ChunkPlan> build_chunk(const Plan& plan, int j) {
   std::vector<Iv> ivs;
   for (int t = 0; t < n; ++t) {
     if (cp->leaf[t].direct) continue;
-    const int tt = cp->leaf[t].step;
-    ivs.push_back({align_up(cp->numel[t] * 8), tt, t == root ? ns : tt, t});
+    const int tt = ns > 0 ? when(cp->leaf[t].step) : 0;
+    ivs.push_back({align_up(cp->numel[t] * 8), tt, t == root ? t_end : tt, t});
   }
   for (int s = 0; s < ns; ++s) {
     const int c = n + s;
-    ivs.push_back({align_up(cp->numel[c] * 8), s, consumer[c], c});
+    ivs.push_back({align_up(cp->numel[c] * 8), when(s), consumer[c] < ns ? when(consumer[c]) : t_end, c});
   }
   std::vector<int> idx(ivs.size());
   std::iota(idx.begin(), idx.end(), 0);

@@ -83,6 +83,7 @@ _SIGS = {
     "tnc_plan_get_order": (C.c_int, [_P, C.c_int32, _I32P, C.c_int32, _I32P]),
     "tnc_plan_set_max_chunk": (C.c_int, [_P, C.c_int64]),
     "tnc_plan_set_graph": (C.c_int, [_P, C.c_int32]),
+    "tnc_plan_set_grouping": (C.c_int, [_P, C.c_int32]),
     "tnc_plan_autotune": (C.c_int, [_P]),
     "tnc_plan_distribute": (C.c_int, [_P, C.c_int32, C.c_double, C.POINTER(DistHW), C.POINTER(DistStep),
                                       C.c_int32, _I32P, _DP, _DP]),
@@ -258,6 +259,10 @@ def tnc_plan_autotune(plan: int) -> None:
 
 def tnc_plan_set_graph(plan: int, enable: bool) -> None:
     _check(lib().tnc_plan_set_graph(plan, int(enable)))
+
+
+def tnc_plan_set_grouping(plan: int, enable: bool) -> None:
+    _check(lib().tnc_plan_set_grouping(plan, int(enable)))
 
 
 def tnc_plan_set_profile(plan: int, enable: bool) -> None:

@@ -281,3 +281,63 @@ def test_graph_replay_matches_eager(ctx):
         tnc.tnc_contract_async(pg.handle, 0, 1, og.data_ptr(), tnc.OUT_C64)
         torch.cuda.synchronize()
         assert torch.equal(torch.view_as_real(oe), torch.view_as_real(og))
+
+
+def _bits(x):
+    return np.asarray(x).view(np.uint64)
+
+
+@pytest.mark.parametrize("case", ["circuit12_sliced", "circuit12_all", "grid8_bf16x3", "circuit16_wide"])
+def test_level_grouping_is_bitwise_step_order(ctx, case):
+    """Level-grouped launches (one launch per tree level for the small GEMMs
+    and plain leaf gathers) give bitwise the step-by-step result, eagerly and
+    replayed from captured graphs, also on chunks whose leaves carry fixed
+    sliced labels (per-chunk base offsets)."""
+    prec = tnc.PREC_C64
+    max_chunk = None
+    if case == "circuit12_sliced":
+        net, path = configs.circuit12()
+        sl = greedy_slice(net, path.pairs, n_sliced=4)
+        path = Path(path.pairs, sl)
+        max_chunk = 4
+    elif case == "circuit12_all":
+        circ = configs.circuit12_circuit()
+        net = circuit_network(circ, open_qubits=range(12))
+        path = greedy_path(net)
+    elif case == "grid8_bf16x3":
+        net, _ = prescaled_grid(8, 8, 4, seed=1002)
+        path = greedy_path(net)
+        prec = tnc.PREC_BF16X3
+    else:
+        circ = random_circuit(4, 4, 10, seed=77)
+        net = circuit_network(circ, open_qubits=range(4))
+        path = greedy_path(net)
+    print("grouping", case, flush=True)
+    tn = tnc.Network(ctx, net.labels, net.extents, net.open, net.c64().leaves)
+    plans = {}
+    for grouping in (0, 1):
+        for graph in (0, 1):
+            p = tnc.Plan(tn, path.pairs, path.sliced, prec)
+            tnc.tnc_plan_set_grouping(p.handle, grouping)
+            if max_chunk:
+                tnc.tnc_plan_set_max_chunk(p.handle, max_chunk)
+            tnc.tnc_plan_set_graph(p.handle, graph)
+            plans[grouping, graph] = p
+    ref = plans[0, 0].contract()
+    for key, p in plans.items():
+        for rep in range(2):
+            got = p.contract()
+            assert np.array_equal(_bits(got), _bits(ref)), (key, rep)
+    # the grouped plan really groups: one small-GEMM launch per level at most
+    g = plans[1, 0]
+    tnc.tnc_plan_set_profile(g.handle, True)
+    g.contract()
+    ms, launches = tnc.tnc_plan_get_profile(g.handle, -3)
+    n_small = sum(1 for s in range(g.info.n_steps) if g.step(s).kernel == 1)
+    print(f"{case}: {n_small} small steps in {launches} grouped launches", flush=True)
+    if n_small > 1:
+        assert 1 <= launches < n_small
+    ref_or = complex(oc.contract(net, path)) if not net.open else None
+    if ref_or is not None and prec == tnc.PREC_C64:
+        z = complex(ref[0])
+        assert abs(z - ref_or) <= 1e-5 * abs(ref_or)

@@ -181,30 +181,52 @@ def test_errors_are_reported_not_raised_across_the_abi(hctx):
     assert tnc.lib().tnc_last_error().decode()
 
 
-def test_memory_plan_and_chunking(hctx):
+@pytest.mark.parametrize("grouping", [1, 0])
+def test_memory_plan_and_chunking(hctx, grouping):
     net, path = configs.circuit40(n_sliced=16)
     tn = tnc.Network(tnc.Context(-1, arena_bytes=8 << 30), net.labels, net.extents, net.open)
     plan = tnc.Plan(tn, path.pairs, path.sliced)
-    info = plan.info
+    tnc.tnc_plan_set_grouping(plan.handle, grouping)
+    info = tnc.tnc_plan_get_info(plan.handle)
     assert info.n_slices == 2 ** 16
     assert info.max_intermediate <= 2 ** 19
     # first-fit placement stays close to the live-bytes lower bound: at each
-    # step the tensors alive (intermediates not yet consumed, the step's
-    # operands and result) must all be resident
+    # point of the execution order (a step, or a level of the tree when
+    # levels run as groups) the intermediates produced and not yet consumed
+    # must all be resident
     from workloads.paths import path_tensors
     tens, _ = path_tensors(net, path.pairs, path.sliced)
     size = [int(np.prod([net.extents[l] for l in t])) * 8 for t in tens]
     n = net.n_leaves
+    ns = len(path.pairs)
     consumer = {}
     for s_, (a, b) in enumerate(path.pairs):
         consumer[int(a)] = consumer[int(b)] = s_
-    ns = len(path.pairs)
+    lvl = [0] * (n + ns)
+    for s_, (a, b) in enumerate(path.pairs):
+        lvl[n + s_] = 1 + max(lvl[a], lvl[b])
+    when = (lambda s_: lvl[n + s_]) if grouping else (lambda s_: s_)
+    end = when(ns - 1) + 1
     lb = 0
-    for s_ in range(ns):
-        live = sum(size[n + q] for q in range(ns) if q <= s_ <= consumer.get(n + q, ns))
+    for t in range(end + 1):
+        live = sum(size[n + q] for q in range(ns)
+                   if when(q) <= t <= (when(consumer[n + q]) if n + q in consumer else end))
         lb = max(lb, live)
     assert lb <= info.peak_bytes <= 1.5 * lb + (1 << 20)
     assert info.max_chunk >= 64 and info.chunk_peak_bytes <= 8 << 30
+
+
+def test_grouping_keeps_the_plan_shape(hctx):
+    net, path = configs.circuit12()
+    tn = tnc.Network(hctx, net.labels, net.extents, net.open)
+    plan = tnc.Plan(tn, path.pairs)
+    steps = [plan.step(s) for s in range(plan.info.n_steps)]
+    tnc.tnc_plan_set_grouping(plan.handle, 0)
+    for s, st in enumerate(steps):
+        other = plan.step(s)
+        assert (other.m, other.n, other.k, other.h, other.kernel) == (st.m, st.n, st.k, st.h, st.kernel)
+    with pytest.raises(tnc.TncError):
+        tnc.tnc_plan_set_grouping(0, 1)
 
 
 def test_serving_needs_a_device_arena(hctx):
