@@ -158,8 +158,14 @@ typedef struct {
   int32_t kernel;                /* 0 = MFMA tiles, 1 = small-shape VALU kernel,
                                     2 = long-K dot kernel (k large, m*n tiny)  */
   int32_t variant;               /* MFMA workgroup shape (autotuned)           */
+  int32_t swapped;               /* 1 = the GEMM runs transposed (B supplies
+                                    the rows) because that fills MFMA tiles   */
+  int32_t split;                 /* K cut into this many parts (split-K)       */
 } tnc_step_info;
 tnc_status tnc_plan_get_step(tnc_plan plan, int32_t step, tnc_step_info* out);
+/* The same view for the batch of max_chunk slices the executor runs (h then
+ * includes the batched slice labels the step's operands hold). */
+tnc_status tnc_plan_get_batch_step(tnc_plan plan, int32_t step, tnc_step_info* out);
 /* Mode order (labels) tensor `id` is stored in when the plan runs one slice:
  * the target order of the Sec. IV-A backward pass.  Writes min(cap, rank)
  * labels, sets *rank. */

@@ -334,12 +334,9 @@ tnc_status tnc_plan_get_info(tnc_plan plan, tnc_plan_info* out) {
   TNC_CATCH
 }
 
-tnc_status tnc_plan_get_step(tnc_plan plan, int32_t step, tnc_step_info* out) {
-  TNC_TRY
-  if (!plan || !out) fail(TNC_E_ARG, "plan/out is NULL");
-  const ChunkPlan& c0 = *plan->p->chunks[0];
-  if (step < 0 || step >= static_cast<int32_t>(c0.steps.size())) fail(TNC_E_ARG, "step out of range");
-  const StepPlan& s = c0.steps[step];
+static void step_info(const ChunkPlan& c, int32_t step, tnc_step_info* out) {
+  if (step < 0 || step >= static_cast<int32_t>(c.steps.size())) fail(TNC_E_ARG, "step out of range");
+  const StepPlan& s = c.steps[step];
   tnc_step_info i{};
   i.A = s.A;
   i.B = s.B;
@@ -355,7 +352,23 @@ tnc_status tnc_plan_get_step(tnc_plan plan, int32_t step, tnc_step_info* out) {
   i.natural = s.natural ? 1 : 0;
   i.kernel = static_cast<int32_t>(s.kind);
   i.variant = s.variant;
+  i.swapped = s.swap ? 1 : 0;
+  i.split = s.split;
   *out = i;
+}
+
+tnc_status tnc_plan_get_step(tnc_plan plan, int32_t step, tnc_step_info* out) {
+  TNC_TRY
+  if (!plan || !out) fail(TNC_E_ARG, "plan/out is NULL");
+  step_info(*plan->p->chunks[0], step, out);
+  TNC_CATCH
+}
+
+tnc_status tnc_plan_get_batch_step(tnc_plan plan, int32_t step, tnc_step_info* out) {
+  TNC_TRY
+  if (!plan || !out) fail(TNC_E_ARG, "plan/out is NULL");
+  Plan& p = *plan->p;
+  step_info(p.chunk(p.j_max), step, out);
   TNC_CATCH
 }
 

@@ -167,8 +167,9 @@ void assign_variants(const Plan& plan, ChunkPlan& cp, bool tune) {
   Ctx& c = *plan.net->ctx;
   for (StepPlan& sp : cp.steps) {
     if (sp.kind != GemmKernel::MFMA) continue;
-    const TuneKey key{static_cast<int>(plan.prec), static_cast<int>(plan.form), sp.natural ? 0 : 1,
-                      sp.h, sp.m, sp.n, sp.k};
+    const GemmDesc& d = sp.desc;
+    const bool perm = !sp.offM.empty() && sp.split == 1;
+    const TuneKey key{static_cast<int>(plan.prec), static_cast<int>(plan.form), perm ? 1 : 0, d.h, d.m, d.n, d.k};
     bool cached = false;
     {
       std::lock_guard<std::mutex> g(c.tune_mu);
@@ -180,9 +181,9 @@ void assign_variants(const Plan& plan, ChunkPlan& cp, bool tune) {
     }
     if (cached) continue;
     if (tune && !c.host_only)
-      sp.variant = tune_shape(c, key, sp.k, !sp.natural);
+      sp.variant = tune_shape(c, key, d.k, perm);
     else
-      sp.variant = default_variant(plan.prec, plan.form, sp.h, sp.m, sp.n);
+      sp.variant = default_variant(plan.prec, plan.form, d.h, d.m, d.n);
   }
 }
 

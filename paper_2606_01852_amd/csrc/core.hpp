@@ -128,11 +128,22 @@ struct StepPlan {
   std::vector<int> H, M, N, K;
   int64_t h = 1, m = 1, n = 1, k = 1, hA = 1, hB = 1;
   bool natural = true;
+  // launch: the GEMM may run transposed (B as the row operand) when that
+  // fills MFMA tiles better, and with K split into `split` parts whose
+  // partial products go to an arena scratch buffer and are summed by the
+  // split-K epilogue
+  bool swap = false;
+  int la = -1, lb = -1;                       // launch operands (row, column)
+  int64_t lm = 1, ln = 1;                     // launch rows / columns
+  int split = 1;
+  int scratch_buf = -1;                       // arena buffer of the partials
   GemmKernel kind = GemmKernel::SMALL;
   int variant = 0;                            // MFMA tile variant (autotuned)
-  GemmDesc desc{};                            // pointers filled at run time
+  GemmDesc desc{};                            // launch descriptor; pointers filled at run time
   int64_t off_offM = -1, off_offN = -1;       // in the device blob
-  std::vector<int64_t> offM, offN;            // host copies (permuted store)
+  std::vector<int64_t> offM, offN;            // store tables in launch orientation (empty: natural)
+  const int64_t* dev_offM = nullptr;          // device copies of the store tables
+  const int64_t* dev_offN = nullptr;
   std::vector<int> preps;                     // leaf preps launched before the GEMM
 };
 

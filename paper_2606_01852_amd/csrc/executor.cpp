@@ -40,7 +40,7 @@ void materialize(const Net& net, ChunkPlan& cp, hipStream_t stream) {
     p.off_hi = put(blob, p.hi_tab);
   }
   for (StepPlan& sp : cp.steps) {
-    if (sp.natural) continue;
+    if (sp.offM.empty()) continue;
     sp.off_offM = put(blob, sp.offM);
     sp.off_offN = put(blob, sp.offN);
   }
@@ -59,9 +59,13 @@ void materialize(const Net& net, ChunkPlan& cp, hipStream_t stream) {
   if (!blob.empty()) cp.blob.alloc(blob.size());
   char* base = static_cast<char*>(cp.blob.ptr);
   for (StepPlan& sp : cp.steps) {
-    if (sp.natural) continue;
-    sp.desc.offM = reinterpret_cast<const int64_t*>(base + sp.off_offM);
-    sp.desc.offN = reinterpret_cast<const int64_t*>(base + sp.off_offN);
+    if (sp.offM.empty()) continue;
+    sp.dev_offM = reinterpret_cast<const int64_t*>(base + sp.off_offM);
+    sp.dev_offN = reinterpret_cast<const int64_t*>(base + sp.off_offN);
+    if (sp.split == 1) {  // the GEMM stores through them; else the split-K epilogue does
+      sp.desc.offM = sp.dev_offM;
+      sp.desc.offN = sp.dev_offN;
+    }
   }
   const int n = net.n_tensors;
   for (LevelPlan& L : cp.levels) {
@@ -82,12 +86,12 @@ void materialize(const Net& net, ChunkPlan& cp, hipStream_t stream) {
           rel = 1;
           return reinterpret_cast<void*>(static_cast<intptr_t>(cp.buf_off[cp.tensor_buf[id]]));
         };
-        g.d.A = static_cast<const float2*>(operand(sp.A, g.rel_a));
-        g.d.B = static_cast<const float2*>(operand(sp.B, g.rel_b));
+        g.d.A = static_cast<const float2*>(operand(sp.la, g.rel_a));
+        g.d.B = static_cast<const float2*>(operand(sp.lb, g.rel_b));
         g.d.C = static_cast<float2*>(operand(sp.C, g.rel_c));
         tab[q] = g;
         pre[q] = acc;
-        acc += sp.h * sp.m * sp.n;
+        acc += sp.desc.h * sp.desc.m * sp.desc.n;
       }
       L.gemm_total = acc;
     }
@@ -223,11 +227,16 @@ void enqueue_chunk(Plan& plan, ChunkPlan& cp, const RunArgs& a, const int64_t* b
   auto step = [&](int s) {
     StepPlan& sp = cp.steps[s];
     GemmDesc d = sp.desc;
-    d.A = ptr(sp.A);
-    d.B = ptr(sp.B);
-    d.C = ptr(sp.C);
+    d.A = ptr(sp.la);
+    d.B = ptr(sp.lb);
+    float2* c = ptr(sp.C);
+    d.C = sp.split > 1 ? reinterpret_cast<float2*>(a.arena + cp.buf_off[sp.scratch_buf]) : c;
     const int variant = net.ctx->gemm_variant >= 0 ? net.ctx->gemm_variant : sp.variant;
     L.run(s, stream, [&] { return launch_gemm(d, sp.kind, variant, form, prec, stream); });
+    if (sp.split > 1)
+      L.run(s, stream, [&] {
+        return launch_splitk_reduce(d.C, c, sp.h, sp.lm, sp.ln, sp.split, sp.dev_offM, sp.dev_offN, stream);
+      });
   };
   if (cp.grouped) {
     // level by level: the level's plain leaf gathers in one launch, its small

@@ -99,10 +99,10 @@ struct Stage {
 
   template <bool CHECK>
   __device__ __forceinline__ static f4 fetch(const float2* __restrict__ X, int64_t gr, int64_t gk, int64_t rows,
-                                             int64_t k) {
+                                             int64_t k, int64_t ld) {
     f4 v = {0.f, 0.f, 0.f, 0.f};
     if (!CHECK || (gr < rows && gk < k)) {
-      const float2* p = X + gr * k + gk;
+      const float2* p = X + gr * ld + gk;
       if constexpr (VW == 2) {
         v = *reinterpret_cast<const f4*>(p);
       } else {
@@ -116,16 +116,17 @@ struct Stage {
 
   template <bool CHECK>
   __device__ __forceinline__ void load(const float2* __restrict__ A, const float2* __restrict__ B, int64_t m,
-                                       int64_t n, int64_t k, int64_t row0, int64_t col0, int64_t kk, int tid) {
+                                       int64_t n, int64_t k, int64_t ld, int64_t row0, int64_t col0, int64_t kk,
+                                       int tid) {
 #pragma unroll
     for (int i = 0; i < A_LOADS; ++i) {
       const int idx = tid + S::NT * i;
-      a[i] = fetch<CHECK>(A, row0 + idx / PER_ROW, kk + (idx % PER_ROW) * VW, m, k);
+      a[i] = fetch<CHECK>(A, row0 + idx / PER_ROW, kk + (idx % PER_ROW) * VW, m, k, ld);
     }
 #pragma unroll
     for (int i = 0; i < B_LOADS; ++i) {
       const int idx = tid + S::NT * i;
-      b[i] = fetch<CHECK>(B, col0 + idx / PER_ROW, kk + (idx % PER_ROW) * VW, n, k);
+      b[i] = fetch<CHECK>(B, col0 + idx / PER_ROW, kk + (idx % PER_ROW) * VW, n, k, ld);
     }
   }
 
@@ -419,13 +420,14 @@ template <int WM, int WN, int VW, bool CHECK, class Ops>
 __device__ __forceinline__ void main_loop(const GemmDesc& d, const float2* A, const float2* B, const TileCoord& tc,
                                           char* lds, Ops& ops, int tid, int wm, int wn, int lane) {
   const int64_t nk = (d.k + BKC - 1) / BKC;
+  const int64_t ld = row_stride(d);
   Stage<WM, WN, VW> st;
-  st.template load<CHECK>(A, B, d.m, d.n, d.k, tc.row0, tc.col0, 0, tid);
+  st.template load<CHECK>(A, B, d.m, d.n, d.k, ld, tc.row0, tc.col0, 0, tid);
   ops.stage(st, lds, 0, tid);
   __syncthreads();
   for (int64_t kt = 0; kt < nk; ++kt) {
     const int buf = kt & 1;
-    if (kt + 1 < nk) st.template load<CHECK>(A, B, d.m, d.n, d.k, tc.row0, tc.col0, (kt + 1) * BKC, tid);
+    if (kt + 1 < nk) st.template load<CHECK>(A, B, d.m, d.n, d.k, ld, tc.row0, tc.col0, (kt + 1) * BKC, tid);
     ops.compute(lds, buf, wm, wn, lane);
     if (kt + 1 < nk) ops.stage(st, lds, buf ^ 1, tid);
     __syncthreads();
@@ -485,7 +487,7 @@ hipError_t launch_shape(const GemmDesc& d, bool bf16, hipStream_t s) {
 
 template <template <int, int, int> class OpsT>
 hipError_t launch_variant(const GemmDesc& d, int variant, bool bf16, hipStream_t s) {
-  if (d.k % 2 != 0) {  // odd k: 8-byte loads, default shape only
+  if ((d.k | row_stride(d)) % 2 != 0) {  // odd k or row stride: 8-byte loads, default shape only
     const size_t lds = bf16 ? Shape<2, 2>::lds_bf16 : Shape<2, 2>::lds_f32;
     return d.offM ? launch_one<OpsT, 2, 2, 1, true>(d, lds, s) : launch_one<OpsT, 2, 2, 1, false>(d, lds, s);
   }

@@ -25,8 +25,8 @@ __global__ __launch_bounds__(256) void cgemm_small(GemmDesc d) {
     const int64_t j = r - i * d.n;
     int64_t oa, ob;
     batch_offsets(d, b, oa, ob);
-    const float2* a = d.A + oa + i * d.k;
-    const float2* bb = d.B + ob + j * d.k;
+    const float2* a = d.A + oa + i * row_stride(d);
+    const float2* bb = d.B + ob + j * row_stride(d);
     float cr = 0.f, ci = 0.f, crx = 0.f, cix = 0.f;
     for (int64_t l = 0; l < d.k; ++l) {
       const float2 x = a[l];
@@ -75,8 +75,8 @@ __global__ __launch_bounds__(256) void cgemm_dot(GemmDesc d) {
   const int64_t j = r - i * d.n;
   int64_t oa, ob;
   batch_offsets(d, b, oa, ob);
-  const float2* a = d.A + oa + i * d.k;
-  const float2* bb = d.B + ob + j * d.k;
+  const float2* a = d.A + oa + i * row_stride(d);
+  const float2* bb = d.B + ob + j * row_stride(d);
   float cr = 0.f, ci = 0.f, crx = 0.f, cix = 0.f;
   for (int64_t l = lane; l < d.k; l += 64) {
     const float2 x = a[l];
@@ -113,7 +113,41 @@ __global__ __launch_bounds__(256) void cgemm_dot(GemmDesc d) {
   }
 }
 
+__global__ __launch_bounds__(256) void splitk_reduce(const float2* __restrict__ P, float2* __restrict__ C,
+                                                     int64_t h, int64_t m, int64_t n, int64_t S,
+                                                     const int64_t* __restrict__ offM,
+                                                     const int64_t* __restrict__ offN) {
+  const int64_t mn = m * n;
+  const int64_t total = h * mn;
+  for (int64_t idx = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x; idx < total;
+       idx += static_cast<int64_t>(gridDim.x) * blockDim.x) {
+    const int64_t b = idx / mn;
+    const int64_t r = idx - b * mn;
+    const float2* p = P + b * S * mn + r;
+    float cr = 0.f, ci = 0.f;
+    for (int64_t q = 0; q < S; ++q) {
+      const float2 v = p[q * mn];
+      cr += v.x;
+      ci += v.y;
+    }
+    const int64_t i = r / n;
+    const int64_t j = r - i * n;
+    C[b * mn + (offM ? offM[i] + offN[j] : r)] = make_float2(cr, ci);
+  }
+}
+
 }  // namespace
+
+hipError_t launch_splitk_reduce(const float2* P, float2* C, int64_t h, int64_t m, int64_t n, int64_t S,
+                                const int64_t* offM, const int64_t* offN, hipStream_t s) {
+  const int64_t total = h * m * n;
+  if (total <= 0) return hipSuccess;
+  if (S <= 0) return hipErrorInvalidValue;
+  int64_t grid = (total + 255) / 256;
+  if (grid > 1048576) grid = 1048576;
+  hipLaunchKernelGGL(splitk_reduce, dim3(grid), dim3(256), 0, s, P, C, h, m, n, S, offM, offN);
+  return hipGetLastError();
+}
 
 hipError_t launch_gemm_valu(const GemmDesc& d, GemmKernel kind, Prec prec, hipStream_t s) {
   if (d.h <= 0 || d.m <= 0 || d.n <= 0) return hipSuccess;

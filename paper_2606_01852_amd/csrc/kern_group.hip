@@ -47,8 +47,8 @@ __global__ __launch_bounds__(256) void group_small_gemm(const GroupGemm* __restr
     const int64_t j = r - i * d.n;
     int64_t oa, ob;
     batch_offsets(d, b, oa, ob);
-    const float2* A = reloc<const float2>(d.A, e.rel_a, arena) + oa + i * d.k;
-    const float2* B = reloc<const float2>(d.B, e.rel_b, arena) + ob + j * d.k;
+    const float2* A = reloc<const float2>(d.A, e.rel_a, arena) + oa + i * row_stride(d);
+    const float2* B = reloc<const float2>(d.B, e.rel_b, arena) + ob + j * row_stride(d);
     float2* C = reloc<float2>(d.C, e.rel_c, arena);
     float cr = 0.f, ci = 0.f, crx = 0.f, cix = 0.f;
     for (int64_t l = 0; l < d.k; ++l) {

@@ -11,10 +11,14 @@ constexpr int kMaxBatchDims = 24;
 
 // Batched complex GEMM  C[b, i, j] = sum_l A[b, i, l] * B[b, j, l].
 // A, B are K-contiguous ([.. | M | K] and [.. | N | K] storage, row stride
-// k).  The batch index b (0 <= b < h) is row-major over nbd batch dims; the
-// operands' offsets are sum_d digit_d * bs{A,B}[d] (0 = broadcast), C's is
-// b * m * n.  Within one batch entry C is natural row-major [m, n] when offM
-// is null, else element (i, j) sits at offM[i] + offN[j].
+// ldk, which is k when ldk is 0).  The batch index b (0 <= b < h) is
+// row-major over nbd batch dims; the operands' offsets are
+// sum_d digit_d * bs{A,B}[d] (0 = broadcast), C's is b * m * n.  Within one
+// batch entry C is natural row-major [m, n] when offM is null, else element
+// (i, j) sits at offM[i] + offN[j].  A split of the K range into S parts is
+// expressed as one more (innermost) batch dim of extent S with strides
+// k / S, k = k / S and ldk = the full row length; the S partial products
+// are then summed by launch_splitk_reduce.
 struct GemmDesc {
   const float2* A;
   const float2* B;
@@ -28,7 +32,10 @@ struct GemmDesc {
   int64_t bsB[kMaxBatchDims];
   const int64_t* offM;
   const int64_t* offN;
+  int64_t ldk;
 };
+
+__host__ __device__ inline int64_t row_stride(const GemmDesc& d) { return d.ldk ? d.ldk : d.k; }
 
 enum class Form : int { M4 = 0, M3 = 1 };
 enum class Prec : int { C64 = 0, BF16X3 = 1 };
@@ -36,9 +43,17 @@ enum class GemmKernel : int { MFMA = 0, SMALL = 1, DOT = 2 };
 
 // Kernel choice for one step's shape (shared by the planner and the
 // stand-alone GEMM entry point).
+//  * MFMA for shapes that fill its 64 x 32 wave tiles, and for skinny shapes
+//    (m >= 16, n >= 8) with enough work (2^22 complex MACs) that running
+//    MFMA on padded tiles still beats one thread per output;
+//  * DOT (one wave64 per output) for long reductions with few outputs;
+//  * SMALL (one thread per output) for the rest: tiny steps.
 inline GemmKernel choose_gemm_kernel(int64_t h, int64_t m, int64_t n, int64_t k) {
   const int64_t tiles = ((m + 127) / 128) * ((n + 63) / 64) * h;
-  if (m >= 64 && n >= 32 && k >= 16 && tiles < (int64_t{1} << 24)) return GemmKernel::MFMA;
+  if (k >= 16 && tiles < (int64_t{1} << 24)) {
+    if (m >= 64 && n >= 32) return GemmKernel::MFMA;
+    if (m >= 16 && n >= 8 && h * m * n * k >= (int64_t{1} << 22)) return GemmKernel::MFMA;
+  }
   if (k >= 256 && m * n <= 64 && (h * m * n + 3) / 4 < 0x7FFFFF) return GemmKernel::DOT;
   return GemmKernel::SMALL;
 }
@@ -86,6 +101,10 @@ constexpr int kGemmVariants = 7;
 void gemm_variant_tile(int variant, int* bm, int* bnc);
 hipError_t launch_gemm(const GemmDesc& d, GemmKernel kind, int variant, Form form, Prec prec, hipStream_t s);
 hipError_t launch_gemm_valu(const GemmDesc& d, GemmKernel kind, Prec prec, hipStream_t s);
+// Split-K epilogue: C[b, i, j] = sum_{p < S} P[((b * S + p) * m + i) * n + j],
+// p ascending, stored at b * m * n + (offM ? offM[i] + offN[j] : i * n + j).
+hipError_t launch_splitk_reduce(const float2* P, float2* C, int64_t h, int64_t m, int64_t n, int64_t S,
+                                const int64_t* offM, const int64_t* offN, hipStream_t s);
 // Grouped launches (one per tree level).  Operand pointers flagged rel_*
 // hold arena offsets, relocated against the arena base at run time, so the
 // tables stay valid for any arena.

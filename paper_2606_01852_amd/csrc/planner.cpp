@@ -493,10 +493,24 @@ std::unique_ptr<ChunkPlan> build_chunk(const Plan& plan, int j) {
       }
     }
     if (static_cast<int>(me.size()) > kMaxBatchDims) fail(TNC_E_UNSUPPORTED, "too many batch dims");
+    // launch orientation: transposed (B as the row operand) when only that
+    // orientation reaches MFMA, or when it pads the 64 x 32 wave tiles less
+    auto waste = [](int64_t r, int64_t c) {
+      return static_cast<double>((r + 63) / 64 * 64) / r * static_cast<double>((c + 31) / 32 * 32) / c;
+    };
+    const GemmKernel k0 = choose_gemm_kernel(sp.h, sp.m, sp.n, sp.k);
+    const GemmKernel k1 = choose_gemm_kernel(sp.h, sp.n, sp.m, sp.k);
+    sp.swap = k1 == GemmKernel::MFMA && (k0 != GemmKernel::MFMA || waste(sp.n, sp.m) < waste(sp.m, sp.n));
+    sp.kind = sp.swap ? k1 : k0;
+    sp.la = sp.swap ? sp.B : sp.A;
+    sp.lb = sp.swap ? sp.A : sp.B;
+    sp.lm = sp.swap ? sp.n : sp.m;
+    sp.ln = sp.swap ? sp.m : sp.n;
+    if (sp.swap) std::swap(ma, mb);
     GemmDesc& d = sp.desc;
     std::memset(&d, 0, sizeof(d));
-    d.m = sp.m;
-    d.n = sp.n;
+    d.m = sp.lm;
+    d.n = sp.ln;
     d.k = sp.k;
     d.h = sp.h;
     d.nbd = static_cast<int32_t>(me.size());
@@ -511,9 +525,9 @@ std::unique_ptr<ChunkPlan> build_chunk(const Plan& plan, int j) {
       d.bshift[q] = sh;
       if ((int64_t{1} << sh) != me[q]) d.pow2 = 0;
     }
-    if (!sp.natural) {
-      sp.offM.resize(sp.m);
-      sp.offN.resize(sp.n);
+    // store tables (launch orientation) for permuted or transposed stores
+    if (!sp.natural || sp.swap) {
+      std::vector<int64_t> tm(sp.m), tn(sp.n);
       auto fill = [&](const std::vector<int>& ls, std::vector<int64_t>& off) {
         for (int64_t i = 0; i < static_cast<int64_t>(off.size()); ++i) {
           int64_t rest = i, o = 0;
@@ -525,11 +539,38 @@ std::unique_ptr<ChunkPlan> build_chunk(const Plan& plan, int j) {
           off[i] = o;
         }
       };
-      fill(sp.M, sp.offM);
-      fill(sp.N, sp.offN);
-      cp->n_perm_stores++;
+      fill(sp.M, tm);
+      fill(sp.N, tn);
+      sp.offM = sp.swap ? std::move(tn) : std::move(tm);
+      sp.offN = sp.swap ? std::move(tm) : std::move(tn);
     }
-    sp.kind = choose_gemm_kernel(sp.h, sp.m, sp.n, sp.k);
+    if (!sp.natural) cp->n_perm_stores++;
+    // split K when the output alone cannot fill the chip: the K range is cut
+    // into S equal parts (one more batch dim), partial products go to an
+    // arena scratch buffer and the split-K epilogue sums them in order
+    int64_t S = 1;
+    if (sp.kind == GemmKernel::MFMA) {
+      const int64_t t0 = sp.h * ((sp.lm + 127) / 128) * ((sp.ln + 63) / 64);
+      if (t0 < 512 && sp.k >= 2048)
+        while (t0 * S * 2 <= 2048 && sp.k / (S * 2) >= 512 && sp.k % (16 * S * 2) == 0) S *= 2;
+    } else if (sp.kind == GemmKernel::DOT) {
+      const int64_t outs = sp.h * sp.lm * sp.ln;
+      if (outs < 4096 && sp.k >= 8192)
+        while (outs * S * 2 <= 16384 && sp.k / (S * 2) >= 1024 && sp.k % (S * 2) == 0) S *= 2;
+    }
+    if (S > 1 && d.nbd < kMaxBatchDims) {
+      const int q = d.nbd++;
+      d.bext[q] = static_cast<int32_t>(S);
+      d.bsA[q] = sp.k / S;
+      d.bsB[q] = sp.k / S;
+      int sh = 0;
+      while ((int64_t{1} << sh) < S) ++sh;
+      d.bshift[q] = sh;
+      d.h = sp.h * S;
+      d.k = sp.k / S;
+      d.ldk = sp.k;
+      sp.split = static_cast<int>(S);
+    }
     cp->flops += 8.0 * static_cast<double>(sp.h) * sp.m * sp.n * sp.k;
     cp->bytes += 8.0 * (static_cast<double>(sp.hA) * sp.m * sp.k + static_cast<double>(sp.hB) * sp.n * sp.k +
                         static_cast<double>(sp.h) * sp.m * sp.n);
@@ -577,6 +618,9 @@ std::unique_ptr<ChunkPlan> build_chunk(const Plan& plan, int j) {
   for (int s = 0; s < ns; ++s) {
     const int c = n + s;
     ivs.push_back({align_up(cp->numel[c] * 8), when(s), consumer[c] < ns ? when(consumer[c]) : t_end, c});
+    const StepPlan& sp = cp->steps[s];
+    if (sp.split > 1)  // split-K partials, live during the step only
+      ivs.push_back({align_up(sp.h * sp.split * sp.lm * sp.ln * 8), when(s), when(s), -1 - s});
   }
   std::vector<int> idx(ivs.size());
   std::iota(idx.begin(), idx.end(), 0);
@@ -604,8 +648,13 @@ std::unique_ptr<ChunkPlan> build_chunk(const Plan& plan, int j) {
     placed.push_back(x);
   }
   for (size_t q = 0; q < ivs.size(); ++q) {
-    cp->tensor_buf[ivs[q].id] = static_cast<int>(q);
-    if (ivs[q].id < n) cp->leaf[ivs[q].id].buf = static_cast<int>(q);
+    const int id = ivs[q].id;
+    if (id < 0) {
+      cp->steps[-1 - id].scratch_buf = static_cast<int>(q);
+      continue;
+    }
+    cp->tensor_buf[id] = static_cast<int>(q);
+    if (id < n) cp->leaf[id].buf = static_cast<int>(q);
   }
   cp->peak = peak;
 

@@ -43,7 +43,8 @@ class PlanInfo(C.Structure):
 class StepInfo(C.Structure):
     _fields_ = [("A", C.c_int32), ("B", C.c_int32), ("C", C.c_int32), ("nH", C.c_int32), ("nM", C.c_int32),
                 ("nN", C.c_int32), ("nK", C.c_int32), ("h", C.c_int64), ("m", C.c_int64), ("n", C.c_int64),
-                ("k", C.c_int64), ("natural", C.c_int32), ("kernel", C.c_int32), ("variant", C.c_int32)]
+                ("k", C.c_int64), ("natural", C.c_int32), ("kernel", C.c_int32), ("variant", C.c_int32),
+                ("swapped", C.c_int32), ("split", C.c_int32)]
 
 
 class DistHW(C.Structure):
@@ -80,6 +81,7 @@ _SIGS = {
     "tnc_plan_destroy": (C.c_int, [_P]),
     "tnc_plan_get_info": (C.c_int, [_P, C.POINTER(PlanInfo)]),
     "tnc_plan_get_step": (C.c_int, [_P, C.c_int32, C.POINTER(StepInfo)]),
+    "tnc_plan_get_batch_step": (C.c_int, [_P, C.c_int32, C.POINTER(StepInfo)]),
     "tnc_plan_get_order": (C.c_int, [_P, C.c_int32, _I32P, C.c_int32, _I32P]),
     "tnc_plan_set_max_chunk": (C.c_int, [_P, C.c_int64]),
     "tnc_plan_set_graph": (C.c_int, [_P, C.c_int32]),
@@ -222,6 +224,12 @@ def tnc_plan_get_info(plan: int) -> PlanInfo:
 def tnc_plan_get_step(plan: int, step: int) -> StepInfo:
     s = StepInfo()
     _check(lib().tnc_plan_get_step(plan, step, C.byref(s)))
+    return s
+
+
+def tnc_plan_get_batch_step(plan: int, step: int) -> StepInfo:
+    s = StepInfo()
+    _check(lib().tnc_plan_get_batch_step(plan, step, C.byref(s)))
     return s
 
 

@@ -341,3 +341,26 @@ def test_level_grouping_is_bitwise_step_order(ctx, case):
     if ref_or is not None and prec == tnc.PREC_C64:
         z = complex(ref[0])
         assert abs(z - ref_or) <= 1e-5 * abs(ref_or)
+
+
+@pytest.mark.parametrize("dims, batch", [((7, 16, 6), 1), ((2, 20, 1), 1), ((3, 10, 9), 64), ((5, 12, 3), 4)],
+                         ids=["splitk_mfma", "splitk_dot", "transposed", "skinny_split"])
+@pytest.mark.parametrize("prec, form", [(tnc.PREC_C64, tnc.GEMM_4M), (tnc.PREC_C64, tnc.GEMM_3M),
+                                        (tnc.PREC_BF16X3, tnc.GEMM_4M)], ids=["4M", "3M", "bf16x3"])
+def test_split_k_and_transposed_launches(ctx, dims, batch, prec, form):
+    """Steps run with K split into parts (partials summed by the split-K
+    epilogue), or transposed so that MFMA tiles fill, match the oracle."""
+    net, path = pair_network(*dims, seed=8, batch=batch)
+    print("launch shapes", dims, batch, prec, form, flush=True)
+    got, plan, _ = run(ctx, net, path, prec=prec, form=form)
+    s = plan.step(0)
+    ref = oc.contract(net, path)
+    err = rel_fro(got, ref)
+    print(f"h {s.h} m {s.m} n {s.n} k {s.k}: kernel {s.kernel} swapped {s.swapped} split {s.split}; "
+          f"err {err:.2e}", flush=True)
+    if prec == tnc.PREC_BF16X3:
+        emu = oc.contract(net, path, step=osp.split_step)
+        assert rel_fro(got, emu) <= 1e-5
+        assert err <= max(1e-5, 4 * 2.0 ** -16)
+    else:
+        assert err <= 1e-5

@@ -254,3 +254,51 @@ def test_handles_can_be_destroyed_in_any_order():
             tnc.tnc_plan_destroy(p)
             tnc.tnc_net_destroy(n)
             tnc.tnc_ctx_destroy(ctx)
+
+
+def test_slice_invariant_work_runs_once_per_batch(hctx):
+    """In a batch of c slices, a step pays for a batch label only if its
+    operands' subtrees hold that label: slice-invariant subtrees are computed
+    once per batch, not once per slice.  The executed FLOPs of the largest
+    batch are recomputed here from the label sets alone."""
+    net, path = configs.circuit40(n_sliced=16)
+    tn = tnc.Network(tnc.Context(-1, arena_bytes=8 << 30), net.labels, net.extents, net.open)
+    plan = tnc.Plan(tn, path.pairs, path.sliced)
+    info = plan.info
+    c = info.max_chunk
+    j = int(round(np.log2(c)))
+    assert 2 ** j == c and j >= 1
+    batched = set(int(l) for l in path.sliced[len(path.sliced) - j:])
+    from workloads.paths import path_tensors
+    _, ops = path_tensors(net, path.pairs, path.sliced)
+    n = net.n_leaves
+    holds = [set(int(l) for l in lab) & batched for lab in net.labels]
+    executed = 0
+    for s, (a, b) in enumerate(path.pairs):
+        holds.append(holds[a] | holds[b])
+        executed += 8 * ops[s] * int(np.prod([net.extents[l] for l in holds[n + s]]))
+    assert info.chunk_flops == executed
+    # per-slice accounting would be c times the per-slice count; hoisting saves
+    per_slice = c * info.flops_per_slice
+    print(f"batch of {c}: executed {executed:.3e} FLOP vs {per_slice:.3e} slice by slice")
+    assert executed < per_slice
+
+
+@pytest.mark.parametrize("dims, batch, kernel, swapped, split", [
+    ((7, 16, 6), 1, 0, 0, 128),     # 128 x 64 output, k = 2^16: one tile, K cut 128 ways
+    ((2, 20, 1), 1, 2, 0, 1024),    # 4 x 2 outputs, k = 2^20: long dot, K cut 1024 ways
+    ((3, 10, 9), 64, 0, 1, 1),      # 64 x (8 x 512), k = 2^10: MFMA only transposed
+    ((10, 9, 8), 1, 0, 0, 1),       # ordinary tiles: neither
+    ((2, 3, 2), 1, 1, 0, 1),        # tiny: one thread per output
+])
+def test_launch_shape_decisions(hctx, dims, batch, kernel, swapped, split):
+    """Kernel, orientation and split-K choice per step shape (host rules)."""
+    from workloads.pairs import pair_network
+    net, path = pair_network(*dims, seed=7, batch=batch)
+    tn = tnc.Network(hctx, net.labels, net.extents, net.open)
+    plan = tnc.Plan(tn, path.pairs)
+    s = plan.step(0)
+    assert (s.kernel, s.swapped, s.split) == (kernel, swapped, split)
+    assert (s.m, s.n, s.k) == (2 ** dims[0], 2 ** dims[2], 2 ** dims[1])   # logical view unchanged
+    if split > 1:    # the partials sit in the arena next to the result
+        assert plan.info.peak_bytes >= 8 * s.h * s.m * s.n * (split + 1)
