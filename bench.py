@@ -109,12 +109,16 @@ def cpu_baseline(net_a, path_a, net_b, path_b, budget_s: float = 20.0):
                       f"batch entries ({dt2:.1f} s); numpy complex128 tensordot incl. operand transposes"}
 
 
+HEAVY_FLOPS = 2.0 ** 38   # requests planned at >= this many FLOP share one heavy slot
+
+
 def serving_leg(args):
     """Serving mix: a pool of random grid circuits (20..48 qubits, depth 8..14,
     4^j slices, complex64 or split-bf16, planned work capped at 2^43 FLOP),
     Poisson arrivals at ``load`` x the measured saturation throughput of the
-    continuous-batching server; the same arrival trace is replayed through
-    the server with one slot (one request at a time).  Latency is submit to
+    continuous-batching server (heavy requests, >= 2^38 planned FLOP, in a
+    lane of one slot); the same arrival trace is replayed through the server
+    without the heavy lane and with one slot (one request at a time).  Latency is submit to
     done, measured by the library."""
     import threading
 
@@ -145,8 +149,9 @@ def serving_leg(args):
     gaps = rng.exponential(1.0, args.serve_requests)
     outs = [np.zeros(1, dtype=np.complex128) for _ in which]
 
-    def replay(slots, arrivals):
+    def replay(slots, arrivals, heavy=HEAVY_FLOPS):
         tnc.tnc_serve_start(ctx.handle, slots, 1 << 16)
+        tnc.tnc_serve_set_heavy(ctx.handle, heavy, 1)
         t_start = time.perf_counter()
         ids = []
         for i, (w, at) in enumerate(zip(which, arrivals)):
@@ -167,10 +172,13 @@ def serving_leg(args):
     arrivals = np.cumsum(gaps) / rate
     log(f"serving: saturation {sat:.1f} req/s; replaying {len(which)} Poisson arrivals at {rate:.1f} req/s")
     res = {}
-    for name, slots in (("continuous_batching", args.serve_slots), ("one_at_a_time", 1)):
-        lat, wall = replay(slots, arrivals)
+    for name, slots, heavy in (("continuous_batching", args.serve_slots, HEAVY_FLOPS),
+                               ("continuous_no_heavy_lane", args.serve_slots, 0.0),
+                               ("one_at_a_time", 1, 0.0)):
+        lat, wall = replay(slots, arrivals, heavy)
         tot_flops = sum(flops[w] for w in which)
-        res[name] = {"slots": slots, "p50_ms": round(float(np.percentile(lat, 50)) * 1e3, 3),
+        res[name] = {"slots": slots, "heavy_lane_flops": heavy,
+                     "p50_ms": round(float(np.percentile(lat, 50)) * 1e3, 3),
                      "p99_ms": round(float(np.percentile(lat, 99)) * 1e3, 3),
                      "req_per_s": round(len(which) / wall, 2),
                      "tflops": round(tot_flops / wall / 1e12, 3)}

@@ -267,10 +267,19 @@ tnc_status tnc_ctx_sync(tnc_ctx ctx);
 /* ---------------------------------------------------------------- serving
  * Continuous batching: requests are admitted while others run, as soon as a
  * slot and enough arena for the plan's planned peak are free; admitted
- * requests run concurrently on separate streams.  out_c128 (host pointer)
- * must stay valid until the request is done.  TNC_E_BUSY if the queue is
- * full; TNC_E_NOMEM if the request can never fit. */
+ * requests run concurrently on separate streams.  Requests whose planned
+ * work reaches the heavy threshold (default 2^38 FLOP) share a lane of
+ * heavy_slots slots (default 1): a heavy request waits only for heavy ones
+ * ahead of it, and light requests behind a waiting heavy one are admitted
+ * past it.  Otherwise admission is in submission order (a request that does
+ * not fit the free arena yet blocks the ones behind it).  out_c128 (host
+ * pointer) must stay valid until the request is done.  TNC_E_BUSY if the
+ * queue is full; TNC_E_NOMEM if the request can never fit. */
 tnc_status tnc_serve_start(tnc_ctx ctx, int32_t max_inflight, int32_t queue_cap);
+/* Heavy-request lane: threshold in planned FLOPs (<= 0 disables the lane)
+ * and the number of heavy requests that may run at once (>= 1).  Applies to
+ * admissions from now on; TNC_E_ARG if the context is not serving. */
+tnc_status tnc_serve_set_heavy(tnc_ctx ctx, double heavy_flops, int32_t heavy_slots);
 tnc_status tnc_serve_stop(tnc_ctx ctx);
 tnc_status tnc_submit(tnc_ctx ctx, tnc_plan plan, int64_t first_slice, int64_t n_slices,
                       double* out_c128, tnc_req* id);

@@ -8,6 +8,12 @@
 // the kernels of admitted requests overlap on the device.  A request's work
 // and its chunking depend only on its plan and slice range, so its result is
 // the same alone or in a mix.
+//
+// Overlap helps latency-bound requests (many small launches) and only slows
+// compute-bound ones, which already fill the chip alone.  Requests whose
+// planned work reaches a threshold are therefore "heavy" and share a lane of
+// few slots: a heavy request waits for the heavy ones ahead of it, never for
+// light ones, and light requests behind a waiting heavy one go past it.
 #include <chrono>
 #include <condition_variable>
 #include <cstring>
@@ -78,6 +84,9 @@ struct Request {
   int64_t first = 0, count = 0;
   double* out = nullptr;
   int64_t need = 0, work_bytes = 0, acc_off = 0;
+  double flops = 0;
+  bool heavy = false;       // classified at submission
+  bool heavy_slot = false;  // holds a heavy-lane slot while running
   int64_t arena_off = -1;
   Clock::time_point t_submit, t_done;
   bool done = false;
@@ -101,6 +110,21 @@ struct Server {
   bool stop = false;
   uint64_t next_id = 1;
   int inflight = 0;
+  double heavy_flops = 274877906944.0;  // 2^38 planned FLOP
+  int heavy_slots = 1;
+  int heavy_inflight = 0;
+
+  // Next admissible request (queue order), or end(): heavy requests wait for
+  // a heavy slot without blocking light ones; a request that does not fit
+  // the free arena blocks everything behind it (no starvation by size).
+  std::deque<std::shared_ptr<Request>>::iterator pick() {
+    for (auto it = queue.begin(); it != queue.end(); ++it) {
+      const Request& r = **it;
+      if (r.heavy && heavy_inflight >= heavy_slots) continue;
+      return arena.fits(r.need) ? it : queue.end();
+    }
+    return queue.end();
+  }
 
   Server(Ctx& c, int slots, int cap)
       : ctx(c), max_inflight(slots), queue_cap(cap), arena(static_cast<int64_t>(c.arena_bytes)) {}
@@ -133,11 +157,18 @@ struct Server {
       {
         std::unique_lock<std::mutex> g(mu);
         // drain on stop: keep admitting until the queue is empty
-        cv_work.wait(g, [&] { return (stop && queue.empty()) || (!queue.empty() && arena.fits(queue.front()->need)); });
+        std::deque<std::shared_ptr<Request>>::iterator it;
+        cv_work.wait(g, [&] {
+          if (stop && queue.empty()) return true;
+          it = pick();
+          return it != queue.end();
+        });
         if (queue.empty()) return;
-        r = queue.front();
-        queue.pop_front();
+        r = *it;
+        queue.erase(it);
         r->arena_off = arena.alloc(r->need);
+        r->heavy_slot = r->heavy;
+        if (r->heavy) ++heavy_inflight;
         ++inflight;
       }
       execute(*r, stream);
@@ -146,6 +177,7 @@ struct Server {
         arena.release(r->arena_off, r->need);
         r->t_done = Clock::now();
         r->done = true;
+        if (r->heavy_slot) --heavy_inflight;
         --inflight;
       }
       cv_work.notify_all();
@@ -216,6 +248,22 @@ tnc_status tnc_serve_start(tnc_ctx ctx, int32_t max_inflight, int32_t queue_cap)
   return TNC_OK;
 }
 
+tnc_status tnc_serve_set_heavy(tnc_ctx ctx, double heavy_flops, int32_t heavy_slots) {
+  g_error_clear();
+  if (!ctx || !ctx->c->server || heavy_slots < 1) {
+    g_error_set("bad arguments or server not started");
+    return TNC_E_ARG;
+  }
+  Server& s = *ctx->c->server;
+  {
+    std::lock_guard<std::mutex> g(s.mu);
+    s.heavy_flops = heavy_flops;
+    s.heavy_slots = heavy_slots;
+  }
+  s.cv_work.notify_all();
+  return TNC_OK;
+}
+
 tnc_status tnc_serve_stop(tnc_ctx ctx) {
   g_error_clear();
   if (!ctx) {
@@ -247,12 +295,14 @@ tnc_status tnc_submit(tnc_ctx ctx, tnc_plan plan, int64_t first_slice, int64_t n
     r->work_bytes = run_workspace_bytes(p, first_slice, n_slices);
     r->acc_off = r->work_bytes;
     r->need = r->work_bytes + align_up(p.chunks[0]->R * 16);
+    for (const auto& ch : decompose(p, first_slice, n_slices)) r->flops += p.chunk(ch.first).flops;
     if (r->need > static_cast<int64_t>(c.arena_bytes))
       fail(TNC_E_NOMEM, "request needs " + std::to_string(r->need) + " arena bytes, the arena has " +
                             std::to_string(c.arena_bytes));
     {
       std::lock_guard<std::mutex> g(s->mu);
       if (s->queue.size() >= s->queue_cap) fail(TNC_E_BUSY, "serving queue full");
+      r->heavy = s->heavy_flops > 0 && r->flops >= s->heavy_flops;
       r->id = s->next_id++;
       r->t_submit = Clock::now();
       s->queue.push_back(r);

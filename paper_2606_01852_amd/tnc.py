@@ -99,6 +99,7 @@ _SIGS = {
                                     C.c_int64, _P, C.c_int, C.c_int]),
     "tnc_serve_start": (C.c_int, [_P, C.c_int32, C.c_int32]),
     "tnc_serve_stop": (C.c_int, [_P]),
+    "tnc_serve_set_heavy": (C.c_int, [_P, C.c_double, C.c_int32]),
     "tnc_submit": (C.c_int, [_P, _P, C.c_int64, C.c_int64, _DP, C.POINTER(C.c_uint64)]),
     "tnc_poll": (C.c_int, [_P, C.c_uint64, _I32P, _DP]),
     "tnc_wait": (C.c_int, [_P, C.c_uint64, _DP]),
@@ -313,6 +314,10 @@ def tnc_batched_cgemm(ctx: int, h: int, m: int, n: int, k: int, a_dev: int, stri
 
 def tnc_serve_start(ctx: int, max_inflight: int, queue_cap: int) -> None:
     _check(lib().tnc_serve_start(ctx, max_inflight, queue_cap))
+
+
+def tnc_serve_set_heavy(ctx: int, heavy_flops: float, heavy_slots: int = 1) -> None:
+    _check(lib().tnc_serve_set_heavy(ctx, float(heavy_flops), int(heavy_slots)))
 
 
 def tnc_serve_stop(ctx: int) -> None:

@@ -134,3 +134,37 @@ def test_contract_is_refused_while_serving(served):
     assert e.value.status == tnc.E_BUSY
     tnc.tnc_serve_stop(ctx.handle)
     assert plans[0].contract().shape == (1,)
+
+
+def test_heavy_lane_keeps_results(served):
+    """Heavy requests (planned work above a threshold) share a lane of few
+    slots and light ones pass them in the queue; results stay bitwise those
+    of one request at a time, whatever the lane setting."""
+    ctx, pool, nets, plans = served
+    order = list(range(len(plans)))
+    work = [p.info.chunk_flops * (p.info.n_slices // p.info.max_chunk) for p in plans]
+    threshold = float(np.median(work))
+    print("planned work", [f"{w:.2e}" for w in work], "threshold", f"{threshold:.2e}", flush=True)
+    alone = {}
+    for i in order:
+        o, _ = run_all(ctx, plans, [i], 1)
+        alone[i] = o[i]
+    with pytest.raises(tnc.TncError):            # no server running
+        tnc.tnc_serve_set_heavy(ctx.handle, threshold, 1)
+    rng = np.random.Generator(np.random.PCG64(6))
+    mixed = [int(x) for x in rng.permutation(order)] * 2
+    for heavy, slots in ((threshold, 1), (threshold, 2), (0.0, 1)):
+        tnc.tnc_serve_start(ctx.handle, 6, 1024)
+        with pytest.raises(tnc.TncError):
+            tnc.tnc_serve_set_heavy(ctx.handle, heavy, 0)
+        tnc.tnc_serve_set_heavy(ctx.handle, heavy, slots)
+        outs, ids = [], []
+        for i in mixed:
+            out = np.zeros(1, dtype=np.complex128)
+            outs.append((i, out))
+            ids.append(tnc.tnc_submit(ctx.handle, plans[i].handle, 0, plans[i].info.n_slices, out))
+        for rid in ids:
+            tnc.tnc_wait(ctx.handle, rid)
+        tnc.tnc_serve_stop(ctx.handle)
+        for i, out in outs:
+            assert np.array_equal(out.view(np.uint64), alone[i].view(np.uint64)), (heavy, slots, i)
