@@ -34,11 +34,14 @@ PEAK_FP32_MFMA = 157.3   # TFLOP/s, MI355X dense FP32 matrix
 PEAK_BF16_MFMA = 2516.6  # TFLOP/s, MI355X dense bf16 matrix
 PEAK_HBM = 8000.0        # GB/s
 
-# HBM traffic per launch of the dominant kernel (4M GEMM, 4x4-wave tiles, the
-# 2^30-output contraction), from rocprofv3 --pmc FETCH_SIZE (212,037,464 KiB,
-# x2.0) and WRITE_SIZE (8,388,609 KiB, x1.0); the factors are what the same
-# counters read for a 4 GiB device copy.  Set to None when the kernel changes.
-GEMM_TRAFFIC_BYTES = 442.8e9
+# Memory-side traffic per launch of the dominant kernel (4M GEMM, 4x4-wave
+# tiles, the 2^30-output contraction), from rocprofv3 --pmc FETCH_SIZE
+# (368,305,840 KiB, x2.0) and WRITE_SIZE (8,388,608 KiB, x1.0); the factors
+# are what the same counters read for a 4 GiB device copy.  FETCH_SIZE counts
+# every L2 miss (served by the MALL or HBM): with k = 2^14 the A/B panels of
+# the tiles running at once are re-read per K stage.  Set to None when the
+# kernel changes.
+GEMM_TRAFFIC_BYTES = 762.9e9
 
 
 def log(msg: str) -> None:
@@ -308,10 +311,12 @@ def bench_circuit40(args):
     per_step.sort(reverse=True)
     tot = sum(x[0] for x in per_step)
     log(f"profiled run: GEMMs {tot:.1f} ms, leaf permutes {perm_ms:.1f} ms ({perm_n}), reductions {red_ms:.2f} ms")
-    for ms, s in per_step[:12]:
-        st = tnc.tnc_plan_get_step(plan.handle, s)
-        log(f"  step {s:4d}: {ms:8.2f} ms  m {st.m} n {st.n} k {st.k} kernel {st.kernel} natural {st.natural}")
     n_chunks = max(1, n // info.max_chunk)
+    for ms, s in per_step[:12]:
+        st = tnc.tnc_plan_get_batch_step(plan.handle, s)
+        f = 8.0 * st.h * st.m * st.n * st.k * n_chunks
+        log(f"  step {s:4d}: {ms:8.2f} ms  h {st.h} m {st.m} n {st.n} k {st.k} kernel {st.kernel} "
+            f"variant {st.variant} split {st.split} swapped {st.swapped}: {f / ms / 1e9:.1f} TFLOP/s")
     exec_flops = info.chunk_flops * n_chunks if n % info.max_chunk == 0 else info.flops_per_slice * n
     value = exec_flops / dt / 1e12
     log(f"executed {exec_flops:.3e} FLOP ({info.flops_per_slice * n:.3e} without hoisting slice-invariant steps)")
