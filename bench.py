@@ -59,8 +59,8 @@ def parse():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--workload", choices=["pair30", "circuit40", "serve", "small"], default="pair30")
     ap.add_argument("--no-serve", action="store_true", help="skip the serving-latency leg")
-    ap.add_argument("--serve-pool", type=int, default=12)
-    ap.add_argument("--serve-requests", type=int, default=150)
+    ap.add_argument("--serve-pool", type=int, default=24)
+    ap.add_argument("--serve-requests", type=int, default=600)
     ap.add_argument("--serve-load", type=float, default=0.8)
     ap.add_argument("--serve-slots", type=int, default=8)
     ap.add_argument("--slices", type=int, default=0, help="circuit40: slices per run (0 = all)")
@@ -121,7 +121,8 @@ def serving_leg(args):
     Poisson arrivals at ``load`` x the measured saturation throughput of the
     continuous-batching server (heavy requests, >= 2^38 planned FLOP, in a
     lane of one slot); the same arrival trace is replayed through the server
-    without the heavy lane and with one slot (one request at a time).  Latency is submit to
+    without the heavy lane and with one slot (one request at a time), at the
+    main load and at 0.5 and 0.95 of saturation.  Latency is submit to
     done, measured by the library."""
     import threading
 
@@ -171,21 +172,32 @@ def serving_leg(args):
     replay(args.serve_slots, np.zeros(len(which)))
     lat_sat, t_sat = replay(args.serve_slots, np.zeros(len(which)))
     sat = len(which) / t_sat
-    rate = args.serve_load * sat
-    arrivals = np.cumsum(gaps) / rate
-    log(f"serving: saturation {sat:.1f} req/s; replaying {len(which)} Poisson arrivals at {rate:.1f} req/s")
-    res = {}
-    for name, slots, heavy in (("continuous_batching", args.serve_slots, HEAVY_FLOPS),
-                               ("continuous_no_heavy_lane", args.serve_slots, 0.0),
-                               ("one_at_a_time", 1, 0.0)):
-        lat, wall = replay(slots, arrivals, heavy)
-        tot_flops = sum(flops[w] for w in which)
-        res[name] = {"slots": slots, "heavy_lane_flops": heavy,
-                     "p50_ms": round(float(np.percentile(lat, 50)) * 1e3, 3),
-                     "p99_ms": round(float(np.percentile(lat, 99)) * 1e3, 3),
-                     "req_per_s": round(len(which) / wall, 2),
-                     "tflops": round(tot_flops / wall / 1e12, 3)}
-        log(f"serving {name}: {res[name]}")
+    servers = (("continuous_batching", args.serve_slots, HEAVY_FLOPS),
+               ("continuous_no_heavy_lane", args.serve_slots, 0.0),
+               ("one_at_a_time", 1, 0.0))
+    tot_flops = sum(flops[w] for w in which)
+
+    def measure(load):
+        rate = load * sat
+        arrivals = np.cumsum(gaps) / rate
+        log(f"serving: saturation {sat:.1f} req/s; replaying {len(which)} Poisson arrivals at {rate:.1f} req/s")
+        out = {}
+        for name, slots, heavy in servers:
+            lat, wall = replay(slots, arrivals, heavy)
+            out[name] = {"slots": slots, "heavy_lane_flops": heavy,
+                         "p50_ms": round(float(np.percentile(lat, 50)) * 1e3, 3),
+                         "p99_ms": round(float(np.percentile(lat, 99)) * 1e3, 3),
+                         "req_per_s": round(len(which) / wall, 2),
+                         "tflops": round(tot_flops / wall / 1e12, 3)}
+            log(f"serving {name} at load {load}: {out[name]}")
+        return out, rate
+
+    res, rate = measure(args.serve_load)
+    res["other_loads"] = {}
+    for load in (0.5, 0.95):
+        if load != args.serve_load:
+            r, _ = measure(load)
+            res["other_loads"][str(load)] = {k: {"p50_ms": v["p50_ms"], "p99_ms": v["p99_ms"]} for k, v in r.items()}
     res["arrival_rate_req_per_s"] = round(rate, 2)
     res["saturation_req_per_s"] = round(sat, 2)
     res["requests"] = len(which)
