@@ -111,10 +111,13 @@ tnc_status tnc_net_create(tnc_ctx ctx, int32_t n_tensors, const int32_t* ranks,
                           const int32_t* open_labels, const void* const* host_data,
                           tnc_in in, tnc_net* out);
 /* Replace leaf `tensor`'s values (same shape), e.g. a new bitstring's
- * projectors.  Synchronous host-to-device copy. */
+ * projectors.  Synchronous host-to-device copy.  Plans of the network see
+ * the new values from their next run on (cached permuted copies are
+ * refreshed then); replacing a leaf while runs of its network are in flight
+ * is a race. */
 tnc_status tnc_net_set_tensor(tnc_net net, int32_t tensor, const void* host_data, tnc_in in);
 /* Replace leaf `tensor`'s values from a device pointer (complex64, stored
- * order).  Device-to-device copy on the context's stream. */
+ * order).  Device-to-device copy on the context's stream (same rules). */
 tnc_status tnc_net_set_tensor_device(tnc_net net, int32_t tensor, const void* dev_data);
 tnc_status tnc_net_destroy(tnc_net net);
 
@@ -144,6 +147,10 @@ typedef struct {
   int32_t n_permutes;            /* leaves permuted before use                 */
   int32_t n_permuted_stores;     /* steps whose output order interleaves M, N  */
   int32_t n_result;              /* elements of the result tensor              */
+  int32_t n_cached_leaves;       /* leaves without a per-chunk base offset and
+                                    up to 2^22 elements: permuted once into the
+                                    plan's leaf cache (refreshed when their
+                                    data is replaced), not in every run       */
 } tnc_plan_info;
 tnc_status tnc_plan_get_info(tnc_plan plan, tnc_plan_info* out);
 

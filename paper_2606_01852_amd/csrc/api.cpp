@@ -176,6 +176,7 @@ tnc_status tnc_ctx_sync(tnc_ctx ctx) {
 static void upload_leaf(Net& net, int t, const void* host, tnc_in in) {
   DeviceBuf& d = net.leaf[t];
   const int64_t n = net.numel[t];
+  ++net.version[t];
   if (!d.ptr) d.alloc(static_cast<size_t>(n) * 8);
   if (in == TNC_IN_C64) {
     check_hip(hipMemcpy(d.ptr, host, n * 8, hipMemcpyHostToDevice), "leaf upload");
@@ -215,6 +216,7 @@ tnc_status tnc_net_create(tnc_ctx ctx, int32_t n_tensors, const int32_t* ranks, 
   net.open.assign(open_labels, open_labels + n_open);
   validate_net(net);
   net.leaf.resize(n_tensors);
+  net.version.assign(n_tensors, 0);
   if (!ctx->c->host_only) {
     if (!host_data) fail(TNC_E_ARG, "host_data is NULL");
     set_device(*ctx->c);
@@ -246,6 +248,7 @@ tnc_status tnc_net_set_tensor_device(tnc_net net, int32_t tensor, const void* de
   set_device(*n.ctx);
   check_hip(hipMemcpyAsync(n.leaf[tensor].ptr, dev_data, n.numel[tensor] * 8, hipMemcpyDeviceToDevice, n.ctx->stream),
             "leaf copy");
+  ++n.version[tensor];
   TNC_CATCH
 }
 
@@ -329,6 +332,7 @@ tnc_status tnc_plan_get_info(tnc_plan plan, tnc_plan_info* out) {
   info.n_steps = static_cast<int32_t>(p.pairs.size());
   info.n_permutes = c0.n_permutes;
   info.n_permuted_stores = c0.n_perm_stores;
+  info.n_cached_leaves = c0.n_cached;
   info.n_result = static_cast<int32_t>(std::min<int64_t>(c0.R, INT32_MAX));
   *out = info;
   TNC_CATCH

@@ -93,6 +93,7 @@ struct Net {
   std::vector<int> user_batch;            // batch labels in open order
   std::vector<int64_t> numel;             // per leaf
   std::vector<DeviceBuf> leaf;            // resident complex64 leaves
+  std::vector<uint64_t> version;          // per leaf, bumped when its data is replaced
   std::vector<std::vector<int64_t>> stride;  // per leaf, per stored mode
   ~Net();
 };
@@ -121,6 +122,10 @@ struct LeafPrep {
   std::vector<std::pair<int, int64_t>> fixed;  // (sliced label, stride) fixed per chunk
   PermuteHost perm;
   int step = -1;             // step that consumes it
+  // a leaf with no per-chunk base offset is permuted once into the chunk
+  // plan's leaf cache (refreshed when its data is replaced), not per run
+  bool cached = false;
+  int64_t cache_off = -1;
 };
 
 struct StepPlan {
@@ -178,6 +183,10 @@ struct ChunkPlan {
   // device side (built on first use)
   bool materialized = false;
   DeviceBuf blob;
+  DeviceBuf leaf_cache;                      // permuted copies of the cached leaves
+  int64_t cache_bytes = 0;
+  int n_cached = 0;
+  std::vector<uint64_t> cache_version;       // leaf versions the cache holds (empty: not filled)
   std::vector<uint8_t> host_blob;
   double flops = 0, bytes = 0, transpose_bytes = 0;
   int64_t max_tensor = 0;

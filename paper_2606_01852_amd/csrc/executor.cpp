@@ -14,6 +14,11 @@ namespace {
 
 int64_t align_up(int64_t x) { return (x + 255) / 256 * 256; }
 
+// Device address of cached leaf t inside the chunk plan's leaf cache.
+float2* cached_leaf(const ChunkPlan& cp, int t) {
+  return reinterpret_cast<float2*>(static_cast<char*>(cp.leaf_cache.ptr) + cp.leaf[t].cache_off);
+}
+
 template <typename T>
 int64_t put(std::vector<uint8_t>& blob, const std::vector<T>& v) {
   if (v.empty()) return -1;
@@ -57,6 +62,7 @@ void materialize(const Net& net, ChunkPlan& cp, hipStream_t stream) {
     }
   }
   if (!blob.empty()) cp.blob.alloc(blob.size());
+  if (cp.cache_bytes) cp.leaf_cache.alloc(static_cast<size_t>(cp.cache_bytes));
   char* base = static_cast<char*>(cp.blob.ptr);
   for (StepPlan& sp : cp.steps) {
     if (sp.offM.empty()) continue;
@@ -82,6 +88,10 @@ void materialize(const Net& net, ChunkPlan& cp, hipStream_t stream) {
           if (id < n && cp.leaf[id].direct) {
             rel = 0;
             return net.leaf[id].ptr;
+          }
+          if (id < n && cp.leaf[id].cached) {
+            rel = 0;
+            return cached_leaf(cp, id);
           }
           rel = 1;
           return reinterpret_cast<void*>(static_cast<intptr_t>(cp.buf_off[cp.tensor_buf[id]]));
@@ -144,10 +154,61 @@ std::vector<std::pair<int, int64_t>> decompose(const Plan& plan, int64_t first, 
 
 namespace {
 
+// Launch the gather-permute of leaf t into `out`; `bd` points at its
+// per-chunk base offset on the device (null: none).
+hipError_t launch_leaf_prep(const Net& net, const ChunkPlan& cp, int t, float2* out, const int64_t* bd,
+                            hipStream_t stream) {
+  const LeafPrep& lp = cp.leaf[t];
+  const float2* in = static_cast<const float2*>(net.leaf[t].ptr);
+  const char* blob = static_cast<const char*>(cp.blob.ptr);
+  if (lp.perm.tiled) {
+    const PermuteHost& p = lp.perm;
+    PermuteDesc d{};
+    d.in = in;
+    d.out = out;
+    d.tile_in = reinterpret_cast<const int32_t*>(blob + p.off_tile_in);
+    d.tile_slot_r = reinterpret_cast<const int32_t*>(blob + p.off_slot_r);
+    d.tile_out = reinterpret_cast<const int32_t*>(blob + p.off_tile_out);
+    d.tile_slot_w = reinterpret_cast<const int32_t*>(blob + p.off_slot_w);
+    d.lo_tab = reinterpret_cast<const int64_t*>(blob + p.off_lo);
+    d.hi_tab = reinterpret_cast<const int64_t*>(blob + p.off_hi);
+    d.n_tiles = p.n_tiles;
+    d.L = p.L;
+    d.T = p.T;
+    d.slots = p.slots;
+    d.base = 0;
+    d.base_dev = bd;
+    return launch_permute(d, stream);
+  }
+  GatherDesc g = lp.perm.plain;
+  g.in = in;
+  g.out = out;
+  g.base = 0;
+  g.base_dev = bd;
+  return launch_gather(g, stream);
+}
+
+// (Re)fill the leaf cache when it is empty or a cached leaf's data has been
+// replaced since.  Synchronous on `stream`; the context's stream is drained
+// first so that leaf copies enqueued there have landed.
+void refresh_leaf_cache(const Net& net, ChunkPlan& cp, hipStream_t stream) {
+  if (!cp.n_cached) return;
+  bool stale = cp.cache_version.empty();
+  for (int t = 0; t < net.n_tensors && !stale; ++t)
+    if (cp.leaf[t].cached && cp.cache_version[t] != net.version[t]) stale = true;
+  if (!stale) return;
+  if (stream != net.ctx->stream) check_hip(hipStreamSynchronize(net.ctx->stream), "leaf cache");
+  for (int t = 0; t < net.n_tensors; ++t)
+    if (cp.leaf[t].cached) check_hip(launch_leaf_prep(net, cp, t, cached_leaf(cp, t), nullptr, stream), "leaf cache");
+  check_hip(hipStreamSynchronize(stream), "leaf cache");
+  cp.cache_version = net.version;
+}
+
 ChunkPlan& ready(Plan& plan, int j, hipStream_t stream) {
   std::lock_guard<std::mutex> g(plan.mu);
   if (!plan.chunks[j]) plan.chunks[j] = build_chunk(plan, j);
   materialize(*plan.net, *plan.chunks[j], stream);
+  refresh_leaf_cache(*plan.net, *plan.chunks[j], stream);
   return *plan.chunks[j];
 }
 
@@ -186,40 +247,15 @@ void enqueue_chunk(Plan& plan, ChunkPlan& cp, const RunArgs& a, const int64_t* b
   const char* blob = static_cast<const char*>(cp.blob.ptr);
   auto ptr = [&](int id) -> float2* {
     if (id < n && cp.leaf[id].direct) return static_cast<float2*>(net.leaf[id].ptr);
+    if (id < n && cp.leaf[id].cached) return cached_leaf(cp, id);
     if (id == cp.root_id && a.direct_out) return a.direct_out;
     return reinterpret_cast<float2*>(a.arena + cp.buf_off[cp.tensor_buf[id]]);
   };
   auto prep = [&](int t) {
     const LeafPrep& lp = cp.leaf[t];
-    const float2* in = static_cast<const float2*>(net.leaf[t].ptr);
     float2* out = ptr(t);
     const int64_t* bd = lp.base_slot >= 0 ? bases + lp.base_slot : nullptr;
-    if (lp.perm.tiled) {
-      const PermuteHost& p = lp.perm;
-      PermuteDesc d{};
-      d.in = in;
-      d.out = out;
-      d.tile_in = reinterpret_cast<const int32_t*>(blob + p.off_tile_in);
-      d.tile_slot_r = reinterpret_cast<const int32_t*>(blob + p.off_slot_r);
-      d.tile_out = reinterpret_cast<const int32_t*>(blob + p.off_tile_out);
-      d.tile_slot_w = reinterpret_cast<const int32_t*>(blob + p.off_slot_w);
-      d.lo_tab = reinterpret_cast<const int64_t*>(blob + p.off_lo);
-      d.hi_tab = reinterpret_cast<const int64_t*>(blob + p.off_hi);
-      d.n_tiles = p.n_tiles;
-      d.L = p.L;
-      d.T = p.T;
-      d.slots = p.slots;
-      d.base = 0;
-      d.base_dev = bd;
-      L.run(t_prep, stream, [&] { return launch_permute(d, stream); });
-    } else {
-      GatherDesc g = lp.perm.plain;
-      g.in = in;
-      g.out = out;
-      g.base = 0;
-      g.base_dev = bd;
-      L.run(t_prep, stream, [&] { return launch_gather(g, stream); });
-    }
+    L.run(t_prep, stream, [&] { return launch_leaf_prep(net, cp, t, out, bd, stream); });
   };
   if (ns == 0 && !cp.leaf[0].direct) prep(0);
   const Form form = plan.form == TNC_GEMM_3M ? Form::M3 : Form::M4;

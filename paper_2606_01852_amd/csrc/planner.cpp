@@ -441,8 +441,19 @@ std::unique_ptr<ChunkPlan> build_chunk(const Plan& plan, int j) {
     cp->transpose_bytes += 16.0 * static_cast<double>(cp->numel[t]);
   }
   cp->n_base_slots = n_slots;
+  // leaves without a per-chunk base offset are the same in every run: up to
+  // 2^22 elements each they are permuted once into the leaf cache
+  constexpr int64_t kCacheLeafElems = int64_t{1} << 22;
+  for (int t = 0; t < n && ns > 0; ++t) {
+    LeafPrep& lp = cp->leaf[t];
+    if (lp.direct || lp.base_slot >= 0 || cp->numel[t] > kCacheLeafElems) continue;
+    lp.cached = true;
+    lp.cache_off = cp->cache_bytes;
+    cp->cache_bytes += align_up(cp->numel[t] * 8);
+    cp->n_cached++;
+  }
   for (int t = 0; t < n; ++t)
-    if (!cp->leaf[t].direct && ns > 0) cp->steps[cp->leaf[t].step].preps.push_back(t);
+    if (!cp->leaf[t].direct && !cp->leaf[t].cached && ns > 0) cp->steps[cp->leaf[t].step].preps.push_back(t);
 
   // steps: sizes, batch strides, kernel, output offsets
   for (int s = 0; s < ns; ++s) {
@@ -611,7 +622,7 @@ std::unique_ptr<ChunkPlan> build_chunk(const Plan& plan, int j) {
   };
   std::vector<Iv> ivs;
   for (int t = 0; t < n; ++t) {
-    if (cp->leaf[t].direct) continue;
+    if (cp->leaf[t].direct || cp->leaf[t].cached) continue;
     const int tt = ns > 0 ? when(cp->leaf[t].step) : 0;
     ivs.push_back({align_up(cp->numel[t] * 8), tt, t == root ? t_end : tt, t});
   }

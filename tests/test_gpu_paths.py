@@ -364,3 +364,40 @@ def test_split_k_and_transposed_launches(ctx, dims, batch, prec, form):
         assert err <= max(1e-5, 4 * 2.0 ** -16)
     else:
         assert err <= 1e-5
+
+
+def test_replaced_leaves_reach_cached_copies(ctx):
+    """Leaves are permuted once into the plan's cache; replacing one (host or
+    device copy) refreshes the cached copy before the next run, eager and
+    from a captured graph."""
+    from workloads.circuits import haar_unitary
+    circ = configs.circuit12_circuit()
+    net = circuit_network(circ)
+    path = greedy_path(net)
+    tn = tnc.Network(ctx, net.labels, net.extents, net.open, net.c64().leaves)
+    eager = tnc.Plan(tn, path.pairs)
+    graph = tnc.Plan(tn, path.pairs)
+    tnc.tnc_plan_set_graph(graph.handle, True)
+    assert eager.info.n_cached_leaves > 0
+    rng = np.random.Generator(np.random.PCG64(31))
+    two_q = [g for g, (qs, _) in enumerate(circ.gates) if len(qs) == 2]
+    gates = list(circ.gates)
+    for rep, how in enumerate(("initial", "host", "device", "host")):
+        if how != "initial":
+            g = two_q[int(rng.integers(0, len(two_q)))]
+            u = haar_unitary(rng, 4)
+            gates[g] = (gates[g][0], u)
+            t = circ.n_qubits + g                      # leaf of gate g
+            vals = np.ascontiguousarray(u.reshape(2, 2, 2, 2)).astype(np.complex64)
+            if how == "host":
+                tnc.tnc_net_set_tensor(tn.handle, t, vals)
+            else:
+                dev = torch.from_numpy(vals.reshape(-1)).cuda()
+                tnc.tnc_net_set_tensor_device(tn.handle, t, dev.data_ptr())
+                torch.cuda.synchronize()
+        sv = osv.amplitude(circ.n_qubits, [(qs, u.astype(np.complex64).astype(np.complex128)) for qs, u in gates],
+                           circ.bitstring)
+        for p in (eager, graph):
+            z = complex(p.contract()[0])
+            print(f"{how}: {abs(z - sv) / abs(sv):.2e}", flush=True)
+            assert abs(z - sv) <= 1e-5 * abs(sv), (rep, how)
