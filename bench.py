@@ -59,6 +59,7 @@ def parse():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--workload", choices=["pair30", "circuit40", "serve", "small"], default="pair30")
     ap.add_argument("--no-serve", action="store_true", help="skip the serving-latency leg")
+    ap.add_argument("--no-forms", action="store_true", help="skip timing the 3M and split-bf16 forms")
     ap.add_argument("--serve-pool", type=int, default=24)
     ap.add_argument("--serve-requests", type=int, default=600)
     ap.add_argument("--serve-load", type=float, default=0.8)
@@ -452,6 +453,38 @@ def main():
                     "permute_ms_per_launch": round(perm_ms / max(perm_n, 1), 3),
                     "batch_gemm_ms": round(bgemm_ms / max(bgemm_n, 1), 3)},
     }
+    if not args.no_forms and args.form == "4M" and args.prec == "c64":
+        # the same step in the other GEMM forms (same inputs, same arena)
+        res["other_forms"] = {}
+        for name, fprec, fform, fpeak in (("3M", tnc.PREC_C64, tnc.GEMM_3M, PEAK_FP32_MFMA),
+                                          ("bf16x3", tnc.PREC_BF16X3, tnc.GEMM_4M, PEAK_BF16_MFMA / 3)):
+            pa = tnc.Plan(tn_a, path_a.pairs, (), fprec, fform)
+            pb = tnc.Plan(tn_b, path_b.pairs, (), fprec, fform)
+            tnc.tnc_plan_autotune(pa.handle)
+            tnc.tnc_plan_autotune(pb.handle)
+
+            def fstep():
+                tnc.tnc_contract_async(pa.handle, 0, 1, out_a.data_ptr(), tnc.OUT_C64)
+                tnc.tnc_contract_async(pb.handle, 0, 1, out_b.data_ptr(), tnc.OUT_C64)
+
+            fstep()
+            torch.cuda.synchronize()
+            tnc.tnc_plan_set_profile(pa.handle, True)
+            t1 = time.perf_counter()
+            for _ in range(2):
+                fstep()
+            torch.cuda.synchronize()
+            fdt = (time.perf_counter() - t1) / 2
+            g_ms, g_n = tnc.tnc_plan_get_profile(pa.handle, 0)
+            g_s = g_ms / max(g_n, 1) / 1e3
+            res["other_forms"][name] = {
+                "tflops": round(flops_step / fdt / 1e12, 3), "ms_per_step": round(fdt * 1e3, 3),
+                "gemm_tflops": round(plan_a.info.flops_per_slice / g_s / 1e12, 3),
+                "gemm_frac_of_form_peak": round(plan_a.info.flops_per_slice / g_s / 1e12 / fpeak, 4),
+                "variant": tnc.tnc_plan_get_step(pa.handle, 0).variant}
+            log(f"form {name}: {res['other_forms'][name]}")
+            pa.close()
+            pb.close()
     if args.probe_copy:
         src = torch.empty(4 << 30, dtype=torch.uint8, device=dev)
         dst = torch.empty_like(src)

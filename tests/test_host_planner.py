@@ -276,7 +276,10 @@ def test_slice_invariant_work_runs_once_per_batch(hctx):
     executed = 0
     for s, (a, b) in enumerate(path.pairs):
         holds.append(holds[a] | holds[b])
-        executed += 8 * ops[s] * int(np.prod([net.extents[l] for l in holds[n + s]]))
+        mult = int(np.prod([net.extents[l] for l in holds[n + s]]))
+        executed += 8 * ops[s] * mult
+        bs = tnc.tnc_plan_get_batch_step(plan.handle, s)     # the batched step's own view
+        assert bs.h == mult and (bs.m, bs.n, bs.k) == (plan.step(s).m, plan.step(s).n, plan.step(s).k), s
     assert info.chunk_flops == executed
     # per-slice accounting would be c times the per-slice count; hoisting saves
     per_slice = c * info.flops_per_slice
