@@ -3,8 +3,8 @@
 // cgemm_small: one thread per output element, k looped in order; used for
 // the many tiny steps of circuit networks (m, n or k of a few elements).
 // cgemm_dot:   one wave64 per output element for long reductions with few
-// outputs (k large, m*n tiny); the 64 partial sums are combined by a fixed
-// butterfly, so the summation error grows like k/64 + 6 roundings, not k.
+// outputs (k large, m*n tiny); 4 x 64 partial sums are combined by a fixed
+// tree, so the summation error grows like k/256 + 8 roundings, not k.
 // Both honour the split-bf16 precision with the same products as the MFMA
 // kernel (hi*hi and the two cross products accumulated separately).
 #include "gemm_common.hpp"
@@ -59,28 +59,14 @@ __global__ __launch_bounds__(256) void cgemm_small(GemmDesc d) {
 }
 
 // Long reductions with few outputs (k large, m*n tiny): one wave64 per output
-// element; lanes stride over k with coalesced reads and the 64 partial sums
-// are combined by a fixed butterfly, so the summation error grows like
-// (k/64 + 6) roundings instead of k.
+// element; lanes stride over k with coalesced reads, each lane keeping four
+// independent partial sums (four loads per operand in flight), and the
+// 64 x 4 partial sums are combined by a fixed tree, so the summation error
+// grows like (k/256 + 8) roundings instead of k.
 template <bool SPLIT>
-__global__ __launch_bounds__(256) void cgemm_dot(GemmDesc d) {
-  const int lane = threadIdx.x & 63;
-  const int64_t mn = d.m * d.n;
-  const int64_t total = d.h * mn;
-  const int64_t out = static_cast<int64_t>(blockIdx.x) * 4 + (threadIdx.x >> 6);
-  if (out >= total) return;  // uniform per wave
-  const int64_t b = out / mn;
-  const int64_t r = out - b * mn;
-  const int64_t i = r / d.n;
-  const int64_t j = r - i * d.n;
-  int64_t oa, ob;
-  batch_offsets(d, b, oa, ob);
-  const float2* a = d.A + oa + i * row_stride(d);
-  const float2* bb = d.B + ob + j * row_stride(d);
+struct DotAcc {
   float cr = 0.f, ci = 0.f, crx = 0.f, cix = 0.f;
-  for (int64_t l = lane; l < d.k; l += 64) {
-    const float2 x = a[l];
-    const float2 y = bb[l];
+  __device__ __forceinline__ void add(float2 x, float2 y) {
     if constexpr (SPLIT) {
       float h1, x1, h2, x2, h3, x3, h4, x4;
       split_mul(x.x, y.x, h1, x1);
@@ -100,16 +86,54 @@ __global__ __launch_bounds__(256) void cgemm_dot(GemmDesc d) {
       ci = fmaf(x.y, y.x, ci);
     }
   }
-  cr += crx;
-  ci += cix;
+};
+
+template <bool SPLIT>
+__global__ __launch_bounds__(256) void cgemm_dot(GemmDesc d) {
+  const int lane = threadIdx.x & 63;
+  const int64_t mn = d.m * d.n;
+  const int64_t total = d.h * mn;
+  const int64_t out = static_cast<int64_t>(blockIdx.x) * 4 + (threadIdx.x >> 6);
+  if (out >= total) return;  // uniform per wave
+  const int64_t b = out / mn;
+  const int64_t r = out - b * mn;
+  const int64_t i = r / d.n;
+  const int64_t j = r - i * d.n;
+  int64_t oa, ob;
+  batch_offsets(d, b, oa, ob);
+  const float2* a = d.A + oa + i * row_stride(d);
+  const float2* bb = d.B + ob + j * row_stride(d);
+  DotAcc<SPLIT> acc[4];
+  int64_t l = lane;
+  for (; l + 192 < d.k; l += 256) {
+    float2 x[4], y[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      x[u] = a[l + 64 * u];
+      y[u] = bb[l + 64 * u];
+    }
+#pragma unroll
+    for (int u = 0; u < 4; ++u) acc[u].add(x[u], y[u]);
+  }
+#pragma unroll
+  for (int u = 0; u < 3; ++u)  // the last < 256 elements
+    if (l + 64 * u < d.k) acc[u].add(a[l + 64 * u], bb[l + 64 * u]);
+  float cr[4], ci[4];
+#pragma unroll
+  for (int u = 0; u < 4; ++u) {
+    cr[u] = acc[u].cr + acc[u].crx;
+    ci[u] = acc[u].ci + acc[u].cix;
+  }
+  float sr = (cr[0] + cr[1]) + (cr[2] + cr[3]);
+  float si = (ci[0] + ci[1]) + (ci[2] + ci[3]);
 #pragma unroll
   for (int off = 32; off > 0; off >>= 1) {
-    cr += __shfl_xor(cr, off, 64);
-    ci += __shfl_xor(ci, off, 64);
+    sr += __shfl_xor(sr, off, 64);
+    si += __shfl_xor(si, off, 64);
   }
   if (lane == 0) {
     const int64_t c = b * mn + (d.offM ? d.offM[i] + d.offN[j] : r);
-    d.C[c] = make_float2(cr, ci);
+    d.C[c] = make_float2(sr, si);
   }
 }
 
