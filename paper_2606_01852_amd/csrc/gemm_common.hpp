@@ -29,24 +29,10 @@ __device__ __forceinline__ void batch_offsets(const GemmDesc& d, int64_t b, int6
   }
 }
 
-// Round-to-nearest-even float32 -> bf16, as the float32 bit pattern with the
-// low 16 bits cleared.
-__device__ __forceinline__ uint32_t bf16_rne_bits(float x) {
-  uint32_t u = __float_as_uint(x);
-  u += 0x7FFFu + ((u >> 16) & 1u);
-  return u & 0xFFFF0000u;
-}
-
-__device__ __forceinline__ float bf16_round(float x) { return __uint_as_float(bf16_rne_bits(x)); }
-
-// hi/lo bf16 halves (as 16-bit patterns) of one float32: hi = rne(x),
-// lo = rne(x - hi); x - hi is exact in float32.
-__device__ __forceinline__ void split_bf16(float x, uint16_t& hi, uint16_t& lo) {
-  const uint32_t h = bf16_rne_bits(x);
-  const float r = x - __uint_as_float(h);
-  hi = static_cast<uint16_t>(h >> 16);
-  lo = static_cast<uint16_t>(bf16_rne_bits(r) >> 16);
-}
+// Round-to-nearest-even float32 -> bf16 -> float32 (the hardware
+// conversion; bit-identical to clearing the low 16 bits after adding
+// 0x7FFF + the lowest kept bit).
+__device__ __forceinline__ float bf16_round(float x) { return static_cast<float>(static_cast<__bf16>(x)); }
 
 // a*b with both factors split: hi = a_hi b_hi, cross = a_hi b_lo + a_lo b_hi
 // (each product exact in float32).

@@ -57,7 +57,10 @@ struct Shape {
   static constexpr int BNC = 32 * WN;  // complex columns of C per workgroup
   static constexpr int NT = 64 * WM * WN;
   static constexpr size_t lds_f32 = 2 * (BM + BNC) * PITCH * sizeof(float);
-  static constexpr size_t lds_bf16 = 2 * 2 * (BM + BNC) * SPITCH * sizeof(uint16_t);
+  // bf16 stage: A hi/lo planes of BM rows, B' hi/lo planes of 2*BNC real
+  // columns (the 4M real operand, built at staging), two buffers
+  static constexpr int BF16_STAGE = (2 * BM + 4 * BNC) * SPITCH;  // uint16 per buffer
+  static constexpr size_t lds_bf16 = 2 * BF16_STAGE * sizeof(uint16_t);
 };
 
 struct TileCoord {
@@ -148,15 +151,24 @@ struct Stage {
   }
 
   // bf16 planes: the hi and lo halves of every float go to separate planes
-  // at the same position (real k index = 2 * complex k + re/im).
+  // (hardware round-to-nearest-even conversion; lo = rne(x - hi), x - hi
+  // exact in float32).
+  __device__ __forceinline__ static void split(float x, uint16_t& hi, uint16_t& lo) {
+    const __bf16 h = static_cast<__bf16>(x);
+    const __bf16 l = static_cast<__bf16>(x - static_cast<float>(h));
+    hi = __builtin_bit_cast(uint16_t, h);
+    lo = __builtin_bit_cast(uint16_t, l);
+  }
+
+  // A: the staged floats in place (real k index = 2 * complex k + re/im).
   __device__ __forceinline__ static void put_split(uint16_t* hi, uint16_t* lo, int idx, const f4& v) {
     const int pos = (idx / PER_ROW) * SPITCH + 2 * (idx % PER_ROW) * VW;
     uint16_t h[4], l[4];
-    split_bf16(v.x, h[0], l[0]);
-    split_bf16(v.y, h[1], l[1]);
-    split_bf16(v.z, h[2], l[2]);
-    split_bf16(v.w, h[3], l[3]);
+    split(v.x, h[0], l[0]);
+    split(v.y, h[1], l[1]);
     if constexpr (VW == 2) {
+      split(v.z, h[2], l[2]);
+      split(v.w, h[3], l[3]);
       *reinterpret_cast<uint2*>(hi + pos) =
           make_uint2(h[0] | (uint32_t(h[1]) << 16), h[2] | (uint32_t(h[3]) << 16));
       *reinterpret_cast<uint2*>(lo + pos) =
@@ -167,12 +179,40 @@ struct Stage {
     }
   }
 
+  // B: complex column c becomes the real columns 2c = (br, -bi, ...) and
+  // 2c + 1 = (bi, br, ...) of the 4M operand; negating a bf16 flips its
+  // sign bit, which commutes with the split.
+  __device__ __forceinline__ static void put_split_b(uint16_t* hi, uint16_t* lo, int idx, const f4& v) {
+    const int c = idx / PER_ROW;
+    const int pos0 = (2 * c) * SPITCH + 2 * (idx % PER_ROW) * VW;
+    const int pos1 = pos0 + SPITCH;
+    constexpr uint32_t S = 0x8000u;
+    uint16_t h[4], l[4];
+    split(v.x, h[0], l[0]);
+    split(v.y, h[1], l[1]);
+    if constexpr (VW == 2) {
+      split(v.z, h[2], l[2]);
+      split(v.w, h[3], l[3]);
+      *reinterpret_cast<uint2*>(hi + pos0) =
+          make_uint2(h[0] | ((h[1] ^ S) << 16), h[2] | ((h[3] ^ S) << 16));
+      *reinterpret_cast<uint2*>(lo + pos0) =
+          make_uint2(l[0] | ((l[1] ^ S) << 16), l[2] | ((l[3] ^ S) << 16));
+      *reinterpret_cast<uint2*>(hi + pos1) = make_uint2(h[1] | (uint32_t(h[0]) << 16), h[3] | (uint32_t(h[2]) << 16));
+      *reinterpret_cast<uint2*>(lo + pos1) = make_uint2(l[1] | (uint32_t(l[0]) << 16), l[3] | (uint32_t(l[2]) << 16));
+    } else {
+      *reinterpret_cast<uint32_t*>(hi + pos0) = h[0] | ((h[1] ^ S) << 16);
+      *reinterpret_cast<uint32_t*>(lo + pos0) = l[0] | ((l[1] ^ S) << 16);
+      *reinterpret_cast<uint32_t*>(hi + pos1) = h[1] | (uint32_t(h[0]) << 16);
+      *reinterpret_cast<uint32_t*>(lo + pos1) = l[1] | (uint32_t(l[0]) << 16);
+    }
+  }
+
   __device__ __forceinline__ void store_split(uint16_t* Ah, uint16_t* Al, uint16_t* Bh, uint16_t* Bl,
                                               int tid) const {
 #pragma unroll
     for (int i = 0; i < A_LOADS; ++i) put_split(Ah, Al, tid + S::NT * i, a[i]);
 #pragma unroll
-    for (int i = 0; i < B_LOADS; ++i) put_split(Bh, Bl, tid + S::NT * i, b[i]);
+    for (int i = 0; i < B_LOADS; ++i) put_split_b(Bh, Bl, tid + S::NT * i, b[i]);
   }
 };
 
@@ -333,26 +373,26 @@ struct OpsBF16x3 {
   }
 
   __device__ __forceinline__ static const uint16_t* planes(const char* lds, int buf) {
-    return reinterpret_cast<const uint16_t*>(lds) + buf * 2 * (S::BM + S::BNC) * SPITCH;
+    return reinterpret_cast<const uint16_t*>(lds) + buf * S::BF16_STAGE;
   }
 
   __device__ __forceinline__ void stage(const Stage<WM, WN, VW>& st, char* lds, int buf, int tid) const {
     uint16_t* Ah = const_cast<uint16_t*>(planes(lds, buf));
     uint16_t* Al = Ah + S::BM * SPITCH;
     uint16_t* Bh = Al + S::BM * SPITCH;
-    uint16_t* Bl = Bh + S::BNC * SPITCH;
+    uint16_t* Bl = Bh + 2 * S::BNC * SPITCH;
     st.store_split(Ah, Al, Bh, Bl, tid);
   }
 
   // bf16 MFMA 32x32x16: lane (h, r) supplies 8 consecutive K values of row
-  // r; the stage's 32 real k are two sub-steps, lane half h taking
-  // k = 8 * (2s + h) .. +7.
+  // r (A) or real column r (B'); the stage's 32 real k are two sub-steps,
+  // lane half h taking k = 8 * (2s + h) .. +7.
   __device__ __forceinline__ void compute(const char* lds, int buf, int wm, int wn, int lane) {
     const uint16_t* Ah = planes(lds, buf);
     const uint16_t* Al = Ah + S::BM * SPITCH;
     const uint16_t* Bh = Al + S::BM * SPITCH;
-    const uint16_t* Bl = Bh + S::BNC * SPITCH;
-    const int h = lane >> 5, l32 = lane & 31, p = lane & 1;
+    const uint16_t* Bl = Bh + 2 * S::BNC * SPITCH;
+    const int h = lane >> 5, l32 = lane & 31;
 #pragma unroll
     for (int s = 0; s < 2; ++s) {
       const int koff = 8 * (2 * s + h);
@@ -365,21 +405,9 @@ struct OpsBF16x3 {
       }
 #pragma unroll
       for (int j = 0; j < 2; ++j) {
-        const int row = wn * 32 + j * 16 + (l32 >> 1);
-        const s8v rh = *reinterpret_cast<const s8v*>(Bh + row * SPITCH + koff);
-        const s8v rl = *reinterpret_cast<const s8v*>(Bl + row * SPITCH + koff);
-        s8v th, tl;
-#pragma unroll
-        for (int e = 0; e < 8; e += 2) {
-          // pair (re, im) of one complex k; p = 0 -> (re, -im), p = 1 -> (im, re)
-          const short hre = rh[e], him = rh[e + 1], lre = rl[e], lim = rl[e + 1];
-          th[e] = p ? him : hre;
-          th[e + 1] = p ? hre : static_cast<short>(him ^ static_cast<short>(0x8000));
-          tl[e] = p ? lim : lre;
-          tl[e + 1] = p ? lre : static_cast<short>(lim ^ static_cast<short>(0x8000));
-        }
-        bh[j] = th;
-        bl[j] = tl;
+        const int row = 2 * (wn * 32 + j * 16) + l32;  // real column of B'
+        bh[j] = *reinterpret_cast<const s8v*>(Bh + row * SPITCH + koff);
+        bl[j] = *reinterpret_cast<const s8v*>(Bl + row * SPITCH + koff);
       }
 #pragma unroll
       for (int i = 0; i < 2; ++i)
@@ -491,6 +519,9 @@ hipError_t launch_variant(const GemmDesc& d, int variant, bool bf16, hipStream_t
     const size_t lds = bf16 ? Shape<2, 2>::lds_bf16 : Shape<2, 2>::lds_f32;
     return d.offM ? launch_one<OpsT, 2, 2, 1, true>(d, lds, s) : launch_one<OpsT, 2, 2, 1, false>(d, lds, s);
   }
+  // split precision: the 4x4-wave shape would need all 160 KiB of LDS and
+  // spill its accumulators, so it runs as 2x4
+  if (bf16 && variant == 3) variant = 2;
   switch (variant) {
     case 0: return launch_shape<OpsT, 2, 2>(d, bf16, s);
     case 1: return launch_shape<OpsT, 4, 2>(d, bf16, s);
