@@ -463,7 +463,7 @@ __device__ __forceinline__ void main_loop(const GemmDesc& d, const float2* A, co
 }
 
 template <template <int, int, int> class OpsT, int WM, int WN, int VW, bool PERM>
-__global__ __launch_bounds__(64 * WM * WN) void cgemm_mfma(GemmDesc d, int64_t tiles_m, int64_t tiles_n,
+__global__ __launch_bounds__(64 * WM * WN, (WM * WN <= 4) ? 2 : 1) void cgemm_mfma(GemmDesc d, int64_t tiles_m, int64_t tiles_n,
                                                            int64_t total) {
   using S = Shape<WM, WN>;
   extern __shared__ __attribute__((aligned(16))) char lds[];
