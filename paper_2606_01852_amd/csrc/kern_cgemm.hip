@@ -35,6 +35,8 @@
 // remapped so that consecutive tiles land on one XCD (the hardware deals
 // workgroups round-robin over the 8 XCDs, each with its own L2) and tiles
 // sweep N in groups of 8 M-tiles for L2 reuse.
+#include <atomic>
+
 #include "gemm_common.hpp"
 
 namespace tnc {
@@ -494,12 +496,19 @@ hipError_t launch_one(const GemmDesc& d, size_t lds, hipStream_t s) {
   // one workgroup per tile; the grid's work-items must fit 32 bits
   if (total * S::NT > 0xFFFFFFFFLL) return hipErrorInvalidValue;
   auto kern = cgemm_mfma<OpsT, WM, WN, VW, PERM>;
-  static bool attr_set = false;
-  if (!attr_set && lds > 65536) {
-    const hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(kern),
-                                             hipFuncAttributeMaxDynamicSharedMemorySize, static_cast<int>(lds));
-    if (e != hipSuccess) return e;
-    attr_set = true;
+  // LDS above 64 KiB must be allowed per kernel, once per device
+  static std::atomic<uint64_t> attr_set{0};
+  if (lds > 65536) {
+    int dev = 0;
+    const hipError_t ge = hipGetDevice(&dev);
+    if (ge != hipSuccess) return ge;
+    const uint64_t bit = uint64_t{1} << (dev & 63);
+    if (!(attr_set.load(std::memory_order_acquire) & bit)) {
+      const hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(kern),
+                                               hipFuncAttributeMaxDynamicSharedMemorySize, static_cast<int>(lds));
+      if (e != hipSuccess) return e;
+      attr_set.fetch_or(bit, std::memory_order_acq_rel);
+    }
   }
   hipLaunchKernelGGL(kern, dim3(static_cast<unsigned>(total)), dim3(S::NT), lds, s, d, tiles_m, tiles_n, total);
   return hipGetLastError();
