@@ -168,3 +168,41 @@ def test_heavy_lane_keeps_results(served):
         tnc.tnc_serve_stop(ctx.handle)
         for i, out in outs:
             assert np.array_equal(out.view(np.uint64), alone[i].view(np.uint64)), (heavy, slots, i)
+
+
+def test_serving_pool_requests_match_the_state_vector():
+    """Requests of the serving benchmark's own pool (the 20-qubit entries,
+    1 to 1024 slices) served concurrently in complex64 and in split-bf16x3,
+    against the brute-force state vector: 1e-5 for complex64, the split
+    bound max(1e-5, 4 * 2^-16 * depth of the tree) for bf16x3."""
+    from oracle import statevector as osv
+    from workloads import configs
+    arena = torch.empty(8 << 30, dtype=torch.uint8, device="cuda")
+    ctx = tnc.Context(0, arena_bytes=arena.numel(), arena_ptr=arena.data_ptr())
+    entries = [i for i in range(24) if np.prod(configs.serve_request_spec(i)[:2]) <= 20]
+    assert len(entries) >= 3
+    jobs = []
+    for i in entries:
+        circ, net, path, _ = configs.serve_request_circuit(i)
+        gates = [(qs, u.astype(np.complex64).astype(np.complex128)) for qs, u in circ.gates]
+        ref = osv.amplitude(circ.n_qubits, gates, circ.bitstring)
+        depth = [0] * net.n_leaves
+        for a, b in path.pairs:
+            depth.append(1 + max(depth[int(a)], depth[int(b)]))
+        tn = tnc.Network(ctx, net.labels, net.extents, net.open, net.c64().leaves)
+        for prec in (tnc.PREC_C64, tnc.PREC_BF16X3):
+            plan = tnc.Plan(tn, path.pairs, path.sliced, prec)
+            tol = 1e-5 if prec == tnc.PREC_C64 else max(1e-5, 4 * 2.0 ** -16 * depth[-1])
+            jobs.append((i, prec, plan, tn, ref, tol, np.zeros(1, dtype=np.complex128)))
+    tnc.tnc_serve_start(ctx.handle, 8, 256)
+    ids = [tnc.tnc_submit(ctx.handle, j[2].handle, 0, j[2].info.n_slices, j[6]) for j in jobs]
+    for rid in ids:
+        tnc.tnc_wait(ctx.handle, rid)
+    tnc.tnc_serve_stop(ctx.handle)
+    for i, prec, plan, _, ref, tol, out in jobs:
+        err = abs(complex(out[0]) - ref) / abs(ref)
+        print(f"pool entry {i} ({plan.info.n_slices} slices, prec {prec}): err {err:.2e} (tol {tol:.1e})", flush=True)
+        assert err <= tol, (i, prec)
+    for j in jobs:
+        j[2].close()
+    ctx.close()

@@ -75,10 +75,10 @@ def serve_request_spec(i: int):
     return rows, cols, depth, j, prec
 
 
-def serve_request(i: int, max_log2_ops: float = 43.0) -> Tuple[Network, Path, int]:
-    """Network, path (with 4**j slices) and precision flag of pool entry i.
-    Slices are chosen greedily; the request's planned operation count is
-    capped at 2**max_log2_ops by lowering the depth."""
+def serve_request_circuit(i: int, max_log2_ops: float = 43.0):
+    """(circuit, network, path with 4**j slices, precision flag) of pool
+    entry i.  Slices are chosen greedily; the request's planned operation
+    count is capped at 2**max_log2_ops by lowering the depth."""
     rows, cols, depth, j, prec = serve_request_spec(i)
     while True:
         circ = random_circuit(rows, cols, depth, seed=5000 + i)
@@ -88,5 +88,11 @@ def serve_request(i: int, max_log2_ops: float = 43.0) -> Tuple[Network, Path, in
         big, ops = path_cost(net, p.pairs, sl)
         n_sl = 4 ** j
         if np.log2(max(ops, 1) * n_sl * 8) <= max_log2_ops or depth <= 4:
-            return net, Path(p.pairs, sl), prec
+            return circ, net, Path(p.pairs, sl), prec
         depth -= 1
+
+
+def serve_request(i: int, max_log2_ops: float = 43.0) -> Tuple[Network, Path, int]:
+    """Network, path (with 4**j slices) and precision flag of pool entry i."""
+    _, net, path, prec = serve_request_circuit(i, max_log2_ops)
+    return net, path, prec
