@@ -357,7 +357,7 @@ def bench_circuit40(args):
 def main():
     args = parse()
     if args.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU; multi-GPU execution is not part of it",
+        print(json.dumps({"error": "this executor runs on one GPU; multi-GPU execution is not implemented",
                           "n_gpus": args.gpus}))
         sys.exit(2)
     if args.workload == "circuit40":

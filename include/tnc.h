@@ -202,8 +202,8 @@ tnc_status tnc_plan_set_profile(tnc_plan plan, int32_t enable);
 tnc_status tnc_plan_get_profile(tnc_plan plan, int32_t step, double* ms, int64_t* launches);
 
 /* ---------------------------------------------------------------- distribution plan
- * Offline planning of a multi-GPU execution (Sec. IV-B), on the host; this
- * build executes nothing across GPUs.  Steps whose operands or output reach
+ * Offline planning of a multi-GPU execution (Sec. IV-B), on the host; the
+ * library executes nothing across GPUs.  Steps whose operands or output reach
  * large_bytes start use-chains (the tensor's consumers up the tree, to the
  * last large step); along each chain a DP over the distributed modes
  * (Eq. (4) prefixes, tracked by label) chooses keep or redistribute per
