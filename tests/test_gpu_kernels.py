@@ -88,6 +88,8 @@ GEMM_SHAPES = [
     (1, 1, 1, 1),
     (3, 1, 1, 5000),       # long-K dot kernel
     (2, 4, 8, 1024),       # long-K dot kernel, several outputs
+    (8, 16, 200, 512),     # skinny: MFMA on padded tiles (m < 64)
+    (4, 40, 9, 2048),      # skinny in both m and n
 ]
 
 
@@ -137,8 +139,9 @@ def split_emulated_gemm(A, B):
     return (prod3(ar, br) - prod3(ai, bi)) + 1j * (prod3(ar, bi) + prod3(ai, br))
 
 
-@pytest.mark.parametrize("shape", [(1, 256, 128, 64), (2, 130, 70, 33), (3, 20, 5, 7), (2, 2, 3, 700)],
-                         ids=["tiles", "ragged", "small", "dot"])
+@pytest.mark.parametrize("shape", [(1, 256, 128, 64), (2, 130, 70, 33), (3, 20, 5, 7), (2, 2, 3, 700),
+                                   (8, 16, 200, 512)],
+                         ids=["tiles", "ragged", "small", "dot", "skinny"])
 def test_cgemm_bf16x3_matches_split_emulation(ctx, shape):
     h, m, n, k = shape
     rng = np.random.Generator(np.random.PCG64(m + n + k))
