@@ -395,6 +395,8 @@ def main():
     arena_bytes = max(sizes) + (64 << 20)
     arena = torch.empty(arena_bytes, dtype=torch.uint8, device=dev)
     ctx = tnc.Context(0, arena_bytes=arena_bytes, arena_ptr=arena.data_ptr(), stream=stream.cuda_stream)
+    hw = tnc.tnc_device_calibrate(ctx.handle)
+    log(f"measured ceilings: FP32 MFMA {hw.flops_per_s / 1e12:.1f} TFLOP/s, copy {hw.hbm_bytes_per_s / 1e9:.0f} GB/s")
     log("uploading leaves")
     tn_a = tnc.Network(ctx, net_a.labels, net_a.extents, net_a.open, net_a.leaves)
     tn_b = tnc.Network(ctx, net_b.labels, net_b.extents, net_b.open, net_b.leaves)
@@ -459,6 +461,11 @@ def main():
                    "pct_fp32_mfma_peak": round(100 * value / PEAK_FP32_MFMA, 1)},
         "roofline": {"bound": "mfma", "achieved": round(achieved, 3), "peak": round(peak, 1),
                      "unit": "TFLOP/s", "frac": round(achieved / peak, 4), "traffic": GEMM_TRAFFIC_BYTES},
+        "measured_ceilings": {"fp32_mfma_tflops": round(hw.flops_per_s / 1e12, 2),
+                              "copy_gbs": round(hw.hbm_bytes_per_s / 1e9, 1),
+                              "gemm_frac_of_measured_mfma": round(achieved / (hw.flops_per_s / 1e12), 4),
+                              "permute_frac_of_measured_copy": round(perm_gbs / (hw.hbm_bytes_per_s / 1e9), 4)
+                              if perm_gbs else None},
         "kernels": {"gemm_ms": round(gemm_avg_s * 1e3, 3),
                     "permute_ms_per_launch": round(perm_ms / max(perm_n, 1), 3),
                     "batch_gemm_ms": round(bgemm_ms / max(bgemm_n, 1), 3)},

@@ -650,6 +650,52 @@ tnc_status tnc_permute(tnc_ctx ctx, const void* in, void* out, int32_t rank, con
   TNC_CATCH
 }
 
+tnc_status tnc_device_calibrate(tnc_ctx ctx, tnc_dist_hw* hw) {
+  TNC_TRY
+  if (!ctx || !hw) fail(TNC_E_ARG, "ctx/hw is NULL");
+  Ctx& c = *ctx->c;
+  if (c.host_only) fail(TNC_E_ARG, "host-only context");
+  set_device(c);
+  check_hip(hipStreamSynchronize(c.stream), "stream synchronize");
+  int cus = 0;
+  check_hip(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, c.device), "device attribute");
+  const int blocks = 8 * std::max(cus, 1);
+  const int iters = 4000;
+  const int64_t copy_bytes = int64_t{512} << 20;
+  DeviceBuf sink, src, dst;
+  sink.alloc(static_cast<size_t>(blocks) * 256 * sizeof(float));
+  src.alloc(static_cast<size_t>(copy_bytes));
+  dst.alloc(static_cast<size_t>(copy_bytes));
+  check_hip(hipMemsetAsync(src.ptr, 0, static_cast<size_t>(copy_bytes), c.stream), "memset");
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  check_hip(hipEventCreate(&e0), "event");
+  check_hip(hipEventCreate(&e1), "event");
+  auto best_ms = [&](auto&& launch) {
+    float best = 1e30f;
+    for (int rep = 0; rep < 3; ++rep) {
+      check_hip(launch(), "calibration launch");  // warm-up
+      check_hip(hipEventRecord(e0, c.stream), "event");
+      check_hip(launch(), "calibration launch");
+      check_hip(hipEventRecord(e1, c.stream), "event");
+      check_hip(hipEventSynchronize(e1), "event");
+      float ms = 0.f;
+      check_hip(hipEventElapsedTime(&ms, e0, e1), "event");
+      best = std::min(best, ms);
+    }
+    return static_cast<double>(best);
+  };
+  const double mfma_ms =
+      best_ms([&] { return launch_mfma_rate(static_cast<float*>(sink.ptr), blocks, iters, c.stream); });
+  const double copy_ms = best_ms([&] { return launch_copy_rate(src.ptr, dst.ptr, copy_bytes, c.stream); });
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  // per wave and round: 8 MFMAs of 16 x 16 x 4 multiply-adds
+  const double flops = static_cast<double>(blocks) * 4 * iters * 8 * (16.0 * 16 * 4 * 2);
+  hw->flops_per_s = flops / (mfma_ms * 1e-3);
+  hw->hbm_bytes_per_s = 2.0 * static_cast<double>(copy_bytes) / (copy_ms * 1e-3);
+  TNC_CATCH
+}
+
 tnc_status tnc_batched_cgemm(tnc_ctx ctx, int64_t h, int64_t m, int64_t n, int64_t k, const void* A,
                              int64_t stride_a, const void* B, int64_t stride_b, void* C, tnc_prec prec,
                              tnc_cgemm form) {

@@ -89,6 +89,7 @@ _SIGS = {
     "tnc_plan_autotune": (C.c_int, [_P]),
     "tnc_plan_distribute": (C.c_int, [_P, C.c_int32, C.c_double, C.POINTER(DistHW), C.POINTER(DistStep),
                                       C.c_int32, _I32P, _DP, _DP]),
+    "tnc_device_calibrate": (C.c_int, [_P, C.POINTER(DistHW)]),
     "tnc_plan_set_profile": (C.c_int, [_P, C.c_int32]),
     "tnc_plan_get_profile": (C.c_int, [_P, C.c_int32, _DP, _I64P]),
     "tnc_contract": (C.c_int, [_P, C.c_int64, C.c_int64, _DP]),
@@ -244,6 +245,14 @@ def tnc_plan_get_order(plan: int, tensor_id: int) -> list:
 
 def tnc_plan_set_max_chunk(plan: int, max_chunk: int) -> None:
     _check(lib().tnc_plan_set_max_chunk(plan, max_chunk))
+
+
+def tnc_device_calibrate(ctx: int) -> DistHW:
+    """Measured FP32 MFMA rate (flops_per_s) and copy bandwidth
+    (hbm_bytes_per_s) of the context's device."""
+    hw = DistHW()
+    _check(lib().tnc_device_calibrate(ctx, C.byref(hw)))
+    return hw
 
 
 def tnc_plan_distribute(plan: int, n_gpus: int, large_bytes: float, hbm: float, flops: float, net: float,

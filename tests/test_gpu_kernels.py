@@ -209,3 +209,16 @@ def test_autotune_keeps_results_and_persists(ctx, tmp_path, monkeypatch):
     tn3 = tnc.Network(c3, net.labels, net.extents, net.open, net.c64().leaves)
     plan3 = tnc.Plan(tn3, path.pairs)
     assert tnc.tnc_plan_get_step(plan3.handle, 0).variant == v
+
+
+def test_device_calibration(ctx):
+    """The measured FP32 MFMA rate and copy bandwidth are plausible for the
+    device (they feed the distribution cost model and the bench's measured
+    ceilings)."""
+    hw = tnc.tnc_device_calibrate(ctx.handle)
+    print(f"calibration: FP32 MFMA {hw.flops_per_s / 1e12:.1f} TFLOP/s, copy {hw.hbm_bytes_per_s / 1e9:.0f} GB/s",
+          flush=True)
+    assert 20e12 < hw.flops_per_s < 400e12
+    assert 0.5e12 < hw.hbm_bytes_per_s < 20e12
+    with pytest.raises(tnc.TncError):
+        tnc.tnc_device_calibrate(tnc.Context(-1).handle)
