@@ -234,8 +234,8 @@ tnc_status tnc_plan_distribute(tnc_plan plan, int32_t n_gpus, double large_bytes
 /* Measure the context's device: hw->flops_per_s = the FP32 MFMA rate of a
  * max-rate loop (independent accumulator chains, all compute units, no
  * memory traffic), hw->hbm_bytes_per_s = bytes read + written per second by
- * a 16-byte-per-lane copy of 512 MiB (best of three after a warm-up each).
- * net_bytes_per_s and latency_s are left as they are.  Allocates 1 GiB of
+ * a 16-byte-per-lane copy of 2 GiB (best of three after a warm-up each).
+ * net_bytes_per_s and latency_s are left as they are.  Allocates 4 GiB of
  * device memory for the duration of the call; synchronous; TNC_E_ARG on a
  * host-only context. */
 tnc_status tnc_device_calibrate(tnc_ctx ctx, tnc_dist_hw* hw);

@@ -661,7 +661,7 @@ tnc_status tnc_device_calibrate(tnc_ctx ctx, tnc_dist_hw* hw) {
   check_hip(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, c.device), "device attribute");
   const int blocks = 8 * std::max(cus, 1);
   const int iters = 4000;
-  const int64_t copy_bytes = int64_t{512} << 20;
+  const int64_t copy_bytes = int64_t{2} << 30;  // far above the 256 MiB last-level cache
   DeviceBuf sink, src, dst;
   sink.alloc(static_cast<size_t>(blocks) * 256 * sizeof(float));
   src.alloc(static_cast<size_t>(copy_bytes));

@@ -220,5 +220,6 @@ def test_device_calibration(ctx):
           flush=True)
     assert 20e12 < hw.flops_per_s < 400e12
     assert 0.5e12 < hw.hbm_bytes_per_s < 20e12
+    host = tnc.Context(-1)     # keep the handle alive across the call
     with pytest.raises(tnc.TncError):
-        tnc.tnc_device_calibrate(tnc.Context(-1).handle)
+        tnc.tnc_device_calibrate(host.handle)
