@@ -8,7 +8,9 @@ Device pointers are passed as Python ints (e.g. ``tensor.data_ptr()``).
 """
 from __future__ import annotations
 
+import atexit
 import ctypes as C
+import weakref
 import os
 from typing import Optional, Sequence
 
@@ -354,12 +356,27 @@ def tnc_wait(ctx: int, rid: int) -> float:
 
 
 # ---------------------------------------------------------------- handle owners
+_live_contexts: "weakref.WeakSet" = weakref.WeakSet()
+
+
+@atexit.register
+def _close_live_contexts() -> None:
+    # stop servers (their worker threads call the HIP runtime) while the
+    # interpreter and the runtime are still alive
+    for c in list(_live_contexts):
+        try:
+            c.close()
+        except Exception:
+            pass
+
+
 class Context:
     """Owns a tnc_ctx.  ``device=-1`` plans on the host only."""
 
     def __init__(self, device: int = 0, arena_bytes: int = 0, arena_ptr: int = 0, stream: int = 0):
         self.device = device
         self.handle = tnc_ctx_create(device, arena_ptr, arena_bytes, stream)
+        _live_contexts.add(self)
 
     def sync(self) -> None:
         tnc_ctx_sync(self.handle)
