@@ -216,7 +216,8 @@ def serving_leg(args):
 def bench_small(args):
     """Latency-bound and mixed workloads: the 12-qubit circuit amplitude
     (153 tiny steps, 13 tree levels) step by step or level-grouped, eager or
-    replayed as a hipGraph; all 4096 amplitudes with the
+    replayed as a hipGraph; 64 bitstrings as one batched network; all 4096
+    amplitudes with the
     FP64 norm, and the closed 8x8 bond-4 grid in complex64, 3M and split-bf16."""
     import torch
 
@@ -251,6 +252,15 @@ def bench_small(args):
             out[key] = round(dt * 1e6, 1)
             p.close()
     circ = configs.circuit12_circuit()
+    from workloads.circuits import circuit_network_batched
+    bits = np.random.Generator(np.random.PCG64(64)).integers(0, 2, size=(64, circ.n_qubits))
+    netb = circuit_network_batched(circ, bits)
+    tnb = tnc.Network(ctx, netb.labels, netb.extents, netb.open, netb.c64().leaves)
+    pb = tnc.Plan(tnb, greedy_path(netb).pairs)
+    tnc.tnc_plan_set_graph(pb.handle, True)
+    dt = timed(lambda: pb.contract(), 100)
+    out["circuit12_64_bitstrings_one_plan_us"] = round(dt * 1e6, 1)
+    pb.close()
     netall = circuit_network(circ, open_qubits=range(12))
     pathall = greedy_path(netall)
     tna = tnc.Network(ctx, netall.labels, netall.extents, netall.open, netall.c64().leaves)

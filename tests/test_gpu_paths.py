@@ -401,3 +401,28 @@ def test_replaced_leaves_reach_cached_copies(ctx):
             z = complex(p.contract()[0])
             print(f"{how}: {abs(z - sv) / abs(sv):.2e}", flush=True)
             assert abs(z - sv) <= 1e-5 * abs(sv), (rep, how)
+
+
+def test_batched_bitstring_amplitudes(ctx):
+    """64 amplitude queries of one circuit as one network (a batch label on
+    the projector leaves): every step that sees a projector runs batched
+    over the 64 bitstrings in one launch; each amplitude matches the state
+    vector and the single-bitstring plan."""
+    from workloads.circuits import circuit_network_batched
+    circ = configs.circuit12_circuit()
+    rng = np.random.Generator(np.random.PCG64(64))
+    bits = rng.integers(0, 2, size=(64, circ.n_qubits))
+    net = circuit_network_batched(circ, bits)
+    path = greedy_path(net)
+    print("batched bitstrings", flush=True)
+    z, plan, _ = run(ctx, net, path)
+    gates = [(qs, u.astype(np.complex64).astype(np.complex128)) for qs, u in circ.gates]
+    sv = osv.run(circ.n_qubits, gates)
+    ref = np.array([sv[tuple(b)] for b in bits])
+    assert z.shape == (64,)
+    err = np.max(np.abs(z - ref)) / np.max(np.abs(ref))
+    print(f"64 amplitudes: max err / max |amp| {err:.2e}, steps with batch {sum(plan.step(s).h > 1 for s in range(plan.info.n_steps))}", flush=True)
+    assert rel_fro(z, ref) <= 1e-5 and err <= 1e-5
+    single = circuit_network(circ, bitstring=bits[5])
+    z5, _, _ = run(ctx, single, greedy_path(single))
+    assert abs(z[5] - z5) <= 1e-5 * abs(z5)

@@ -75,6 +75,21 @@ def test_circuit12_all_amplitudes_and_unitarity():
     assert abs(np.sum(np.abs(amps) ** 2) - 1.0) <= 1e-12
 
 
+def test_batched_bitstrings_match_the_state_vector():
+    """A batch label shared by all projector leaves (one network, B
+    amplitudes) gives the state vector's entries at the B bitstrings."""
+    from workloads.circuits import circuit_network_batched
+    circ = configs.circuit12_circuit()
+    rng = np.random.Generator(np.random.PCG64(3))
+    bits = rng.integers(0, 2, size=(16, circ.n_qubits))
+    net = circuit_network_batched(circ, bits)
+    amps = oc.contract(net, greedy_path(net), leaves=net.leaves)
+    sv = osv.run(circ.n_qubits, circ.gates)
+    ref = np.array([sv[tuple(b)] for b in bits])
+    assert amps.shape == (16,)
+    assert rel(amps, ref) <= 1e-12
+
+
 def test_order_independence_circuit_and_grid():
     net, p1 = configs.circuit12()
     p2 = random_greedy_path(net, seed=3)

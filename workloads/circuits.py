@@ -113,3 +113,23 @@ def circuit_network(circ: Circuit, bitstring: Optional[Sequence[int]] = None,
         labels.append((cur[q],))
     extents = np.full(next_label, 2, dtype=np.int64)
     return Network(leaves, labels, extents, tuple(cur[q] for q in open_qubits))
+
+
+def circuit_network_batched(circ: Circuit, bitstrings: np.ndarray) -> Network:
+    """Tensor network of the amplitudes <x_b| C |0...0> for a batch of B
+    bitstrings (array of shape (B, n_qubits)): one network whose projector
+    leaves share an extra open label of extent B (a batch label), so the
+    result is the vector of the B amplitudes."""
+    bits = np.asarray(bitstrings, dtype=np.int64)
+    B = bits.shape[0]
+    base = circuit_network(circ, open_qubits=range(circ.n_qubits))
+    batch = len(base.extents)
+    leaves = list(base.leaves)
+    labels = list(base.labels)
+    for q, wire in enumerate(base.open):
+        v = np.zeros((B, 2), dtype=np.complex128)
+        v[np.arange(B), bits[:, q]] = 1.0
+        leaves.append(v)
+        labels.append((batch, wire))
+    extents = np.concatenate([base.extents, np.array([B], dtype=np.int64)])
+    return Network(leaves, labels, extents, (batch,))
