@@ -90,11 +90,31 @@ __device__ __forceinline__ TileCoord map_tile(int64_t tiles_m, int64_t tiles_n, 
   return tc;
 }
 
-// Global -> register staging of one K stage (VW complex per load).
-template <int WM, int WN, int VW>
+// Global -> register staging of one K stage (VW complex per load).  With
+// SWZ the rows are dealt to the 8-lane groups in a permuted order within
+// each block of 8 rows, so that the two groups of a 16-lane 8-byte LDS store
+// cycle hit disjoint banks (rows 80 bytes apart: A rows 4 apart, B' rows 4
+// apart = complex columns 2 apart); the data layout itself is unchanged.
+template <int WM, int WN, int VW, bool SWZ = false>
 struct Stage {
   using S = Shape<WM, WN>;
   static constexpr int PER_ROW = BKC / VW;
+  __device__ __forceinline__ static int row_a(int idx) {
+    const int g = idx / PER_ROW;
+    if constexpr (SWZ && VW == 2) {
+      constexpr int p[8] = {0, 4, 1, 5, 2, 6, 3, 7};
+      return (g & ~7) | p[g & 7];
+    }
+    return g;
+  }
+  __device__ __forceinline__ static int row_b(int idx) {
+    const int g = idx / PER_ROW;
+    if constexpr (SWZ && VW == 2) {
+      constexpr int p[8] = {0, 2, 1, 3, 4, 6, 5, 7};
+      return (g & ~7) | p[g & 7];
+    }
+    return g;
+  }
   static constexpr int A_LOADS = S::BM * PER_ROW / S::NT;
   static constexpr int B_LOADS = S::BNC * PER_ROW / S::NT;
   static_assert(A_LOADS >= 1 && A_LOADS * S::NT == S::BM * PER_ROW, "A staging must tile evenly");
@@ -126,17 +146,17 @@ struct Stage {
 #pragma unroll
     for (int i = 0; i < A_LOADS; ++i) {
       const int idx = tid + S::NT * i;
-      a[i] = fetch<CHECK>(A, row0 + idx / PER_ROW, kk + (idx % PER_ROW) * VW, m, k, ld);
+      a[i] = fetch<CHECK>(A, row0 + row_a(idx), kk + (idx % PER_ROW) * VW, m, k, ld);
     }
 #pragma unroll
     for (int i = 0; i < B_LOADS; ++i) {
       const int idx = tid + S::NT * i;
-      b[i] = fetch<CHECK>(B, col0 + idx / PER_ROW, kk + (idx % PER_ROW) * VW, n, k, ld);
+      b[i] = fetch<CHECK>(B, col0 + row_b(idx), kk + (idx % PER_ROW) * VW, n, k, ld);
     }
   }
 
-  __device__ __forceinline__ static void put_f32(float* base, int idx, const f4& v) {
-    float* p = base + (idx / PER_ROW) * PITCH + 2 * (idx % PER_ROW) * VW;
+  __device__ __forceinline__ static void put_f32(float* base, int row, int idx, const f4& v) {
+    float* p = base + row * PITCH + 2 * (idx % PER_ROW) * VW;
     if constexpr (VW == 2) {
       *reinterpret_cast<f4*>(p) = v;
     } else {
@@ -147,9 +167,9 @@ struct Stage {
 
   __device__ __forceinline__ void store_f32(float* As, float* Bs, int tid) const {
 #pragma unroll
-    for (int i = 0; i < A_LOADS; ++i) put_f32(As, tid + S::NT * i, a[i]);
+    for (int i = 0; i < A_LOADS; ++i) put_f32(As, row_a(tid + S::NT * i), tid + S::NT * i, a[i]);
 #pragma unroll
-    for (int i = 0; i < B_LOADS; ++i) put_f32(Bs, tid + S::NT * i, b[i]);
+    for (int i = 0; i < B_LOADS; ++i) put_f32(Bs, row_b(tid + S::NT * i), tid + S::NT * i, b[i]);
   }
 
   // bf16 planes: the hi and lo halves of every float go to separate planes
@@ -164,7 +184,7 @@ struct Stage {
 
   // A: the staged floats in place (real k index = 2 * complex k + re/im).
   __device__ __forceinline__ static void put_split(uint16_t* hi, uint16_t* lo, int idx, const f4& v) {
-    const int pos = (idx / PER_ROW) * SPITCH + 2 * (idx % PER_ROW) * VW;
+    const int pos = row_a(idx) * SPITCH + 2 * (idx % PER_ROW) * VW;
     uint16_t h[4], l[4];
     split(v.x, h[0], l[0]);
     split(v.y, h[1], l[1]);
@@ -185,7 +205,7 @@ struct Stage {
   // 2c + 1 = (bi, br, ...) of the 4M operand; negating a bf16 flips its
   // sign bit, which commutes with the split.
   __device__ __forceinline__ static void put_split_b(uint16_t* hi, uint16_t* lo, int idx, const f4& v) {
-    const int c = idx / PER_ROW;
+    const int c = row_b(idx);
     const int pos0 = (2 * c) * SPITCH + 2 * (idx % PER_ROW) * VW;
     const int pos1 = pos0 + SPITCH;
     constexpr uint32_t S = 0x8000u;
@@ -226,6 +246,7 @@ __device__ __forceinline__ int64_t c_index(const GemmDesc& d, bool perm, int64_t
 template <int WM, int WN, int VW>
 struct Ops4M {
   using S = Shape<WM, WN>;
+  static constexpr bool kSwizzle = false;
   f16v acc[2][2];
 
   __device__ __forceinline__ void init() {
@@ -237,7 +258,8 @@ struct Ops4M {
         for (int v = 0; v < 16; ++v) acc[i][j][v] = 0.f;
   }
 
-  __device__ __forceinline__ void stage(const Stage<WM, WN, VW>& st, char* lds, int buf, int tid) const {
+  template <class St>
+  __device__ __forceinline__ void stage(const St& st, char* lds, int buf, int tid) const {
     float* As = reinterpret_cast<float*>(lds) + buf * (S::BM + S::BNC) * PITCH;
     st.store_f32(As, As + S::BM * PITCH, tid);
   }
@@ -299,6 +321,7 @@ struct Ops4M {
 template <int WM, int WN, int VW>
 struct Ops3M {
   using S = Shape<WM, WN>;
+  static constexpr bool kSwizzle = false;
   f16v t1[2], t2[2], t3[2];
 
   __device__ __forceinline__ void init() {
@@ -308,7 +331,8 @@ struct Ops3M {
       for (int v = 0; v < 16; ++v) t1[i][v] = t2[i][v] = t3[i][v] = 0.f;
   }
 
-  __device__ __forceinline__ void stage(const Stage<WM, WN, VW>& st, char* lds, int buf, int tid) const {
+  template <class St>
+  __device__ __forceinline__ void stage(const St& st, char* lds, int buf, int tid) const {
     float* As = reinterpret_cast<float*>(lds) + buf * (S::BM + S::BNC) * PITCH;
     st.store_f32(As, As + S::BM * PITCH, tid);
   }
@@ -360,6 +384,7 @@ struct Ops3M {
 template <int WM, int WN, int VW>
 struct OpsBF16x3 {
   using S = Shape<WM, WN>;
+  static constexpr bool kSwizzle = true;
   // hi*hi products and the two cross products accumulate separately: the
   // cross terms are ~2^-8 smaller, so their rounding barely adds to that of
   // the main sum
@@ -378,7 +403,8 @@ struct OpsBF16x3 {
     return reinterpret_cast<const uint16_t*>(lds) + buf * S::BF16_STAGE;
   }
 
-  __device__ __forceinline__ void stage(const Stage<WM, WN, VW>& st, char* lds, int buf, int tid) const {
+  template <class St>
+  __device__ __forceinline__ void stage(const St& st, char* lds, int buf, int tid) const {
     uint16_t* Ah = const_cast<uint16_t*>(planes(lds, buf));
     uint16_t* Al = Ah + S::BM * SPITCH;
     uint16_t* Bh = Al + S::BM * SPITCH;
@@ -451,7 +477,7 @@ __device__ __forceinline__ void main_loop(const GemmDesc& d, const float2* A, co
                                           char* lds, Ops& ops, int tid, int wm, int wn, int lane) {
   const int64_t nk = (d.k + BKC - 1) / BKC;
   const int64_t ld = row_stride(d);
-  Stage<WM, WN, VW> st;
+  Stage<WM, WN, VW, Ops::kSwizzle> st;
   st.template load<CHECK>(A, B, d.m, d.n, d.k, ld, tc.row0, tc.col0, 0, tid);
   ops.stage(st, lds, 0, tid);
   __syncthreads();
