@@ -173,59 +173,58 @@ struct Stage {
   }
 
   // bf16 planes: the hi and lo halves of every float go to separate planes
-  // (hardware round-to-nearest-even conversion; lo = rne(x - hi), x - hi
-  // exact in float32).
-  __device__ __forceinline__ static void split(float x, uint16_t& hi, uint16_t& lo) {
-    const __bf16 h = static_cast<__bf16>(x);
-    const __bf16 l = static_cast<__bf16>(x - static_cast<float>(h));
-    hi = __builtin_bit_cast(uint16_t, h);
-    lo = __builtin_bit_cast(uint16_t, l);
+  // (hardware round-to-nearest-even conversion of two floats at a time,
+  // packed [first | second << 16]; lo = rne(x - hi), x - hi exact in
+  // float32).
+  __device__ __forceinline__ static void split2(float x, float y, uint32_t& hi, uint32_t& lo) {
+    typedef float fv2 __attribute__((ext_vector_type(2)));
+    typedef __bf16 bv2 __attribute__((ext_vector_type(2)));
+    hi = __builtin_bit_cast(uint32_t, __builtin_convertvector((fv2){x, y}, bv2));
+    const float rx = x - __uint_as_float(hi << 16);
+    const float ry = y - __uint_as_float(hi & 0xFFFF0000u);
+    lo = __builtin_bit_cast(uint32_t, __builtin_convertvector((fv2){rx, ry}, bv2));
   }
 
   // A: the staged floats in place (real k index = 2 * complex k + re/im).
   __device__ __forceinline__ static void put_split(uint16_t* hi, uint16_t* lo, int idx, const f4& v) {
     const int pos = row_a(idx) * SPITCH + 2 * (idx % PER_ROW) * VW;
-    uint16_t h[4], l[4];
-    split(v.x, h[0], l[0]);
-    split(v.y, h[1], l[1]);
+    uint32_t h01, l01;
+    split2(v.x, v.y, h01, l01);
     if constexpr (VW == 2) {
-      split(v.z, h[2], l[2]);
-      split(v.w, h[3], l[3]);
-      *reinterpret_cast<uint2*>(hi + pos) =
-          make_uint2(h[0] | (uint32_t(h[1]) << 16), h[2] | (uint32_t(h[3]) << 16));
-      *reinterpret_cast<uint2*>(lo + pos) =
-          make_uint2(l[0] | (uint32_t(l[1]) << 16), l[2] | (uint32_t(l[3]) << 16));
+      uint32_t h23, l23;
+      split2(v.z, v.w, h23, l23);
+      *reinterpret_cast<uint2*>(hi + pos) = make_uint2(h01, h23);
+      *reinterpret_cast<uint2*>(lo + pos) = make_uint2(l01, l23);
     } else {
-      *reinterpret_cast<uint32_t*>(hi + pos) = h[0] | (uint32_t(h[1]) << 16);
-      *reinterpret_cast<uint32_t*>(lo + pos) = l[0] | (uint32_t(l[1]) << 16);
+      *reinterpret_cast<uint32_t*>(hi + pos) = h01;
+      *reinterpret_cast<uint32_t*>(lo + pos) = l01;
     }
   }
 
   // B: complex column c becomes the real columns 2c = (br, -bi, ...) and
   // 2c + 1 = (bi, br, ...) of the 4M operand; negating a bf16 flips its
-  // sign bit, which commutes with the split.
+  // sign bit (which commutes with the split), swapping re/im rotates the
+  // packed pair by 16 bits.
   __device__ __forceinline__ static void put_split_b(uint16_t* hi, uint16_t* lo, int idx, const f4& v) {
     const int c = row_b(idx);
     const int pos0 = (2 * c) * SPITCH + 2 * (idx % PER_ROW) * VW;
     const int pos1 = pos0 + SPITCH;
-    constexpr uint32_t S = 0x8000u;
-    uint16_t h[4], l[4];
-    split(v.x, h[0], l[0]);
-    split(v.y, h[1], l[1]);
+    constexpr uint32_t NEG_IM = 0x80000000u;
+    auto swap = [](uint32_t w) { return (w >> 16) | (w << 16); };
+    uint32_t h01, l01;
+    split2(v.x, v.y, h01, l01);
     if constexpr (VW == 2) {
-      split(v.z, h[2], l[2]);
-      split(v.w, h[3], l[3]);
-      *reinterpret_cast<uint2*>(hi + pos0) =
-          make_uint2(h[0] | ((h[1] ^ S) << 16), h[2] | ((h[3] ^ S) << 16));
-      *reinterpret_cast<uint2*>(lo + pos0) =
-          make_uint2(l[0] | ((l[1] ^ S) << 16), l[2] | ((l[3] ^ S) << 16));
-      *reinterpret_cast<uint2*>(hi + pos1) = make_uint2(h[1] | (uint32_t(h[0]) << 16), h[3] | (uint32_t(h[2]) << 16));
-      *reinterpret_cast<uint2*>(lo + pos1) = make_uint2(l[1] | (uint32_t(l[0]) << 16), l[3] | (uint32_t(l[2]) << 16));
+      uint32_t h23, l23;
+      split2(v.z, v.w, h23, l23);
+      *reinterpret_cast<uint2*>(hi + pos0) = make_uint2(h01 ^ NEG_IM, h23 ^ NEG_IM);
+      *reinterpret_cast<uint2*>(lo + pos0) = make_uint2(l01 ^ NEG_IM, l23 ^ NEG_IM);
+      *reinterpret_cast<uint2*>(hi + pos1) = make_uint2(swap(h01), swap(h23));
+      *reinterpret_cast<uint2*>(lo + pos1) = make_uint2(swap(l01), swap(l23));
     } else {
-      *reinterpret_cast<uint32_t*>(hi + pos0) = h[0] | ((h[1] ^ S) << 16);
-      *reinterpret_cast<uint32_t*>(lo + pos0) = l[0] | ((l[1] ^ S) << 16);
-      *reinterpret_cast<uint32_t*>(hi + pos1) = h[1] | (uint32_t(h[0]) << 16);
-      *reinterpret_cast<uint32_t*>(lo + pos1) = l[1] | (uint32_t(l[0]) << 16);
+      *reinterpret_cast<uint32_t*>(hi + pos0) = h01 ^ NEG_IM;
+      *reinterpret_cast<uint32_t*>(lo + pos0) = l01 ^ NEG_IM;
+      *reinterpret_cast<uint32_t*>(hi + pos1) = swap(h01);
+      *reinterpret_cast<uint32_t*>(lo + pos1) = swap(l01);
     }
   }
 
