@@ -2,9 +2,9 @@
 //
 // For every distinct step shape (precision, form, output store, h, m, n, k)
 // the candidate workgroup shapes are timed with HIP events on a stand-in
-// problem of the same m/n/k structure (the batch, then m, cut down so that a
-// trial takes a few milliseconds while keeping thousands of tiles), and the
-// fastest is kept.  Choices live in a per-context cache, optionally backed
+// problem of the same structure (K, then the batch, then m cut down so that
+// a trial stays near 2e13 FLOP while keeping the step's tile grid where
+// possible), and the fastest is kept.  Choices live in a per-context cache, optionally backed
 // by a text file (TNC_AUTOTUNE_CACHE) so later processes skip the timing.
 // Without tuning a shape-based default is used.
 #include <algorithm>
@@ -94,10 +94,13 @@ int tune_shape(Ctx& c, const TuneKey& key, int64_t k, bool perm_store) {
   const std::vector<int> cand = candidates(prec, form, key.h, key.m, key.n);
   int best = cand.front();
   if (cand.size() > 1) {
-    // stand-in problem: same m/n/k structure, batch then m reduced to keep a
-    // trial near 4e12 FLOP while it still has thousands of tiles
+    // stand-in problem near 2e13 FLOP (about 0.15 s): K is cut first (down
+    // to 2048, enough stages per tile to rank the shapes as at full K), which
+    // keeps the tile grid -- and so the wave quantization over the CUs that
+    // separates the shapes -- exactly that of the step; then the batch, then m
     int64_t h = key.h, m = key.m;
-    const double target = 4e12;
+    const double target = 2e13;
+    while (k > 2048 && k % 32 == 0 && 8.0 * h * m * key.n * k > target) k /= 2;
     while (h > 1 && 8.0 * h * m * key.n * k > target) h = (h + 1) / 2;
     while (m > 4096 && 8.0 * h * m * key.n * k > target) m = (m / 2 + 255) / 256 * 256;
     DeviceBuf a, b, cc, offm, offn;
