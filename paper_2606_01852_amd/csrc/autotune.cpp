@@ -1,4 +1,5 @@
-// Autotuner for the MFMA tile variant of each GEMM step.
+// Autotuner for the MFMA tile variant of each GEMM step (an extension; the
+// paper leaves each step's kernel to its library).
 //
 // For every distinct step shape (precision, form, output store, h, m, n, k)
 // the candidate workgroup shapes are timed with HIP events on a stand-in

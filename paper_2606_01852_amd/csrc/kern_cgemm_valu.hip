@@ -1,4 +1,6 @@
-// Complex GEMM kernels for shapes that do not fill MFMA tiles (VALU).
+// Complex GEMM kernels for shapes that do not fill MFMA tiles (VALU): the
+// same pairwise-contraction-as-GEMM of Sec. II-B for steps with few
+// outputs or tiny extents.
 //
 // cgemm_small: one thread per output element, k looped in order; used for
 // the many tiny steps of circuit networks (m, n or k of a few elements).

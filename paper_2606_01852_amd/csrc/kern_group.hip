@@ -1,5 +1,5 @@
 // Grouped launches: every small step (or leaf gather) of one level of the
-// contraction tree in a single kernel.
+// contraction tree (the SSA path of Sec. II-B) in a single kernel.
 //
 // Steps of one level depend only on lower levels, so they can run together.
 // Circuit and grid networks have hundreds of tiny steps but trees only

@@ -1,6 +1,9 @@
-// Host planner: network and path validation, GEMM-oriented mode reordering
-// (paper Sec. IV-A), per-step GEMM groups, permutation tables and the arena
-// memory plan.  Everything here runs on the host before any device work.
+// Host planner: network and path validation (labels join two tensors, or
+// one tensor and the open list: Sec. II-A), the per-step GEMM groups H/M/N/K
+// and their costs (Sec. II-B, Eq. (1)-(3)), GEMM-oriented mode reordering
+// (Sec. IV-A), slicing as batch labels (Sec. II-C), permutation tables and
+// the arena memory plan.  Everything here runs on the host before any
+// device work.
 #include <algorithm>
 #include <cstring>
 #include <numeric>

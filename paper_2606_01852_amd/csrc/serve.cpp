@@ -1,4 +1,5 @@
-// Continuous-batching server.
+// Continuous-batching server (an extension: the paper runs one
+// contraction at a time).
 //
 // Requests (plan, slice range, host output) are queued by tnc_submit.  A
 // request is admitted -- while others are still running -- as soon as a

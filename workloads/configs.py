@@ -1,5 +1,8 @@
 """The benchmark workloads as seeded synthetic inputs.
 
+They stand in for the paper's instances (random quantum circuits and
+many-body lattices, Sec. V), which are not used.
+
 Seeds follow ``PCG64(1000 + workload id)``; serving request ``i`` uses
 ``PCG64(5000 + i)``.
 
