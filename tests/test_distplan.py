@@ -110,3 +110,33 @@ def test_redistribution_goes_to_the_size_valley():
     chains = od.use_chains(labels, pairs, opn, ext, 8 * 2 ** 6)
     best = od.brute_force(chains[0], 8, hw)
     assert total == pytest.approx(best[0], rel=1e-12) and list(best[1]) == [False, True, False, False]
+
+
+def test_planner_on_a_circuit_workload():
+    """The 40-qubit circuit (no slicing) planned for 8 MI355X-like devices:
+    every use-chain of at most 12 equations gets the exhaustive optimum, and
+    every equation keeps or takes an Eq. (4) prefix of its output's modes."""
+    from workloads import configs
+    net, path = configs.circuit40(n_sliced=0)
+    plan = tnc.Plan(tnc.Network(tnc.Context(-1), net.labels, net.extents, net.open), path.pairs)
+    hw = dict(B_dev=5.4e12, F_dev=140e12, B_net=7 * 153e9, lat=10e-6)
+    large = 8.0 * 2 ** 24
+    steps, total, moved = tnc.tnc_plan_distribute(plan.handle, 8, large, hw["B_dev"], hw["F_dev"],
+                                                  hw["B_net"], hw["lat"])
+    assert steps and total > 0 and moved >= 0
+    chains = od.use_chains(net.labels, path.pairs, net.open, net.extents, large)
+    by_chain = {}
+    for s in steps:
+        by_chain.setdefault(s.chain, []).append(s)
+    feasible = [c for c in chains if od.prefix_modes(c[0]["order"], c[0]["ext"], 8)]
+    checked = 0
+    for (cid, recs), chain in zip(sorted(by_chain.items()), feasible):
+        assert [r.step for r in recs] == [e["step"] for e in chain]
+        if len(chain) <= 12:
+            best = od.brute_force(chain, 8, hw)
+            mine = od.evaluate(chain, 8, hw, [r.state == 2 for r in recs[1:]])
+            assert best is not None and mine == pytest.approx(best[0], rel=1e-9)
+            checked += 1
+    print(f"{len(by_chain)} chains, {len(steps)} equations, {checked} checked exhaustively; "
+          f"modelled {total:.3e} s, {moved / 1e9:.2f} GB redistributed")
+    assert checked >= 1
