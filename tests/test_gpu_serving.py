@@ -206,3 +206,34 @@ def test_serving_pool_requests_match_the_state_vector():
     for j in jobs:
         j[2].close()
     ctx.close()
+
+
+def test_served_graph_plans_match_eager(served):
+    """Plans that replay their chunks as captured hipGraphs give, served
+    concurrently, bitwise the eager result of the same plan alone."""
+    ctx, pool, nets, plans = served
+    order = list(range(len(plans)))
+    alone = {}
+    for i in order:
+        o, _ = run_all(ctx, plans, [i], 1)
+        alone[i] = o[i]
+    gplans = []
+    for i, (net, path) in enumerate(pool):
+        p = tnc.Plan(nets[i], path.pairs, path.sliced)
+        tnc.tnc_plan_set_graph(p.handle, True)
+        gplans.append(p)
+    rng = np.random.Generator(np.random.PCG64(8))
+    mixed = [int(x) for x in rng.permutation(order)] * 2
+    tnc.tnc_serve_start(ctx.handle, 6, 1024)
+    outs, ids = [], []
+    for i in mixed:
+        out = np.zeros(1, dtype=np.complex128)
+        outs.append((i, out))
+        ids.append(tnc.tnc_submit(ctx.handle, gplans[i].handle, 0, gplans[i].info.n_slices, out))
+    for rid in ids:
+        tnc.tnc_wait(ctx.handle, rid)
+    tnc.tnc_serve_stop(ctx.handle)
+    for i, out in outs:
+        assert np.array_equal(out.view(np.uint64), alone[i].view(np.uint64)), i
+    for p in gplans:
+        p.close()
