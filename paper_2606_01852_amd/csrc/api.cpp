@@ -134,6 +134,8 @@ tnc_status tnc_ctx_create(int device, void* arena, size_t arena_bytes, void* str
       c.own_arena = true;
     }
     load_tune_cache(c);
+    prepare_gemm_kernels();
+    (void)hipGetLastError();  // best effort: launches retry lazily
     if (stream) {
       c.stream = static_cast<hipStream_t>(stream);
     } else {

@@ -512,6 +512,24 @@ __global__ __launch_bounds__(64 * WM * WN, (WM * WN <= 4) ? 2 : 1) void cgemm_mf
   ops.store(d, PERM, tc, wm, wn, lane);
 }
 
+// LDS above 64 KiB must be allowed per kernel, once per device (done for
+// every instance when a context is created, so that no first launch inside
+// a graph capture has to do it).
+template <template <int, int, int> class OpsT, int WM, int WN, int VW, bool PERM>
+hipError_t ensure_lds(size_t lds) {
+  static std::atomic<uint64_t> attr_set{0};
+  if (lds <= 65536) return hipSuccess;
+  int dev = 0;
+  const hipError_t ge = hipGetDevice(&dev);
+  if (ge != hipSuccess) return ge;
+  const uint64_t bit = uint64_t{1} << (dev & 63);
+  if (attr_set.load(std::memory_order_acquire) & bit) return hipSuccess;
+  const hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(cgemm_mfma<OpsT, WM, WN, VW, PERM>),
+                                           hipFuncAttributeMaxDynamicSharedMemorySize, static_cast<int>(lds));
+  if (e == hipSuccess) attr_set.fetch_or(bit, std::memory_order_acq_rel);
+  return e;
+}
+
 template <template <int, int, int> class OpsT, int WM, int WN, int VW, bool PERM>
 hipError_t launch_one(const GemmDesc& d, size_t lds, hipStream_t s) {
   using S = Shape<WM, WN>;
@@ -520,23 +538,33 @@ hipError_t launch_one(const GemmDesc& d, size_t lds, hipStream_t s) {
   const int64_t total = tiles_m * tiles_n * d.h;
   // one workgroup per tile; the grid's work-items must fit 32 bits
   if (total * S::NT > 0xFFFFFFFFLL) return hipErrorInvalidValue;
-  auto kern = cgemm_mfma<OpsT, WM, WN, VW, PERM>;
-  // LDS above 64 KiB must be allowed per kernel, once per device
-  static std::atomic<uint64_t> attr_set{0};
-  if (lds > 65536) {
-    int dev = 0;
-    const hipError_t ge = hipGetDevice(&dev);
-    if (ge != hipSuccess) return ge;
-    const uint64_t bit = uint64_t{1} << (dev & 63);
-    if (!(attr_set.load(std::memory_order_acquire) & bit)) {
-      const hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(kern),
-                                               hipFuncAttributeMaxDynamicSharedMemorySize, static_cast<int>(lds));
-      if (e != hipSuccess) return e;
-      attr_set.fetch_or(bit, std::memory_order_acq_rel);
-    }
-  }
-  hipLaunchKernelGGL(kern, dim3(static_cast<unsigned>(total)), dim3(S::NT), lds, s, d, tiles_m, tiles_n, total);
+  const hipError_t e = ensure_lds<OpsT, WM, WN, VW, PERM>(lds);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL((cgemm_mfma<OpsT, WM, WN, VW, PERM>), dim3(static_cast<unsigned>(total)), dim3(S::NT), lds, s, d,
+                     tiles_m, tiles_n, total);
   return hipGetLastError();
+}
+
+template <template <int, int, int> class OpsT, int WM, int WN>
+void prepare_shape(bool bf16) {
+  using S = Shape<WM, WN>;
+  const size_t lds = bf16 ? S::lds_bf16 : S::lds_f32;
+  (void)ensure_lds<OpsT, WM, WN, 2, false>(lds);
+  (void)ensure_lds<OpsT, WM, WN, 2, true>(lds);
+}
+
+template <template <int, int, int> class OpsT>
+void prepare_ops(bool bf16) {
+  prepare_shape<OpsT, 2, 2>(bf16);
+  prepare_shape<OpsT, 4, 2>(bf16);
+  prepare_shape<OpsT, 2, 4>(bf16);
+  if (!bf16) prepare_shape<OpsT, 4, 4>(bf16);  // split precision runs 4x4 as 2x4
+  prepare_shape<OpsT, 1, 2>(bf16);
+  prepare_shape<OpsT, 2, 1>(bf16);
+  prepare_shape<OpsT, 1, 1>(bf16);
+  const size_t lds = bf16 ? Shape<2, 2>::lds_bf16 : Shape<2, 2>::lds_f32;  // odd-k path
+  (void)ensure_lds<OpsT, 2, 2, 1, false>(lds);
+  (void)ensure_lds<OpsT, 2, 2, 1, true>(lds);
 }
 
 template <template <int, int, int> class OpsT, int WM, int WN>
@@ -569,6 +597,12 @@ hipError_t launch_variant(const GemmDesc& d, int variant, bool bf16, hipStream_t
 }
 
 }  // namespace
+
+void prepare_gemm_kernels() {
+  prepare_ops<Ops4M>(false);
+  prepare_ops<Ops3M>(false);
+  prepare_ops<OpsBF16x3>(true);
+}
 
 void gemm_variant_tile(int variant, int* bm, int* bnc) {
   static const int wm[kGemmVariants] = {2, 4, 2, 4, 1, 2, 1};

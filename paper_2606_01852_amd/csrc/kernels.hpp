@@ -99,6 +99,9 @@ struct GatherDesc {
 // wave owning 64 x 32 complex of C (gemm_variant_tile gives the block tile).
 constexpr int kGemmVariants = 7;
 void gemm_variant_tile(int variant, int* bm, int* bnc);
+// Allow every MFMA kernel instance its LDS on the current device (best
+// effort; launches do it lazily as well).
+void prepare_gemm_kernels();
 hipError_t launch_gemm(const GemmDesc& d, GemmKernel kind, int variant, Form form, Prec prec, hipStream_t s);
 hipError_t launch_gemm_valu(const GemmDesc& d, GemmKernel kind, Prec prec, hipStream_t s);
 // Split-K epilogue: C[b, i, j] = sum_{p < S} P[((b * S + p) * m + i) * n + j],
