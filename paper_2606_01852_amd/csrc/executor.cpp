@@ -384,8 +384,14 @@ void run_plan(Plan& plan, const RunArgs& a) {
     fail(TNC_E_NOMEM, "run needs " + std::to_string(need) + " arena bytes, have " + std::to_string(a.arena_bytes));
   int64_t* cur_dev = reinterpret_cast<int64_t*>(a.arena + cur_off);
   int64_t* bases_dev = reinterpret_cast<int64_t*>(a.arena + bases_off);
-  check_hip(hipMemcpyAsync(bases_dev, bases.data(), bases.size() * sizeof(int64_t), hipMemcpyHostToDevice, a.stream),
-            "upload chunk bases");
+  // leaves with fixed sliced labels read their per-chunk offsets on the
+  // device; without any, nothing needs uploading (or copying per chunk)
+  bool any_bases = false;
+  for (auto& c : chunks) any_bases |= plan.chunks[c.first]->n_base_slots > 0;
+  if (any_bases)
+    check_hip(hipMemcpyAsync(bases_dev, bases.data(), bases.size() * sizeof(int64_t), hipMemcpyHostToDevice,
+                             a.stream),
+              "upload chunk bases");
 
   std::vector<std::pair<std::pair<hipEvent_t, hipEvent_t>, int>> ev;
   Launcher L{plan, plan.profile && !plan.graph ? &ev : nullptr};
@@ -393,9 +399,10 @@ void run_plan(Plan& plan, const RunArgs& a) {
     ChunkPlan& cp = ready(plan, chunks[c].first, a.stream);
     if (plan.graph) {
       hipGraphExec_t exec = chunk_graph(plan, cp, a, cur_dev);
-      check_hip(hipMemcpyAsync(cur_dev, bases_dev + c * slots, slots * sizeof(int64_t), hipMemcpyDeviceToDevice,
-                               a.stream),
-                "chunk bases");
+      if (cp.n_base_slots)
+        check_hip(hipMemcpyAsync(cur_dev, bases_dev + c * slots, slots * sizeof(int64_t), hipMemcpyDeviceToDevice,
+                                 a.stream),
+                  "chunk bases");
       check_hip(hipGraphLaunch(exec, a.stream), "graph launch");
     } else {
       enqueue_chunk(plan, cp, a, bases_dev + c * slots, a.stream, L);

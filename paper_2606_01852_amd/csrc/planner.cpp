@@ -565,8 +565,10 @@ std::unique_ptr<ChunkPlan> build_chunk(const Plan& plan, int j) {
     int64_t S = 1;
     if (sp.kind == GemmKernel::MFMA) {
       const int64_t t0 = sp.h * ((sp.lm + 127) / 128) * ((sp.ln + 63) / 64);
-      if (t0 < 512 && sp.k >= 2048)
-        while (t0 * S * 2 <= 2048 && sp.k / (S * 2) >= 512 && sp.k % (16 * S * 2) == 0) S *= 2;
+      // parts of at least 8 K stages (128 complex); a long K on few tiles is
+      // a long serial loop on few CUs, whatever the step's size
+      if (t0 < 512 && sp.k >= 256)
+        while (t0 * S * 2 <= 2048 && sp.k / (S * 2) >= 128 && sp.k % (16 * S * 2) == 0) S *= 2;
     } else if (sp.kind == GemmKernel::DOT) {
       const int64_t outs = sp.h * sp.lm * sp.ln;
       if (outs < 4096 && sp.k >= 8192)

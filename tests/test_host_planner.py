@@ -207,10 +207,16 @@ def test_memory_plan_and_chunking(hctx, grouping):
         lvl[n + s_] = 1 + max(lvl[a], lvl[b])
     when = (lambda s_: lvl[n + s_]) if grouping else (lambda s_: s_)
     end = when(ns - 1) + 1
+    # split-K partial products (S x the step's output) are live during their step
+    scratch = []
+    for q in range(ns):
+        st = plan.step(q)
+        scratch.append(8 * st.h * st.m * st.n * st.split if st.split > 1 else 0)
     lb = 0
     for t in range(end + 1):
         live = sum(size[n + q] for q in range(ns)
                    if when(q) <= t <= (when(consumer[n + q]) if n + q in consumer else end))
+        live += sum(scratch[q] for q in range(ns) if when(q) == t)
         lb = max(lb, live)
     assert lb <= info.peak_bytes <= 1.5 * lb + (1 << 20)
     assert info.max_chunk >= 64 and info.chunk_peak_bytes <= 8 << 30
@@ -288,10 +294,11 @@ def test_slice_invariant_work_runs_once_per_batch(hctx):
 
 
 @pytest.mark.parametrize("dims, batch, kernel, swapped, split", [
-    ((7, 16, 6), 1, 0, 0, 128),     # 128 x 64 output, k = 2^16: one tile, K cut 128 ways
+    ((7, 16, 6), 1, 0, 0, 512),     # 128 x 64 output, k = 2^16: one tile, K cut 512 ways
     ((2, 20, 1), 1, 2, 0, 1024),    # 4 x 2 outputs, k = 2^20: long dot, K cut 1024 ways
-    ((3, 10, 9), 64, 0, 1, 1),      # 64 x (8 x 512), k = 2^10: MFMA only transposed
-    ((10, 9, 8), 1, 0, 0, 1),       # ordinary tiles: neither
+    ((3, 10, 9), 64, 0, 1, 8),      # 64 x (8 x 512), k = 2^10: MFMA only transposed, 256 tiles: K cut 8 ways
+    ((10, 9, 8), 1, 0, 0, 4),       # 32 tiles, k = 512: K cut 4 ways (parts of 128)
+    ((12, 9, 10), 1, 0, 0, 1),      # 512 tiles of 128 x 64: no split
     ((2, 3, 2), 1, 1, 0, 1),        # tiny: one thread per output
 ])
 def test_launch_shape_decisions(hctx, dims, batch, kernel, swapped, split):
