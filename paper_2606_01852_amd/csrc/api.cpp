@@ -522,13 +522,22 @@ tnc_status tnc_contract(tnc_plan plan, int64_t first_slice, int64_t n_slices, do
   a.arena_bytes = c.arena_bytes;
   a.acc = static_cast<double2*>(p.acc.ptr);
   a.stream = c.stream;
-  check_hip(launch_fill_zero(a.acc, c0.R * 16, c.stream), "zero accumulator");
+  a.fresh_acc = true;
   run_plan(p, a);
-  std::vector<double> tmp(static_cast<size_t>(2 * c0.R));
-  check_hip(hipMemcpyAsync(tmp.data(), a.acc, c0.R * 16, hipMemcpyDeviceToHost, c.stream), "result copy");
+  // the result comes back through the plan's pinned staging buffer
+  const size_t res_bytes = static_cast<size_t>(c0.R) * 16;
+  if (p.host_res_bytes < res_bytes) {
+    if (p.host_res) (void)hipHostFree(p.host_res);
+    p.host_res = nullptr;
+    p.host_res_bytes = 0;
+    check_hip(hipHostMalloc(&p.host_res, res_bytes, hipHostMallocDefault), "pinned result buffer");
+    p.host_res_bytes = res_bytes;
+  }
+  check_hip(hipMemcpyAsync(p.host_res, a.acc, res_bytes, hipMemcpyDeviceToHost, c.stream), "result copy");
   check_hip(hipStreamSynchronize(c.stream), "stream synchronize");
+  const double* tmp = static_cast<const double*>(p.host_res);
   if (c0.result_perm.empty()) {
-    std::memcpy(out_c128, tmp.data(), tmp.size() * sizeof(double));
+    std::memcpy(out_c128, tmp, res_bytes);
   } else {
     for (int64_t u = 0; u < c0.R; ++u) {
       out_c128[2 * u] = tmp[2 * c0.result_perm[u]];
@@ -560,12 +569,12 @@ tnc_status tnc_contract_async(tnc_plan plan, int64_t first_slice, int64_t n_slic
     run_plan(p, a);
   } else if (out_type == TNC_OUT_C64) {
     a.acc = static_cast<double2*>(p.acc.ptr);
-    check_hip(launch_fill_zero(a.acc, c0.R * 16, c.stream), "zero accumulator");
+    a.fresh_acc = true;
     run_plan(p, a);
     check_hip(launch_c128_to_c64(a.acc, static_cast<float2*>(out_dev), c0.R, c.stream), "result conversion");
   } else if (out_type == TNC_OUT_C128) {
     a.acc = static_cast<double2*>(out_dev);
-    check_hip(launch_fill_zero(a.acc, c0.R * 16, c.stream), "zero accumulator");
+    a.fresh_acc = true;
     run_plan(p, a);
   } else {
     fail(TNC_E_ARG, "unknown output type");

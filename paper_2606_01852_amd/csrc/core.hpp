@@ -204,8 +204,10 @@ struct GraphKey {
   const void* acc;
   const void* out;
   const void* bases;
+  bool overwrite;
   bool operator<(const GraphKey& o) const {
     if (j != o.j) return j < o.j;
+    if (overwrite != o.overwrite) return overwrite < o.overwrite;
     if (arena != o.arena) return arena < o.arena;
     if (acc != o.acc) return acc < o.acc;
     if (out != o.out) return out < o.out;
@@ -224,6 +226,8 @@ struct Plan {
   tnc_cgemm form = TNC_GEMM_4M;
   int64_t max_chunk_user = -1;
   int grouping = 1;                   // level-grouped launches
+  void* host_res = nullptr;           // pinned staging of tnc_contract's result
+  size_t host_res_bytes = 0;
   int graph = 0;
   int profile = 0;
   int j_max = 0;
@@ -265,6 +269,7 @@ struct RunArgs {
   double2* acc = nullptr;       // device accumulator (n_result complex128)
   float2* direct_out = nullptr; // single-slice runs: the last step writes here, no reduction
   hipStream_t stream = nullptr;
+  bool fresh_acc = false;       // acc holds garbage: the first chunk's reduction overwrites it
 };
 void run_plan(Plan& plan, const RunArgs& a);
 // Arena bytes run_plan needs for a slice range (intermediates of the largest

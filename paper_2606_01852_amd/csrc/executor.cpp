@@ -238,8 +238,8 @@ namespace {
 
 // Enqueue one chunk: leaf permutations, one GEMM per step, the FP64
 // reduction of the root.  `bases` points at this chunk's leaf base offsets.
-void enqueue_chunk(Plan& plan, ChunkPlan& cp, const RunArgs& a, const int64_t* bases, hipStream_t stream,
-                   Launcher& L) {
+void enqueue_chunk(Plan& plan, ChunkPlan& cp, const RunArgs& a, const int64_t* bases, bool overwrite,
+                   hipStream_t stream, Launcher& L) {
   Net& net = *plan.net;
   const int n = net.n_tensors;
   const int ns = static_cast<int>(plan.pairs.size());
@@ -302,14 +302,14 @@ void enqueue_chunk(Plan& plan, ChunkPlan& cp, const RunArgs& a, const int64_t* b
   }
   if (!a.direct_out) {
     const float2* root = ptr(cp.root_id);
-    L.run(t_red, stream, [&] { return launch_reduce_fp64(root, a.acc, cp.hs, cp.R, stream); });
+    L.run(t_red, stream, [&] { return launch_reduce_fp64(root, a.acc, cp.hs, cp.R, overwrite, stream); });
   }
 }
 
 // The captured graph of one chunk plan for one set of buffers (created on
 // first use, replayed afterwards).
-hipGraphExec_t chunk_graph(Plan& plan, ChunkPlan& cp, const RunArgs& a, const int64_t* cur_bases) {
-  const GraphKey key{cp.j, a.arena, a.acc, a.direct_out, cur_bases};
+hipGraphExec_t chunk_graph(Plan& plan, ChunkPlan& cp, const RunArgs& a, const int64_t* cur_bases, bool overwrite) {
+  const GraphKey key{cp.j, a.arena, a.acc, a.direct_out, cur_bases, overwrite};
   std::lock_guard<std::mutex> g(plan.graph_mu);
   auto it = plan.graphs.find(key);
   if (it != plan.graphs.end()) return it->second;
@@ -318,7 +318,7 @@ hipGraphExec_t chunk_graph(Plan& plan, ChunkPlan& cp, const RunArgs& a, const in
   check_hip(hipStreamBeginCapture(plan.capture_stream, hipStreamCaptureModeThreadLocal), "begin capture");
   Launcher none{plan, nullptr};
   try {
-    enqueue_chunk(plan, cp, a, cur_bases, plan.capture_stream, none);
+    enqueue_chunk(plan, cp, a, cur_bases, overwrite, plan.capture_stream, none);
   } catch (...) {
     (void)hipStreamEndCapture(plan.capture_stream, &graph);
     if (graph) (void)hipGraphDestroy(graph);
@@ -398,14 +398,14 @@ void run_plan(Plan& plan, const RunArgs& a) {
   for (size_t c = 0; c < chunks.size(); ++c) {
     ChunkPlan& cp = ready(plan, chunks[c].first, a.stream);
     if (plan.graph) {
-      hipGraphExec_t exec = chunk_graph(plan, cp, a, cur_dev);
+      hipGraphExec_t exec = chunk_graph(plan, cp, a, cur_dev, a.fresh_acc && c == 0);
       if (cp.n_base_slots)
         check_hip(hipMemcpyAsync(cur_dev, bases_dev + c * slots, slots * sizeof(int64_t), hipMemcpyDeviceToDevice,
                                  a.stream),
                   "chunk bases");
       check_hip(hipGraphLaunch(exec, a.stream), "graph launch");
     } else {
-      enqueue_chunk(plan, cp, a, bases_dev + c * slots, a.stream, L);
+      enqueue_chunk(plan, cp, a, bases_dev + c * slots, a.fresh_acc && c == 0, a.stream, L);
     }
   }
   if (!ev.empty()) {
@@ -426,6 +426,7 @@ Plan::~Plan() {
   }
   for (auto& g : graphs) (void)hipGraphExecDestroy(g.second);
   if (capture_stream) (void)hipStreamDestroy(capture_stream);
+  if (host_res) (void)hipHostFree(host_res);
 }
 
 void drain_profile(Plan& plan) {

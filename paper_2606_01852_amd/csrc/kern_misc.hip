@@ -13,7 +13,7 @@ namespace {
 // One workgroup per output element: thread t adds s = t, t + 256, ... in
 // order, then a fixed LDS tree combines the 256 partial sums.
 __global__ __launch_bounds__(256) void reduce_fp64_block(const float2* root, double2* acc, int64_t hs,
-                                                          int64_t R) {
+                                                          int64_t R, int overwrite) {
   __shared__ double sr[256], si[256];
   const int64_t i = blockIdx.x;
   double xr = 0.0, xi = 0.0;
@@ -33,7 +33,7 @@ __global__ __launch_bounds__(256) void reduce_fp64_block(const float2* root, dou
     __syncthreads();
   }
   if (threadIdx.x == 0) {
-    double2 a = acc[i];
+    double2 a = overwrite ? make_double2(0.0, 0.0) : acc[i];
     a.x += sr[0];
     a.y += si[0];
     acc[i] = a;
@@ -42,7 +42,7 @@ __global__ __launch_bounds__(256) void reduce_fp64_block(const float2* root, dou
 
 // One thread per output element, s in order.
 __global__ __launch_bounds__(256) void reduce_fp64_thread(const float2* root, double2* acc, int64_t hs,
-                                                           int64_t R) {
+                                                           int64_t R, int overwrite) {
   for (int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x; i < R;
        i += static_cast<int64_t>(gridDim.x) * blockDim.x) {
     double xr = 0.0, xi = 0.0;
@@ -51,7 +51,7 @@ __global__ __launch_bounds__(256) void reduce_fp64_thread(const float2* root, do
       xr += static_cast<double>(v.x);
       xi += static_cast<double>(v.y);
     }
-    double2 a = acc[i];
+    double2 a = overwrite ? make_double2(0.0, 0.0) : acc[i];
     a.x += xr;
     a.y += xi;
     acc[i] = a;
@@ -96,12 +96,14 @@ int64_t grid_for(int64_t n) {
 
 }  // namespace
 
-hipError_t launch_reduce_fp64(const float2* root, double2* acc, int64_t hs, int64_t R, hipStream_t s) {
+hipError_t launch_reduce_fp64(const float2* root, double2* acc, int64_t hs, int64_t R, bool overwrite,
+                              hipStream_t s) {
   if (R <= 0 || hs <= 0) return hipSuccess;
+  const int ow = overwrite ? 1 : 0;
   if (hs >= 64 && R <= 65536)
-    hipLaunchKernelGGL(reduce_fp64_block, dim3(static_cast<unsigned>(R)), dim3(256), 0, s, root, acc, hs, R);
+    hipLaunchKernelGGL(reduce_fp64_block, dim3(static_cast<unsigned>(R)), dim3(256), 0, s, root, acc, hs, R, ow);
   else
-    hipLaunchKernelGGL(reduce_fp64_thread, dim3(grid_for(R)), dim3(256), 0, s, root, acc, hs, R);
+    hipLaunchKernelGGL(reduce_fp64_thread, dim3(grid_for(R)), dim3(256), 0, s, root, acc, hs, R, ow);
   return hipGetLastError();
 }
 

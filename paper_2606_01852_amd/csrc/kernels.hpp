@@ -133,8 +133,10 @@ hipError_t launch_group_gather(const GroupGather* table, const int64_t* prefix, 
 hipError_t launch_permute(const PermuteDesc& d, hipStream_t s);
 hipError_t launch_gather(const GatherDesc& d, hipStream_t s);
 // acc[i] += sum_s root[s * R + i] (complex64 in, complex128 out), pairwise
-// over s in a fixed tree; hs = number of s.
-hipError_t launch_reduce_fp64(const float2* root, double2* acc, int64_t hs, int64_t R, hipStream_t s);
+// over s in a fixed tree; hs = number of s.  overwrite: acc[i] = the sum
+// (the same bits as adding it to a zeroed accumulator).
+hipError_t launch_reduce_fp64(const float2* root, double2* acc, int64_t hs, int64_t R, bool overwrite,
+                              hipStream_t s);
 // out = sum_i |acc[i]|^2 in FP64 (one value written to *out, device pointer).
 hipError_t launch_norm2(const double2* acc, int64_t R, double* out, hipStream_t s);
 hipError_t launch_fill_zero(void* p, int64_t bytes, hipStream_t s);

@@ -107,6 +107,8 @@ struct Server {
   std::unordered_map<uint64_t, std::shared_ptr<Request>> reqs;
   std::vector<std::thread> workers;
   std::vector<hipStream_t> streams;
+  std::vector<void*> pinned;            // per slot: pinned result staging
+  std::vector<size_t> pinned_bytes;
   ArenaAllocator arena;
   bool stop = false;
   uint64_t next_id = 1;
@@ -138,6 +140,8 @@ struct Server {
     cv_work.notify_all();
     for (auto& t : workers) t.join();
     for (hipStream_t s : streams) (void)hipStreamDestroy(s);
+    for (void* p : pinned)
+      if (p) (void)hipHostFree(p);
   }
 
   void start() {
@@ -147,6 +151,8 @@ struct Server {
       check_hip(hipStreamCreate(&s), "hipStreamCreate");
       streams.push_back(s);
     }
+    pinned.assign(max_inflight, nullptr);
+    pinned_bytes.assign(max_inflight, 0);
     for (int i = 0; i < max_inflight; ++i) workers.emplace_back([this, i] { loop(i); });
   }
 
@@ -172,7 +178,7 @@ struct Server {
         if (r->heavy) ++heavy_inflight;
         ++inflight;
       }
-      execute(*r, stream);
+      execute(*r, slot, stream);
       {
         std::lock_guard<std::mutex> g(mu);
         arena.release(r->arena_off, r->need);
@@ -186,7 +192,7 @@ struct Server {
     }
   }
 
-  void execute(Request& r, hipStream_t stream) {
+  void execute(Request& r, int slot, hipStream_t stream) {
     try {
       Plan& p = *r.plan;
       const ChunkPlan& c0 = *p.chunks[0];
@@ -197,13 +203,22 @@ struct Server {
       a.arena_bytes = static_cast<size_t>(r.work_bytes);
       a.acc = reinterpret_cast<double2*>(ctx.arena + r.arena_off + r.acc_off);
       a.stream = stream;
-      check_hip(launch_fill_zero(a.acc, c0.R * 16, stream), "zero accumulator");
+      a.fresh_acc = true;
       run_plan(p, a);
-      std::vector<double> tmp(static_cast<size_t>(2 * c0.R));
-      check_hip(hipMemcpyAsync(tmp.data(), a.acc, c0.R * 16, hipMemcpyDeviceToHost, stream), "result copy");
+      // the slot's pinned staging buffer, grown on demand
+      const size_t res_bytes = static_cast<size_t>(c0.R) * 16;
+      if (pinned_bytes[slot] < res_bytes) {
+        if (pinned[slot]) (void)hipHostFree(pinned[slot]);
+        pinned[slot] = nullptr;
+        pinned_bytes[slot] = 0;
+        check_hip(hipHostMalloc(&pinned[slot], res_bytes, hipHostMallocDefault), "pinned result buffer");
+        pinned_bytes[slot] = res_bytes;
+      }
+      check_hip(hipMemcpyAsync(pinned[slot], a.acc, res_bytes, hipMemcpyDeviceToHost, stream), "result copy");
       check_hip(hipStreamSynchronize(stream), "stream synchronize");
+      const double* tmp = static_cast<const double*>(pinned[slot]);
       if (c0.result_perm.empty()) {
-        std::memcpy(r.out, tmp.data(), tmp.size() * sizeof(double));
+        std::memcpy(r.out, tmp, res_bytes);
       } else {
         for (int64_t u = 0; u < c0.R; ++u) {
           r.out[2 * u] = tmp[2 * c0.result_perm[u]];
