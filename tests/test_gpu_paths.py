@@ -426,3 +426,47 @@ def test_batched_bitstring_amplitudes(ctx):
     single = circuit_network(circ, bitstring=bits[5])
     z5, _, _ = run(ctx, single, greedy_path(single))
     assert abs(z[5] - z5) <= 1e-5 * abs(z5)
+
+
+@pytest.mark.parametrize("seed", range(6))
+def test_random_trees_odd_extents_and_slices(ctx, seed):
+    """Random tree networks with extents 1..5 (non-power-of-two batch and
+    slice extents, extent-1 labels, a rank-0 leaf), two sliced labels and
+    every chunk size: each matches the oracle; chunking does not change the
+    sum beyond FP64 rounding."""
+    rng = np.random.Generator(np.random.PCG64(4100 + seed))
+    n_leaves = int(rng.integers(5, 12))
+    labels = [[] for _ in range(n_leaves)]
+    nxt = 0
+    for t in range(1, n_leaves):
+        s = int(rng.integers(0, t))
+        labels[s].append(nxt); labels[t].append(nxt); nxt += 1
+    for _ in range(n_leaves // 2):
+        s, t = rng.choice(n_leaves, 2, replace=False)
+        labels[int(s)].append(nxt); labels[int(t)].append(nxt); nxt += 1
+    opn = []
+    for _ in range(2):
+        t = int(rng.integers(0, n_leaves))
+        labels[t].append(nxt); opn.append(nxt); nxt += 1
+    labels.append([])                                    # a rank-0 leaf (a scalar factor)
+    ext = rng.integers(1, 6, size=nxt).astype(np.int64)
+    labels = [tuple(int(x) for x in rng.permutation(l)) for l in labels]
+    leaves = [(rng.standard_normal(tuple(int(ext[l]) for l in lab) or ()) +
+               1j * rng.standard_normal(tuple(int(ext[l]) for l in lab) or ())).astype(np.complex128)
+              for lab in labels]
+    net = Network(leaves, labels, ext, tuple(opn))
+    path = greedy_path(net)
+    closed = [l for l in range(nxt) if l not in opn and ext[l] > 1]
+    sl = tuple(int(x) for x in rng.choice(closed, size=min(2, len(closed)), replace=False))
+    p = Path(path.pairs, sl)
+    ref = oc.contract(net, p)
+    print(f"random tree seed {seed}: {n_leaves + 1} leaves, sliced {sl} extents {[int(ext[l]) for l in sl]}",
+          flush=True)
+    n_slices = int(np.prod([ext[l] for l in sl])) if sl else 1
+    vals = []
+    for mc in sorted({1, int(ext[sl[-1]]) if sl else 1, n_slices}):
+        got, plan, _ = run(ctx, net, p, max_chunk=mc)
+        assert rel_fro(np.asarray(got), np.asarray(ref)) <= 1e-5, mc
+        vals.append(np.asarray(got))
+    for v in vals[1:]:
+        assert rel_fro(v, vals[0]) <= 1e-12
