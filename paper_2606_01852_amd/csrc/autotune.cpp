@@ -3,9 +3,10 @@
 //
 // For every distinct step shape (precision, form, output store, h, m, n, k)
 // the candidate workgroup shapes are timed with HIP events on a stand-in
-// problem of the same structure (K, then the batch, then m cut down so that
-// a trial stays near 2e13 FLOP while keeping the step's tile grid where
-// possible), and the fastest is kept.  Choices live in a per-context cache, optionally backed
+// problem of the same structure, filled with hashed uniform values (m, then
+// K down to 8192, then the batch cut so that a trial stays near 2e13 FLOP
+// while keeping enough tiles to show the step's wave quantization), and the
+// fastest is kept.  Choices live in a per-context cache, optionally backed
 // by a text file (TNC_AUTOTUNE_CACHE) so later processes skip the timing.
 // Without tuning a shape-based default is used.
 #include <algorithm>
@@ -37,7 +38,7 @@ double padding_waste(int variant, int64_t m, int64_t n) {
 // Ranking of the variants by measured per-tile throughput on large shapes.
 const std::vector<int>& ranking(tnc_prec prec, tnc_cgemm form) {
   static const std::vector<int> r4m = {3, 2, 0, 1, 4, 5, 6};
-  static const std::vector<int> r3m = {0, 2, 4, 1, 5, 6};
+  static const std::vector<int> r3m = {2, 0, 4, 1, 5, 6};
   static const std::vector<int> rbf = {2, 0, 1, 4, 5, 6};
   if (prec == TNC_PREC_BF16X3) return rbf;
   return form == TNC_GEMM_3M ? r3m : r4m;
@@ -95,21 +96,28 @@ int tune_shape(Ctx& c, const TuneKey& key, int64_t k, bool perm_store) {
   const std::vector<int> cand = candidates(prec, form, key.h, key.m, key.n);
   int best = cand.front();
   if (cand.size() > 1) {
-    // stand-in problem near 2e13 FLOP (about 0.15 s): K is cut first (down
-    // to 2048, enough stages per tile to rank the shapes as at full K), which
-    // keeps the tile grid -- and so the wave quantization over the CUs that
-    // separates the shapes -- exactly that of the step; then the batch, then m
+    // stand-in problem near 2e13 FLOP (about 0.15 s).  m is cut first while
+    // the grid keeps 8 or more rounds of the largest workgroup (256 x 128)
+    // over the 256 CUs, so wave quantization -- which separates the shapes on
+    // few-tile steps -- stays that of the step; K stays whole there, since
+    // whether a K panel fits an XCD's 4 MiB L2 also ranks the shapes (3M
+    // (2,2) leads (2,4) at k = 2048 and trails it by 5 % at k = 16384).
+    // Then K (down to 8192), the batch, and m below that bound.
     int64_t h = key.h, m = key.m;
     const double target = 2e13;
-    while (k > 2048 && k % 32 == 0 && 8.0 * h * m * key.n * k > target) k /= 2;
-    while (h > 1 && 8.0 * h * m * key.n * k > target) h = (h + 1) / 2;
-    while (m > 4096 && 8.0 * h * m * key.n * k > target) m = (m / 2 + 255) / 256 * 256;
+    auto flop = [&] { return 8.0 * h * m * key.n * k; };
+    auto half_m = [](int64_t x) { return (x / 2 + 255) / 256 * 256; };
+    while (m > 8192 && flop() > target && h * ((half_m(m) + 255) / 256) * ((key.n + 127) / 128) >= 2048)
+      m = half_m(m);
+    while (k > 8192 && k % 32 == 0 && flop() > target) k /= 2;
+    while (h > 1 && flop() > target) h = (h + 1) / 2;
+    while (m > 4096 && flop() > target) m = half_m(m);
     DeviceBuf a, b, cc, offm, offn;
     a.alloc(static_cast<size_t>(h * m * k) * 8);
     b.alloc(static_cast<size_t>(h * key.n * k) * 8);
     cc.alloc(static_cast<size_t>(h * m * key.n) * 8);
-    check_hip(hipMemsetAsync(a.ptr, 0, a.bytes, c.stream), "tune memset");
-    check_hip(hipMemsetAsync(b.ptr, 0, b.bytes, c.stream), "tune memset");
+    check_hip(launch_fill_hash(static_cast<float*>(a.ptr), h * m * k * 2, 0x5eed0001u, c.stream), "tune fill");
+    check_hip(launch_fill_hash(static_cast<float*>(b.ptr), h * key.n * k * 2, 0x5eed0002u, c.stream), "tune fill");
     GemmDesc d;
     std::memset(&d, 0, sizeof(d));
     d.A = static_cast<const float2*>(a.ptr);

@@ -80,6 +80,23 @@ __global__ __launch_bounds__(256) void fill_zero_kernel(uint32_t* p, int64_t wor
     p[i] = 0u;
 }
 
+// Uniform values in [-1, 1) from a 32-bit integer hash of the index (the
+// "lowbias32" mixer of C. Wellons' hash-prospector); stand-in operands whose
+// bits toggle as real data do (all-zero operands let the MFMA pipes run
+// cooler and faster than on data).
+__global__ __launch_bounds__(256) void fill_hash_kernel(float* p, int64_t n, uint32_t seed) {
+  for (int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x; i < n;
+       i += static_cast<int64_t>(gridDim.x) * blockDim.x) {
+    uint32_t x = static_cast<uint32_t>(i) ^ (static_cast<uint32_t>(i >> 32) * 0x9e3779b9u) ^ seed;
+    x ^= x >> 16;
+    x *= 0x7feb352du;
+    x ^= x >> 15;
+    x *= 0x846ca68bu;
+    x ^= x >> 16;
+    p[i] = static_cast<float>(x >> 8) * (1.0f / 8388608.0f) - 1.0f;
+  }
+}
+
 __global__ __launch_bounds__(256) void c128_to_c64_kernel(const double2* in, float2* out, int64_t n) {
   for (int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x; i < n;
        i += static_cast<int64_t>(gridDim.x) * blockDim.x) {
@@ -117,6 +134,12 @@ hipError_t launch_fill_zero(void* p, int64_t bytes, hipStream_t s) {
   if (bytes % 4) return hipErrorInvalidValue;
   hipLaunchKernelGGL(fill_zero_kernel, dim3(grid_for(bytes / 4)), dim3(256), 0, s,
                      static_cast<uint32_t*>(p), bytes / 4);
+  return hipGetLastError();
+}
+
+hipError_t launch_fill_hash(float* p, int64_t n, uint32_t seed, hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(fill_hash_kernel, dim3(grid_for(n)), dim3(256), 0, s, p, n, seed);
   return hipGetLastError();
 }
 

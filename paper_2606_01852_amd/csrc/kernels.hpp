@@ -140,6 +140,9 @@ hipError_t launch_reduce_fp64(const float2* root, double2* acc, int64_t hs, int6
 // out = sum_i |acc[i]|^2 in FP64 (one value written to *out, device pointer).
 hipError_t launch_norm2(const double2* acc, int64_t R, double* out, hipStream_t s);
 hipError_t launch_fill_zero(void* p, int64_t bytes, hipStream_t s);
+// p[i] = a hash of (i, seed) mapped to [-1, 1), i < n floats (autotuner
+// stand-in operands).
+hipError_t launch_fill_hash(float* p, int64_t n, uint32_t seed, hipStream_t s);
 // Calibration: `blocks` workgroups of 256 threads running `iters` rounds of
 // 8 FP32 16x16x4 MFMAs per wave (out: blocks * 256 floats, never written in
 // practice); a grid-stride 16-byte copy of `bytes` (a multiple of 16).
