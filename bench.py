@@ -285,7 +285,109 @@ def bench_small(args):
         out[f"grid8_{name}_ms"] = round(dt * 1e3, 3)
         out[f"grid8_{name}_tflops"] = round(p.info.flops_per_slice / dt / 1e12, 3)
         p.close()
+    out["amplitude_queries"] = amplitude_query_leg(ctx)
     print(json.dumps({"small_workloads": out}), flush=True)
+
+
+def amplitude_query_leg(ctx, n_queries: int = 4096):
+    """circuit12 amplitude queries (random bitstrings) served as row requests
+    through the library's server (8 slots): one batcher of 64 rows per batch
+    (dynamic batching: the queued queries' same-shape steps share each
+    launch) vs 8 batchers of one row (one query per run, up to 8 running at
+    once).  A burst of all queries gives the saturation rate (submission from
+    this Python thread included); Poisson streams at 0.5 and 3 x the one-row
+    servers' saturation give p50/p99 latency (submit to done, measured by the
+    library).  Rows are checked against 64-row batched contractions."""
+    import ctypes as C
+
+    from paper_2606_01852_amd import tnc
+    from workloads import configs
+    from workloads.circuits import circuit_network_batched
+    from workloads.paths import greedy_path
+
+    circ = configs.circuit12_circuit()
+    nq = circ.n_qubits
+    rng = np.random.Generator(np.random.PCG64(4096))
+    bits = rng.integers(0, 2, size=(n_queries, nq))
+    eye = [np.ascontiguousarray(np.eye(2, dtype=np.complex128)[b]) for b in (0, 1)]
+    ptr_rows = [(C.c_void_p * nq)(*[eye[int(x)].ctypes.data for x in bits[i]]) for i in range(n_queries)]
+    outs = np.zeros(n_queries, dtype=np.complex128)
+    out_ptrs = [outs[i:].ctypes.data_as(C.POINTER(C.c_double)) for i in range(n_queries)]
+    L = tnc.lib()
+
+    def make(B, copies):
+        made = []
+        for _ in range(copies):
+            net = circuit_network_batched(circ, np.zeros((B, nq), dtype=np.int64))
+            beta = net.open[0]
+            carriers = [t for t, lab in enumerate(net.labels) if beta in lab]
+            tn = tnc.Network(ctx, net.labels, net.extents, net.open, net.c64().leaves)
+            p = tnc.Plan(tn, greedy_path(net).pairs)
+            tnc.tnc_plan_set_graph(p.handle, True)
+            made.append((tn, p, tnc.Batcher(p, beta, carriers)))
+        return made
+
+    def replay(made, arrivals):
+        tnc.tnc_serve_start(ctx.handle, 8, 1 << 16)
+        rid = C.c_uint64()
+        ids = []
+        t_start = time.perf_counter()
+        for i, at in enumerate(arrivals):
+            delay = t_start + at - time.perf_counter()
+            if delay > 0:
+                time.sleep(delay)
+            b = made[i % len(made)][2].handle
+            st = L.tnc_submit_row(ctx.handle, b, ptr_rows[i], tnc.IN_C128, out_ptrs[i], C.byref(rid))
+            if st != tnc.OK:
+                raise tnc.TncError(st, L.tnc_last_error().decode())
+            ids.append(rid.value)
+        lat = np.array([tnc.tnc_wait(ctx.handle, r) for r in ids])
+        wall = time.perf_counter() - t_start
+        tnc.tnc_serve_stop(ctx.handle)
+        return lat, wall
+
+    servers = {"batched_64_rows": make(64, 1), "one_row_x8": make(1, 8)}
+    res, sat, got = {}, {}, {}
+    for name, made in servers.items():
+        replay(made, np.zeros(256))                      # warm-up: tables, graphs
+        lat, wall = replay(made, np.zeros(n_queries))
+        sat[name] = n_queries / wall
+        got[name] = outs.copy()
+        res[name] = {"burst_queries_per_s": round(sat[name], 1)}
+        log(f"amplitude queries {name}: burst of {n_queries} at {sat[name]:.0f} queries/s")
+    # the bursts' rows against 64-row batched contractions of the same bitstrings
+    ref = np.empty(n_queries, dtype=np.complex128)
+    net = circuit_network_batched(circ, bits[:64])
+    beta = net.open[0]
+    carriers = [t for t, lab in enumerate(net.labels) if beta in lab]
+    tn = tnc.Network(ctx, net.labels, net.extents, net.open, net.c64().leaves)
+    p = tnc.Plan(tn, greedy_path(net).pairs)
+    for c0 in range(0, n_queries, 64):
+        netc = circuit_network_batched(circ, bits[c0:c0 + 64])
+        for t in carriers:
+            tn.set_tensor(t, netc.leaves[t])
+        ref[c0:c0 + 64] = p.contract()
+    res["batched_rows_bitwise_equal_to_contraction"] = bool(
+        np.array_equal(got["batched_64_rows"].view(np.uint64), ref.view(np.uint64)))
+    res["one_row_rel_frobenius_diff"] = float(np.linalg.norm(got["one_row_x8"] - ref) / np.linalg.norm(ref))
+    p.close()
+    tn.close()
+    gaps = rng.exponential(1.0, n_queries)
+    for load in (0.5, 3.0):
+        rate = load * sat["one_row_x8"]
+        arrivals = np.cumsum(gaps) / rate
+        for name, made in servers.items():
+            lat, wall = replay(made, arrivals)
+            res[name][f"rate_{load}x"] = {"queries_per_s": round(rate, 1),
+                                          "p50_us": round(float(np.percentile(lat, 50)) * 1e6, 1),
+                                          "p99_us": round(float(np.percentile(lat, 99)) * 1e6, 1)}
+            log(f"amplitude queries {name} at {rate:.0f}/s: {res[name][f'rate_{load}x']}")
+    for made in servers.values():
+        for tn, p, b in made:
+            b.close()
+            p.close()
+            tn.close()
+    return res
 
 
 def bench_circuit40(args):

@@ -73,6 +73,7 @@ typedef enum { TNC_IN_C64 = 0, TNC_IN_C128 = 1 } tnc_in;
 typedef struct tnc_ctx_s* tnc_ctx;
 typedef struct tnc_net_s* tnc_net;
 typedef struct tnc_plan_s* tnc_plan;
+typedef struct tnc_batcher_s* tnc_batcher;
 typedef uint64_t tnc_req;
 
 /* Last error message of the calling thread ("" if none).  Owned by the
@@ -298,6 +299,38 @@ tnc_status tnc_serve_set_heavy(tnc_ctx ctx, double heavy_flops, int32_t heavy_sl
 tnc_status tnc_serve_stop(tnc_ctx ctx);
 tnc_status tnc_submit(tnc_ctx ctx, tnc_plan plan, int64_t first_slice, int64_t n_slices,
                       double* out_c128, tnc_req* id);
+
+/* Dynamic batching of row requests (an extension; the paper serves no
+ * requests).  `plan`'s network carries an open label `batch_label` of
+ * extent B that is the first label of its open list and the outermost
+ * stored mode of each of the n_leaves listed leaves, and no other leaf
+ * carries it (e.g. the projector leaves of B amplitude queries of one
+ * circuit).  A row request supplies those leaves' values for one batch row;
+ * the server takes up to B queued rows of one batcher at once, writes them
+ * into rows 0..k-1 of the listed leaves (device copies owned by the network)
+ * and runs the plan once over all its slices, so the same-shape steps of k
+ * requests run as one launch per step.  Rows k..B-1 keep older values and
+ * their results are dropped.  One batch of a batcher runs at a time; rows
+ * queued meanwhile go into the next.  A row's result is the row of the
+ * plan's result at its batch position (the result without the batch label,
+ * R / B complex values).
+ * tnc_batcher_create: TNC_E_ARG if the label or the leaves do not have that
+ * form, TNC_E_BUSY if the network already has a batcher.  The listed leaves
+ * are excluded from the plan's leaf cache (chunks built before are
+ * rebuilt); call it when the plan is not running.  While a batcher exists,
+ * tnc_submit refuses plans on its network (TNC_E_BUSY): batches overwrite
+ * its leaves.  The handle may be destroyed while rows are queued (they still
+ * run); the network is released from the batcher when the last row is done. */
+tnc_status tnc_batcher_create(tnc_plan plan, int32_t batch_label, int32_t n_leaves, const int32_t* leaves,
+                              tnc_batcher* out);
+tnc_status tnc_batcher_destroy(tnc_batcher b);
+/* Queue one row: row_data[i] = host pointer to the values of leaves[i]
+ * without the batch mode (numel / B elements, stored order, element type
+ * `in`), copied before the call returns; out_c128 (host, R / B complex128)
+ * must stay valid until the request is done.  Heavy classification and
+ * admission as for tnc_submit, with the batch's work and arena need. */
+tnc_status tnc_submit_row(tnc_ctx ctx, tnc_batcher b, const void* const* row_data, tnc_in in, double* out_c128,
+                          tnc_req* id);
 /* done = 1 when finished; latency_s = submit-to-done wall time (else 0);
  * status of the request's execution is returned once done. */
 tnc_status tnc_poll(tnc_ctx ctx, tnc_req id, int32_t* done, double* latency_s);

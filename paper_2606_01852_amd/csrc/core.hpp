@@ -94,6 +94,7 @@ struct Net {
   std::vector<int64_t> numel;             // per leaf
   std::vector<DeviceBuf> leaf;            // resident complex64 leaves
   std::vector<uint64_t> version;          // per leaf, bumped when its data is replaced
+  std::atomic<int> n_batchers{0};         // a batcher writes rows of its leaves
   std::vector<std::vector<int64_t>> stride;  // per leaf, per stored mode
   ~Net();
 };
@@ -226,6 +227,7 @@ struct Plan {
   tnc_cgemm form = TNC_GEMM_4M;
   int64_t max_chunk_user = -1;
   int grouping = 1;                   // level-grouped launches
+  std::vector<char> volatile_leaf;    // per leaf: data changes between runs (never cached)
   void* host_res = nullptr;           // pinned staging of tnc_contract's result
   size_t host_res_bytes = 0;
   int graph = 0;
@@ -290,4 +292,10 @@ struct tnc_net_s {
 };
 struct tnc_plan_s {
   std::shared_ptr<tnc::Plan> p;
+};
+namespace tnc {
+struct Batcher;
+}
+struct tnc_batcher_s {
+  std::shared_ptr<tnc::Batcher> b;
 };

@@ -445,11 +445,13 @@ std::unique_ptr<ChunkPlan> build_chunk(const Plan& plan, int j) {
   }
   cp->n_base_slots = n_slots;
   // leaves without a per-chunk base offset are the same in every run: up to
-  // 2^22 elements each they are permuted once into the leaf cache
+  // 2^22 elements each they are permuted once into the leaf cache (not the
+  // leaves a batcher rewrites before every run)
   constexpr int64_t kCacheLeafElems = int64_t{1} << 22;
   for (int t = 0; t < n && ns > 0; ++t) {
     LeafPrep& lp = cp->leaf[t];
     if (lp.direct || lp.base_slot >= 0 || cp->numel[t] > kCacheLeafElems) continue;
+    if (!plan.volatile_leaf.empty() && plan.volatile_leaf[t]) continue;
     lp.cached = true;
     lp.cache_off = cp->cache_bytes;
     cp->cache_bytes += align_up(cp->numel[t] * 8);

@@ -15,6 +15,12 @@
 // planned work reaches a threshold are therefore "heavy" and share a lane of
 // few slots: a heavy request waits for the heavy ones ahead of it, never for
 // light ones, and light requests behind a waiting heavy one go past it.
+//
+// Row requests of a batcher (a plan with a batch label whose rows come from
+// the requests) are taken together: up to B queued rows of one batcher form
+// one job, whose rows are written into the batch-labelled leaves before the
+// plan runs once, so the same-shape steps of those requests share each
+// launch.  A batcher runs one job at a time (its leaves hold one batch).
 #include <chrono>
 #include <condition_variable>
 #include <cstring>
@@ -78,6 +84,8 @@ class ArenaAllocator {
   std::map<int64_t, int64_t> free_;
 };
 
+}  // namespace
+
 struct Request {
   uint64_t id = 0;
   std::shared_ptr<Plan> plan_ref;   // keeps the plan alive while queued or running
@@ -89,13 +97,14 @@ struct Request {
   bool heavy = false;       // classified at submission
   bool heavy_slot = false;  // holds a heavy-lane slot while running
   int64_t arena_off = -1;
+  std::shared_ptr<Batcher> batcher;  // row request (or a batcher's token): its batcher
+  bool token = false;                // stands for the batcher's waiting rows in the queue
+  std::vector<float2> row;           // row values of the listed leaves (complex64)
   Clock::time_point t_submit, t_done;
   bool done = false;
   tnc_status status = TNC_OK;
   std::string err;
 };
-
-}  // namespace
 
 struct Server {
   Ctx& ctx;
@@ -109,6 +118,8 @@ struct Server {
   std::vector<hipStream_t> streams;
   std::vector<void*> pinned;            // per slot: pinned result staging
   std::vector<size_t> pinned_bytes;
+  std::vector<void*> pinned_in;         // per slot: pinned staging of batch rows
+  std::vector<size_t> pinned_in_bytes;
   ArenaAllocator arena;
   bool stop = false;
   uint64_t next_id = 1;
@@ -142,6 +153,8 @@ struct Server {
     for (hipStream_t s : streams) (void)hipStreamDestroy(s);
     for (void* p : pinned)
       if (p) (void)hipHostFree(p);
+    for (void* p : pinned_in)
+      if (p) (void)hipHostFree(p);
   }
 
   void start() {
@@ -153,6 +166,8 @@ struct Server {
     }
     pinned.assign(max_inflight, nullptr);
     pinned_bytes.assign(max_inflight, 0);
+    pinned_in.assign(max_inflight, nullptr);
+    pinned_in_bytes.assign(max_inflight, 0);
     for (int i = 0; i < max_inflight; ++i) workers.emplace_back([this, i] { loop(i); });
   }
 
@@ -160,7 +175,7 @@ struct Server {
     (void)hipSetDevice(ctx.device);
     hipStream_t stream = streams[slot];
     for (;;) {
-      std::shared_ptr<Request> r;
+      std::vector<std::shared_ptr<Request>> job;  // one request, or rows of one batcher
       {
         std::unique_lock<std::mutex> g(mu);
         // drain on stop: keep admitting until the queue is empty
@@ -171,24 +186,144 @@ struct Server {
           return it != queue.end();
         });
         if (queue.empty()) return;
-        r = *it;
-        queue.erase(it);
-        r->arena_off = arena.alloc(r->need);
-        r->heavy_slot = r->heavy;
-        if (r->heavy) ++heavy_inflight;
+        if ((*it)->token) {
+          // a batcher's token: up to B of its waiting rows, in submission order
+          Batcher& b = *(*it)->batcher;
+          while (!b.rows.empty() && static_cast<int64_t>(job.size()) < b.B) {
+            job.push_back(b.rows.front());
+            b.rows.pop_front();
+          }
+          b.queued = false;
+          queue.erase(it);
+          if (job.empty()) continue;  // no rows behind the token (never queued so)
+          b.busy = true;
+          job[0]->heavy = b.flops >= heavy_flops && heavy_flops > 0;
+        } else {
+          job.push_back(*it);
+          queue.erase(it);
+        }
+        Request& r = *job[0];
+        r.arena_off = arena.alloc(r.need);
+        r.heavy_slot = r.heavy;
+        if (r.heavy) ++heavy_inflight;
         ++inflight;
       }
-      execute(*r, slot, stream);
+      if (job[0]->batcher)
+        execute_rows(job, slot, stream);
+      else
+        execute(*job[0], slot, stream);
       {
         std::lock_guard<std::mutex> g(mu);
-        arena.release(r->arena_off, r->need);
-        r->t_done = Clock::now();
-        r->done = true;
-        if (r->heavy_slot) --heavy_inflight;
+        Request& r = *job[0];
+        arena.release(r.arena_off, r.need);
+        const Clock::time_point now = Clock::now();
+        for (auto& q : job) {
+          q->t_done = now;
+          q->done = true;
+          q->row.clear();
+          q->row.shrink_to_fit();
+        }
+        if (r.heavy_slot) --heavy_inflight;
         --inflight;
+        if (r.batcher) {
+          Batcher& b = *r.batcher;
+          b.busy = false;
+          if (!b.rows.empty()) enqueue_token(r.batcher);  // rows that came in meanwhile
+        }
       }
       cv_work.notify_all();
       cv_done.notify_all();
+    }
+  }
+
+  // Queue a token for a batcher's waiting rows (server mutex held).
+  void enqueue_token(const std::shared_ptr<Batcher>& b) {
+    auto t = std::make_shared<Request>();
+    t->token = true;
+    t->batcher = b;
+    t->need = b->need;
+    t->flops = b->flops;
+    t->heavy = heavy_flops > 0 && b->flops >= heavy_flops;
+    queue.push_back(t);
+    b->queued = true;
+  }
+
+  // Grow a slot's pinned staging buffer to `bytes`.
+  static void* staging(std::vector<void*>& bufs, std::vector<size_t>& sizes, int slot, size_t bytes) {
+    if (sizes[slot] < bytes) {
+      if (bufs[slot]) (void)hipHostFree(bufs[slot]);
+      bufs[slot] = nullptr;
+      sizes[slot] = 0;
+      check_hip(hipHostMalloc(&bufs[slot], bytes, hipHostMallocDefault), "pinned staging buffer");
+      sizes[slot] = bytes;
+    }
+    return bufs[slot];
+  }
+
+  // Run `plan` over all its slices in the request's arena interval; the FP64
+  // result lands in the slot's pinned buffer (synchronous on `stream`).
+  const double* run_to_host(Request& r, Plan& p, int slot, hipStream_t stream) {
+    const ChunkPlan& c0 = *p.chunks[0];
+    RunArgs a;
+    a.first = r.first;
+    a.count = r.count;
+    a.arena = ctx.arena + r.arena_off;
+    a.arena_bytes = static_cast<size_t>(r.work_bytes);
+    a.acc = reinterpret_cast<double2*>(ctx.arena + r.arena_off + r.acc_off);
+    a.stream = stream;
+    a.fresh_acc = true;
+    run_plan(p, a);
+    const size_t res_bytes = static_cast<size_t>(c0.R) * 16;
+    void* host = staging(pinned, pinned_bytes, slot, res_bytes);
+    check_hip(hipMemcpyAsync(host, a.acc, res_bytes, hipMemcpyDeviceToHost, stream), "result copy");
+    check_hip(hipStreamSynchronize(stream), "stream synchronize");
+    return static_cast<const double*>(host);
+  }
+
+  // Rows of one batcher: rows 0..k-1 of each listed leaf (the batch label is
+  // its outermost mode, so they are contiguous) come from the k requests in
+  // order, the plan runs once, and request j gets row j of the result.
+  void execute_rows(std::vector<std::shared_ptr<Request>>& job, int slot, hipStream_t stream) {
+    Request& r0 = *job[0];
+    try {
+      Batcher& b = *r0.batcher;
+      Plan& p = *b.plan;
+      Net& n = *p.net;
+      const int64_t k = static_cast<int64_t>(job.size());
+      float2* in = static_cast<float2*>(
+          staging(pinned_in, pinned_in_bytes, slot, static_cast<size_t>(k * b.row_total) * sizeof(float2)));
+      int64_t off = 0, src = 0;
+      for (size_t i = 0; i < b.leaves.size(); ++i) {
+        const int64_t re = b.row_elems[i];
+        for (int64_t j = 0; j < k; ++j)
+          std::memcpy(in + off + j * re, job[j]->row.data() + src, static_cast<size_t>(re) * sizeof(float2));
+        check_hip(hipMemcpyAsync(n.leaf[b.leaves[i]].ptr, in + off, static_cast<size_t>(k * re) * sizeof(float2),
+                                 hipMemcpyHostToDevice, stream),
+                  "row upload");
+        off += k * re;
+        src += re;
+      }
+      const double* tmp = run_to_host(r0, p, slot, stream);
+      const ChunkPlan& c0 = *p.chunks[0];
+      for (int64_t j = 0; j < k; ++j) {
+        double* out = job[j]->out;
+        for (int64_t u = 0; u < b.out_row; ++u) {
+          const int64_t g = j * b.out_row + u;
+          const int64_t s = c0.result_perm.empty() ? g : c0.result_perm[g];
+          out[2 * u] = tmp[2 * s];
+          out[2 * u + 1] = tmp[2 * s + 1];
+        }
+      }
+    } catch (const Error& e) {
+      for (auto& q : job) {
+        q->status = e.code;
+        q->err = e.msg;
+      }
+    } catch (const std::exception& e) {
+      for (auto& q : job) {
+        q->status = TNC_E_DEVICE;
+        q->err = e.what();
+      }
     }
   }
 
@@ -196,29 +331,9 @@ struct Server {
     try {
       Plan& p = *r.plan;
       const ChunkPlan& c0 = *p.chunks[0];
-      RunArgs a;
-      a.first = r.first;
-      a.count = r.count;
-      a.arena = ctx.arena + r.arena_off;
-      a.arena_bytes = static_cast<size_t>(r.work_bytes);
-      a.acc = reinterpret_cast<double2*>(ctx.arena + r.arena_off + r.acc_off);
-      a.stream = stream;
-      a.fresh_acc = true;
-      run_plan(p, a);
-      // the slot's pinned staging buffer, grown on demand
-      const size_t res_bytes = static_cast<size_t>(c0.R) * 16;
-      if (pinned_bytes[slot] < res_bytes) {
-        if (pinned[slot]) (void)hipHostFree(pinned[slot]);
-        pinned[slot] = nullptr;
-        pinned_bytes[slot] = 0;
-        check_hip(hipHostMalloc(&pinned[slot], res_bytes, hipHostMallocDefault), "pinned result buffer");
-        pinned_bytes[slot] = res_bytes;
-      }
-      check_hip(hipMemcpyAsync(pinned[slot], a.acc, res_bytes, hipMemcpyDeviceToHost, stream), "result copy");
-      check_hip(hipStreamSynchronize(stream), "stream synchronize");
-      const double* tmp = static_cast<const double*>(pinned[slot]);
+      const double* tmp = run_to_host(r, p, slot, stream);
       if (c0.result_perm.empty()) {
-        std::memcpy(r.out, tmp, res_bytes);
+        std::memcpy(r.out, tmp, static_cast<size_t>(c0.R) * 16);
       } else {
         for (int64_t u = 0; u < c0.R; ++u) {
           r.out[2 * u] = tmp[2 * c0.result_perm[u]];
@@ -234,6 +349,10 @@ struct Server {
     }
   }
 };
+
+Batcher::~Batcher() {
+  if (plan) --plan->net->n_batchers;
+}
 
 std::shared_ptr<Server> make_server(Ctx& ctx, int max_inflight, int queue_cap) {
   auto s = std::make_shared<Server>(ctx, max_inflight, queue_cap);
@@ -300,6 +419,8 @@ tnc_status tnc_submit(tnc_ctx ctx, tnc_plan plan, int64_t first_slice, int64_t n
     if (!s) fail(TNC_E_ARG, "server not started");
     Plan& p = *plan->p;
     if (p.net->ctx != &c) fail(TNC_E_ARG, "plan belongs to another context");
+    if (p.net->n_batchers.load() > 0)
+      fail(TNC_E_BUSY, "the plan's network has a batcher, whose batches rewrite its leaves: submit rows");
     if (first_slice < 0 || n_slices < 1 || first_slice + n_slices > p.n_slices) fail(TNC_E_ARG, "bad slice range");
     auto r = std::make_shared<Request>();
     r->plan_ref = plan->p;
@@ -325,6 +446,143 @@ tnc_status tnc_submit(tnc_ctx ctx, tnc_plan plan, int64_t first_slice, int64_t n
       s->reqs[r->id] = r;
     }
     s->cv_work.notify_all();
+    *id = r->id;
+  } catch (const Error& e) {
+    g_error_set(e.msg);
+    return e.code;
+  }
+  return TNC_OK;
+}
+
+tnc_status tnc_batcher_create(tnc_plan plan, int32_t batch_label, int32_t n_leaves, const int32_t* leaves,
+                              tnc_batcher* out) {
+  g_error_clear();
+  try {
+    if (!plan || !out || n_leaves < 1 || !leaves) fail(TNC_E_ARG, "bad batcher arguments");
+    Plan& p = *plan->p;
+    Net& n = *p.net;
+    Ctx& c = *n.ctx;
+    const int L = static_cast<int>(n.extents.size());
+    if (batch_label < 0 || batch_label >= L) fail(TNC_E_ARG, "batch label out of range");
+    if (n.kind[batch_label] != LabelKind::Open && n.kind[batch_label] != LabelKind::Batch)
+      fail(TNC_E_ARG, "batch label " + std::to_string(batch_label) + " is not open");
+    if (n.open.empty() || n.open[0] != batch_label) fail(TNC_E_ARG, "the batch label must lead the open list");
+    std::vector<char> listed(n.n_tensors, 0);
+    for (int i = 0; i < n_leaves; ++i) {
+      const int t = leaves[i];
+      if (t < 0 || t >= n.n_tensors) fail(TNC_E_ARG, "leaf out of range");
+      if (listed[t]) fail(TNC_E_ARG, "leaf " + std::to_string(t) + " listed twice");
+      listed[t] = 1;
+      if (n.labels[t].empty() || n.labels[t][0] != batch_label)
+        fail(TNC_E_ARG, "the batch label is not the outermost mode of leaf " + std::to_string(t));
+    }
+    for (int t = 0; t < n.n_tensors; ++t)
+      for (int l : n.labels[t])
+        if (l == batch_label && !listed[t])
+          fail(TNC_E_ARG, "leaf " + std::to_string(t) + " carries the batch label but is not listed");
+    if (n.n_batchers.load() > 0) fail(TNC_E_BUSY, "the network already has a batcher");
+    if (c.server) fail(TNC_E_BUSY, "the context is serving: create batchers before tnc_serve_start");
+    // re-plan with the listed leaves out of the leaf cache
+    if (!c.host_only) {
+      set_device(c);
+      check_hip(hipStreamSynchronize(c.stream), "sync before re-planning");
+      drain_profile(p);
+    }
+    {
+      std::lock_guard<std::mutex> lk(p.graph_mu);
+      for (auto& e : p.graphs) (void)hipGraphExecDestroy(e.second);
+      p.graphs.clear();
+    }
+    p.volatile_leaf.assign(n.n_tensors, 0);
+    for (int i = 0; i < n_leaves; ++i) p.volatile_leaf[leaves[i]] = 1;
+    choose_chunking(p, c.arena_bytes);
+    auto b = std::make_shared<Batcher>();
+    b->plan_ref = plan->p;
+    b->label = batch_label;
+    b->B = n.extents[batch_label];
+    for (int i = 0; i < n_leaves; ++i) {
+      b->leaves.push_back(leaves[i]);
+      b->row_elems.push_back(n.numel[leaves[i]] / b->B);
+      b->row_total += b->row_elems.back();
+    }
+    const int64_t R = p.chunks[0]->R;
+    b->out_row = R / b->B;
+    b->work_bytes = run_workspace_bytes(p, 0, p.n_slices);
+    b->need = b->work_bytes + align_up(R * 16);
+    for (const auto& ch : decompose(p, 0, p.n_slices)) b->flops += p.chunk(ch.first).flops;
+    if (!c.host_only && b->need > static_cast<int64_t>(c.arena_bytes))
+      fail(TNC_E_NOMEM, "a batch needs " + std::to_string(b->need) + " arena bytes, the arena has " +
+                            std::to_string(c.arena_bytes));
+    b->plan = &p;  // from here on the batcher holds the network
+    ++n.n_batchers;
+    *out = new tnc_batcher_s{b};
+  } catch (const Error& e) {
+    g_error_set(e.msg);
+    return e.code;
+  }
+  return TNC_OK;
+}
+
+tnc_status tnc_batcher_destroy(tnc_batcher b) {
+  g_error_clear();
+  delete b;  // queued rows keep the batcher alive until they are done
+  return TNC_OK;
+}
+
+tnc_status tnc_submit_row(tnc_ctx ctx, tnc_batcher bh, const void* const* row_data, tnc_in in, double* out_c128,
+                          tnc_req* id) {
+  g_error_clear();
+  try {
+    if (!ctx || !bh || !row_data || !out_c128 || !id) fail(TNC_E_ARG, "NULL argument");
+    if (in != TNC_IN_C64 && in != TNC_IN_C128) fail(TNC_E_ARG, "unknown input type");
+    Ctx& c = *ctx->c;
+    Server* s = c.server.get();
+    if (!s) fail(TNC_E_ARG, "server not started");
+    const std::shared_ptr<Batcher>& b = bh->b;
+    if (b->plan->net->ctx != &c) fail(TNC_E_ARG, "batcher belongs to another context");
+    if (b->need > static_cast<int64_t>(c.arena_bytes))
+      fail(TNC_E_NOMEM, "a batch needs " + std::to_string(b->need) + " arena bytes, the arena has " +
+                            std::to_string(c.arena_bytes));
+    auto r = std::make_shared<Request>();
+    r->plan_ref = b->plan_ref;
+    r->plan = b->plan;
+    r->batcher = b;
+    r->first = 0;
+    r->count = b->plan->n_slices;
+    r->out = out_c128;
+    r->work_bytes = b->work_bytes;
+    r->acc_off = b->work_bytes;
+    r->need = b->need;
+    r->flops = b->flops;
+    r->row.resize(static_cast<size_t>(b->row_total));
+    int64_t off = 0;
+    for (size_t i = 0; i < b->leaves.size(); ++i) {
+      if (!row_data[i]) fail(TNC_E_ARG, "row data of listed leaf " + std::to_string(i) + " is NULL");
+      const int64_t re = b->row_elems[i];
+      if (in == TNC_IN_C64) {
+        std::memcpy(r->row.data() + off, row_data[i], static_cast<size_t>(re) * sizeof(float2));
+      } else {
+        const double* d = static_cast<const double*>(row_data[i]);
+        for (int64_t e = 0; e < re; ++e)
+          r->row[off + e] = make_float2(static_cast<float>(d[2 * e]), static_cast<float>(d[2 * e + 1]));
+      }
+      off += re;
+    }
+    bool wake = false;
+    {
+      std::lock_guard<std::mutex> g(s->mu);
+      if (b->rows.size() >= s->queue_cap) fail(TNC_E_BUSY, "batcher queue full");
+      r->id = s->next_id++;
+      r->t_submit = Clock::now();
+      b->rows.push_back(r);
+      s->reqs[r->id] = r;
+      // a running or already queued batch picks the row up; else queue a token
+      if (!b->busy && !b->queued) {
+        s->enqueue_token(b);
+        wake = true;
+      }
+    }
+    if (wake) s->cv_work.notify_all();
     *id = r->id;
   } catch (const Error& e) {
     g_error_set(e.msg);

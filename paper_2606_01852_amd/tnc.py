@@ -104,6 +104,9 @@ _SIGS = {
     "tnc_serve_stop": (C.c_int, [_P]),
     "tnc_serve_set_heavy": (C.c_int, [_P, C.c_double, C.c_int32]),
     "tnc_submit": (C.c_int, [_P, _P, C.c_int64, C.c_int64, _DP, C.POINTER(C.c_uint64)]),
+    "tnc_batcher_create": (C.c_int, [_P, C.c_int32, C.c_int32, _I32P, C.POINTER(_P)]),
+    "tnc_batcher_destroy": (C.c_int, [_P]),
+    "tnc_submit_row": (C.c_int, [_P, _P, C.POINTER(_P), C.c_int, _DP, C.POINTER(C.c_uint64)]),
     "tnc_poll": (C.c_int, [_P, C.c_uint64, _I32P, _DP]),
     "tnc_wait": (C.c_int, [_P, C.c_uint64, _DP]),
 }
@@ -342,6 +345,28 @@ def tnc_submit(ctx: int, plan: int, first: int, count: int, out: np.ndarray) -> 
     return rid.value
 
 
+def tnc_batcher_create(plan: int, batch_label: int, leaves) -> int:
+    lv = np.ascontiguousarray(np.asarray(leaves, dtype=np.int32))
+    h = _P()
+    _check(lib().tnc_batcher_create(plan, int(batch_label), int(lv.size), lv.ctypes.data_as(_I32P), C.byref(h)))
+    return h.value
+
+
+def tnc_batcher_destroy(b: int) -> None:
+    _check(lib().tnc_batcher_destroy(b))
+
+
+def tnc_submit_row(ctx: int, b: int, rows, out: np.ndarray) -> int:
+    """rows[i]: values of the batcher's i-th leaf for one batch row (the leaf
+    without its batch mode), complex128; copied before the call returns."""
+    assert out.dtype == np.complex128 and out.flags.c_contiguous
+    arrs = [np.ascontiguousarray(np.asarray(r, dtype=np.complex128)) for r in rows]
+    ptrs = (_P * max(1, len(arrs)))(*[a.ctypes.data for a in arrs])
+    rid = C.c_uint64()
+    _check(lib().tnc_submit_row(ctx, b, ptrs, IN_C128, out.ctypes.data_as(_DP), C.byref(rid)))
+    return rid.value
+
+
 def tnc_poll(ctx: int, rid: int):
     done = C.c_int32()
     lat = C.c_double()
@@ -406,6 +431,26 @@ class Network:
     def close(self) -> None:
         if self.handle:
             tnc_net_destroy(self.handle)
+            self.handle = 0
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Batcher:
+    """Row requests of `plan` batched over its batch label (see tnc_batcher_create)."""
+
+    def __init__(self, plan: "Plan", batch_label: int, leaves):
+        self.plan = plan
+        self.leaves = [int(t) for t in leaves]
+        self.handle = tnc_batcher_create(plan.handle, batch_label, self.leaves)
+
+    def close(self) -> None:
+        if self.handle:
+            tnc_batcher_destroy(self.handle)
             self.handle = 0
 
     def __del__(self):

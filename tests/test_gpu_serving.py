@@ -237,3 +237,85 @@ def test_served_graph_plans_match_eager(served):
         assert np.array_equal(out.view(np.uint64), alone[i].view(np.uint64)), i
     for p in gplans:
         p.close()
+
+
+def test_batcher_rows_match_batched_contract_and_state_vector():
+    """Row requests of a batcher (circuit12 amplitude queries, B = 16 rows per
+    batch), served among ordinary requests: each equals bitwise its row of a
+    batched contraction of the same bitstrings on a separate network (so the
+    row's batch position and its batch-mates do not matter), and the
+    brute-force state vector within 1e-5.  Plans on the batcher's network
+    are refused for ordinary submission."""
+    from oracle import statevector as osv
+    from workloads import configs
+    from workloads.circuits import circuit_network_batched
+    circ = configs.circuit12_circuit()
+    nq, B, n_req = circ.n_qubits, 16, 40
+    rng = np.random.Generator(np.random.PCG64(515))
+    bits = rng.integers(0, 2, size=(n_req, nq))
+    bits[24:28] = bits[0:4]                      # repeated queries
+    arena = torch.empty(2 << 30, dtype=torch.uint8, device="cuda")
+    ctx = tnc.Context(0, arena_bytes=arena.numel(), arena_ptr=arena.data_ptr())
+    net = circuit_network_batched(circ, np.zeros((B, nq), dtype=np.int64))
+    beta = net.open[0]
+    carriers = [t for t, lab in enumerate(net.labels) if beta in lab]   # projector of qubit q = carriers[q]
+    path = greedy_path(net)
+    tn = tnc.Network(ctx, net.labels, net.extents, net.open, net.c64().leaves)
+    plan = tnc.Plan(tn, path.pairs)
+    batcher = tnc.Batcher(plan, beta, carriers)
+
+    # reference rows: batched contractions of the same bitstrings, B at a time
+    tn_ref = tnc.Network(ctx, net.labels, net.extents, net.open, net.c64().leaves)
+    plan_ref = tnc.Plan(tn_ref, path.pairs)
+    ref = np.empty(n_req, dtype=np.complex128)
+    for c0 in range(0, n_req, B):
+        chunk = np.zeros((B, nq), dtype=np.int64)
+        chunk[:min(B, n_req - c0)] = bits[c0:c0 + B]
+        netc = circuit_network_batched(circ, chunk)
+        for t in carriers:
+            tn_ref.set_tensor(t, netc.leaves[t])
+        ref[c0:c0 + B] = plan_ref.contract()[:min(B, n_req - c0)]
+
+    others = [configs.circuit12()]
+    other_plans = []
+    for onet, opath in others:
+        otn = tnc.Network(ctx, onet.labels, onet.extents, onet.open, onet.c64().leaves)
+        other_plans.append((otn, tnc.Plan(otn, opath.pairs, opath.sliced)))
+    other_alone = [p.contract().copy() for _, p in other_plans]
+
+    tnc.tnc_serve_start(ctx.handle, 8, 1024)
+    with pytest.raises(tnc.TncError) as e:
+        tnc.tnc_submit(ctx.handle, plan.handle, 0, 1, np.zeros(B, dtype=np.complex128))
+    assert e.value.status == tnc.E_BUSY
+    outs, ids, oids = [], [], []
+    eye = np.eye(2, dtype=np.complex128)
+    for i in range(n_req):
+        out = np.zeros(1, dtype=np.complex128)
+        outs.append(out)
+        ids.append(tnc.tnc_submit_row(ctx.handle, batcher.handle, [eye[bits[i, q]] for q in range(nq)], out))
+        if i % 10 == 0:
+            o = np.zeros(1, dtype=np.complex128)
+            oids.append((tnc.tnc_submit(ctx.handle, other_plans[0][1].handle, 0, 1, o), o))
+    lat = [tnc.tnc_wait(ctx.handle, rid) for rid in ids]
+    for rid, _ in oids:
+        tnc.tnc_wait(ctx.handle, rid)
+    tnc.tnc_serve_stop(ctx.handle)
+    print(f"batcher: {n_req} rows, p50 latency {1e3 * np.median(lat):.2f} ms", flush=True)
+
+    got = np.array([o[0] for o in outs])
+    assert np.array_equal(got.view(np.uint64), ref.view(np.uint64))
+    assert np.array_equal(got[24:28].view(np.uint64), got[0:4].view(np.uint64))
+    for _, o in oids:
+        assert np.array_equal(o.view(np.uint64), other_alone[0].view(np.uint64))
+    gates = [(qs, u.astype(np.complex64).astype(np.complex128)) for qs, u in circ.gates]
+    sv = osv.run(nq, gates)
+    for i in range(n_req):
+        want = sv[tuple(int(x) for x in bits[i])]
+        assert abs(got[i] - want) <= 1e-5 * abs(want), i
+    batcher.close()
+    for otn, p in other_plans:
+        p.close()
+        otn.close()
+    plan_ref.close()
+    plan.close()
+    ctx.close()

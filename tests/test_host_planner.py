@@ -312,3 +312,68 @@ def test_launch_shape_decisions(hctx, dims, batch, kernel, swapped, split):
     assert (s.m, s.n, s.k) == (2 ** dims[0], 2 ** dims[2], 2 ** dims[1])   # logical view unchanged
     if split > 1:    # the partials sit in the arena next to the result
         assert plan.info.peak_bytes >= 8 * s.h * s.m * s.n * (split + 1)
+
+
+def _batched_circuit(n_rows=16):
+    from workloads.circuits import circuit_network_batched
+    circ = configs.circuit12_circuit()
+    bits = np.zeros((n_rows, circ.n_qubits), dtype=np.int64)
+    return circuit_network_batched(circ, bits)
+
+
+def test_batcher_validation_and_cache_exclusion(hctx):
+    """A batcher needs its batch label open, leading the open list and
+    outermost in every leaf that carries it; one batcher per network; its
+    leaves leave the plan's leaf cache.  All decided on the host."""
+    net = _batched_circuit()
+    beta = net.open[0]
+    carriers = [t for t, lab in enumerate(net.labels) if beta in lab]
+    assert len(carriers) == 12 and all(net.labels[t][0] == beta for t in carriers)
+    path = greedy_path(net)
+    tn = tnc.Network(hctx, net.labels, net.extents, net.open)
+    plan = tnc.Plan(tn, path.pairs)
+    cached_before = tnc.tnc_plan_get_info(plan.handle).n_cached_leaves
+
+    def err(label, leaves):
+        with pytest.raises(tnc.TncError) as e:
+            tnc.Batcher(plan, label, leaves)
+        return e.value.status
+
+    closed = next(l for l in range(len(net.extents)) if l not in net.open)
+    assert err(closed, carriers) == tnc.E_ARG                 # not open
+    assert err(beta, carriers[:-1]) == tnc.E_ARG              # a carrier left out
+    assert err(beta, carriers + [carriers[0]]) == tnc.E_ARG   # listed twice
+    other = next(t for t in range(net.n_leaves) if t not in carriers)
+    assert err(beta, carriers + [other]) == tnc.E_ARG         # leaf without the label
+    b = tnc.Batcher(plan, beta, carriers)
+    assert err(beta, carriers) == tnc.E_BUSY                  # one batcher per network
+    assert tnc.tnc_plan_get_info(plan.handle).n_result == 16
+    assert tnc.tnc_plan_get_info(plan.handle).n_cached_leaves == cached_before  # projectors: stored as targeted
+    b.close()
+    tnc.Batcher(plan, beta, carriers).close()                # free again after destroy
+
+    # the label must lead the open list and be the outermost stored mode
+    perm_net = Network(net.leaves, [tuple(reversed(l)) if t in carriers else l
+                                    for t, l in enumerate(net.labels)], net.extents, net.open)
+    tn2 = tnc.Network(hctx, perm_net.labels, perm_net.extents, perm_net.open)
+    plan2 = tnc.Plan(tn2, path.pairs)
+    with pytest.raises(tnc.TncError) as e:
+        tnc.Batcher(plan2, beta, carriers)
+    assert e.value.status == tnc.E_ARG
+
+
+def test_batcher_leaves_leave_the_leaf_cache(hctx):
+    """A batch-labelled leaf stored (beta, j, i) is targeted (beta, i, j)
+    (reduced modes ascending): without a batcher it is permuted once into the
+    leaf cache; a batcher rewrites it before every run, so the re-planned
+    chunk permutes it per run instead."""
+    labels = [(2, 1, 0), (0, 1)]
+    ext = np.array([3, 5, 4], dtype=np.int64)
+    tn = tnc.Network(hctx, labels, ext, (2,))
+    plan = tnc.Plan(tn, [(0, 1)])
+    assert plan.order(0) == [2, 0, 1]
+    assert tnc.tnc_plan_get_info(plan.handle).n_cached_leaves == 1
+    b = tnc.Batcher(plan, 2, [0])
+    assert tnc.tnc_plan_get_info(plan.handle).n_cached_leaves == 0
+    assert tnc.tnc_plan_get_info(plan.handle).n_permutes == 1
+    b.close()
