@@ -216,19 +216,23 @@ struct Server {
         std::lock_guard<std::mutex> g(mu);
         Request& r = *job[0];
         arena.release(r.arena_off, r.need);
+        if (r.heavy_slot) --heavy_inflight;
+        --inflight;
+        if (r.batcher) {
+          std::shared_ptr<Batcher> b = r.batcher;
+          b->busy = false;
+          if (!b->rows.empty()) enqueue_token(b);  // rows that came in meanwhile
+          // drop the rows' references before they are marked done: with its
+          // handle destroyed and no rows left the batcher releases its
+          // network here, before any waiter returns
+          for (auto& q : job) q->batcher.reset();
+        }
         const Clock::time_point now = Clock::now();
         for (auto& q : job) {
           q->t_done = now;
           q->done = true;
           q->row.clear();
           q->row.shrink_to_fit();
-        }
-        if (r.heavy_slot) --heavy_inflight;
-        --inflight;
-        if (r.batcher) {
-          Batcher& b = *r.batcher;
-          b.busy = false;
-          if (!b.rows.empty()) enqueue_token(r.batcher);  // rows that came in meanwhile
         }
       }
       cv_work.notify_all();

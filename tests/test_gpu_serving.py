@@ -319,3 +319,48 @@ def test_batcher_rows_match_batched_contract_and_state_vector():
     plan_ref.close()
     plan.close()
     ctx.close()
+
+
+def test_batcher_sliced_plan_odd_batch_and_early_destroy():
+    """A batcher over a sliced plan (two sliced labels, every batch sums all
+    slices in FP64) with B = 5 rows: 23 row requests match the state vector
+    within 1e-5.  The batcher handle is destroyed while its rows are still
+    queued (they run), and its network then takes ordinary requests again."""
+    from oracle import statevector as osv
+    from workloads import configs
+    from workloads.circuits import circuit_network_batched
+    circ = configs.circuit12_circuit()
+    nq, B, n_req = circ.n_qubits, 5, 23
+    bits = np.random.Generator(np.random.PCG64(77)).integers(0, 2, size=(n_req, nq))
+    arena = torch.empty(2 << 30, dtype=torch.uint8, device="cuda")
+    ctx = tnc.Context(0, arena_bytes=arena.numel(), arena_ptr=arena.data_ptr())
+    net = circuit_network_batched(circ, np.zeros((B, nq), dtype=np.int64))
+    beta = net.open[0]
+    carriers = [t for t, lab in enumerate(net.labels) if beta in lab]
+    path = greedy_path(net)
+    sl = greedy_slice(net, path.pairs, n_sliced=2)
+    assert len(sl) == 2
+    tn = tnc.Network(ctx, net.labels, net.extents, net.open, net.c64().leaves)
+    plan = tnc.Plan(tn, path.pairs, sl)
+    assert plan.info.n_slices == 4
+    batcher = tnc.Batcher(plan, beta, carriers)
+    eye = np.eye(2, dtype=np.complex128)
+    tnc.tnc_serve_start(ctx.handle, 4, 256)
+    outs = [np.zeros(1, dtype=np.complex128) for _ in range(n_req)]
+    ids = [tnc.tnc_submit_row(ctx.handle, batcher.handle, [eye[bits[i, q]] for q in range(nq)], outs[i])
+           for i in range(n_req)]
+    batcher.close()                                   # rows still queued keep it alive
+    for rid in ids:
+        tnc.tnc_wait(ctx.handle, rid)
+    # the last row is done, so the network is free for ordinary requests again
+    whole = np.zeros(B, dtype=np.complex128)
+    tnc.tnc_wait(ctx.handle, tnc.tnc_submit(ctx.handle, plan.handle, 0, plan.info.n_slices, whole))
+    tnc.tnc_serve_stop(ctx.handle)
+    gates = [(qs, u.astype(np.complex64).astype(np.complex128)) for qs, u in circ.gates]
+    sv = osv.run(nq, gates)
+    for i in range(n_req):
+        want = sv[tuple(int(x) for x in bits[i])]
+        assert abs(outs[i][0] - want) <= 1e-5 * abs(want), i
+    plan.close()
+    tn.close()
+    ctx.close()
