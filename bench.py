@@ -31,6 +31,7 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 PEAK_FP32_MFMA = 157.3   # TFLOP/s, MI355X dense FP32 matrix
+PEAK_HBM_TBS = 8.0       # TB/s, MI355X HBM3E
 PEAK_BF16_MFMA = 2516.6  # TFLOP/s, MI355X dense bf16 matrix
 PEAK_HBM = 8000.0        # GB/s
 
@@ -42,6 +43,23 @@ PEAK_HBM = 8000.0        # GB/s
 # the tiles running at once are re-read per K stage.  Set to None when the
 # kernel changes.
 GEMM_TRAFFIC_BYTES = 750.6e9
+
+
+def path_roofline_s(tnc, plan, n_runs: int = 1, leaf_permutes: bool = True) -> float:
+    """The Sec. IV cost model as the path's roofline: every step of one
+    device batch at max(its algorithmic bytes 8 (hA m k + hB n k + h m n) /
+    8 TB/s, its FLOPs 8 h m n k / 157.3 TFLOP/s), plus the leaf permutes at
+    16 bytes per element / 8 TB/s; times the number of batches run."""
+    info = tnc.tnc_plan_get_info(plan.handle)
+    t = 0.0
+    for s in range(info.n_steps):
+        st = tnc.tnc_plan_get_batch_step(plan.handle, s)
+        fl = 8.0 * st.h * st.m * st.n * st.k
+        by = 8.0 * (st.hA * st.m * st.k + st.hB * st.n * st.k + st.h * st.m * st.n)
+        t += max(by / (PEAK_HBM_TBS * 1e12), fl / (PEAK_FP32_MFMA * 1e12))
+    if leaf_permutes:
+        t += info.transpose_bytes / (PEAK_HBM_TBS * 1e12)
+    return t * n_runs
 
 
 def log(msg: str) -> None:
@@ -107,11 +125,20 @@ def cpu_baseline(net_a, path_a, net_b, path_b, n_fixed: int = 6):
     dt2 = time.perf_counter() - t0
     t_total += dt2
     flops_total += 8.0 * 4 * 1024 * 256 * 1024
-    threads = max((i.get("num_threads", 1) for i in threadpool_info()), default=1)
+    pools = threadpool_info()
+    threads = max((i.get("num_threads", 1) for i in pools), default=1)
+    blas = ", ".join(sorted({f"{i.get('internal_api', '?')} {i.get('version', '')}".strip() for i in pools})) or "?"
+    cpu = "?"
+    try:
+        with open("/proc/cpuinfo") as f:
+            cpu = next((ln.split(":", 1)[1].strip() for ln in f if ln.startswith("model name")), "?")
+    except OSError:
+        pass
     return {"value": flops_total / t_total / 1e12, "unit": "complex TFLOP/s", "cores": int(threads),
             "kind": "oracle",
             "sample": f"pair30 rows with {n_fixed} leading M labels fixed (1/{2 ** n_fixed} of the work, {dt:.1f} s) + 4 of 64 "
-                      f"batch entries ({dt2:.1f} s); numpy complex128 tensordot incl. operand transposes"}
+                      f"batch entries ({dt2:.1f} s); numpy complex128 tensordot incl. operand transposes; "
+                      f"{cpu}, BLAS {blas}"}
 
 
 HEAVY_FLOPS = 2.0 ** 38   # requests planned at >= this many FLOP share one heavy slot
@@ -455,6 +482,26 @@ def bench_circuit40(args):
             perm_steps += 1
             avoided += 16.0 * st.h * st.m * st.n * n_chunks
     log(f"{perm_steps} of {info.n_steps} steps store in consumer order: {avoided / 1e9:.1f} GB of transposes avoided")
+    roof_s = path_roofline_s(tnc, plan, n_chunks, leaf_permutes=False)
+    log(f"path roofline (GEMM steps of the batched run): {roof_s * 1e3:.1f} ms = {roof_s / dt:.3f} of the measured")
+    # the same slices contracted one at a time (a chunk of one slice), the
+    # per-slice loop whose cost the paper projects as t_slice * 2^b
+    single = tnc.Plan(tn, path.pairs, path.sliced, prec, form)
+    tnc.tnc_plan_set_max_chunk(single.handle, 1)
+    tnc.tnc_plan_set_graph(single.handle, True)
+    tnc.tnc_plan_autotune(single.handle)
+    n_loop = 32
+    for i in range(2):
+        single.contract(i, 1)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    for i in range(n_loop):
+        single.contract(i, 1)
+    torch.cuda.synchronize()
+    t_slice = (time.perf_counter() - t1) / n_loop
+    single.close()
+    log(f"one slice at a time: {t_slice * 1e3:.2f} ms per slice -> {t_slice * n:.1f} s for {n} slices "
+        f"(batched: {dt:.2f} s, {t_slice * n / dt:.1f}x)")
     res = {"metric": "complex TFLOP/s of path execution (% MFMA peak) + p50/p99 request latency",
            "value": round(value, 3), "unit": "complex TFLOP/s", "n_gpus": 1, "steps": args.steps,
            "warmup": args.warmup, "ms_per_step": round(dt * 1e3, 3), "higher_is_better": True,
@@ -463,7 +510,11 @@ def bench_circuit40(args):
            "config": {"workload": "circuit40: 5x8 grid, depth 12, 16 sliced labels", "slices": n,
                       "chunk": info.max_chunk, "amplitude": [z[0].real, z[0].imag],
                       "permuted_store_steps": perm_steps, "transposes_avoided_gb": round(avoided / 1e9, 2),
-                      "per_slice_equivalent_tflops": round(info.flops_per_slice * n / dt / 1e12, 3)}}
+                      "per_slice_equivalent_tflops": round(info.flops_per_slice * n / dt / 1e12, 3),
+                      "path_roofline_frac": round(roof_s / dt, 4),
+                      "slice_loop_ms_per_slice": round(t_slice * 1e3, 3),
+                      "slice_loop_extrapolated_s": round(t_slice * n, 2),
+                      "batched_speedup_vs_slice_loop": round(t_slice * n / dt, 2)}}
     print(json.dumps(res), flush=True)
 
 
@@ -571,7 +622,9 @@ def main():
         "config": {"workload": "pair30+pair_batch64: A 30 modes x B 28 modes (14 shared, 2^30 outputs) and "
                                "64 x (20 x 18 modes, 10 shared); extents 2; random stored mode orders",
                    "form": args.form, "prec": args.prec, "scale": args.scale,
-                   "pct_fp32_mfma_peak": round(100 * value / PEAK_FP32_MFMA, 1)},
+                   "pct_fp32_mfma_peak": round(100 * value / PEAK_FP32_MFMA, 1),
+                   "path_roofline_frac": round((path_roofline_s(tnc, plan_a) + path_roofline_s(tnc, plan_b))
+                                               / (dt / args.steps), 4)},
         "roofline": {"bound": "mfma", "achieved": round(achieved, 3), "peak": round(peak, 1),
                      "unit": "TFLOP/s", "frac": round(achieved / peak, 4), "traffic": GEMM_TRAFFIC_BYTES},
         "measured_ceilings": {"fp32_mfma_tflops": round(hw.flops_per_s / 1e12, 2),

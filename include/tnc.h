@@ -169,6 +169,9 @@ typedef struct {
   int32_t swapped;               /* 1 = the GEMM runs transposed (B supplies
                                     the rows) because that fills MFMA tiles   */
   int32_t split;                 /* K cut into this many parts (split-K)       */
+  int64_t hA, hB;                /* batch entries A and B hold (1 = broadcast
+                                    over the batch): the algorithmic bytes of
+                                    the step are 8 (hA m k + hB n k + h m n)  */
 } tnc_step_info;
 tnc_status tnc_plan_get_step(tnc_plan plan, int32_t step, tnc_step_info* out);
 /* The same view for the batch of max_chunk slices the executor runs (h then

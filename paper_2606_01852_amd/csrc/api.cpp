@@ -360,6 +360,8 @@ static void step_info(const ChunkPlan& c, int32_t step, tnc_step_info* out) {
   i.variant = s.variant;
   i.swapped = s.swap ? 1 : 0;
   i.split = s.split;
+  i.hA = s.hA;
+  i.hB = s.hB;
   *out = i;
 }
 
