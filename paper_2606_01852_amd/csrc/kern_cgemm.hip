@@ -237,8 +237,26 @@ struct Stage {
   }
 };
 
-__device__ __forceinline__ int64_t c_index(const GemmDesc& d, bool perm, int64_t b, int64_t row, int64_t col) {
-  return b * d.m * d.n + (perm ? d.offM[row] + d.offN[col] : row * d.n + col);
+// Output offsets within one batch entry of C, in complex elements: a row's
+// (offM[row], or row * n) plus a column's (offN[col], or col); -1 marks a
+// row or column outside C.  Epilogues read them into registers before
+// issuing any store: C and the store tables are different arrays, but the
+// compiler cannot know it, so a table read between two stores would wait
+// for each read in turn.
+__device__ __forceinline__ int64_t col_offset(const GemmDesc& d, bool perm, int64_t col) {
+  return col < d.n ? (perm ? d.offN[col] : col) : -1;
+}
+
+// Rows 8*(v>>2) + 4*h + (v&3) of a 32-row MFMA block starting at row0, for
+// v = v0 .. v0+7 (the accumulator layout of a 32x32 MFMA).
+__device__ __forceinline__ void row_offsets8(const GemmDesc& d, bool perm, int64_t row0, int h, int v0,
+                                             int64_t (&o)[8]) {
+#pragma unroll
+  for (int u = 0; u < 8; ++u) {
+    const int v = v0 + u;
+    const int64_t row = row0 + 8 * (v >> 2) + 4 * h + (v & 3);
+    o[u] = row < d.m ? (perm ? d.offM[row] : row * d.n) : -1;
+  }
 }
 
 // ------------------------------------------------------------------ 4M, FP32 MFMA
@@ -299,18 +317,23 @@ struct Ops4M {
   __device__ __forceinline__ void store(const GemmDesc& d, bool perm, const TileCoord& tc, int wm, int wn,
                                         int lane) const {
     const int h = lane >> 5, l32 = lane & 31;
-    float* C = reinterpret_cast<float*>(d.C);
+    // real column tc.col0*2 + wn*64 + j*32 + l32: complex column >> 1, re/im by parity
+    float* C = reinterpret_cast<float*>(d.C + tc.b * d.m * d.n) + (l32 & 1);
+    int64_t co[2];
+#pragma unroll
+    for (int j = 0; j < 2; ++j) co[j] = col_offset(d, perm, (tc.col0 * 2 + wn * 64 + j * 32 + l32) >> 1);
 #pragma unroll
     for (int i = 0; i < 2; ++i)
 #pragma unroll
-      for (int j = 0; j < 2; ++j) {
-        const int64_t ncr = tc.col0 * 2 + wn * 64 + j * 32 + l32;  // real column
-        const int64_t col = ncr >> 1;
-        if (col >= d.n) continue;
+      for (int v0 = 0; v0 < 16; v0 += 8) {
+        int64_t ro[8];
+        row_offsets8(d, perm, tc.row0 + wm * 64 + i * 32, h, v0, ro);
 #pragma unroll
-        for (int v = 0; v < 16; ++v) {
-          const int64_t row = tc.row0 + wm * 64 + i * 32 + 8 * (v >> 2) + 4 * h + (v & 3);
-          if (row < d.m) C[2 * c_index(d, perm, tc.b, row, col) + (ncr & 1)] = acc[i][j][v];
+        for (int j = 0; j < 2; ++j) {
+          if (co[j] < 0) continue;
+#pragma unroll
+          for (int u = 0; u < 8; ++u)
+            if (ro[u] >= 0) C[2 * (ro[u] + co[j])] = acc[i][j][v0 + u];
         }
       }
   }
@@ -362,18 +385,24 @@ struct Ops3M {
   __device__ __forceinline__ void store(const GemmDesc& d, bool perm, const TileCoord& tc, int wm, int wn,
                                         int lane) const {
     const int h = lane >> 5, l32 = lane & 31;
-    const int64_t col = tc.col0 + wn * 32 + l32;
-    if (col >= d.n) return;
+    const int64_t co = col_offset(d, perm, tc.col0 + wn * 32 + l32);
+    if (co < 0) return;
+    float2* C = d.C + tc.b * d.m * d.n + co;
 #pragma unroll
     for (int i = 0; i < 2; ++i)
 #pragma unroll
-      for (int v = 0; v < 16; ++v) {
-        const int64_t row = tc.row0 + wm * 64 + i * 32 + 8 * (v >> 2) + 4 * h + (v & 3);
-        if (row < d.m) {
-          float2 o;
-          o.x = t1[i][v] - t2[i][v];
-          o.y = t3[i][v] - t1[i][v] - t2[i][v];
-          d.C[c_index(d, perm, tc.b, row, col)] = o;
+      for (int v0 = 0; v0 < 16; v0 += 8) {
+        int64_t ro[8];
+        row_offsets8(d, perm, tc.row0 + wm * 64 + i * 32, h, v0, ro);
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+          const int v = v0 + u;
+          if (ro[u] >= 0) {
+            float2 o;
+            o.x = t1[i][v] - t2[i][v];
+            o.y = t3[i][v] - t1[i][v] - t2[i][v];
+            C[ro[u]] = o;
+          }
         }
       }
   }
@@ -453,18 +482,22 @@ struct OpsBF16x3 {
   __device__ __forceinline__ void store(const GemmDesc& d, bool perm, const TileCoord& tc, int wm, int wn,
                                         int lane) const {
     const int h = lane >> 5, l32 = lane & 31;
-    float* C = reinterpret_cast<float*>(d.C);
+    float* C = reinterpret_cast<float*>(d.C + tc.b * d.m * d.n) + (l32 & 1);
+    int64_t co[2];
+#pragma unroll
+    for (int j = 0; j < 2; ++j) co[j] = col_offset(d, perm, (tc.col0 * 2 + wn * 64 + j * 32 + l32) >> 1);
 #pragma unroll
     for (int i = 0; i < 2; ++i)
 #pragma unroll
-      for (int j = 0; j < 2; ++j) {
-        const int64_t ncr = tc.col0 * 2 + wn * 64 + j * 32 + l32;
-        const int64_t col = ncr >> 1;
-        if (col >= d.n) continue;
+      for (int v0 = 0; v0 < 16; v0 += 8) {
+        int64_t ro[8];
+        row_offsets8(d, perm, tc.row0 + wm * 64 + i * 32, h, v0, ro);
 #pragma unroll
-        for (int v = 0; v < 16; ++v) {
-          const int64_t row = tc.row0 + wm * 64 + i * 32 + 8 * (v >> 2) + 4 * h + (v & 3);
-          if (row < d.m) C[2 * c_index(d, perm, tc.b, row, col) + (ncr & 1)] = acc[i][j][v] + accx[i][j][v];
+        for (int j = 0; j < 2; ++j) {
+          if (co[j] < 0) continue;
+#pragma unroll
+          for (int u = 0; u < 8; ++u)
+            if (ro[u] >= 0) C[2 * (ro[u] + co[j])] = acc[i][j][v0 + u] + accx[i][j][v0 + u];
         }
       }
   }
