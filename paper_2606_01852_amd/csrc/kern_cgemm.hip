@@ -239,10 +239,12 @@ struct Stage {
 
 // Output offsets within one batch entry of C, in complex elements: a row's
 // (offM[row], or row * n) plus a column's (offN[col], or col); -1 marks a
-// row or column outside C.  Epilogues read them into registers before
-// issuing any store: C and the store tables are different arrays, but the
-// compiler cannot know it, so a table read between two stores would wait
-// for each read in turn.
+// row or column outside C.  Permuted-store epilogues read them into
+// registers before issuing any store: C and the store tables are different
+// arrays, but the compiler cannot know it, so a table read between two
+// stores would wait for each read in turn.  (Row-major stores compute their
+// addresses inline: that keeps the main loop's register allocation, and so
+// its schedule, as it is without tables.)
 __device__ __forceinline__ int64_t col_offset(const GemmDesc& d, bool perm, int64_t col) {
   return col < d.n ? (perm ? d.offN[col] : col) : -1;
 }
@@ -319,6 +321,21 @@ struct Ops4M {
     const int h = lane >> 5, l32 = lane & 31;
     // real column tc.col0*2 + wn*64 + j*32 + l32: complex column >> 1, re/im by parity
     float* C = reinterpret_cast<float*>(d.C + tc.b * d.m * d.n) + (l32 & 1);
+    if (!perm) {  // row-major [M|N]: addresses from the indices alone
+#pragma unroll
+      for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < 2; ++j) {
+          const int64_t col = (tc.col0 * 2 + wn * 64 + j * 32 + l32) >> 1;
+          if (col >= d.n) continue;
+#pragma unroll
+          for (int v = 0; v < 16; ++v) {
+            const int64_t row = tc.row0 + wm * 64 + i * 32 + 8 * (v >> 2) + 4 * h + (v & 3);
+            if (row < d.m) C[2 * (row * d.n + col)] = acc[i][j][v];
+          }
+        }
+      return;
+    }
     int64_t co[2];
 #pragma unroll
     for (int j = 0; j < 2; ++j) co[j] = col_offset(d, perm, (tc.col0 * 2 + wn * 64 + j * 32 + l32) >> 1);
@@ -385,6 +402,24 @@ struct Ops3M {
   __device__ __forceinline__ void store(const GemmDesc& d, bool perm, const TileCoord& tc, int wm, int wn,
                                         int lane) const {
     const int h = lane >> 5, l32 = lane & 31;
+    if (!perm) {  // row-major [M|N]: addresses from the indices alone
+      const int64_t col = tc.col0 + wn * 32 + l32;
+      if (col >= d.n) return;
+      float2* C = d.C + tc.b * d.m * d.n + col;
+#pragma unroll
+      for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int v = 0; v < 16; ++v) {
+          const int64_t row = tc.row0 + wm * 64 + i * 32 + 8 * (v >> 2) + 4 * h + (v & 3);
+          if (row < d.m) {
+            float2 o;
+            o.x = t1[i][v] - t2[i][v];
+            o.y = t3[i][v] - t1[i][v] - t2[i][v];
+            C[row * d.n] = o;
+          }
+        }
+      return;
+    }
     const int64_t co = col_offset(d, perm, tc.col0 + wn * 32 + l32);
     if (co < 0) return;
     float2* C = d.C + tc.b * d.m * d.n + co;
@@ -483,6 +518,21 @@ struct OpsBF16x3 {
                                         int lane) const {
     const int h = lane >> 5, l32 = lane & 31;
     float* C = reinterpret_cast<float*>(d.C + tc.b * d.m * d.n) + (l32 & 1);
+    if (!perm) {  // row-major [M|N]: addresses from the indices alone
+#pragma unroll
+      for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < 2; ++j) {
+          const int64_t col = (tc.col0 * 2 + wn * 64 + j * 32 + l32) >> 1;
+          if (col >= d.n) continue;
+#pragma unroll
+          for (int v = 0; v < 16; ++v) {
+            const int64_t row = tc.row0 + wm * 64 + i * 32 + 8 * (v >> 2) + 4 * h + (v & 3);
+            if (row < d.m) C[2 * (row * d.n + col)] = acc[i][j][v] + accx[i][j][v];
+          }
+        }
+      return;
+    }
     int64_t co[2];
 #pragma unroll
     for (int j = 0; j < 2; ++j) co[j] = col_offset(d, perm, (tc.col0 * 2 + wn * 64 + j * 32 + l32) >> 1);
