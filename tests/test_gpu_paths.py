@@ -206,6 +206,29 @@ def test_direct_device_output_single_contraction(ctx):
     assert rel_fro(out.cpu().numpy().reshape(ref.shape), ref) <= 1e-5
 
 
+def test_async_outputs_and_context_sync(ctx):
+    """tnc_contract_async into a complex128 device buffer (FP64 sum over a
+    sliced range) and into complex64, completed by tnc_ctx_sync alone: equal
+    to the synchronous result (bitwise for complex128, its rounding for
+    complex64)."""
+    net, path = configs.circuit12(open_qubits=(0, 5))
+    sl = greedy_slice(net, path.pairs, n_sliced=2)
+    tn = tnc.Network(ctx, net.labels, net.extents, net.open, net.c64().leaves)
+    plan = tnc.Plan(tn, path.pairs, sl)
+    want = plan.contract()
+    n = plan.info.n_result
+    out128 = torch.empty(n, dtype=torch.complex128, device="cuda")
+    out64 = torch.empty(n, dtype=torch.complex64, device="cuda")
+    tnc.tnc_contract_async(plan.handle, 0, plan.info.n_slices, out128.data_ptr(), tnc.OUT_C128)
+    tnc.tnc_ctx_sync(ctx.handle)
+    got128 = out128.cpu().numpy()
+    tnc.tnc_contract_async(plan.handle, 0, plan.info.n_slices, out64.data_ptr(), tnc.OUT_C64)
+    tnc.tnc_ctx_sync(ctx.handle)
+    got64 = out64.cpu().numpy()
+    assert np.array_equal(got128.view(np.uint64), np.asarray(want).view(np.uint64))
+    assert np.array_equal(got64, np.asarray(want).astype(np.complex64))
+
+
 def test_degenerate_networks(ctx):
     rng = np.random.Generator(np.random.PCG64(8))
     # one leaf, no steps, result in a permuted order

@@ -364,3 +364,30 @@ def test_batcher_sliced_plan_odd_batch_and_early_destroy():
     plan.close()
     tn.close()
     ctx.close()
+
+
+def test_poll_reports_completion_and_unknown_ids(served):
+    """tnc_poll says "not done" (latency 0) until the request finishes, then
+    done with its latency; the polled result equals the request alone; an id
+    already collected by tnc_wait is unknown (TNC_E_ARG)."""
+    import time
+    ctx, pool, nets, plans = served
+    alone, _ = run_all(ctx, plans, [1], 1)
+    tnc.tnc_serve_start(ctx.handle, 2, 64)
+    out = np.zeros(1, dtype=np.complex128)
+    rid = tnc.tnc_submit(ctx.handle, plans[1].handle, 0, plans[1].info.n_slices, out)
+    t0 = time.time()
+    while True:
+        done, lat = tnc.tnc_poll(ctx.handle, rid)
+        if done:
+            break
+        assert lat == 0.0
+        assert time.time() - t0 < 60, "request did not finish"
+        time.sleep(0.0005)
+    assert lat > 0.0
+    assert tnc.tnc_wait(ctx.handle, rid) == lat
+    with pytest.raises(tnc.TncError) as e:
+        tnc.tnc_poll(ctx.handle, rid)
+    assert e.value.status == tnc.E_ARG
+    tnc.tnc_serve_stop(ctx.handle)
+    assert np.array_equal(out.view(np.uint64), alone[1].view(np.uint64))

@@ -39,6 +39,11 @@ def test_library_exports_every_declared_symbol():
     assert "gfx950" in tnc.tnc_version()
 
 
+def test_device_count_never_fails():
+    n = tnc.tnc_device_count()
+    assert isinstance(n, int) and n >= 0
+
+
 @pytest.fixture(scope="module")
 def hctx():
     return tnc.Context(-1)
