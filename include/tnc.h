@@ -293,7 +293,8 @@ tnc_status tnc_ctx_sync(tnc_ctx ctx);
  * past it.  Otherwise admission is in submission order (a request that does
  * not fit the free arena yet blocks the ones behind it).  out_c128 (host
  * pointer) must stay valid until the request is done.  TNC_E_BUSY if the
- * queue is full; TNC_E_NOMEM if the request can never fit. */
+ * queue is full or the plan's network has a batcher (see below);
+ * TNC_E_NOMEM if the request can never fit. */
 tnc_status tnc_serve_start(tnc_ctx ctx, int32_t max_inflight, int32_t queue_cap);
 /* Heavy-request lane: threshold in planned FLOPs (<= 0 disables the lane)
  * and the number of heavy requests that may run at once (>= 1).  Applies to
