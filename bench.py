@@ -95,10 +95,10 @@ def parse():
     return ap.parse_args()
 
 
-def cpu_baseline(net_a, path_a, net_b, path_b, n_fixed: int = 6):
+def cpu_baseline(net_a, path_a, net_b, path_b, n_fixed: int = 5):
     """The oracle (complex128 numpy) on a bounded sample: the big contraction
-    with its n_fixed leading M labels fixed to one value (1/64 of the rows
-    for 6, about 15 s on 16 host threads) and 4 of the 64 batch entries.
+    with its n_fixed leading M labels fixed to one value (1/32 of the rows
+    for 5, about 10 s on 16 host threads) and 4 of the 64 batch entries.
     Rate = sample FLOPs (8 per complex MAC) / time."""
     from threadpoolctl import threadpool_info
 
@@ -106,7 +106,7 @@ def cpu_baseline(net_a, path_a, net_b, path_b, n_fixed: int = 6):
     from workloads.network import Network, Path
 
     t_total, flops_total = 0.0, 0.0
-    # big pair: fix M labels 0..7 (open labels; taken as a sub-network)
+    # big pair: fix the leading M labels (open labels; taken as a sub-network)
     a, b = net_a.leaves
     la, lb = net_a.labels
     fix = {l: 0 for l in range(n_fixed)}
