@@ -78,13 +78,17 @@ def test_permute_bit_exact(ctx, name, ext, perm):
 
 
 GEMM_SHAPES = [
-    (1, 128, 64, 16),      # exactly one tile
-    (1, 200, 100, 50),     # ragged m, n, k
-    (2, 300, 70, 33),      # odd k: 8-byte loads
+    (512, 128, 64, 16),    # exactly one MFMA tile per batch entry
+    (24, 200, 100, 50),    # ragged m, n, k on MFMA tiles
+    (20, 300, 70, 33),     # odd k: 8-byte loads
     (3, 1000, 500, 600),   # many tiles, batch
     (1, 4096, 1024, 256),
     (5, 10, 3, 4),         # small-shape kernel
-    (7, 64, 32, 16),       # smallest MFMA shape
+    (160, 64, 32, 16),     # smallest MFMA shape
+    (1, 128, 64, 16),      # the same shapes with under 2^22 MACs and short K:
+    (1, 200, 100, 50),     #   one thread per output
+    (2, 300, 70, 33),
+    (7, 64, 32, 16),
     (1, 1, 1, 1),
     (3, 1, 1, 5000),       # long-K dot kernel
     (2, 4, 8, 1024),       # long-K dot kernel, several outputs
@@ -139,9 +143,9 @@ def split_emulated_gemm(A, B):
     return (prod3(ar, br) - prod3(ai, bi)) + 1j * (prod3(ar, bi) + prod3(ai, br))
 
 
-@pytest.mark.parametrize("shape", [(1, 256, 128, 64), (2, 130, 70, 33), (3, 20, 5, 7), (2, 2, 3, 700),
-                                   (8, 16, 200, 512)],
-                         ids=["tiles", "ragged", "small", "dot", "skinny"])
+@pytest.mark.parametrize("shape", [(4, 256, 128, 64), (16, 130, 70, 33), (3, 20, 5, 7), (2, 2, 3, 700),
+                                   (8, 16, 200, 512), (1, 256, 128, 64)],
+                         ids=["tiles", "ragged", "small", "dot", "skinny", "short_k_small"])
 def test_cgemm_bf16x3_matches_split_emulation(ctx, shape):
     h, m, n, k = shape
     rng = np.random.Generator(np.random.PCG64(m + n + k))

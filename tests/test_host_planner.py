@@ -305,6 +305,8 @@ def test_slice_invariant_work_runs_once_per_batch(hctx):
     ((10, 9, 8), 1, 0, 0, 4),       # 32 tiles, k = 512: K cut 4 ways (parts of 128)
     ((12, 9, 10), 1, 0, 0, 1),      # 512 tiles of 128 x 64: no split
     ((2, 3, 2), 1, 1, 0, 1),        # tiny: one thread per output
+    ((6, 6, 6), 1, 1, 0, 1),        # 64 x 64 x 64 (2^18 MACs, short K): one thread per output
+    ((8, 7, 8), 1, 0, 0, 1),        # 256 x 256 x 128 (2^23 MACs): MFMA, K too short to split
 ])
 def test_launch_shape_decisions(hctx, dims, batch, kernel, swapped, split):
     """Kernel, orientation and split-K choice per step shape (host rules)."""
