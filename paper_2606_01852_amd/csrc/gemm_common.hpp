@@ -43,4 +43,50 @@ __device__ __forceinline__ void split_mul(float a, float b, float& hi, float& cr
   cross = ah * bl + al * bh;
 }
 
+// c += x * y for one complex product, in the fixed order the one-thread-
+// per-output kernels use (split precision: hi products into cr/ci, cross
+// products into crx/cix).
+template <bool SPLIT>
+__device__ __forceinline__ void cmac(float2 x, float2 y, float& cr, float& ci, float& crx, float& cix) {
+  if constexpr (SPLIT) {
+    float h1, x1, h2, x2, h3, x3, h4, x4;
+    split_mul(x.x, y.x, h1, x1);
+    split_mul(x.y, y.y, h2, x2);
+    split_mul(x.x, y.y, h3, x3);
+    split_mul(x.y, y.x, h4, x4);
+    cr += h1;
+    cr -= h2;
+    ci += h3;
+    ci += h4;
+    crx += x1 - x2;
+    cix += x3 + x4;
+  } else {
+    cr = fmaf(x.x, y.x, cr);
+    cr = fmaf(-x.y, y.y, cr);
+    ci = fmaf(x.x, y.y, ci);
+    ci = fmaf(x.y, y.x, ci);
+  }
+}
+
+// sum over l < k of A[l] * B[l], accumulated in order l = 0, 1, ...: the
+// elements are loaded four at a time ahead of their products (eight loads
+// in flight instead of two per step of a latency-bound loop); the rounding
+// sequence is that of the plain loop.
+template <bool SPLIT>
+__device__ __forceinline__ void cdot_serial(const float2* A, const float2* B, int64_t k, float& cr, float& ci,
+                                            float& crx, float& cix) {
+  int64_t l = 0;
+  for (; l + 4 <= k; l += 4) {
+    float2 x[4], y[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      x[u] = A[l + u];
+      y[u] = B[l + u];
+    }
+#pragma unroll
+    for (int u = 0; u < 4; ++u) cmac<SPLIT>(x[u], y[u], cr, ci, crx, cix);
+  }
+  for (; l < k; ++l) cmac<SPLIT>(A[l], B[l], cr, ci, crx, cix);
+}
+
 }  // namespace tnc

@@ -30,28 +30,7 @@ __global__ __launch_bounds__(256) void cgemm_small(GemmDesc d) {
     const float2* a = d.A + oa + i * row_stride(d);
     const float2* bb = d.B + ob + j * row_stride(d);
     float cr = 0.f, ci = 0.f, crx = 0.f, cix = 0.f;
-    for (int64_t l = 0; l < d.k; ++l) {
-      const float2 x = a[l];
-      const float2 y = bb[l];
-      if constexpr (SPLIT) {
-        float h1, x1, h2, x2, h3, x3, h4, x4;
-        split_mul(x.x, y.x, h1, x1);
-        split_mul(x.y, y.y, h2, x2);
-        split_mul(x.x, y.y, h3, x3);
-        split_mul(x.y, y.x, h4, x4);
-        cr += h1;
-        cr -= h2;
-        ci += h3;
-        ci += h4;
-        crx += x1 - x2;
-        cix += x3 + x4;
-      } else {
-        cr = fmaf(x.x, y.x, cr);
-        cr = fmaf(-x.y, y.y, cr);
-        ci = fmaf(x.x, y.y, ci);
-        ci = fmaf(x.y, y.x, ci);
-      }
-    }
+    cdot_serial<SPLIT>(a, bb, d.k, cr, ci, crx, cix);
     const int64_t c = b * mn + (d.offM ? d.offM[i] + d.offN[j] : r);
     if constexpr (SPLIT)
       d.C[c] = make_float2(cr + crx, ci + cix);
@@ -68,26 +47,7 @@ __global__ __launch_bounds__(256) void cgemm_small(GemmDesc d) {
 template <bool SPLIT>
 struct DotAcc {
   float cr = 0.f, ci = 0.f, crx = 0.f, cix = 0.f;
-  __device__ __forceinline__ void add(float2 x, float2 y) {
-    if constexpr (SPLIT) {
-      float h1, x1, h2, x2, h3, x3, h4, x4;
-      split_mul(x.x, y.x, h1, x1);
-      split_mul(x.y, y.y, h2, x2);
-      split_mul(x.x, y.y, h3, x3);
-      split_mul(x.y, y.x, h4, x4);
-      cr += h1;
-      cr -= h2;
-      ci += h3;
-      ci += h4;
-      crx += x1 - x2;
-      cix += x3 + x4;
-    } else {
-      cr = fmaf(x.x, y.x, cr);
-      cr = fmaf(-x.y, y.y, cr);
-      ci = fmaf(x.x, y.y, ci);
-      ci = fmaf(x.y, y.x, ci);
-    }
-  }
+  __device__ __forceinline__ void add(float2 x, float2 y) { cmac<SPLIT>(x, y, cr, ci, crx, cix); }
 };
 
 template <bool SPLIT>

@@ -51,28 +51,7 @@ __global__ __launch_bounds__(256) void group_small_gemm(const GroupGemm* __restr
     const float2* B = reloc<const float2>(d.B, e.rel_b, arena) + ob + j * row_stride(d);
     float2* C = reloc<float2>(d.C, e.rel_c, arena);
     float cr = 0.f, ci = 0.f, crx = 0.f, cix = 0.f;
-    for (int64_t l = 0; l < d.k; ++l) {
-      const float2 x = A[l];
-      const float2 y = B[l];
-      if constexpr (SPLIT) {
-        float h1, x1, h2, x2, h3, x3, h4, x4;
-        split_mul(x.x, y.x, h1, x1);
-        split_mul(x.y, y.y, h2, x2);
-        split_mul(x.x, y.y, h3, x3);
-        split_mul(x.y, y.x, h4, x4);
-        cr += h1;
-        cr -= h2;
-        ci += h3;
-        ci += h4;
-        crx += x1 - x2;
-        cix += x3 + x4;
-      } else {
-        cr = fmaf(x.x, y.x, cr);
-        cr = fmaf(-x.y, y.y, cr);
-        ci = fmaf(x.x, y.y, ci);
-        ci = fmaf(x.y, y.x, ci);
-      }
-    }
+    cdot_serial<SPLIT>(A, B, d.k, cr, ci, crx, cix);
     const int64_t c = b * mn + (d.offM ? d.offM[i] + d.offN[j] : r);
     if constexpr (SPLIT)
       C[c] = make_float2(cr + crx, ci + cix);
