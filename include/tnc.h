@@ -2,9 +2,9 @@
  * tnc.h -- C ABI of the MI355X (gfx950) tensor-network path executor.
  *
  * The library executes a fixed pairwise contraction path over a complex
- * tensor network on one GPU (arXiv 2606.01852, Sec. IV: "the input is a
- * contraction-path descriptor ... initial tensors, the pairwise contraction
- * sequence, and any slicing metadata").  Every step is put into GEMM form by
+ * tensor network on one GPU (arXiv 2606.01852, Sec. IV: the method takes as
+ * given the leaf tensors, the order of pairwise contractions and which labels
+ * are sliced).  Every step is put into GEMM form by
  * the GEMM-oriented mode reordering of Sec. IV-A and runs as a batched
  * complex GEMM on MFMA; operands whose stored order differs from the order
  * the step needs are permuted by an LDS-tiled transpose.
@@ -29,8 +29,8 @@
  *     across the ABI.  On error, outputs are left untouched and
  *     tnc_last_error() (thread-local) says why.  Asynchronous device faults
  *     surface as TNC_E_DEVICE at the next synchronising call.
- *   - Threads: tnc_submit / tnc_poll / tnc_wait are thread-safe; every other
- *     call is single-threaded per context.
+ *   - Threads: tnc_submit / tnc_submit_row / tnc_poll / tnc_wait are
+ *     thread-safe; every other call is single-threaded per context.
  *   - "Device pointer" means memory on the context's GPU (e.g. a torch CUDA
  *     tensor's data_ptr()); "host pointer" means ordinary host memory.
  */
@@ -212,7 +212,7 @@ tnc_status tnc_plan_get_profile(tnc_plan plan, int32_t step, double* ms, int64_t
  * last large step); along each chain a DP over the distributed modes
  * (Eq. (4) prefixes, tracked by label) chooses keep or redistribute per
  * equation under the cost model of Eq. (5)-(7), with forced redistribution
- * when a distributed mode is about to be summed and a gather at the end. */
+ * before an equation that sums a distributed mode, and a gather at the end. */
 typedef struct {
   double hbm_bytes_per_s;   /* B_dev: device memory bandwidth              */
   double flops_per_s;       /* F_dev: device peak FLOP rate                */

@@ -2,9 +2,9 @@
 
 ORACLE -- test infrastructure only (see the package header).
 
-What the pass computes (Sec. IV-A, "Backward pass and emergent lifetime
-ordering"; worked example in Fig. 3):
-  * the root's mode order is fixed by the problem (its open labels);
+What the pass computes (Sec. IV-A, its backward pass; worked example in
+Fig. 3):
+  * the root's mode order is the requested result order (its open labels);
   * visiting the steps from the last to the first, each step's output order
     is already known; each operand's order becomes
         [its labels kept by the step, in the output's order || labels summed here]

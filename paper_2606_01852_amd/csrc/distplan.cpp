@@ -8,7 +8,7 @@
 //  * the first equation distributes its output on the shortest prefix of its
 //    mode order whose extents multiply to >= P (Eq. (4)); modes are tracked
 //    by label, so the tag each label carries (the step that sums it) decides
-//    when a distributed mode is about to be summed;
+//    which equation sums a distributed mode;
 //  * every later equation keeps the inherited modes or redistributes to a
 //    fresh prefix; a distributed mode summed by the next equation forces the
 //    redistribution; the chain ends with a gather;

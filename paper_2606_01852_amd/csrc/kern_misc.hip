@@ -1,7 +1,8 @@
 // FP64 cross-slice accumulation, FP64 norm, fill and conversion kernels.
 //
-// Slicing (paper Sec. II-C) runs independent sub-networks whose partial
-// results are summed at the end.  The per-slice results come out of the
+// Slicing (paper Sec. II-C) splits the contraction into independent
+// sub-networks, one per value of the sliced labels, and the answer is the
+// total over them.  The per-slice results come out of the
 // complex64 path; their sum is formed in FP64 in a fixed order so that a
 // request's result does not depend on what else runs beside it.
 #include "kernels.hpp"
