@@ -95,10 +95,10 @@ def parse():
     return ap.parse_args()
 
 
-def cpu_baseline(net_a, path_a, net_b, path_b, n_fixed: int = 5):
+def cpu_baseline(net_a, path_a, net_b, path_b, n_fixed: int = 4):
     """The oracle (complex128 numpy) on a bounded sample: the big contraction
-    with its n_fixed leading M labels fixed to one value (1/32 of the rows
-    for 5, about 10 s on 16 host threads) and 4 of the 64 batch entries.
+    with its n_fixed leading M labels fixed to one value (1/16 of the rows
+    for 4, 10-25 s on 16 host threads) and 4 of the 64 batch entries.
     Rate = sample FLOPs (8 per complex MAC) / time."""
     from threadpoolctl import threadpool_info
 
