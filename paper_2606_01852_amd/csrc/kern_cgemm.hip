@@ -261,6 +261,51 @@ __device__ __forceinline__ void row_offsets8(const GemmDesc& d, bool perm, int64
   }
 }
 
+// Permuted store of a wave's 64 x 32 complex block held in the 4M layout
+// (MFMA 32x32 accumulators over real columns: even lanes hold the real and
+// odd lanes the imaginary part of one complex column, for rows v and v+1 of
+// each register pair).  One lane swap lets the even lane store row v's
+// complex value and the odd lane row v+1's, as 8-byte stores (half the
+// store instructions of a 4-byte store per part); each lane reads only the
+// row offsets of the rows it stores.  The swap runs in both lanes of a pair
+// whatever their row bounds (the column bound is shared by the pair).
+// val(i, j, v) is the lane's accumulated value of MFMA block (i, j), entry v.
+template <class Val>
+__device__ __forceinline__ void store_perm_pairs(const GemmDesc& d, const TileCoord& tc, int wm, int wn, int lane,
+                                                 Val val) {
+  const int h = lane >> 5, l32 = lane & 31;
+  const bool odd = l32 & 1;
+  float2* Cz = d.C + tc.b * d.m * d.n;
+  int64_t co[2];
+#pragma unroll
+  for (int j = 0; j < 2; ++j) co[j] = col_offset(d, true, (tc.col0 * 2 + wn * 64 + j * 32 + l32) >> 1);
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int v0 = 0; v0 < 16; v0 += 8) {
+      // this lane stores rows v = v0 + 2t + odd of the 32-row block
+      int64_t ro[4];
+#pragma unroll
+      for (int t = 0; t < 4; ++t) {
+        const int v = v0 + 2 * t + (odd ? 1 : 0);
+        const int64_t row = tc.row0 + wm * 64 + i * 32 + 8 * (v >> 2) + 4 * h + (v & 3);
+        ro[t] = row < d.m ? d.offM[row] : -1;
+      }
+#pragma unroll
+      for (int j = 0; j < 2; ++j) {
+        if (co[j] < 0) continue;
+#pragma unroll
+        for (int t = 0; t < 4; ++t) {
+          const float a0 = val(i, j, v0 + 2 * t), a1 = val(i, j, v0 + 2 * t + 1);
+          const int sent = __builtin_bit_cast(int, odd ? a0 : a1);
+          // quad_perm [1,0,3,2]: exchange with the neighbouring lane
+          const float got = __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, sent, 0xB1, 0xF, 0xF, false));
+          if (ro[t] >= 0) Cz[ro[t] + co[j]] = odd ? make_float2(got, a1) : make_float2(a0, got);
+        }
+      }
+    }
+}
+
 // ------------------------------------------------------------------ 4M, FP32 MFMA
 template <int WM, int WN, int VW>
 struct Ops4M {
@@ -336,42 +381,7 @@ struct Ops4M {
         }
       return;
     }
-    // Lanes 2c and 2c+1 hold the real and imaginary parts of one complex
-    // column for rows v and v+1: one lane swap lets the even lane store row
-    // v's complex value and the odd lane row v+1's, as 8-byte stores (half
-    // the store instructions of a 4-byte store per part).  The swap runs in
-    // both lanes of a pair whatever their row bounds (the column bound is
-    // shared by the pair).
-    const bool odd = l32 & 1;
-    float2* Cz = d.C + tc.b * d.m * d.n;
-    int64_t co[2];
-#pragma unroll
-    for (int j = 0; j < 2; ++j) co[j] = col_offset(d, perm, (tc.col0 * 2 + wn * 64 + j * 32 + l32) >> 1);
-#pragma unroll
-    for (int i = 0; i < 2; ++i)
-#pragma unroll
-      for (int v0 = 0; v0 < 16; v0 += 8) {
-        // this lane stores rows v = v0 + 2t + odd of the 32-row block
-        int64_t ro[4];
-#pragma unroll
-        for (int t = 0; t < 4; ++t) {
-          const int v = v0 + 2 * t + (odd ? 1 : 0);
-          const int64_t row = tc.row0 + wm * 64 + i * 32 + 8 * (v >> 2) + 4 * h + (v & 3);
-          ro[t] = row < d.m ? d.offM[row] : -1;
-        }
-#pragma unroll
-        for (int j = 0; j < 2; ++j) {
-          if (co[j] < 0) continue;
-#pragma unroll
-          for (int t = 0; t < 4; ++t) {
-            const float a0 = acc[i][j][v0 + 2 * t], a1 = acc[i][j][v0 + 2 * t + 1];
-            const int sent = __builtin_bit_cast(int, odd ? a0 : a1);
-            // quad_perm [1,0,3,2]: exchange with the neighbouring lane
-            const float got = __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, sent, 0xB1, 0xF, 0xF, false));
-            if (ro[t] >= 0) Cz[ro[t] + co[j]] = odd ? make_float2(got, a1) : make_float2(a0, got);
-          }
-        }
-      }
+    store_perm_pairs(d, tc, wm, wn, lane, [&](int i, int j, int v) { return acc[i][j][v]; });
   }
 };
 
@@ -552,23 +562,7 @@ struct OpsBF16x3 {
         }
       return;
     }
-    int64_t co[2];
-#pragma unroll
-    for (int j = 0; j < 2; ++j) co[j] = col_offset(d, perm, (tc.col0 * 2 + wn * 64 + j * 32 + l32) >> 1);
-#pragma unroll
-    for (int i = 0; i < 2; ++i)
-#pragma unroll
-      for (int v0 = 0; v0 < 16; v0 += 8) {
-        int64_t ro[8];
-        row_offsets8(d, perm, tc.row0 + wm * 64 + i * 32, h, v0, ro);
-#pragma unroll
-        for (int j = 0; j < 2; ++j) {
-          if (co[j] < 0) continue;
-#pragma unroll
-          for (int u = 0; u < 8; ++u)
-            if (ro[u] >= 0) C[2 * (ro[u] + co[j])] = acc[i][j][v0 + u] + accx[i][j][v0 + u];
-        }
-      }
+    store_perm_pairs(d, tc, wm, wn, lane, [&](int i, int j, int v) { return acc[i][j][v] + accx[i][j][v]; });
   }
 };
 
