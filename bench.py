@@ -100,8 +100,6 @@ def cpu_baseline(net_a, path_a, net_b, path_b, n_fixed: int = 4):
     with its n_fixed leading M labels fixed to one value (1/16 of the rows
     for 4, 10-25 s on 16 host threads) and 4 of the 64 batch entries.
     Rate = sample FLOPs (8 per complex MAC) / time."""
-    from threadpoolctl import threadpool_info
-
     from oracle import contract as oc
     from workloads.network import Network, Path
 
@@ -129,6 +127,16 @@ def cpu_baseline(net_a, path_a, net_b, path_b, n_fixed: int = 4):
     dt2 = time.perf_counter() - t0
     t_total += dt2
     flops_total += 8.0 * 4 * 1024 * 256 * 1024
+    threads, host = host_description()
+    return {"value": flops_total / t_total / 1e12, "unit": "complex TFLOP/s", "cores": threads,
+            "kind": "oracle",
+            "sample": f"pair30 rows with {n_fixed} leading M labels fixed (1/{2 ** n_fixed} of the work, {dt:.1f} s) + 4 of 64 "
+                      f"batch entries ({dt2:.1f} s); numpy complex128 tensordot incl. operand transposes; {host}"}
+
+
+def host_description():
+    """(BLAS threads, "CPU model, BLAS library") of this process."""
+    from threadpoolctl import threadpool_info
     pools = threadpool_info()
     threads = max((i.get("num_threads", 1) for i in pools), default=1)
     blas = ", ".join(sorted({f"{i.get('internal_api', '?')} {i.get('version') or ''}".strip() for i in pools})) or "?"
@@ -138,11 +146,28 @@ def cpu_baseline(net_a, path_a, net_b, path_b, n_fixed: int = 4):
             cpu = next((ln.split(":", 1)[1].strip() for ln in f if ln.startswith("model name")), "?")
     except OSError:
         pass
-    return {"value": flops_total / t_total / 1e12, "unit": "complex TFLOP/s", "cores": int(threads),
+    return int(threads), f"{cpu}, BLAS {blas}"
+
+
+def cpu_baseline_slices(net, path, flops_per_slice: float, n_slices: int, n_sample: int = 128):
+    """The oracle on a bounded sample of the sliced workload: n_sample seeded
+    random slices, each contracted alone along the path (numpy complex128,
+    as the paper's per-slice loop would), about 10 s on 16 host threads.
+    Rate = the sample's FLOPs (the plan's per-slice count, 8 per complex
+    MAC) / time."""
+    from oracle import contract as oc
+    rng = np.random.Generator(np.random.PCG64(1040))
+    sample = [int(x) for x in rng.choice(n_slices, min(n_sample, n_slices), replace=False)]
+    t0 = time.perf_counter()
+    for s in sample:
+        oc.contract(net, path, slices=[s])
+    dt = time.perf_counter() - t0
+    threads, host = host_description()
+    return {"value": flops_per_slice * len(sample) / dt / 1e12, "unit": "complex TFLOP/s", "cores": threads,
             "kind": "oracle",
-            "sample": f"pair30 rows with {n_fixed} leading M labels fixed (1/{2 ** n_fixed} of the work, {dt:.1f} s) + 4 of 64 "
-                      f"batch entries ({dt2:.1f} s); numpy complex128 tensordot incl. operand transposes; "
-                      f"{cpu}, BLAS {blas}"}
+            "sample": f"{len(sample)} of {n_slices} slices, each alone ({dt:.1f} s, {dt / len(sample) * 1e3:.0f} ms "
+                      f"per slice: {dt / len(sample) * n_slices:.0f} s extrapolated to all); numpy complex128 "
+                      f"tensordot; {host}"}
 
 
 HEAVY_FLOPS = 2.0 ** 38   # requests planned at >= this many FLOP share one heavy slot
@@ -520,6 +545,9 @@ def bench_circuit40(args):
                       "slice_loop_ms_per_slice": round(t_slice * 1e3, 3),
                       "slice_loop_extrapolated_s": round(t_slice * n, 2),
                       "batched_speedup_vs_slice_loop": round(t_slice * n / dt, 2)}}
+    if not args.no_cpu:
+        log("cpu baseline (oracle on a bounded sample of slices)")
+        res["cpu_baseline"] = cpu_baseline_slices(net, path, info.flops_per_slice, info.n_slices)
     print(json.dumps(res), flush=True)
 
 
