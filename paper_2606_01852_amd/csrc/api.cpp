@@ -65,24 +65,6 @@ void set_device(const Ctx& c) {
 
 using namespace tnc;
 
-#define TNC_TRY            \
-  tnc::g_error_clear();    \
-  try {
-#define TNC_CATCH                                   \
-  }                                                 \
-  catch (const tnc::Error& e) {                     \
-    tnc::g_error_set(e.msg);                        \
-    return e.code;                                  \
-  }                                                 \
-  catch (const std::bad_alloc&) {                   \
-    tnc::g_error_set("host allocation failed");     \
-    return TNC_E_NOMEM;                             \
-  }                                                 \
-  catch (const std::exception& e) {                 \
-    tnc::g_error_set(e.what());                     \
-    return TNC_E_ARG;                               \
-  }                                                 \
-  return TNC_OK;
 
 namespace tnc {
 namespace {

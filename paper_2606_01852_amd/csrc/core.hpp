@@ -9,6 +9,8 @@
 #include <cstdint>
 #include <memory>
 #include <mutex>
+#include <new>
+#include <stdexcept>
 #include <string>
 #include <vector>
 
@@ -284,6 +286,28 @@ std::vector<std::pair<int, int64_t>> decompose(const Plan& plan, int64_t first, 
 
 // Handles own a reference each: a plan keeps its network alive and a network
 // its context, so handles may be destroyed in any order.
+// Body of every C entry point: status codes and tnc_last_error() only,
+// nothing thrown across the ABI (allocation failures -> TNC_E_NOMEM, other
+// standard exceptions -> TNC_E_ARG).
+#define TNC_TRY            \
+  tnc::g_error_clear();    \
+  try {
+#define TNC_CATCH                                   \
+  }                                                 \
+  catch (const tnc::Error& e) {                     \
+    tnc::g_error_set(e.msg);                        \
+    return e.code;                                  \
+  }                                                 \
+  catch (const std::bad_alloc&) {                   \
+    tnc::g_error_set("host allocation failed");     \
+    return TNC_E_NOMEM;                             \
+  }                                                 \
+  catch (const std::exception& e) {                 \
+    tnc::g_error_set(e.what());                     \
+    return TNC_E_ARG;                               \
+  }                                                 \
+  return TNC_OK;
+
 struct tnc_ctx_s {
   std::shared_ptr<tnc::Ctx> c;
 };

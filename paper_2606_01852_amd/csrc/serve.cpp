@@ -371,8 +371,7 @@ using namespace tnc;
 extern "C" {
 
 tnc_status tnc_serve_start(tnc_ctx ctx, int32_t max_inflight, int32_t queue_cap) {
-  g_error_clear();
-  try {
+  TNC_TRY
     if (!ctx) fail(TNC_E_ARG, "ctx is NULL");
     Ctx& c = *ctx->c;
     set_device(c);
@@ -380,11 +379,7 @@ tnc_status tnc_serve_start(tnc_ctx ctx, int32_t max_inflight, int32_t queue_cap)
     if (max_inflight < 1 || max_inflight > 64 || queue_cap < 1) fail(TNC_E_ARG, "bad serving limits");
     if (c.server) fail(TNC_E_BUSY, "server already running");
     c.server = make_server(c, max_inflight, queue_cap);
-  } catch (const Error& e) {
-    g_error_set(e.msg);
-    return e.code;
-  }
-  return TNC_OK;
+  TNC_CATCH
 }
 
 tnc_status tnc_serve_set_heavy(tnc_ctx ctx, double heavy_flops, int32_t heavy_slots) {
@@ -415,8 +410,7 @@ tnc_status tnc_serve_stop(tnc_ctx ctx) {
 
 tnc_status tnc_submit(tnc_ctx ctx, tnc_plan plan, int64_t first_slice, int64_t n_slices, double* out_c128,
                       tnc_req* id) {
-  g_error_clear();
-  try {
+  TNC_TRY
     if (!ctx || !plan || !out_c128 || !id) fail(TNC_E_ARG, "NULL argument");
     Ctx& c = *ctx->c;
     Server* s = c.server.get();
@@ -451,17 +445,12 @@ tnc_status tnc_submit(tnc_ctx ctx, tnc_plan plan, int64_t first_slice, int64_t n
     }
     s->cv_work.notify_all();
     *id = r->id;
-  } catch (const Error& e) {
-    g_error_set(e.msg);
-    return e.code;
-  }
-  return TNC_OK;
+  TNC_CATCH
 }
 
 tnc_status tnc_batcher_create(tnc_plan plan, int32_t batch_label, int32_t n_leaves, const int32_t* leaves,
                               tnc_batcher* out) {
-  g_error_clear();
-  try {
+  TNC_TRY
     if (!plan || !out || n_leaves < 1 || !leaves) fail(TNC_E_ARG, "bad batcher arguments");
     Plan& p = *plan->p;
     Net& n = *p.net;
@@ -500,6 +489,20 @@ tnc_status tnc_batcher_create(tnc_plan plan, int32_t batch_label, int32_t n_leav
     p.volatile_leaf.assign(n.n_tensors, 0);
     for (int i = 0; i < n_leaves; ++i) p.volatile_leaf[leaves[i]] = 1;
     choose_chunking(p, c.arena_bytes);
+    // on failure below, the plan goes back to caching every leaf it may
+    struct Restore {
+      Plan& p;
+      size_t arena;
+      bool armed = true;
+      ~Restore() {
+        if (!armed) return;
+        p.volatile_leaf.clear();
+        try {
+          choose_chunking(p, arena);
+        } catch (...) {
+        }
+      }
+    } restore{p, c.arena_bytes};
     auto b = std::make_shared<Batcher>();
     b->plan_ref = plan->p;
     b->label = batch_label;
@@ -517,14 +520,11 @@ tnc_status tnc_batcher_create(tnc_plan plan, int32_t batch_label, int32_t n_leav
     if (!c.host_only && b->need > static_cast<int64_t>(c.arena_bytes))
       fail(TNC_E_NOMEM, "a batch needs " + std::to_string(b->need) + " arena bytes, the arena has " +
                             std::to_string(c.arena_bytes));
+    *out = new tnc_batcher_s{b};
+    restore.armed = false;
     b->plan = &p;  // from here on the batcher holds the network
     ++n.n_batchers;
-    *out = new tnc_batcher_s{b};
-  } catch (const Error& e) {
-    g_error_set(e.msg);
-    return e.code;
-  }
-  return TNC_OK;
+  TNC_CATCH
 }
 
 tnc_status tnc_batcher_destroy(tnc_batcher b) {
@@ -535,8 +535,7 @@ tnc_status tnc_batcher_destroy(tnc_batcher b) {
 
 tnc_status tnc_submit_row(tnc_ctx ctx, tnc_batcher bh, const void* const* row_data, tnc_in in, double* out_c128,
                           tnc_req* id) {
-  g_error_clear();
-  try {
+  TNC_TRY
     if (!ctx || !bh || !row_data || !out_c128 || !id) fail(TNC_E_ARG, "NULL argument");
     if (in != TNC_IN_C64 && in != TNC_IN_C128) fail(TNC_E_ARG, "unknown input type");
     Ctx& c = *ctx->c;
@@ -588,11 +587,7 @@ tnc_status tnc_submit_row(tnc_ctx ctx, tnc_batcher bh, const void* const* row_da
     }
     if (wake) s->cv_work.notify_all();
     *id = r->id;
-  } catch (const Error& e) {
-    g_error_set(e.msg);
-    return e.code;
-  }
-  return TNC_OK;
+  TNC_CATCH
 }
 
 static tnc_status finish(Request& r, double* latency_s) {
