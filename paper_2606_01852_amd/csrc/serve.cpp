@@ -383,11 +383,8 @@ tnc_status tnc_serve_start(tnc_ctx ctx, int32_t max_inflight, int32_t queue_cap)
 }
 
 tnc_status tnc_serve_set_heavy(tnc_ctx ctx, double heavy_flops, int32_t heavy_slots) {
-  g_error_clear();
-  if (!ctx || !ctx->c->server || heavy_slots < 1) {
-    g_error_set("bad arguments or server not started");
-    return TNC_E_ARG;
-  }
+  TNC_TRY
+  if (!ctx || !ctx->c->server || heavy_slots < 1) fail(TNC_E_ARG, "bad arguments or server not started");
   Server& s = *ctx->c->server;
   {
     std::lock_guard<std::mutex> g(s.mu);
@@ -395,17 +392,14 @@ tnc_status tnc_serve_set_heavy(tnc_ctx ctx, double heavy_flops, int32_t heavy_sl
     s.heavy_slots = heavy_slots;
   }
   s.cv_work.notify_all();
-  return TNC_OK;
+  TNC_CATCH
 }
 
 tnc_status tnc_serve_stop(tnc_ctx ctx) {
-  g_error_clear();
-  if (!ctx) {
-    g_error_set("ctx is NULL");
-    return TNC_E_ARG;
-  }
+  TNC_TRY
+  if (!ctx) fail(TNC_E_ARG, "ctx is NULL");
   ctx->c->server.reset();  // drains the queue: workers finish every request first
-  return TNC_OK;
+  TNC_CATCH
 }
 
 tnc_status tnc_submit(tnc_ctx ctx, tnc_plan plan, int64_t first_slice, int64_t n_slices, double* out_c128,
@@ -528,9 +522,9 @@ tnc_status tnc_batcher_create(tnc_plan plan, int32_t batch_label, int32_t n_leav
 }
 
 tnc_status tnc_batcher_destroy(tnc_batcher b) {
-  g_error_clear();
+  TNC_TRY
   delete b;  // queued rows keep the batcher alive until they are done
-  return TNC_OK;
+  TNC_CATCH
 }
 
 tnc_status tnc_submit_row(tnc_ctx ctx, tnc_batcher bh, const void* const* row_data, tnc_in in, double* out_c128,
@@ -597,43 +591,33 @@ static tnc_status finish(Request& r, double* latency_s) {
 }
 
 tnc_status tnc_poll(tnc_ctx ctx, tnc_req id, int32_t* done, double* latency_s) {
-  g_error_clear();
-  if (!ctx || !done || !ctx->c->server) {
-    g_error_set("bad arguments or server not started");
-    return TNC_E_ARG;
-  }
+  TNC_TRY
+  if (!ctx || !done || !ctx->c->server) fail(TNC_E_ARG, "bad arguments or server not started");
   Server& s = *ctx->c->server;
   std::lock_guard<std::mutex> g(s.mu);
   auto it = s.reqs.find(id);
-  if (it == s.reqs.end()) {
-    g_error_set("unknown request id");
-    return TNC_E_ARG;
-  }
+  if (it == s.reqs.end()) fail(TNC_E_ARG, "unknown request id");
   *done = it->second->done ? 1 : 0;
   if (!it->second->done) {
     if (latency_s) *latency_s = 0;
     return TNC_OK;
   }
   return finish(*it->second, latency_s);
+  TNC_CATCH
 }
 
 tnc_status tnc_wait(tnc_ctx ctx, tnc_req id, double* latency_s) {
-  g_error_clear();
-  if (!ctx || !ctx->c->server) {
-    g_error_set("bad arguments or server not started");
-    return TNC_E_ARG;
-  }
+  TNC_TRY
+  if (!ctx || !ctx->c->server) fail(TNC_E_ARG, "bad arguments or server not started");
   Server& s = *ctx->c->server;
   std::unique_lock<std::mutex> g(s.mu);
   auto it = s.reqs.find(id);
-  if (it == s.reqs.end()) {
-    g_error_set("unknown request id");
-    return TNC_E_ARG;
-  }
+  if (it == s.reqs.end()) fail(TNC_E_ARG, "unknown request id");
   std::shared_ptr<Request> r = it->second;
   s.cv_done.wait(g, [&] { return r->done; });
   s.reqs.erase(id);
   return finish(*r, latency_s);
+  TNC_CATCH
 }
 
 }  // extern "C"
