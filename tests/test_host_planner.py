@@ -354,6 +354,9 @@ def test_batcher_validation_and_cache_exclusion(hctx):
     assert err(beta, carriers + [other]) == tnc.E_ARG         # leaf without the label
     b = tnc.Batcher(plan, beta, carriers)
     assert err(beta, carriers) == tnc.E_BUSY                  # one batcher per network
+    with pytest.raises(tnc.TncError) as e:                    # rows need a serving context
+        tnc.tnc_submit_row(hctx.handle, b.handle, [np.eye(2)[0]] * len(carriers), np.zeros(1, np.complex128))
+    assert e.value.status == tnc.E_ARG
     assert tnc.tnc_plan_get_info(plan.handle).n_result == 16
     assert tnc.tnc_plan_get_info(plan.handle).n_cached_leaves == cached_before  # projectors: stored as targeted
     b.close()
