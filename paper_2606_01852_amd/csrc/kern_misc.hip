@@ -26,7 +26,7 @@ __global__ __launch_bounds__(256) void reduce_fp64_block(const float2* root, dou
   sr[threadIdx.x] = xr;
   si[threadIdx.x] = xi;
   __syncthreads();
-  for (int w = 128; w > 0; w >>= 1) {
+  for (unsigned w = 128; w > 0; w >>= 1) {
     if (threadIdx.x < w) {
       sr[threadIdx.x] += sr[threadIdx.x + w];
       si[threadIdx.x] += si[threadIdx.x + w];
@@ -68,7 +68,7 @@ __global__ __launch_bounds__(256) void norm2_kernel(const double2* acc, int64_t 
   }
   sm[threadIdx.x] = x;
   __syncthreads();
-  for (int w = 128; w > 0; w >>= 1) {
+  for (unsigned w = 128; w > 0; w >>= 1) {
     if (threadIdx.x < w) sm[threadIdx.x] += sm[threadIdx.x + w];
     __syncthreads();
   }

@@ -605,18 +605,18 @@ std::unique_ptr<ChunkPlan> build_chunk(const Plan& plan, int j) {
   if (cp->grouped) {
     cp->levels.assign(lvl[root] + 1, LevelPlan{});
     for (int s = 0; s < ns; ++s) {
-      LevelPlan& L = cp->levels[lvl[n + s]];
+      LevelPlan& level = cp->levels[lvl[n + s]];
       const StepPlan& sp = cp->steps[s];
       if (sp.kind == GemmKernel::SMALL && n + s != root)
-        L.group_steps.push_back(s);
+        level.group_steps.push_back(s);
       else
-        L.single_steps.push_back(s);
+        level.single_steps.push_back(s);
       for (int t : sp.preps) {
         const LeafPrep& lp = cp->leaf[t];
         if (!lp.perm.tiled && lp.perm.plain.rank <= kGroupRank)
-          L.group_leaves.push_back(t);
+          level.group_leaves.push_back(t);
         else
-          L.single_leaves.push_back(t);
+          level.single_leaves.push_back(t);
       }
     }
   }
