@@ -18,4 +18,6 @@ Contraction on Multiple GPUs"):
                (Sec. II-B, Eq. (1)-(3)); 8 real FLOPs per complex MAC
   split        bf16 hi/lo split by round-to-nearest-even bit manipulation and
                the three-product emulation of a split-precision product
+  distplan     keep-or-redistribute choices along a use-chain by exhaustive
+               enumeration under the cost model (Sec. IV-B, Eq. (4)-(7))
 """
