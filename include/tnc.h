@@ -70,6 +70,10 @@ typedef enum { TNC_GEMM_4M = 0, TNC_GEMM_3M = 1 } tnc_cgemm;
 /* Element type of host leaf data handed to the library. */
 typedef enum { TNC_IN_C64 = 0, TNC_IN_C128 = 1 } tnc_in;
 
+/* Entry points take these choices as int32_t holding one of the constants
+ * above (any other value is TNC_E_ARG), so that no caller can hand the
+ * library an enum value outside its range. */
+
 typedef struct tnc_ctx_s* tnc_ctx;
 typedef struct tnc_net_s* tnc_net;
 typedef struct tnc_plan_s* tnc_plan;
@@ -110,13 +114,13 @@ tnc_status tnc_net_create(tnc_ctx ctx, int32_t n_tensors, const int32_t* ranks,
                           const int32_t* labels, int32_t n_labels,
                           const int64_t* extent_of_label, int32_t n_open,
                           const int32_t* open_labels, const void* const* host_data,
-                          tnc_in in, tnc_net* out);
+                          int32_t in /* tnc_in */, tnc_net* out);
 /* Replace leaf `tensor`'s values (same shape), e.g. a new bitstring's
  * projectors.  Synchronous host-to-device copy.  Plans of the network see
  * the new values from their next run on (cached permuted copies are
  * refreshed then); replacing a leaf while runs of its network are in flight
  * is a race. */
-tnc_status tnc_net_set_tensor(tnc_net net, int32_t tensor, const void* host_data, tnc_in in);
+tnc_status tnc_net_set_tensor(tnc_net net, int32_t tensor, const void* host_data, int32_t in /* tnc_in */);
 /* Replace leaf `tensor`'s values from a device pointer (complex64, stored
  * order).  Device-to-device copy on the context's stream (same rules). */
 tnc_status tnc_net_set_tensor_device(tnc_net net, int32_t tensor, const void* dev_data);
@@ -130,7 +134,7 @@ tnc_status tnc_net_destroy(tnc_net net);
  * still complete. */
 tnc_status tnc_plan_create(tnc_net net, int32_t n_steps, const int32_t* ssa_pairs,
                            int32_t n_sliced, const int32_t* sliced_labels,
-                           tnc_prec prec, tnc_cgemm cgemm, tnc_plan* out);
+                           int32_t prec /* tnc_prec */, int32_t cgemm /* tnc_cgemm */, tnc_plan* out);
 tnc_status tnc_plan_destroy(tnc_plan plan);
 
 typedef struct {
@@ -257,7 +261,7 @@ tnc_status tnc_contract(tnc_plan plan, int64_t first_slice, int64_t n_slices, do
  * otherwise the FP64 sum is rounded to complex64 at the end. */
 typedef enum { TNC_OUT_C128 = 0, TNC_OUT_C64 = 1 } tnc_out;
 tnc_status tnc_contract_async(tnc_plan plan, int64_t first_slice, int64_t n_slices, void* out_dev,
-                              tnc_out out_type);
+                              int32_t out_type /* tnc_out */);
 /* Sum of |R|^2 over the last result of this plan, in FP64 on the device. */
 tnc_status tnc_plan_result_norm2(tnc_plan plan, double* out);
 
@@ -265,7 +269,10 @@ tnc_status tnc_plan_result_norm2(tnc_plan plan, double* out);
  * Operand permutation (a bit copy): out[pi(idx)] = in[idx] for a complex64
  * tensor of `rank` modes with extents in[rank] (input order); perm[j] = the
  * input mode that becomes output mode j.  in/out: device pointers, must not
- * overlap.  Asynchronous on the context's stream. */
+ * overlap.  Asynchronous on the context's stream.  TNC_E_ARG for an extent
+ * below 1, a size past 2^60 elements or a perm that is not a permutation
+ * (checked before any device work); TNC_E_UNSUPPORTED on a host-only
+ * context or above 64 modes. */
 tnc_status tnc_permute(tnc_ctx ctx, const void* in, void* out, int32_t rank,
                        const int64_t* extents, const int32_t* perm);
 /* Batched complex GEMM with both operands K-contiguous:
@@ -274,7 +281,7 @@ tnc_status tnc_permute(tnc_ctx ctx, const void* in, void* out, int32_t rank,
  * batch stride of 0 for A or B broadcasts it).  Asynchronous. */
 tnc_status tnc_batched_cgemm(tnc_ctx ctx, int64_t h, int64_t m, int64_t n, int64_t k,
                              const void* A, int64_t stride_a, const void* B, int64_t stride_b,
-                             void* C, tnc_prec prec, tnc_cgemm form);
+                             void* C, int32_t prec /* tnc_prec */, int32_t form /* tnc_cgemm */);
 /* Force the MFMA tile variant of every complex GEMM this context launches
  * (0 .. tnc_gemm_variant_count()-1; -1 = the plan's autotuned choice).  For
  * tests and tuning sweeps. */
@@ -333,8 +340,8 @@ tnc_status tnc_batcher_destroy(tnc_batcher b);
  * `in`), copied before the call returns; out_c128 (host, R / B complex128)
  * must stay valid until the request is done.  Heavy classification and
  * admission as for tnc_submit, with the batch's work and arena need. */
-tnc_status tnc_submit_row(tnc_ctx ctx, tnc_batcher b, const void* const* row_data, tnc_in in, double* out_c128,
-                          tnc_req* id);
+tnc_status tnc_submit_row(tnc_ctx ctx, tnc_batcher b, const void* const* row_data, int32_t in /* tnc_in */,
+                          double* out_c128, tnc_req* id);
 /* done = 1 when finished; latency_s = submit-to-done wall time (else 0);
  * status of the request's execution is returned once done. */
 tnc_status tnc_poll(tnc_ctx ctx, tnc_req id, int32_t* done, double* latency_s);

@@ -157,7 +157,7 @@ tnc_status tnc_ctx_sync(tnc_ctx ctx) {
   TNC_CATCH
 }
 
-static void upload_leaf(Net& net, int t, const void* host, tnc_in in) {
+static void upload_leaf(Net& net, int t, const void* host, int32_t in) {
   DeviceBuf& d = net.leaf[t];
   const int64_t n = net.numel[t];
   ++net.version[t];
@@ -176,9 +176,10 @@ static void upload_leaf(Net& net, int t, const void* host, tnc_in in) {
 
 tnc_status tnc_net_create(tnc_ctx ctx, int32_t n_tensors, const int32_t* ranks, const int32_t* labels,
                           int32_t n_labels, const int64_t* extent_of_label, int32_t n_open,
-                          const int32_t* open_labels, const void* const* host_data, tnc_in in, tnc_net* out) {
+                          const int32_t* open_labels, const void* const* host_data, int32_t in, tnc_net* out) {
   TNC_TRY
   if (!ctx || !out) fail(TNC_E_ARG, "ctx/out is NULL");
+  if (in != TNC_IN_C64 && in != TNC_IN_C128) fail(TNC_E_ARG, "unknown input element type");
   if (n_tensors < 1 || !ranks || n_labels < 0 || (n_labels && !extent_of_label) || n_open < 0 ||
       (n_open && !open_labels))
     fail(TNC_E_ARG, "bad network arguments");
@@ -213,9 +214,10 @@ tnc_status tnc_net_create(tnc_ctx ctx, int32_t n_tensors, const int32_t* ranks, 
   TNC_CATCH
 }
 
-tnc_status tnc_net_set_tensor(tnc_net net, int32_t tensor, const void* host_data, tnc_in in) {
+tnc_status tnc_net_set_tensor(tnc_net net, int32_t tensor, const void* host_data, int32_t in) {
   TNC_TRY
   if (!net || !host_data) fail(TNC_E_ARG, "net/host_data is NULL");
+  if (in != TNC_IN_C64 && in != TNC_IN_C128) fail(TNC_E_ARG, "unknown input element type");
   Net& n = *net->n;
   if (tensor < 0 || tensor >= n.n_tensors) fail(TNC_E_ARG, "tensor out of range");
   set_device(*n.ctx);
@@ -243,7 +245,7 @@ tnc_status tnc_net_destroy(tnc_net net) {
 }
 
 tnc_status tnc_plan_create(tnc_net net, int32_t n_steps, const int32_t* ssa_pairs, int32_t n_sliced,
-                           const int32_t* sliced_labels, tnc_prec prec, tnc_cgemm cgemm, tnc_plan* out) {
+                           const int32_t* sliced_labels, int32_t prec, int32_t cgemm, tnc_plan* out) {
   TNC_TRY
   if (!net || !out) fail(TNC_E_ARG, "net/out is NULL");
   if (n_steps < 0 || (n_steps && !ssa_pairs) || n_sliced < 0 || (n_sliced && !sliced_labels))
@@ -258,8 +260,8 @@ tnc_status tnc_plan_create(tnc_net net, int32_t n_steps, const int32_t* ssa_pair
   Plan& p = *h->p;
   p.net_ref = net->n;
   p.net = &n;
-  p.prec = prec;
-  p.form = cgemm;
+  p.prec = static_cast<tnc_prec>(prec);
+  p.form = static_cast<tnc_cgemm>(cgemm);
   for (int s = 0; s < n_steps; ++s) p.pairs.push_back({ssa_pairs[2 * s], ssa_pairs[2 * s + 1]});
   validate_path(n, p.pairs);
   std::vector<char> seen(n.extents.size(), 0);
@@ -532,9 +534,10 @@ tnc_status tnc_contract(tnc_plan plan, int64_t first_slice, int64_t n_slices, do
 }
 
 tnc_status tnc_contract_async(tnc_plan plan, int64_t first_slice, int64_t n_slices, void* out_dev,
-                              tnc_out out_type) {
+                              int32_t out_type) {
   TNC_TRY
   if (!plan || !out_dev) fail(TNC_E_ARG, "plan/out is NULL");
+  if (out_type != TNC_OUT_C64 && out_type != TNC_OUT_C128) fail(TNC_E_ARG, "unknown output type");
   Plan& p = *plan->p;
   Ctx& c = *p.net->ctx;
   set_device(c);
@@ -585,12 +588,11 @@ tnc_status tnc_permute(tnc_ctx ctx, const void* in, void* out, int32_t rank, con
                        const int32_t* perm) {
   TNC_TRY
   if (!ctx || !in || !out || rank < 0 || (rank && (!extents || !perm))) fail(TNC_E_ARG, "bad arguments");
-  Ctx& c = *ctx->c;
-  set_device(c);
   std::vector<int64_t> ist(rank);
   int64_t s = 1;
   for (int q = rank - 1; q >= 0; --q) {
     if (extents[q] < 1) fail(TNC_E_ARG, "extent < 1");
+    if (s > INT64_MAX / 8 / extents[q]) fail(TNC_E_ARG, "tensor size overflows int64");
     ist[q] = s;
     s *= extents[q];
   }
@@ -603,6 +605,8 @@ tnc_status tnc_permute(tnc_ctx ctx, const void* in, void* out, int32_t rank, con
     ext[q] = extents[p];
     st[q] = ist[p];
   }
+  Ctx& c = *ctx->c;
+  set_device(c);
   PermuteHost ph = build_permute(ext, st);
   if (!ph.tiled) {
     GatherDesc g = ph.plain;
@@ -692,11 +696,13 @@ tnc_status tnc_device_calibrate(tnc_ctx ctx, tnc_dist_hw* hw) {
 }
 
 tnc_status tnc_batched_cgemm(tnc_ctx ctx, int64_t h, int64_t m, int64_t n, int64_t k, const void* A,
-                             int64_t stride_a, const void* B, int64_t stride_b, void* C, tnc_prec prec,
-                             tnc_cgemm form) {
+                             int64_t stride_a, const void* B, int64_t stride_b, void* C, int32_t prec,
+                             int32_t form) {
   TNC_TRY
   if (!ctx || !A || !B || !C || h < 1 || m < 1 || n < 1 || k < 1 || stride_a < 0 || stride_b < 0)
     fail(TNC_E_ARG, "bad arguments");
+  if (prec != TNC_PREC_C64 && prec != TNC_PREC_BF16X3) fail(TNC_E_ARG, "unknown precision");
+  if (form != TNC_GEMM_4M && form != TNC_GEMM_3M) fail(TNC_E_ARG, "unknown GEMM form");
   if (prec == TNC_PREC_BF16X3 && form == TNC_GEMM_3M) fail(TNC_E_UNSUPPORTED, "split precision runs in 4M form");
   Ctx& c = *ctx->c;
   set_device(c);

@@ -527,7 +527,7 @@ tnc_status tnc_batcher_destroy(tnc_batcher b) {
   TNC_CATCH
 }
 
-tnc_status tnc_submit_row(tnc_ctx ctx, tnc_batcher bh, const void* const* row_data, tnc_in in, double* out_c128,
+tnc_status tnc_submit_row(tnc_ctx ctx, tnc_batcher bh, const void* const* row_data, int32_t in, double* out_c128,
                           tnc_req* id) {
   TNC_TRY
     if (!ctx || !bh || !row_data || !out_c128 || !id) fail(TNC_E_ARG, "NULL argument");

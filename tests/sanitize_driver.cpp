@@ -1,0 +1,284 @@
+// Host-side driver of the C ABI for the sanitizer test (AddressSanitizer and
+// UndefinedBehaviorSanitizer on the host code; no GPU is touched: every call
+// goes to a host-only context).
+//
+// Input (whitespace-separated integers, one network per file):
+//   n_tensors  then per tensor: rank, labels...
+//   n_labels   then the extent of every label
+//   n_open     then the open labels
+//   n_steps    then the SSA pairs
+//   n_sliced   then the sliced labels
+//   batch_label (-1: none), then n_leaves and the leaves of a batcher
+// For each network the driver plans it (both execution orders, every chunk
+// size), queries every step and order, plans its distribution over 2, 4 and
+// 8 devices, creates and destroys a batcher when asked, and checks that
+// malformed inputs come back as status codes.  Prints "ok <file>" per file.
+#include <cstdio>
+#include <cstdlib>
+#include <fstream>
+#include <vector>
+
+#include "../include/tnc.h"
+
+namespace {
+
+int fails = 0;
+
+void expect(bool cond, const char* what, const char* file) {
+  if (!cond) {
+    std::fprintf(stderr, "FAIL %s: %s (%s)\n", file, what, tnc_last_error());
+    ++fails;
+  }
+}
+
+struct NetFile {
+  int n_tensors = 0;
+  std::vector<int32_t> ranks, labels;
+  std::vector<int64_t> extents;
+  std::vector<int32_t> open, pairs, sliced, batch_leaves;
+  int batch_label = -1;
+};
+
+bool read_net(const char* path, NetFile& f) {
+  std::ifstream in(path);
+  if (!in) return false;
+  in >> f.n_tensors;
+  for (int t = 0; t < f.n_tensors; ++t) {
+    int r = 0;
+    in >> r;
+    f.ranks.push_back(r);
+    for (int q = 0; q < r; ++q) {
+      int l = 0;
+      in >> l;
+      f.labels.push_back(l);
+    }
+  }
+  int n = 0;
+  in >> n;
+  f.extents.resize(n);
+  for (auto& e : f.extents) in >> e;
+  in >> n;
+  f.open.resize(n);
+  for (auto& o : f.open) in >> o;
+  in >> n;
+  f.pairs.resize(2 * n);
+  for (auto& p : f.pairs) in >> p;
+  in >> n;
+  f.sliced.resize(n);
+  for (auto& s : f.sliced) in >> s;
+  in >> f.batch_label >> n;
+  f.batch_leaves.resize(n);
+  for (auto& b : f.batch_leaves) in >> b;
+  return static_cast<bool>(in);
+}
+
+void exercise(tnc_ctx ctx, const NetFile& f, const char* file) {
+  tnc_net net = nullptr;
+  expect(tnc_net_create(ctx, f.n_tensors, f.ranks.data(), f.labels.data(), static_cast<int32_t>(f.extents.size()),
+                        f.extents.data(), static_cast<int32_t>(f.open.size()), f.open.data(), nullptr, TNC_IN_C64,
+                        &net) == TNC_OK,
+         "net_create", file);
+  if (!net) return;
+  const int32_t n_steps = static_cast<int32_t>(f.pairs.size() / 2);
+  tnc_plan plan = nullptr;
+  expect(tnc_plan_create(net, n_steps, f.pairs.data(), static_cast<int32_t>(f.sliced.size()), f.sliced.data(),
+                         TNC_PREC_C64, TNC_GEMM_4M, &plan) == TNC_OK,
+         "plan_create", file);
+  if (plan) {
+    tnc_plan_info info;
+    for (int grouping = 1; grouping >= 0; --grouping) {
+      expect(tnc_plan_set_grouping(plan, grouping) == TNC_OK, "set_grouping", file);
+      for (int64_t cap : {int64_t{1}, int64_t{4}, int64_t{-1}}) {
+        expect(tnc_plan_set_max_chunk(plan, cap) == TNC_OK, "set_max_chunk", file);
+        expect(tnc_plan_get_info(plan, &info) == TNC_OK, "get_info", file);
+        for (int32_t s = 0; s < n_steps; ++s) {
+          tnc_step_info st;
+          expect(tnc_plan_get_step(plan, s, &st) == TNC_OK, "get_step", file);
+          expect(tnc_plan_get_batch_step(plan, s, &st) == TNC_OK, "get_batch_step", file);
+        }
+      }
+    }
+    std::vector<int32_t> order(64);
+    for (int32_t id = 0; id < f.n_tensors + n_steps; ++id) {
+      int32_t rank = 0;
+      expect(tnc_plan_get_order(plan, id, order.data(), 64, &rank) == TNC_OK, "get_order", file);
+    }
+    tnc_step_info st;
+    expect(tnc_plan_get_step(plan, n_steps, &st) == TNC_E_ARG, "step out of range", file);
+    tnc_dist_hw hw{5.3e12, 1.4e14, 1.0e11, 2e-6};
+    std::vector<tnc_dist_step> steps(4096);
+    for (int P : {2, 4, 8}) {
+      int32_t n_out = 0;
+      double total = 0, moved = 0;
+      expect(tnc_plan_distribute(plan, P, 1e3, &hw, steps.data(), static_cast<int32_t>(steps.size()), &n_out,
+                                 &total, &moved) == TNC_OK,
+             "distribute", file);
+    }
+    if (f.batch_label >= 0) {
+      tnc_batcher b = nullptr;
+      expect(tnc_batcher_create(plan, f.batch_label, static_cast<int32_t>(f.batch_leaves.size()),
+                                f.batch_leaves.data(), &b) == TNC_OK,
+             "batcher_create", file);
+      tnc_batcher b2 = nullptr;
+      expect(tnc_batcher_create(plan, f.batch_label, static_cast<int32_t>(f.batch_leaves.size()),
+                                f.batch_leaves.data(), &b2) == TNC_E_BUSY,
+             "second batcher refused", file);
+      expect(tnc_batcher_destroy(b) == TNC_OK, "batcher_destroy", file);
+    }
+    expect(tnc_plan_destroy(plan) == TNC_OK, "plan_destroy", file);
+  }
+  // malformed paths: a repeated id, an id out of range
+  if (n_steps > 0) {
+    std::vector<int32_t> bad = f.pairs;
+    bad[1] = bad[0];
+    tnc_plan p2 = nullptr;
+    expect(tnc_plan_create(net, n_steps, bad.data(), 0, nullptr, TNC_PREC_C64, TNC_GEMM_4M, &p2) != TNC_OK,
+           "repeated id rejected", file);
+    bad = f.pairs;
+    bad[0] = f.n_tensors + n_steps + 7;
+    expect(tnc_plan_create(net, n_steps, bad.data(), 0, nullptr, TNC_PREC_C64, TNC_GEMM_4M, &p2) != TNC_OK,
+           "id out of range rejected", file);
+  }
+  expect(tnc_net_destroy(net) == TNC_OK, "net_destroy", file);
+}
+
+tnc_status make_net(tnc_ctx ctx, const std::vector<int32_t>& ranks, const std::vector<int32_t>& labels,
+                    const std::vector<int64_t>& ext, const std::vector<int32_t>& open, tnc_net* out) {
+  *out = nullptr;
+  return tnc_net_create(ctx, static_cast<int32_t>(ranks.size()), ranks.data(), labels.data(),
+                        static_cast<int32_t>(ext.size()), ext.data(), static_cast<int32_t>(open.size()),
+                        open.empty() ? nullptr : open.data(), nullptr, TNC_IN_C64, out);
+}
+
+// Arguments every entry point must turn into a status code, never a crash.
+void malformed(tnc_ctx ctx) {
+  const char* F = "malformed";
+  tnc_net net = nullptr;
+  // networks: label out of range, label repeated in a tensor, extent 0, an
+  // open label repeated or on no tensor, a negative rank, no tensors, a label
+  // held by three tensors, an intermediate past int64
+  expect(make_net(ctx, {2, 1}, {0, 3, 0}, {2, 2}, {}, &net) == TNC_E_ARG, "label out of range", F);
+  expect(make_net(ctx, {2, 1}, {0, 0, 0}, {2}, {}, &net) == TNC_E_ARG, "label repeated", F);
+  expect(make_net(ctx, {1, 1}, {0, 0}, {0}, {}, &net) == TNC_E_ARG, "extent 0", F);
+  expect(make_net(ctx, {1, 1}, {0, 1}, {2, 2}, {0, 0}, &net) == TNC_E_ARG, "open repeated", F);
+  expect(make_net(ctx, {1, 1}, {0, 0}, {2, 2}, {1}, &net) == TNC_E_ARG, "open on no tensor", F);
+  expect(make_net(ctx, {-1, 1}, {0, 0}, {2}, {}, &net) == TNC_E_ARG, "negative rank", F);
+  expect(tnc_net_create(ctx, 0, nullptr, nullptr, 0, nullptr, 0, nullptr, nullptr, TNC_IN_C64, &net) == TNC_E_ARG,
+         "no tensors", F);
+  expect(make_net(ctx, {1, 1, 1}, {0, 0, 0}, {2}, {}, &net) == TNC_E_ARG, "hyperedge", F);
+  {
+    const int32_t r[2] = {1, 1}, l[2] = {0, 0};
+    const int64_t e[1] = {2};
+    expect(tnc_net_create(ctx, 2, r, l, 1, e, 0, nullptr, nullptr, 5, &net) == TNC_E_ARG, "input type", F);
+  }
+  expect(tnc_net_create(nullptr, 1, nullptr, nullptr, 0, nullptr, 0, nullptr, nullptr, TNC_IN_C64, &net) == TNC_E_ARG,
+         "null ctx", F);
+  {
+    // A(a b c d) B(c d e f): the product's open labels a b e f at 2^20 each
+    const std::vector<int64_t> big = {1 << 20, 1 << 20, 2, 2, 1 << 20, 1 << 20};
+    if (make_net(ctx, {4, 4}, {0, 1, 2, 3, 2, 3, 4, 5}, big, {0, 1, 4, 5}, &net) == TNC_OK) {
+      const int32_t pair[2] = {0, 1};
+      tnc_plan p = nullptr;
+      expect(tnc_plan_create(net, 1, pair, 0, nullptr, TNC_PREC_C64, TNC_GEMM_4M, &p) != TNC_OK, "size overflow", F);
+      tnc_net_destroy(net);
+    } else {
+      expect(false, "overflowing net refused at creation", F);
+    }
+  }
+  // plans over A(0 1) B(1 2) C(2 0), closed: wrong step counts, bad slices,
+  // bad enums, the split precision in the 3M form
+  expect(make_net(ctx, {2, 2, 2}, {0, 1, 1, 2, 2, 0}, {3, 4, 5}, {}, &net) == TNC_OK, "triangle", F);
+  if (net) {
+    tnc_plan p = nullptr;
+    const int32_t good[4] = {0, 1, 3, 2};
+    const int32_t self[4] = {0, 0, 3, 2};
+    const int32_t fwd[4] = {0, 4, 3, 2};
+    expect(tnc_plan_create(net, 1, good, 0, nullptr, TNC_PREC_C64, TNC_GEMM_4M, &p) == TNC_E_PATH, "short path", F);
+    expect(tnc_plan_create(net, 2, self, 0, nullptr, TNC_PREC_C64, TNC_GEMM_4M, &p) == TNC_E_PATH, "self pair", F);
+    expect(tnc_plan_create(net, 2, fwd, 0, nullptr, TNC_PREC_C64, TNC_GEMM_4M, &p) == TNC_E_PATH, "forward id", F);
+    expect(tnc_plan_create(net, 2, nullptr, 0, nullptr, TNC_PREC_C64, TNC_GEMM_4M, &p) == TNC_E_ARG, "null path", F);
+    const int32_t sl_bad[2] = {7, 0}, sl_rep[2] = {1, 1};
+    expect(tnc_plan_create(net, 2, good, 1, sl_bad, TNC_PREC_C64, TNC_GEMM_4M, &p) == TNC_E_ARG, "slice range", F);
+    expect(tnc_plan_create(net, 2, good, 2, sl_rep, TNC_PREC_C64, TNC_GEMM_4M, &p) == TNC_E_ARG, "slice twice", F);
+    expect(tnc_plan_create(net, 2, good, 0, nullptr, 9, TNC_GEMM_4M, &p) == TNC_E_ARG,
+           "unknown precision", F);
+    expect(tnc_plan_create(net, 2, good, 0, nullptr, TNC_PREC_C64, 9, &p) == TNC_E_ARG,
+           "unknown form", F);
+    expect(tnc_plan_create(net, 2, good, 0, nullptr, TNC_PREC_BF16X3, TNC_GEMM_3M, &p) == TNC_E_UNSUPPORTED,
+           "split 3M", F);
+    const int32_t sl[1] = {1};
+    expect(tnc_plan_create(net, 2, good, 1, sl, TNC_PREC_C64, TNC_GEMM_4M, &p) == TNC_OK, "triangle plan", F);
+    if (p) {
+      tnc_dist_hw hw{5.3e12, 1.4e14, 1.0e11, 2e-6};
+      int32_t n_out = 0;
+      double total = 0, moved = 0;
+      tnc_dist_step steps[8];
+      expect(tnc_plan_distribute(p, 1, 1e3, &hw, steps, 8, &n_out, &total, &moved) == TNC_E_ARG, "one gpu", F);
+      tnc_dist_hw neg{-1.0, 1.4e14, 1.0e11, 2e-6};
+      expect(tnc_plan_distribute(p, 4, 1e3, &neg, steps, 8, &n_out, &total, &moved) == TNC_E_ARG, "bad hw", F);
+      // cap 0 still reports the step count (0 here: extents 3 and 5 do not
+      // split four ways); a short cap writes only its part
+      expect(tnc_plan_distribute(p, 4, 1.0, &hw, nullptr, 0, &n_out, &total, &moved) == TNC_OK && n_out >= 0,
+             "distribute cap 0", F);
+      const int32_t full = n_out;
+      expect(tnc_plan_distribute(p, 4, 1.0, &hw, steps, 1, &n_out, &total, &moved) == TNC_OK && n_out == full,
+             "distribute cap 1", F);
+      int32_t order[1], rank = 0;
+      expect(tnc_plan_get_order(p, 3, order, 1, &rank) == TNC_OK, "order cap short", F);
+      expect(tnc_plan_get_order(p, 5, order, 1, &rank) == TNC_E_ARG, "order id", F);
+      expect(tnc_plan_get_order(p, -1, order, 1, &rank) == TNC_E_ARG, "order id negative", F);
+      tnc_step_info st;
+      expect(tnc_plan_get_step(p, -1, &st) == TNC_E_ARG, "negative step", F);
+      double out[2];
+      expect(tnc_contract(p, 0, 1, out) == TNC_E_UNSUPPORTED, "host-only contract", F);
+      const int32_t leaf[1] = {0};
+      tnc_batcher b = nullptr;
+      expect(tnc_batcher_create(p, 0, 1, leaf, &b) == TNC_E_ARG, "batch label closed", F);
+      expect(tnc_batcher_create(p, 0, 0, leaf, &b) == TNC_E_ARG, "batcher with no leaves", F);
+      tnc_plan_destroy(p);
+    }
+    tnc_net_destroy(net);
+  }
+  // permutes: checked before any device work, then refused on a host context
+  {
+    const int64_t ext[3] = {4, 5, 6}, huge[3] = {int64_t{1} << 30, int64_t{1} << 30, 64};
+    const int32_t perm[3] = {2, 0, 1}, dup[3] = {2, 2, 1}, out_of[3] = {3, 0, 1};
+    float dummy[2];
+    expect(tnc_permute(ctx, dummy, dummy, 3, ext, dup) == TNC_E_ARG, "perm repeated", F);
+    expect(tnc_permute(ctx, dummy, dummy, 3, ext, out_of) == TNC_E_ARG, "perm out of range", F);
+    expect(tnc_permute(ctx, dummy, dummy, 3, huge, perm) == TNC_E_ARG, "permute size overflow", F);
+    expect(tnc_permute(ctx, dummy, dummy, 3, ext, perm) == TNC_E_UNSUPPORTED, "permute on host", F);
+    expect(tnc_batched_cgemm(ctx, 1, 0, 4, 4, dummy, 0, dummy, 0, dummy, TNC_PREC_C64, TNC_GEMM_4M) == TNC_E_ARG,
+           "gemm m 0", F);
+    expect(tnc_batched_cgemm(ctx, 1, 4, 4, 4, dummy, 0, dummy, 0, dummy, 7, TNC_GEMM_4M) == TNC_E_ARG,
+           "gemm precision", F);
+    expect(tnc_batched_cgemm(ctx, 1, 4, 4, 4, dummy, 0, dummy, 0, dummy, TNC_PREC_C64, -3) == TNC_E_ARG,
+           "gemm form", F);
+    expect(tnc_serve_start(ctx, 4, 16) == TNC_E_UNSUPPORTED, "serve on host", F);
+  }
+  expect(tnc_plan_destroy(nullptr) == TNC_OK, "destroy null plan", F);
+  expect(tnc_net_destroy(nullptr) == TNC_OK, "destroy null net", F);
+}
+
+}  // namespace
+
+int main(int argc, char** argv) {
+  tnc_ctx ctx = nullptr;
+  if (tnc_ctx_create(-1, nullptr, size_t{64} << 30, nullptr, &ctx) != TNC_OK) {
+    std::fprintf(stderr, "host context: %s\n", tnc_last_error());
+    return 2;
+  }
+  malformed(ctx);
+  std::printf("ok malformed\n");
+  for (int i = 1; i < argc; ++i) {
+    NetFile f;
+    if (!read_net(argv[i], f)) {
+      std::fprintf(stderr, "cannot read %s\n", argv[i]);
+      return 2;
+    }
+    exercise(ctx, f, argv[i]);
+    std::printf("ok %s\n", argv[i]);
+  }
+  tnc_ctx_destroy(ctx);
+  return fails ? 1 : 0;
+}
