@@ -75,11 +75,11 @@ _SIGS = {
     "tnc_ctx_set_gemm_variant": (C.c_int, [_P, C.c_int32]),
     "tnc_gemm_variant_count": (C.c_int, []),
     "tnc_net_create": (C.c_int, [_P, C.c_int32, _I32P, _I32P, C.c_int32, _I64P, C.c_int32, _I32P,
-                                 C.POINTER(_P), C.c_int, C.POINTER(_P)]),
-    "tnc_net_set_tensor": (C.c_int, [_P, C.c_int32, _P, C.c_int]),
+                                 C.POINTER(_P), C.c_int32, C.POINTER(_P)]),
+    "tnc_net_set_tensor": (C.c_int, [_P, C.c_int32, _P, C.c_int32]),
     "tnc_net_set_tensor_device": (C.c_int, [_P, C.c_int32, _P]),
     "tnc_net_destroy": (C.c_int, [_P]),
-    "tnc_plan_create": (C.c_int, [_P, C.c_int32, _I32P, C.c_int32, _I32P, C.c_int, C.c_int, C.POINTER(_P)]),
+    "tnc_plan_create": (C.c_int, [_P, C.c_int32, _I32P, C.c_int32, _I32P, C.c_int32, C.c_int32, C.POINTER(_P)]),
     "tnc_plan_destroy": (C.c_int, [_P]),
     "tnc_plan_get_info": (C.c_int, [_P, C.POINTER(PlanInfo)]),
     "tnc_plan_get_step": (C.c_int, [_P, C.c_int32, C.POINTER(StepInfo)]),
@@ -95,18 +95,18 @@ _SIGS = {
     "tnc_plan_set_profile": (C.c_int, [_P, C.c_int32]),
     "tnc_plan_get_profile": (C.c_int, [_P, C.c_int32, _DP, _I64P]),
     "tnc_contract": (C.c_int, [_P, C.c_int64, C.c_int64, _DP]),
-    "tnc_contract_async": (C.c_int, [_P, C.c_int64, C.c_int64, _P, C.c_int]),
+    "tnc_contract_async": (C.c_int, [_P, C.c_int64, C.c_int64, _P, C.c_int32]),
     "tnc_plan_result_norm2": (C.c_int, [_P, _DP]),
     "tnc_permute": (C.c_int, [_P, _P, _P, C.c_int32, _I64P, _I32P]),
     "tnc_batched_cgemm": (C.c_int, [_P, C.c_int64, C.c_int64, C.c_int64, C.c_int64, _P, C.c_int64, _P,
-                                    C.c_int64, _P, C.c_int, C.c_int]),
+                                    C.c_int64, _P, C.c_int32, C.c_int32]),
     "tnc_serve_start": (C.c_int, [_P, C.c_int32, C.c_int32]),
     "tnc_serve_stop": (C.c_int, [_P]),
     "tnc_serve_set_heavy": (C.c_int, [_P, C.c_double, C.c_int32]),
     "tnc_submit": (C.c_int, [_P, _P, C.c_int64, C.c_int64, _DP, C.POINTER(C.c_uint64)]),
     "tnc_batcher_create": (C.c_int, [_P, C.c_int32, C.c_int32, _I32P, C.POINTER(_P)]),
     "tnc_batcher_destroy": (C.c_int, [_P]),
-    "tnc_submit_row": (C.c_int, [_P, _P, C.POINTER(_P), C.c_int, _DP, C.POINTER(C.c_uint64)]),
+    "tnc_submit_row": (C.c_int, [_P, _P, C.POINTER(_P), C.c_int32, _DP, C.POINTER(C.c_uint64)]),
     "tnc_poll": (C.c_int, [_P, C.c_uint64, _I32P, _DP]),
     "tnc_wait": (C.c_int, [_P, C.c_uint64, _DP]),
 }

@@ -387,3 +387,40 @@ def test_batcher_leaves_leave_the_leaf_cache(hctx):
     assert tnc.tnc_plan_get_info(plan.handle).n_cached_leaves == 0
     assert tnc.tnc_plan_get_info(plan.handle).n_permutes == 1
     b.close()
+
+
+def test_choice_arguments_are_checked_before_use(hctx):
+    """Precision, GEMM form and element types cross the ABI as plain integers
+    and are checked before anything else uses them; permute arguments are
+    checked before any device work (a host-only context then refuses it)."""
+    import ctypes as C
+    L = tnc.lib()
+    tn = tnc.Network(hctx, [(0, 1), (1, 2), (2, 0)], np.array([3, 4, 5], dtype=np.int64), ())
+    pairs = np.array([0, 1, 3, 2], dtype=np.int32)
+    pp = pairs.ctypes.data_as(C.POINTER(C.c_int32))
+    out = C.c_void_p()
+    for prec, form, want in ((9, tnc.GEMM_4M, tnc.E_ARG), (-1, tnc.GEMM_4M, tnc.E_ARG),
+                             (tnc.PREC_C64, 2, tnc.E_ARG), (tnc.PREC_BF16X3, tnc.GEMM_3M, tnc.E_UNSUPPORTED)):
+        assert L.tnc_plan_create(tn.handle, 2, pp, 0, None, prec, form, C.byref(out)) == want
+    assert L.tnc_plan_create(tn.handle, 2, pp, 0, None, tnc.PREC_C64, tnc.GEMM_3M, C.byref(out)) == tnc.OK
+    assert L.tnc_plan_destroy(out) == tnc.OK
+    ranks = np.array([1, 1], dtype=np.int32)
+    labs = np.array([0, 0], dtype=np.int32)
+    ext = np.array([2], dtype=np.int64)
+    net = C.c_void_p()
+    assert L.tnc_net_create(hctx.handle, 2, ranks.ctypes.data_as(C.POINTER(C.c_int32)),
+                            labs.ctypes.data_as(C.POINTER(C.c_int32)), 1,
+                            ext.ctypes.data_as(C.POINTER(C.c_int64)), 0, None, None, 7, C.byref(net)) == tnc.E_ARG
+    buf = np.zeros(4, dtype=np.complex64)
+    e3 = np.array([4, 5, 6], dtype=np.int64)
+    huge = np.array([1 << 30, 1 << 30, 64], dtype=np.int64)
+    perm = np.array([2, 0, 1], dtype=np.int32)
+    dup = np.array([2, 2, 1], dtype=np.int32)
+
+    def permute(e, p):
+        return L.tnc_permute(hctx.handle, buf.ctypes.data, buf.ctypes.data, 3, e.ctypes.data_as(C.POINTER(C.c_int64)),
+                             p.ctypes.data_as(C.POINTER(C.c_int32)))
+    assert permute(e3, dup) == tnc.E_ARG
+    assert permute(huge, perm) == tnc.E_ARG
+    assert permute(e3, perm) == tnc.E_UNSUPPORTED
+    tn.close()
