@@ -227,3 +227,30 @@ def test_device_calibration(ctx):
     host = tnc.Context(-1)     # keep the handle alive across the call
     with pytest.raises(tnc.TncError):
         tnc.tnc_device_calibrate(host.handle)
+
+
+def test_bad_choices_are_refused_before_any_launch(ctx):
+    """On a device context, unknown precisions, GEMM forms and output types
+    and malformed permutes come back as TNC_E_ARG and leave the output
+    untouched (nothing was launched)."""
+    import ctypes as C
+    L = tnc.lib()
+    a = to_dev(torch, np.ones((4, 8), dtype=np.complex64))
+    c = torch.full((4, 4), 7.0 + 0j, dtype=torch.complex64, device="cuda")
+    for prec, form in ((7, tnc.GEMM_4M), (tnc.PREC_C64, -3)):
+        st = L.tnc_batched_cgemm(ctx.handle, 1, 4, 4, 8, a.data_ptr(), 0, a.data_ptr(), 0, c.data_ptr(), prec, form)
+        assert st == tnc.E_ARG
+    ext = np.array([4, 8], dtype=np.int64)
+    for perm, e in (([1, 1], ext), ([1, 0], np.array([1 << 31, 1 << 31], dtype=np.int64))):
+        p = np.array(perm, dtype=np.int32)
+        st = L.tnc_permute(ctx.handle, a.data_ptr(), c.data_ptr(), 2, e.ctypes.data_as(C.POINTER(C.c_int64)),
+                           p.ctypes.data_as(C.POINTER(C.c_int32)))
+        assert st == tnc.E_ARG
+    tn = tnc.Network(ctx, [(0, 1), (1, 2)], np.array([4, 8, 4], dtype=np.int64), (0, 2),
+                     [np.ones((4, 8), np.complex64), np.ones((8, 4), np.complex64)])
+    plan = tnc.Plan(tn, [(0, 1)])
+    assert L.tnc_contract_async(plan.handle, 0, 1, c.data_ptr(), 5) == tnc.E_ARG
+    torch.cuda.synchronize()
+    assert bool((c == (7.0 + 0j)).all())
+    plan.close()
+    tn.close()
