@@ -391,3 +391,91 @@ def test_poll_reports_completion_and_unknown_ids(served):
     assert e.value.status == tnc.E_ARG
     tnc.tnc_serve_stop(ctx.handle)
     assert np.array_equal(out.view(np.uint64), alone[1].view(np.uint64))
+
+
+def test_concurrent_submitters_and_waiters(served):
+    """The submit / submit_row / poll / wait calls are thread-safe: four
+    Python threads (ctypes drops the GIL inside each call, so the calls
+    overlap) submit ordinary requests and wait on or poll their own ids while
+    a fifth submits batcher rows.  Every result equals bitwise the same
+    request served alone, and every row its row of a batched contraction."""
+    import threading
+
+    from workloads import configs
+    from workloads.circuits import circuit_network_batched
+    ctx, pool, nets, plans = served
+    alone = {}
+    for i in range(len(plans)):
+        o, _ = run_all(ctx, plans, [i], 1)
+        alone[i] = o[i]
+
+    circ = configs.circuit12_circuit()
+    nq, B, n_rows = circ.n_qubits, 8, 24
+    net = circuit_network_batched(circ, np.zeros((B, nq), dtype=np.int64))
+    beta = net.open[0]
+    carriers = [t for t, lab in enumerate(net.labels) if beta in lab]
+    path = greedy_path(net)
+    bits = np.random.Generator(np.random.PCG64(616)).integers(0, 2, size=(n_rows, nq))
+    tn_ref = tnc.Network(ctx, net.labels, net.extents, net.open, net.c64().leaves)
+    plan_ref = tnc.Plan(tn_ref, path.pairs)
+    ref = np.empty(n_rows, dtype=np.complex128)
+    for c0 in range(0, n_rows, B):
+        netc = circuit_network_batched(circ, bits[c0:c0 + B])
+        for t in carriers:
+            tn_ref.set_tensor(t, netc.leaves[t])
+        ref[c0:c0 + B] = plan_ref.contract()
+    tn_b = tnc.Network(ctx, net.labels, net.extents, net.open, net.c64().leaves)
+    plan_b = tnc.Plan(tn_b, path.pairs)
+    batcher = tnc.Batcher(plan_b, beta, carriers)
+
+    errors, results, rows_out = [], [], np.zeros(n_rows, dtype=np.complex128)
+    lock = threading.Lock()
+    eye = np.eye(2, dtype=np.complex128)
+
+    def submitter(t):
+        try:
+            rng = np.random.Generator(np.random.PCG64(900 + t))
+            mine = []
+            for i in (int(x) for x in rng.integers(0, len(plans), size=8)):
+                out = np.zeros(1, dtype=np.complex128)
+                mine.append((i, out, tnc.tnc_submit(ctx.handle, plans[i].handle, 0, plans[i].info.n_slices, out)))
+            for n, (i, out, rid) in enumerate(mine):
+                if n % 2:
+                    while not tnc.tnc_poll(ctx.handle, rid)[0]:
+                        pass
+                tnc.tnc_wait(ctx.handle, rid)
+            with lock:
+                results.extend((i, out) for i, out, _ in mine)
+        except Exception as e:  # noqa: BLE001 - reported by the main thread
+            errors.append(repr(e))
+
+    def row_submitter():
+        try:
+            outs = [rows_out[i:i + 1] for i in range(n_rows)]
+            rids = [tnc.tnc_submit_row(ctx.handle, batcher.handle, [eye[bits[i, q]] for q in range(nq)], outs[i])
+                    for i in range(n_rows)]
+            for rid in rids:
+                tnc.tnc_wait(ctx.handle, rid)
+        except Exception as e:  # noqa: BLE001
+            errors.append(repr(e))
+
+    tnc.tnc_serve_start(ctx.handle, 6, 1024)
+    threads = [threading.Thread(target=submitter, args=(t,)) for t in range(4)]
+    threads.append(threading.Thread(target=row_submitter))
+    for th in threads:
+        th.start()
+    for th in threads:
+        th.join(timeout=90)
+    alive = [th.is_alive() for th in threads]
+    tnc.tnc_serve_stop(ctx.handle)
+    assert not any(alive), alive
+    assert not errors, errors
+    assert len(results) == 32
+    for i, out in results:
+        assert np.array_equal(out.view(np.uint64), alone[i].view(np.uint64)), i
+    assert np.array_equal(rows_out.view(np.uint64), ref.view(np.uint64))
+    batcher.close()
+    plan_b.close()
+    tn_b.close()
+    plan_ref.close()
+    tn_ref.close()
