@@ -193,7 +193,10 @@ tnc_status tnc_plan_set_max_chunk(tnc_plan plan, int64_t max_chunk);
  * file named by the environment variable TNC_AUTOTUNE_CACHE if set).
  * Untuned steps use a shape-based default.  Synchronous. */
 tnc_status tnc_plan_autotune(tnc_plan plan);
-/* 1 = capture each chunk's launches in a hipGraph and replay it. */
+/* 1 = capture each chunk's launches in a hipGraph and replay it.  A graph is
+ * kept per chunk and set of buffers (arena interval, output, accumulator),
+ * at most 64 per plan; runs with further buffer sets are launched eagerly
+ * (same results). */
 tnc_status tnc_plan_set_graph(tnc_plan plan, int32_t enable);
 /* 1 (default) = run the contraction tree level by level (a step's level is
  * one more than the highest of its operands'): the small VALU GEMMs of one

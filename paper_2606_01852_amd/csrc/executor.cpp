@@ -307,12 +307,19 @@ void enqueue_chunk(Plan& plan, ChunkPlan& cp, const RunArgs& a, const int64_t* b
 }
 
 // The captured graph of one chunk plan for one set of buffers (created on
-// first use, replayed afterwards).
+// first use, replayed afterwards), or nullptr once the plan holds
+// kMaxGraphsPerPlan graphs: callers that keep handing in new buffers (a new
+// output tensor per call, requests at ever different arena offsets) then run
+// the chunk eagerly instead of growing the cache.  Nothing is evicted, so no
+// graph is destroyed while another thread may have it in flight.
+constexpr size_t kMaxGraphsPerPlan = 64;
+
 hipGraphExec_t chunk_graph(Plan& plan, ChunkPlan& cp, const RunArgs& a, const int64_t* cur_bases, bool overwrite) {
   const GraphKey key{cp.j, a.arena, a.acc, a.direct_out, cur_bases, overwrite};
   std::lock_guard<std::mutex> g(plan.graph_mu);
   auto it = plan.graphs.find(key);
   if (it != plan.graphs.end()) return it->second;
+  if (plan.graphs.size() >= kMaxGraphsPerPlan) return nullptr;
   if (!plan.capture_stream) check_hip(hipStreamCreate(&plan.capture_stream), "hipStreamCreate");
   hipGraph_t graph = nullptr;
   check_hip(hipStreamBeginCapture(plan.capture_stream, hipStreamCaptureModeThreadLocal), "begin capture");
@@ -397,8 +404,8 @@ void run_plan(Plan& plan, const RunArgs& a) {
   Launcher L{plan, plan.profile && !plan.graph ? &ev : nullptr};
   for (size_t c = 0; c < chunks.size(); ++c) {
     ChunkPlan& cp = ready(plan, chunks[c].first, a.stream);
-    if (plan.graph) {
-      hipGraphExec_t exec = chunk_graph(plan, cp, a, cur_dev, a.fresh_acc && c == 0);
+    hipGraphExec_t exec = plan.graph ? chunk_graph(plan, cp, a, cur_dev, a.fresh_acc && c == 0) : nullptr;
+    if (exec) {
       if (cp.n_base_slots)
         check_hip(hipMemcpyAsync(cur_dev, bases_dev + c * slots, slots * sizeof(int64_t), hipMemcpyDeviceToDevice,
                                  a.stream),

@@ -306,6 +306,30 @@ def test_graph_replay_matches_eager(ctx):
         assert torch.equal(torch.view_as_real(oe), torch.view_as_real(og))
 
 
+def test_graph_cache_cap_falls_back_to_eager(ctx):
+    """Every new output buffer of a single-slice direct-output run is a new
+    graph key; past the per-plan cap (64 graphs) runs are launched eagerly.
+    80 distinct buffers, then the first ones again: all bitwise equal to the
+    eager plan's result."""
+    net, path = pair_network(8, 7, 6, seed=11)
+    tn = tnc.Network(ctx, net.labels, net.extents, net.open, net.c64().leaves)
+    pe, pg = tnc.Plan(tn, path.pairs), tnc.Plan(tn, path.pairs)
+    tnc.tnc_plan_set_graph(pg.handle, True)
+    n = pe.info.n_result
+    ref = torch.empty(n, dtype=torch.complex64, device="cuda")
+    tnc.tnc_contract_async(pe.handle, 0, 1, ref.data_ptr(), tnc.OUT_C64)
+    outs = [torch.zeros(n, dtype=torch.complex64, device="cuda") for _ in range(80)]
+    for o in outs + outs[:8]:
+        o.zero_()
+        tnc.tnc_contract_async(pg.handle, 0, 1, o.data_ptr(), tnc.OUT_C64)
+    torch.cuda.synchronize()
+    for i, o in enumerate(outs):
+        assert torch.equal(torch.view_as_real(o), torch.view_as_real(ref)), i
+    pg.close()
+    pe.close()
+    tn.close()
+
+
 def _bits(x):
     return np.asarray(x).view(np.uint64)
 
