@@ -346,7 +346,10 @@ tnc_status tnc_batcher_destroy(tnc_batcher b);
 tnc_status tnc_submit_row(tnc_ctx ctx, tnc_batcher b, const void* const* row_data, int32_t in /* tnc_in */,
                           double* out_c128, tnc_req* id);
 /* done = 1 when finished; latency_s = submit-to-done wall time (else 0);
- * status of the request's execution is returned once done. */
+ * status of the request's execution is returned once done.  tnc_wait
+ * collects an id (after it, the id is unknown: TNC_E_ARG); tnc_poll does
+ * not.  A finished request no longer holds its plan, but its small record
+ * stays until collected or until the server stops. */
 tnc_status tnc_poll(tnc_ctx ctx, tnc_req id, int32_t* done, double* latency_s);
 tnc_status tnc_wait(tnc_ctx ctx, tnc_req id, double* latency_s);
 

@@ -88,7 +88,7 @@ class ArenaAllocator {
 
 struct Request {
   uint64_t id = 0;
-  std::shared_ptr<Plan> plan_ref;   // keeps the plan alive while queued or running
+  std::shared_ptr<Plan> plan_ref;   // keeps the plan alive while queued or running (dropped when done)
   Plan* plan = nullptr;
   int64_t first = 0, count = 0;
   double* out = nullptr;
@@ -212,6 +212,10 @@ struct Server {
         execute_rows(job, slot, stream);
       else
         execute(*job[0], slot, stream);
+      // plans of finished requests, released at the end of this iteration,
+      // after the lock and the notifications (a last reference tears the
+      // plan down, with device synchronizations)
+      std::vector<std::shared_ptr<Plan>> finished;
       {
         std::lock_guard<std::mutex> g(mu);
         Request& r = *job[0];
@@ -233,6 +237,8 @@ struct Server {
           q->done = true;
           q->row.clear();
           q->row.shrink_to_fit();
+          finished.push_back(std::move(q->plan_ref));
+          q->plan = nullptr;
         }
       }
       cv_work.notify_all();
