@@ -342,6 +342,30 @@ hipGraphExec_t chunk_graph(Plan& plan, ChunkPlan& cp, const RunArgs& a, const in
 
 }  // namespace
 
+// Add the timings of profiled launches to the step timers and free their
+// events (plan.mu held): all of them, waiting for each, or only those that
+// have completed.
+static void fold_events(Plan& plan, bool wait) {
+  size_t keep = 0;
+  for (size_t i = 0; i < plan.pending.size(); ++i) {
+    const auto e = plan.pending[i];
+    if (wait)
+      check_hip(hipEventSynchronize(e.first.second), "event sync");
+    else if (hipEventQuery(e.first.second) != hipSuccess) {
+      plan.pending[keep++] = e;
+      continue;
+    }
+    float ms = 0.f;
+    check_hip(hipEventElapsedTime(&ms, e.first.first, e.first.second), "event time");
+    StepTimer& t = plan.timers[e.second];
+    t.ms += ms;
+    t.launches += 1;
+    (void)hipEventDestroy(e.first.first);
+    (void)hipEventDestroy(e.first.second);
+  }
+  plan.pending.resize(keep);
+}
+
 int64_t run_workspace_bytes(Plan& plan, int64_t first, int64_t count) {
   const auto chunks = decompose(plan, first, count);
   int64_t peak = 0;
@@ -419,6 +443,8 @@ void run_plan(Plan& plan, const RunArgs& a) {
     std::lock_guard<std::mutex> g(plan.mu);
     if (plan.timers.size() < static_cast<size_t>(ns + 3)) plan.timers.resize(ns + 3);
     for (auto& e : ev) plan.pending.push_back(e);
+    // long profiled sessions: fold what has finished without waiting
+    if (plan.pending.size() > 16384) fold_events(plan, false);
   }
 }
 
@@ -438,17 +464,7 @@ Plan::~Plan() {
 
 void drain_profile(Plan& plan) {
   std::lock_guard<std::mutex> g(plan.mu);
-  for (auto& e : plan.pending) {
-    check_hip(hipEventSynchronize(e.first.second), "event sync");
-    float ms = 0.f;
-    check_hip(hipEventElapsedTime(&ms, e.first.first, e.first.second), "event time");
-    StepTimer& t = plan.timers[e.second];
-    t.ms += ms;
-    t.launches += 1;
-    (void)hipEventDestroy(e.first.first);
-    (void)hipEventDestroy(e.first.second);
-  }
-  plan.pending.clear();
+  fold_events(plan, true);
 }
 
 }  // namespace tnc
