@@ -517,3 +517,26 @@ def test_random_trees_odd_extents_and_slices(ctx, seed):
         vals.append(np.asarray(got))
     for v in vals[1:]:
         assert rel_fro(v, vals[0]) <= 1e-12
+
+
+def test_profile_counts_survive_long_sessions(ctx):
+    """A profiled plan run 20,000 times (its MFMA step's launches timed with
+    events, past the point where finished timings are folded without
+    waiting) reports every launch."""
+    net, path = pair_network(9, 8, 7, seed=12)
+    tn = tnc.Network(ctx, net.labels, net.extents, net.open, net.c64().leaves)
+    plan = tnc.Plan(tn, path.pairs)
+    tnc.tnc_plan_set_profile(plan.handle, True)
+    out = torch.empty(plan.info.n_result, dtype=torch.complex64, device="cuda")
+    tnc.tnc_contract_async(plan.handle, 0, 1, out.data_ptr(), tnc.OUT_C64)
+    torch.cuda.synchronize()
+    _, per_run = tnc.tnc_plan_get_profile(plan.handle, 0)
+    assert per_run >= 1
+    n_runs = 20000
+    for _ in range(n_runs):
+        tnc.tnc_contract_async(plan.handle, 0, 1, out.data_ptr(), tnc.OUT_C64)
+    torch.cuda.synchronize()
+    ms, launches = tnc.tnc_plan_get_profile(plan.handle, 0)
+    assert launches == per_run * (n_runs + 1) and ms > 0
+    plan.close()
+    tn.close()
