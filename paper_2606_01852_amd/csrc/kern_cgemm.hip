@@ -22,11 +22,13 @@
 // BF16x3: each float32 plane is split into bf16 hi/lo (round to nearest
 // even) while it is staged into LDS; every real product becomes
 // a_hi b_hi + (a_hi b_lo + a_lo b_hi) on bf16 MFMA with FP32 accumulation
-// (hi and cross terms in separate accumulators).
+// (hi and cross terms in separate accumulators; in the wide-wave variant,
+// one accumulator).
 //
-// Tiling.  A wave64 always owns a 64 x 32 complex tile of C (2x2 MFMA
-// 32x32 blocks of the real view, or 2x1 complex blocks in 3M); a workgroup
-// is WM x WN waves, so its tile is 64*WM x 32*WN complex.  K advances 16
+// Tiling.  A wave64 owns a 64 x 32 complex tile of C (2x2 MFMA 32x32 blocks
+// of the real view, or 2x1 complex blocks in 3M); a workgroup is WM x WN
+// waves, so its tile is 64*WM x 32*WN complex.  The split-bf16 256 x 128
+// tile instead runs 4x2 waves of 64 x 64 complex each (2x4 blocks).  K advances 16
 // complex per stage through double-buffered LDS (rows padded to 144 B: the
 // 16-byte fragment reads of 16 lanes hit 16 distinct 4-bank groups).  Each
 // lane reads 4 consecutive real k and feeds them to 4 successive MFMAs; the
@@ -53,10 +55,10 @@ constexpr int PITCH = 36;   // floats per LDS row (32 data + 4 pad)
 constexpr int SPITCH = 40;  // uint16 per LDS row of a bf16 plane (32 data + 8 pad)
 constexpr int GROUP_M = 8;
 
-template <int WM, int WN>
+template <int WM, int WN, int PW = 1>
 struct Shape {
-  static constexpr int BM = 64 * WM;   // rows of C per workgroup
-  static constexpr int BNC = 32 * WN;  // complex columns of C per workgroup
+  static constexpr int BM = 64 * WM;        // rows of C per workgroup
+  static constexpr int BNC = 32 * WN * PW;  // complex columns of C per workgroup (PW per wave)
   static constexpr int NT = 64 * WM * WN;
   static constexpr size_t lds_f32 = 2 * (BM + BNC) * PITCH * sizeof(float);
   // bf16 stage: A hi/lo planes of BM rows, B' hi/lo planes of 2*BNC real
@@ -95,9 +97,9 @@ __device__ __forceinline__ TileCoord map_tile(int64_t tiles_m, int64_t tiles_n, 
 // each block of 8 rows, so that the two groups of a 16-lane 8-byte LDS store
 // cycle hit disjoint banks (rows 80 bytes apart: A rows 4 apart, B' rows 4
 // apart = complex columns 2 apart); the data layout itself is unchanged.
-template <int WM, int WN, int VW, bool SWZ = false>
+template <int WM, int WN, int VW, bool SWZ = false, int PW = 1>
 struct Stage {
-  using S = Shape<WM, WN>;
+  using S = Shape<WM, WN, PW>;
   static constexpr int PER_ROW = BKC / VW;
   __device__ __forceinline__ static int row_a(int idx) {
     const int g = idx / PER_ROW;
@@ -270,15 +272,16 @@ __device__ __forceinline__ void row_offsets8(const GemmDesc& d, bool perm, int64
 // row offsets of the rows it stores.  The swap runs in both lanes of a pair
 // whatever their row bounds (the column bound is shared by the pair).
 // val(i, j, v) is the lane's accumulated value of MFMA block (i, j), entry v.
-template <class Val>
+template <int PW = 1, class Val>
 __device__ __forceinline__ void store_perm_pairs(const GemmDesc& d, const TileCoord& tc, int wm, int wn, int lane,
                                                  Val val) {
+  constexpr int NJ = 2 * PW;  // 32-real-column blocks per wave
   const int h = lane >> 5, l32 = lane & 31;
   const bool odd = l32 & 1;
   float2* Cz = d.C + tc.b * d.m * d.n;
-  int64_t co[2];
+  int64_t co[NJ];
 #pragma unroll
-  for (int j = 0; j < 2; ++j) co[j] = col_offset(d, true, (tc.col0 * 2 + wn * 64 + j * 32 + l32) >> 1);
+  for (int j = 0; j < NJ; ++j) co[j] = col_offset(d, true, (tc.col0 * 2 + wn * 64 * PW + j * 32 + l32) >> 1);
 #pragma unroll
   for (int i = 0; i < 2; ++i)
 #pragma unroll
@@ -292,7 +295,7 @@ __device__ __forceinline__ void store_perm_pairs(const GemmDesc& d, const TileCo
         ro[t] = row < d.m ? d.offM[row] : -1;
       }
 #pragma unroll
-      for (int j = 0; j < 2; ++j) {
+      for (int j = 0; j < NJ; ++j) {
         if (co[j] < 0) continue;
 #pragma unroll
         for (int t = 0; t < 4; ++t) {
@@ -311,6 +314,7 @@ template <int WM, int WN, int VW>
 struct Ops4M {
   using S = Shape<WM, WN>;
   static constexpr bool kSwizzle = false;
+  static constexpr int kPW = 1;
   f16v acc[2][2];
 
   __device__ __forceinline__ void init() {
@@ -390,6 +394,7 @@ template <int WM, int WN, int VW>
 struct Ops3M {
   using S = Shape<WM, WN>;
   static constexpr bool kSwizzle = false;
+  static constexpr int kPW = 1;
   f16v t1[2], t2[2], t3[2];
 
   __device__ __forceinline__ void init() {
@@ -477,6 +482,7 @@ template <int WM, int WN, int VW>
 struct OpsBF16x3 {
   using S = Shape<WM, WN>;
   static constexpr bool kSwizzle = true;
+  static constexpr int kPW = 1;
   // hi*hi products and the two cross products accumulate separately: the
   // cross terms are ~2^-8 smaller, so their rounding barely adds to that of
   // the main sum
@@ -566,13 +572,110 @@ struct OpsBF16x3 {
   }
 };
 
+// ------------------------------------------------------------------ split BF16x3, wide waves
+// The same products with each wave covering 64 complex columns (four
+// 32-column blocks of the real 4M operand) instead of 32: every A fragment
+// read from LDS feeds four blocks instead of two and the workgroup's staging
+// (and its split) is shared by twice the MFMA work, so the kernel issues
+// about 40 % fewer instructions per MFMA.  The accumulator budget of the
+// wider tile allows one accumulator set: hi*hi and the two cross products
+// accumulate together (FP32, as in the 4M kernel).
+template <int WM, int WN, int VW>
+struct OpsBF16x3W {
+  using S = Shape<WM, WN, 2>;
+  static constexpr bool kSwizzle = true;
+  static constexpr int kPW = 2;
+  f16v acc[2][4];
+
+  __device__ __forceinline__ void init() {
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+      for (int j = 0; j < 4; ++j)
+#pragma unroll
+        for (int v = 0; v < 16; ++v) acc[i][j][v] = 0.f;
+  }
+
+  __device__ __forceinline__ static const uint16_t* planes(const char* lds, int buf) {
+    return reinterpret_cast<const uint16_t*>(lds) + buf * S::BF16_STAGE;
+  }
+
+  template <class St>
+  __device__ __forceinline__ void stage(const St& st, char* lds, int buf, int tid) const {
+    uint16_t* Ah = const_cast<uint16_t*>(planes(lds, buf));
+    uint16_t* Al = Ah + S::BM * SPITCH;
+    uint16_t* Bh = Al + S::BM * SPITCH;
+    uint16_t* Bl = Bh + 2 * S::BNC * SPITCH;
+    st.store_split(Ah, Al, Bh, Bl, tid);
+  }
+
+  // lane (h, r) supplies 8 consecutive K values of row r (A) or real column
+  // r (B') per 32x32x16 MFMA, as in OpsBF16x3; this wave's real columns of
+  // B' are 128 * wn + 32 * j + r, j = 0..3.
+  __device__ __forceinline__ void compute(const char* lds, int buf, int wm, int wn, int lane) {
+    const uint16_t* Ah = planes(lds, buf);
+    const uint16_t* Al = Ah + S::BM * SPITCH;
+    const uint16_t* Bh = Al + S::BM * SPITCH;
+    const uint16_t* Bl = Bh + 2 * S::BNC * SPITCH;
+    const int h = lane >> 5, l32 = lane & 31;
+#pragma unroll
+    for (int s = 0; s < 2; ++s) {
+      const int koff = 8 * (2 * s + h);
+      s8v ah[2], al[2];
+#pragma unroll
+      for (int i = 0; i < 2; ++i) {
+        const int row = wm * 64 + i * 32 + l32;
+        ah[i] = *reinterpret_cast<const s8v*>(Ah + row * SPITCH + koff);
+        al[i] = *reinterpret_cast<const s8v*>(Al + row * SPITCH + koff);
+      }
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        const int row = 128 * wn + 32 * j + l32;
+        const s8v bh = *reinterpret_cast<const s8v*>(Bh + row * SPITCH + koff);
+        const s8v bl = *reinterpret_cast<const s8v*>(Bl + row * SPITCH + koff);
+#pragma unroll
+        for (int i = 0; i < 2; ++i) {
+          acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(__builtin_bit_cast(bf8, ah[i]),
+                                                              __builtin_bit_cast(bf8, bl), acc[i][j], 0, 0, 0);
+          acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(__builtin_bit_cast(bf8, al[i]),
+                                                              __builtin_bit_cast(bf8, bh), acc[i][j], 0, 0, 0);
+          acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(__builtin_bit_cast(bf8, ah[i]),
+                                                              __builtin_bit_cast(bf8, bh), acc[i][j], 0, 0, 0);
+        }
+      }
+    }
+  }
+
+  __device__ __forceinline__ void store(const GemmDesc& d, bool perm, const TileCoord& tc, int wm, int wn,
+                                        int lane) const {
+    const int h = lane >> 5, l32 = lane & 31;
+    float* C = reinterpret_cast<float*>(d.C + tc.b * d.m * d.n) + (l32 & 1);
+    if (!perm) {
+#pragma unroll
+      for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+          const int64_t col = (tc.col0 * 2 + wn * 128 + j * 32 + l32) >> 1;
+          if (col >= d.n) continue;
+#pragma unroll
+          for (int v = 0; v < 16; ++v) {
+            const int64_t row = tc.row0 + wm * 64 + i * 32 + 8 * (v >> 2) + 4 * h + (v & 3);
+            if (row < d.m) C[2 * (row * d.n + col)] = acc[i][j][v];
+          }
+        }
+      return;
+    }
+    store_perm_pairs<2>(d, tc, wm, wn, lane, [&](int i, int j, int v) { return acc[i][j][v]; });
+  }
+};
+
 // ------------------------------------------------------------------ driver
 template <int WM, int WN, int VW, bool CHECK, class Ops>
 __device__ __forceinline__ void main_loop(const GemmDesc& d, const float2* A, const float2* B, const TileCoord& tc,
                                           char* lds, Ops& ops, int tid, int wm, int wn, int lane) {
   const int64_t nk = (d.k + BKC - 1) / BKC;
   const int64_t ld = row_stride(d);
-  Stage<WM, WN, VW, Ops::kSwizzle> st;
+  Stage<WM, WN, VW, Ops::kSwizzle, Ops::kPW> st;
   st.template load<CHECK>(A, B, d.m, d.n, d.k, ld, tc.row0, tc.col0, 0, tid);
   ops.stage(st, lds, 0, tid);
   __syncthreads();
@@ -588,7 +691,7 @@ __device__ __forceinline__ void main_loop(const GemmDesc& d, const float2* A, co
 template <template <int, int, int> class OpsT, int WM, int WN, int VW, bool PERM>
 __global__ __launch_bounds__(64 * WM * WN, (WM * WN <= 4) ? 2 : 1) void cgemm_mfma(GemmDesc d, int64_t tiles_m, int64_t tiles_n,
                                                            int64_t total) {
-  using S = Shape<WM, WN>;
+  using S = Shape<WM, WN, OpsT<WM, WN, VW>::kPW>;
   extern __shared__ __attribute__((aligned(16))) char lds[];
   const int tid = threadIdx.x;
   const int lane = tid & 63, wave = tid >> 6;
@@ -628,7 +731,7 @@ hipError_t ensure_lds(size_t lds) {
 
 template <template <int, int, int> class OpsT, int WM, int WN, int VW, bool PERM>
 hipError_t launch_one(const GemmDesc& d, size_t lds, hipStream_t s) {
-  using S = Shape<WM, WN>;
+  using S = Shape<WM, WN, OpsT<WM, WN, VW>::kPW>;
   const int64_t tiles_m = (d.m + S::BM - 1) / S::BM;
   const int64_t tiles_n = (d.n + S::BNC - 1) / S::BNC;
   const int64_t total = tiles_m * tiles_n * d.h;
@@ -643,7 +746,7 @@ hipError_t launch_one(const GemmDesc& d, size_t lds, hipStream_t s) {
 
 template <template <int, int, int> class OpsT, int WM, int WN>
 void prepare_shape(bool bf16) {
-  using S = Shape<WM, WN>;
+  using S = Shape<WM, WN, OpsT<WM, WN, 2>::kPW>;
   const size_t lds = bf16 ? S::lds_bf16 : S::lds_f32;
   (void)ensure_lds<OpsT, WM, WN, 2, false>(lds);
   (void)ensure_lds<OpsT, WM, WN, 2, true>(lds);
@@ -654,7 +757,7 @@ void prepare_ops(bool bf16) {
   prepare_shape<OpsT, 2, 2>(bf16);
   prepare_shape<OpsT, 4, 2>(bf16);
   prepare_shape<OpsT, 2, 4>(bf16);
-  if (!bf16) prepare_shape<OpsT, 4, 4>(bf16);  // split precision runs 4x4 as 2x4
+  if (!bf16) prepare_shape<OpsT, 4, 4>(bf16);  // split precision: 4x2 wide waves (prepare_gemm_kernels)
   prepare_shape<OpsT, 1, 2>(bf16);
   prepare_shape<OpsT, 2, 1>(bf16);
   prepare_shape<OpsT, 1, 1>(bf16);
@@ -665,7 +768,7 @@ void prepare_ops(bool bf16) {
 
 template <template <int, int, int> class OpsT, int WM, int WN>
 hipError_t launch_shape(const GemmDesc& d, bool bf16, hipStream_t s) {
-  using S = Shape<WM, WN>;
+  using S = Shape<WM, WN, OpsT<WM, WN, 2>::kPW>;
   const size_t lds = bf16 ? S::lds_bf16 : S::lds_f32;
   const bool perm = d.offM != nullptr;
   return perm ? launch_one<OpsT, WM, WN, 2, true>(d, lds, s) : launch_one<OpsT, WM, WN, 2, false>(d, lds, s);
@@ -677,9 +780,9 @@ hipError_t launch_variant(const GemmDesc& d, int variant, bool bf16, hipStream_t
     const size_t lds = bf16 ? Shape<2, 2>::lds_bf16 : Shape<2, 2>::lds_f32;
     return d.offM ? launch_one<OpsT, 2, 2, 1, true>(d, lds, s) : launch_one<OpsT, 2, 2, 1, false>(d, lds, s);
   }
-  // split precision: the 4x4-wave shape would need all 160 KiB of LDS and
-  // spill its accumulators, so it runs as 2x4
-  if (bf16 && variant == 3) variant = 2;
+  // split precision: the 256 x 128 tile runs as 4x2 wide waves (16 waves of
+  // the narrow kind would spill their two accumulator sets)
+  if (bf16 && variant == 3) return launch_shape<OpsBF16x3W, 4, 2>(d, true, s);
   switch (variant) {
     case 0: return launch_shape<OpsT, 2, 2>(d, bf16, s);
     case 1: return launch_shape<OpsT, 4, 2>(d, bf16, s);
@@ -698,6 +801,7 @@ void prepare_gemm_kernels() {
   prepare_ops<Ops4M>(false);
   prepare_ops<Ops3M>(false);
   prepare_ops<OpsBF16x3>(true);
+  prepare_shape<OpsBF16x3W, 4, 2>(true);
 }
 
 void gemm_variant_tile(int variant, int* bm, int* bnc) {

@@ -178,6 +178,27 @@ def test_grid8_bond4(ctx, prec):
     assert 0 < abs(z) * 2.0 ** -shift < 1e-20
 
 
+def test_grid8_bf16x3_wide_tile_permuted_stores(ctx):
+    """Split-bf16x3's 256 x 128 tile (wide waves, one accumulator set) forced
+    on every MFMA step of grid8, most of them stored in consumer order:
+    within the split bounds of the emulation and of the exact value."""
+    net, shift = prescaled_grid(8, 8, 4, seed=1002)
+    path = greedy_path(net)
+    tnc.tnc_ctx_set_gemm_variant(ctx.handle, 3)
+    try:
+        z, plan, _ = run(ctx, net, path, prec=tnc.PREC_BF16X3)
+    finally:
+        tnc.tnc_ctx_set_gemm_variant(ctx.handle, -1)
+    steps = [tnc.tnc_plan_get_step(plan.handle, s) for s in range(len(path.pairs))]
+    assert any(st.kernel == 0 and st.natural == 0 for st in steps)   # MFMA with permuted store
+    exact = complex(oc.contract(net, path))
+    emu = complex(oc.contract(net, path, step=osp.split_step))
+    t_emu, t_exact = split_tols(net, path)
+    print(f"grid8 bf16x3 wide tile: err vs emulation {abs(z - emu) / abs(emu):.2e} (tol {t_emu:.1e})", flush=True)
+    assert abs(z - emu) <= t_emu * abs(emu)
+    assert abs(z - exact) <= t_exact * abs(exact)
+
+
 def test_pair_permuted_operands(ctx):
     net, path = pair_network(10, 9, 8, seed=3)
     print("pair 10/9/8", flush=True)
