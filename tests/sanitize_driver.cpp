@@ -1,6 +1,6 @@
-// Host-side driver of the C ABI for the sanitizer test (AddressSanitizer and
-// UndefinedBehaviorSanitizer on the host code; no GPU is touched: every call
-// goes to a host-only context).
+// Host-side driver of the C ABI for the sanitizer tests (AddressSanitizer,
+// UndefinedBehaviorSanitizer or ThreadSanitizer on the host code; no GPU is
+// touched: every call goes to a host-only context).
 //
 // Input (whitespace-separated integers, one network per file):
 //   n_tensors  then per tensor: rank, labels...
@@ -12,17 +12,24 @@
 // For each network the driver plans it (both execution orders, every chunk
 // size), queries every step and order, plans its distribution over 2, 4 and
 // 8 devices, creates and destroys a batcher when asked, and checks that
-// malformed inputs come back as status codes.  Prints "ok <file>" per file.
+// malformed paths come back as status codes; a fixed set of malformed
+// networks, paths, slices and kernel arguments runs first.  Prints
+// "ok <file>" per file.  With --threads N first, N threads each plan every
+// network on a context of their own at the same time (for ThreadSanitizer:
+// contexts share no mutable state).
+#include <atomic>
 #include <cstdio>
 #include <cstdlib>
+#include <cstring>
 #include <fstream>
+#include <thread>
 #include <vector>
 
 #include "../include/tnc.h"
 
 namespace {
 
-int fails = 0;
+std::atomic<int> fails{0};
 
 void expect(bool cond, const char* what, const char* file) {
   if (!cond) {
@@ -262,7 +269,34 @@ void malformed(tnc_ctx ctx) {
 
 }  // namespace
 
+int threaded(int n_threads, int n_files, char** files) {
+  std::vector<NetFile> nets(n_files);
+  for (int i = 0; i < n_files; ++i)
+    if (!read_net(files[i], nets[i])) {
+      std::fprintf(stderr, "cannot read %s\n", files[i]);
+      return 2;
+    }
+  std::vector<std::thread> pool;
+  for (int t = 0; t < n_threads; ++t)
+    pool.emplace_back([&, t] {
+      tnc_ctx ctx = nullptr;
+      if (tnc_ctx_create(-1, nullptr, size_t{64} << 30, nullptr, &ctx) != TNC_OK) {
+        ++fails;
+        return;
+      }
+      for (int i = 0; i < n_files; ++i) {
+        const int f = (i + t) % n_files;  // threads start on different networks
+        exercise(ctx, nets[f], files[f]);
+        std::printf("ok %s\n", files[f]);
+      }
+      tnc_ctx_destroy(ctx);
+    });
+  for (auto& th : pool) th.join();
+  return fails ? 1 : 0;
+}
+
 int main(int argc, char** argv) {
+  if (argc > 2 && std::strcmp(argv[1], "--threads") == 0) return threaded(std::atoi(argv[2]), argc - 3, argv + 3);
   tnc_ctx ctx = nullptr;
   if (tnc_ctx_create(-1, nullptr, size_t{64} << 30, nullptr, &ctx) != TNC_OK) {
     std::fprintf(stderr, "host context: %s\n", tnc_last_error());

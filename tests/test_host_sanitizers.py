@@ -1,4 +1,5 @@
-"""The host code of the library under AddressSanitizer and UndefinedBehaviorSanitizer.
+"""The host code of the library under AddressSanitizer and UndefinedBehaviorSanitizer,
+and under ThreadSanitizer with several contexts planning at once.
 
 The planner, the distribution planner, the batcher's validation and the C ABI's
 error paths are rebuilt with host-side instrumentation (the device code is
@@ -6,7 +7,9 @@ the ordinary build's objects) and linked into ``sanitize_driver.cpp``, which
 plans a set of networks on a host-only context (every execution order and
 chunk size, every step query, distribution over 2, 4 and 8 devices) and feeds
 the ABI malformed inputs.  Any out-of-bounds access, use after free, leak or
-undefined operation ends the driver with a report.  No GPU is used.
+undefined operation ends the driver with a report.  The ThreadSanitizer build
+runs the same planning in four threads, each on a context of its own
+(independent contexts share no mutable state).  No GPU is used.
 """
 import concurrent.futures as cf
 import os
@@ -26,6 +29,7 @@ ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 HOST_SOURCES = ["api", "planner", "executor", "serve", "autotune", "distplan"]
 SAN = ["-Xarch_host", "-fsanitize=address", "-Xarch_host", "-fsanitize=undefined",
        "-Xarch_host", "-fno-sanitize-recover=undefined", "-Xarch_host", "-fno-omit-frame-pointer"]
+TSAN = ["-Xarch_host", "-fsanitize=thread"]
 
 pytestmark = pytest.mark.skipif(shutil.which("hipcc") is None, reason="hipcc not installed")
 
@@ -53,18 +57,21 @@ def _hipcc(args):
         raise RuntimeError("hipcc " + " ".join(args) + "\n" + r.stderr)
 
 
-@pytest.fixture(scope="module")
-def driver(tmp_path_factory):
-    out = tmp_path_factory.mktemp("san")
+def _build_driver(out, san):
     common = ["-O1", "-g", "-std=c++17", "-fPIC", f"--offload-arch={pkg_build.ARCH}",
-              "-I", os.path.join(ROOT, "include")] + pkg_build.DEVICE_FLAGS + SAN
+              "-I", os.path.join(ROOT, "include")] + pkg_build.DEVICE_FLAGS + san
     jobs = [(os.path.join(pkg_build.CSRC, f + ".cpp"), str(out / (f + ".o"))) for f in HOST_SOURCES]
     jobs.append((os.path.join(ROOT, "tests", "sanitize_driver.cpp"), str(out / "driver.o")))
     with cf.ThreadPoolExecutor(max_workers=4) as ex:
         list(ex.map(lambda j: _hipcc(common + ["-c", j[0], "-o", j[1]]), jobs))
     exe = str(out / "sanitize_driver")
-    _hipcc([f"--offload-arch={pkg_build.ARCH}"] + SAN + [j[1] for j in jobs] + _kernel_objects() + ["-o", exe])
+    _hipcc([f"--offload-arch={pkg_build.ARCH}"] + san + [j[1] for j in jobs] + _kernel_objects() + ["-o", exe])
     return exe
+
+
+@pytest.fixture(scope="module")
+def driver(tmp_path_factory):
+    return _build_driver(tmp_path_factory.mktemp("san"), SAN)
 
 
 def _write_net(path, net, pairs, sliced=(), batch_label=-1, batch_leaves=()):
@@ -119,3 +126,15 @@ def test_host_code_is_clean_under_asan_and_ubsan(driver, tmp_path):
     assert r.returncode == 0, report
     assert "runtime error" not in r.stderr, report
     assert r.stdout.count("ok ") == len(files) + 1, report
+
+
+def test_concurrent_contexts_are_race_free_under_tsan(tmp_path_factory, tmp_path):
+    exe = _build_driver(tmp_path_factory.mktemp("tsan"), TSAN)
+    files = _networks(tmp_path)
+    env = dict(os.environ)
+    env["TSAN_OPTIONS"] = "halt_on_error=1:exitcode=23"
+    r = subprocess.run([exe, "--threads", "4"] + files, capture_output=True, text=True, timeout=600, env=env)
+    report = r.stdout[-2000:] + r.stderr[-8000:]
+    assert r.returncode == 0, report
+    assert "ThreadSanitizer" not in r.stderr, report
+    assert r.stdout.count("ok ") == 4 * len(files), report
