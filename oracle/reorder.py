@@ -78,11 +78,6 @@ def reorder(labels: Sequence[Sequence[int]], pairs: np.ndarray, open_labels: Seq
     return target, steps
 
 
-def leaf_permuted(labels: Sequence[Sequence[int]], target: List[List[int]]) -> List[bool]:
-    """Leaves whose stored order differs from the order their consumer needs."""
-    return [list(labels[t]) != target[t] for t in range(len(labels))]
-
-
 def lifetimes(labels: Sequence[Sequence[int]], pairs: np.ndarray, open_labels: Sequence[int],
               batch_order: Sequence[int] = ()) -> Dict[int, float]:
     """Step index at which each label is summed (inf for labels never summed):

@@ -25,6 +25,47 @@ def test_cost_formulas_hand_example(golden_dir):
     assert abs(got - c["expect"]) <= 1e-15
 
 
+def test_gemm_and_gather_terms_hand_example(golden_dir):
+    """Eq. (6) per-device GEMM time (chain operand and output split P ways,
+    the other operand whole on every device) and the chain-end gather, on
+    hand-computed values: a replicated operand divided by P, or a gather
+    without its (P - 1) / P factor, misses them."""
+    d = json.load(open(os.path.join(golden_dir, "dist_cost_example.json")))
+    for g in d["gemm"]:
+        eq = dict(a=g["a"], b=g["b"], c=g["c"], ops=g["ops"])
+        got = od.t_gemm(eq, g["P"], dict(B_dev=g["B_dev"], F_dev=g["F_dev"]))
+        assert got == pytest.approx(g["expect"], rel=1e-12)
+    g = d["gather"]
+    assert od.t_gather(dict(c=g["c"]), g["P"], dict(B_net=g["B_net"])) == pytest.approx(g["expect"], rel=1e-12)
+
+
+def test_chain_schedule_hand_example(golden_dir):
+    """A three-equation chain whose every term was computed by hand (Eq. (4)
+    prefixes, Eq. (6) per equation, one forced redistribution under Eq. (7),
+    the final gather): the oracle's enumeration and the library's DP both
+    reach exactly the hand-computed optimum and schedule."""
+    c = json.load(open(os.path.join(golden_dir, "dist_cost_example.json")))["chain"]
+    hw = dict(B_dev=c["B_dev"], F_dev=c["F_dev"], B_net=c["B_net"], lat=c["lat"])
+    ext = np.full(c["n_labels"], 2, dtype=np.int64)
+    labels = [tuple(x) for x in c["labels"]]
+    pairs = np.array(c["pairs"], dtype=np.int32)
+    chains = od.use_chains(labels, pairs, tuple(c["open"]), ext, c["large_bytes"])
+    assert len(chains) == 1 and [e["step"] for e in chains[0]] == [0, 1, 2]
+    for e, tg in zip(chains[0], c["t_gemm"]):
+        assert od.t_gemm(e, c["P"], hw) == pytest.approx(tg, rel=1e-12)
+    best, bits = od.brute_force(chains[0], c["P"], hw)
+    assert best == pytest.approx(c["total"], rel=1e-12) and list(bits) == c["redist"]
+    assert od.evaluate(chains[0], c["P"], hw, [False, False]) is None   # keeping (0, 1) into eq2 is forbidden
+    plan = tnc.Plan(tnc.Network(tnc.Context(-1), labels, ext, tuple(c["open"])), pairs)
+    steps, total, moved = tnc.tnc_plan_distribute(plan.handle, c["P"], c["large_bytes"], hw["B_dev"], hw["F_dev"],
+                                                  hw["B_net"], hw["lat"])
+    assert [s.state for s in steps] == c["states"]
+    assert [s.t_gemm_s for s in steps] == pytest.approx(c["t_gemm"], rel=1e-12)
+    assert steps[1].t_comm_s == pytest.approx(c["t_comm"], rel=1e-12)
+    assert total == pytest.approx(c["total"], rel=1e-12)
+    assert moved == pytest.approx(c["moved"], rel=1e-12)
+
+
 def caterpillar(rng, n_side, n_main=8, max_new=3, max_sum=3):
     """A main tensor absorbing side tensors one by one (all extents 2): each
     side tensor sums some current modes of the main tensor and adds new
