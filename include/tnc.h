@@ -30,7 +30,12 @@
  *     tnc_last_error() (thread-local) says why.  Asynchronous device faults
  *     surface as TNC_E_DEVICE at the next synchronising call.
  *   - Threads: tnc_submit / tnc_submit_row / tnc_poll / tnc_wait are
- *     thread-safe; every other call is single-threaded per context.
+ *     thread-safe; every other call is single-threaded per context.  While
+ *     a context serves (tnc_serve_start .. tnc_serve_stop), calls that would
+ *     change what its worker threads read return TNC_E_BUSY: replacing
+ *     leaves, tnc_plan_set_max_chunk / _autotune / _set_graph /
+ *     _set_grouping / _set_profile, tnc_ctx_set_gemm_variant, and direct
+ *     contractions (tnc_contract, tnc_contract_async).
  *   - "Device pointer" means memory on the context's GPU (e.g. a torch CUDA
  *     tensor's data_ptr()); "host pointer" means ordinary host memory.
  */
@@ -116,7 +121,10 @@ tnc_status tnc_net_create(tnc_ctx ctx, int32_t n_tensors, const int32_t* ranks,
                           const int32_t* open_labels, const void* const* host_data,
                           int32_t in /* tnc_in */, tnc_net* out);
 /* Replace leaf `tensor`'s values (same shape), e.g. a new bitstring's
- * projectors.  Synchronous host-to-device copy.  Plans of the network see
+ * projectors: the network's structure and the path stay, only a leaf's data
+ * changes (Sec. II-A: a leaf is a tensor of the network; an amplitude
+ * query fixes the output qubits' values through such leaves).
+ * Synchronous host-to-device copy.  Plans of the network see
  * the new values from their next run on (cached permuted copies are
  * refreshed then); replacing a leaf while runs of its network are in flight
  * is a race. */
@@ -253,7 +261,10 @@ tnc_status tnc_device_calibrate(tnc_ctx ctx, tnc_dist_hw* hw);
 
 /* ---------------------------------------------------------------- contract
  * Sum over slices [first_slice, first_slice + n_slices) of the sliced
- * contractions, accumulated in FP64 on the device; out_c128 (host pointer,
+ * contractions (Sec. II-C: slicing fixes the sliced labels, each slice is an
+ * independent contraction, and the result is the sum over all slices; every
+ * slice is contracted along the path as in Sec. II-B), accumulated in FP64
+ * on the device; out_c128 (host pointer,
  * n_result complex128 values, open-label order) receives the result.  A
  * closed network (n_open = 0) yields one amplitude.  Synchronous. */
 tnc_status tnc_contract(tnc_plan plan, int64_t first_slice, int64_t n_slices, double* out_c128);
@@ -304,7 +315,11 @@ tnc_status tnc_ctx_sync(tnc_ctx ctx);
  * not fit the free arena yet blocks the ones behind it).  out_c128 (host
  * pointer) must stay valid until the request is done.  TNC_E_BUSY if the
  * queue is full or the plan's network has a batcher (see below);
- * TNC_E_NOMEM if the request can never fit. */
+ * TNC_E_NOMEM if the request can never fit.
+ * On a host-only context (device -1, with an arena size) the server admits
+ * and queues in the same way but executes nothing: every request completes
+ * with TNC_E_UNSUPPORTED and leaves its output untouched (a dry run of the
+ * admission and queueing). */
 tnc_status tnc_serve_start(tnc_ctx ctx, int32_t max_inflight, int32_t queue_cap);
 /* Heavy-request lane: threshold in planned FLOPs (<= 0 disables the lane)
  * and the number of heavy requests that may run at once (>= 1).  Applies to

@@ -16,12 +16,35 @@ void check_hip(hipError_t e, const char* what) {
   if (e != hipSuccess) fail(TNC_E_DEVICE, std::string(what) + ": " + hipGetErrorString(e));
 }
 
+std::recursive_mutex& runtime_mu() {
+  static std::recursive_mutex mu;
+  return mu;
+}
+
+void* pinned_alloc(size_t bytes, const char* what) {
+  std::lock_guard<std::recursive_mutex> g(runtime_mu());
+  void* p = nullptr;
+  check_hip(hipHostMalloc(&p, bytes, hipHostMallocDefault), what);
+  return p;
+}
+
+void pinned_free(void* p) {
+  if (!p) return;
+  std::lock_guard<std::recursive_mutex> g(runtime_mu());
+  (void)hipHostFree(p);
+}
+
+void refuse_while_serving(const Ctx& c, const char* what) {
+  if (c.server) fail(TNC_E_BUSY, std::string("the context is serving: ") + what + " is refused until tnc_serve_stop");
+}
+
 DeviceBuf::~DeviceBuf() { reset(); }
 
 void DeviceBuf::alloc(size_t n) {
   reset();
   if (n == 0) return;
   void* p = nullptr;
+  std::lock_guard<std::recursive_mutex> g(runtime_mu());
   const hipError_t e = hipMalloc(&p, n);
   if (e != hipSuccess) {
     (void)hipGetLastError();
@@ -33,7 +56,10 @@ void DeviceBuf::alloc(size_t n) {
 }
 
 void DeviceBuf::reset() {
-  if (ptr) (void)hipFree(ptr);
+  if (ptr) {
+    std::lock_guard<std::recursive_mutex> g(runtime_mu());
+    (void)hipFree(ptr);
+  }
   ptr = nullptr;
   bytes = 0;
 }
@@ -51,6 +77,7 @@ Ctx::~Ctx() {
     (void)hipSetDevice(device);
     if (stream) (void)hipStreamSynchronize(stream);
     scratch.reset();
+    std::lock_guard<std::recursive_mutex> g(runtime_mu());
     if (own_arena && arena) (void)hipFree(arena);
     if (own_stream && stream) (void)hipStreamDestroy(stream);
   }
@@ -107,6 +134,7 @@ tnc_status tnc_ctx_create(int device, void* arena, size_t arena_bytes, void* str
       c.arena = static_cast<char*>(arena);
     } else if (arena_bytes) {
       void* p = nullptr;
+      std::lock_guard<std::recursive_mutex> g(runtime_mu());
       const hipError_t e = hipMalloc(&p, arena_bytes);
       if (e != hipSuccess) {
         (void)hipGetLastError();
@@ -121,6 +149,7 @@ tnc_status tnc_ctx_create(int device, void* arena, size_t arena_bytes, void* str
     if (stream) {
       c.stream = static_cast<hipStream_t>(stream);
     } else {
+      std::lock_guard<std::recursive_mutex> g(runtime_mu());
       check_hip(hipStreamCreate(&c.stream), "hipStreamCreate");
       c.own_stream = true;
     }
@@ -143,6 +172,7 @@ tnc_status tnc_ctx_set_gemm_variant(tnc_ctx ctx, int32_t variant) {
   TNC_TRY
   if (!ctx) fail(TNC_E_ARG, "ctx is NULL");
   if (variant < -1 || variant >= kGemmVariants) fail(TNC_E_ARG, "variant out of range");
+  refuse_while_serving(*ctx->c, "changing the forced tile variant");
   ctx->c->gemm_variant = variant;
   TNC_CATCH
 }
@@ -220,6 +250,7 @@ tnc_status tnc_net_set_tensor(tnc_net net, int32_t tensor, const void* host_data
   if (in != TNC_IN_C64 && in != TNC_IN_C128) fail(TNC_E_ARG, "unknown input element type");
   Net& n = *net->n;
   if (tensor < 0 || tensor >= n.n_tensors) fail(TNC_E_ARG, "tensor out of range");
+  refuse_while_serving(*n.ctx, "replacing a leaf");
   set_device(*n.ctx);
   check_hip(hipStreamSynchronize(n.ctx->stream), "stream synchronize");
   upload_leaf(n, tensor, host_data, in);
@@ -231,6 +262,7 @@ tnc_status tnc_net_set_tensor_device(tnc_net net, int32_t tensor, const void* de
   if (!net || !dev_data) fail(TNC_E_ARG, "net/dev_data is NULL");
   Net& n = *net->n;
   if (tensor < 0 || tensor >= n.n_tensors) fail(TNC_E_ARG, "tensor out of range");
+  refuse_while_serving(*n.ctx, "replacing a leaf");
   set_device(*n.ctx);
   check_hip(hipMemcpyAsync(n.leaf[tensor].ptr, dev_data, n.numel[tensor] * 8, hipMemcpyDeviceToDevice, n.ctx->stream),
             "leaf copy");
@@ -379,6 +411,7 @@ tnc_status tnc_plan_set_max_chunk(tnc_plan plan, int64_t max_chunk) {
   TNC_TRY
   if (!plan) fail(TNC_E_ARG, "plan is NULL");
   Plan& p = *plan->p;
+  refuse_while_serving(*p.net->ctx, "changing the chunk cap");
   p.max_chunk_user = max_chunk;
   int j = 0;
   for (int q = 1; q < static_cast<int>(p.suffix_prod.size()); ++q) {
@@ -421,16 +454,21 @@ tnc_status tnc_plan_autotune(tnc_plan plan) {
   TNC_TRY
   if (!plan) fail(TNC_E_ARG, "plan is NULL");
   Plan& p = *plan->p;
+  refuse_while_serving(*p.net->ctx, "autotuning");
   set_device(*p.net->ctx);
-  std::lock_guard<std::mutex> g(p.mu);
-  for (auto& cp : p.chunks)
-    if (cp) assign_variants(p, *cp, true);
+  {
+    std::lock_guard<std::mutex> g(p.mu);
+    for (auto& cp : p.chunks)
+      if (cp) assign_variants(p, *cp, true);
+  }
+  p.drop_graphs();  // captured graphs hold the previous tile variants
   TNC_CATCH
 }
 
 tnc_status tnc_plan_set_graph(tnc_plan plan, int32_t enable) {
   TNC_TRY
   if (!plan) fail(TNC_E_ARG, "plan is NULL");
+  refuse_while_serving(*plan->p->net->ctx, "switching graph replay");
   plan->p->graph = enable ? 1 : 0;
   TNC_CATCH
 }
@@ -440,7 +478,7 @@ tnc_status tnc_plan_set_grouping(tnc_plan plan, int32_t enable) {
   if (!plan) fail(TNC_E_ARG, "plan is NULL");
   Plan& p = *plan->p;
   Ctx& c = *p.net->ctx;
-  if (c.server) fail(TNC_E_BUSY, "the context is serving: plans cannot change");
+  refuse_while_serving(c, "changing the execution order");
   const int g = enable ? 1 : 0;
   if (g == p.grouping) return TNC_OK;
   if (!c.host_only) {
@@ -448,11 +486,7 @@ tnc_status tnc_plan_set_grouping(tnc_plan plan, int32_t enable) {
     check_hip(hipStreamSynchronize(c.stream), "sync before re-planning");
     drain_profile(p);
   }
-  {
-    std::lock_guard<std::mutex> lk(p.graph_mu);
-    for (auto& e : p.graphs) (void)hipGraphExecDestroy(e.second);
-    p.graphs.clear();
-  }
+  p.drop_graphs();
   p.grouping = g;
   choose_chunking(p, c.arena_bytes);
   TNC_CATCH
@@ -462,6 +496,7 @@ tnc_status tnc_plan_set_profile(tnc_plan plan, int32_t enable) {
   TNC_TRY
   if (!plan) fail(TNC_E_ARG, "plan is NULL");
   Plan& p = *plan->p;
+  refuse_while_serving(*p.net->ctx, "switching profiling");
   if (!p.net->ctx->host_only) drain_profile(p);
   p.profile = enable ? 1 : 0;
   p.timers.assign(p.pairs.size() + 3, StepTimer{});
@@ -497,8 +532,8 @@ tnc_status tnc_contract(tnc_plan plan, int64_t first_slice, int64_t n_slices, do
   if (!plan || !out_c128) fail(TNC_E_ARG, "plan/out is NULL");
   Plan& p = *plan->p;
   Ctx& c = *p.net->ctx;
+  refuse_while_serving(c, "a direct contraction (submit a request instead)");
   set_device(c);
-  if (c.server) fail(TNC_E_BUSY, "the context is serving: submit requests instead");
   check_range(p, first_slice, n_slices);
   const ChunkPlan& c0 = *p.chunks[0];
   RunArgs a;
@@ -513,10 +548,10 @@ tnc_status tnc_contract(tnc_plan plan, int64_t first_slice, int64_t n_slices, do
   // the result comes back through the plan's pinned staging buffer
   const size_t res_bytes = static_cast<size_t>(c0.R) * 16;
   if (p.host_res_bytes < res_bytes) {
-    if (p.host_res) (void)hipHostFree(p.host_res);
+    pinned_free(p.host_res);
     p.host_res = nullptr;
     p.host_res_bytes = 0;
-    check_hip(hipHostMalloc(&p.host_res, res_bytes, hipHostMallocDefault), "pinned result buffer");
+    p.host_res = pinned_alloc(res_bytes, "pinned result buffer");
     p.host_res_bytes = res_bytes;
   }
   check_hip(hipMemcpyAsync(p.host_res, a.acc, res_bytes, hipMemcpyDeviceToHost, c.stream), "result copy");
@@ -540,8 +575,8 @@ tnc_status tnc_contract_async(tnc_plan plan, int64_t first_slice, int64_t n_slic
   if (out_type != TNC_OUT_C64 && out_type != TNC_OUT_C128) fail(TNC_E_ARG, "unknown output type");
   Plan& p = *plan->p;
   Ctx& c = *p.net->ctx;
+  refuse_while_serving(c, "a direct contraction (submit a request instead)");
   set_device(c);
-  if (c.server) fail(TNC_E_BUSY, "the context is serving: submit requests instead");
   check_range(p, first_slice, n_slices);
   const ChunkPlan& c0 = *p.chunks[0];
   if (!c0.result_perm.empty()) fail(TNC_E_UNSUPPORTED, "device results need batch labels leading the open order");

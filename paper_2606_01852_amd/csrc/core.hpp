@@ -32,6 +32,20 @@ void g_error_clear();
 void g_error_set(const std::string& m);
 const char* g_error_get();
 
+// Process-wide lock around the HIP runtime calls that capture, allocate or
+// free: graph capture and instantiation, graph destruction, device and
+// pinned host allocations and frees, stream creation and destruction.
+// Server workers of every context capture graphs and grow staging buffers
+// from their own threads; with this lock no allocation or free (some of
+// which synchronise the device) runs while another thread is between the
+// begin and the end of a capture, and no two captures overlap, so nothing
+// depends on how the runtime handles such overlaps.  Recursive: a holder
+// may allocate.
+std::recursive_mutex& runtime_mu();
+// Pinned host memory (hipHostMalloc / hipHostFree) under runtime_mu().
+void* pinned_alloc(size_t bytes, const char* what);
+void pinned_free(void* p);
+
 // Device allocation owned by the library.
 struct DeviceBuf {
   void* ptr = nullptr;
@@ -208,8 +222,10 @@ struct GraphKey {
   const void* out;
   const void* bases;
   bool overwrite;
+  int variant;  // the context's forced GEMM tile variant when captured (-1: the plan's)
   bool operator<(const GraphKey& o) const {
     if (j != o.j) return j < o.j;
+    if (variant != o.variant) return variant < o.variant;
     if (overwrite != o.overwrite) return overwrite < o.overwrite;
     if (arena != o.arena) return arena < o.arena;
     if (acc != o.acc) return acc < o.acc;
@@ -246,7 +262,14 @@ struct Plan {
   hipStream_t capture_stream = nullptr;
   ~Plan();
   ChunkPlan& chunk(int j);
+  // Destroy every captured graph (after the context's stream is drained):
+  // the chunk plans or their tile variants changed.
+  void drop_graphs();
 };
+
+// TNC_E_BUSY while the context serves: plans, networks and launch settings
+// that the server's workers read are not changed under them.
+void refuse_while_serving(const Ctx& c, const char* what);
 
 // planner.cpp
 void validate_net(Net& net);

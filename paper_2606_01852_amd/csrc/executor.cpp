@@ -315,11 +315,13 @@ void enqueue_chunk(Plan& plan, ChunkPlan& cp, const RunArgs& a, const int64_t* b
 constexpr size_t kMaxGraphsPerPlan = 64;
 
 hipGraphExec_t chunk_graph(Plan& plan, ChunkPlan& cp, const RunArgs& a, const int64_t* cur_bases, bool overwrite) {
-  const GraphKey key{cp.j, a.arena, a.acc, a.direct_out, cur_bases, overwrite};
+  const GraphKey key{cp.j, a.arena, a.acc, a.direct_out, cur_bases, overwrite, plan.net->ctx->gemm_variant};
   std::lock_guard<std::mutex> g(plan.graph_mu);
   auto it = plan.graphs.find(key);
   if (it != plan.graphs.end()) return it->second;
   if (plan.graphs.size() >= kMaxGraphsPerPlan) return nullptr;
+  // capture and instantiation run alone in the process (runtime_mu)
+  std::lock_guard<std::recursive_mutex> rt(runtime_mu());
   if (!plan.capture_stream) check_hip(hipStreamCreate(&plan.capture_stream), "hipStreamCreate");
   hipGraph_t graph = nullptr;
   check_hip(hipStreamBeginCapture(plan.capture_stream, hipStreamCaptureModeThreadLocal), "begin capture");
@@ -457,9 +459,22 @@ Plan::~Plan() {
     (void)hipEventDestroy(e.first.first);
     (void)hipEventDestroy(e.first.second);
   }
+  std::lock_guard<std::recursive_mutex> rt(runtime_mu());
   for (auto& g : graphs) (void)hipGraphExecDestroy(g.second);
   if (capture_stream) (void)hipStreamDestroy(capture_stream);
-  if (host_res) (void)hipHostFree(host_res);
+  pinned_free(host_res);
+  chunks.clear();  // device tables and leaf caches, freed under the lock
+  acc.reset();
+  norm.reset();
+}
+
+void Plan::drop_graphs() {
+  const Ctx& c = *net->ctx;
+  if (!c.host_only) check_hip(hipStreamSynchronize(c.stream), "sync before dropping graphs");
+  std::lock_guard<std::mutex> lk(graph_mu);
+  std::lock_guard<std::recursive_mutex> rt(runtime_mu());
+  for (auto& e : graphs) (void)hipGraphExecDestroy(e.second);
+  graphs.clear();
 }
 
 void drain_profile(Plan& plan) {

@@ -21,6 +21,12 @@
 // one job, whose rows are written into the batch-labelled leaves before the
 // plan runs once, so the same-shape steps of those requests share each
 // launch.  A batcher runs one job at a time (its leaves hold one batch).
+//
+// On a host-only context the server admits and queues exactly as it would
+// on a device (admission by planned arena bytes, the heavy lane, batcher
+// tokens) but executes nothing: every request completes with
+// TNC_E_UNSUPPORTED.  That lets the queueing code run, with its threads,
+// where there is no GPU.
 #include <chrono>
 #include <condition_variable>
 #include <cstring>
@@ -150,19 +156,26 @@ struct Server {
     }
     cv_work.notify_all();
     for (auto& t : workers) t.join();
-    for (hipStream_t s : streams) (void)hipStreamDestroy(s);
-    for (void* p : pinned)
-      if (p) (void)hipHostFree(p);
-    for (void* p : pinned_in)
-      if (p) (void)hipHostFree(p);
+    {
+      std::lock_guard<std::recursive_mutex> rt(runtime_mu());
+      for (hipStream_t s : streams)
+        if (s) (void)hipStreamDestroy(s);
+    }
+    for (void* p : pinned) pinned_free(p);
+    for (void* p : pinned_in) pinned_free(p);
   }
 
   void start() {
-    (void)hipSetDevice(ctx.device);
-    for (int i = 0; i < max_inflight; ++i) {
-      hipStream_t s = nullptr;
-      check_hip(hipStreamCreate(&s), "hipStreamCreate");
-      streams.push_back(s);
+    if (!ctx.host_only) {
+      (void)hipSetDevice(ctx.device);
+      std::lock_guard<std::recursive_mutex> rt(runtime_mu());
+      for (int i = 0; i < max_inflight; ++i) {
+        hipStream_t s = nullptr;
+        check_hip(hipStreamCreate(&s), "hipStreamCreate");
+        streams.push_back(s);
+      }
+    } else {
+      streams.assign(max_inflight, nullptr);
     }
     pinned.assign(max_inflight, nullptr);
     pinned_bytes.assign(max_inflight, 0);
@@ -172,7 +185,7 @@ struct Server {
   }
 
   void loop(int slot) {
-    (void)hipSetDevice(ctx.device);
+    if (!ctx.host_only) (void)hipSetDevice(ctx.device);
     hipStream_t stream = streams[slot];
     for (;;) {
       std::vector<std::shared_ptr<Request>> job;  // one request, or rows of one batcher
@@ -258,17 +271,20 @@ struct Server {
     b->queued = true;
   }
 
-  // Grow a slot's pinned staging buffer to `bytes`.
+  // Grow a slot's pinned staging buffer to `bytes` (only this slot's worker
+  // uses it, after its previous job has synchronised).
   static void* staging(std::vector<void*>& bufs, std::vector<size_t>& sizes, int slot, size_t bytes) {
     if (sizes[slot] < bytes) {
-      if (bufs[slot]) (void)hipHostFree(bufs[slot]);
+      pinned_free(bufs[slot]);
       bufs[slot] = nullptr;
       sizes[slot] = 0;
-      check_hip(hipHostMalloc(&bufs[slot], bytes, hipHostMallocDefault), "pinned staging buffer");
+      bufs[slot] = pinned_alloc(bytes, "pinned staging buffer");
       sizes[slot] = bytes;
     }
     return bufs[slot];
   }
+
+  static constexpr const char* kHostOnly = "host-only context: the request was admitted but nothing runs";
 
   // Run `plan` over all its slices in the request's arena interval; the FP64
   // result lands in the slot's pinned buffer (synchronous on `stream`).
@@ -295,6 +311,13 @@ struct Server {
   // order, the plan runs once, and request j gets row j of the result.
   void execute_rows(std::vector<std::shared_ptr<Request>>& job, int slot, hipStream_t stream) {
     Request& r0 = *job[0];
+    if (ctx.host_only) {
+      for (auto& q : job) {
+        q->status = TNC_E_UNSUPPORTED;
+        q->err = kHostOnly;
+      }
+      return;
+    }
     try {
       Batcher& b = *r0.batcher;
       Plan& p = *b.plan;
@@ -338,6 +361,11 @@ struct Server {
   }
 
   void execute(Request& r, int slot, hipStream_t stream) {
+    if (ctx.host_only) {
+      r.status = TNC_E_UNSUPPORTED;
+      r.err = kHostOnly;
+      return;
+    }
     try {
       Plan& p = *r.plan;
       const ChunkPlan& c0 = *p.chunks[0];
@@ -380,8 +408,11 @@ tnc_status tnc_serve_start(tnc_ctx ctx, int32_t max_inflight, int32_t queue_cap)
   TNC_TRY
     if (!ctx) fail(TNC_E_ARG, "ctx is NULL");
     Ctx& c = *ctx->c;
-    set_device(c);
-    if (!c.arena || !c.arena_bytes) fail(TNC_E_ARG, "serving needs an arena");
+    if (!c.host_only) {
+      set_device(c);
+      if (!c.arena) fail(TNC_E_ARG, "serving needs an arena");
+    }
+    if (!c.arena_bytes) fail(TNC_E_ARG, "serving needs an arena size");
     if (max_inflight < 1 || max_inflight > 64 || queue_cap < 1) fail(TNC_E_ARG, "bad serving limits");
     if (c.server) fail(TNC_E_BUSY, "server already running");
     c.server = make_server(c, max_inflight, queue_cap);
@@ -481,11 +512,7 @@ tnc_status tnc_batcher_create(tnc_plan plan, int32_t batch_label, int32_t n_leav
       check_hip(hipStreamSynchronize(c.stream), "sync before re-planning");
       drain_profile(p);
     }
-    {
-      std::lock_guard<std::mutex> lk(p.graph_mu);
-      for (auto& e : p.graphs) (void)hipGraphExecDestroy(e.second);
-      p.graphs.clear();
-    }
+    p.drop_graphs();
     p.volatile_leaf.assign(n.n_tensors, 0);
     for (int i = 0; i < n_leaves; ++i) p.volatile_leaf[leaves[i]] = 1;
     choose_chunking(p, c.arena_bytes);

@@ -16,7 +16,10 @@
 // networks, paths, slices and kernel arguments runs first.  Prints
 // "ok <file>" per file.  With --threads N first, N threads each plan every
 // network on a context of their own at the same time (for ThreadSanitizer:
-// contexts share no mutable state).
+// contexts share no mutable state).  Both modes end with a serving run on a
+// host-only context ("ok serving"): its server admits and queues requests
+// and batcher rows from several submitting threads with its own worker
+// threads, and completes each without executing it.
 #include <atomic>
 #include <cstdio>
 #include <cstdlib>
@@ -261,10 +264,158 @@ void malformed(tnc_ctx ctx) {
            "gemm precision", F);
     expect(tnc_batched_cgemm(ctx, 1, 4, 4, 4, dummy, 0, dummy, 0, dummy, TNC_PREC_C64, -3) == TNC_E_ARG,
            "gemm form", F);
-    expect(tnc_serve_start(ctx, 4, 16) == TNC_E_UNSUPPORTED, "serve on host", F);
+    tnc_ctx sized = nullptr;
+    expect(tnc_ctx_create(-1, nullptr, 0, nullptr, &sized) == TNC_OK, "host context without arena", F);
+    expect(tnc_serve_start(sized, 4, 16) == TNC_E_ARG, "serve without an arena size", F);
+    tnc_ctx_destroy(sized);
+    expect(tnc_serve_start(ctx, 0, 16) == TNC_E_ARG, "serve with no slots", F);
   }
   expect(tnc_plan_destroy(nullptr) == TNC_OK, "destroy null plan", F);
   expect(tnc_net_destroy(nullptr) == TNC_OK, "destroy null net", F);
+}
+
+int64_t numel_of(const NetFile& f, int t) {
+  int64_t pos = 0;
+  for (int u = 0; u < t; ++u) pos += f.ranks[u];
+  int64_t n = 1;
+  for (int q = 0; q < f.ranks[t]; ++q) n *= f.extents[f.labels[pos + q]];
+  return n;
+}
+
+// Serving on a host-only context: `submitters` threads submit whole-plan
+// requests and batcher rows, poll and wait, while the server's worker
+// threads admit them by planned arena bytes; every request must complete
+// with TNC_E_UNSUPPORTED.  Calls that would change a plan or a network
+// under the workers must be refused while it serves.  Two rounds: the
+// second with the heavy lane on and a batcher destroyed while its rows may
+// still be queued.
+void serve_exercise(const std::vector<NetFile>& files, int submitters) {
+  const char* F = "serving";
+  tnc_ctx ctx = nullptr;
+  if (tnc_ctx_create(-1, nullptr, size_t{64} << 30, nullptr, &ctx) != TNC_OK) {
+    expect(false, "host context", F);
+    return;
+  }
+  struct Entry {
+    tnc_net net = nullptr;
+    tnc_plan plan = nullptr;
+    tnc_batcher batcher = nullptr;
+    int64_t n_result = 1, n_slices = 1, row_result = 1;
+    std::vector<std::vector<double>> rows;  // per listed leaf: one row of complex128 values
+  };
+  std::vector<Entry> es;
+  for (const NetFile& f : files) {
+    Entry e;
+    if (tnc_net_create(ctx, f.n_tensors, f.ranks.data(), f.labels.data(), static_cast<int32_t>(f.extents.size()),
+                       f.extents.data(), static_cast<int32_t>(f.open.size()), f.open.data(), nullptr, TNC_IN_C64,
+                       &e.net) != TNC_OK)
+      continue;
+    const int32_t n_steps = static_cast<int32_t>(f.pairs.size() / 2);
+    if (tnc_plan_create(e.net, n_steps, f.pairs.data(), static_cast<int32_t>(f.sliced.size()), f.sliced.data(),
+                        TNC_PREC_C64, TNC_GEMM_4M, &e.plan) != TNC_OK) {
+      tnc_net_destroy(e.net);
+      continue;  // too large for the arena
+    }
+    tnc_plan_info info;
+    expect(tnc_plan_get_info(e.plan, &info) == TNC_OK, "serving info", F);
+    e.n_result = info.n_result;
+    e.n_slices = info.n_slices;
+    if (e.n_result > (1 << 16)) {  // host outputs of every request stay small
+      tnc_plan_destroy(e.plan);
+      tnc_net_destroy(e.net);
+      continue;
+    }
+    if (f.batch_label >= 0) {
+      expect(tnc_batcher_create(e.plan, f.batch_label, static_cast<int32_t>(f.batch_leaves.size()),
+                                f.batch_leaves.data(), &e.batcher) == TNC_OK,
+             "serving batcher", F);
+      const int64_t B = f.extents[f.batch_label];
+      e.row_result = e.n_result / B;
+      for (int t : f.batch_leaves) e.rows.emplace_back(static_cast<size_t>(2 * numel_of(f, t) / B), 0.5);
+    }
+    es.push_back(std::move(e));
+  }
+  expect(!es.empty(), "networks to serve", F);
+  for (int round = 0; round < 2 && !es.empty(); ++round) {
+    expect(tnc_serve_start(ctx, 6, 1 << 14) == TNC_OK, "serve_start", F);
+    expect(tnc_serve_start(ctx, 6, 16) == TNC_E_BUSY, "second server", F);
+    expect(tnc_serve_set_heavy(ctx, round ? 1e6 : 0.0, 2) == TNC_OK, "heavy lane", F);
+    tnc_plan p0 = es[0].plan;
+    int32_t rank = 0;
+    double out[2] = {0, 0};
+    expect(tnc_plan_set_max_chunk(p0, 4) == TNC_E_BUSY, "set_max_chunk while serving", F);
+    expect(tnc_plan_set_graph(p0, 1) == TNC_E_BUSY, "set_graph while serving", F);
+    expect(tnc_plan_set_grouping(p0, 0) == TNC_E_BUSY, "set_grouping while serving", F);
+    expect(tnc_plan_set_profile(p0, 1) == TNC_E_BUSY, "set_profile while serving", F);
+    expect(tnc_plan_autotune(p0) == TNC_E_BUSY, "autotune while serving", F);
+    expect(tnc_ctx_set_gemm_variant(ctx, 1) == TNC_E_BUSY, "forced variant while serving", F);
+    expect(tnc_contract(p0, 0, 1, out) == TNC_E_BUSY, "contract while serving", F);
+    expect(tnc_contract_async(p0, 0, 1, out, TNC_OUT_C128) == TNC_E_BUSY, "contract_async while serving", F);
+    expect(tnc_net_set_tensor(es[0].net, 0, out, TNC_IN_C128) == TNC_E_BUSY, "set_tensor while serving", F);
+    expect(tnc_net_set_tensor_device(es[0].net, 0, out) == TNC_E_BUSY, "set_tensor_device while serving", F);
+    expect(tnc_plan_get_order(p0, 0, nullptr, 0, &rank) == TNC_OK, "queries stay allowed", F);
+    std::vector<std::thread> pool;
+    for (int t = 0; t < submitters; ++t)
+      pool.emplace_back([&, t] {
+        std::vector<std::pair<tnc_req, std::vector<double>>> mine;
+        for (int i = 0; i < 48; ++i) {
+          const Entry& e = es[(t + i) % es.size()];
+          std::vector<double> res;
+          tnc_req id = 0;
+          tnc_status st;
+          if (!e.rows.empty()) {
+            res.assign(static_cast<size_t>(2 * e.row_result), 0.0);
+            std::vector<const void*> ptrs;
+            for (const auto& r : e.rows) ptrs.push_back(r.data());
+            st = tnc_submit_row(ctx, e.batcher, ptrs.data(), TNC_IN_C128, res.data(), &id);
+          } else {
+            res.assign(static_cast<size_t>(2 * e.n_result), 0.0);
+            const int64_t first = i % e.n_slices;
+            st = tnc_submit(ctx, e.plan, first, 1 + (e.n_slices - first - 1) * (i % 2), res.data(), &id);
+          }
+          expect(st == TNC_OK, "submit", F);
+          if (st != TNC_OK) continue;
+          if (i % 3 == 0) {
+            int32_t d = 0;
+            double lat = 0;
+            const tnc_status ps = tnc_poll(ctx, id, &d, &lat);
+            expect(ps == TNC_OK || (d == 1 && ps == TNC_E_UNSUPPORTED), "poll", F);
+          }
+          mine.emplace_back(id, std::move(res));
+        }
+        for (auto& m : mine) {
+          double lat = -1;
+          expect(tnc_wait(ctx, m.first, &lat) == TNC_E_UNSUPPORTED && lat >= 0, "request completes unexecuted", F);
+          for (double v : m.second) expect(v == 0.0, "output untouched", F);
+        }
+        int32_t d = 0;
+        if (!mine.empty()) expect(tnc_poll(ctx, mine[0].first, &d, nullptr) == TNC_E_ARG, "collected id unknown", F);
+      });
+    for (auto& th : pool) th.join();
+    if (round == 1)
+      for (Entry& e : es)
+        if (e.batcher) {
+          // rows queued now keep the batcher alive until they are done
+          std::vector<const void*> ptrs;
+          for (const auto& r : e.rows) ptrs.push_back(r.data());
+          std::vector<std::vector<double>> res(8, std::vector<double>(static_cast<size_t>(2 * e.row_result), 0.0));
+          std::vector<tnc_req> ids(8, 0);
+          for (int i = 0; i < 8; ++i)
+            expect(tnc_submit_row(ctx, e.batcher, ptrs.data(), TNC_IN_C128, res[i].data(), &ids[i]) == TNC_OK,
+                   "late row", F);
+          expect(tnc_batcher_destroy(e.batcher) == TNC_OK, "batcher destroyed while serving", F);
+          e.batcher = nullptr;
+          for (tnc_req id : ids) expect(tnc_wait(ctx, id, nullptr) == TNC_E_UNSUPPORTED, "late row completes", F);
+        }
+    expect(tnc_serve_stop(ctx) == TNC_OK, "serve_stop", F);
+    expect(tnc_plan_set_max_chunk(p0, -1) == TNC_OK, "set_max_chunk after serving", F);
+  }
+  for (Entry& e : es) {
+    if (e.batcher) tnc_batcher_destroy(e.batcher);
+    tnc_plan_destroy(e.plan);
+    tnc_net_destroy(e.net);
+  }
+  tnc_ctx_destroy(ctx);
 }
 
 }  // namespace
@@ -292,6 +443,8 @@ int threaded(int n_threads, int n_files, char** files) {
       tnc_ctx_destroy(ctx);
     });
   for (auto& th : pool) th.join();
+  serve_exercise(nets, n_threads);
+  std::printf("ok serving\n");
   return fails ? 1 : 0;
 }
 
@@ -304,6 +457,7 @@ int main(int argc, char** argv) {
   }
   malformed(ctx);
   std::printf("ok malformed\n");
+  std::vector<NetFile> nets;
   for (int i = 1; i < argc; ++i) {
     NetFile f;
     if (!read_net(argv[i], f)) {
@@ -312,7 +466,10 @@ int main(int argc, char** argv) {
     }
     exercise(ctx, f, argv[i]);
     std::printf("ok %s\n", argv[i]);
+    nets.push_back(std::move(f));
   }
   tnc_ctx_destroy(ctx);
+  serve_exercise(nets, 4);
+  std::printf("ok serving\n");
   return fails ? 1 : 0;
 }

@@ -240,10 +240,43 @@ def test_grouping_keeps_the_plan_shape(hctx):
         tnc.tnc_plan_set_grouping(0, 1)
 
 
-def test_serving_needs_a_device_arena(hctx):
+def test_host_only_server_queues_without_running_and_refuses_changes():
+    """A host-only context with an arena size serves as a dry run: requests
+    are admitted and complete with TNC_E_UNSUPPORTED, outputs untouched.
+    While it serves, every call that would change what the workers read is
+    refused with TNC_E_BUSY; after tnc_serve_stop they work again."""
+    bare = tnc.Context(-1)
     with pytest.raises(tnc.TncError) as e:
-        tnc.tnc_serve_start(hctx.handle, 2, 8)
-    assert e.value.status in (tnc.E_ARG, tnc.E_UNSUPPORTED)
+        tnc.tnc_serve_start(bare.handle, 2, 8)       # no arena size to admit against
+    assert e.value.status == tnc.E_ARG
+    ctx = tnc.Context(-1, arena_bytes=1 << 30)
+    net, path = configs.circuit12()
+    tn = tnc.Network(ctx, net.labels, net.extents, net.open)
+    plan = tnc.Plan(tn, path.pairs)
+    tnc.tnc_serve_start(ctx.handle, 3, 64)
+    refused = [lambda: tnc.tnc_plan_set_max_chunk(plan.handle, 1),
+               lambda: tnc.tnc_plan_autotune(plan.handle),
+               lambda: tnc.tnc_plan_set_graph(plan.handle, True),
+               lambda: tnc.tnc_plan_set_grouping(plan.handle, False),
+               lambda: tnc.tnc_plan_set_profile(plan.handle, True),
+               lambda: tnc.tnc_ctx_set_gemm_variant(ctx.handle, 2),
+               lambda: tnc.tnc_net_set_tensor(tn.handle, 0, net.c64().leaves[0]),
+               lambda: tnc.tnc_net_set_tensor_device(tn.handle, 0, 1 << 20),
+               lambda: tnc.tnc_contract(plan.handle, 0, 1, 1)]
+    for call in refused:
+        with pytest.raises(tnc.TncError) as e:
+            call()
+        assert e.value.status == tnc.E_BUSY
+    outs = [np.zeros(1, dtype=np.complex128) for _ in range(16)]
+    ids = [tnc.tnc_submit(ctx.handle, plan.handle, 0, 1, o) for o in outs]
+    for rid in ids:
+        with pytest.raises(tnc.TncError) as e:
+            tnc.tnc_wait(ctx.handle, rid)
+        assert e.value.status == tnc.E_UNSUPPORTED
+    assert all(o[0] == 0 for o in outs)
+    tnc.tnc_serve_stop(ctx.handle)
+    tnc.tnc_plan_set_max_chunk(plan.handle, 1)       # allowed again
+    tnc.tnc_plan_set_grouping(plan.handle, False)
 
 
 def test_handles_can_be_destroyed_in_any_order():

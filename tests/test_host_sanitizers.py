@@ -9,7 +9,12 @@ chunk size, every step query, distribution over 2, 4 and 8 devices) and feeds
 the ABI malformed inputs.  Any out-of-bounds access, use after free, leak or
 undefined operation ends the driver with a report.  The ThreadSanitizer build
 runs the same planning in four threads, each on a context of its own
-(independent contexts share no mutable state).  No GPU is used.
+(independent contexts share no mutable state).  Both builds end with a
+serving run on a host-only context: four threads submit requests and batcher
+rows, poll and wait while the server's six worker threads admit and complete
+them (unexecuted, as a host-only server does), a batcher is destroyed with
+rows queued, and every call that would change a plan under the workers is
+refused.  No GPU is used.
 """
 import concurrent.futures as cf
 import os
@@ -125,7 +130,7 @@ def test_host_code_is_clean_under_asan_and_ubsan(driver, tmp_path):
     report = r.stdout[-4000:] + r.stderr[-8000:]
     assert r.returncode == 0, report
     assert "runtime error" not in r.stderr, report
-    assert r.stdout.count("ok ") == len(files) + 1, report
+    assert r.stdout.count("ok ") == len(files) + 2, report
 
 
 def test_concurrent_contexts_are_race_free_under_tsan(tmp_path_factory, tmp_path):
@@ -137,4 +142,4 @@ def test_concurrent_contexts_are_race_free_under_tsan(tmp_path_factory, tmp_path
     report = r.stdout[-2000:] + r.stderr[-8000:]
     assert r.returncode == 0, report
     assert "ThreadSanitizer" not in r.stderr, report
-    assert r.stdout.count("ok ") == 4 * len(files), report
+    assert r.stdout.count("ok ") == 4 * len(files) + 1, report
