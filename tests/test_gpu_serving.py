@@ -208,6 +208,100 @@ def test_serving_pool_requests_match_the_state_vector():
     ctx.close()
 
 
+def _tree_depth(n_leaves, pairs):
+    depth = [0] * n_leaves
+    for a, b in pairs:
+        depth.append(1 + max(depth[int(a)], depth[int(b)]))
+    return depth[-1]
+
+
+def test_serving_pool_requests_above_20_qubits():
+    """Requests of the serving benchmark's pool beyond 20 qubits, served
+    together in one mix:
+      * a 24-qubit request (4 slices, complex64) against the brute-force
+        state vector (1e-5);
+      * two 25-qubit requests (64 slices; complex64 and split-bf16x3), whole
+        sums against the FP64 tensor-network oracle;
+      * a seeded sample of four pool entries of 28..48 qubits, three seeded
+        slices each served as single-slice requests, against the FP64
+        oracle's contraction of the same slice.  Per-slice amplitudes of
+        random circuits are Porter-Thomas distributed, so each error is
+        bounded relative to the root-mean-square of the request's sampled
+        slices (the circuit40 reading); split-bf16x3 requests use their
+        bound max(1e-5, 4 * 2^-16 * tree depth)."""
+    from oracle import statevector as osv
+    from workloads import configs
+    from workloads.paths import path_cost
+    arena = torch.empty(16 << 30, dtype=torch.uint8, device="cuda")
+    ctx = tnc.Context(0, arena_bytes=arena.numel(), arena_ptr=arena.data_ptr())
+    rng = np.random.Generator(np.random.PCG64(5005))
+    big = [i for i in range(64) if np.prod(configs.serve_request_spec(i)[:2]) > 26
+           and configs.serve_request_spec(i)[3] >= 3]
+    sampled = []
+    for i in rng.permutation(big):
+        circ, net, path, prec = configs.serve_request_circuit(int(i))
+        _, ops = path_cost(net, path.pairs, path.sliced)
+        if ops <= 2 ** 28:                          # the oracle contracts a slice in well under a second
+            sampled.append((int(i), circ, net, path, prec))
+        if len(sampled) == 4:
+            break
+    assert len(sampled) == 4
+    jobs = []       # (label, plan, tn, first, count, ref, tol, out)
+
+    def add(label, net, path, prec, first, count, ref, tol):
+        tn = tnc.Network(ctx, net.labels, net.extents, net.open, net.c64().leaves)
+        plan = tnc.Plan(tn, path.pairs, path.sliced, tnc.PREC_BF16X3 if prec else tnc.PREC_C64)
+        jobs.append((label, plan, tn, first, count, ref, tol, np.zeros(1, dtype=np.complex128)))
+
+    # state vector: entry 41 (6 x 4 grid, depth 8, 4 slices, complex64)
+    circ, net, path, prec = configs.serve_request_circuit(41)
+    assert circ.n_qubits == 24 and prec == 0
+    gates = [(qs, u.astype(np.complex64).astype(np.complex128)) for qs, u in circ.gates]
+    print("entry 41: state vector of 24 qubits", flush=True)
+    sv = osv.amplitude(circ.n_qubits, gates, circ.bitstring)
+    add("entry 41 vs state vector", net, path, 0, 0, int(np.prod([net.extents[l] for l in path.sliced])),
+        [sv], 1e-5)
+    # whole 25-qubit requests against the FP64 tensor-network oracle
+    for i in (27, 29):
+        circ, net, path, prec = configs.serve_request_circuit(i)
+        assert circ.n_qubits == 25
+        print(f"entry {i}: FP64 oracle over all slices", flush=True)
+        ref = complex(oc.contract(net, path))
+        tol = max(1e-5, 4 * 2.0 ** -16 * _tree_depth(net.n_leaves, path.pairs)) if prec else 1e-5
+        add(f"entry {i} (prec {prec}) vs oracle", net, path, prec, 0,
+            int(np.prod([net.extents[l] for l in path.sliced])), [ref], tol)
+    # sampled slices of larger requests
+    for i, circ, net, path, prec in sampled:
+        n_sl = int(np.prod([net.extents[l] for l in path.sliced]))
+        srng = np.random.Generator(np.random.PCG64(6000 + i))
+        for s in (int(x) for x in srng.choice(n_sl, 3, replace=False)):
+            print(f"entry {i} ({circ.n_qubits} qubits): oracle slice {s} of {n_sl}", flush=True)
+            ref = complex(oc.contract(net, path, slices=[s]))
+            tol = max(1e-5, 4 * 2.0 ** -16 * _tree_depth(net.n_leaves, path.pairs)) if prec else 1e-5
+            add(f"entry {i} slice {s} (prec {prec})", net, path, prec, s, 1, [ref], tol)
+    tnc.tnc_serve_start(ctx.handle, 8, 256)
+    ids = [tnc.tnc_submit(ctx.handle, j[1].handle, j[3], j[4], j[7]) for j in jobs]
+    for rid in ids:
+        tnc.tnc_wait(ctx.handle, rid)
+    tnc.tnc_serve_stop(ctx.handle)
+    # per request: rms of its sampled references (one value for whole requests)
+    groups = {}
+    for j in jobs:
+        groups.setdefault(j[0].split(" slice")[0], []).append(j)
+    for key, js in groups.items():
+        refs = np.array([j[5][0] for j in js])
+        rms = float(np.sqrt(np.mean(np.abs(refs) ** 2)))
+        for label, plan, tn, first, count, ref, tol, out in js:
+            err = abs(complex(out[0]) - ref[0])
+            print(f"{label}: |err| / rms {err / rms:.2e}, relative {err / abs(ref[0]):.2e} (tol {tol:.1e})",
+                  flush=True)
+            assert err <= tol * rms, label
+    for j in jobs:
+        j[1].close()
+        j[2].close()
+    ctx.close()
+
+
 def test_served_graph_plans_match_eager(served):
     """Plans that replay their chunks as captured hipGraphs give, served
     concurrently, bitwise the eager result of the same plan alone."""
