@@ -289,6 +289,22 @@ tnc_status tnc_plan_result_norm2(tnc_plan plan, double* out);
  * context or above 64 modes. */
 tnc_status tnc_permute(tnc_ctx ctx, const void* in, void* out, int32_t rank,
                        const int64_t* extents, const int32_t* perm);
+/* The same permutation for callers that cannot allocate device memory
+ * (code under stream capture, tight serving loops, harnesses that forbid
+ * allocation): same arguments, checks and result as tnc_permute, but the
+ * permutation's index tables go to a fixed device-resident table area of
+ * 1 MiB per GPU that the library holds from its first context on that GPU
+ * until the process ends, instead of memory the library allocates.
+ * TNC_E_NOMEM if the tables need more than 1 MiB (decided on the host
+ * before any device work; the tables of a 2^30-element permutation take
+ * about 130 KiB).  Every call on one GPU shares that area and leaves its
+ * own tables in it: a call first waits for the context's stream (earlier
+ * calls on it have finished reading the area), copies its tables and waits
+ * for the copy, then launches.  Calls that overlap on one GPU from
+ * different streams or threads race on the area.  Small permutations that
+ * run as a plain gather use no tables and do not wait. */
+tnc_status tnc_permute_noalloc(tnc_ctx ctx, const void* in, void* out, int32_t rank,
+                               const int64_t* extents, const int32_t* perm);
 /* Batched complex GEMM with both operands K-contiguous:
  *   C[b, i, j] = sum_l A[b, i, l] * B[b, j, l]     (no conjugation)
  * A: h*m*k, B: h*n*k, C: h*m*n complex64 (device pointers, contiguous; a

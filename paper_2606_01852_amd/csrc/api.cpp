@@ -143,6 +143,11 @@ tnc_status tnc_ctx_create(int device, void* arena, size_t arena_bytes, void* str
       c.arena = static_cast<char*>(p);
       c.own_arena = true;
     }
+    // per-device address of the allocation-free permute tables, looked up
+    // once here with the device current; if the lookup fails, the error is
+    // cleared and tnc_permute_noalloc looks again and reports it
+    void* tables = nullptr;
+    if (static_table_area(device, &tables) != hipSuccess) (void)hipGetLastError();
     load_tune_cache(c);
     prepare_gemm_kernels();
     (void)hipGetLastError();  // best effort: launches retry lazily
@@ -619,10 +624,20 @@ tnc_status tnc_plan_result_norm2(tnc_plan plan, double* out) {
   TNC_CATCH
 }
 
-tnc_status tnc_permute(tnc_ctx ctx, const void* in, void* out, int32_t rank, const int64_t* extents,
-                       const int32_t* perm) {
-  TNC_TRY
-  if (!ctx || !in || !out || rank < 0 || (rank && (!extents || !perm))) fail(TNC_E_ARG, "bad arguments");
+}  // extern "C"
+
+namespace {
+
+// A checked permutation of a complex64 tensor: its gather-permute and, when
+// tiled, the index tables packed into one host blob (parts 256-byte
+// aligned, offsets in off[]).
+struct PermuteJob {
+  PermuteHost ph;
+  std::vector<uint8_t> blob;
+  size_t off[6] = {0, 0, 0, 0, 0, 0};
+};
+
+PermuteJob plan_permute(int32_t rank, const int64_t* extents, const int32_t* perm) {
   std::vector<int64_t> ist(rank);
   int64_t s = 1;
   for (int q = rank - 1; q >= 0; --q) {
@@ -640,47 +655,91 @@ tnc_status tnc_permute(tnc_ctx ctx, const void* in, void* out, int32_t rank, con
     ext[q] = extents[p];
     st[q] = ist[p];
   }
-  Ctx& c = *ctx->c;
-  set_device(c);
-  PermuteHost ph = build_permute(ext, st);
-  if (!ph.tiled) {
-    GatherDesc g = ph.plain;
-    g.in = static_cast<const float2*>(in);
-    g.out = static_cast<float2*>(out);
-    check_hip(launch_gather(g, c.stream), "gather launch");
-  } else {
-    std::vector<uint8_t> blob;
+  PermuteJob j;
+  j.ph = build_permute(ext, st);
+  if (j.ph.tiled) {
     auto put = [&](const void* src, size_t bytes) {
-      const size_t off = (blob.size() + 255) / 256 * 256;
-      blob.resize(off + bytes);
-      std::memcpy(blob.data() + off, src, bytes);
+      const size_t off = (j.blob.size() + 255) / 256 * 256;
+      j.blob.resize(off + bytes);
+      std::memcpy(j.blob.data() + off, src, bytes);
       return off;
     };
-    const size_t o1 = put(ph.tile_in.data(), ph.tile_in.size() * 4);
-    const size_t o2 = put(ph.tile_slot_r.data(), ph.tile_slot_r.size() * 4);
-    const size_t o3 = put(ph.tile_out.data(), ph.tile_out.size() * 4);
-    const size_t o4 = put(ph.tile_slot_w.data(), ph.tile_slot_w.size() * 4);
-    const size_t o5 = put(ph.lo_tab.data(), ph.lo_tab.size() * 8);
-    const size_t o6 = put(ph.hi_tab.data(), ph.hi_tab.size() * 8);
-    check_hip(hipStreamSynchronize(c.stream), "stream synchronize");
-    if (c.scratch.bytes < blob.size()) c.scratch.alloc(blob.size());
-    check_hip(hipMemcpy(c.scratch.ptr, blob.data(), blob.size(), hipMemcpyHostToDevice), "table upload");
-    const char* b = static_cast<const char*>(c.scratch.ptr);
-    PermuteDesc d{};
-    d.in = static_cast<const float2*>(in);
-    d.out = static_cast<float2*>(out);
-    d.tile_in = reinterpret_cast<const int32_t*>(b + o1);
-    d.tile_slot_r = reinterpret_cast<const int32_t*>(b + o2);
-    d.tile_out = reinterpret_cast<const int32_t*>(b + o3);
-    d.tile_slot_w = reinterpret_cast<const int32_t*>(b + o4);
-    d.lo_tab = reinterpret_cast<const int64_t*>(b + o5);
-    d.hi_tab = reinterpret_cast<const int64_t*>(b + o6);
-    d.n_tiles = ph.n_tiles;
-    d.L = ph.L;
-    d.T = ph.T;
-    d.slots = ph.slots;
-    check_hip(launch_permute(d, c.stream), "permute launch");
+    const PermuteHost& ph = j.ph;
+    j.off[0] = put(ph.tile_in.data(), ph.tile_in.size() * 4);
+    j.off[1] = put(ph.tile_slot_r.data(), ph.tile_slot_r.size() * 4);
+    j.off[2] = put(ph.tile_out.data(), ph.tile_out.size() * 4);
+    j.off[3] = put(ph.tile_slot_w.data(), ph.tile_slot_w.size() * 4);
+    j.off[4] = put(ph.lo_tab.data(), ph.lo_tab.size() * 8);
+    j.off[5] = put(ph.hi_tab.data(), ph.hi_tab.size() * 8);
   }
+  return j;
+}
+
+// Launch a planned permutation; `tables` is the device copy of j.blob.
+hipError_t launch_permute_job(const PermuteJob& j, const void* in, void* out, const char* tables, hipStream_t s) {
+  if (!j.ph.tiled) {
+    GatherDesc g = j.ph.plain;
+    g.in = static_cast<const float2*>(in);
+    g.out = static_cast<float2*>(out);
+    return launch_gather(g, s);
+  }
+  PermuteDesc d{};
+  d.in = static_cast<const float2*>(in);
+  d.out = static_cast<float2*>(out);
+  d.tile_in = reinterpret_cast<const int32_t*>(tables + j.off[0]);
+  d.tile_slot_r = reinterpret_cast<const int32_t*>(tables + j.off[1]);
+  d.tile_out = reinterpret_cast<const int32_t*>(tables + j.off[2]);
+  d.tile_slot_w = reinterpret_cast<const int32_t*>(tables + j.off[3]);
+  d.lo_tab = reinterpret_cast<const int64_t*>(tables + j.off[4]);
+  d.hi_tab = reinterpret_cast<const int64_t*>(tables + j.off[5]);
+  d.n_tiles = j.ph.n_tiles;
+  d.L = j.ph.L;
+  d.T = j.ph.T;
+  d.slots = j.ph.slots;
+  return launch_permute(d, s);
+}
+
+}  // namespace
+
+extern "C" {
+
+tnc_status tnc_permute(tnc_ctx ctx, const void* in, void* out, int32_t rank, const int64_t* extents,
+                       const int32_t* perm) {
+  TNC_TRY
+  if (!ctx || !in || !out || rank < 0 || (rank && (!extents || !perm))) fail(TNC_E_ARG, "bad arguments");
+  const PermuteJob j = plan_permute(rank, extents, perm);
+  Ctx& c = *ctx->c;
+  set_device(c);
+  if (j.ph.tiled) {
+    check_hip(hipStreamSynchronize(c.stream), "stream synchronize");
+    if (c.scratch.bytes < j.blob.size()) c.scratch.alloc(j.blob.size());
+    check_hip(hipMemcpy(c.scratch.ptr, j.blob.data(), j.blob.size(), hipMemcpyHostToDevice), "table upload");
+  }
+  check_hip(launch_permute_job(j, in, out, static_cast<const char*>(c.scratch.ptr), c.stream), "permute launch");
+  TNC_CATCH
+}
+
+tnc_status tnc_permute_noalloc(tnc_ctx ctx, const void* in, void* out, int32_t rank, const int64_t* extents,
+                               const int32_t* perm) {
+  TNC_TRY
+  if (!ctx || !in || !out || rank < 0 || (rank && (!extents || !perm))) fail(TNC_E_ARG, "bad arguments");
+  const PermuteJob j = plan_permute(rank, extents, perm);
+  if (j.blob.size() > kStaticPermuteTableBytes)
+    fail(TNC_E_NOMEM, "the permutation's index tables need " + std::to_string(j.blob.size()) +
+                          " bytes, above the fixed table area of " + std::to_string(kStaticPermuteTableBytes));
+  Ctx& c = *ctx->c;
+  set_device(c);
+  void* tables = nullptr;
+  if (j.ph.tiled) {
+    check_hip(static_table_area(c.device, &tables), "table area address");
+    // earlier launches on this stream may still read the shared tables: wait
+    // for them, copy the new tables, and wait for the copy (the host blob
+    // is pageable and goes away when this call returns)
+    check_hip(hipStreamSynchronize(c.stream), "stream synchronize");
+    check_hip(hipMemcpyAsync(tables, j.blob.data(), j.blob.size(), hipMemcpyHostToDevice, c.stream), "table upload");
+    check_hip(hipStreamSynchronize(c.stream), "table upload");
+  }
+  check_hip(launch_permute_job(j, in, out, static_cast<const char*>(tables), c.stream), "permute launch");
   TNC_CATCH
 }
 

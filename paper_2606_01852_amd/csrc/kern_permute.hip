@@ -8,9 +8,37 @@
 // the output's innermost modes innermost (contiguous runs), so both sides of
 // HBM traffic are coalesced.  All index arithmetic is precomputed on the
 // host into small tables; the kernel only adds offsets.
+#include <mutex>
+
 #include "kernels.hpp"
 
+// Table area of the permutes that allocate nothing: the index tables of
+// such a call are copied here instead of into memory the library allocates.
+// Each GPU holds its own copy of the array at its own address; host code
+// uses only the address looked up per device below, never this name (in
+// host code it does not denote device memory).
+static __device__ __align__(256) unsigned char scratch[tnc::kStaticPermuteTableBytes];
+
 namespace tnc {
+
+namespace {
+constexpr int kMaxDevices = 64;
+std::mutex g_table_mu;
+void* g_table_ptr[kMaxDevices] = {};
+}  // namespace
+
+hipError_t static_table_area(int device, void** out) {
+  if (device < 0 || device >= kMaxDevices) return hipErrorInvalidDevice;
+  std::lock_guard<std::mutex> g(g_table_mu);
+  if (!g_table_ptr[device]) {
+    void* p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return e;
+    g_table_ptr[device] = p;
+  }
+  *out = g_table_ptr[device];
+  return hipSuccess;
+}
 
 namespace {
 

@@ -135,6 +135,12 @@ hipError_t launch_group_gather(const GroupGather* table, const int64_t* prefix, 
                                const int64_t* bases, hipStream_t s);
 
 hipError_t launch_permute(const PermuteDesc& d, hipStream_t s);
+// Fixed device-resident table area for permutes of callers that cannot
+// allocate (tnc_permute_noalloc): kStaticPermuteTableBytes per GPU, shared
+// by every such call on that GPU.  static_table_area looks its address up
+// once per device (the device must be current) and returns it.
+constexpr size_t kStaticPermuteTableBytes = size_t{1} << 20;
+hipError_t static_table_area(int device, void** out);
 hipError_t launch_gather(const GatherDesc& d, hipStream_t s);
 // acc[i] += sum_s root[s * R + i] (complex64 in, complex128 out), pairwise
 // over s in a fixed tree; hs = number of s.  overwrite: acc[i] = the sum

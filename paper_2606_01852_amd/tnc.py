@@ -98,6 +98,7 @@ _SIGS = {
     "tnc_contract_async": (C.c_int, [_P, C.c_int64, C.c_int64, _P, C.c_int32]),
     "tnc_plan_result_norm2": (C.c_int, [_P, _DP]),
     "tnc_permute": (C.c_int, [_P, _P, _P, C.c_int32, _I64P, _I32P]),
+    "tnc_permute_noalloc": (C.c_int, [_P, _P, _P, C.c_int32, _I64P, _I32P]),
     "tnc_batched_cgemm": (C.c_int, [_P, C.c_int64, C.c_int64, C.c_int64, C.c_int64, _P, C.c_int64, _P,
                                     C.c_int64, _P, C.c_int32, C.c_int32]),
     "tnc_serve_start": (C.c_int, [_P, C.c_int32, C.c_int32]),
@@ -115,11 +116,20 @@ _lib: Optional[C.CDLL] = None
 
 
 def lib() -> C.CDLL:
-    """Load libtnc.so (raises if it has not been built)."""
+    """Load libtnc.so (raises if it has not been built).
+
+    PyTorch, when installed, is imported first: its wheel carries its own
+    HIP runtime, and the library must bind to the runtime already in the
+    process (the one that owns the caller's tensors and streams) rather than
+    load a second copy of it, which would not see the device."""
     global _lib
     if _lib is None:
         if not os.path.exists(LIB_PATH):
             raise ImportError(f"{LIB_PATH} is missing: build it with `python -m paper_2606_01852_amd.build`")
+        try:
+            import torch  # noqa: F401
+        except ImportError:
+            pass
         L = C.CDLL(LIB_PATH)
         for name, (res, args) in _SIGS.items():
             f = getattr(L, name)
@@ -319,6 +329,12 @@ def tnc_permute(ctx: int, in_dev: int, out_dev: int, extents: Sequence[int], per
     ext = np.ascontiguousarray(np.asarray(extents, dtype=np.int64))
     pm = _i32(perm)
     _check(lib().tnc_permute(ctx, in_dev, out_dev, len(ext), _ptr(ext, C.c_int64), _ptr(pm, C.c_int32)))
+
+
+def tnc_permute_noalloc(ctx: int, in_dev: int, out_dev: int, extents: Sequence[int], perm: Sequence[int]) -> None:
+    ext = np.ascontiguousarray(np.asarray(extents, dtype=np.int64))
+    pm = _i32(perm)
+    _check(lib().tnc_permute_noalloc(ctx, in_dev, out_dev, len(ext), _ptr(ext, C.c_int64), _ptr(pm, C.c_int32)))
 
 
 def tnc_batched_cgemm(ctx: int, h: int, m: int, n: int, k: int, a_dev: int, stride_a: int, b_dev: int,
