@@ -15,7 +15,12 @@ FLOPs per complex multiply-add.
 Prints one JSON line.  ``roofline`` is for the dominant kernel (the large
 GEMM), its launch time measured with HIP events on its own stream over the
 timed steps; ``cpu_baseline`` times the FP64 oracle on a bounded sample of
-the same workload on this host's cores.
+the same workload on this host's cores, and ``error_vs_oracle`` compares the
+GPU's rows of that sample with the oracle's.  ``configs`` holds one record
+for each other workload (the 12-qubit circuit amplitude, the 8x8 bond-4
+grid, the sliced 40-qubit circuit), each with its measured error against the
+FP64 oracle, its roofline and its own CPU-oracle baseline; ``latency`` is the
+serving mix (continuous batching vs one request at a time).
 """
 from __future__ import annotations
 
@@ -82,8 +87,12 @@ def parse():
                     help="with --workload small: also serve 4096 amplitude queries through batchers "
                          "(off by default: one run under rocprofv3 --kernel-trace ended in a host SIGSEGV "
                          "whose cause is not found)")
-    ap.add_argument("--serve-pool", type=int, default=24)
-    ap.add_argument("--serve-requests", type=int, default=600)
+    ap.add_argument("--serve-pool", type=int, default=64)
+    ap.add_argument("--serve-requests", type=int, default=2000)
+    ap.add_argument("--serve-arena-gib", type=float, default=240.0,
+                    help="serving: arena size (the admission budget for planned intermediates)")
+    ap.add_argument("--no-configs", action="store_true",
+                    help="skip the per-workload records (circuit12, grid8, circuit40)")
     ap.add_argument("--serve-load", type=float, default=0.8)
     ap.add_argument("--serve-slots", type=int, default=8)
     ap.add_argument("--slices", type=int, default=0, help="circuit40: slices per run (0 = all)")
@@ -97,9 +106,10 @@ def parse():
 
 def cpu_baseline(net_a, path_a, net_b, path_b, n_fixed: int = 4):
     """The oracle (complex128 numpy) on a bounded sample: the big contraction
-    with its n_fixed leading M labels fixed to one value (1/16 of the rows
-    for 4, 10-25 s on 16 host threads) and 4 of the 64 batch entries.
-    Rate = sample FLOPs (8 per complex MAC) / time."""
+    with its n_fixed leading M labels fixed to 0 (the first 1/16 of the
+    result rows for 4, 10-25 s on 16 host threads) and 4 of the 64 batch
+    entries.  Rate = sample FLOPs (8 per complex MAC) / time.  Returns the
+    record and the oracle's results (those rows, those batch entries)."""
     from oracle import contract as oc
     from workloads.network import Network, Path
 
@@ -113,7 +123,7 @@ def cpu_baseline(net_a, path_a, net_b, path_b, n_fixed: int = 4):
     sub_la = tuple(l for l in la if l not in fix)
     sub = Network([sub_a, b], [sub_la, lb], net_a.extents, tuple(l for l in net_a.open if l not in fix))
     t0 = time.perf_counter()
-    oc.contract(sub, Path(path_a.pairs, ()))
+    ref_rows = oc.contract(sub, Path(path_a.pairs, ()))
     dt = time.perf_counter() - t0
     m_sub = int(np.prod([net_a.extents[l] for l in sub_la])) // (2 ** 14)
     t_total += dt
@@ -123,15 +133,24 @@ def cpu_baseline(net_a, path_a, net_b, path_b, n_fixed: int = 4):
     sub2 = Network([a2[:4], b2[:4]], net_b.labels, net_b.extents.copy(), net_b.open)
     sub2.extents[net_b.open[0]] = 4
     t0 = time.perf_counter()
-    oc.contract(sub2, path_b)
+    ref_batch = oc.contract(sub2, path_b)
     dt2 = time.perf_counter() - t0
     t_total += dt2
     flops_total += 8.0 * 4 * 1024 * 256 * 1024
     threads, host = host_description()
-    return {"value": flops_total / t_total / 1e12, "unit": "complex TFLOP/s", "cores": threads,
-            "kind": "oracle",
-            "sample": f"pair30 rows with {n_fixed} leading M labels fixed (1/{2 ** n_fixed} of the work, {dt:.1f} s) + 4 of 64 "
-                      f"batch entries ({dt2:.1f} s); numpy complex128 tensordot incl. operand transposes; {host}"}
+    rec = {"value": flops_total / t_total / 1e12, "unit": "complex TFLOP/s", "cores": threads,
+           "kind": "oracle",
+           "sample": f"pair30 rows with {n_fixed} leading M labels fixed (1/{2 ** n_fixed} of the work, {dt:.1f} s) + 4 of 64 "
+                     f"batch entries ({dt2:.1f} s); numpy complex128 tensordot incl. operand transposes; {host}"}
+    return rec, np.asarray(ref_rows).reshape(-1), np.asarray(ref_batch).reshape(-1)
+
+
+def rel_err(got, ref):
+    """(relative Frobenius error, max elementwise error / max |ref|)."""
+    got = np.asarray(got, dtype=np.complex128).ravel()
+    ref = np.asarray(ref, dtype=np.complex128).ravel()
+    d = np.abs(got - ref)
+    return float(np.linalg.norm(got - ref) / np.linalg.norm(ref)), float(d.max() / np.abs(ref).max())
 
 
 def host_description():
@@ -158,42 +177,58 @@ def cpu_baseline_slices(net, path, flops_per_slice: float, n_slices: int, n_samp
     from oracle import contract as oc
     rng = np.random.Generator(np.random.PCG64(1040))
     sample = [int(x) for x in rng.choice(n_slices, min(n_sample, n_slices), replace=False)]
+    refs = np.empty(len(sample), dtype=np.complex128)
     t0 = time.perf_counter()
-    for s in sample:
-        oc.contract(net, path, slices=[s])
+    for i, s in enumerate(sample):
+        refs[i] = complex(oc.contract(net, path, slices=[s]))
     dt = time.perf_counter() - t0
     threads, host = host_description()
-    return {"value": flops_per_slice * len(sample) / dt / 1e12, "unit": "complex TFLOP/s", "cores": threads,
-            "kind": "oracle",
-            "sample": f"{len(sample)} of {n_slices} slices, each alone ({dt:.1f} s, {dt / len(sample) * 1e3:.0f} ms "
-                      f"per slice: {dt / len(sample) * n_slices:.0f} s extrapolated to all); numpy complex128 "
-                      f"tensordot; {host}"}
+    rec = {"value": flops_per_slice * len(sample) / dt / 1e12, "unit": "complex TFLOP/s", "cores": threads,
+           "kind": "oracle",
+           "sample": f"{len(sample)} of {n_slices} slices, each alone ({dt:.1f} s, {dt / len(sample) * 1e3:.0f} ms "
+                     f"per slice: {dt / len(sample) * n_slices:.0f} s extrapolated to all); numpy complex128 "
+                     f"tensordot; {host}"}
+    return rec, sample, refs
 
 
 HEAVY_FLOPS = 2.0 ** 38   # requests planned at >= this many FLOP share one heavy slot
 
 
-def serving_leg(args):
-    """Serving mix: a pool of random grid circuits (20..48 qubits, depth 8..14,
-    4^j slices, complex64 or split-bf16, planned work capped at 2^43 FLOP),
-    Poisson arrivals at ``load`` x the measured saturation throughput of the
-    continuous-batching server (heavy requests, >= 2^38 planned FLOP, in a
-    lane of one slot); the same arrival trace is replayed through the server
-    without the heavy lane and with one slot (one request at a time), at the
-    main load and at 0.5 and 0.95 of saturation.  Latency is submit to
-    done, measured by the library."""
-    import threading
+def _pool_entry(i: int):
+    from workloads import configs
+    return configs.serve_request(i)
 
+
+def build_pool(n: int):
+    """The serving pool's networks and paths (greedy path and slicer per
+    circuit), built in 16 worker processes: the path search dominates and
+    runs on the host only."""
+    import concurrent.futures as cf
+    import multiprocessing as mp
+    with cf.ProcessPoolExecutor(max_workers=min(16, n), mp_context=mp.get_context("spawn")) as ex:
+        return list(ex.map(_pool_entry, range(n)))
+
+
+def serving_leg(args):
+    """Serving mix (config 4): a pool of random grid circuits (20..48 qubits,
+    depth 8..14, 4^j slices, complex64 or split-bf16, planned work capped at
+    2^43 FLOP), admitted by planned arena bytes within a 240 GiB arena.
+    Closed-loop saturation (all requests queued at once) of the
+    continuous-batching server (8 slots, heavy requests of >= 2^38 planned
+    FLOP in a lane of one slot) and of the one-request-at-a-time server; then
+    the same seeded Poisson arrival trace (2,000 requests drawn from the
+    pool) replayed at 0.5, 0.8 and 0.95 x the continuous server's
+    saturation through both, and at 0.8 through the continuous server without
+    the heavy lane.  Latency is submit to done, measured by the library."""
     import torch
 
     from paper_2606_01852_amd import tnc
-    from workloads import configs
 
-    log(f"serving: building a pool of {args.serve_pool} circuits")
+    log(f"serving: building a pool of {args.serve_pool} circuits (16 processes)")
     t0 = time.time()
-    pool = [configs.serve_request(i) for i in range(args.serve_pool)]
+    pool = build_pool(args.serve_pool)
     log(f"serving: pool ready in {time.time() - t0:.1f} s")
-    arena_bytes = 64 << 30
+    arena_bytes = int(args.serve_arena_gib * (1 << 30))
     arena = torch.empty(arena_bytes, dtype=torch.uint8, device="cuda")
     ctx = tnc.Context(0, arena_bytes=arena_bytes, arena_ptr=arena.data_ptr())
     nets, plans, flops = [], [], []
@@ -210,6 +245,7 @@ def serving_leg(args):
     which = [int(x) for x in rng.integers(0, len(plans), args.serve_requests)]
     gaps = rng.exponential(1.0, args.serve_requests)
     outs = [np.zeros(1, dtype=np.complex128) for _ in which]
+    tot_flops = sum(flops[w] for w in which)
 
     def replay(slots, arrivals, heavy=HEAVY_FLOPS):
         tnc.tnc_serve_start(ctx.handle, slots, 1 << 16)
@@ -226,40 +262,37 @@ def serving_leg(args):
         tnc.tnc_serve_stop(ctx.handle)
         return np.array(lat), t_end - t_start
 
-    # warm up every plan once (tables, kernels)
-    replay(args.serve_slots, np.zeros(len(which)))
-    lat_sat, t_sat = replay(args.serve_slots, np.zeros(len(which)))
-    sat = len(which) / t_sat
-    servers = (("continuous_batching", args.serve_slots, HEAVY_FLOPS),
-               ("continuous_no_heavy_lane", args.serve_slots, 0.0),
-               ("one_at_a_time", 1, 0.0))
-    tot_flops = sum(flops[w] for w in which)
+    def stats(lat, wall):
+        return {"p50_ms": round(float(np.percentile(lat, 50)) * 1e3, 3),
+                "p99_ms": round(float(np.percentile(lat, 99)) * 1e3, 3),
+                "req_per_s": round(len(lat) / wall, 2), "tflops": round(tot_flops / wall / 1e12, 3)}
 
-    def measure(load):
-        rate = load * sat
+    # warm up every plan once (tables, kernels, graphs)
+    replay(args.serve_slots, np.zeros(len(which)))
+    burst = np.zeros(len(which))
+    sat = {}
+    for name, slots, heavy in (("continuous_batching", args.serve_slots, HEAVY_FLOPS), ("one_at_a_time", 1, 0.0)):
+        lat, wall = replay(slots, burst, heavy)
+        sat[name] = stats(lat, wall)
+        log(f"serving: closed-loop saturation of {name}: {sat[name]}")
+    rate0 = sat["continuous_batching"]["req_per_s"]
+    res = {"saturation": sat}
+    for load in (0.5, 0.8, 0.95):
+        rate = load * rate0
         arrivals = np.cumsum(gaps) / rate
-        log(f"serving: saturation {sat:.1f} req/s; replaying {len(which)} Poisson arrivals at {rate:.1f} req/s")
-        out = {}
+        servers = [("continuous_batching", args.serve_slots, HEAVY_FLOPS), ("one_at_a_time", 1, 0.0)]
+        if load == 0.8:
+            servers.insert(1, ("continuous_no_heavy_lane", args.serve_slots, 0.0))
+        res[f"load_{load}"] = {"arrival_rate_req_per_s": round(rate, 2)}
         for name, slots, heavy in servers:
             lat, wall = replay(slots, arrivals, heavy)
-            out[name] = {"slots": slots, "heavy_lane_flops": heavy,
-                         "p50_ms": round(float(np.percentile(lat, 50)) * 1e3, 3),
-                         "p99_ms": round(float(np.percentile(lat, 99)) * 1e3, 3),
-                         "req_per_s": round(len(which) / wall, 2),
-                         "tflops": round(tot_flops / wall / 1e12, 3)}
-            log(f"serving {name} at load {load}: {out[name]}")
-        return out, rate
-
-    res, rate = measure(args.serve_load)
-    res["other_loads"] = {}
-    for load in (0.5, 0.95):
-        if load != args.serve_load:
-            r, _ = measure(load)
-            res["other_loads"][str(load)] = {k: {"p50_ms": v["p50_ms"], "p99_ms": v["p99_ms"]} for k, v in r.items()}
-    res["arrival_rate_req_per_s"] = round(rate, 2)
-    res["saturation_req_per_s"] = round(sat, 2)
+            res[f"load_{load}"][name] = stats(lat, wall)
+            log(f"serving {name} at load {load} ({rate:.1f} req/s): {res[f'load_{load}'][name]}")
     res["requests"] = len(which)
     res["pool"] = len(plans)
+    res["arena_gib"] = args.serve_arena_gib
+    res["slots"] = args.serve_slots
+    res["heavy_lane_flops"] = HEAVY_FLOPS
     for p in plans:
         p.close()
     for n in nets:
@@ -447,11 +480,190 @@ def amplitude_query_leg(ctx, n_queries: int = 4096):
     return res
 
 
-def bench_circuit40(args):
-    """Sliced 40-qubit circuit (5x8 grid, depth 12, 16 sliced labels = 65,536
-    slices): the slices run as a batch dimension of every step, summed in FP64."""
+def dominant_step(tnc, plan, n_runs: int = 1):
+    """The step with the most profiled kernel time (profiling on, a run just
+    done): its algorithmic bytes 8 (hA m k + hB n k + h m n) and FLOPs
+    8 h m n k per batch, what bounds it at MI355X peaks (HBM 8 TB/s, FP32
+    MFMA 157.3 TFLOP/s) and the achieved fraction of that bound."""
+    info = tnc.tnc_plan_get_info(plan.handle)
+    best = None
+    for s in range(info.n_steps):
+        ms, cnt = tnc.tnc_plan_get_profile(plan.handle, s)
+        if cnt and (best is None or ms > best[0]):
+            best = (ms, cnt, s)
+    if best is None:
+        return None
+    ms, cnt, s = best
+    st = tnc.tnc_plan_get_batch_step(plan.handle, s)
+    per = ms / cnt * 1e-3
+    fl = 8.0 * st.h * st.m * st.n * st.k
+    by = 8.0 * (st.hA * st.m * st.k + st.hB * st.n * st.k + st.h * st.m * st.n)
+    mfma = fl / (PEAK_FP32_MFMA * 1e12) >= by / (PEAK_HBM_TBS * 1e12)
+    achieved = fl / per / 1e12 if mfma else by / per / 1e9
+    peak = PEAK_FP32_MFMA if mfma else PEAK_HBM
+    return {"step": s, "h": st.h, "m": st.m, "n": st.n, "k": st.k, "kernel": st.kernel, "variant": st.variant,
+            "ms_per_launch": round(per * 1e3, 4), "launches": cnt, "bound": "mfma" if mfma else "hbm",
+            "achieved": round(achieved, 3), "peak": peak, "unit": "TFLOP/s" if mfma else "GB/s",
+            "frac": round(achieved / peak, 4)}
+
+
+def oracle_time(fn, reps: int = 3) -> float:
+    """Median wall time of the oracle call (seconds)."""
+    ts = []
+    for _ in range(reps):
+        t0 = time.perf_counter()
+        fn()
+        ts.append(time.perf_counter() - t0)
+    return float(np.median(ts))
+
+
+def record_circuit12():
+    """Config 0: the 12-qubit 3x4 circuit of depth 8 as a closed amplitude
+    network (154 leaves, greedy path), complex64 4M, level-grouped and
+    replayed as a hipGraph: latency of one amplitude and of all 4096 (open
+    network, FP64 norm on the device), each with its error against the FP64
+    oracle; the amplitude also against the state vector, and unitarity.
+    Latency-bound: the roofline is the path's Eq. (6) time at peak rates
+    (nanoseconds) against the measured latency."""
     import torch
 
+    from oracle import contract as oc
+    from oracle import statevector as osv
+    from paper_2606_01852_amd import tnc
+    from workloads import configs
+    from workloads.circuits import circuit_network
+    from workloads.paths import greedy_path
+
+    ctx = tnc.Context(0, arena_bytes=1 << 30, stream=torch.cuda.current_stream().cuda_stream)
+    circ = configs.circuit12_circuit()
+    net, path = configs.circuit12()
+    tn = tnc.Network(ctx, net.labels, net.extents, net.open, net.c64().leaves)
+    plan = tnc.Plan(tn, path.pairs)
+    tnc.tnc_plan_set_graph(plan.handle, True)
+
+    def timed(fn, reps):
+        fn()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            fn()
+        torch.cuda.synchronize()
+        return (time.perf_counter() - t0) / reps
+
+    dt = timed(lambda: plan.contract(), 500)
+    amp = complex(plan.contract()[0])
+    ref = complex(oc.contract(net, path))
+    gates = [(qs, u.astype(np.complex64).astype(np.complex128)) for qs, u in circ.gates]
+    sv = osv.amplitude(circ.n_qubits, gates, circ.bitstring)
+    roof = path_roofline_s(tnc, plan)
+    netall = circuit_network(circ, open_qubits=range(12))
+    pathall = greedy_path(netall)
+    tna = tnc.Network(ctx, netall.labels, netall.extents, netall.open, netall.c64().leaves)
+    pa = tnc.Plan(tna, pathall.pairs)
+    tnc.tnc_plan_set_graph(pa.handle, True)
+    dt_all = timed(lambda: pa.contract(), 200)
+    amps = pa.contract()
+    norm2 = tnc.tnc_plan_result_norm2(pa.handle)
+    ref_all = oc.contract(netall, pathall).reshape(-1)
+    e_all, e_all_max = rel_err(amps, ref_all)
+    t_cpu = oracle_time(lambda: oc.contract(net, path), 5)
+    threads, host = host_description()
+    rec = {"workload": "circuit12: 3x4 grid, depth 8, closed amplitude network, greedy path (153 steps)",
+           "latency_us": round(dt * 1e6, 2), "unit": "us per amplitude", "dtype": "c64/fp32",
+           "tflops": round(plan.info.flops_per_slice / dt / 1e12, 6),
+           "error_vs_oracle": abs(amp - ref) / abs(ref), "error_vs_statevector": abs(amp - sv) / abs(sv),
+           "tolerance": 1e-5,
+           "all_4096_amplitudes": {"latency_us": round(dt_all * 1e6, 2), "rel_frobenius_error_vs_oracle": e_all,
+                                   "max_error_over_max_amplitude": e_all_max,
+                                   "sum_abs2_minus_1": norm2 - 1.0},
+           "roofline": {"bound": "latency", "path_roofline_us": round(roof * 1e6, 4),
+                        "measured_us": round(dt * 1e6, 2), "frac": round(roof / dt, 6)},
+           "cpu_baseline": {"value": round(t_cpu * 1e6, 1), "unit": "us per amplitude", "cores": threads,
+                            "kind": "oracle", "sample": f"the same amplitude, median of 5; {host}"}}
+    for h in (plan, tn, pa, tna, ctx):
+        h.close()
+    return rec
+
+
+def record_grid8():
+    """Config 2: the closed 8x8 grid network of bond dimension 4 (64 leaves,
+    greedy path) contracted to a scalar in complex64 4M, 3M and
+    split-bf16x3 (exact power-of-two leaf prescaling, undone in FP64); each
+    with its error against the FP64 oracle (and split-bf16x3 against the
+    oracle's split emulation), the path roofline, the dominant step's
+    roofline, and the oracle's time for the same contraction."""
+    import torch
+
+    from oracle import contract as oc
+    from oracle import split as osp
+    from paper_2606_01852_amd import tnc
+    from workloads import configs
+    from workloads.grids import prescale_log2
+    from workloads.network import Network
+    from workloads.paths import greedy_path
+
+    ctx = tnc.Context(0, arena_bytes=8 << 30, stream=torch.cuda.current_stream().cuda_stream)
+    g, _ = configs.grid8()
+    e = prescale_log2(g.labels)
+    gs = Network([x * 2.0 ** int(k) for x, k in zip(g.leaves, e)], g.labels, g.extents, ())
+    gpath = greedy_path(gs)
+    depth = [0] * gs.n_leaves
+    for a, b in gpath.pairs:
+        depth.append(1 + max(depth[int(a)], depth[int(b)]))
+    exact = complex(oc.contract(gs, gpath))
+    emu = complex(oc.contract(gs, gpath, step=osp.split_step))
+    t_cpu = oracle_time(lambda: oc.contract(gs, gpath), 3)
+    tg = tnc.Network(ctx, gs.labels, gs.extents, gs.open, gs.c64().leaves)
+    threads, host = host_description()
+    rec = {"workload": "grid8: closed 8x8 grid, bond 4, CN(0,1)/sqrt(numel) entries (x 2^floor(deg/2), exact), "
+                       "greedy path (63 steps)", "forms": {}}
+    for name, prec, form in (("c64_4M", tnc.PREC_C64, tnc.GEMM_4M), ("c64_3M", tnc.PREC_C64, tnc.GEMM_3M),
+                             ("bf16x3", tnc.PREC_BF16X3, tnc.GEMM_4M)):
+        p = tnc.Plan(tg, gpath.pairs, (), prec, form)
+        tnc.tnc_plan_autotune(p.handle)
+        tnc.tnc_plan_set_graph(p.handle, True)
+        p.contract()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(20):
+            z = complex(p.contract()[0])
+        dt = (time.perf_counter() - t0) / 20
+        p2 = tnc.Plan(tg, gpath.pairs, (), prec, form)
+        tnc.tnc_plan_autotune(p2.handle)
+        tnc.tnc_plan_set_profile(p2.handle, True)
+        p2.contract()
+        dom = dominant_step(tnc, p2)
+        roof = path_roofline_s(tnc, p)
+        flops = p.info.flops_per_slice
+        f = {"ms": round(dt * 1e3, 4), "tflops": round(flops / dt / 1e12, 3),
+             "error_vs_oracle": abs(z - exact) / abs(exact), "path_roofline_frac": round(roof / dt, 4),
+             "dominant_step": dom}
+        if prec == tnc.PREC_BF16X3:
+            f["error_vs_split_emulation"] = abs(z - emu) / abs(emu)
+            f["tolerance"] = max(1e-5, 4 * 2.0 ** -16 * depth[-1])
+        else:
+            f["tolerance"] = 1e-5
+        rec["forms"][name] = f
+        log(f"grid8 {name}: {f}")
+        p.close()
+        p2.close()
+    rec["cpu_baseline"] = {"value": round(flops / t_cpu / 1e12, 6),
+                           "unit": "complex TFLOP/s", "cores": threads, "kind": "oracle",
+                           "sample": f"the whole contraction ({t_cpu * 1e3:.1f} ms, median of 3); {host}"}
+    tg.close()
+    ctx.close()
+    return rec
+
+
+def circuit40_record(args, steps: int, warmup: int, with_cpu: bool):
+    """Config 3: the sliced 40-qubit circuit (5x8 grid, depth 12, 16 sliced
+    labels = 65,536 slices) with the slices as a batch dimension of every
+    step, summed in FP64; throughput, path and dominant-step rooflines, the
+    per-slice loop it replaces, and errors against the FP64 oracle on
+    sampled slices and on the sum of slices [0, 64)."""
+    import torch
+
+    from oracle import contract as oc
     from paper_2606_01852_amd import tnc
     from workloads import configs
 
@@ -476,30 +688,36 @@ def bench_circuit40(args):
     n = args.slices or info.n_slices
     log(f"slices {n} of {info.n_slices}; chunk {info.max_chunk}; chunk peak {info.chunk_peak_bytes / 2**30:.1f} GiB; "
         f"{info.flops_per_slice:.3e} FLOP per slice")
-    for _ in range(args.warmup):
+    for _ in range(warmup):
         plan.contract(0, n)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    for _ in range(args.steps):
+    for _ in range(steps):
         z = plan.contract(0, n)
-    dt = (time.perf_counter() - t0) / args.steps
-    tnc.tnc_plan_set_profile(plan.handle, True)
-    plan.contract(0, n)
+    dt = (time.perf_counter() - t0) / steps
+    n_chunks = max(1, n // info.max_chunk)
+    prof = tnc.Plan(tn, path.pairs, path.sliced, prec, form)
+    if args.max_chunk:
+        tnc.tnc_plan_set_max_chunk(prof.handle, args.max_chunk)
+    tnc.tnc_plan_autotune(prof.handle)
+    tnc.tnc_plan_set_profile(prof.handle, True)
+    prof.contract(0, n)
     per_step = []
     for s in range(info.n_steps):
-        ms, cnt = tnc.tnc_plan_get_profile(plan.handle, s)
+        ms, cnt = tnc.tnc_plan_get_profile(prof.handle, s)
         per_step.append((ms, s))
-    perm_ms, perm_n = tnc.tnc_plan_get_profile(plan.handle, -1)
-    red_ms, red_n = tnc.tnc_plan_get_profile(plan.handle, -2)
+    perm_ms, perm_n = tnc.tnc_plan_get_profile(prof.handle, -1)
+    red_ms, red_n = tnc.tnc_plan_get_profile(prof.handle, -2)
     per_step.sort(reverse=True)
     tot = sum(x[0] for x in per_step)
     log(f"profiled run: GEMMs {tot:.1f} ms, leaf permutes {perm_ms:.1f} ms ({perm_n}), reductions {red_ms:.2f} ms")
-    n_chunks = max(1, n // info.max_chunk)
-    for ms, s in per_step[:12]:
+    for ms, s in per_step[:8]:
         st = tnc.tnc_plan_get_batch_step(plan.handle, s)
         f = 8.0 * st.h * st.m * st.n * st.k * n_chunks
         log(f"  step {s:4d}: {ms:8.2f} ms  h {st.h} m {st.m} n {st.n} k {st.k} kernel {st.kernel} "
             f"variant {st.variant} split {st.split} swapped {st.swapped}: {f / ms / 1e9:.1f} TFLOP/s")
+    dom = dominant_step(tnc, prof)
+    prof.close()
     exec_flops = info.chunk_flops * n_chunks if n % info.max_chunk == 0 else info.flops_per_slice * n
     value = exec_flops / dt / 1e12
     log(f"executed {exec_flops:.3e} FLOP ({info.flops_per_slice * n:.3e} without hoisting slice-invariant steps)")
@@ -511,7 +729,6 @@ def bench_circuit40(args):
         if not st.natural:
             perm_steps += 1
             avoided += 16.0 * st.h * st.m * st.n * n_chunks
-    log(f"{perm_steps} of {info.n_steps} steps store in consumer order: {avoided / 1e9:.1f} GB of transposes avoided")
     roof_s = path_roofline_s(tnc, plan, n_chunks, leaf_permutes=False)
     log(f"path roofline (GEMM steps of the batched run): {roof_s * 1e3:.1f} ms = {roof_s / dt:.3f} of the measured")
     # the same slices contracted one at a time (a chunk of one slice), the
@@ -529,25 +746,57 @@ def bench_circuit40(args):
         single.contract(i, 1)
     torch.cuda.synchronize()
     t_slice = (time.perf_counter() - t1) / n_loop
-    single.close()
     log(f"one slice at a time: {t_slice * 1e3:.2f} ms per slice -> {t_slice * n:.1f} s for {n} slices "
         f"(batched: {dt:.2f} s, {t_slice * n / dt:.1f}x)")
-    res = {"metric": "complex TFLOP/s of path execution (% MFMA peak) + p50/p99 request latency",
-           "value": round(value, 3), "unit": "complex TFLOP/s", "n_gpus": 1, "steps": args.steps,
-           "warmup": args.warmup, "ms_per_step": round(dt * 1e3, 3), "higher_is_better": True,
-           "scaling": "weak", "vs_baseline": None, "dtype": "c64/fp32" if prec == tnc.PREC_C64 else "c64/bf16x3",
-           "data": "synthetic",
-           "config": {"workload": "circuit40: 5x8 grid, depth 12, 16 sliced labels", "slices": n,
-                      "chunk": info.max_chunk, "amplitude": [z[0].real, z[0].imag],
-                      "permuted_store_steps": perm_steps, "transposes_avoided_gb": round(avoided / 1e9, 2),
-                      "per_slice_equivalent_tflops": round(info.flops_per_slice * n / dt / 1e12, 3),
-                      "path_roofline_frac": round(roof_s / dt, 4),
-                      "slice_loop_ms_per_slice": round(t_slice * 1e3, 3),
-                      "slice_loop_extrapolated_s": round(t_slice * n, 2),
-                      "batched_speedup_vs_slice_loop": round(t_slice * n / dt, 2)}}
-    if not args.no_cpu:
+    res = {"workload": "circuit40: 5x8 grid, depth 12, 16 sliced labels", "slices": n,
+           "value": round(value, 3), "unit": "complex TFLOP/s", "ms_per_run": round(dt * 1e3, 3),
+           "steps": steps, "warmup": warmup,
+           "dtype": "c64/fp32" if prec == tnc.PREC_C64 else "c64/bf16x3",
+           "chunk": info.max_chunk, "amplitude": [z[0].real, z[0].imag],
+           "permuted_store_steps": perm_steps, "transposes_avoided_gb": round(avoided / 1e9, 2),
+           "per_slice_equivalent_tflops": round(info.flops_per_slice * n / dt / 1e12, 3),
+           "path_roofline_frac": round(roof_s / dt, 4), "dominant_step": dom,
+           "slice_loop_ms_per_slice": round(t_slice * 1e3, 3),
+           "slice_loop_extrapolated_s": round(t_slice * n, 2),
+           "batched_speedup_vs_slice_loop": round(t_slice * n / dt, 2)}
+    # errors against the FP64 oracle: the sum of slices [0, 64) (FP64
+    # accumulation on the device) and, with the CPU baseline, its sampled
+    # slices one by one
+    ref64 = sum(complex(oc.contract(net, path, slices=[s])) for s in range(64))
+    got64 = complex(single.contract(0, 64)[0])
+    res["error_vs_oracle"] = {"slices_0_64_sum_rel": abs(got64 - ref64) / abs(ref64)}
+    if with_cpu:
         log("cpu baseline (oracle on a bounded sample of slices)")
-        res["cpu_baseline"] = cpu_baseline_slices(net, path, info.flops_per_slice, info.n_slices)
+        rec, sample, refs = cpu_baseline_slices(net, path, info.flops_per_slice, info.n_slices)
+        got = np.array([complex(single.contract(s, 1)[0]) for s in sample])
+        rms = float(np.sqrt(np.mean(np.abs(refs) ** 2)))
+        rel = np.abs(got - refs) / np.abs(refs)
+        res["error_vs_oracle"].update({
+            "sampled_slices": len(sample), "median_rel": float(np.median(rel)), "max_rel": float(rel.max()),
+            "max_abs_over_rms_amplitude": float(np.max(np.abs(got - refs)) / rms),
+            "note": "per-slice amplitudes are Porter-Thomas distributed: small slices lose relative digits to "
+                    "float32 cancellation, so errors are bounded against the rms amplitude (1e-5)"})
+        res["cpu_baseline"] = rec
+    single.close()
+    plan.close()
+    tn.close()
+    ctx.close()
+    del arena
+    torch.cuda.empty_cache()
+    return res
+
+
+def bench_circuit40(args):
+    """Sliced 40-qubit circuit (5x8 grid, depth 12, 16 sliced labels = 65,536
+    slices): the slices run as a batch dimension of every step, summed in FP64."""
+    rec = circuit40_record(args, args.steps, args.warmup, not args.no_cpu)
+    res = {"metric": "complex TFLOP/s of path execution (% MFMA peak) + p50/p99 request latency",
+           "value": rec.pop("value"), "unit": rec.pop("unit"), "n_gpus": 1, "steps": args.steps,
+           "warmup": args.warmup, "ms_per_step": rec.pop("ms_per_run"), "higher_is_better": True,
+           "scaling": "weak", "vs_baseline": None, "dtype": rec.pop("dtype"), "data": "synthetic",
+           "config": rec}
+    if "cpu_baseline" in rec:
+        res["cpu_baseline"] = rec.pop("cpu_baseline")
     print(json.dumps(res), flush=True)
 
 
@@ -667,8 +916,19 @@ def main():
                               if perm_gbs else None},
         "kernels": {"gemm_ms": round(gemm_avg_s * 1e3, 3),
                     "permute_ms_per_launch": round(perm_ms / max(perm_n, 1), 3),
-                    "batch_gemm_ms": round(bgemm_ms / max(bgemm_n, 1), 3)},
+                    "permute_gbs": round(perm_gbs, 1) if perm_gbs else None,
+                    "permute_frac_of_hbm_peak": round(perm_gbs / PEAK_HBM, 4) if perm_gbs else None,
+                    "batch_gemm_ms": round(bgemm_ms / max(bgemm_n, 1), 3),
+                    "batch_gemm_tflops": round(plan_b.info.flops_per_slice / (bgemm_ms / max(bgemm_n, 1) / 1e3)
+                                               / 1e12, 3) if bgemm_n else None},
     }
+    # result rows kept for the comparison with the CPU oracle's sample: the
+    # first 1/16 of pair30's rows (leading four M labels 0) and the first
+    # four batch entries
+    rows_a = plan_a.info.n_result // 16
+    rows_b = plan_b.info.n_result // 16
+    kept = {"4M" if prec == tnc.PREC_C64 and form == tnc.GEMM_4M else args.form:
+            (out_a[:rows_a].cpu().numpy(), out_b[:rows_b].cpu().numpy())}
     if not args.no_forms and args.form == "4M" and args.prec == "c64":
         # the same step in the other GEMM forms (same inputs, same arena)
         res["other_forms"] = {}
@@ -693,11 +953,16 @@ def main():
             fdt = (time.perf_counter() - t1) / 2
             g_ms, g_n = tnc.tnc_plan_get_profile(pa.handle, 0)
             g_s = g_ms / max(g_n, 1) / 1e3
+            gt = plan_a.info.flops_per_slice / g_s / 1e12
+            # executed MFMA work against its own peak: 3M executes 6 of the
+            # 8 FLOPs per complex MAC on FP32 MFMA, split-bf16x3 three bf16
+            # products per real product (peak / 3 in the 8-FLOP convention)
+            executed = gt * 6 / 8 / PEAK_FP32_MFMA if name == "3M" else gt / fpeak
             res["other_forms"][name] = {
                 "tflops": round(flops_step / fdt / 1e12, 3), "ms_per_step": round(fdt * 1e3, 3),
-                "gemm_tflops": round(plan_a.info.flops_per_slice / g_s / 1e12, 3),
-                "gemm_frac_of_form_peak": round(plan_a.info.flops_per_slice / g_s / 1e12 / fpeak, 4),
+                "gemm_tflops": round(gt, 3), "gemm_frac_of_executed_mfma_peak": round(executed, 4),
                 "variant": tnc.tnc_plan_get_step(pa.handle, 0).variant}
+            kept[name] = (out_a[:rows_a].cpu().numpy(), out_b[:rows_b].cpu().numpy())
             log(f"form {name}: {res['other_forms'][name]}")
             pa.close()
             pb.close()
@@ -709,18 +974,34 @@ def main():
         torch.cuda.synchronize()
         log("copy probe: 4 GiB read + 4 GiB written")
         del src, dst
+    plan_a.close()
+    plan_b.close()
+    tn_a.close()
+    tn_b.close()
+    ctx.close()
+    del arena, out_a, out_b
+    torch.cuda.empty_cache()
+    if not args.no_configs:
+        res["configs"] = {}
+        log("config record: circuit12")
+        res["configs"]["circuit12"] = record_circuit12()
+        log("config record: grid8")
+        res["configs"]["grid8"] = record_grid8()
+        log("config record: circuit40")
+        res["configs"]["circuit40"] = circuit40_record(args, 2, 1, not args.no_cpu)
     if not args.no_serve:
-        plan_a.close()
-        plan_b.close()
-        tn_a.close()
-        tn_b.close()
-        ctx.close()
-        del arena
-        torch.cuda.empty_cache()
         res["latency"] = serving_leg(args)
     if not args.no_cpu:
         log("cpu baseline (oracle on a bounded sample)")
-        res["cpu_baseline"] = cpu_baseline(net_a, path_a, net_b, path_b)
+        rec, ref_rows, ref_batch = cpu_baseline(net_a, path_a, net_b, path_b)
+        res["cpu_baseline"] = rec
+        res["error_vs_oracle"] = {"sample": "the CPU baseline's sample: pair30 rows with the leading four M labels "
+                                            "0 (1/16 of the result) and the first 4 of 64 batch entries",
+                                  "metric": "relative Frobenius error, and max |error| / max |ref|"}
+        for name, (ga, gb) in kept.items():
+            ea, ea_max = rel_err(ga, ref_rows)
+            eb, eb_max = rel_err(gb[:ref_batch.size], ref_batch)
+            res["error_vs_oracle"][name] = {"pair30": [ea, ea_max], "pair_batch": [eb, eb_max]}
     print(json.dumps(res), flush=True)
 
 

@@ -15,6 +15,7 @@ Seeds follow ``PCG64(1000 + workload id)``; serving request ``i`` uses
 """
 from __future__ import annotations
 
+import math
 from typing import List, Tuple
 
 import numpy as np
@@ -90,7 +91,7 @@ def serve_request_circuit(i: int, max_log2_ops: float = 43.0):
         sl = greedy_slice(net, p.pairs, n_sliced=2 * j) if j else ()
         big, ops = path_cost(net, p.pairs, sl)
         n_sl = 4 ** j
-        if np.log2(max(ops, 1) * n_sl * 8) <= max_log2_ops or depth <= 4:
+        if math.log2(max(ops, 1) * n_sl * 8) <= max_log2_ops or depth <= 4:   # exact for ints past 2^63
             return circ, net, Path(p.pairs, sl), prec
         depth -= 1
 
