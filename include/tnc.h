@@ -341,6 +341,23 @@ tnc_status tnc_serve_start(tnc_ctx ctx, int32_t max_inflight, int32_t queue_cap)
  * and the number of heavy requests that may run at once (>= 1).  Applies to
  * admissions from now on; TNC_E_ARG if the context is not serving. */
 tnc_status tnc_serve_set_heavy(tnc_ctx ctx, double heavy_flops, int32_t heavy_slots);
+/* Fusion of light requests with one structure (an extension): requests
+ * below the heavy threshold whose plans have the same network shape, path,
+ * slicing, precision, GEMM form, chunking and tile variants, over slice
+ * ranges that split into the same chunks (e.g. amplitudes of several
+ * circuits of one geometry and depth, or slice ranges of one sliced
+ * network), are admitted together as one job of up to max_requests
+ * (default 8; 1 disables fusion) and run in lockstep: every MFMA step of
+ * the job is one grouped launch over the requests' GEMMs of that step (one
+ * persistent kernel whose workgroups loop over the tiles of all of them).
+ * Each request's result is bitwise the one it gets alone: its every output
+ * element is computed by the same tile code in the same order.  Applies to
+ * admissions from now on; TNC_E_ARG if the context is not serving or
+ * max_requests is outside 1..64. */
+tnc_status tnc_serve_set_fusion(tnc_ctx ctx, int32_t max_requests);
+/* Counters since tnc_serve_start: jobs run (a fused job or a batch of rows
+ * counts once), fused jobs, and requests that ran in fused jobs. */
+tnc_status tnc_serve_get_stats(tnc_ctx ctx, int64_t* jobs, int64_t* fused_jobs, int64_t* fused_requests);
 tnc_status tnc_serve_stop(tnc_ctx ctx);
 tnc_status tnc_submit(tnc_ctx ctx, tnc_plan plan, int64_t first_slice, int64_t n_slices,
                       double* out_c128, tnc_req* id);

@@ -303,6 +303,20 @@ void run_plan(Plan& plan, const RunArgs& a);
 // chunk, the current chunk's leaf bases, every chunk's leaf bases).
 int64_t run_workspace_bytes(Plan& plan, int64_t first, int64_t count);
 void drain_profile(Plan& plan);
+// Lockstep execution of runs of plans with one structure (fused serving
+// jobs): structure_key identifies plans and slice ranges that can run
+// together; lockstep_table_entries is the grouped-launch table size of n
+// such runs; run_lockstep needs `cap` >= that many entries in pinned host
+// memory (`host`) and device memory (`dev`), and every run's RunArgs on
+// `stream`.
+struct LockstepRun {
+  Plan* plan = nullptr;
+  RunArgs a;
+};
+std::string structure_key(Plan& plan, int64_t first, int64_t count);
+int64_t lockstep_table_entries(Plan& plan, int64_t first, int64_t count, int n_runs);
+void run_lockstep(std::vector<LockstepRun>& runs, GroupedEntry* host, GroupedEntry* dev, int64_t cap,
+                  hipStream_t stream);
 std::vector<std::pair<int, int64_t>> decompose(const Plan& plan, int64_t first, int64_t count);
 
 }  // namespace tnc

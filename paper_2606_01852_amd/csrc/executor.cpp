@@ -5,6 +5,7 @@
 // planned schedule; slicing, Sec. II-C, becomes a batch dimension).
 #include <algorithm>
 #include <cstring>
+#include <map>
 
 #include "core.hpp"
 
@@ -238,72 +239,108 @@ namespace {
 
 // Enqueue one chunk: leaf permutations, one GEMM per step, the FP64
 // reduction of the root.  `bases` points at this chunk's leaf base offsets.
-void enqueue_chunk(Plan& plan, ChunkPlan& cp, const RunArgs& a, const int64_t* bases, bool overwrite,
-                   hipStream_t stream, Launcher& L) {
+// The launches of one chunk of one run, one piece at a time: a leaf's
+// preparation, a step's GEMM, a level's grouped gathers and small GEMMs,
+// the FP64 reduction of the root.  `bases` points at the chunk's leaf base
+// offsets on the device.
+struct ChunkOps {
+  Plan& plan;
+  ChunkPlan& cp;
+  const RunArgs& a;
+  const int64_t* bases;
+  hipStream_t stream;
+  Launcher& L;
   Net& net = *plan.net;
   const int n = net.n_tensors;
   const int ns = static_cast<int>(plan.pairs.size());
   const int t_prep = ns, t_red = ns + 1, t_group = ns + 2;
   const char* blob = static_cast<const char*>(cp.blob.ptr);
-  auto ptr = [&](int id) -> float2* {
+  const Form form = plan.form == TNC_GEMM_3M ? Form::M3 : Form::M4;
+  const Prec prec = plan.prec == TNC_PREC_BF16X3 ? Prec::BF16X3 : Prec::C64;
+
+  float2* ptr(int id) const {
     if (id < n && cp.leaf[id].direct) return static_cast<float2*>(net.leaf[id].ptr);
     if (id < n && cp.leaf[id].cached) return cached_leaf(cp, id);
     if (id == cp.root_id && a.direct_out) return a.direct_out;
     return reinterpret_cast<float2*>(a.arena + cp.buf_off[cp.tensor_buf[id]]);
-  };
-  auto prep = [&](int t) {
+  }
+  void prep(int t) {
     const LeafPrep& lp = cp.leaf[t];
     float2* out = ptr(t);
     const int64_t* bd = lp.base_slot >= 0 ? bases + lp.base_slot : nullptr;
     L.run(t_prep, stream, [&] { return launch_leaf_prep(net, cp, t, out, bd, stream); });
-  };
-  if (ns == 0 && !cp.leaf[0].direct) prep(0);
-  const Form form = plan.form == TNC_GEMM_3M ? Form::M3 : Form::M4;
-  const Prec prec = plan.prec == TNC_PREC_BF16X3 ? Prec::BF16X3 : Prec::C64;
-  auto step = [&](int s) {
-    StepPlan& sp = cp.steps[s];
+  }
+  int variant(const StepPlan& sp) const { return net.ctx->gemm_variant >= 0 ? net.ctx->gemm_variant : sp.variant; }
+  // The step's launch descriptor with this run's pointers (the split-K
+  // partials go to the step's arena scratch buffer).
+  GemmDesc desc(int s) const {
+    const StepPlan& sp = cp.steps[s];
     GemmDesc d = sp.desc;
     d.A = ptr(sp.la);
     d.B = ptr(sp.lb);
+    d.C = sp.split > 1 ? reinterpret_cast<float2*>(a.arena + cp.buf_off[sp.scratch_buf]) : ptr(sp.C);
+    return d;
+  }
+  void splitk(int s) {
+    const StepPlan& sp = cp.steps[s];
+    if (sp.split <= 1) return;
+    const GemmDesc d = desc(s);
     float2* c = ptr(sp.C);
-    d.C = sp.split > 1 ? reinterpret_cast<float2*>(a.arena + cp.buf_off[sp.scratch_buf]) : c;
-    const int variant = net.ctx->gemm_variant >= 0 ? net.ctx->gemm_variant : sp.variant;
-    L.run(s, stream, [&] { return launch_gemm(d, sp.kind, variant, form, prec, stream); });
-    if (sp.split > 1)
-      L.run(s, stream, [&] {
-        return launch_splitk_reduce(d.C, c, sp.h, sp.lm, sp.ln, sp.split, sp.dev_offM, sp.dev_offN, stream);
-      });
-  };
+    L.run(s, stream, [&] {
+      return launch_splitk_reduce(d.C, c, sp.h, sp.lm, sp.ln, sp.split, sp.dev_offM, sp.dev_offN, stream);
+    });
+  }
+  void step(int s) {
+    const StepPlan& sp = cp.steps[s];
+    const GemmDesc d = desc(s);
+    L.run(s, stream, [&] { return launch_gemm(d, sp.kind, variant(sp), form, prec, stream); });
+    splitk(s);
+  }
+  void level_gathers(const LevelPlan& lv) {
+    if (lv.group_leaves.empty()) return;
+    L.run(t_prep, stream, [&] {
+      return launch_group_gather(reinterpret_cast<const GroupGather*>(blob + lv.off_gather),
+                                 reinterpret_cast<const int64_t*>(blob + lv.off_gather_prefix),
+                                 static_cast<int>(lv.group_leaves.size()), lv.gather_total, a.arena, bases, stream);
+    });
+  }
+  void level_small_gemms(const LevelPlan& lv) {
+    if (lv.group_steps.empty()) return;
+    L.run(t_group, stream, [&] {
+      return launch_group_gemm(reinterpret_cast<const GroupGemm*>(blob + lv.off_gemm),
+                               reinterpret_cast<const int64_t*>(blob + lv.off_gemm_prefix),
+                               static_cast<int>(lv.group_steps.size()), lv.gemm_total, a.arena, prec, stream);
+    });
+  }
+  void reduce(bool overwrite) {
+    if (a.direct_out) return;
+    const float2* root = ptr(cp.root_id);
+    L.run(t_red, stream, [&] { return launch_reduce_fp64(root, a.acc, cp.hs, cp.R, overwrite, stream); });
+  }
+};
+
+// Enqueue one chunk: leaf permutations, one GEMM per step, the FP64
+// reduction of the root.  `bases` points at this chunk's leaf base offsets.
+void enqueue_chunk(Plan& plan, ChunkPlan& cp, const RunArgs& a, const int64_t* bases, bool overwrite,
+                   hipStream_t stream, Launcher& L) {
+  ChunkOps op{plan, cp, a, bases, stream, L};
+  if (op.ns == 0 && !cp.leaf[0].direct) op.prep(0);
   if (cp.grouped) {
     // level by level: the level's plain leaf gathers in one launch, its small
     // GEMMs in another, everything else one launch each
     for (const LevelPlan& lv : cp.levels) {
-      if (!lv.group_leaves.empty())
-        L.run(t_prep, stream, [&] {
-          return launch_group_gather(reinterpret_cast<const GroupGather*>(blob + lv.off_gather),
-                                     reinterpret_cast<const int64_t*>(blob + lv.off_gather_prefix),
-                                     static_cast<int>(lv.group_leaves.size()), lv.gather_total, a.arena, bases,
-                                     stream);
-        });
-      for (int t : lv.single_leaves) prep(t);
-      if (!lv.group_steps.empty())
-        L.run(t_group, stream, [&] {
-          return launch_group_gemm(reinterpret_cast<const GroupGemm*>(blob + lv.off_gemm),
-                                   reinterpret_cast<const int64_t*>(blob + lv.off_gemm_prefix),
-                                   static_cast<int>(lv.group_steps.size()), lv.gemm_total, a.arena, prec, stream);
-        });
-      for (int s : lv.single_steps) step(s);
+      op.level_gathers(lv);
+      for (int t : lv.single_leaves) op.prep(t);
+      op.level_small_gemms(lv);
+      for (int s : lv.single_steps) op.step(s);
     }
   } else {
-    for (int s = 0; s < ns; ++s) {
-      for (int t : cp.steps[s].preps) prep(t);
-      step(s);
+    for (int s = 0; s < op.ns; ++s) {
+      for (int t : cp.steps[s].preps) op.prep(t);
+      op.step(s);
     }
   }
-  if (!a.direct_out) {
-    const float2* root = ptr(cp.root_id);
-    L.run(t_red, stream, [&] { return launch_reduce_fp64(root, a.acc, cp.hs, cp.R, overwrite, stream); });
-  }
+  op.reduce(overwrite);
 }
 
 // The captured graph of one chunk plan for one set of buffers (created on
@@ -380,10 +417,23 @@ int64_t run_workspace_bytes(Plan& plan, int64_t first, int64_t count) {
   return align_up(peak) + align_up(slots * 8) + align_up(static_cast<int64_t>(chunks.size()) * slots * 8);
 }
 
-void run_plan(Plan& plan, const RunArgs& a) {
+namespace {
+
+// The chunks of a run, every chunk plan ready on the device, and the
+// per-chunk leaf base offsets uploaded into the run's workspace
+// ([intermediates | current chunk's bases | all chunks' bases]).
+struct RunBases {
+  std::vector<std::pair<int, int64_t>> chunks;
+  int slots = 1;
+  int64_t* cur_dev = nullptr;
+  int64_t* bases_dev = nullptr;
+};
+
+RunBases prepare_run(Plan& plan, const RunArgs& a) {
   Net& net = *plan.net;
-  const int ns = static_cast<int>(plan.pairs.size());
-  const auto chunks = decompose(plan, a.first, a.count);
+  RunBases rb;
+  rb.chunks = decompose(plan, a.first, a.count);
+  const auto& chunks = rb.chunks;
   if (chunks.empty()) fail(TNC_E_ARG, "empty slice range");
   // per-chunk base offsets of leaves that carry fixed sliced labels
   int slots = 1;
@@ -409,36 +459,45 @@ void run_plan(Plan& plan, const RunArgs& a) {
       bases[c * slots + lp.base_slot] = off;
     }
   }
-  // workspace: [intermediates | current chunk's bases | all chunks' bases]
   const int64_t cur_off = align_up(peak);
   const int64_t bases_off = cur_off + align_up(slots * 8);
   const size_t need = static_cast<size_t>(bases_off) + bases.size() * sizeof(int64_t);
   if (need > a.arena_bytes)
     fail(TNC_E_NOMEM, "run needs " + std::to_string(need) + " arena bytes, have " + std::to_string(a.arena_bytes));
-  int64_t* cur_dev = reinterpret_cast<int64_t*>(a.arena + cur_off);
-  int64_t* bases_dev = reinterpret_cast<int64_t*>(a.arena + bases_off);
+  rb.slots = slots;
+  rb.cur_dev = reinterpret_cast<int64_t*>(a.arena + cur_off);
+  rb.bases_dev = reinterpret_cast<int64_t*>(a.arena + bases_off);
   // leaves with fixed sliced labels read their per-chunk offsets on the
-  // device; without any, nothing needs uploading (or copying per chunk)
+  // device; without any, nothing needs uploading (or copying per chunk).
+  // The host vector is pageable: the runtime copies it before returning.
   bool any_bases = false;
   for (auto& c : chunks) any_bases |= plan.chunks[c.first]->n_base_slots > 0;
   if (any_bases)
-    check_hip(hipMemcpyAsync(bases_dev, bases.data(), bases.size() * sizeof(int64_t), hipMemcpyHostToDevice,
+    check_hip(hipMemcpyAsync(rb.bases_dev, bases.data(), bases.size() * sizeof(int64_t), hipMemcpyHostToDevice,
                              a.stream),
               "upload chunk bases");
+  return rb;
+}
 
+}  // namespace
+
+void run_plan(Plan& plan, const RunArgs& a) {
+  const int ns = static_cast<int>(plan.pairs.size());
+  const RunBases rb = prepare_run(plan, a);
+  const auto& chunks = rb.chunks;
   std::vector<std::pair<std::pair<hipEvent_t, hipEvent_t>, int>> ev;
   Launcher L{plan, plan.profile && !plan.graph ? &ev : nullptr};
   for (size_t c = 0; c < chunks.size(); ++c) {
     ChunkPlan& cp = ready(plan, chunks[c].first, a.stream);
-    hipGraphExec_t exec = plan.graph ? chunk_graph(plan, cp, a, cur_dev, a.fresh_acc && c == 0) : nullptr;
+    hipGraphExec_t exec = plan.graph ? chunk_graph(plan, cp, a, rb.cur_dev, a.fresh_acc && c == 0) : nullptr;
     if (exec) {
       if (cp.n_base_slots)
-        check_hip(hipMemcpyAsync(cur_dev, bases_dev + c * slots, slots * sizeof(int64_t), hipMemcpyDeviceToDevice,
-                                 a.stream),
+        check_hip(hipMemcpyAsync(rb.cur_dev, rb.bases_dev + c * rb.slots, rb.slots * sizeof(int64_t),
+                                 hipMemcpyDeviceToDevice, a.stream),
                   "chunk bases");
       check_hip(hipGraphLaunch(exec, a.stream), "graph launch");
     } else {
-      enqueue_chunk(plan, cp, a, bases_dev + c * slots, a.fresh_acc && c == 0, a.stream, L);
+      enqueue_chunk(plan, cp, a, rb.bases_dev + c * rb.slots, a.fresh_acc && c == 0, a.stream, L);
     }
   }
   if (!ev.empty()) {
@@ -447,6 +506,159 @@ void run_plan(Plan& plan, const RunArgs& a) {
     for (auto& e : ev) plan.pending.push_back(e);
     // long profiled sessions: fold what has finished without waiting
     if (plan.pending.size() > 16384) fold_events(plan, false);
+  }
+}
+
+// ------------------------------------------------------------------ lockstep
+// Several runs of plans with one structure (the same path, shapes, chunking
+// and tile variants, see structure_key) over slice ranges with the same
+// chunk sequence, executed together on one stream: chunk by chunk and level
+// by level, every run's leaf preparations and small GEMMs are launched as
+// in a run of its own, and every MFMA step goes out as one grouped launch
+// over the runs' GEMMs of that step.  Each output element is computed by the
+// same tile code in the same order as alone, so every run's result is
+// bitwise its result alone.
+
+std::string structure_key(Plan& plan, int64_t first, int64_t count) {
+  std::string k;
+  auto put = [&](int64_t v) { k.append(reinterpret_cast<const char*>(&v), sizeof v); };
+  const Net& net = *plan.net;
+  put(net.n_tensors);
+  for (const auto& lab : net.labels) {
+    put(static_cast<int64_t>(lab.size()));
+    for (int l : lab) put(l);
+  }
+  put(static_cast<int64_t>(net.extents.size()));
+  for (int64_t e : net.extents) put(e);
+  put(static_cast<int64_t>(net.open.size()));
+  for (int l : net.open) put(l);
+  for (const auto& pr : plan.pairs) put(pr[0] * int64_t{1 << 30} + pr[1]);
+  put(static_cast<int64_t>(plan.sliced.size()));
+  for (int l : plan.sliced) put(l);
+  put(plan.prec);
+  put(plan.form);
+  put(plan.grouping);
+  put(net.ctx->gemm_variant);
+  put(static_cast<int64_t>(plan.volatile_leaf.size()));
+  for (char v : plan.volatile_leaf) put(v);
+  const auto chunks = decompose(plan, first, count);
+  put(static_cast<int64_t>(chunks.size()));
+  std::vector<char> seen(plan.chunks.size(), 0);
+  for (auto& c : chunks) {
+    put(c.first);
+    if (seen[c.first]) continue;
+    seen[c.first] = 1;
+    const ChunkPlan& cp = plan.chunk(c.first);
+    for (const StepPlan& sp : cp.steps) {
+      put(static_cast<int64_t>(sp.kind));
+      put(sp.variant);
+      put(sp.split);
+    }
+  }
+  return k;
+}
+
+int64_t lockstep_table_entries(Plan& plan, int64_t first, int64_t count, int n_runs) {
+  const auto chunks = decompose(plan, first, count);
+  std::vector<char> seen(plan.chunks.size(), 0);
+  int64_t e = 0;
+  for (auto& c : chunks) {
+    if (seen[c.first]) continue;
+    seen[c.first] = 1;
+    for (const StepPlan& sp : plan.chunk(c.first).steps) e += sp.kind == GemmKernel::MFMA ? n_runs : 0;
+  }
+  return e;
+}
+
+void run_lockstep(std::vector<LockstepRun>& runs, GroupedEntry* host, GroupedEntry* dev, int64_t cap,
+                  hipStream_t stream) {
+  const int K = static_cast<int>(runs.size());
+  if (K < 1) return;
+  std::vector<RunBases> rb;
+  for (auto& r : runs) rb.push_back(prepare_run(*r.plan, r.a));
+  for (int r = 1; r < K; ++r) {
+    bool same = rb[r].chunks.size() == rb[0].chunks.size();
+    for (size_t c = 0; same && c < rb[0].chunks.size(); ++c) same = rb[r].chunks[c].first == rb[0].chunks[c].first;
+    if (!same) fail(TNC_E_ARG, "lockstep runs need the same chunk sequence");
+  }
+  Plan& p0 = *runs[0].plan;
+  const Form form = p0.form == TNC_GEMM_3M ? Form::M3 : Form::M4;
+  const Prec prec = p0.prec == TNC_PREC_BF16X3 ? Prec::BF16X3 : Prec::C64;
+  Launcher none{p0, nullptr};
+  auto ops_of = [&](size_t c) {
+    std::vector<std::unique_ptr<ChunkOps>> ops;
+    const int j = rb[0].chunks[c].first;
+    for (int r = 0; r < K; ++r)
+      ops.emplace_back(new ChunkOps{*runs[r].plan, *runs[r].plan->chunks[j], runs[r].a,
+                                    rb[r].bases_dev + c * rb[r].slots, stream, none});
+    return ops;
+  };
+  // grouped tables of every MFMA step of every chunk plan used, uploaded once
+  std::map<std::pair<int, int>, std::pair<int64_t, int64_t>> grouped;  // (j, step) -> (first entry, tiles)
+  int64_t used = 0;
+  for (size_t c = 0; c < rb[0].chunks.size(); ++c) {
+    const int j = rb[0].chunks[c].first;
+    const ChunkPlan& cp0 = *p0.chunks[j];
+    if (grouped.count({j, -1})) continue;
+    grouped[{j, -1}] = {0, 0};
+    auto ops = ops_of(c);
+    for (int s = 0; s < static_cast<int>(cp0.steps.size()); ++s) {
+      if (cp0.steps[s].kind != GemmKernel::MFMA) continue;
+      const int v = ops[0]->variant(cp0.steps[s]);
+      bool ok = used + K <= cap;
+      for (int r = 0; ok && r < K; ++r) {
+        const StepPlan& sp = ops[r]->cp.steps[s];
+        ok = sp.kind == GemmKernel::MFMA && ops[r]->variant(sp) == v;
+      }
+      if (!ok) continue;
+      for (int r = 0; r < K; ++r) host[used + r].d = ops[r]->desc(s);
+      const int64_t total = grouped_layout(host + used, K, v);
+      if (total <= 0) continue;
+      grouped[{j, s}] = {used, total};
+      used += K;
+    }
+  }
+  if (used)
+    check_hip(hipMemcpyAsync(dev, host, static_cast<size_t>(used) * sizeof(GroupedEntry), hipMemcpyHostToDevice,
+                             stream),
+              "upload grouped GEMM tables");
+  for (size_t c = 0; c < rb[0].chunks.size(); ++c) {
+    const int j = rb[0].chunks[c].first;
+    auto ops = ops_of(c);
+    const ChunkPlan& cp0 = *p0.chunks[j];
+    auto gemm = [&](int s) {
+      auto it = grouped.find({j, s});
+      if (it == grouped.end()) {
+        for (auto& op : ops) op->step(s);
+        return;
+      }
+      const int v = ops[0]->variant(cp0.steps[s]);
+      check_hip(launch_gemm_grouped(dev + it->second.first, K, it->second.second, v, form, prec, stream),
+                "grouped GEMM launch");
+      for (auto& op : ops) op->splitk(s);
+    };
+    const int ns = static_cast<int>(cp0.steps.size());
+    if (ns == 0)
+      for (auto& op : ops)
+        if (!op->cp.leaf[0].direct) op->prep(0);
+    if (cp0.grouped) {
+      for (size_t li = 0; li < cp0.levels.size(); ++li) {
+        for (auto& op : ops) {
+          const LevelPlan& lv = op->cp.levels[li];
+          op->level_gathers(lv);
+          for (int t : lv.single_leaves) op->prep(t);
+          op->level_small_gemms(lv);
+        }
+        for (int s : cp0.levels[li].single_steps) gemm(s);
+      }
+    } else {
+      for (int s = 0; s < ns; ++s) {
+        for (auto& op : ops)
+          for (int t : op->cp.steps[s].preps) op->prep(t);
+        gemm(s);
+      }
+    }
+    for (int r = 0; r < K; ++r) ops[r]->reduce(runs[r].a.fresh_acc && c == 0);
   }
 }
 

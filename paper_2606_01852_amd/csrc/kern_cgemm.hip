@@ -71,11 +71,10 @@ struct TileCoord {
   int64_t b, row0, col0;
 };
 
+// Tile of workgroup index `wg` (already in XCD order) within one GEMM:
+// batch entry, then groups of GROUP_M M-tiles swept along N.
 template <int BM, int BNC>
-__device__ __forceinline__ TileCoord map_tile(int64_t tiles_m, int64_t tiles_n, int64_t total) {
-  int64_t wg = blockIdx.x;
-  const int64_t per = total >> 3;
-  if (wg < (per << 3)) wg = (wg & 7) * per + (wg >> 3);
+__device__ __forceinline__ TileCoord tile_of(int64_t wg, int64_t tiles_m, int64_t tiles_n) {
   const int64_t tpb = tiles_m * tiles_n;
   const int64_t b = wg / tpb;
   const int64_t r = wg - b * tpb;
@@ -90,6 +89,14 @@ __device__ __forceinline__ TileCoord map_tile(int64_t tiles_m, int64_t tiles_n, 
   tc.row0 = (first_m + rr % gsz) * BM;
   tc.col0 = (rr / gsz) * BNC;
   return tc;
+}
+
+template <int BM, int BNC>
+__device__ __forceinline__ TileCoord map_tile(int64_t tiles_m, int64_t tiles_n, int64_t total) {
+  int64_t wg = blockIdx.x;
+  const int64_t per = total >> 3;
+  if (wg < (per << 3)) wg = (wg & 7) * per + (wg >> 3);
+  return tile_of<BM, BNC>(wg, tiles_m, tiles_n);
 }
 
 // Global -> register staging of one K stage (VW complex per load).  With
@@ -711,6 +718,43 @@ __global__ __launch_bounds__(64 * WM * WN, (WM * WN <= 4) ? 2 : 1) void cgemm_mf
   ops.store(d, PERM, tc, wm, wn, lane);
 }
 
+// Persistent grouped form: workgroups loop over the tiles of every entry of
+// the table.  Tiles are dealt to the 8 XCDs in contiguous ranges (tiles of
+// one entry stay on few XCDs, whose L2 they share) and each workgroup of an
+// XCD takes every nb-th tile of its range.  The tile's work is the
+// single-GEMM kernel's, line for line.
+template <template <int, int, int> class OpsT, int WM, int WN>
+__global__ __launch_bounds__(64 * WM * WN, (WM * WN <= 4) ? 2 : 1) void cgemm_mfma_grouped(
+    const GroupedEntry* __restrict__ tab, int n, int64_t total) {
+  using S = Shape<WM, WN, OpsT<WM, WN, 2>::kPW>;
+  extern __shared__ __attribute__((aligned(16))) char lds[];
+  const int tid = threadIdx.x;
+  const int lane = tid & 63, wave = tid >> 6;
+  const int wm = wave / WN, wn = wave % WN;
+  const int64_t per = (total + 7) >> 3;  // tiles per XCD
+  const int64_t xcd = blockIdx.x & 7, nb = gridDim.x >> 3;
+  for (int64_t q = blockIdx.x >> 3; q < per; q += nb) {
+    const int64_t t = xcd * per + q;
+    if (t >= total) break;
+    int e = 0;
+    while (e + 1 < n && tab[e + 1].tile0 <= t) ++e;
+    const GemmDesc& d = tab[e].d;
+    const TileCoord tc = tile_of<S::BM, S::BNC>(t - tab[e].tile0, tab[e].tiles_m, tab[e].tiles_n);
+    int64_t oa, ob;
+    batch_offsets(d, tc.b, oa, ob);
+    const float2* __restrict__ A = d.A + oa;
+    const float2* __restrict__ B = d.B + ob;
+    OpsT<WM, WN, 2> ops;
+    ops.init();
+    const bool interior = tc.row0 + S::BM <= d.m && tc.col0 + S::BNC <= d.n && d.k % BKC == 0;
+    if (interior)
+      main_loop<WM, WN, 2, false>(d, A, B, tc, lds, ops, tid, wm, wn, lane);
+    else
+      main_loop<WM, WN, 2, true>(d, A, B, tc, lds, ops, tid, wm, wn, lane);
+    ops.store(d, d.offM != nullptr, tc, wm, wn, lane);
+  }
+}
+
 // LDS above 64 KiB must be allowed per kernel, once per device (done for
 // every instance when a context is created, so that no first launch inside
 // a graph capture has to do it).
@@ -745,11 +789,58 @@ hipError_t launch_one(const GemmDesc& d, size_t lds, hipStream_t s) {
 }
 
 template <template <int, int, int> class OpsT, int WM, int WN>
+hipError_t ensure_lds_grouped(size_t lds) {
+  static std::atomic<uint64_t> attr_set{0};
+  if (lds <= 65536) return hipSuccess;
+  int dev = 0;
+  const hipError_t ge = hipGetDevice(&dev);
+  if (ge != hipSuccess) return ge;
+  const uint64_t bit = uint64_t{1} << (dev & 63);
+  if (attr_set.load(std::memory_order_acquire) & bit) return hipSuccess;
+  const hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(cgemm_mfma_grouped<OpsT, WM, WN>),
+                                           hipFuncAttributeMaxDynamicSharedMemorySize, static_cast<int>(lds));
+  if (e == hipSuccess) attr_set.fetch_or(bit, std::memory_order_acq_rel);
+  return e;
+}
+
+template <template <int, int, int> class OpsT, int WM, int WN>
 void prepare_shape(bool bf16) {
   using S = Shape<WM, WN, OpsT<WM, WN, 2>::kPW>;
   const size_t lds = bf16 ? S::lds_bf16 : S::lds_f32;
   (void)ensure_lds<OpsT, WM, WN, 2, false>(lds);
   (void)ensure_lds<OpsT, WM, WN, 2, true>(lds);
+  (void)ensure_lds_grouped<OpsT, WM, WN>(lds);
+}
+
+// Persistent grid: a multiple of 8 (one range of tiles per XCD), at most
+// two workgroups per compute unit, never more than the tiles.
+template <template <int, int, int> class OpsT, int WM, int WN>
+hipError_t launch_grouped_shape(const GroupedEntry* tab, int n, int64_t total, bool bf16, hipStream_t s) {
+  using S = Shape<WM, WN, OpsT<WM, WN, 2>::kPW>;
+  const size_t lds = bf16 ? S::lds_bf16 : S::lds_f32;
+  const hipError_t e = ensure_lds_grouped<OpsT, WM, WN>(lds);
+  if (e != hipSuccess) return e;
+  int64_t grid = (total + 7) / 8 * 8;
+  if (grid > 512) grid = 512;
+  hipLaunchKernelGGL((cgemm_mfma_grouped<OpsT, WM, WN>), dim3(static_cast<unsigned>(grid)), dim3(S::NT), lds, s, tab,
+                     n, total);
+  return hipGetLastError();
+}
+
+template <template <int, int, int> class OpsT>
+hipError_t launch_grouped_variant(const GroupedEntry* tab, int n, int64_t total, int variant, bool bf16,
+                                  hipStream_t s) {
+  if (bf16 && variant == 3) return launch_grouped_shape<OpsBF16x3W, 4, 2>(tab, n, total, true, s);
+  switch (variant) {
+    case 0: return launch_grouped_shape<OpsT, 2, 2>(tab, n, total, bf16, s);
+    case 1: return launch_grouped_shape<OpsT, 4, 2>(tab, n, total, bf16, s);
+    case 2: return launch_grouped_shape<OpsT, 2, 4>(tab, n, total, bf16, s);
+    case 3: return launch_grouped_shape<OpsT, 4, 4>(tab, n, total, bf16, s);
+    case 4: return launch_grouped_shape<OpsT, 1, 2>(tab, n, total, bf16, s);
+    case 5: return launch_grouped_shape<OpsT, 2, 1>(tab, n, total, bf16, s);
+    case 6: return launch_grouped_shape<OpsT, 1, 1>(tab, n, total, bf16, s);
+    default: return hipErrorInvalidValue;
+  }
 }
 
 template <template <int, int, int> class OpsT>
@@ -810,6 +901,29 @@ void gemm_variant_tile(int variant, int* bm, int* bnc) {
   if (variant < 0 || variant >= kGemmVariants) variant = 0;
   *bm = 64 * wm[variant];
   *bnc = 32 * wn[variant];
+}
+
+int64_t grouped_layout(GroupedEntry* e, int n, int variant) {
+  int bm = 0, bnc = 0;
+  gemm_variant_tile(variant, &bm, &bnc);
+  int64_t total = 0;
+  for (int i = 0; i < n; ++i) {
+    const GemmDesc& d = e[i].d;
+    if (d.h <= 0 || d.m <= 0 || d.n <= 0 || d.k <= 0 || (d.k | row_stride(d)) % 2 != 0) return 0;
+    e[i].tiles_m = (d.m + bm - 1) / bm;
+    e[i].tiles_n = (d.n + bnc - 1) / bnc;
+    e[i].tile0 = total;
+    total += e[i].tiles_m * e[i].tiles_n * d.h;
+  }
+  return total;
+}
+
+hipError_t launch_gemm_grouped(const GroupedEntry* dev, int n, int64_t total, int variant, Form form, Prec prec,
+                               hipStream_t s) {
+  if (n <= 0 || total <= 0) return hipSuccess;
+  if (prec == Prec::BF16X3) return launch_grouped_variant<OpsBF16x3>(dev, n, total, variant, true, s);
+  if (form == Form::M3) return launch_grouped_variant<Ops3M>(dev, n, total, variant, false, s);
+  return launch_grouped_variant<Ops4M>(dev, n, total, variant, false, s);
 }
 
 hipError_t launch_gemm(const GemmDesc& d, GemmKernel kind, int variant, Form form, Prec prec, hipStream_t s) {

@@ -107,6 +107,24 @@ void gemm_variant_tile(int variant, int* bm, int* bnc);
 // effort; launches do it lazily as well).
 void prepare_gemm_kernels();
 hipError_t launch_gemm(const GemmDesc& d, GemmKernel kind, int variant, Form form, Prec prec, hipStream_t s);
+// Grouped MFMA launch: several GEMMs (any shapes, pointers, batch strides
+// and store tables) that share one tile variant, precision and form, run by
+// one persistent launch whose workgroups loop over the tiles of all of them.
+// Every tile is computed exactly as the single-GEMM kernel of that variant
+// computes it, so each result is bitwise the same as a launch of its own.
+// Entries need even k and row stride (16-byte operand loads).
+struct GroupedEntry {
+  GemmDesc d;
+  int64_t tiles_m, tiles_n;   // tile grid of one batch entry
+  int64_t tile0;              // first tile of this entry in the launch
+};
+// Fill tiles_m, tiles_n and tile0 of e[0..n) for `variant`; returns the
+// launch's total tiles (0 when an entry cannot run grouped: odd k or row
+// stride).
+int64_t grouped_layout(GroupedEntry* e, int n, int variant);
+// `dev` is the device copy of the n entries laid out by grouped_layout.
+hipError_t launch_gemm_grouped(const GroupedEntry* dev, int n, int64_t total, int variant, Form form, Prec prec,
+                               hipStream_t s);
 hipError_t launch_gemm_valu(const GemmDesc& d, GemmKernel kind, Prec prec, hipStream_t s);
 // Split-K epilogue: C[b, i, j] = sum_{p < S} P[((b * S + p) * m + i) * n + j],
 // p ascending, stored at b * m * n + (offM ? offM[i] + offN[j] : i * n + j).

@@ -22,6 +22,14 @@
 // plan runs once, so the same-shape steps of those requests share each
 // launch.  A batcher runs one job at a time (its leaves hold one batch).
 //
+// Light requests whose plans have one structure (the same network shape,
+// path, slicing, precision, chunking and tile variants: e.g. amplitudes of
+// several circuits of one geometry, or slice ranges of one network) are
+// fused: a worker that admits such a request also admits up to
+// fuse_max - 1 queued requests with the same structure key, and runs them
+// in lockstep, every MFMA step as one grouped launch over all of them.  Each
+// result is bitwise the one the request gets alone.
+//
 // On a host-only context the server admits and queues exactly as it would
 // on a device (admission by planned arena bytes, the heavy lane, batcher
 // tokens) but executes nothing: every request completes with
@@ -106,6 +114,9 @@ struct Request {
   std::shared_ptr<Batcher> batcher;  // row request (or a batcher's token): its batcher
   bool token = false;                // stands for the batcher's waiting rows in the queue
   std::vector<float2> row;           // row values of the listed leaves (complex64)
+  std::string key;                   // structure key (fusable light request), or empty
+  int64_t table_entries = 0;         // grouped-launch table entries of one run
+  int64_t table_off = -1, table_bytes = 0;  // a fused job's table (first request of the job)
   Clock::time_point t_submit, t_done;
   bool done = false;
   tnc_status status = TNC_OK;
@@ -126,6 +137,10 @@ struct Server {
   std::vector<size_t> pinned_bytes;
   std::vector<void*> pinned_in;         // per slot: pinned staging of batch rows
   std::vector<size_t> pinned_in_bytes;
+  std::vector<void*> pinned_tab;        // per slot: pinned staging of grouped-launch tables
+  std::vector<size_t> pinned_tab_bytes;
+  int fuse_max = 8;                     // requests per fused job (1: no fusion)
+  int64_t n_jobs = 0, n_fused_jobs = 0, n_fused_requests = 0;
   ArenaAllocator arena;
   bool stop = false;
   uint64_t next_id = 1;
@@ -163,6 +178,7 @@ struct Server {
     }
     for (void* p : pinned) pinned_free(p);
     for (void* p : pinned_in) pinned_free(p);
+    for (void* p : pinned_tab) pinned_free(p);
   }
 
   void start() {
@@ -181,6 +197,8 @@ struct Server {
     pinned_bytes.assign(max_inflight, 0);
     pinned_in.assign(max_inflight, nullptr);
     pinned_in_bytes.assign(max_inflight, 0);
+    pinned_tab.assign(max_inflight, nullptr);
+    pinned_tab_bytes.assign(max_inflight, 0);
     for (int i = 0; i < max_inflight; ++i) workers.emplace_back([this, i] { loop(i); });
   }
 
@@ -220,9 +238,17 @@ struct Server {
         r.heavy_slot = r.heavy;
         if (r.heavy) ++heavy_inflight;
         ++inflight;
+        if (!r.key.empty() && fuse_max > 1) gather_fusable(job);
+        ++n_jobs;
+        if (job.size() > 1) {
+          ++n_fused_jobs;
+          n_fused_requests += static_cast<int64_t>(job.size());
+        }
       }
       if (job[0]->batcher)
         execute_rows(job, slot, stream);
+      else if (job.size() > 1)
+        execute_fused(job, slot, stream);
       else
         execute(*job[0], slot, stream);
       // plans of finished requests, released at the end of this iteration,
@@ -233,6 +259,10 @@ struct Server {
         std::lock_guard<std::mutex> g(mu);
         Request& r = *job[0];
         arena.release(r.arena_off, r.need);
+        if (!r.batcher)  // a fused job's other requests and its table
+          for (size_t q = 1; q < job.size(); ++q) arena.release(job[q]->arena_off, job[q]->need);
+        if (r.table_off >= 0) arena.release(r.table_off, r.table_bytes);
+        r.table_off = -1;
         if (r.heavy_slot) --heavy_inflight;
         --inflight;
         if (r.batcher) {
@@ -257,6 +287,37 @@ struct Server {
       cv_work.notify_all();
       cv_done.notify_all();
     }
+  }
+
+  // A fused job (server mutex held): queued light requests with job[0]'s
+  // structure key join it while the arena has room for each of them and for
+  // the job's grouped-launch table; a request that does not fit stays queued.
+  void gather_fusable(std::vector<std::shared_ptr<Request>>& job) {
+    Request& r0 = *job[0];
+    for (auto it = queue.begin(); it != queue.end() && static_cast<int>(job.size()) < fuse_max;) {
+      Request& q = **it;
+      if (q.token || q.heavy || q.key != r0.key) {
+        ++it;
+        continue;
+      }
+      const int64_t off = arena.alloc(q.need);
+      if (off < 0) break;
+      q.arena_off = off;
+      job.push_back(*it);
+      it = queue.erase(it);
+    }
+    if (job.size() == 1) return;
+    r0.table_bytes = std::max<int64_t>(1, r0.table_entries * static_cast<int64_t>(job.size())) *
+                     static_cast<int64_t>(sizeof(GroupedEntry));
+    r0.table_off = arena.alloc(r0.table_bytes);
+    if (r0.table_off >= 0) return;
+    // no room for the table: the others go back to the front of the queue
+    for (size_t q = job.size() - 1; q >= 1; --q) {
+      arena.release(job[q]->arena_off, job[q]->need);
+      job[q]->arena_off = -1;
+      queue.push_front(job[q]);
+    }
+    job.resize(1);
   }
 
   // Queue a token for a batcher's waiting rows (server mutex held).
@@ -360,6 +421,75 @@ struct Server {
     }
   }
 
+  // Requests of one structure in lockstep (run_lockstep), every result
+  // staged through the slot's pinned buffer.
+  void execute_fused(std::vector<std::shared_ptr<Request>>& job, int slot, hipStream_t stream) {
+    if (ctx.host_only) {
+      for (auto& q : job) {
+        q->status = TNC_E_UNSUPPORTED;
+        q->err = kHostOnly;
+      }
+      return;
+    }
+    try {
+      const int K = static_cast<int>(job.size());
+      std::vector<LockstepRun> runs(K);
+      size_t res_total = 0;
+      for (int q = 0; q < K; ++q) {
+        Request& r = *job[q];
+        runs[q].plan = r.plan;
+        RunArgs& a = runs[q].a;
+        a.first = r.first;
+        a.count = r.count;
+        a.arena = ctx.arena + r.arena_off;
+        a.arena_bytes = static_cast<size_t>(r.work_bytes);
+        a.acc = reinterpret_cast<double2*>(ctx.arena + r.arena_off + r.acc_off);
+        a.stream = stream;
+        a.fresh_acc = true;
+        res_total += static_cast<size_t>(r.plan->chunks[0]->R) * 16;
+      }
+      Request& r0 = *job[0];
+      const int64_t cap = r0.table_bytes / static_cast<int64_t>(sizeof(GroupedEntry));
+      auto* host_tab = static_cast<GroupedEntry*>(
+          staging(pinned_tab, pinned_tab_bytes, slot, static_cast<size_t>(r0.table_bytes)));
+      auto* dev_tab = reinterpret_cast<GroupedEntry*>(ctx.arena + r0.table_off);
+      run_lockstep(runs, host_tab, dev_tab, cap, stream);
+      char* host = static_cast<char*>(staging(pinned, pinned_bytes, slot, res_total));
+      size_t off = 0;
+      for (int q = 0; q < K; ++q) {
+        const size_t b = static_cast<size_t>(job[q]->plan->chunks[0]->R) * 16;
+        check_hip(hipMemcpyAsync(host + off, runs[q].a.acc, b, hipMemcpyDeviceToHost, stream), "result copy");
+        off += b;
+      }
+      check_hip(hipStreamSynchronize(stream), "stream synchronize");
+      off = 0;
+      for (int q = 0; q < K; ++q) {
+        Request& r = *job[q];
+        const ChunkPlan& c0 = *r.plan->chunks[0];
+        const double* tmp = reinterpret_cast<const double*>(host + off);
+        if (c0.result_perm.empty()) {
+          std::memcpy(r.out, tmp, static_cast<size_t>(c0.R) * 16);
+        } else {
+          for (int64_t u = 0; u < c0.R; ++u) {
+            r.out[2 * u] = tmp[2 * c0.result_perm[u]];
+            r.out[2 * u + 1] = tmp[2 * c0.result_perm[u] + 1];
+          }
+        }
+        off += static_cast<size_t>(c0.R) * 16;
+      }
+    } catch (const Error& e) {
+      for (auto& q : job) {
+        q->status = e.code;
+        q->err = e.msg;
+      }
+    } catch (const std::exception& e) {
+      for (auto& q : job) {
+        q->status = TNC_E_DEVICE;
+        q->err = e.what();
+      }
+    }
+  }
+
   void execute(Request& r, int slot, hipStream_t stream) {
     if (ctx.host_only) {
       r.status = TNC_E_UNSUPPORTED;
@@ -432,6 +562,28 @@ tnc_status tnc_serve_set_heavy(tnc_ctx ctx, double heavy_flops, int32_t heavy_sl
   TNC_CATCH
 }
 
+tnc_status tnc_serve_set_fusion(tnc_ctx ctx, int32_t max_requests) {
+  TNC_TRY
+  if (!ctx || !ctx->c->server || max_requests < 1 || max_requests > 64)
+    fail(TNC_E_ARG, "bad arguments or server not started");
+  Server& s = *ctx->c->server;
+  std::lock_guard<std::mutex> g(s.mu);
+  s.fuse_max = max_requests;
+  TNC_CATCH
+}
+
+tnc_status tnc_serve_get_stats(tnc_ctx ctx, int64_t* jobs, int64_t* fused_jobs, int64_t* fused_requests) {
+  TNC_TRY
+  if (!ctx || !ctx->c->server || !jobs || !fused_jobs || !fused_requests)
+    fail(TNC_E_ARG, "bad arguments or server not started");
+  Server& s = *ctx->c->server;
+  std::lock_guard<std::mutex> g(s.mu);
+  *jobs = s.n_jobs;
+  *fused_jobs = s.n_fused_jobs;
+  *fused_requests = s.n_fused_requests;
+  TNC_CATCH
+}
+
 tnc_status tnc_serve_stop(tnc_ctx ctx) {
   TNC_TRY
   if (!ctx) fail(TNC_E_ARG, "ctx is NULL");
@@ -466,9 +618,21 @@ tnc_status tnc_submit(tnc_ctx ctx, tnc_plan plan, int64_t first_slice, int64_t n
       fail(TNC_E_NOMEM, "request needs " + std::to_string(r->need) + " arena bytes, the arena has " +
                             std::to_string(c.arena_bytes));
     {
+      bool fuse = false;
+      {
+        std::lock_guard<std::mutex> g(s->mu);
+        fuse = s->fuse_max > 1 && !(s->heavy_flops > 0 && r->flops >= s->heavy_flops);
+      }
+      if (fuse) {  // light request: may share grouped launches with others of its structure
+        r->key = structure_key(p, first_slice, n_slices);
+        r->table_entries = lockstep_table_entries(p, first_slice, n_slices, 1);
+      }
+    }
+    {
       std::lock_guard<std::mutex> g(s->mu);
       if (s->queue.size() >= s->queue_cap) fail(TNC_E_BUSY, "serving queue full");
       r->heavy = s->heavy_flops > 0 && r->flops >= s->heavy_flops;
+      if (r->heavy) r->key.clear();
       r->id = s->next_id++;
       r->t_submit = Clock::now();
       s->queue.push_back(r);

@@ -104,6 +104,8 @@ _SIGS = {
     "tnc_serve_start": (C.c_int, [_P, C.c_int32, C.c_int32]),
     "tnc_serve_stop": (C.c_int, [_P]),
     "tnc_serve_set_heavy": (C.c_int, [_P, C.c_double, C.c_int32]),
+    "tnc_serve_set_fusion": (C.c_int, [_P, C.c_int32]),
+    "tnc_serve_get_stats": (C.c_int, [_P, _I64P, _I64P, _I64P]),
     "tnc_submit": (C.c_int, [_P, _P, C.c_int64, C.c_int64, _DP, C.POINTER(C.c_uint64)]),
     "tnc_batcher_create": (C.c_int, [_P, C.c_int32, C.c_int32, _I32P, C.POINTER(_P)]),
     "tnc_batcher_destroy": (C.c_int, [_P]),
@@ -348,6 +350,17 @@ def tnc_serve_start(ctx: int, max_inflight: int, queue_cap: int) -> None:
 
 def tnc_serve_set_heavy(ctx: int, heavy_flops: float, heavy_slots: int = 1) -> None:
     _check(lib().tnc_serve_set_heavy(ctx, float(heavy_flops), int(heavy_slots)))
+
+
+def tnc_serve_set_fusion(ctx: int, max_requests: int) -> None:
+    _check(lib().tnc_serve_set_fusion(ctx, max_requests))
+
+
+def tnc_serve_get_stats(ctx: int):
+    """(jobs, fused jobs, requests run in fused jobs) since the server started."""
+    j, fj, fr = C.c_int64(), C.c_int64(), C.c_int64()
+    _check(lib().tnc_serve_get_stats(ctx, C.byref(j), C.byref(fj), C.byref(fr)))
+    return j.value, fj.value, fr.value
 
 
 def tnc_serve_stop(ctx: int) -> None:

@@ -340,6 +340,8 @@ void serve_exercise(const std::vector<NetFile>& files, int submitters) {
     expect(tnc_serve_start(ctx, 6, 1 << 14) == TNC_OK, "serve_start", F);
     expect(tnc_serve_start(ctx, 6, 16) == TNC_E_BUSY, "second server", F);
     expect(tnc_serve_set_heavy(ctx, round ? 1e6 : 0.0, 2) == TNC_OK, "heavy lane", F);
+    expect(tnc_serve_set_fusion(ctx, round ? 4 : 1) == TNC_OK, "fusion", F);
+    expect(tnc_serve_set_fusion(ctx, 0) == TNC_E_ARG, "fusion limit", F);
     tnc_plan p0 = es[0].plan;
     int32_t rank = 0;
     double out[2] = {0, 0};
@@ -407,6 +409,10 @@ void serve_exercise(const std::vector<NetFile>& files, int submitters) {
           e.batcher = nullptr;
           for (tnc_req id : ids) expect(tnc_wait(ctx, id, nullptr) == TNC_E_UNSUPPORTED, "late row completes", F);
         }
+    int64_t jobs = 0, fused_jobs = 0, fused_requests = 0;
+    expect(tnc_serve_get_stats(ctx, &jobs, &fused_jobs, &fused_requests) == TNC_OK && jobs > 0 &&
+               fused_requests >= 2 * fused_jobs,
+           "serving counters", F);
     expect(tnc_serve_stop(ctx) == TNC_OK, "serve_stop", F);
     expect(tnc_plan_set_max_chunk(p0, -1) == TNC_OK, "set_max_chunk after serving", F);
   }

@@ -573,3 +573,91 @@ def test_concurrent_submitters_and_waiters(served):
     tn_b.close()
     plan_ref.close()
     tn_ref.close()
+
+
+def _serve_each(ctx, items, fuse):
+    """Serve (plan, first, count) items with one slot; with `fuse`, a slow
+    request queued first lets the items queue up behind it, so that the
+    worker admits them together.  Returns the outputs and the server's
+    (jobs, fused jobs, fused requests)."""
+    tnc.tnc_serve_start(ctx.handle, 1, 1024)
+    tnc.tnc_serve_set_fusion(ctx.handle, 8 if fuse else 1)
+    blocker = None
+    if fuse:
+        circ = random_circuit(6, 6, 10, seed=8100)       # 1.5e12 FLOP: ~10 ms of work ahead of the items
+        net = circuit_network(circ)
+        path = greedy_path(net)
+        sl = greedy_slice(net, path.pairs, n_sliced=4)
+        btn = tnc.Network(ctx, net.labels, net.extents, net.open, net.c64().leaves)
+        bplan = tnc.Plan(btn, path.pairs, sl)
+        bout = np.zeros(1, dtype=np.complex128)
+        blocker = (btn, bplan, tnc.tnc_submit(ctx.handle, bplan.handle, 0, bplan.info.n_slices, bout))
+    outs = [np.zeros(p.info.n_result, dtype=np.complex128) for p, _, _ in items]
+    ids = [tnc.tnc_submit(ctx.handle, p.handle, f, c, o) for (p, f, c), o in zip(items, outs)]
+    if blocker:
+        tnc.tnc_wait(ctx.handle, blocker[2])
+    for rid in ids:
+        tnc.tnc_wait(ctx.handle, rid)
+    stats = tnc.tnc_serve_get_stats(ctx.handle)
+    tnc.tnc_serve_stop(ctx.handle)
+    if blocker:
+        blocker[1].close()
+        blocker[0].close()
+    return outs, stats
+
+
+@pytest.mark.parametrize("prec, form", [(tnc.PREC_C64, tnc.GEMM_4M), (tnc.PREC_C64, tnc.GEMM_3M),
+                                        (tnc.PREC_BF16X3, tnc.GEMM_4M)], ids=["4M", "3M", "bf16x3"])
+def test_fused_requests_are_bitwise_alone(served, prec, form):
+    """Light requests of one structure run as one fused job, every MFMA step
+    a grouped launch over all of them: (i) six 5x5-grid circuits of depth 10
+    with different gates and bitstrings (same network shape, so the same
+    path, slicing and plan structure), four slices each; (ii) one sliced
+    network's slices as four requests of one chunk each.  Every result is
+    bitwise the one the request gets alone, and matches the oracle."""
+    ctx = served[0]
+    nets, items, refs, handles = [], [], [], []
+    for seed in range(6):
+        circ = random_circuit(5, 5, 10, seed=8200 + seed)
+        net = circuit_network(circ)
+        path = greedy_path(net)
+        sl = greedy_slice(net, path.pairs, n_sliced=2)
+        nets.append((net, Path(path.pairs, sl)))
+    # one structure: every network has the same path and slicing
+    assert all(np.array_equal(n[1].pairs, nets[0][1].pairs) and n[1].sliced == nets[0][1].sliced for n in nets)
+    for net, path in nets:
+        tn = tnc.Network(ctx, net.labels, net.extents, net.open, net.c64().leaves)
+        p = tnc.Plan(tn, path.pairs, path.sliced, prec, form)
+        handles.append((tn, p))
+        items.append((p, 0, p.info.n_slices))
+        refs.append(complex(oc.contract(net, path)))
+    # one network's four slices, one chunk (one slice) per request
+    net, path = nets[0]
+    tn = tnc.Network(ctx, net.labels, net.extents, net.open, net.c64().leaves)
+    ps = tnc.Plan(tn, path.pairs, path.sliced, prec, form)
+    tnc.tnc_plan_set_max_chunk(ps.handle, 1)
+    ps.info = tnc.tnc_plan_get_info(ps.handle)
+    handles.append((tn, ps))
+    for s in range(ps.info.n_slices):
+        items.append((ps, s, 1))
+        refs.append(complex(oc.contract(net, path, slices=[s])))
+    n_mfma = sum(tnc.tnc_plan_get_batch_step(items[0][0].handle, s).kernel == 0
+                 for s in range(items[0][0].info.n_steps))
+    assert n_mfma >= 3
+    print(f"fusion: {len(items)} requests, {n_mfma} MFMA steps per chunk", flush=True)
+    alone, st_alone = _serve_each(ctx, items, fuse=False)
+    mix, st_mix = _serve_each(ctx, items, fuse=True)
+    print(f"fusion: alone {st_alone}, mixed {st_mix}", flush=True)
+    assert st_alone[1] == 0
+    assert st_mix[1] >= 2 and st_mix[2] >= 6
+    for i, (a, m) in enumerate(zip(alone, mix)):
+        assert np.array_equal(a.view(np.uint64), m.view(np.uint64)), i
+    depth = _tree_depth(nets[0][0].n_leaves, nets[0][1].pairs)
+    tol = 1e-5 if prec == tnc.PREC_C64 else max(1e-5, 4 * 2.0 ** -16 * depth)
+    rms = np.sqrt(np.mean(np.abs(np.array(refs[6:])) ** 2))
+    for i, (m, ref) in enumerate(zip(mix, refs)):
+        scale = abs(ref) if i < 6 else rms     # single slices: Porter-Thomas, bounded by the rms
+        assert abs(complex(m[0]) - ref) <= tol * scale, (i, complex(m[0]), ref)
+    for tn, p in handles:
+        p.close()
+        tn.close()
