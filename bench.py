@@ -96,9 +96,15 @@ def parse():
     ap.add_argument("--serve-load", type=float, default=0.8)
     ap.add_argument("--serve-slots", type=int, default=8)
     ap.add_argument("--slices", type=int, default=0, help="circuit40: slices per run (0 = all)")
-    ap.add_argument("--arena-gib", type=float, default=64.0, help="circuit40: arena size")
+    ap.add_argument("--arena-gib", type=float, default=160.0, help="circuit40: arena size")
     ap.add_argument("--max-chunk", type=int, default=0, help="circuit40: cap on slices per batch")
     ap.add_argument("--graph", action="store_true", help="circuit40: replay chunks as hipGraphs")
+    ap.add_argument("--counters", action="store_true",
+                    help="circuit40: only the timed runs (default tile variants, no profiled run, no comparisons, "
+                         "no error checks): for rocprofv3 counter passes")
+    ap.add_argument("--store-order", type=int, choices=[0, 1], default=0,
+                    help="circuit40: 1 = store interleaved outputs through a separate transpose instead of the "
+                         "GEMM's permuted-store epilogue (to measure what the epilogue saves)")
     ap.add_argument("--probe-copy", action="store_true",
                     help="after timing, run one 4 GiB device-to-device copy (calibrates HBM counters)")
     return ap.parse_args()
@@ -291,6 +297,7 @@ def serving_leg(args):
     res["requests"] = len(which)
     res["pool"] = len(plans)
     res["arena_gib"] = args.serve_arena_gib
+    res["fusion"] = fusion_leg(ctx, tnc)
     res["slots"] = args.serve_slots
     res["heavy_lane_flops"] = HEAVY_FLOPS
     for p in plans:
@@ -300,6 +307,52 @@ def serving_leg(args):
     ctx.close()
     del arena
     torch.cuda.empty_cache()
+    return res
+
+
+def fusion_leg(ctx, tnc, n: int = 256):
+    """Light requests of one structure: amplitudes of 64 random 5x5-grid
+    circuits of depth 10 (different gates and bitstrings, one network shape,
+    so one path: 2 sliced labels, 4 slices, 8.9e9 FLOP each), 256 requests
+    queued at once through the 8-slot server with fusion of up to 8
+    same-structure requests per job (their MFMA steps as grouped launches)
+    and without; the results are compared bitwise."""
+    from workloads.circuits import circuit_network, random_circuit
+    from workloads.paths import greedy_path, greedy_slice
+
+    circs = [random_circuit(5, 5, 10, seed=9000 + i) for i in range(64)]
+    nets = [circuit_network(c) for c in circs]
+    path = greedy_path(nets[0])                   # structure only: the same for every circuit
+    sl = greedy_slice(nets[0], path.pairs, n_sliced=2)
+    tns = [tnc.Network(ctx, x.labels, x.extents, x.open, x.c64().leaves) for x in nets]
+    plans = [tnc.Plan(t, path.pairs, sl) for t in tns]
+    for p in plans:
+        p.info = tnc.tnc_plan_get_info(p.handle)
+    outs = {}
+    res = {"requests": n, "circuits": len(plans), "flops_per_request": plans[0].info.flops_per_slice * 4}
+    for name, fuse in (("warmup", 8), ("unfused", 1), ("fused_8", 8)):
+        tnc.tnc_serve_start(ctx.handle, 8, 1 << 16)
+        tnc.tnc_serve_set_fusion(ctx.handle, fuse)
+        o = [np.zeros(1, dtype=np.complex128) for _ in range(n)]
+        t0 = time.perf_counter()
+        ids = [tnc.tnc_submit(ctx.handle, plans[i % len(plans)].handle, 0, plans[i % len(plans)].info.n_slices,
+                              o[i]) for i in range(n)]
+        lat = np.array([tnc.tnc_wait(ctx.handle, r) for r in ids])
+        wall = time.perf_counter() - t0
+        jobs, fj, fr = tnc.tnc_serve_get_stats(ctx.handle)
+        tnc.tnc_serve_stop(ctx.handle)
+        outs[name] = np.array([x[0] for x in o])
+        res[name] = {"req_per_s": round(n / wall, 1), "tflops": round(n * res["flops_per_request"] / wall / 1e12, 3),
+                     "p50_ms": round(float(np.percentile(lat, 50)) * 1e3, 3),
+                     "p99_ms": round(float(np.percentile(lat, 99)) * 1e3, 3),
+                     "jobs": jobs, "fused_jobs": fj, "fused_requests": fr}
+        log(f"fusion leg {name}: {res[name]}")
+    del res["warmup"]
+    res["bitwise_equal"] = bool(np.array_equal(outs["fused_8"].view(np.uint64), outs["unfused"].view(np.uint64)))
+    for p in plans:
+        p.close()
+    for t in tns:
+        t.close()
     return res
 
 
@@ -681,8 +734,11 @@ def circuit40_record(args, steps: int, warmup: int, with_cpu: bool):
         tnc.tnc_plan_set_max_chunk(plan.handle, args.max_chunk)
     if args.graph:
         tnc.tnc_plan_set_graph(plan.handle, True)
+    if args.store_order:
+        tnc.tnc_plan_set_store_order(plan.handle, args.store_order)
     t_tune = time.time()
-    tnc.tnc_plan_autotune(plan.handle)
+    if not args.counters:
+        tnc.tnc_plan_autotune(plan.handle)
     log(f"autotuned in {time.time() - t_tune:.1f} s")
     info = tnc.tnc_plan_get_info(plan.handle)
     n = args.slices or info.n_slices
@@ -695,6 +751,16 @@ def circuit40_record(args, steps: int, warmup: int, with_cpu: bool):
     for _ in range(steps):
         z = plan.contract(0, n)
     dt = (time.perf_counter() - t0) / steps
+    if args.counters:
+        log(f"counter run: {steps} runs of {n} slices at {dt * 1e3:.1f} ms, store order {args.store_order}")
+        res = {"workload": "circuit40 counter run", "slices": n, "chunk": info.max_chunk,
+               "store_order": args.store_order, "ms_per_run": round(dt * 1e3, 3), "amplitude": [z[0].real, z[0].imag]}
+        plan.close()
+        tn.close()
+        ctx.close()
+        del arena
+        torch.cuda.empty_cache()
+        return res
     n_chunks = max(1, n // info.max_chunk)
     prof = tnc.Plan(tn, path.pairs, path.sliced, prec, form)
     if args.max_chunk:
@@ -759,6 +825,37 @@ def circuit40_record(args, steps: int, warmup: int, with_cpu: bool):
            "slice_loop_ms_per_slice": round(t_slice * 1e3, 3),
            "slice_loop_extrapolated_s": round(t_slice * n, 2),
            "batched_speedup_vs_slice_loop": round(t_slice * n / dt, 2)}
+    # the executor without the permuted-store epilogue: interleaved outputs
+    # stored in launch order and transposed by a separate launch (its
+    # scratch buffers may shrink the chunk; both orders are timed at the
+    # same chunk size)
+    if args.store_order == 0:
+        def timed_plan(order, cap):
+            q = tnc.Plan(tn, path.pairs, path.sliced, prec, form)
+            if cap:
+                tnc.tnc_plan_set_max_chunk(q.handle, cap)
+            tnc.tnc_plan_set_store_order(q.handle, order)
+            tnc.tnc_plan_autotune(q.handle)
+            zq = q.contract(0, n)
+            torch.cuda.synchronize()
+            t2 = time.perf_counter()
+            for _ in range(steps):
+                zq = q.contract(0, n)
+            dq = (time.perf_counter() - t2) / steps
+            cq = tnc.tnc_plan_get_info(q.handle).max_chunk
+            q.close()
+            return dq, zq, cq
+        dt_alt, za, chunk_alt = timed_plan(1, args.max_chunk)
+        if chunk_alt != info.max_chunk:
+            dt_same, zs, _ = timed_plan(0, chunk_alt)
+        else:
+            dt_same, zs = dt, z
+        res["separate_transpose_store"] = {
+            "chunk": chunk_alt, "ms_per_run": round(dt_alt * 1e3, 3),
+            "epilogue_ms_per_run_same_chunk": round(dt_same * 1e3, 3),
+            "epilogue_saves_ms": round((dt_alt - dt_same) * 1e3, 3),
+            "bitwise_equal": bool(np.array_equal(np.asarray(za).view(np.uint64), np.asarray(zs).view(np.uint64)))}
+        log(f"separate-transpose store: {res['separate_transpose_store']}")
     # errors against the FP64 oracle: the sum of slices [0, 64) (FP64
     # accumulation on the device) and, with the CPU baseline, its sampled
     # slices one by one
@@ -789,7 +886,10 @@ def circuit40_record(args, steps: int, warmup: int, with_cpu: bool):
 def bench_circuit40(args):
     """Sliced 40-qubit circuit (5x8 grid, depth 12, 16 sliced labels = 65,536
     slices): the slices run as a batch dimension of every step, summed in FP64."""
-    rec = circuit40_record(args, args.steps, args.warmup, not args.no_cpu)
+    rec = circuit40_record(args, args.steps, args.warmup, not args.no_cpu and not args.counters)
+    if args.counters:
+        print(json.dumps(rec), flush=True)
+        return
     res = {"metric": "complex TFLOP/s of path execution (% MFMA peak) + p50/p99 request latency",
            "value": rec.pop("value"), "unit": rec.pop("unit"), "n_gpus": 1, "steps": args.steps,
            "warmup": args.warmup, "ms_per_step": rec.pop("ms_per_run"), "higher_is_better": True,

@@ -213,6 +213,17 @@ tnc_status tnc_plan_set_graph(tnc_plan plan, int32_t enable);
  * re-plans the chunks (the arena layout follows the execution order) and
  * drops captured graphs; refused with TNC_E_BUSY while the context serves. */
 tnc_status tnc_plan_set_grouping(tnc_plan plan, int32_t enable);
+/* Where an interleaved output is put in its consumer's order (Sec. IV-A:
+ * the reordering exists so that no transpose runs between steps).  0
+ * (default): the GEMM's epilogue stores every element straight to its
+ * place in the consumer's order (per-row and per-column offset tables).
+ * 1: the GEMM stores [batch | rows | columns] into a scratch buffer of the
+ * arena and a separate LDS-tiled transpose writes the consumer's order: the
+ * executor without the permuted-store epilogue, kept to measure what the
+ * epilogue saves (results are bitwise the same).  Steps with split K keep
+ * their epilogue pass.  Re-plans the chunks and drops captured graphs;
+ * TNC_E_BUSY while the context serves. */
+tnc_status tnc_plan_set_store_order(tnc_plan plan, int32_t mode);
 /* 1 = time every kernel with HIP events on the launch stream. */
 tnc_status tnc_plan_set_profile(tnc_plan plan, int32_t enable);
 /* Per-step accumulated kernel time (ms) and launch count since profiling was

@@ -497,6 +497,25 @@ tnc_status tnc_plan_set_grouping(tnc_plan plan, int32_t enable) {
   TNC_CATCH
 }
 
+tnc_status tnc_plan_set_store_order(tnc_plan plan, int32_t mode) {
+  TNC_TRY
+  if (!plan) fail(TNC_E_ARG, "plan is NULL");
+  if (mode != 0 && mode != 1) fail(TNC_E_ARG, "store order must be 0 or 1");
+  Plan& p = *plan->p;
+  Ctx& c = *p.net->ctx;
+  refuse_while_serving(c, "changing the store order");
+  if (mode == p.store_order) return TNC_OK;
+  if (!c.host_only) {
+    set_device(c);
+    check_hip(hipStreamSynchronize(c.stream), "sync before re-planning");
+    drain_profile(p);
+  }
+  p.drop_graphs();
+  p.store_order = mode;
+  choose_chunking(p, c.arena_bytes);
+  TNC_CATCH
+}
+
 tnc_status tnc_plan_set_profile(tnc_plan plan, int32_t enable) {
   TNC_TRY
   if (!plan) fail(TNC_E_ARG, "plan is NULL");

@@ -112,6 +112,10 @@ int tune_shape(Ctx& c, const TuneKey& key, int64_t k, bool perm_store) {
     while (k > 8192 && k % 32 == 0 && flop() > target) k /= 2;
     while (h > 1 && flop() > target) h = (h + 1) / 2;
     while (m > 4096 && flop() > target) m = half_m(m);
+    // and its operands stay within 8 GiB beside the caller's arena (the
+    // batch shrinks; 2048 or more tiles remain for batches of this size)
+    auto bytes = [&] { return 8.0 * h * (m * k + key.n * k + m * key.n); };
+    while (h > 1 && bytes() > 8.0 * (int64_t{1} << 30)) h = (h + 1) / 2;
     DeviceBuf a, b, cc, offm, offn;
     a.alloc(static_cast<size_t>(h * m * k) * 8);
     b.alloc(static_cast<size_t>(h * key.n * k) * 8);

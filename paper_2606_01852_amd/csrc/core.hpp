@@ -167,6 +167,11 @@ struct StepPlan {
   const int64_t* dev_offM = nullptr;          // device copies of the store tables
   const int64_t* dev_offN = nullptr;
   std::vector<int> preps;                     // leaf preps launched before the GEMM
+  // separate-transpose store (the plan's store order 1): the GEMM stores
+  // [H | launch rows | launch columns] into the step's scratch buffer and
+  // this permutation writes it in the consumer's order
+  bool trans = false;
+  PermuteHost tperm;
 };
 
 // One level of the contraction tree: the steps whose operands are all
@@ -245,6 +250,7 @@ struct Plan {
   tnc_cgemm form = TNC_GEMM_4M;
   int64_t max_chunk_user = -1;
   int grouping = 1;                   // level-grouped launches
+  int store_order = 0;                // 0: GEMM epilogue stores in consumer order; 1: separate transpose
   std::vector<char> volatile_leaf;    // per leaf: data changes between runs (never cached)
   void* host_res = nullptr;           // pinned staging of tnc_contract's result
   size_t host_res_bytes = 0;

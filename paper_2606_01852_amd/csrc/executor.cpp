@@ -46,6 +46,15 @@ void materialize(const Net& net, ChunkPlan& cp, hipStream_t stream) {
     p.off_hi = put(blob, p.hi_tab);
   }
   for (StepPlan& sp : cp.steps) {
+    if (sp.trans && sp.tperm.tiled) {
+      PermuteHost& p = sp.tperm;
+      p.off_tile_in = put(blob, p.tile_in);
+      p.off_slot_r = put(blob, p.tile_slot_r);
+      p.off_tile_out = put(blob, p.tile_out);
+      p.off_slot_w = put(blob, p.tile_slot_w);
+      p.off_lo = put(blob, p.lo_tab);
+      p.off_hi = put(blob, p.hi_tab);
+    }
     if (sp.offM.empty()) continue;
     sp.off_offM = put(blob, sp.offM);
     sp.off_offN = put(blob, sp.offN);
@@ -155,15 +164,13 @@ std::vector<std::pair<int, int64_t>> decompose(const Plan& plan, int64_t first, 
 
 namespace {
 
-// Launch the gather-permute of leaf t into `out`; `bd` points at its
-// per-chunk base offset on the device (null: none).
-hipError_t launch_leaf_prep(const Net& net, const ChunkPlan& cp, int t, float2* out, const int64_t* bd,
-                            hipStream_t stream) {
-  const LeafPrep& lp = cp.leaf[t];
-  const float2* in = static_cast<const float2*>(net.leaf[t].ptr);
+// Launch a planned gather-permute from `in` into `out` (tables in the chunk
+// plan's device blob); `bd` points at a per-chunk base offset on the device
+// (null: none).
+hipError_t launch_planned_permute(const PermuteHost& p, const ChunkPlan& cp, const float2* in, float2* out,
+                                  const int64_t* bd, hipStream_t stream) {
   const char* blob = static_cast<const char*>(cp.blob.ptr);
-  if (lp.perm.tiled) {
-    const PermuteHost& p = lp.perm;
+  if (p.tiled) {
     PermuteDesc d{};
     d.in = in;
     d.out = out;
@@ -181,12 +188,19 @@ hipError_t launch_leaf_prep(const Net& net, const ChunkPlan& cp, int t, float2* 
     d.base_dev = bd;
     return launch_permute(d, stream);
   }
-  GatherDesc g = lp.perm.plain;
+  GatherDesc g = p.plain;
   g.in = in;
   g.out = out;
   g.base = 0;
   g.base_dev = bd;
   return launch_gather(g, stream);
+}
+
+// Launch the gather-permute of leaf t into `out`; `bd` points at its
+// per-chunk base offset on the device (null: none).
+hipError_t launch_leaf_prep(const Net& net, const ChunkPlan& cp, int t, float2* out, const int64_t* bd,
+                            hipStream_t stream) {
+  return launch_planned_permute(cp.leaf[t].perm, cp, static_cast<const float2*>(net.leaf[t].ptr), out, bd, stream);
 }
 
 // (Re)fill the leaf cache when it is empty or a cached leaf's data has been
@@ -272,20 +286,27 @@ struct ChunkOps {
   }
   int variant(const StepPlan& sp) const { return net.ctx->gemm_variant >= 0 ? net.ctx->gemm_variant : sp.variant; }
   // The step's launch descriptor with this run's pointers (the split-K
-  // partials go to the step's arena scratch buffer).
+  // partials, or the output before its separate transpose, go to the
+  // step's arena scratch buffer).
   GemmDesc desc(int s) const {
     const StepPlan& sp = cp.steps[s];
     GemmDesc d = sp.desc;
     d.A = ptr(sp.la);
     d.B = ptr(sp.lb);
-    d.C = sp.split > 1 ? reinterpret_cast<float2*>(a.arena + cp.buf_off[sp.scratch_buf]) : ptr(sp.C);
+    d.C = sp.split > 1 || sp.trans ? reinterpret_cast<float2*>(a.arena + cp.buf_off[sp.scratch_buf]) : ptr(sp.C);
     return d;
   }
-  void splitk(int s) {
+  // What follows the GEMM: the split-K epilogue, or the separate transpose
+  // into the consumer's order.
+  void finish(int s) {
     const StepPlan& sp = cp.steps[s];
-    if (sp.split <= 1) return;
+    if (sp.split <= 1 && !sp.trans) return;
     const GemmDesc d = desc(s);
     float2* c = ptr(sp.C);
+    if (sp.trans) {
+      L.run(s, stream, [&] { return launch_planned_permute(sp.tperm, cp, d.C, c, nullptr, stream); });
+      return;
+    }
     L.run(s, stream, [&] {
       return launch_splitk_reduce(d.C, c, sp.h, sp.lm, sp.ln, sp.split, sp.dev_offM, sp.dev_offN, stream);
     });
@@ -294,7 +315,7 @@ struct ChunkOps {
     const StepPlan& sp = cp.steps[s];
     const GemmDesc d = desc(s);
     L.run(s, stream, [&] { return launch_gemm(d, sp.kind, variant(sp), form, prec, stream); });
-    splitk(s);
+    finish(s);
   }
   void level_gathers(const LevelPlan& lv) {
     if (lv.group_leaves.empty()) return;
@@ -538,6 +559,7 @@ std::string structure_key(Plan& plan, int64_t first, int64_t count) {
   put(plan.prec);
   put(plan.form);
   put(plan.grouping);
+  put(plan.store_order);
   put(net.ctx->gemm_variant);
   put(static_cast<int64_t>(plan.volatile_leaf.size()));
   for (char v : plan.volatile_leaf) put(v);
@@ -635,7 +657,7 @@ void run_lockstep(std::vector<LockstepRun>& runs, GroupedEntry* host, GroupedEnt
       const int v = ops[0]->variant(cp0.steps[s]);
       check_hip(launch_gemm_grouped(dev + it->second.first, K, it->second.second, v, form, prec, stream),
                 "grouped GEMM launch");
-      for (auto& op : ops) op->splitk(s);
+      for (auto& op : ops) op->finish(s);
     };
     const int ns = static_cast<int>(cp0.steps.size());
     if (ns == 0)

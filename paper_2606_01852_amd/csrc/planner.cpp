@@ -589,6 +589,36 @@ std::unique_ptr<ChunkPlan> build_chunk(const Plan& plan, int j) {
       d.ldk = sp.k;
       sp.split = static_cast<int>(S);
     }
+    // the fallback the permuted-store epilogue replaces: store in the launch
+    // order and transpose into the consumer's order with a separate
+    // permutation (split-K steps keep their epilogue, itself a separate pass)
+    if (plan.store_order == 1 && !sp.natural && sp.split == 1) {
+      sp.trans = true;
+      sp.offM.clear();
+      sp.offN.clear();
+      const std::vector<int>& rows = sp.swap ? sp.N : sp.M;
+      const std::vector<int>& cols = sp.swap ? sp.M : sp.N;
+      std::unordered_map<int, int64_t> ts;   // stride of each label in [H | rows | cols]
+      int64_t st = 1;
+      for (int q = static_cast<int>(cols.size()) - 1; q >= 0; --q) {
+        ts[cols[q]] = st;
+        st *= net.extents[cols[q]];
+      }
+      for (int q = static_cast<int>(rows.size()) - 1; q >= 0; --q) {
+        ts[rows[q]] = st;
+        st *= net.extents[rows[q]];
+      }
+      for (int q = static_cast<int>(sp.H.size()) - 1; q >= 0; --q) {
+        ts[sp.H[q]] = st;
+        st *= net.extents[sp.H[q]];
+      }
+      std::vector<int64_t> ext, ist;
+      for (int l : cp->order[sp.C]) {
+        ext.push_back(net.extents[l]);
+        ist.push_back(ts.at(l));
+      }
+      sp.tperm = build_permute(ext, ist);
+    }
     cp->flops += 8.0 * static_cast<double>(sp.h) * sp.m * sp.n * sp.k;
     cp->bytes += 8.0 * (static_cast<double>(sp.hA) * sp.m * sp.k + static_cast<double>(sp.hB) * sp.n * sp.k +
                         static_cast<double>(sp.h) * sp.m * sp.n);
@@ -607,7 +637,7 @@ std::unique_ptr<ChunkPlan> build_chunk(const Plan& plan, int j) {
     for (int s = 0; s < ns; ++s) {
       LevelPlan& level = cp->levels[lvl[n + s]];
       const StepPlan& sp = cp->steps[s];
-      if (sp.kind == GemmKernel::SMALL && n + s != root)
+      if (sp.kind == GemmKernel::SMALL && n + s != root && !sp.trans)
         level.group_steps.push_back(s);
       else
         level.single_steps.push_back(s);
@@ -637,7 +667,7 @@ std::unique_ptr<ChunkPlan> build_chunk(const Plan& plan, int j) {
     const int c = n + s;
     ivs.push_back({align_up(cp->numel[c] * 8), when(s), consumer[c] < ns ? when(consumer[c]) : t_end, c});
     const StepPlan& sp = cp->steps[s];
-    if (sp.split > 1)  // split-K partials, live during the step only
+    if (sp.split > 1 || sp.trans)  // split-K partials or the untransposed output, live during the step only
       ivs.push_back({align_up(sp.h * sp.split * sp.lm * sp.ln * 8), when(s), when(s), -1 - s});
   }
   std::vector<int> idx(ivs.size());

@@ -88,6 +88,7 @@ _SIGS = {
     "tnc_plan_set_max_chunk": (C.c_int, [_P, C.c_int64]),
     "tnc_plan_set_graph": (C.c_int, [_P, C.c_int32]),
     "tnc_plan_set_grouping": (C.c_int, [_P, C.c_int32]),
+    "tnc_plan_set_store_order": (C.c_int, [_P, C.c_int32]),
     "tnc_plan_autotune": (C.c_int, [_P]),
     "tnc_plan_distribute": (C.c_int, [_P, C.c_int32, C.c_double, C.POINTER(DistHW), C.POINTER(DistStep),
                                       C.c_int32, _I32P, _DP, _DP]),
@@ -298,6 +299,10 @@ def tnc_plan_set_graph(plan: int, enable: bool) -> None:
 
 def tnc_plan_set_grouping(plan: int, enable: bool) -> None:
     _check(lib().tnc_plan_set_grouping(plan, int(enable)))
+
+
+def tnc_plan_set_store_order(plan: int, mode: int) -> None:
+    _check(lib().tnc_plan_set_store_order(plan, int(mode)))
 
 
 def tnc_plan_set_profile(plan: int, enable: bool) -> None:

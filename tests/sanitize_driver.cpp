@@ -9,7 +9,7 @@
 //   n_steps    then the SSA pairs
 //   n_sliced   then the sliced labels
 //   batch_label (-1: none), then n_leaves and the leaves of a batcher
-// For each network the driver plans it (both execution orders, every chunk
+// For each network the driver plans it (both execution orders and store orders, every chunk
 // size), queries every step and order, plans its distribution over 2, 4 and
 // 8 devices, creates and destroys a batcher when asked, and checks that
 // malformed paths come back as status codes; a fixed set of malformed
@@ -96,8 +96,10 @@ void exercise(tnc_ctx ctx, const NetFile& f, const char* file) {
          "plan_create", file);
   if (plan) {
     tnc_plan_info info;
-    for (int grouping = 1; grouping >= 0; --grouping) {
+    for (int mode = 0; mode < 4; ++mode) {
+      const int grouping = mode & 1 ? 0 : 1, store = mode >> 1;
       expect(tnc_plan_set_grouping(plan, grouping) == TNC_OK, "set_grouping", file);
+      expect(tnc_plan_set_store_order(plan, store) == TNC_OK, "set_store_order", file);
       for (int64_t cap : {int64_t{1}, int64_t{4}, int64_t{-1}}) {
         expect(tnc_plan_set_max_chunk(plan, cap) == TNC_OK, "set_max_chunk", file);
         expect(tnc_plan_get_info(plan, &info) == TNC_OK, "get_info", file);
@@ -108,6 +110,7 @@ void exercise(tnc_ctx ctx, const NetFile& f, const char* file) {
         }
       }
     }
+    expect(tnc_plan_set_store_order(plan, 2) == TNC_E_ARG, "store order out of range", file);
     std::vector<int32_t> order(64);
     for (int32_t id = 0; id < f.n_tensors + n_steps; ++id) {
       int32_t rank = 0;

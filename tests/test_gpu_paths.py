@@ -610,3 +610,47 @@ def test_profile_counts_survive_long_sessions(ctx):
     assert launches == per_run * (n_runs + 1) and ms > 0
     plan.close()
     tn.close()
+
+
+@pytest.mark.parametrize("case", ["circuit12_grouped", "circuit12_stepwise", "grid8_4M", "grid8_3M",
+                                  "grid8_bf16x3", "interleaved_pair", "sliced_circuit20"])
+def test_separate_transpose_store_is_bitwise_the_epilogue(ctx, case):
+    """Store order 1 (the GEMM stores in launch order, a separate transpose
+    writes the consumer's order) gives bitwise the results of the
+    permuted-store epilogue (store order 0): the same products, moved by a
+    bit copy instead of the epilogue's addressing."""
+    prec, form, grouping, sl = tnc.PREC_C64, tnc.GEMM_4M, True, ()
+    if case.startswith("circuit12"):
+        net, path = configs.circuit12(open_qubits=(0, 5, 11))
+        grouping = case.endswith("grouped")
+    elif case.startswith("grid8"):
+        net, _ = prescaled_grid(8, 8, 4, seed=1002)
+        path = greedy_path(net)
+        prec = tnc.PREC_BF16X3 if case.endswith("bf16x3") else tnc.PREC_C64
+        form = tnc.GEMM_3M if case.endswith("3M") else tnc.GEMM_4M
+    elif case == "interleaved_pair":
+        net, path = interleaved_pair(3, 12, 25, 7, 15, 130, seed=43)
+    else:
+        circ = random_circuit(4, 5, 10, seed=4321)
+        net = circuit_network(circ)
+        p = greedy_path(net)
+        sl = greedy_slice(net, p.pairs, n_sliced=3)
+        path = Path(p.pairs, sl)
+    tn = tnc.Network(ctx, net.labels, net.extents, net.open, net.c64().leaves)
+    got = {}
+    for mode in (0, 1):
+        plan = tnc.Plan(tn, path.pairs, path.sliced, prec, form)
+        tnc.tnc_plan_set_grouping(plan.handle, grouping)
+        tnc.tnc_plan_set_store_order(plan.handle, mode)
+        if sl:
+            tnc.tnc_plan_set_max_chunk(plan.handle, 4)
+        got[mode] = plan.contract()
+        n_perm = tnc.tnc_plan_get_info(plan.handle).n_permuted_stores
+        plan.close()
+    print(f"{case}: {n_perm} permuted-store steps", flush=True)
+    assert n_perm > 0
+    assert np.array_equal(got[0].view(np.uint64), got[1].view(np.uint64))
+    ref = oc.contract(net, path)
+    if prec == tnc.PREC_C64:
+        assert_close(got[1], np.asarray(ref).reshape(-1))
+    tn.close()
