@@ -164,6 +164,9 @@ typedef struct {
                                     up to 2^22 elements: permuted once into the
                                     plan's leaf cache (refreshed when their
                                     data is replaced), not in every run       */
+  int32_t n_inplace_leaves;      /* leaves whose sliced labels are fixed per
+                                    chunk, read in place by the GEMM that
+                                    consumes them (no gather per batch)      */
 } tnc_plan_info;
 tnc_status tnc_plan_get_info(tnc_plan plan, tnc_plan_info* out);
 

@@ -143,6 +143,9 @@ struct LeafPrep {
   // plan's leaf cache (refreshed when its data is replaced), not per run
   bool cached = false;
   int64_t cache_off = -1;
+  // a leaf with a per-chunk base offset consumed by a one-thread-per-output
+  // GEMM is read in place through the step's operand tables (no gather)
+  bool inplace = false;
 };
 
 struct StepPlan {
@@ -172,6 +175,9 @@ struct StepPlan {
   // this permutation writes it in the consumer's order
   bool trans = false;
   PermuteHost tperm;
+  // in-place operand tables (launch orientation): rowA, kA, rowB, kB
+  std::vector<int64_t> tab[4];
+  int64_t off_tab[4] = {-1, -1, -1, -1};
 };
 
 // One level of the contraction tree: the steps whose operands are all

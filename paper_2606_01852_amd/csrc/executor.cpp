@@ -36,7 +36,7 @@ void materialize(const Net& net, ChunkPlan& cp, hipStream_t stream) {
   std::vector<uint8_t>& blob = cp.host_blob;
   blob.clear();
   for (LeafPrep& lp : cp.leaf) {
-    if (lp.direct || !lp.perm.tiled) continue;
+    if (lp.direct || lp.inplace || !lp.perm.tiled) continue;
     PermuteHost& p = lp.perm;
     p.off_tile_in = put(blob, p.tile_in);
     p.off_slot_r = put(blob, p.tile_slot_r);
@@ -55,6 +55,7 @@ void materialize(const Net& net, ChunkPlan& cp, hipStream_t stream) {
       p.off_lo = put(blob, p.lo_tab);
       p.off_hi = put(blob, p.hi_tab);
     }
+    for (int q = 0; q < 4; ++q) sp.off_tab[q] = put(blob, sp.tab[q]);
     if (sp.offM.empty()) continue;
     sp.off_offM = put(blob, sp.offM);
     sp.off_offN = put(blob, sp.offN);
@@ -75,6 +76,9 @@ void materialize(const Net& net, ChunkPlan& cp, hipStream_t stream) {
   if (cp.cache_bytes) cp.leaf_cache.alloc(static_cast<size_t>(cp.cache_bytes));
   char* base = static_cast<char*>(cp.blob.ptr);
   for (StepPlan& sp : cp.steps) {
+    const int64_t** tabs[4] = {&sp.desc.rowA, &sp.desc.kA, &sp.desc.rowB, &sp.desc.kB};
+    for (int q = 0; q < 4; ++q)
+      if (sp.off_tab[q] >= 0) *tabs[q] = reinterpret_cast<const int64_t*>(base + sp.off_tab[q]);
     if (sp.offM.empty()) continue;
     sp.dev_offM = reinterpret_cast<const int64_t*>(base + sp.off_offM);
     sp.dev_offN = reinterpret_cast<const int64_t*>(base + sp.off_offN);
@@ -95,7 +99,7 @@ void materialize(const Net& net, ChunkPlan& cp, hipStream_t stream) {
         std::memset(&g, 0, sizeof(g));
         g.d = sp.desc;
         auto operand = [&](int id, int32_t& rel) -> void* {
-          if (id < n && cp.leaf[id].direct) {
+          if (id < n && (cp.leaf[id].direct || cp.leaf[id].inplace)) {
             rel = 0;
             return net.leaf[id].ptr;
           }
@@ -109,6 +113,8 @@ void materialize(const Net& net, ChunkPlan& cp, hipStream_t stream) {
         g.d.A = static_cast<const float2*>(operand(sp.la, g.rel_a));
         g.d.B = static_cast<const float2*>(operand(sp.lb, g.rel_b));
         g.d.C = static_cast<float2*>(operand(sp.C, g.rel_c));
+        g.slot_a = sp.la < n && cp.leaf[sp.la].inplace ? cp.leaf[sp.la].base_slot : -1;
+        g.slot_b = sp.lb < n && cp.leaf[sp.lb].inplace ? cp.leaf[sp.lb].base_slot : -1;
         tab[q] = g;
         pre[q] = acc;
         acc += sp.desc.h * sp.desc.m * sp.desc.n;
@@ -273,7 +279,7 @@ struct ChunkOps {
   const Prec prec = plan.prec == TNC_PREC_BF16X3 ? Prec::BF16X3 : Prec::C64;
 
   float2* ptr(int id) const {
-    if (id < n && cp.leaf[id].direct) return static_cast<float2*>(net.leaf[id].ptr);
+    if (id < n && (cp.leaf[id].direct || cp.leaf[id].inplace)) return static_cast<float2*>(net.leaf[id].ptr);
     if (id < n && cp.leaf[id].cached) return cached_leaf(cp, id);
     if (id == cp.root_id && a.direct_out) return a.direct_out;
     return reinterpret_cast<float2*>(a.arena + cp.buf_off[cp.tensor_buf[id]]);
@@ -294,6 +300,9 @@ struct ChunkOps {
     d.A = ptr(sp.la);
     d.B = ptr(sp.lb);
     d.C = sp.split > 1 || sp.trans ? reinterpret_cast<float2*>(a.arena + cp.buf_off[sp.scratch_buf]) : ptr(sp.C);
+    auto slot = [&](int id) { return id < n && cp.leaf[id].inplace ? bases + cp.leaf[id].base_slot : nullptr; };
+    d.baseA = slot(sp.la);
+    d.baseB = slot(sp.lb);
     return d;
   }
   // What follows the GEMM: the split-K epilogue, or the separate transpose
@@ -330,7 +339,7 @@ struct ChunkOps {
     L.run(t_group, stream, [&] {
       return launch_group_gemm(reinterpret_cast<const GroupGemm*>(blob + lv.off_gemm),
                                reinterpret_cast<const int64_t*>(blob + lv.off_gemm_prefix),
-                               static_cast<int>(lv.group_steps.size()), lv.gemm_total, a.arena, prec, stream);
+                               static_cast<int>(lv.group_steps.size()), lv.gemm_total, a.arena, bases, prec, stream);
     });
   }
   void reduce(bool overwrite) {

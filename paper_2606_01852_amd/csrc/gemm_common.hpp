@@ -89,4 +89,18 @@ __device__ __forceinline__ void cdot_serial(const float2* A, const float2* B, in
   for (; l < k; ++l) cmac<SPLIT>(A[l], B[l], cr, ci, crx, cix);
 }
 
+// The same sum with operands read through tables (an operand without
+// tables is K-contiguous at a0 / b0): element l of the A row at
+// a0[kA[l]], of the B row at b0[kB[l]]; the accumulation order is that of
+// cdot_serial, so the result is bitwise the one of contiguous copies.
+template <bool SPLIT>
+__device__ __forceinline__ void cdot_tables(const float2* a0, const int64_t* kA, const float2* b0, const int64_t* kB,
+                                            int64_t k, float& cr, float& ci, float& crx, float& cix) {
+  for (int64_t l = 0; l < k; ++l) {
+    const float2 x = kA ? a0[kA[l]] : a0[l];
+    const float2 y = kB ? b0[kB[l]] : b0[l];
+    cmac<SPLIT>(x, y, cr, ci, crx, cix);
+  }
+}
+
 }  // namespace tnc

@@ -27,10 +27,14 @@ __global__ __launch_bounds__(256) void cgemm_small(GemmDesc d) {
     const int64_t j = r - i * d.n;
     int64_t oa, ob;
     batch_offsets(d, b, oa, ob);
-    const float2* a = d.A + oa + i * row_stride(d);
-    const float2* bb = d.B + ob + j * row_stride(d);
     float cr = 0.f, ci = 0.f, crx = 0.f, cix = 0.f;
-    cdot_serial<SPLIT>(a, bb, d.k, cr, ci, crx, cix);
+    if (d.kA || d.kB) {
+      const float2* a = d.A + oa + (d.baseA ? *d.baseA : 0) + (d.rowA ? d.rowA[i] : i * row_stride(d));
+      const float2* bb = d.B + ob + (d.baseB ? *d.baseB : 0) + (d.rowB ? d.rowB[j] : j * row_stride(d));
+      cdot_tables<SPLIT>(a, d.kA, bb, d.kB, d.k, cr, ci, crx, cix);
+    } else {
+      cdot_serial<SPLIT>(d.A + oa + i * row_stride(d), d.B + ob + j * row_stride(d), d.k, cr, ci, crx, cix);
+    }
     const int64_t c = b * mn + (d.offM ? d.offM[i] + d.offN[j] : r);
     if constexpr (SPLIT)
       d.C[c] = make_float2(cr + crx, ci + cix);

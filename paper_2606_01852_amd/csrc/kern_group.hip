@@ -33,7 +33,7 @@ __device__ __forceinline__ T* reloc(const void* p, int flag, char* arena) {
 
 template <bool SPLIT>
 __global__ __launch_bounds__(256) void group_small_gemm(const GroupGemm* __restrict__ g, const int64_t* __restrict__ prefix,
-                                                        int n, int64_t total, char* arena) {
+                                                        int n, int64_t total, char* arena, const int64_t* bases) {
   for (int64_t gt = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x; gt < total;
        gt += static_cast<int64_t>(gridDim.x) * blockDim.x) {
     const int s = find_item(prefix, n, gt);
@@ -47,11 +47,17 @@ __global__ __launch_bounds__(256) void group_small_gemm(const GroupGemm* __restr
     const int64_t j = r - i * d.n;
     int64_t oa, ob;
     batch_offsets(d, b, oa, ob);
-    const float2* A = reloc<const float2>(d.A, e.rel_a, arena) + oa + i * row_stride(d);
-    const float2* B = reloc<const float2>(d.B, e.rel_b, arena) + ob + j * row_stride(d);
+    const float2* A = reloc<const float2>(d.A, e.rel_a, arena) + oa;
+    const float2* B = reloc<const float2>(d.B, e.rel_b, arena) + ob;
     float2* C = reloc<float2>(d.C, e.rel_c, arena);
     float cr = 0.f, ci = 0.f, crx = 0.f, cix = 0.f;
-    cdot_serial<SPLIT>(A, B, d.k, cr, ci, crx, cix);
+    if (d.kA || d.kB) {  // in-place leaf operands (tables, per-chunk base offsets)
+      A += (e.slot_a >= 0 ? bases[e.slot_a] : 0) + (d.rowA ? d.rowA[i] : i * row_stride(d));
+      B += (e.slot_b >= 0 ? bases[e.slot_b] : 0) + (d.rowB ? d.rowB[j] : j * row_stride(d));
+      cdot_tables<SPLIT>(A, d.kA, B, d.kB, d.k, cr, ci, crx, cix);
+    } else {
+      cdot_serial<SPLIT>(A + i * row_stride(d), B + j * row_stride(d), d.k, cr, ci, crx, cix);
+    }
     const int64_t c = b * mn + (d.offM ? d.offM[i] + d.offN[j] : r);
     if constexpr (SPLIT)
       C[c] = make_float2(cr + crx, ci + cix);
@@ -88,12 +94,14 @@ int64_t grid_for(int64_t total) {
 }  // namespace
 
 hipError_t launch_group_gemm(const GroupGemm* table, const int64_t* prefix, int n, int64_t total, char* arena,
-                             Prec prec, hipStream_t s) {
+                             const int64_t* bases, Prec prec, hipStream_t s) {
   if (n <= 0 || total <= 0) return hipSuccess;
   if (prec == Prec::BF16X3)
-    hipLaunchKernelGGL(group_small_gemm<true>, dim3(grid_for(total)), dim3(256), 0, s, table, prefix, n, total, arena);
+    hipLaunchKernelGGL(group_small_gemm<true>, dim3(grid_for(total)), dim3(256), 0, s, table, prefix, n, total, arena,
+                       bases);
   else
-    hipLaunchKernelGGL(group_small_gemm<false>, dim3(grid_for(total)), dim3(256), 0, s, table, prefix, n, total, arena);
+    hipLaunchKernelGGL(group_small_gemm<false>, dim3(grid_for(total)), dim3(256), 0, s, table, prefix, n, total, arena,
+                       bases);
   return hipGetLastError();
 }
 

@@ -33,6 +33,16 @@ struct GemmDesc {
   const int64_t* offM;
   const int64_t* offN;
   int64_t ldk;
+  // Operands read in place through tables (leaves whose sliced labels are
+  // fixed per chunk, consumed by the one-thread-per-output kernels only):
+  // element (b, i, l) of A is A[batch offset + *baseA + rowA[i] + kA[l]]
+  // (B likewise); null tables: i * ldk + l, null base: 0.
+  const int64_t* rowA;
+  const int64_t* kA;
+  const int64_t* baseA;
+  const int64_t* rowB;
+  const int64_t* kB;
+  const int64_t* baseB;
 };
 
 __host__ __device__ inline int64_t row_stride(const GemmDesc& d) { return d.ldk ? d.ldk : d.k; }
@@ -136,6 +146,7 @@ hipError_t launch_splitk_reduce(const float2* P, float2* C, int64_t h, int64_t m
 struct GroupGemm {
   GemmDesc d;
   int32_t rel_a, rel_b, rel_c, pad;
+  int32_t slot_a, slot_b;   // per-chunk base offset of an in-place operand (-1: none)
 };
 constexpr int kGroupRank = 32;
 struct GroupGather {
@@ -148,7 +159,7 @@ struct GroupGather {
 };
 // prefix[i] = first work item of entry i (work items: output elements).
 hipError_t launch_group_gemm(const GroupGemm* table, const int64_t* prefix, int n, int64_t total, char* arena,
-                             Prec prec, hipStream_t s);
+                             const int64_t* bases, Prec prec, hipStream_t s);
 hipError_t launch_group_gather(const GroupGather* table, const int64_t* prefix, int n, int64_t total, char* arena,
                                const int64_t* bases, hipStream_t s);
 

@@ -472,8 +472,28 @@ std::unique_ptr<ChunkPlan> build_chunk(const Plan& plan, int j) {
     sp.m = prod(sp.M);
     sp.n = prod(sp.N);
     sp.k = prod(sp.K);
+    // A leaf whose sliced labels are fixed per chunk would be gathered into
+    // the arena before every batch; when this step runs one thread per
+    // output (no transposed launch), it is read in place instead: its own
+    // strides, row and K offset tables, and the chunk's base offset.
+    const bool small_step = choose_gemm_kernel(sp.h, sp.m, sp.n, sp.k) == GemmKernel::SMALL &&
+                            choose_gemm_kernel(sp.h, sp.n, sp.m, sp.k) != GemmKernel::MFMA;
+    for (int x : {sp.A, sp.B})
+      if (x < n && small_step && cp->leaf[x].base_slot >= 0 && !cp->leaf[x].inplace) {
+        cp->leaf[x].inplace = true;
+        cp->n_permutes--;
+        cp->transpose_bytes -= 16.0 * static_cast<double>(cp->numel[x]);
+        auto& pr = sp.preps;
+        pr.erase(std::remove(pr.begin(), pr.end(), x), pr.end());
+      }
     auto strides_of = [&](int id) {
       std::unordered_map<int, int64_t> m;
+      if (id < n && cp->leaf[id].inplace) {  // the leaf's own strides (fixed labels dropped)
+        const std::vector<int>& stored = net.labels[id];
+        for (size_t q = 0; q < stored.size(); ++q)
+          if (!removed[stored[q]]) m[stored[q]] = net.stride[id][q];
+        return m;
+      }
       const std::vector<int>& o = cp->order[id];
       int64_t s2 = 1;
       for (int q = static_cast<int>(o.size()) - 1; q >= 0; --q) {
@@ -540,6 +560,31 @@ std::unique_ptr<ChunkPlan> build_chunk(const Plan& plan, int j) {
       while ((int64_t{1} << sh) < me[q]) ++sh;
       d.bshift[q] = sh;
       if ((int64_t{1} << sh) != me[q]) d.pow2 = 0;
+    }
+    // operand tables of in-place leaves: row i (digits over the operand's
+    // kept labels in the output's order) and K index l (digits over K)
+    auto table = [&](const std::vector<int>& ls, const std::unordered_map<int, int64_t>& st) {
+      int64_t cnt = 1;
+      for (int l : ls) cnt *= net.extents[l];
+      std::vector<int64_t> off(cnt);
+      for (int64_t i = 0; i < cnt; ++i) {
+        int64_t rest = i, o = 0;
+        for (int q = static_cast<int>(ls.size()) - 1; q >= 0; --q) {
+          const int64_t e = net.extents[ls[q]];
+          o += (rest % e) * st.at(ls[q]);
+          rest /= e;
+        }
+        off[i] = o;
+      }
+      return off;
+    };
+    if (sp.la < n && cp->leaf[sp.la].inplace) {
+      sp.tab[0] = table(sp.swap ? sp.N : sp.M, sp.swap ? sb : sa);
+      sp.tab[1] = table(sp.K, sp.swap ? sb : sa);
+    }
+    if (sp.lb < n && cp->leaf[sp.lb].inplace) {
+      sp.tab[2] = table(sp.swap ? sp.M : sp.N, sp.swap ? sa : sb);
+      sp.tab[3] = table(sp.K, sp.swap ? sa : sb);
     }
     // store tables (launch orientation) for permuted or transposed stores
     if (!sp.natural || sp.swap) {
@@ -659,7 +704,7 @@ std::unique_ptr<ChunkPlan> build_chunk(const Plan& plan, int j) {
   };
   std::vector<Iv> ivs;
   for (int t = 0; t < n; ++t) {
-    if (cp->leaf[t].direct || cp->leaf[t].cached) continue;
+    if (cp->leaf[t].direct || cp->leaf[t].cached || cp->leaf[t].inplace) continue;
     const int tt = ns > 0 ? when(cp->leaf[t].step) : 0;
     ivs.push_back({align_up(cp->numel[t] * 8), tt, t == root ? t_end : tt, t});
   }

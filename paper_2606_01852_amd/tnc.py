@@ -39,7 +39,8 @@ class PlanInfo(C.Structure):
                 ("transpose_bytes", C.c_double), ("n_slices", C.c_int64),
                 ("max_intermediate", C.c_int64), ("peak_bytes", C.c_int64), ("max_chunk", C.c_int64),
                 ("chunk_peak_bytes", C.c_int64), ("chunk_flops", C.c_double), ("n_steps", C.c_int32), ("n_permutes", C.c_int32),
-                ("n_permuted_stores", C.c_int32), ("n_result", C.c_int32), ("n_cached_leaves", C.c_int32)]
+                ("n_permuted_stores", C.c_int32), ("n_result", C.c_int32), ("n_cached_leaves", C.c_int32),
+                ("n_inplace_leaves", C.c_int32)]
 
 
 class StepInfo(C.Structure):
