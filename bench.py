@@ -310,49 +310,62 @@ def serving_leg(args):
     return res
 
 
-def fusion_leg(ctx, tnc, n: int = 256):
-    """Light requests of one structure: amplitudes of 64 random 5x5-grid
-    circuits of depth 10 (different gates and bitstrings, one network shape,
-    so one path: 2 sliced labels, 4 slices, 8.9e9 FLOP each), 256 requests
-    queued at once through the 8-slot server with fusion of up to 8
-    same-structure requests per job (their MFMA steps as grouped launches)
-    and without; the results are compared bitwise."""
+def fusion_leg(ctx, tnc, n: int = 512):
+    """Light requests of one structure, queued all at once through the
+    8-slot server, with fusion of up to 8 same-structure requests per job
+    and without; the results are compared bitwise.  Two mixes of 64 random
+    circuits each (different gates and bitstrings, one network shape, so one
+    path and slicing): 4x5-grid circuits of depth 10 (1 sliced label,
+    2.4e8 FLOP over 18 launches per amplitude: launch-bound, fused by the
+    server's default criterion) and 5x5-grid circuits of depth 10 (2 sliced
+    labels, 8.9e9 FLOP over 20 launches: bound by the GPU's arithmetic, not
+    fused by default; forced fusion timed for comparison)."""
     from workloads.circuits import circuit_network, random_circuit
     from workloads.paths import greedy_path, greedy_slice
 
-    circs = [random_circuit(5, 5, 10, seed=9000 + i) for i in range(64)]
-    nets = [circuit_network(c) for c in circs]
-    path = greedy_path(nets[0])                   # structure only: the same for every circuit
-    sl = greedy_slice(nets[0], path.pairs, n_sliced=2)
-    tns = [tnc.Network(ctx, x.labels, x.extents, x.open, x.c64().leaves) for x in nets]
-    plans = [tnc.Plan(t, path.pairs, sl) for t in tns]
-    for p in plans:
-        p.info = tnc.tnc_plan_get_info(p.handle)
-    outs = {}
-    res = {"requests": n, "circuits": len(plans), "flops_per_request": plans[0].info.flops_per_slice * 4}
-    for name, fuse in (("warmup", 8), ("unfused", 1), ("fused_8", 8)):
-        tnc.tnc_serve_start(ctx.handle, 8, 1 << 16)
-        tnc.tnc_serve_set_fusion(ctx.handle, fuse)
-        o = [np.zeros(1, dtype=np.complex128) for _ in range(n)]
-        t0 = time.perf_counter()
-        ids = [tnc.tnc_submit(ctx.handle, plans[i % len(plans)].handle, 0, plans[i % len(plans)].info.n_slices,
-                              o[i]) for i in range(n)]
-        lat = np.array([tnc.tnc_wait(ctx.handle, r) for r in ids])
-        wall = time.perf_counter() - t0
-        jobs, fj, fr = tnc.tnc_serve_get_stats(ctx.handle)
-        tnc.tnc_serve_stop(ctx.handle)
-        outs[name] = np.array([x[0] for x in o])
-        res[name] = {"req_per_s": round(n / wall, 1), "tflops": round(n * res["flops_per_request"] / wall / 1e12, 3),
-                     "p50_ms": round(float(np.percentile(lat, 50)) * 1e3, 3),
-                     "p99_ms": round(float(np.percentile(lat, 99)) * 1e3, 3),
-                     "jobs": jobs, "fused_jobs": fj, "fused_requests": fr}
-        log(f"fusion leg {name}: {res[name]}")
-    del res["warmup"]
-    res["bitwise_equal"] = bool(np.array_equal(outs["fused_8"].view(np.uint64), outs["unfused"].view(np.uint64)))
-    for p in plans:
-        p.close()
-    for t in tns:
-        t.close()
+    res = {"requests": n, "circuits": 64, "slots": 8, "max_fused": 8,
+           "flops_per_launch_criterion": tnc.FUSE_FLOPS_PER_LAUNCH}
+    for name, rows, cols, n_sl in (("launch_bound_4x5_d10", 4, 5, 1), ("gpu_bound_5x5_d10", 5, 5, 2)):
+        circs = [random_circuit(rows, cols, 10, seed=9000 + i) for i in range(64)]
+        nets = [circuit_network(c) for c in circs]
+        path = greedy_path(nets[0])               # structure only: the same for every circuit
+        sl = greedy_slice(nets[0], path.pairs, n_sliced=n_sl)
+        tns = [tnc.Network(ctx, x.labels, x.extents, x.open, x.c64().leaves) for x in nets]
+        plans = [tnc.Plan(t, path.pairs, sl) for t in tns]
+        for p in plans:
+            p.info = tnc.tnc_plan_get_info(p.handle)
+        flops = plans[0].info.flops_per_slice * plans[0].info.n_slices
+        r = {"flops_per_request": flops, "launches_per_request": plans[0].info.n_launches}
+        outs = {}
+        legs = [("warmup", 8, tnc.FUSE_ALL), ("unfused", 1, tnc.FUSE_ALL), ("fused_8", 8, tnc.FUSE_FLOPS_PER_LAUNCH)]
+        if flops >= plans[0].info.n_launches * tnc.FUSE_FLOPS_PER_LAUNCH:
+            legs.append(("fused_8_forced", 8, tnc.FUSE_ALL))
+        for leg, fuse, per_launch in legs:
+            tnc.tnc_serve_start(ctx.handle, 8, 1 << 16)
+            tnc.tnc_serve_set_fusion(ctx.handle, fuse, per_launch)
+            o = [np.zeros(1, dtype=np.complex128) for _ in range(n)]
+            t0 = time.perf_counter()
+            ids = [tnc.tnc_submit(ctx.handle, plans[i % 64].handle, 0, plans[i % 64].info.n_slices, o[i])
+                   for i in range(n)]
+            lat = np.array([tnc.tnc_wait(ctx.handle, q) for q in ids])
+            wall = time.perf_counter() - t0
+            jobs, fj, fr = tnc.tnc_serve_get_stats(ctx.handle)
+            tnc.tnc_serve_stop(ctx.handle)
+            outs[leg] = np.array([x[0] for x in o])
+            r[leg] = {"req_per_s": round(n / wall, 1), "tflops": round(n * flops / wall / 1e12, 3),
+                      "p50_ms": round(float(np.percentile(lat, 50)) * 1e3, 3),
+                      "p99_ms": round(float(np.percentile(lat, 99)) * 1e3, 3),
+                      "jobs": jobs, "fused_jobs": fj, "fused_requests": fr}
+            log(f"fusion leg {name} {leg}: {r[leg]}")
+        del r["warmup"]
+        r["bitwise_equal"] = all(bool(np.array_equal(outs[k].view(np.uint64), outs["unfused"].view(np.uint64)))
+                                 for k in outs if k != "unfused")
+        r["fused_over_unfused"] = round(r["fused_8"]["req_per_s"] / r["unfused"]["req_per_s"], 3)
+        res[name] = r
+        for p in plans:
+            p.close()
+        for t in tns:
+            t.close()
     return res
 
 

@@ -167,6 +167,10 @@ typedef struct {
   int32_t n_inplace_leaves;      /* leaves whose sliced labels are fixed per
                                     chunk, read in place by the GEMM that
                                     consumes them (no gather per batch)      */
+  int64_t n_launches;            /* launches of one eager run over all slices
+                                    (chunk base copies, leaf preparations,
+                                    GEMMs and their epilogues or grouped
+                                    launches, reductions)                   */
 } tnc_plan_info;
 tnc_status tnc_plan_get_info(tnc_plan plan, tnc_plan_info* out);
 
@@ -361,14 +365,22 @@ tnc_status tnc_serve_set_heavy(tnc_ctx ctx, double heavy_flops, int32_t heavy_sl
  * ranges that split into the same chunks (e.g. amplitudes of several
  * circuits of one geometry and depth, or slice ranges of one sliced
  * network), are admitted together as one job of up to max_requests
- * (default 8; 1 disables fusion) and run in lockstep: every MFMA step of
- * the job is one grouped launch over the requests' GEMMs of that step (one
- * persistent kernel whose workgroups loop over the tiles of all of them).
- * Each request's result is bitwise the one it gets alone: its every output
- * element is computed by the same tile code in the same order.  Applies to
- * admissions from now on; TNC_E_ARG if the context is not serving or
- * max_requests is outside 1..64. */
-tnc_status tnc_serve_set_fusion(tnc_ctx ctx, int32_t max_requests);
+ * (default 8; 1 disables fusion) and run in lockstep with the launches of
+ * one run: every MFMA step is one grouped launch over the requests' GEMMs
+ * of that step (one persistent kernel whose workgroups loop over the tiles
+ * of all of them), and every tree level's small GEMMs and leaf gathers of
+ * all the requests are one launch each.  Only launch-bound requests are
+ * fused: planned FLOP below flops_per_launch times the launches of the
+ * request's own run (tnc_plan_info.n_launches for a whole-range request;
+ * default 2^27, about what ~3 us of launch latency is worth at the small
+ * steps' rate); heavier requests gain nothing and would lose the overlap
+ * of separate streams.  A huge flops_per_launch (e.g. 1e300) fuses every
+ * light request.  Each request's result is bitwise the one it gets alone:
+ * its every output element is computed by the same tile code in the same
+ * order.  Applies to admissions from now on; TNC_E_ARG if the context is
+ * not serving, max_requests is outside 1..64 or flops_per_launch is not
+ * positive. */
+tnc_status tnc_serve_set_fusion(tnc_ctx ctx, int32_t max_requests, double flops_per_launch);
 /* Counters since tnc_serve_start: jobs run (a fused job or a batch of rows
  * counts once), fused jobs, and requests that ran in fused jobs. */
 tnc_status tnc_serve_get_stats(tnc_ctx ctx, int64_t* jobs, int64_t* fused_jobs, int64_t* fused_requests);

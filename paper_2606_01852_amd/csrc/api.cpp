@@ -357,6 +357,7 @@ tnc_status tnc_plan_get_info(tnc_plan plan, tnc_plan_info* out) {
   info.n_permuted_stores = c0.n_perm_stores;
   info.n_cached_leaves = c0.n_cached;
   for (const LeafPrep& lp : c0.leaf) info.n_inplace_leaves += lp.inplace ? 1 : 0;
+  info.n_launches = lockstep_info(p, 0, p.n_slices).launches;
   info.n_result = static_cast<int32_t>(std::min<int64_t>(c0.R, INT32_MAX));
   *out = info;
   TNC_CATCH

@@ -268,7 +268,8 @@ struct Plan {
   std::vector<std::pair<std::pair<hipEvent_t, hipEvent_t>, int>> pending;  // profiling events
   DeviceBuf acc;         // complex128 result accumulator (synchronous calls)
   DeviceBuf norm;        // one double
-  std::mutex mu;         // guards lazy chunk building
+  std::mutex mu;         // guards lazy chunk building and key_prefix
+  std::string key_prefix;  // structure_key's part fixed at creation (built on first use)
   std::mutex graph_mu;   // guards the graph cache
   std::map<GraphKey, hipGraphExec_t> graphs;
   hipStream_t capture_stream = nullptr;
@@ -317,17 +318,25 @@ int64_t run_workspace_bytes(Plan& plan, int64_t first, int64_t count);
 void drain_profile(Plan& plan);
 // Lockstep execution of runs of plans with one structure (fused serving
 // jobs): structure_key identifies plans and slice ranges that can run
-// together; lockstep_table_entries is the grouped-launch table size of n
-// such runs; run_lockstep needs `cap` >= that many entries in pinned host
-// memory (`host`) and device memory (`dev`), and every run's RunArgs on
-// `stream`.
+// together; run_lockstep needs `cap` >= lockstep_table_bytes bytes of pinned
+// host memory and of device memory for the job's tables, and every run's
+// RunArgs on `stream`.
 struct LockstepRun {
   Plan* plan = nullptr;
   RunArgs a;
 };
 std::string structure_key(Plan& plan, int64_t first, int64_t count);
-int64_t lockstep_table_entries(Plan& plan, int64_t first, int64_t count, int n_runs);
-void run_lockstep(std::vector<LockstepRun>& runs, GroupedEntry* host, GroupedEntry* dev, int64_t cap,
+// What a run contributes to a lockstep job: its bytes of the job's tables,
+// the number of sub-tables (each aligned to 256 bytes), and the launches
+// the run issues on its own (eager; the measure of how launch-bound it is).
+struct LockstepInfo {
+  size_t bytes_per_run = 0;
+  int64_t parts = 0;
+  int64_t launches = 0;
+};
+LockstepInfo lockstep_info(Plan& plan, int64_t first, int64_t count);
+size_t lockstep_table_bytes(const LockstepInfo& t, int n_runs);
+void run_lockstep(std::vector<LockstepRun>& runs, void* host_tables, void* dev_tables, size_t cap,
                   hipStream_t stream);
 std::vector<std::pair<int, int64_t>> decompose(const Plan& plan, int64_t first, int64_t count);
 

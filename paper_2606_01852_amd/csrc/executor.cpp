@@ -552,24 +552,33 @@ void run_plan(Plan& plan, const RunArgs& a) {
 std::string structure_key(Plan& plan, int64_t first, int64_t count) {
   std::string k;
   auto put = [&](int64_t v) { k.append(reinterpret_cast<const char*>(&v), sizeof v); };
-  const Net& net = *plan.net;
-  put(net.n_tensors);
-  for (const auto& lab : net.labels) {
-    put(static_cast<int64_t>(lab.size()));
-    for (int l : lab) put(l);
+  {
+    // what a plan fixes at creation (network shape, path, slicing) is keyed
+    // once per plan
+    std::lock_guard<std::mutex> g(plan.mu);
+    if (plan.key_prefix.empty()) {
+      const Net& net = *plan.net;
+      put(net.n_tensors);
+      for (const auto& lab : net.labels) {
+        put(static_cast<int64_t>(lab.size()));
+        for (int l : lab) put(l);
+      }
+      put(static_cast<int64_t>(net.extents.size()));
+      for (int64_t e : net.extents) put(e);
+      put(static_cast<int64_t>(net.open.size()));
+      for (int l : net.open) put(l);
+      for (const auto& pr : plan.pairs) put(pr[0] * int64_t{1 << 30} + pr[1]);
+      put(static_cast<int64_t>(plan.sliced.size()));
+      for (int l : plan.sliced) put(l);
+      plan.key_prefix = k;
+    }
+    k = plan.key_prefix;
   }
-  put(static_cast<int64_t>(net.extents.size()));
-  for (int64_t e : net.extents) put(e);
-  put(static_cast<int64_t>(net.open.size()));
-  for (int l : net.open) put(l);
-  for (const auto& pr : plan.pairs) put(pr[0] * int64_t{1 << 30} + pr[1]);
-  put(static_cast<int64_t>(plan.sliced.size()));
-  for (int l : plan.sliced) put(l);
   put(plan.prec);
   put(plan.form);
   put(plan.grouping);
   put(plan.store_order);
-  put(net.ctx->gemm_variant);
+  put(plan.net->ctx->gemm_variant);
   put(static_cast<int64_t>(plan.volatile_leaf.size()));
   for (char v : plan.volatile_leaf) put(v);
   const auto chunks = decompose(plan, first, count);
@@ -589,19 +598,60 @@ std::string structure_key(Plan& plan, int64_t first, int64_t count) {
   return k;
 }
 
-int64_t lockstep_table_entries(Plan& plan, int64_t first, int64_t count, int n_runs) {
+namespace {
+
+constexpr size_t kTableAlign = 256;
+size_t table_align(size_t x) { return (x + kTableAlign - 1) / kTableAlign * kTableAlign; }
+
+}  // namespace
+
+LockstepInfo lockstep_info(Plan& plan, int64_t first, int64_t count) {
+  LockstepInfo t;
   const auto chunks = decompose(plan, first, count);
   std::vector<char> seen(plan.chunks.size(), 0);
-  int64_t e = 0;
   for (auto& c : chunks) {
+    const ChunkPlan& cp = plan.chunk(c.first);
+    // launches of this chunk in a run of its own (enqueue_chunk's order)
+    auto step_launches = [&](const StepPlan& sp) { return 1 + (sp.split > 1 || sp.trans ? 1 : 0); };
+    int64_t nl = 1 + (cp.n_base_slots ? 1 : 0);  // reduction, chunk bases
+    if (cp.steps.empty() && !cp.leaf[0].direct) ++nl;
+    if (cp.grouped) {
+      for (const LevelPlan& lv : cp.levels) {
+        nl += (lv.group_leaves.empty() ? 0 : 1) + (lv.group_steps.empty() ? 0 : 1);
+        nl += static_cast<int64_t>(lv.single_leaves.size());
+        for (int s : lv.single_steps) nl += step_launches(cp.steps[s]);
+      }
+    } else {
+      for (const StepPlan& sp : cp.steps) nl += static_cast<int64_t>(sp.preps.size()) + step_launches(sp);
+    }
+    t.launches += nl;
     if (seen[c.first]) continue;
     seen[c.first] = 1;
-    for (const StepPlan& sp : plan.chunk(c.first).steps) e += sp.kind == GemmKernel::MFMA ? n_runs : 0;
+    for (const StepPlan& sp : cp.steps)
+      if (sp.kind == GemmKernel::MFMA) {
+        t.bytes_per_run += sizeof(GroupedEntry);
+        t.parts += 1;
+      }
+    if (!cp.grouped) continue;
+    for (const LevelPlan& lv : cp.levels) {
+      if (!lv.group_steps.empty()) {
+        t.bytes_per_run += lv.group_steps.size() * (sizeof(GroupGemm) + sizeof(int64_t));
+        t.parts += 2;
+      }
+      if (!lv.group_leaves.empty()) {
+        t.bytes_per_run += lv.group_leaves.size() * (sizeof(GroupGather) + sizeof(int64_t));
+        t.parts += 2;
+      }
+    }
   }
-  return e;
+  return t;
 }
 
-void run_lockstep(std::vector<LockstepRun>& runs, GroupedEntry* host, GroupedEntry* dev, int64_t cap,
+size_t lockstep_table_bytes(const LockstepInfo& t, int n_runs) {
+  return static_cast<size_t>(n_runs) * t.bytes_per_run + static_cast<size_t>(t.parts) * kTableAlign + kTableAlign;
+}
+
+void run_lockstep(std::vector<LockstepRun>& runs, void* host_tables, void* dev_tables, size_t cap,
                   hipStream_t stream) {
   const int K = static_cast<int>(runs.size());
   if (K < 1) return;
@@ -620,43 +670,123 @@ void run_lockstep(std::vector<LockstepRun>& runs, GroupedEntry* host, GroupedEnt
     std::vector<std::unique_ptr<ChunkOps>> ops;
     const int j = rb[0].chunks[c].first;
     for (int r = 0; r < K; ++r)
-      ops.emplace_back(new ChunkOps{*runs[r].plan, *runs[r].plan->chunks[j], runs[r].a,
-                                    rb[r].bases_dev + c * rb[r].slots, stream, none});
+      ops.emplace_back(new ChunkOps{*runs[r].plan, *runs[r].plan->chunks[j], runs[r].a, rb[r].cur_dev, stream, none});
     return ops;
   };
-  // grouped tables of every MFMA step of every chunk plan used, uploaded once
-  std::map<std::pair<int, int>, std::pair<int64_t, int64_t>> grouped;  // (j, step) -> (first entry, tiles)
-  int64_t used = 0;
+  // Tables of the job, built once on the host and uploaded once: per MFMA
+  // step the K runs' GEMMs (grouped launch), per tree level the K runs'
+  // small GEMMs and plain gathers as one table each, with absolute
+  // pointers (every run has its own arena and base offsets).  Tables serve
+  // every chunk of a chunk plan, so leaf bases are read from each run's
+  // "current chunk" slot, refreshed before the chunk's first launch.
+  char* host = static_cast<char*>(host_tables);
+  char* dev = static_cast<char*>(dev_tables);
+  size_t used = 0;
+  auto take = [&](size_t bytes) -> size_t {
+    const size_t off = table_align(used);
+    if (off + bytes > cap) fail(TNC_E_NOMEM, "grouped-launch tables exceed their buffer");
+    used = off + bytes;
+    return off;
+  };
+  struct LevelTabs {
+    size_t gemm = 0, gemm_pre = 0, gath = 0, gath_pre = 0;
+    int n_gemm = 0, n_gath = 0;
+    int64_t gemm_total = 0, gath_total = 0;
+  };
+  std::map<std::pair<int, int>, std::pair<size_t, int64_t>> grouped;  // (j, step) -> (offset, tiles)
+  std::map<std::pair<int, int>, LevelTabs> levtabs;                   // (j, level)
+  std::vector<char> built(p0.chunks.size(), 0);
   for (size_t c = 0; c < rb[0].chunks.size(); ++c) {
     const int j = rb[0].chunks[c].first;
+    if (built[j]) continue;
+    built[j] = 1;
     const ChunkPlan& cp0 = *p0.chunks[j];
-    if (grouped.count({j, -1})) continue;
-    grouped[{j, -1}] = {0, 0};
     auto ops = ops_of(c);
     for (int s = 0; s < static_cast<int>(cp0.steps.size()); ++s) {
       if (cp0.steps[s].kind != GemmKernel::MFMA) continue;
       const int v = ops[0]->variant(cp0.steps[s]);
-      bool ok = used + K <= cap;
+      bool ok = true;
       for (int r = 0; ok && r < K; ++r) {
         const StepPlan& sp = ops[r]->cp.steps[s];
         ok = sp.kind == GemmKernel::MFMA && ops[r]->variant(sp) == v;
       }
       if (!ok) continue;
-      for (int r = 0; r < K; ++r) host[used + r].d = ops[r]->desc(s);
-      const int64_t total = grouped_layout(host + used, K, v);
-      if (total <= 0) continue;
-      grouped[{j, s}] = {used, total};
-      used += K;
+      const size_t off = take(K * sizeof(GroupedEntry));
+      auto* e = reinterpret_cast<GroupedEntry*>(host + off);
+      for (int r = 0; r < K; ++r) {
+        std::memset(&e[r], 0, sizeof(GroupedEntry));
+        e[r].d = ops[r]->desc(s);
+      }
+      const int64_t total = grouped_layout(e, K, v);
+      if (total > 0) grouped[{j, s}] = {off, total};
+    }
+    if (!cp0.grouped) continue;
+    for (size_t li = 0; li < cp0.levels.size(); ++li) {
+      LevelTabs t;
+      const LevelPlan& lv0 = cp0.levels[li];
+      t.n_gemm = K * static_cast<int>(lv0.group_steps.size());
+      t.n_gath = K * static_cast<int>(lv0.group_leaves.size());
+      if (t.n_gemm) {
+        t.gemm = take(t.n_gemm * sizeof(GroupGemm));
+        t.gemm_pre = take(t.n_gemm * sizeof(int64_t));
+        auto* tab = reinterpret_cast<GroupGemm*>(host + t.gemm);
+        auto* pre = reinterpret_cast<int64_t*>(host + t.gemm_pre);
+        int q = 0;
+        for (int r = 0; r < K; ++r) {
+          const ChunkPlan& cp = ops[r]->cp;
+          const LevelPlan& lv = cp.levels[li];
+          const auto* src = reinterpret_cast<const GroupGemm*>(cp.host_blob.data() + lv.off_gemm);
+          char* ar = runs[r].a.arena;
+          for (size_t x = 0; x < lv.group_steps.size(); ++x, ++q) {
+            GroupGemm g = src[x];
+            if (g.rel_a) g.d.A = reinterpret_cast<const float2*>(ar + reinterpret_cast<intptr_t>(g.d.A));
+            if (g.rel_b) g.d.B = reinterpret_cast<const float2*>(ar + reinterpret_cast<intptr_t>(g.d.B));
+            if (g.rel_c) g.d.C = reinterpret_cast<float2*>(ar + reinterpret_cast<intptr_t>(g.d.C));
+            g.rel_a = g.rel_b = g.rel_c = 0;
+            if (g.slot_a >= 0) g.d.baseA = rb[r].cur_dev + g.slot_a;
+            if (g.slot_b >= 0) g.d.baseB = rb[r].cur_dev + g.slot_b;
+            g.slot_a = g.slot_b = -1;
+            tab[q] = g;
+            pre[q] = t.gemm_total;
+            t.gemm_total += g.d.h * g.d.m * g.d.n;
+          }
+        }
+      }
+      if (t.n_gath) {
+        t.gath = take(t.n_gath * sizeof(GroupGather));
+        t.gath_pre = take(t.n_gath * sizeof(int64_t));
+        auto* tab = reinterpret_cast<GroupGather*>(host + t.gath);
+        auto* pre = reinterpret_cast<int64_t*>(host + t.gath_pre);
+        int q = 0;
+        for (int r = 0; r < K; ++r) {
+          const ChunkPlan& cp = ops[r]->cp;
+          const LevelPlan& lv = cp.levels[li];
+          const auto* src = reinterpret_cast<const GroupGather*>(cp.host_blob.data() + lv.off_gather);
+          for (size_t x = 0; x < lv.group_leaves.size(); ++x, ++q) {
+            GroupGather g = src[x];
+            g.out_abs = reinterpret_cast<float2*>(runs[r].a.arena + g.out_off);
+            g.base_abs = g.base_slot >= 0 ? rb[r].cur_dev + g.base_slot : nullptr;
+            g.base_slot = -1;
+            tab[q] = g;
+            pre[q] = t.gath_total;
+            t.gath_total += cp.numel[lv.group_leaves[x]];
+          }
+        }
+      }
+      levtabs[{j, static_cast<int>(li)}] = t;
     }
   }
   if (used)
-    check_hip(hipMemcpyAsync(dev, host, static_cast<size_t>(used) * sizeof(GroupedEntry), hipMemcpyHostToDevice,
-                             stream),
-              "upload grouped GEMM tables");
+    check_hip(hipMemcpyAsync(dev, host, used, hipMemcpyHostToDevice, stream), "upload grouped tables");
   for (size_t c = 0; c < rb[0].chunks.size(); ++c) {
     const int j = rb[0].chunks[c].first;
     auto ops = ops_of(c);
     const ChunkPlan& cp0 = *p0.chunks[j];
+    for (int r = 0; r < K; ++r)  // the chunk's leaf bases into each run's current slot
+      if (ops[r]->cp.n_base_slots)
+        check_hip(hipMemcpyAsync(rb[r].cur_dev, rb[r].bases_dev + c * rb[r].slots, rb[r].slots * sizeof(int64_t),
+                                 hipMemcpyDeviceToDevice, stream),
+                  "chunk bases");
     auto gemm = [&](int s) {
       auto it = grouped.find({j, s});
       if (it == grouped.end()) {
@@ -664,7 +794,8 @@ void run_lockstep(std::vector<LockstepRun>& runs, GroupedEntry* host, GroupedEnt
         return;
       }
       const int v = ops[0]->variant(cp0.steps[s]);
-      check_hip(launch_gemm_grouped(dev + it->second.first, K, it->second.second, v, form, prec, stream),
+      check_hip(launch_gemm_grouped(reinterpret_cast<const GroupedEntry*>(dev + it->second.first), K,
+                                    it->second.second, v, form, prec, stream),
                 "grouped GEMM launch");
       for (auto& op : ops) op->finish(s);
     };
@@ -674,18 +805,25 @@ void run_lockstep(std::vector<LockstepRun>& runs, GroupedEntry* host, GroupedEnt
         if (!op->cp.leaf[0].direct) op->prep(0);
     if (cp0.grouped) {
       for (size_t li = 0; li < cp0.levels.size(); ++li) {
-        for (auto& op : ops) {
-          const LevelPlan& lv = op->cp.levels[li];
-          op->level_gathers(lv);
-          for (int t : lv.single_leaves) op->prep(t);
-          op->level_small_gemms(lv);
-        }
+        const LevelTabs& t = levtabs.at({j, static_cast<int>(li)});
+        if (t.n_gath)
+          check_hip(launch_group_gather(reinterpret_cast<const GroupGather*>(dev + t.gath),
+                                        reinterpret_cast<const int64_t*>(dev + t.gath_pre), t.n_gath, t.gath_total,
+                                        nullptr, nullptr, stream),
+                    "grouped gathers");
+        for (auto& op : ops)
+          for (int tl : op->cp.levels[li].single_leaves) op->prep(tl);
+        if (t.n_gemm)
+          check_hip(launch_group_gemm(reinterpret_cast<const GroupGemm*>(dev + t.gemm),
+                                      reinterpret_cast<const int64_t*>(dev + t.gemm_pre), t.n_gemm, t.gemm_total,
+                                      nullptr, nullptr, prec, stream),
+                    "grouped small GEMMs");
         for (int s : cp0.levels[li].single_steps) gemm(s);
       }
     } else {
       for (int s = 0; s < ns; ++s) {
         for (auto& op : ops)
-          for (int t : op->cp.steps[s].preps) op->prep(t);
+          for (int tl : op->cp.steps[s].preps) op->prep(tl);
         gemm(s);
       }
     }

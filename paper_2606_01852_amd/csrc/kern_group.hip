@@ -52,8 +52,8 @@ __global__ __launch_bounds__(256) void group_small_gemm(const GroupGemm* __restr
     float2* C = reloc<float2>(d.C, e.rel_c, arena);
     float cr = 0.f, ci = 0.f, crx = 0.f, cix = 0.f;
     if (d.kA || d.kB) {  // in-place leaf operands (tables, per-chunk base offsets)
-      A += (e.slot_a >= 0 ? bases[e.slot_a] : 0) + (d.rowA ? d.rowA[i] : i * row_stride(d));
-      B += (e.slot_b >= 0 ? bases[e.slot_b] : 0) + (d.rowB ? d.rowB[j] : j * row_stride(d));
+      A += (e.slot_a >= 0 ? bases[e.slot_a] : (d.baseA ? *d.baseA : 0)) + (d.rowA ? d.rowA[i] : i * row_stride(d));
+      B += (e.slot_b >= 0 ? bases[e.slot_b] : (d.baseB ? *d.baseB : 0)) + (d.rowB ? d.rowB[j] : j * row_stride(d));
       cdot_tables<SPLIT>(A, d.kA, B, d.kB, d.k, cr, ci, crx, cix);
     } else {
       cdot_serial<SPLIT>(A + i * row_stride(d), B + j * row_stride(d), d.k, cr, ci, crx, cix);
@@ -73,14 +73,14 @@ __global__ __launch_bounds__(256) void group_gather(const GroupGather* __restric
     const int s = find_item(prefix, n, gt);
     const GroupGather& e = g[s];
     int64_t rest = gt - prefix[s];
-    int64_t off = e.base_slot >= 0 ? bases[e.base_slot] : 0;
+    int64_t off = e.base_abs ? *e.base_abs : (e.base_slot >= 0 ? bases[e.base_slot] : 0);
     for (int j = e.rank - 1; j >= 0; --j) {
       const int64_t x = e.ext[j];
       const int64_t q = rest / x;
       off += (rest - q * x) * e.in_stride[j];
       rest = q;
     }
-    float2* out = reinterpret_cast<float2*>(arena + e.out_off);
+    float2* out = e.out_abs ? e.out_abs : reinterpret_cast<float2*>(arena + e.out_off);
     out[gt - prefix[s]] = e.in[off];
   }
 }

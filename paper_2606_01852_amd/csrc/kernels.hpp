@@ -156,8 +156,14 @@ struct GroupGather {
   int32_t base_slot;    // slot of the chunk's base offset (-1: none)
   int64_t ext[kGroupRank];
   int64_t in_stride[kGroupRank];
+  // absolute forms (tables that mix several runs, each with its own arena
+  // and base offsets): used when set
+  float2* out_abs;
+  const int64_t* base_abs;
 };
 // prefix[i] = first work item of entry i (work items: output elements).
+// An in-place operand's base offset comes from bases[slot_a] when slot_a >=
+// 0, else from *d.baseA when set (tables mixing several runs).
 hipError_t launch_group_gemm(const GroupGemm* table, const int64_t* prefix, int n, int64_t total, char* arena,
                              const int64_t* bases, Prec prec, hipStream_t s);
 hipError_t launch_group_gather(const GroupGather* table, const int64_t* prefix, int n, int64_t total, char* arena,

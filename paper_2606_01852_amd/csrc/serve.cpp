@@ -25,10 +25,12 @@
 // Light requests whose plans have one structure (the same network shape,
 // path, slicing, precision, chunking and tile variants: e.g. amplitudes of
 // several circuits of one geometry, or slice ranges of one network) are
-// fused: a worker that admits such a request also admits up to
-// fuse_max - 1 queued requests with the same structure key, and runs them
-// in lockstep, every MFMA step as one grouped launch over all of them.  Each
-// result is bitwise the one the request gets alone.
+// fused when they are launch-bound (kFuseFlopsPerLaunch): a worker that
+// admits such a request also admits up to fuse_max - 1 queued requests with
+// the same structure key, and runs them in lockstep with the launches of
+// one run: every MFMA step and every tree level's small GEMMs and gathers
+// as one grouped launch over all of them.  Each result is bitwise the one
+// the request gets alone.
 //
 // On a host-only context the server admits and queues exactly as it would
 // on a device (admission by planned arena bytes, the heavy lane, batcher
@@ -115,7 +117,7 @@ struct Request {
   bool token = false;                // stands for the batcher's waiting rows in the queue
   std::vector<float2> row;           // row values of the listed leaves (complex64)
   std::string key;                   // structure key (fusable light request), or empty
-  int64_t table_entries = 0;         // grouped-launch table entries of one run
+  LockstepInfo tables;               // its share of a fused job's tables
   int64_t table_off = -1, table_bytes = 0;  // a fused job's table (first request of the job)
   Clock::time_point t_submit, t_done;
   bool done = false;
@@ -140,6 +142,13 @@ struct Server {
   std::vector<void*> pinned_tab;        // per slot: pinned staging of grouped-launch tables
   std::vector<size_t> pinned_tab_bytes;
   int fuse_max = 8;                     // requests per fused job (1: no fusion)
+  // A light request is fused only if it is launch-bound: planned FLOP below
+  // this many per launch of its own run.  A dependent launch costs ~3 us and
+  // the small steps of such requests sustain ~45 TFLOP/s, so below ~1.3e8
+  // FLOP per launch (the default, 2^27) a run waits on launches rather than
+  // on arithmetic, and fusing shares those launches; heavier requests gain
+  // nothing from it and lose the overlap of separate streams.
+  double fuse_flops_per_launch = 134217728.0;
   int64_t n_jobs = 0, n_fused_jobs = 0, n_fused_requests = 0;
   ArenaAllocator arena;
   bool stop = false;
@@ -307,8 +316,7 @@ struct Server {
       it = queue.erase(it);
     }
     if (job.size() == 1) return;
-    r0.table_bytes = std::max<int64_t>(1, r0.table_entries * static_cast<int64_t>(job.size())) *
-                     static_cast<int64_t>(sizeof(GroupedEntry));
+    r0.table_bytes = static_cast<int64_t>(lockstep_table_bytes(r0.tables, static_cast<int>(job.size())));
     r0.table_off = arena.alloc(r0.table_bytes);
     if (r0.table_off >= 0) return;
     // no room for the table: the others go back to the front of the queue
@@ -449,11 +457,8 @@ struct Server {
         res_total += static_cast<size_t>(r.plan->chunks[0]->R) * 16;
       }
       Request& r0 = *job[0];
-      const int64_t cap = r0.table_bytes / static_cast<int64_t>(sizeof(GroupedEntry));
-      auto* host_tab = static_cast<GroupedEntry*>(
-          staging(pinned_tab, pinned_tab_bytes, slot, static_cast<size_t>(r0.table_bytes)));
-      auto* dev_tab = reinterpret_cast<GroupedEntry*>(ctx.arena + r0.table_off);
-      run_lockstep(runs, host_tab, dev_tab, cap, stream);
+      void* host_tab = staging(pinned_tab, pinned_tab_bytes, slot, static_cast<size_t>(r0.table_bytes));
+      run_lockstep(runs, host_tab, ctx.arena + r0.table_off, static_cast<size_t>(r0.table_bytes), stream);
       char* host = static_cast<char*>(staging(pinned, pinned_bytes, slot, res_total));
       size_t off = 0;
       for (int q = 0; q < K; ++q) {
@@ -562,13 +567,14 @@ tnc_status tnc_serve_set_heavy(tnc_ctx ctx, double heavy_flops, int32_t heavy_sl
   TNC_CATCH
 }
 
-tnc_status tnc_serve_set_fusion(tnc_ctx ctx, int32_t max_requests) {
+tnc_status tnc_serve_set_fusion(tnc_ctx ctx, int32_t max_requests, double flops_per_launch) {
   TNC_TRY
-  if (!ctx || !ctx->c->server || max_requests < 1 || max_requests > 64)
+  if (!ctx || !ctx->c->server || max_requests < 1 || max_requests > 64 || !(flops_per_launch > 0))
     fail(TNC_E_ARG, "bad arguments or server not started");
   Server& s = *ctx->c->server;
   std::lock_guard<std::mutex> g(s.mu);
   s.fuse_max = max_requests;
+  s.fuse_flops_per_launch = flops_per_launch;
   TNC_CATCH
 }
 
@@ -619,13 +625,16 @@ tnc_status tnc_submit(tnc_ctx ctx, tnc_plan plan, int64_t first_slice, int64_t n
                             std::to_string(c.arena_bytes));
     {
       bool fuse = false;
+      double per_launch = 0;
       {
         std::lock_guard<std::mutex> g(s->mu);
         fuse = s->fuse_max > 1 && !(s->heavy_flops > 0 && r->flops >= s->heavy_flops);
+        per_launch = s->fuse_flops_per_launch;
       }
       if (fuse) {  // light request: may share grouped launches with others of its structure
-        r->key = structure_key(p, first_slice, n_slices);
-        r->table_entries = lockstep_table_entries(p, first_slice, n_slices, 1);
+        r->tables = lockstep_info(p, first_slice, n_slices);
+        if (r->flops < static_cast<double>(r->tables.launches) * per_launch)
+          r->key = structure_key(p, first_slice, n_slices);
       }
     }
     {

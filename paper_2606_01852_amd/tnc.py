@@ -40,7 +40,7 @@ class PlanInfo(C.Structure):
                 ("max_intermediate", C.c_int64), ("peak_bytes", C.c_int64), ("max_chunk", C.c_int64),
                 ("chunk_peak_bytes", C.c_int64), ("chunk_flops", C.c_double), ("n_steps", C.c_int32), ("n_permutes", C.c_int32),
                 ("n_permuted_stores", C.c_int32), ("n_result", C.c_int32), ("n_cached_leaves", C.c_int32),
-                ("n_inplace_leaves", C.c_int32)]
+                ("n_inplace_leaves", C.c_int32), ("n_launches", C.c_int64)]
 
 
 class StepInfo(C.Structure):
@@ -106,7 +106,7 @@ _SIGS = {
     "tnc_serve_start": (C.c_int, [_P, C.c_int32, C.c_int32]),
     "tnc_serve_stop": (C.c_int, [_P]),
     "tnc_serve_set_heavy": (C.c_int, [_P, C.c_double, C.c_int32]),
-    "tnc_serve_set_fusion": (C.c_int, [_P, C.c_int32]),
+    "tnc_serve_set_fusion": (C.c_int, [_P, C.c_int32, C.c_double]),
     "tnc_serve_get_stats": (C.c_int, [_P, _I64P, _I64P, _I64P]),
     "tnc_submit": (C.c_int, [_P, _P, C.c_int64, C.c_int64, _DP, C.POINTER(C.c_uint64)]),
     "tnc_batcher_create": (C.c_int, [_P, C.c_int32, C.c_int32, _I32P, C.POINTER(_P)]),
@@ -358,8 +358,12 @@ def tnc_serve_set_heavy(ctx: int, heavy_flops: float, heavy_slots: int = 1) -> N
     _check(lib().tnc_serve_set_heavy(ctx, float(heavy_flops), int(heavy_slots)))
 
 
-def tnc_serve_set_fusion(ctx: int, max_requests: int) -> None:
-    _check(lib().tnc_serve_set_fusion(ctx, max_requests))
+FUSE_FLOPS_PER_LAUNCH = float(2 ** 27)   # the server's default fusion criterion
+FUSE_ALL = 1e300                          # fuse every light request of one structure
+
+
+def tnc_serve_set_fusion(ctx: int, max_requests: int, flops_per_launch: float = FUSE_FLOPS_PER_LAUNCH) -> None:
+    _check(lib().tnc_serve_set_fusion(ctx, max_requests, flops_per_launch))
 
 
 def tnc_serve_get_stats(ctx: int):

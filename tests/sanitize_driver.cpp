@@ -343,8 +343,9 @@ void serve_exercise(const std::vector<NetFile>& files, int submitters) {
     expect(tnc_serve_start(ctx, 6, 1 << 14) == TNC_OK, "serve_start", F);
     expect(tnc_serve_start(ctx, 6, 16) == TNC_E_BUSY, "second server", F);
     expect(tnc_serve_set_heavy(ctx, round ? 1e6 : 0.0, 2) == TNC_OK, "heavy lane", F);
-    expect(tnc_serve_set_fusion(ctx, round ? 4 : 1) == TNC_OK, "fusion", F);
-    expect(tnc_serve_set_fusion(ctx, 0) == TNC_E_ARG, "fusion limit", F);
+    expect(tnc_serve_set_fusion(ctx, round ? 4 : 1, round ? 1e300 : 134217728.0) == TNC_OK, "fusion", F);
+    expect(tnc_serve_set_fusion(ctx, 0, 1.0) == TNC_E_ARG, "fusion limit", F);
+    expect(tnc_serve_set_fusion(ctx, 4, 0.0) == TNC_E_ARG, "fusion criterion", F);
     tnc_plan p0 = es[0].plan;
     int32_t rank = 0;
     double out[2] = {0, 0};

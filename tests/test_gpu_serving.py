@@ -575,13 +575,14 @@ def test_concurrent_submitters_and_waiters(served):
     tn_ref.close()
 
 
-def _serve_each(ctx, items, fuse):
+def _serve_each(ctx, items, fuse, flops_per_launch=tnc.FUSE_ALL):
     """Serve (plan, first, count) items with one slot; with `fuse`, a slow
     request queued first lets the items queue up behind it, so that the
-    worker admits them together.  Returns the outputs and the server's
-    (jobs, fused jobs, fused requests)."""
+    worker admits them together (by default every light request of one
+    structure is fused, launch-bound or not).  Returns the outputs and the
+    server's (jobs, fused jobs, fused requests)."""
     tnc.tnc_serve_start(ctx.handle, 1, 1024)
-    tnc.tnc_serve_set_fusion(ctx.handle, 8 if fuse else 1)
+    tnc.tnc_serve_set_fusion(ctx.handle, 8 if fuse else 1, flops_per_launch)
     blocker = None
     if fuse:
         circ = random_circuit(6, 6, 10, seed=8100)       # 1.5e12 FLOP: ~10 ms of work ahead of the items
@@ -658,6 +659,39 @@ def test_fused_requests_are_bitwise_alone(served, prec, form):
     for i, (m, ref) in enumerate(zip(mix, refs)):
         scale = abs(ref) if i < 6 else rms     # single slices: Porter-Thomas, bounded by the rms
         assert abs(complex(m[0]) - ref) <= tol * scale, (i, complex(m[0]), ref)
+    for tn, p in handles:
+        p.close()
+        tn.close()
+
+
+def test_fusion_takes_only_launch_bound_requests(served):
+    """The server's default criterion fuses a light request only if it is
+    launch-bound (planned FLOP below 2^27 per launch of its own run): six
+    4x5-grid circuits of depth 10 (2.4e8 FLOP over 18 launches) queued
+    behind a slow request run as one fused job; six 5x5-grid circuits of
+    depth 10 (8.9e9 FLOP over 20 launches) queued with them run one by one.
+    Every result is bitwise the one the request gets alone."""
+    ctx = served[0]
+    items, handles, launch_bound = [], [], []
+    for rows, cols in ((4, 5), (5, 5)):
+        ns = 1 if rows == 4 else 2
+        for seed in range(6):
+            net = circuit_network(random_circuit(rows, cols, 10, seed=8300 + seed))
+            path = greedy_path(net)
+            sl = greedy_slice(net, path.pairs, n_sliced=ns)
+            tn = tnc.Network(ctx, net.labels, net.extents, net.open, net.c64().leaves)
+            p = tnc.Plan(tn, path.pairs, sl)
+            handles.append((tn, p))
+            items.append((p, 0, p.info.n_slices))
+            info = tnc.tnc_plan_get_info(p.handle)
+            launch_bound.append(info.flops_per_slice * info.n_slices < info.n_launches * tnc.FUSE_FLOPS_PER_LAUNCH)
+    assert launch_bound == [True] * 6 + [False] * 6
+    alone, _ = _serve_each(ctx, items, fuse=False)
+    mix, st = _serve_each(ctx, items, fuse=True, flops_per_launch=tnc.FUSE_FLOPS_PER_LAUNCH)
+    print(f"fusion criterion: {st}", flush=True)
+    assert st == (1 + 1 + 6, 1, 6)       # blocker, one fused job of the six 4x5 circuits, six 5x5 alone
+    for i, (a, m) in enumerate(zip(alone, mix)):
+        assert np.array_equal(a.view(np.uint64), m.view(np.uint64)), i
     for tn, p in handles:
         p.close()
         tn.close()
