@@ -945,11 +945,15 @@ def main():
     # plan on the host first to size the arena
     hctx = tnc.Context(-1)
     sizes = []
+    forms = [(prec, form)]
+    if not args.no_forms and args.form == "4M" and args.prec == "c64":
+        forms += [(tnc.PREC_C64, tnc.GEMM_3M), (tnc.PREC_BF16X3, tnc.GEMM_4M)]
     for net, path in ((net_a, path_a), (net_b, path_b)):
         tn = tnc.Network(hctx, net.labels, net.extents, net.open)
-        p = tnc.Plan(tn, path.pairs, (), prec, form)
-        sizes.append(p.info.peak_bytes)
-        p.close()
+        for fp, ff in forms:   # split precision also holds its operands' bf16 planes
+            p = tnc.Plan(tn, path.pairs, (), fp, ff)
+            sizes.append(p.info.peak_bytes)
+            p.close()
         tn.close()
     arena_bytes = max(sizes) + (64 << 20)
     arena = torch.empty(arena_bytes, dtype=torch.uint8, device=dev)
@@ -1074,7 +1078,8 @@ def main():
             res["other_forms"][name] = {
                 "tflops": round(flops_step / fdt / 1e12, 3), "ms_per_step": round(fdt * 1e3, 3),
                 "gemm_tflops": round(gt, 3), "gemm_frac_of_executed_mfma_peak": round(executed, 4),
-                "variant": tnc.tnc_plan_get_step(pa.handle, 0).variant}
+                "variant": tnc.tnc_plan_get_step(pa.handle, 0).variant,
+                "presplit": bool(tnc.tnc_plan_get_step(pa.handle, 0).presplit)}
             kept[name] = (out_a[:rows_a].cpu().numpy(), out_b[:rows_b].cpu().numpy())
             log(f"form {name}: {res['other_forms'][name]}")
             pa.close()

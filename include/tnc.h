@@ -191,6 +191,10 @@ typedef struct {
   int64_t hA, hB;                /* batch entries A and B hold (1 = broadcast
                                     over the batch): the algorithmic bytes of
                                     the step are 8 (hA m k + hB n k + h m n)  */
+  int32_t presplit;              /* 1 = split-bf16x3 step whose operands are
+                                    split once into bf16 planes (in the plan's
+                                    arena) and staged global -> LDS directly;
+                                    bitwise the result of variant 3          */
 } tnc_step_info;
 tnc_status tnc_plan_get_step(tnc_plan plan, int32_t step, tnc_step_info* out);
 /* The same view for the batch of max_chunk slices the executor runs (h then

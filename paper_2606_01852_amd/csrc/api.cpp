@@ -385,6 +385,7 @@ static void step_info(const ChunkPlan& c, int32_t step, tnc_step_info* out) {
   i.split = s.split;
   i.hA = s.hA;
   i.hB = s.hB;
+  i.presplit = s.presplit ? 1 : 0;
   *out = i;
 }
 

@@ -175,6 +175,10 @@ struct StepPlan {
   // this permutation writes it in the consumer's order
   bool trans = false;
   PermuteHost tperm;
+  // split precision on operands split once into bf16 planes (large steps of
+  // one batch entry): the planes live in this arena buffer during the step
+  bool presplit = false;
+  int presplit_buf = -1;
   // in-place operand tables (launch orientation): rowA, kA, rowB, kB
   std::vector<int64_t> tab[4];
   int64_t off_tab[4] = {-1, -1, -1, -1};

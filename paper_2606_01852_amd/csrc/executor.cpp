@@ -320,10 +320,18 @@ struct ChunkOps {
       return launch_splitk_reduce(d.C, c, sp.h, sp.lm, sp.ln, sp.split, sp.dev_offM, sp.dev_offN, stream);
     });
   }
+  // a forced tile variant (tnc_ctx_set_gemm_variant) runs every MFMA step
+  // on that variant, pre-split steps included
+  bool presplit(const StepPlan& sp) const { return sp.presplit && net.ctx->gemm_variant < 0; }
   void step(int s) {
     const StepPlan& sp = cp.steps[s];
     const GemmDesc d = desc(s);
-    L.run(s, stream, [&] { return launch_gemm(d, sp.kind, variant(sp), form, prec, stream); });
+    if (presplit(sp)) {
+      void* planes = a.arena + cp.buf_off[sp.presplit_buf];
+      L.run(s, stream, [&] { return launch_gemm_presplit(d, planes, stream); });
+    } else {
+      L.run(s, stream, [&] { return launch_gemm(d, sp.kind, variant(sp), form, prec, stream); });
+    }
     finish(s);
   }
   void level_gathers(const LevelPlan& lv) {
@@ -703,7 +711,7 @@ void run_lockstep(std::vector<LockstepRun>& runs, void* host_tables, void* dev_t
     const ChunkPlan& cp0 = *p0.chunks[j];
     auto ops = ops_of(c);
     for (int s = 0; s < static_cast<int>(cp0.steps.size()); ++s) {
-      if (cp0.steps[s].kind != GemmKernel::MFMA) continue;
+      if (cp0.steps[s].kind != GemmKernel::MFMA || ops[0]->presplit(cp0.steps[s])) continue;
       const int v = ops[0]->variant(cp0.steps[s]);
       bool ok = true;
       for (int r = 0; ok && r < K; ++r) {

@@ -755,6 +755,205 @@ __global__ __launch_bounds__(64 * WM * WN, (WM * WN <= 4) ? 2 : 1) void cgemm_mf
   }
 }
 
+// ------------------------------------------ split-bf16x3 on pre-split planes
+// Large split-precision steps split each operand once, into bf16 planes in
+// global memory, instead of in the staging of every workgroup that reads
+// it.  A row of A (or of the 4M real operand B': row 2c = (br, -bi, ...),
+// row 2c + 1 = (bi, br, ...)) is stored in blocks of 16 complex k, 128
+// bytes = [32 bf16 hi | 32 bf16 lo] of its 32 floats; rows are padded to
+// the tile and k to 16 with zeros, so staging needs no bounds tests and
+// moves blocks straight from global memory into LDS (16 bytes per lane,
+// global_load_lds_dwordx4: no registers and no VALU on the way).  The split
+// is the staging kernels' (round to nearest even, lo = rne(x - hi)) and the
+// tile's products and accumulation order are those of OpsBF16x3W, so the
+// result is bitwise that of the wide-wave kernel.
+//
+// LDS: two stages of four unpadded planes (256 rows x 64 bytes each); the
+// four 16-byte slots of a row are permuted by row (slot = chunk ^ ((row >> 2)
+// & 3)), so that the fragment reads of 16 lanes (16 rows, one chunk) hit 16
+// distinct 4-bank groups.  Each stage has one barrier, in its middle: the
+// waves issue the first half's MFMAs (whose fragments they read during the
+// previous half) and read the second half's fragments, then meet; after the
+// barrier the stage's loads two stages ahead go out into the buffer just
+// released, the next stage's first fragments are read, and the second
+// half's MFMAs run, their issue interleaved with those reads.
+constexpr int PS_PLANE = 256 * 64;        // bytes of one LDS plane
+constexpr int PS_STAGE = 4 * PS_PLANE;    // A hi, A lo, B' hi, B' lo
+constexpr size_t PS_LDS = 2 * PS_STAGE;   // 128 KiB
+
+// uint32 (bf16 pair) index of the hi half of complex element (row, kc) in
+// planes of kp complex columns; the lo half is 16 further
+__device__ __forceinline__ int64_t ps_index(int64_t row, int64_t kc, int64_t kp) {
+  return row * 2 * kp + 32 * (kc >> 4) + (kc & 15);
+}
+
+__device__ __forceinline__ void ps_split(float x, float y, uint32_t& hi, uint32_t& lo) {
+  Stage<4, 2, 2, true, 2>::split2(x, y, hi, lo);
+}
+
+// One thread per complex element of the padded planes; 16 consecutive
+// threads cover one 128-byte block (their loads 128 contiguous bytes of
+// the row, their stores the block).
+__global__ __launch_bounds__(256) void split_planes_a(const float2* __restrict__ X, int64_t rows, int64_t k,
+                                                     int64_t ld, uint32_t nkb, uint32_t blocks, int64_t kp,
+                                                     uint32_t* __restrict__ out) {
+  for (uint32_t t = blockIdx.x * 256u + threadIdx.x; t < blocks * 16u; t += gridDim.x * 256u) {
+    const uint32_t b = t >> 4, e = t & 15;
+    const int64_t row = b / nkb, kc = int64_t{b % nkb} * 16 + e;
+    uint64_t v = 0;
+    if (row < rows && kc < k) v = __builtin_nontemporal_load(reinterpret_cast<const uint64_t*>(X + row * ld + kc));
+    uint32_t hi, lo;
+    ps_split(__uint_as_float(static_cast<uint32_t>(v)), __uint_as_float(static_cast<uint32_t>(v >> 32)), hi, lo);
+    const int64_t p = ps_index(row, kc, kp);
+    __builtin_nontemporal_store(hi, out + p);
+    __builtin_nontemporal_store(lo, out + p + 16);
+  }
+}
+
+// B -> the planes of B' (two real rows per complex row of B; negating a
+// bf16 flips its sign bit, swapping re/im rotates the packed pair).
+__global__ __launch_bounds__(256) void split_planes_b(const float2* __restrict__ X, int64_t rows, int64_t k,
+                                                     int64_t ld, uint32_t nkb, uint32_t blocks, int64_t kp,
+                                                     uint32_t* __restrict__ out) {
+  for (uint32_t t = blockIdx.x * 256u + threadIdx.x; t < blocks * 16u; t += gridDim.x * 256u) {
+    const uint32_t b = t >> 4, e = t & 15;
+    const int64_t row = b / nkb, kc = int64_t{b % nkb} * 16 + e;
+    uint64_t v = 0;
+    if (row < rows && kc < k) v = __builtin_nontemporal_load(reinterpret_cast<const uint64_t*>(X + row * ld + kc));
+    uint32_t hi, lo;
+    ps_split(__uint_as_float(static_cast<uint32_t>(v)), __uint_as_float(static_cast<uint32_t>(v >> 32)), hi, lo);
+    const int64_t p0 = ps_index(2 * row, kc, kp), p1 = p0 + 2 * kp;
+    __builtin_nontemporal_store(hi ^ 0x80000000u, out + p0);
+    __builtin_nontemporal_store(lo ^ 0x80000000u, out + p0 + 16);
+    __builtin_nontemporal_store((hi >> 16) | (hi << 16), out + p1);
+    __builtin_nontemporal_store((lo >> 16) | (lo << 16), out + p1 + 16);
+  }
+}
+
+struct PsFrag {
+  s8v ah[2], al[2], bh[4], bl[4];
+};
+
+// Fragments of sub-step s (16 real k) for wave (wm, wn), as OpsBF16x3W
+// reads them: lane (h, r) takes 8 consecutive k of row r (A) or real column
+// r (B').
+__device__ __forceinline__ void ps_read(const char* stage, int wm, int wn, int h, int l32, int s, PsFrag& f) {
+  const int ch = 2 * s + h;
+#pragma unroll
+  for (int i = 0; i < 2; ++i) {
+    const int row = wm * 64 + i * 32 + l32;
+    const int off = row * 64 + 16 * (ch ^ ((row >> 2) & 3));
+    f.ah[i] = *reinterpret_cast<const s8v*>(stage + off);
+    f.al[i] = *reinterpret_cast<const s8v*>(stage + PS_PLANE + off);
+  }
+#pragma unroll
+  for (int j = 0; j < 4; ++j) {
+    const int row = 128 * wn + 32 * j + l32;
+    const int off = row * 64 + 16 * (ch ^ ((row >> 2) & 3));
+    f.bh[j] = *reinterpret_cast<const s8v*>(stage + 2 * PS_PLANE + off);
+    f.bl[j] = *reinterpret_cast<const s8v*>(stage + 3 * PS_PLANE + off);
+  }
+}
+
+// OpsBF16x3W's products in its order: per block, a_hi b_lo, a_lo b_hi, a_hi b_hi
+__device__ __forceinline__ void ps_mfma(f16v (&acc)[2][4], const PsFrag& f) {
+#pragma unroll
+  for (int j = 0; j < 4; ++j)
+#pragma unroll
+    for (int i = 0; i < 2; ++i) {
+      acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(__builtin_bit_cast(bf8, f.ah[i]),
+                                                          __builtin_bit_cast(bf8, f.bl[j]), acc[i][j], 0, 0, 0);
+      acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(__builtin_bit_cast(bf8, f.al[i]),
+                                                          __builtin_bit_cast(bf8, f.bh[j]), acc[i][j], 0, 0, 0);
+      acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(__builtin_bit_cast(bf8, f.ah[i]),
+                                                          __builtin_bit_cast(bf8, f.bh[j]), acc[i][j], 0, 0, 0);
+    }
+}
+
+// Stage kk's blocks of the tile into LDS buffer `buf`: 64 wave-loads of 1
+// KiB (16 rows x 4 slots of one plane), 8 per wave.  `wave` is uniform.
+__device__ __forceinline__ void ps_issue(char* lds, int buf, int64_t kk, const uint32_t* gA, const uint32_t* gB,
+                                         int64_t kp, int wave, int lane) {
+#pragma unroll
+  for (int q = 0; q < 8; ++q) {
+    const int bid = wave * 8 + q;
+    const int plane = bid >> 4, rb = bid & 15;
+    const int row = rb * 16 + (lane >> 2), slot = lane & 3;
+    const int c = slot ^ ((row >> 2) & 3);
+    const uint32_t* g = (plane < 2 ? gA : gB) + row * 2 * kp + 2 * kk + 16 * (plane & 1) + 4 * c;
+    char* dst = lds + buf * PS_STAGE + plane * PS_PLANE + rb * 1024;
+    __builtin_amdgcn_global_load_lds(static_cast<const void*>(g), (__attribute__((address_space(3))) void*)dst, 16, 0,
+                                     0);
+  }
+}
+
+// One K stage (16 complex k).  ISSUE: load stage kt + 2 after the barrier;
+// READ: read the next stage's first fragments into f0.
+template <bool ISSUE, bool READ>
+__device__ __forceinline__ void ps_stage(f16v (&acc)[2][4], PsFrag& f0, PsFrag& f1, char* lds, int64_t kt,
+                                         const uint32_t* gA, const uint32_t* gB, int64_t kp, int wave, int lane,
+                                         int wm, int wn, int h, int l32) {
+  const int buf = kt & 1;
+  ps_read(lds + buf * PS_STAGE, wm, wn, h, l32, 1, f1);
+  ps_mfma(acc, f0);
+#pragma unroll
+  for (int r = 0; r < 12; ++r) {  // one fragment read per two MFMAs
+    __builtin_amdgcn_sched_group_barrier(0x100, 1, 0);
+    __builtin_amdgcn_sched_group_barrier(0x008, 2, 0);
+  }
+  __builtin_amdgcn_s_waitcnt(0);  // this wave's reads done, stage kt + 1 landed
+  __syncthreads();
+  if constexpr (ISSUE) ps_issue(lds, buf, (kt + 2) * BKC, gA, gB, kp, wave, lane);
+  if constexpr (READ) ps_read(lds + (buf ^ 1) * PS_STAGE, wm, wn, h, l32, 0, f0);
+  ps_mfma(acc, f1);
+  if constexpr (ISSUE) __builtin_amdgcn_sched_group_barrier(0x020, 8, 0);
+  if constexpr (READ) {
+#pragma unroll
+    for (int r = 0; r < 12; ++r) {
+      __builtin_amdgcn_sched_group_barrier(0x100, 1, 0);
+      __builtin_amdgcn_sched_group_barrier(0x008, 2, 0);
+    }
+  }
+}
+
+// gfx9 s_waitcnt immediate: vmcnt <= 8, expcnt and lgkmcnt not waited for
+constexpr int kWaitVm8 = 0x0F78;
+
+template <bool PERM>
+__global__ __launch_bounds__(512, 1) void cgemm_bf16x3_presplit(GemmDesc d, const uint32_t* __restrict__ Ap,
+                                                                const uint32_t* __restrict__ Bp, int64_t kp,
+                                                                int64_t tiles_m, int64_t tiles_n, int64_t total) {
+  extern __shared__ __attribute__((aligned(16))) char lds[];
+  const int tid = threadIdx.x;
+  const int lane = tid & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+  const int wm = wave >> 1, wn = wave & 1;
+  const int h = lane >> 5, l32 = lane & 31;
+  const TileCoord tc = map_tile<kPresplitBM, kPresplitBNC>(tiles_m, tiles_n, total);
+  const uint32_t* gA = Ap + tc.row0 * 2 * kp;
+  const uint32_t* gB = Bp + 2 * tc.col0 * 2 * kp;
+  const int64_t nk = kp / BKC;
+  OpsBF16x3W<4, 2, 2> ops;
+  ops.init();
+  PsFrag f0, f1;
+  ps_issue(lds, 0, 0, gA, gB, kp, wave, lane);
+  if (nk > 1) {
+    ps_issue(lds, 1, BKC, gA, gB, kp, wave, lane);
+    __builtin_amdgcn_s_waitcnt(kWaitVm8);  // stage 0 landed (loads complete in order)
+  } else {
+    __builtin_amdgcn_s_waitcnt(0);
+  }
+  __syncthreads();
+  ps_read(lds, wm, wn, h, l32, 0, f0);
+  if (nk > 1) {
+    for (int64_t kt = 0; kt + 2 < nk; ++kt)
+      ps_stage<true, true>(ops.acc, f0, f1, lds, kt, gA, gB, kp, wave, lane, wm, wn, h, l32);
+    ps_stage<false, true>(ops.acc, f0, f1, lds, nk - 2, gA, gB, kp, wave, lane, wm, wn, h, l32);
+  }
+  ps_stage<false, false>(ops.acc, f0, f1, lds, nk - 1, gA, gB, kp, wave, lane, wm, wn, h, l32);
+  ops.store(d, PERM, tc, wm, wn, lane);
+}
+
 // LDS above 64 KiB must be allowed per kernel, once per device (done for
 // every instance when a context is created, so that no first launch inside
 // a graph capture has to do it).
@@ -924,6 +1123,51 @@ hipError_t launch_gemm_grouped(const GroupedEntry* dev, int n, int64_t total, in
   if (prec == Prec::BF16X3) return launch_grouped_variant<OpsBF16x3>(dev, n, total, variant, true, s);
   if (form == Form::M3) return launch_grouped_variant<Ops3M>(dev, n, total, variant, false, s);
   return launch_grouped_variant<Ops4M>(dev, n, total, variant, false, s);
+}
+
+hipError_t launch_gemm_presplit(const GemmDesc& d, void* planes, hipStream_t s) {
+  if (d.h <= 0 || d.m <= 0 || d.n <= 0) return hipSuccess;
+  if (d.k <= 0 || d.h != 1 || d.rowA || d.kA || d.rowB || d.kB || !planes ||
+      reinterpret_cast<uintptr_t>(planes) % 256 != 0)
+    return hipErrorInvalidValue;
+  const int64_t mp = presplit_rows_a(d.m), np2 = presplit_rows_b(d.n), kp = presplit_k(d.k);
+  const int64_t nkb = kp / 16;
+  // one thread per padded element, counted in 32 bits
+  if ((mp > np2 / 2 ? mp : np2 / 2) * kp >= (int64_t{1} << 31)) return hipErrorInvalidValue;
+  static std::atomic<uint64_t> attr_set{0};
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return e;
+  const uint64_t bit = uint64_t{1} << (dev & 63);
+  if (!(attr_set.load(std::memory_order_acquire) & bit)) {
+    e = hipFuncSetAttribute(reinterpret_cast<const void*>(cgemm_bf16x3_presplit<false>),
+                            hipFuncAttributeMaxDynamicSharedMemorySize, static_cast<int>(PS_LDS));
+    if (e == hipSuccess)
+      e = hipFuncSetAttribute(reinterpret_cast<const void*>(cgemm_bf16x3_presplit<true>),
+                              hipFuncAttributeMaxDynamicSharedMemorySize, static_cast<int>(PS_LDS));
+    if (e != hipSuccess) return e;
+    attr_set.fetch_or(bit, std::memory_order_acq_rel);
+  }
+  uint32_t* Ap = static_cast<uint32_t*>(planes);
+  uint32_t* Bp = Ap + mp * 2 * kp;
+  const int64_t ld = row_stride(d);
+  auto grid = [](int64_t threads) {
+    const int64_t g = (threads + 255) / 256;
+    return static_cast<unsigned>(g < 131072 ? g : 131072);
+  };
+  const uint32_t blocks_a = static_cast<uint32_t>(mp * nkb), blocks_b = static_cast<uint32_t>(np2 / 2 * nkb);
+  hipLaunchKernelGGL(split_planes_a, dim3(grid(int64_t{blocks_a} * 16)), dim3(256), 0, s, d.A, d.m, d.k, ld,
+                     static_cast<uint32_t>(nkb), blocks_a, kp, Ap);
+  hipLaunchKernelGGL(split_planes_b, dim3(grid(int64_t{blocks_b} * 16)), dim3(256), 0, s, d.B, d.n, d.k, ld,
+                     static_cast<uint32_t>(nkb), blocks_b, kp, Bp);
+  const int64_t tiles_m = mp / kPresplitBM, tiles_n = np2 / 2 / kPresplitBNC, total = tiles_m * tiles_n;
+  if (d.offM)
+    hipLaunchKernelGGL(cgemm_bf16x3_presplit<true>, dim3(static_cast<unsigned>(total)), dim3(512), PS_LDS, s, d, Ap,
+                       Bp, kp, tiles_m, tiles_n, total);
+  else
+    hipLaunchKernelGGL(cgemm_bf16x3_presplit<false>, dim3(static_cast<unsigned>(total)), dim3(512), PS_LDS, s, d, Ap,
+                       Bp, kp, tiles_m, tiles_n, total);
+  return hipGetLastError();
 }
 
 hipError_t launch_gemm(const GemmDesc& d, GemmKernel kind, int variant, Form form, Prec prec, hipStream_t s) {

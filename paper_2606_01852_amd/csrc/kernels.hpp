@@ -136,6 +136,20 @@ int64_t grouped_layout(GroupedEntry* e, int n, int variant);
 hipError_t launch_gemm_grouped(const GroupedEntry* dev, int n, int64_t total, int variant, Form form, Prec prec,
                                hipStream_t s);
 hipError_t launch_gemm_valu(const GemmDesc& d, GemmKernel kind, Prec prec, hipStream_t s);
+// Split-bf16x3 on operands split once into bf16 planes (large steps of one
+// batch entry, h == 1, no operand tables): the launch splits A and B into
+// `planes` (presplit_plane_bytes(m, n, k) bytes of device memory, 256-byte
+// aligned) and runs the 256 x 128 wide-wave tile on them with direct
+// global -> LDS staging.  Bitwise the result of the wide-wave variant (3).
+constexpr int64_t kPresplitBM = 256, kPresplitBNC = 128;
+inline int64_t presplit_rows_a(int64_t m) { return (m + kPresplitBM - 1) / kPresplitBM * kPresplitBM; }
+inline int64_t presplit_rows_b(int64_t n) { return 2 * ((n + kPresplitBNC - 1) / kPresplitBNC * kPresplitBNC); }
+inline int64_t presplit_k(int64_t k) { return (k + 15) / 16 * 16; }
+inline size_t presplit_plane_bytes(int64_t m, int64_t n, int64_t k) {
+  // per row and 16 complex k: 128 bytes (32 bf16 hi, 32 bf16 lo)
+  return static_cast<size_t>((presplit_rows_a(m) + presplit_rows_b(n)) * presplit_k(k) * 8);
+}
+hipError_t launch_gemm_presplit(const GemmDesc& d, void* planes, hipStream_t s);
 // Split-K epilogue: C[b, i, j] = sum_{p < S} P[((b * S + p) * m + i) * n + j],
 // p ascending, stored at b * m * n + (offM ? offM[i] + offN[j] : i * n + j).
 hipError_t launch_splitk_reduce(const float2* P, float2* C, int64_t h, int64_t m, int64_t n, int64_t S,

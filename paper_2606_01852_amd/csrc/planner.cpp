@@ -664,6 +664,12 @@ std::unique_ptr<ChunkPlan> build_chunk(const Plan& plan, int j) {
       }
       sp.tperm = build_permute(ext, ist);
     }
+    // split precision on large single GEMMs: split each operand once into
+    // bf16 planes (8 + 8 bytes per element of A, 8 + 16 of B moved: about 1 %
+    // of the GEMM's time from 4096 x 4096 up) rather than in the staging of
+    // every workgroup that reads it
+    sp.presplit = plan.prec == TNC_PREC_BF16X3 && sp.kind == GemmKernel::MFMA && sp.split == 1 && !sp.trans &&
+                  d.h == 1 && sp.lm >= 4096 && sp.ln >= 4096;
     cp->flops += 8.0 * static_cast<double>(sp.h) * sp.m * sp.n * sp.k;
     cp->bytes += 8.0 * (static_cast<double>(sp.hA) * sp.m * sp.k + static_cast<double>(sp.hB) * sp.n * sp.k +
                         static_cast<double>(sp.h) * sp.m * sp.n);
@@ -714,6 +720,9 @@ std::unique_ptr<ChunkPlan> build_chunk(const Plan& plan, int j) {
     const StepPlan& sp = cp->steps[s];
     if (sp.split > 1 || sp.trans)  // split-K partials or the untransposed output, live during the step only
       ivs.push_back({align_up(sp.h * sp.split * sp.lm * sp.ln * 8), when(s), when(s), -1 - s});
+    if (sp.presplit)  // the operands' bf16 planes, live during the step only
+      ivs.push_back({align_up(static_cast<int64_t>(presplit_plane_bytes(sp.lm, sp.ln, sp.k))), when(s), when(s),
+                     -1 - ns - s});
   }
   std::vector<int> idx(ivs.size());
   std::iota(idx.begin(), idx.end(), 0);
@@ -743,7 +752,11 @@ std::unique_ptr<ChunkPlan> build_chunk(const Plan& plan, int j) {
   for (size_t q = 0; q < ivs.size(); ++q) {
     const int id = ivs[q].id;
     if (id < 0) {
-      cp->steps[-1 - id].scratch_buf = static_cast<int>(q);
+      const int s = -1 - id;
+      if (s < ns)
+        cp->steps[s].scratch_buf = static_cast<int>(q);
+      else
+        cp->steps[s - ns].presplit_buf = static_cast<int>(q);
       continue;
     }
     cp->tensor_buf[id] = static_cast<int>(q);

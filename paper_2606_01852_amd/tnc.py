@@ -47,7 +47,8 @@ class StepInfo(C.Structure):
     _fields_ = [("A", C.c_int32), ("B", C.c_int32), ("C", C.c_int32), ("nH", C.c_int32), ("nM", C.c_int32),
                 ("nN", C.c_int32), ("nK", C.c_int32), ("h", C.c_int64), ("m", C.c_int64), ("n", C.c_int64),
                 ("k", C.c_int64), ("natural", C.c_int32), ("kernel", C.c_int32), ("variant", C.c_int32),
-                ("swapped", C.c_int32), ("split", C.c_int32), ("hA", C.c_int64), ("hB", C.c_int64)]
+                ("swapped", C.c_int32), ("split", C.c_int32), ("hA", C.c_int64), ("hB", C.c_int64),
+                ("presplit", C.c_int32)]
 
 
 class DistHW(C.Structure):

@@ -200,6 +200,52 @@ def test_grid8_bf16x3_wide_tile_permuted_stores(ctx):
     assert abs(z - exact) <= t_exact * abs(exact)
 
 
+@pytest.mark.parametrize("order", ["natural", "interleaved"])
+def test_presplit_bf16x3_is_bitwise_the_wide_tile(ctx, order):
+    """Large split-bf16x3 steps split their operands once into bf16 planes
+    and stage them global -> LDS directly: one GEMM of 4160 x 4224 x 200
+    (ragged against the 256 x 128 tile, k padded to 208), stored row-major
+    or in an interleaved consumer order.  The result is bitwise that of the
+    wide-wave kernel (variant 3, forced), within 1e-5 of the oracle's split
+    emulation, and every element within the split bound of the exact
+    product."""
+    rng = np.random.Generator(np.random.PCG64(4160))
+    ext = np.array([64, 65, 66, 64, 200], dtype=np.int64)
+    la, lb = (0, 1, 4), (2, 3, 4)
+
+    def cn(lab):
+        shape = tuple(int(ext[l]) for l in lab)
+        x = rng.standard_normal(shape + (2,), dtype=np.float32) * np.float32(np.sqrt(0.5))
+        return x.view(np.complex64).reshape(shape)
+    out = (0, 1, 2, 3) if order == "natural" else (0, 2, 1, 3)
+    net = Network([cn(la), cn(lb)], [la, lb], ext, out)
+    path = Path(np.array([[0, 1]], dtype=np.int32), ())
+    print(f"presplit bf16x3 {order}", flush=True)
+    z, plan, _ = run(ctx, net, path, prec=tnc.PREC_BF16X3)
+    st = tnc.tnc_plan_get_step(plan.handle, 0)
+    assert st.kernel == 0 and st.presplit == 1 and st.split == 1
+    assert st.natural == (1 if order == "natural" else 0)
+    tnc.tnc_ctx_set_gemm_variant(ctx.handle, 3)
+    try:
+        w, _, _ = run(ctx, net, path, prec=tnc.PREC_BF16X3)
+    finally:
+        tnc.tnc_ctx_set_gemm_variant(ctx.handle, -1)
+    assert np.array_equal(np.asarray(z).view(np.uint64), np.asarray(w).view(np.uint64))
+    emu = oc.contract(net, path, step=osp.split_step)
+    err = assert_close(z, emu, tol=1e-5, what="presplit vs emulation")
+    # exact product and the split bound 3 * 2^-16 * sum_l (|ar|+|ai|)(|br|+|bi|) per element
+    A = net.leaves[0].reshape(64 * 65, 200).astype(np.complex128)
+    B = net.leaves[1].reshape(66 * 64, 200).astype(np.complex128)
+    exact = (A @ B.T).reshape(64, 65, 66, 64)
+    bound = (3 * 2.0 ** -16 * ((np.abs(A.real) + np.abs(A.imag)) @ (np.abs(B.real) + np.abs(B.imag)).T)
+             .reshape(64, 65, 66, 64))
+    if order != "natural":
+        exact = exact.transpose(0, 2, 1, 3)
+        bound = bound.transpose(0, 2, 1, 3)
+    assert np.all(np.abs(np.asarray(z) - exact) <= bound + 1e-6 * np.abs(exact))
+    print(f"presplit bf16x3 {order}: err vs emulation {err:.2e}, bitwise = wide tile", flush=True)
+
+
 def interleaved_pair(z, a, b, c, d, k, seed):
     """One contraction A[z, a, b, k] B[z, c, d, k] whose result order
     (z, a, c, b, d) interleaves the M labels (a, b) with the N labels (c, d):
