@@ -372,7 +372,8 @@ tnc_status tnc_serve_set_heavy(tnc_ctx ctx, double heavy_flops, int32_t heavy_sl
  * (default 8; 1 disables fusion) and run in lockstep with the launches of
  * one run: every MFMA step is one grouped launch over the requests' GEMMs
  * of that step (one persistent kernel whose workgroups loop over the tiles
- * of all of them), and every tree level's small GEMMs and leaf gathers of
+ * of all of them; complex64 tile variants 0-3 in 4M and 0-2 in 3M, other
+ * steps one launch per request), and every tree level's small GEMMs and leaf gathers of
  * all the requests are one launch each.  Only launch-bound requests are
  * fused: planned FLOP below flops_per_launch times the launches of the
  * request's own run (tnc_plan_info.n_launches for a whole-range request;

@@ -713,6 +713,7 @@ void run_lockstep(std::vector<LockstepRun>& runs, void* host_tables, void* dev_t
     for (int s = 0; s < static_cast<int>(cp0.steps.size()); ++s) {
       if (cp0.steps[s].kind != GemmKernel::MFMA || ops[0]->presplit(cp0.steps[s])) continue;
       const int v = ops[0]->variant(cp0.steps[s]);
+      if (!grouped_variant_ok(form, prec, v)) continue;  // no grouped form: per-request launches
       bool ok = true;
       for (int r = 0; ok && r < K; ++r) {
         const StepPlan& sp = ops[r]->cp.steps[s];

@@ -38,6 +38,7 @@
 // workgroups round-robin over the 8 XCDs, each with its own L2) and tiles
 // sweep N in groups of 8 M-tiles for L2 reuse.
 #include <atomic>
+#include <type_traits>
 
 #include "gemm_common.hpp"
 
@@ -1002,13 +1003,13 @@ hipError_t ensure_lds_grouped(size_t lds) {
   return e;
 }
 
-template <template <int, int, int> class OpsT, int WM, int WN>
+template <template <int, int, int> class OpsT, int WM, int WN, bool GROUPED = true>
 void prepare_shape(bool bf16) {
   using S = Shape<WM, WN, OpsT<WM, WN, 2>::kPW>;
   const size_t lds = bf16 ? S::lds_bf16 : S::lds_f32;
   (void)ensure_lds<OpsT, WM, WN, 2, false>(lds);
   (void)ensure_lds<OpsT, WM, WN, 2, true>(lds);
-  (void)ensure_lds_grouped<OpsT, WM, WN>(lds);
+  if constexpr (GROUPED) (void)ensure_lds_grouped<OpsT, WM, WN>(lds);
 }
 
 // Persistent grid: a multiple of 8 (one range of tiles per XCD), at most
@@ -1026,31 +1027,52 @@ hipError_t launch_grouped_shape(const GroupedEntry* tab, int n, int64_t total, b
   return hipGetLastError();
 }
 
+// Grouped forms are built only where the persistent tile loop fits the
+// registers without spilling (compiler resource report for gfx950): 4M
+// variants 0-3 and 3M variants 0-2.  Other grouped launches fail with
+// hipErrorInvalidValue; callers run those GEMMs one launch each.
 template <template <int, int, int> class OpsT>
-hipError_t launch_grouped_variant(const GroupedEntry* tab, int n, int64_t total, int variant, bool bf16,
-                                  hipStream_t s) {
-  if (bf16 && variant == 3) return launch_grouped_shape<OpsBF16x3W, 4, 2>(tab, n, total, true, s);
-  switch (variant) {
-    case 0: return launch_grouped_shape<OpsT, 2, 2>(tab, n, total, bf16, s);
-    case 1: return launch_grouped_shape<OpsT, 4, 2>(tab, n, total, bf16, s);
-    case 2: return launch_grouped_shape<OpsT, 2, 4>(tab, n, total, bf16, s);
-    case 3: return launch_grouped_shape<OpsT, 4, 4>(tab, n, total, bf16, s);
-    case 4: return launch_grouped_shape<OpsT, 1, 2>(tab, n, total, bf16, s);
-    case 5: return launch_grouped_shape<OpsT, 2, 1>(tab, n, total, bf16, s);
-    case 6: return launch_grouped_shape<OpsT, 1, 1>(tab, n, total, bf16, s);
-    default: return hipErrorInvalidValue;
+constexpr int grouped_variants() {
+  if constexpr (std::is_same_v<OpsT<2, 2, 2>, Ops4M<2, 2, 2>>) return 4;
+  if constexpr (std::is_same_v<OpsT<2, 2, 2>, Ops3M<2, 2, 2>>) return 3;
+  return 0;
+}
+
+template <template <int, int, int> class OpsT>
+hipError_t launch_grouped_variant(const GroupedEntry* tab, int n, int64_t total, int variant, hipStream_t s) {
+  constexpr int nv = grouped_variants<OpsT>();
+  if (variant < 0 || variant >= nv) return hipErrorInvalidValue;
+  if constexpr (nv > 0) {
+    switch (variant) {
+      case 0: return launch_grouped_shape<OpsT, 2, 2>(tab, n, total, false, s);
+      case 1: return launch_grouped_shape<OpsT, 4, 2>(tab, n, total, false, s);
+      case 2: return launch_grouped_shape<OpsT, 2, 4>(tab, n, total, false, s);
+      default:
+        if constexpr (nv > 3) return launch_grouped_shape<OpsT, 4, 4>(tab, n, total, false, s);
+        return hipErrorInvalidValue;
+    }
   }
+  return hipErrorInvalidValue;
+}
+
+// The narrow split tile has no (4,4) instance: split precision runs that
+// tile size as 4x2 wide waves (the narrow waves' two accumulator sets would
+// spill).
+template <template <int, int, int> class OpsT>
+constexpr bool is_split() {
+  return std::is_same_v<OpsT<2, 2, 2>, OpsBF16x3<2, 2, 2>>;
 }
 
 template <template <int, int, int> class OpsT>
 void prepare_ops(bool bf16) {
-  prepare_shape<OpsT, 2, 2>(bf16);
-  prepare_shape<OpsT, 4, 2>(bf16);
-  prepare_shape<OpsT, 2, 4>(bf16);
-  if (!bf16) prepare_shape<OpsT, 4, 4>(bf16);  // split precision: 4x2 wide waves (prepare_gemm_kernels)
-  prepare_shape<OpsT, 1, 2>(bf16);
-  prepare_shape<OpsT, 2, 1>(bf16);
-  prepare_shape<OpsT, 1, 1>(bf16);
+  constexpr int nv = grouped_variants<OpsT>();
+  prepare_shape<OpsT, 2, 2, (nv > 0)>(bf16);
+  prepare_shape<OpsT, 4, 2, (nv > 1)>(bf16);
+  prepare_shape<OpsT, 2, 4, (nv > 2)>(bf16);
+  if constexpr (!is_split<OpsT>()) prepare_shape<OpsT, 4, 4, (nv > 3)>(bf16);
+  prepare_shape<OpsT, 1, 2, false>(bf16);
+  prepare_shape<OpsT, 2, 1, false>(bf16);
+  prepare_shape<OpsT, 1, 1, false>(bf16);
   const size_t lds = bf16 ? Shape<2, 2>::lds_bf16 : Shape<2, 2>::lds_f32;  // odd-k path
   (void)ensure_lds<OpsT, 2, 2, 1, false>(lds);
   (void)ensure_lds<OpsT, 2, 2, 1, true>(lds);
@@ -1072,12 +1094,13 @@ hipError_t launch_variant(const GemmDesc& d, int variant, bool bf16, hipStream_t
   }
   // split precision: the 256 x 128 tile runs as 4x2 wide waves (16 waves of
   // the narrow kind would spill their two accumulator sets)
-  if (bf16 && variant == 3) return launch_shape<OpsBF16x3W, 4, 2>(d, true, s);
   switch (variant) {
     case 0: return launch_shape<OpsT, 2, 2>(d, bf16, s);
     case 1: return launch_shape<OpsT, 4, 2>(d, bf16, s);
     case 2: return launch_shape<OpsT, 2, 4>(d, bf16, s);
-    case 3: return launch_shape<OpsT, 4, 4>(d, bf16, s);
+    case 3:
+      if constexpr (is_split<OpsT>()) return launch_shape<OpsBF16x3W, 4, 2>(d, true, s);
+      else return launch_shape<OpsT, 4, 4>(d, bf16, s);
     case 4: return launch_shape<OpsT, 1, 2>(d, bf16, s);
     case 5: return launch_shape<OpsT, 2, 1>(d, bf16, s);
     case 6: return launch_shape<OpsT, 1, 1>(d, bf16, s);
@@ -1091,7 +1114,7 @@ void prepare_gemm_kernels() {
   prepare_ops<Ops4M>(false);
   prepare_ops<Ops3M>(false);
   prepare_ops<OpsBF16x3>(true);
-  prepare_shape<OpsBF16x3W, 4, 2>(true);
+  prepare_shape<OpsBF16x3W, 4, 2, false>(true);
 }
 
 void gemm_variant_tile(int variant, int* bm, int* bnc) {
@@ -1117,12 +1140,17 @@ int64_t grouped_layout(GroupedEntry* e, int n, int variant) {
   return total;
 }
 
+bool grouped_variant_ok(Form form, Prec prec, int variant) {
+  if (prec == Prec::BF16X3) return false;
+  return variant >= 0 && variant < (form == Form::M3 ? grouped_variants<Ops3M>() : grouped_variants<Ops4M>());
+}
+
 hipError_t launch_gemm_grouped(const GroupedEntry* dev, int n, int64_t total, int variant, Form form, Prec prec,
                                hipStream_t s) {
   if (n <= 0 || total <= 0) return hipSuccess;
-  if (prec == Prec::BF16X3) return launch_grouped_variant<OpsBF16x3>(dev, n, total, variant, true, s);
-  if (form == Form::M3) return launch_grouped_variant<Ops3M>(dev, n, total, variant, false, s);
-  return launch_grouped_variant<Ops4M>(dev, n, total, variant, false, s);
+  if (!grouped_variant_ok(form, prec, variant)) return hipErrorInvalidValue;
+  if (form == Form::M3) return launch_grouped_variant<Ops3M>(dev, n, total, variant, s);
+  return launch_grouped_variant<Ops4M>(dev, n, total, variant, s);
 }
 
 hipError_t launch_gemm_presplit(const GemmDesc& d, void* planes, hipStream_t s) {

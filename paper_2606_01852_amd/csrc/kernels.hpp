@@ -122,7 +122,10 @@ hipError_t launch_gemm(const GemmDesc& d, GemmKernel kind, int variant, Form for
 // one persistent launch whose workgroups loop over the tiles of all of them.
 // Every tile is computed exactly as the single-GEMM kernel of that variant
 // computes it, so each result is bitwise the same as a launch of its own.
-// Entries need even k and row stride (16-byte operand loads).
+// Entries need even k and row stride (16-byte operand loads).  Grouped
+// forms exist only where the persistent tile loop fits the registers
+// without spilling (grouped_variant_ok: 4M variants 0-3, 3M variants 0-2);
+// other launches fail with hipErrorInvalidValue.
 struct GroupedEntry {
   GemmDesc d;
   int64_t tiles_m, tiles_n;   // tile grid of one batch entry
@@ -133,6 +136,7 @@ struct GroupedEntry {
 // stride).
 int64_t grouped_layout(GroupedEntry* e, int n, int variant);
 // `dev` is the device copy of the n entries laid out by grouped_layout.
+bool grouped_variant_ok(Form form, Prec prec, int variant);
 hipError_t launch_gemm_grouped(const GroupedEntry* dev, int n, int64_t total, int variant, Form form, Prec prec,
                                hipStream_t s);
 hipError_t launch_gemm_valu(const GemmDesc& d, GemmKernel kind, Prec prec, hipStream_t s);

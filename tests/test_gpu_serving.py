@@ -610,8 +610,10 @@ def _serve_each(ctx, items, fuse, flops_per_launch=tnc.FUSE_ALL):
 @pytest.mark.parametrize("prec, form", [(tnc.PREC_C64, tnc.GEMM_4M), (tnc.PREC_C64, tnc.GEMM_3M),
                                         (tnc.PREC_BF16X3, tnc.GEMM_4M)], ids=["4M", "3M", "bf16x3"])
 def test_fused_requests_are_bitwise_alone(served, prec, form):
-    """Light requests of one structure run as one fused job, every MFMA step
-    a grouped launch over all of them: (i) six 5x5-grid circuits of depth 10
+    """Light requests of one structure run as one fused job (each tree
+    level's small GEMMs and gathers one launch over all of them, every MFMA
+    step one grouped launch in 4M and 3M; split precision has no grouped MFMA
+    form and launches those steps per request): (i) six 5x5-grid circuits of depth 10
     with different gates and bitstrings (same network shape, so the same
     path, slicing and plan structure), four slices each; (ii) one sliced
     network's slices as four requests of one chunk each.  Every result is
