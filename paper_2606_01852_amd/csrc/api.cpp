@@ -718,6 +718,7 @@ hipError_t launch_permute_job(const PermuteJob& j, const void* in, void* out, co
   d.L = j.ph.L;
   d.T = j.ph.T;
   d.slots = j.ph.slots;
+  d.pairs = j.ph.pairs ? 1 : 0;
   return launch_permute(d, s);
 }
 

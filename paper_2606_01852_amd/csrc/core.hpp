@@ -118,6 +118,10 @@ struct Net {
 // A tile decomposition of one gather-permute (host copy of the tables).
 struct PermuteHost {
   bool tiled = false;
+  // every even read-order element and its successor are adjacent in the
+  // input, every even write-order element and its successor adjacent in the
+  // output, all at even offsets: the tile moves as 16-byte pairs
+  bool pairs = false;
   int32_t T = 0, slots = 0, L = 1;
   int64_t n_tiles = 0;
   std::vector<int32_t> tile_in, tile_slot_r, tile_out, tile_slot_w;

@@ -192,6 +192,7 @@ hipError_t launch_planned_permute(const PermuteHost& p, const ChunkPlan& cp, con
     d.slots = p.slots;
     d.base = 0;
     d.base_dev = bd;
+    d.pairs = p.pairs ? 1 : 0;
     return launch_permute(d, stream);
   }
   GatherDesc g = p.plain;

@@ -93,6 +93,7 @@ struct PermuteDesc {
   int32_t slots;               // LDS slots used (>= T, padding included)
   int64_t base;                // constant input offset
   const int64_t* base_dev;     // optional extra input offset read on device
+  int32_t pairs;               // the tables allow 16-byte pairs (PermuteHost::pairs)
 };
 
 // Plain gather: out[w] = in[base + sum_d digit_d(w) * in_stride[d]] over

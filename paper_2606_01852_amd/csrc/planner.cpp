@@ -282,6 +282,12 @@ PermuteHost build_permute(const std::vector<int64_t>& ext0, const std::vector<in
   };
   make_tab(split, static_cast<int>(outer.size()), P.lo_tab);
   make_tab(0, split, P.hi_tab);
+  P.pairs = T % 2 == 0;
+  for (int64_t x = 0; P.pairs && x < T; x += 2)
+    P.pairs = P.tile_in[x] % 2 == 0 && P.tile_in[x + 1] == P.tile_in[x] + 1 && P.tile_out[x] % 2 == 0 &&
+              P.tile_out[x + 1] == P.tile_out[x] + 1;
+  for (size_t q = 0; P.pairs && q < P.lo_tab.size(); ++q) P.pairs = P.lo_tab[q] % 2 == 0;
+  for (size_t q = 0; P.pairs && q < P.hi_tab.size(); ++q) P.pairs = P.hi_tab[q] % 2 == 0;
   P.L = static_cast<int32_t>(L);
   P.n_tiles = n_tiles;
   P.tiled = true;
