@@ -313,19 +313,21 @@ def serving_leg(args):
 def fusion_leg(ctx, tnc, n: int = 512):
     """Light requests of one structure, queued all at once through the
     8-slot server, with fusion of up to 8 same-structure requests per job
-    and without; the results are compared bitwise.  Two mixes of 64 random
+    and without; the results are compared bitwise.  Three mixes of 64 random
     circuits each (different gates and bitstrings, one network shape, so one
-    path and slicing): 4x5-grid circuits of depth 10 (1 sliced label,
-    2.4e8 FLOP over 18 launches per amplitude: launch-bound, fused by the
-    server's default criterion) and 5x5-grid circuits of depth 10 (2 sliced
-    labels, 8.9e9 FLOP over 20 launches: bound by the GPU's arithmetic, not
-    fused by default; forced fusion timed for comparison)."""
+    path and slicing), by planned FLOP per launch of a request's own run:
+    4x5-grid circuits of depth 10 (1 sliced label, 2.4e8 FLOP over 18
+    launches per amplitude: launch-bound), 5x5 of depth 10 (2 sliced labels,
+    8.9e9 over 20) and 5x6 of depth 10 (2 sliced labels, 9.8e10 over 24:
+    bound by the GPU's arithmetic).  Where the server's default criterion
+    does not fuse a mix, forced fusion is timed for comparison."""
     from workloads.circuits import circuit_network, random_circuit
     from workloads.paths import greedy_path, greedy_slice
 
     res = {"requests": n, "circuits": 64, "slots": 8, "max_fused": 8,
            "flops_per_launch_criterion": tnc.FUSE_FLOPS_PER_LAUNCH}
-    for name, rows, cols, n_sl in (("launch_bound_4x5_d10", 4, 5, 1), ("gpu_bound_5x5_d10", 5, 5, 2)):
+    for name, rows, cols, n_sl in (("launch_bound_4x5_d10", 4, 5, 1), ("mixed_5x5_d10", 5, 5, 2),
+                                   ("gpu_bound_5x6_d10", 5, 6, 2)):
         circs = [random_circuit(rows, cols, 10, seed=9000 + i) for i in range(64)]
         nets = [circuit_network(c) for c in circs]
         path = greedy_path(nets[0])               # structure only: the same for every circuit

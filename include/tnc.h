@@ -372,14 +372,14 @@ tnc_status tnc_serve_set_heavy(tnc_ctx ctx, double heavy_flops, int32_t heavy_sl
  * (default 8; 1 disables fusion) and run in lockstep with the launches of
  * one run: every MFMA step is one grouped launch over the requests' GEMMs
  * of that step (one persistent kernel whose workgroups loop over the tiles
- * of all of them; complex64 tile variants 0-3 in 4M and 0-2 in 3M, other
- * steps one launch per request), and every tree level's small GEMMs and leaf gathers of
- * all the requests are one launch each.  Only launch-bound requests are
- * fused: planned FLOP below flops_per_launch times the launches of the
- * request's own run (tnc_plan_info.n_launches for a whole-range request;
- * default 2^27, about what ~3 us of launch latency is worth at the small
- * steps' rate); heavier requests gain nothing and would lose the overlap
- * of separate streams.  A huge flops_per_launch (e.g. 1e300) fuses every
+ * of all of them; every tile variant in 4M, all but 3 in 3M, 0 and 4-6 in
+ * split precision, other steps one launch per request), and every tree level's small GEMMs and leaf gathers of
+ * all the requests are one launch each.  Only requests that wait on their
+ * launches more than on their arithmetic are fused: planned FLOP below
+ * flops_per_launch times the launches of the request's own run
+ * (tnc_plan_info.n_launches for a whole-range request; default 2^30, set
+ * between a measured 1.05x gain at 4.5e8 FLOP per launch and a 0.96x loss
+ * at 4.1e9); heavier requests would lose the overlap of separate streams.  A huge flops_per_launch (e.g. 1e300) fuses every
  * light request.  Each request's result is bitwise the one it gets alone:
  * its every output element is computed by the same tile code in the same
  * order.  Applies to admissions from now on; TNC_E_ARG if the context is

@@ -642,14 +642,14 @@ LockstepInfo lockstep_info(Plan& plan, int64_t first, int64_t count) {
         t.parts += 1;
       }
     if (!cp.grouped) continue;
-    for (const LevelPlan& lv : cp.levels) {
+    for (const LevelPlan& lv : cp.levels) {  // per run: one GroupRun per grouped launch
       if (!lv.group_steps.empty()) {
-        t.bytes_per_run += lv.group_steps.size() * (sizeof(GroupGemm) + sizeof(int64_t));
-        t.parts += 2;
+        t.bytes_per_run += sizeof(GroupRun);
+        t.parts += 1;
       }
       if (!lv.group_leaves.empty()) {
-        t.bytes_per_run += lv.group_leaves.size() * (sizeof(GroupGather) + sizeof(int64_t));
-        t.parts += 2;
+        t.bytes_per_run += sizeof(GroupRun);
+        t.parts += 1;
       }
     }
   }
@@ -683,11 +683,10 @@ void run_lockstep(std::vector<LockstepRun>& runs, void* host_tables, void* dev_t
     return ops;
   };
   // Tables of the job, built once on the host and uploaded once: per MFMA
-  // step the K runs' GEMMs (grouped launch), per tree level the K runs'
-  // small GEMMs and plain gathers as one table each, with absolute
-  // pointers (every run has its own arena and base offsets).  Tables serve
-  // every chunk of a chunk plan, so leaf bases are read from each run's
-  // "current chunk" slot, refreshed before the chunk's first launch.
+  // step the K runs' GEMMs (grouped launch), per tree level one GroupRun
+  // per run for its small GEMMs and one for its plain gathers.  Tables
+  // serve every chunk of a chunk plan, so leaf bases are read from each
+  // run's "current chunk" slot, refreshed before the chunk's first launch.
   char* host = static_cast<char*>(host_tables);
   char* dev = static_cast<char*>(dev_tables);
   size_t used = 0;
@@ -698,8 +697,8 @@ void run_lockstep(std::vector<LockstepRun>& runs, void* host_tables, void* dev_t
     return off;
   };
   struct LevelTabs {
-    size_t gemm = 0, gemm_pre = 0, gath = 0, gath_pre = 0;
-    int n_gemm = 0, n_gath = 0;
+    size_t gemm = 0, gath = 0;   // offsets of the GroupRun tables
+    int n_gemm = 0, n_gath = 0;  // runs in them (0: no such launch)
     int64_t gemm_total = 0, gath_total = 0;
   };
   std::map<std::pair<int, int>, std::pair<size_t, int64_t>> grouped;  // (j, step) -> (offset, tiles)
@@ -731,57 +730,37 @@ void run_lockstep(std::vector<LockstepRun>& runs, void* host_tables, void* dev_t
       if (total > 0) grouped[{j, s}] = {off, total};
     }
     if (!cp0.grouped) continue;
+    // per level, the runs' own device tables (materialized with each plan)
+    // as one launch over runs: each run brings its arena and its current
+    // leaf bases, so no run's table is copied or rewritten here
     for (size_t li = 0; li < cp0.levels.size(); ++li) {
       LevelTabs t;
       const LevelPlan& lv0 = cp0.levels[li];
-      t.n_gemm = K * static_cast<int>(lv0.group_steps.size());
-      t.n_gath = K * static_cast<int>(lv0.group_leaves.size());
-      if (t.n_gemm) {
-        t.gemm = take(t.n_gemm * sizeof(GroupGemm));
-        t.gemm_pre = take(t.n_gemm * sizeof(int64_t));
-        auto* tab = reinterpret_cast<GroupGemm*>(host + t.gemm);
-        auto* pre = reinterpret_cast<int64_t*>(host + t.gemm_pre);
-        int q = 0;
+      auto runs_table = [&](bool gemm_tab, int64_t& total) {
+        const size_t off = take(K * sizeof(GroupRun));
+        auto* gr = reinterpret_cast<GroupRun*>(host + off);
         for (int r = 0; r < K; ++r) {
           const ChunkPlan& cp = ops[r]->cp;
           const LevelPlan& lv = cp.levels[li];
-          const auto* src = reinterpret_cast<const GroupGemm*>(cp.host_blob.data() + lv.off_gemm);
-          char* ar = runs[r].a.arena;
-          for (size_t x = 0; x < lv.group_steps.size(); ++x, ++q) {
-            GroupGemm g = src[x];
-            if (g.rel_a) g.d.A = reinterpret_cast<const float2*>(ar + reinterpret_cast<intptr_t>(g.d.A));
-            if (g.rel_b) g.d.B = reinterpret_cast<const float2*>(ar + reinterpret_cast<intptr_t>(g.d.B));
-            if (g.rel_c) g.d.C = reinterpret_cast<float2*>(ar + reinterpret_cast<intptr_t>(g.d.C));
-            g.rel_a = g.rel_b = g.rel_c = 0;
-            if (g.slot_a >= 0) g.d.baseA = rb[r].cur_dev + g.slot_a;
-            if (g.slot_b >= 0) g.d.baseB = rb[r].cur_dev + g.slot_b;
-            g.slot_a = g.slot_b = -1;
-            tab[q] = g;
-            pre[q] = t.gemm_total;
-            t.gemm_total += g.d.h * g.d.m * g.d.n;
-          }
+          const char* blob = static_cast<const char*>(cp.blob.ptr);
+          std::memset(&gr[r], 0, sizeof(GroupRun));
+          gr[r].table = blob + (gemm_tab ? lv.off_gemm : lv.off_gather);
+          gr[r].prefix = reinterpret_cast<const int64_t*>(blob + (gemm_tab ? lv.off_gemm_prefix : lv.off_gather_prefix));
+          gr[r].n = static_cast<int32_t>(gemm_tab ? lv.group_steps.size() : lv.group_leaves.size());
+          gr[r].arena = runs[r].a.arena;
+          gr[r].bases = rb[r].cur_dev;
+          gr[r].first = total;
+          total += gemm_tab ? lv.gemm_total : lv.gather_total;
         }
+        return off;
+      };
+      if (!lv0.group_steps.empty()) {
+        t.n_gemm = K;
+        t.gemm = runs_table(true, t.gemm_total);
       }
-      if (t.n_gath) {
-        t.gath = take(t.n_gath * sizeof(GroupGather));
-        t.gath_pre = take(t.n_gath * sizeof(int64_t));
-        auto* tab = reinterpret_cast<GroupGather*>(host + t.gath);
-        auto* pre = reinterpret_cast<int64_t*>(host + t.gath_pre);
-        int q = 0;
-        for (int r = 0; r < K; ++r) {
-          const ChunkPlan& cp = ops[r]->cp;
-          const LevelPlan& lv = cp.levels[li];
-          const auto* src = reinterpret_cast<const GroupGather*>(cp.host_blob.data() + lv.off_gather);
-          for (size_t x = 0; x < lv.group_leaves.size(); ++x, ++q) {
-            GroupGather g = src[x];
-            g.out_abs = reinterpret_cast<float2*>(runs[r].a.arena + g.out_off);
-            g.base_abs = g.base_slot >= 0 ? rb[r].cur_dev + g.base_slot : nullptr;
-            g.base_slot = -1;
-            tab[q] = g;
-            pre[q] = t.gath_total;
-            t.gath_total += cp.numel[lv.group_leaves[x]];
-          }
-        }
+      if (!lv0.group_leaves.empty()) {
+        t.n_gath = K;
+        t.gath = runs_table(false, t.gath_total);
       }
       levtabs[{j, static_cast<int>(li)}] = t;
     }
@@ -817,16 +796,14 @@ void run_lockstep(std::vector<LockstepRun>& runs, void* host_tables, void* dev_t
       for (size_t li = 0; li < cp0.levels.size(); ++li) {
         const LevelTabs& t = levtabs.at({j, static_cast<int>(li)});
         if (t.n_gath)
-          check_hip(launch_group_gather(reinterpret_cast<const GroupGather*>(dev + t.gath),
-                                        reinterpret_cast<const int64_t*>(dev + t.gath_pre), t.n_gath, t.gath_total,
-                                        nullptr, nullptr, stream),
+          check_hip(launch_group_gather_runs(reinterpret_cast<const GroupRun*>(dev + t.gath), t.n_gath, t.gath_total,
+                                             stream),
                     "grouped gathers");
         for (auto& op : ops)
           for (int tl : op->cp.levels[li].single_leaves) op->prep(tl);
         if (t.n_gemm)
-          check_hip(launch_group_gemm(reinterpret_cast<const GroupGemm*>(dev + t.gemm),
-                                      reinterpret_cast<const int64_t*>(dev + t.gemm_pre), t.n_gemm, t.gemm_total,
-                                      nullptr, nullptr, prec, stream),
+          check_hip(launch_group_gemm_runs(reinterpret_cast<const GroupRun*>(dev + t.gemm), t.n_gemm, t.gemm_total,
+                                           prec, stream),
                     "grouped small GEMMs");
         for (int s : cp0.levels[li].single_steps) gemm(s);
       }

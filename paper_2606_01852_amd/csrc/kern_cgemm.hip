@@ -723,9 +723,18 @@ __global__ __launch_bounds__(64 * WM * WN, (WM * WN <= 4) ? 2 : 1) void cgemm_mf
 // the table.  Tiles are dealt to the 8 XCDs in contiguous ranges (tiles of
 // one entry stay on few XCDs, whose L2 they share) and each workgroup of an
 // XCD takes every nb-th tile of its range.  The tile's work is the
-// single-GEMM kernel's, line for line.
+// single-GEMM kernel's, line for line.  The tile loop keeps more values
+// live than one tile does, so most instances are built for one workgroup
+// per CU, which lets the compiler keep accumulators in AGPRs instead of
+// spilling (the persistent grid runs a fixed number of workgroups anyway);
+// the complex64 (2,2) tile fits two.
 template <template <int, int, int> class OpsT, int WM, int WN>
-__global__ __launch_bounds__(64 * WM * WN, (WM * WN <= 4) ? 2 : 1) void cgemm_mfma_grouped(
+constexpr int grouped_min_blocks() {
+  return WM * WN == 4 && !std::is_same_v<OpsT<2, 2, 2>, OpsBF16x3<2, 2, 2>> ? 2 : 1;
+}
+
+template <template <int, int, int> class OpsT, int WM, int WN>
+__global__ __launch_bounds__(64 * WM * WN, (grouped_min_blocks<OpsT, WM, WN>())) void cgemm_mfma_grouped(
     const GroupedEntry* __restrict__ tab, int n, int64_t total) {
   using S = Shape<WM, WN, OpsT<WM, WN, 2>::kPW>;
   extern __shared__ __attribute__((aligned(16))) char lds[];
@@ -1012,44 +1021,55 @@ void prepare_shape(bool bf16) {
   if constexpr (GROUPED) (void)ensure_lds_grouped<OpsT, WM, WN>(lds);
 }
 
-// Persistent grid: a multiple of 8 (one range of tiles per XCD), at most
-// two workgroups per compute unit, never more than the tiles.
+// Persistent grid: a multiple of 8 (one range of tiles per XCD), never more
+// than the tiles; at most 512 workgroups (two per compute unit), or 2048
+// waves for the shapes of fewer than four waves.
 template <template <int, int, int> class OpsT, int WM, int WN>
 hipError_t launch_grouped_shape(const GroupedEntry* tab, int n, int64_t total, bool bf16, hipStream_t s) {
   using S = Shape<WM, WN, OpsT<WM, WN, 2>::kPW>;
   const size_t lds = bf16 ? S::lds_bf16 : S::lds_f32;
   const hipError_t e = ensure_lds_grouped<OpsT, WM, WN>(lds);
   if (e != hipSuccess) return e;
+  constexpr int64_t cap = WM * WN < 4 ? 2048 / (WM * WN) : 512;
   int64_t grid = (total + 7) / 8 * 8;
-  if (grid > 512) grid = 512;
+  if (grid > cap) grid = cap;
   hipLaunchKernelGGL((cgemm_mfma_grouped<OpsT, WM, WN>), dim3(static_cast<unsigned>(grid)), dim3(S::NT), lds, s, tab,
                      n, total);
   return hipGetLastError();
 }
 
 // Grouped forms are built only where the persistent tile loop fits the
-// registers without spilling (compiler resource report for gfx950): 4M
-// variants 0-3 and 3M variants 0-2.  Other grouped launches fail with
-// hipErrorInvalidValue; callers run those GEMMs one launch each.
+// registers without spilling (compiler resource report for gfx950, with
+// the launch bounds above): every complex64 4M shape, 3M but (4,4), and
+// split precision's (2,2), (1,2), (2,1), (1,1).  Other grouped launches fail
+// with hipErrorInvalidValue; callers run those GEMMs one launch each.
 template <template <int, int, int> class OpsT>
-constexpr int grouped_variants() {
-  if constexpr (std::is_same_v<OpsT<2, 2, 2>, Ops4M<2, 2, 2>>) return 4;
-  if constexpr (std::is_same_v<OpsT<2, 2, 2>, Ops3M<2, 2, 2>>) return 3;
-  return 0;
+constexpr bool grouped_ok(int variant) {
+  if (variant < 0 || variant >= kGemmVariants) return false;
+  if constexpr (std::is_same_v<OpsT<2, 2, 2>, OpsBF16x3<2, 2, 2>>) return variant == 0 || variant >= 4;
+  if constexpr (std::is_same_v<OpsT<2, 2, 2>, Ops3M<2, 2, 2>>) return variant != 3;
+  return true;
 }
 
 template <template <int, int, int> class OpsT>
-hipError_t launch_grouped_variant(const GroupedEntry* tab, int n, int64_t total, int variant, hipStream_t s) {
-  constexpr int nv = grouped_variants<OpsT>();
-  if (variant < 0 || variant >= nv) return hipErrorInvalidValue;
-  if constexpr (nv > 0) {
+hipError_t launch_grouped_variant(const GroupedEntry* tab, int n, int64_t total, int variant, bool bf16,
+                                  hipStream_t s) {
+  if (!grouped_ok<OpsT>(variant)) return hipErrorInvalidValue;
+  switch (variant) {
+    case 0: return launch_grouped_shape<OpsT, 2, 2>(tab, n, total, bf16, s);
+    case 4: return launch_grouped_shape<OpsT, 1, 2>(tab, n, total, bf16, s);
+    case 5: return launch_grouped_shape<OpsT, 2, 1>(tab, n, total, bf16, s);
+    case 6: return launch_grouped_shape<OpsT, 1, 1>(tab, n, total, bf16, s);
+    default: break;
+  }
+  if constexpr (!std::is_same_v<OpsT<2, 2, 2>, OpsBF16x3<2, 2, 2>>) {
     switch (variant) {
-      case 0: return launch_grouped_shape<OpsT, 2, 2>(tab, n, total, false, s);
-      case 1: return launch_grouped_shape<OpsT, 4, 2>(tab, n, total, false, s);
-      case 2: return launch_grouped_shape<OpsT, 2, 4>(tab, n, total, false, s);
-      default:
-        if constexpr (nv > 3) return launch_grouped_shape<OpsT, 4, 4>(tab, n, total, false, s);
-        return hipErrorInvalidValue;
+      case 1: return launch_grouped_shape<OpsT, 4, 2>(tab, n, total, bf16, s);
+      case 2: return launch_grouped_shape<OpsT, 2, 4>(tab, n, total, bf16, s);
+      case 3:
+        if constexpr (!std::is_same_v<OpsT<2, 2, 2>, Ops3M<2, 2, 2>>) return launch_grouped_shape<OpsT, 4, 4>(tab, n, total, bf16, s);
+        break;
+      default: break;
     }
   }
   return hipErrorInvalidValue;
@@ -1065,14 +1085,13 @@ constexpr bool is_split() {
 
 template <template <int, int, int> class OpsT>
 void prepare_ops(bool bf16) {
-  constexpr int nv = grouped_variants<OpsT>();
-  prepare_shape<OpsT, 2, 2, (nv > 0)>(bf16);
-  prepare_shape<OpsT, 4, 2, (nv > 1)>(bf16);
-  prepare_shape<OpsT, 2, 4, (nv > 2)>(bf16);
-  if constexpr (!is_split<OpsT>()) prepare_shape<OpsT, 4, 4, (nv > 3)>(bf16);
-  prepare_shape<OpsT, 1, 2, false>(bf16);
-  prepare_shape<OpsT, 2, 1, false>(bf16);
-  prepare_shape<OpsT, 1, 1, false>(bf16);
+  prepare_shape<OpsT, 2, 2, grouped_ok<OpsT>(0)>(bf16);
+  prepare_shape<OpsT, 4, 2, grouped_ok<OpsT>(1)>(bf16);
+  prepare_shape<OpsT, 2, 4, grouped_ok<OpsT>(2)>(bf16);
+  if constexpr (!is_split<OpsT>()) prepare_shape<OpsT, 4, 4, grouped_ok<OpsT>(3)>(bf16);
+  prepare_shape<OpsT, 1, 2, grouped_ok<OpsT>(4)>(bf16);
+  prepare_shape<OpsT, 2, 1, grouped_ok<OpsT>(5)>(bf16);
+  prepare_shape<OpsT, 1, 1, grouped_ok<OpsT>(6)>(bf16);
   const size_t lds = bf16 ? Shape<2, 2>::lds_bf16 : Shape<2, 2>::lds_f32;  // odd-k path
   (void)ensure_lds<OpsT, 2, 2, 1, false>(lds);
   (void)ensure_lds<OpsT, 2, 2, 1, true>(lds);
@@ -1141,16 +1160,16 @@ int64_t grouped_layout(GroupedEntry* e, int n, int variant) {
 }
 
 bool grouped_variant_ok(Form form, Prec prec, int variant) {
-  if (prec == Prec::BF16X3) return false;
-  return variant >= 0 && variant < (form == Form::M3 ? grouped_variants<Ops3M>() : grouped_variants<Ops4M>());
+  if (prec == Prec::BF16X3) return grouped_ok<OpsBF16x3>(variant);
+  return form == Form::M3 ? grouped_ok<Ops3M>(variant) : grouped_ok<Ops4M>(variant);
 }
 
 hipError_t launch_gemm_grouped(const GroupedEntry* dev, int n, int64_t total, int variant, Form form, Prec prec,
                                hipStream_t s) {
   if (n <= 0 || total <= 0) return hipSuccess;
-  if (!grouped_variant_ok(form, prec, variant)) return hipErrorInvalidValue;
-  if (form == Form::M3) return launch_grouped_variant<Ops3M>(dev, n, total, variant, s);
-  return launch_grouped_variant<Ops4M>(dev, n, total, variant, s);
+  if (prec == Prec::BF16X3) return launch_grouped_variant<OpsBF16x3>(dev, n, total, variant, true, s);
+  if (form == Form::M3) return launch_grouped_variant<Ops3M>(dev, n, total, variant, false, s);
+  return launch_grouped_variant<Ops4M>(dev, n, total, variant, false, s);
 }
 
 hipError_t launch_gemm_presplit(const GemmDesc& d, void* planes, hipStream_t s) {

@@ -125,8 +125,8 @@ hipError_t launch_gemm(const GemmDesc& d, GemmKernel kind, int variant, Form for
 // computes it, so each result is bitwise the same as a launch of its own.
 // Entries need even k and row stride (16-byte operand loads).  Grouped
 // forms exist only where the persistent tile loop fits the registers
-// without spilling (grouped_variant_ok: 4M variants 0-3, 3M variants 0-2);
-// other launches fail with hipErrorInvalidValue.
+// without spilling (grouped_variant_ok: every 4M variant, 3M but 3, split
+// precision's 0 and 4-6); other launches fail with hipErrorInvalidValue.
 struct GroupedEntry {
   GemmDesc d;
   int64_t tiles_m, tiles_n;   // tile grid of one batch entry
@@ -175,18 +175,29 @@ struct GroupGather {
   int32_t base_slot;    // slot of the chunk's base offset (-1: none)
   int64_t ext[kGroupRank];
   int64_t in_stride[kGroupRank];
-  // absolute forms (tables that mix several runs, each with its own arena
-  // and base offsets): used when set
-  float2* out_abs;
-  const int64_t* base_abs;
 };
 // prefix[i] = first work item of entry i (work items: output elements).
-// An in-place operand's base offset comes from bases[slot_a] when slot_a >=
-// 0, else from *d.baseA when set (tables mixing several runs).
+// An in-place operand's base offset comes from bases[slot_a].
 hipError_t launch_group_gemm(const GroupGemm* table, const int64_t* prefix, int n, int64_t total, char* arena,
                              const int64_t* bases, Prec prec, hipStream_t s);
 hipError_t launch_group_gather(const GroupGather* table, const int64_t* prefix, int n, int64_t total, char* arena,
                                const int64_t* bases, hipStream_t s);
+// One run's share of a grouped launch over several runs of one structure
+// (a fused serving job): its own device table and prefix sums (those of a
+// launch of its own), its arena, its current leaf base offsets, and its
+// first work item in the launch.  A launch over runs does per work item
+// exactly what the run's own launch does.
+struct GroupRun {
+  const void* table;        // GroupGemm[] or GroupGather[]
+  const int64_t* prefix;
+  char* arena;
+  const int64_t* bases;
+  int64_t first;
+  int32_t n;
+  int32_t pad;
+};
+hipError_t launch_group_gemm_runs(const GroupRun* runs, int n_runs, int64_t total, Prec prec, hipStream_t s);
+hipError_t launch_group_gather_runs(const GroupRun* runs, int n_runs, int64_t total, hipStream_t s);
 
 hipError_t launch_permute(const PermuteDesc& d, hipStream_t s);
 // Fixed device-resident table area for permutes of callers that cannot

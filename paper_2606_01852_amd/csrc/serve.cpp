@@ -142,13 +142,14 @@ struct Server {
   std::vector<void*> pinned_tab;        // per slot: pinned staging of grouped-launch tables
   std::vector<size_t> pinned_tab_bytes;
   int fuse_max = 8;                     // requests per fused job (1: no fusion)
-  // A light request is fused only if it is launch-bound: planned FLOP below
-  // this many per launch of its own run.  A dependent launch costs ~3 us and
-  // the small steps of such requests sustain ~45 TFLOP/s, so below ~1.3e8
-  // FLOP per launch (the default, 2^27) a run waits on launches rather than
-  // on arithmetic, and fusing shares those launches; heavier requests gain
-  // nothing from it and lose the overlap of separate streams.
-  double fuse_flops_per_launch = 134217728.0;
+  // A light request is fused only below this many planned FLOP per launch
+  // of its own run.  Fusing shares launches; it pays while a run waits on
+  // them, and costs the overlap of separate streams once a run's own
+  // arithmetic fills the GPU.  Measured on 8 slots (random grid circuits,
+  // 512 requests): 2.3x the unfused rate at 1.4e7 FLOP per launch (4x5,
+  // depth 10), 1.05x at 4.5e8 (5x5, depth 10), 0.96x at 4.1e9 (5x6, depth
+  // 10); the default, 2^30, lies between the last two.
+  double fuse_flops_per_launch = 1073741824.0;
   int64_t n_jobs = 0, n_fused_jobs = 0, n_fused_requests = 0;
   ArenaAllocator arena;
   bool stop = false;

@@ -359,7 +359,7 @@ def tnc_serve_set_heavy(ctx: int, heavy_flops: float, heavy_slots: int = 1) -> N
     _check(lib().tnc_serve_set_heavy(ctx, float(heavy_flops), int(heavy_slots)))
 
 
-FUSE_FLOPS_PER_LAUNCH = float(2 ** 27)   # the server's default fusion criterion
+FUSE_FLOPS_PER_LAUNCH = float(2 ** 30)   # the server's default fusion criterion
 FUSE_ALL = 1e300                          # fuse every light request of one structure
 
 

@@ -612,8 +612,8 @@ def _serve_each(ctx, items, fuse, flops_per_launch=tnc.FUSE_ALL):
 def test_fused_requests_are_bitwise_alone(served, prec, form):
     """Light requests of one structure run as one fused job (each tree
     level's small GEMMs and gathers one launch over all of them, every MFMA
-    step one grouped launch in 4M and 3M; split precision has no grouped MFMA
-    form and launches those steps per request): (i) six 5x5-grid circuits of depth 10
+    step one grouped launch where its tile has a grouped form, else one
+    launch per request): (i) six 5x5-grid circuits of depth 10
     with different gates and bitstrings (same network shape, so the same
     path, slicing and plan structure), four slices each; (ii) one sliced
     network's slices as four requests of one chunk each.  Every result is
@@ -667,15 +667,15 @@ def test_fused_requests_are_bitwise_alone(served, prec, form):
 
 
 def test_fusion_takes_only_launch_bound_requests(served):
-    """The server's default criterion fuses a light request only if it is
-    launch-bound (planned FLOP below 2^27 per launch of its own run): six
-    4x5-grid circuits of depth 10 (2.4e8 FLOP over 18 launches) queued
-    behind a slow request run as one fused job; six 5x5-grid circuits of
-    depth 10 (8.9e9 FLOP over 20 launches) queued with them run one by one.
-    Every result is bitwise the one the request gets alone."""
+    """The server's default criterion fuses a light request only below 2^30
+    planned FLOP per launch of its own run: six 4x5-grid circuits of depth
+    10 (2.4e8 FLOP over 18 launches) queued behind a slow request run as one
+    fused job; six 5x6-grid circuits of depth 10 (9.8e10 FLOP over 24
+    launches, light but bound by arithmetic) queued with them run one by
+    one.  Every result is bitwise the one the request gets alone."""
     ctx = served[0]
     items, handles, launch_bound = [], [], []
-    for rows, cols in ((4, 5), (5, 5)):
+    for rows, cols in ((4, 5), (5, 6)):
         ns = 1 if rows == 4 else 2
         for seed in range(6):
             net = circuit_network(random_circuit(rows, cols, 10, seed=8300 + seed))
@@ -691,7 +691,7 @@ def test_fusion_takes_only_launch_bound_requests(served):
     alone, _ = _serve_each(ctx, items, fuse=False)
     mix, st = _serve_each(ctx, items, fuse=True, flops_per_launch=tnc.FUSE_FLOPS_PER_LAUNCH)
     print(f"fusion criterion: {st}", flush=True)
-    assert st == (1 + 1 + 6, 1, 6)       # blocker, one fused job of the six 4x5 circuits, six 5x5 alone
+    assert st == (1 + 1 + 6, 1, 6)       # blocker, one fused job of the six 4x5 circuits, six 5x6 alone
     for i, (a, m) in enumerate(zip(alone, mix)):
         assert np.array_equal(a.view(np.uint64), m.view(np.uint64)), i
     for tn, p in handles:
