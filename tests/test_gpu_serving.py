@@ -666,6 +666,42 @@ def test_fused_requests_are_bitwise_alone(served, prec, form):
         tn.close()
 
 
+@pytest.mark.parametrize("prec", [tnc.PREC_C64, tnc.PREC_BF16X3], ids=["4M", "bf16x3"])
+def test_fused_jobs_through_every_grouped_tile_variant(served, prec):
+    """Every tile variant forced on every MFMA step (tnc_ctx_set_gemm_variant)
+    while six 4x5-grid circuits of depth 10 run as one fused job: the steps
+    whose variant has a grouped form (every 4M variant; split precision's
+    0, 4, 5, 6) run as grouped launches, the others one launch per request.
+    Every result is bitwise the one the request gets alone with the same
+    variant."""
+    ctx = served[0]
+    items, handles = [], []
+    for seed in range(6):
+        net = circuit_network(random_circuit(4, 5, 10, seed=8400 + seed))
+        path = greedy_path(net)
+        sl = greedy_slice(net, path.pairs, n_sliced=1)
+        tn = tnc.Network(ctx, net.labels, net.extents, net.open, net.c64().leaves)
+        p = tnc.Plan(tn, path.pairs, sl, prec)
+        handles.append((tn, p))
+        items.append((p, 0, p.info.n_slices))
+    assert any(tnc.tnc_plan_get_batch_step(items[0][0].handle, s).kernel == 0
+               for s in range(items[0][0].info.n_steps))
+    try:
+        for variant in range(7):
+            tnc.tnc_ctx_set_gemm_variant(ctx.handle, variant)
+            alone, _ = _serve_each(ctx, items, fuse=False)
+            mix, st = _serve_each(ctx, items, fuse=True)
+            print(f"variant {variant}: fused {st}", flush=True)
+            assert st[1] >= 1 and st[2] >= 2
+            for i, (a, m) in enumerate(zip(alone, mix)):
+                assert np.array_equal(a.view(np.uint64), m.view(np.uint64)), (variant, i)
+    finally:
+        tnc.tnc_ctx_set_gemm_variant(ctx.handle, -1)
+    for tn, p in handles:
+        p.close()
+        tn.close()
+
+
 def test_fusion_takes_only_launch_bound_requests(served):
     """The server's default criterion fuses a light request only below 2^30
     planned FLOP per launch of its own run: six 4x5-grid circuits of depth
