@@ -38,7 +38,7 @@ double padding_waste(int variant, int64_t m, int64_t n) {
 // Ranking of the variants by measured per-tile throughput on large shapes.
 const std::vector<int>& ranking(tnc_prec prec, tnc_cgemm form) {
   static const std::vector<int> r4m = {3, 2, 0, 1, 4, 5, 6};
-  static const std::vector<int> r3m = {2, 0, 4, 1, 5, 6};
+  static const std::vector<int> r3m = {0, 2, 4, 1, 5, 6};  // 0: three (2,2) workgroups per CU
   static const std::vector<int> rbf = {3, 0, 2, 1, 4, 5, 6};  // 3: the wide-wave 256 x 128 tile
   if (prec == TNC_PREC_BF16X3) return rbf;
   return form == TNC_GEMM_3M ? r3m : r4m;

@@ -323,6 +323,7 @@ struct Ops4M {
   using S = Shape<WM, WN>;
   static constexpr bool kSwizzle = false;
   static constexpr int kPW = 1;
+  static constexpr size_t kLds = S::lds_f32;
   f16v acc[2][2];
 
   __device__ __forceinline__ void init() {
@@ -398,12 +399,25 @@ struct Ops4M {
 };
 
 // ------------------------------------------------------------------ 3M, FP32 MFMA
+// LDS rows are unpadded (32 floats) with their eight 16-byte slots permuted
+// by row (slot = chunk ^ ((row >> 1) & 7)): the fragment reads of 16 lanes
+// (16 consecutive rows, one chunk) and the staging stores of 16 lanes (two
+// rows) each hit 16 distinct 4-bank groups, as the padded rows of the other
+// kernels do, in 49152 instead of 55296 bytes for the (2,2) tile, so three
+// of its workgroups fit a CU (two with padded rows).
 template <int WM, int WN, int VW>
 struct Ops3M {
   using S = Shape<WM, WN>;
   static constexpr bool kSwizzle = false;
   static constexpr int kPW = 1;
+  static constexpr int P3 = 32;  // floats per LDS row
+  static constexpr size_t kLds = 2 * (S::BM + S::BNC) * P3 * sizeof(float);
   f16v t1[2], t2[2], t3[2];
+
+  // float offset of float fo (even) of LDS row `row`
+  __device__ __forceinline__ static int at(int row, int fo) {
+    return row * P3 + ((((fo >> 2) ^ ((row >> 1) & 7)) << 2) | (fo & 3));
+  }
 
   __device__ __forceinline__ void init() {
 #pragma unroll
@@ -413,23 +427,38 @@ struct Ops3M {
   }
 
   template <class St>
+  __device__ __forceinline__ static void put(float* base, int row, int idx, const f4& v) {
+    float* p = base + at(row, 2 * (idx % St::PER_ROW) * VW);
+    if constexpr (VW == 2) {
+      *reinterpret_cast<f4*>(p) = v;
+    } else {
+      p[0] = v.x;
+      p[1] = v.y;
+    }
+  }
+
+  template <class St>
   __device__ __forceinline__ void stage(const St& st, char* lds, int buf, int tid) const {
-    float* As = reinterpret_cast<float*>(lds) + buf * (S::BM + S::BNC) * PITCH;
-    st.store_f32(As, As + S::BM * PITCH, tid);
+    float* As = reinterpret_cast<float*>(lds) + buf * (S::BM + S::BNC) * P3;
+    float* Bs = As + S::BM * P3;
+#pragma unroll
+    for (int i = 0; i < St::A_LOADS; ++i) put<St>(As, St::row_a(tid + S::NT * i), tid + S::NT * i, st.a[i]);
+#pragma unroll
+    for (int i = 0; i < St::B_LOADS; ++i) put<St>(Bs, St::row_b(tid + S::NT * i), tid + S::NT * i, st.b[i]);
   }
 
   __device__ __forceinline__ void compute(const char* lds, int buf, int wm, int wn, int lane) {
-    const float* as = reinterpret_cast<const float*>(lds) + buf * (S::BM + S::BNC) * PITCH;
-    const float* bs = as + S::BM * PITCH;
+    const float* as = reinterpret_cast<const float*>(lds) + buf * (S::BM + S::BNC) * P3;
+    const float* bs = as + S::BM * P3;
     const int h = lane >> 5, l32 = lane & 31;
 #pragma unroll
     for (int g = 0; g < BKC / 4; ++g) {
       const int koff = (4 * g + 2 * h) * 2;
-      const f4 rb = *reinterpret_cast<const f4*>(bs + (wn * 32 + l32) * PITCH + koff);
+      const f4 rb = *reinterpret_cast<const f4*>(bs + at(wn * 32 + l32, koff));
       const float bs0 = rb.x + rb.y, bs1 = rb.z + rb.w;
 #pragma unroll
       for (int i = 0; i < 2; ++i) {
-        const f4 ra = *reinterpret_cast<const f4*>(as + (wm * 64 + i * 32 + l32) * PITCH + koff);
+        const f4 ra = *reinterpret_cast<const f4*>(as + at(wm * 64 + i * 32 + l32, koff));
         const float as0 = ra.x + ra.y, as1 = ra.z + ra.w;
         t1[i] = __builtin_amdgcn_mfma_f32_32x32x2f32(ra.x, rb.x, t1[i], 0, 0, 0);
         t2[i] = __builtin_amdgcn_mfma_f32_32x32x2f32(ra.y, rb.y, t2[i], 0, 0, 0);
@@ -491,6 +520,7 @@ struct OpsBF16x3 {
   using S = Shape<WM, WN>;
   static constexpr bool kSwizzle = true;
   static constexpr int kPW = 1;
+  static constexpr size_t kLds = S::lds_bf16;
   // hi*hi products and the two cross products accumulate separately: the
   // cross terms are ~2^-8 smaller, so their rounding barely adds to that of
   // the main sum
@@ -593,6 +623,7 @@ struct OpsBF16x3W {
   using S = Shape<WM, WN, 2>;
   static constexpr bool kSwizzle = true;
   static constexpr int kPW = 2;
+  static constexpr size_t kLds = S::lds_bf16;
   f16v acc[2][4];
 
   __device__ __forceinline__ void init() {
@@ -696,8 +727,18 @@ __device__ __forceinline__ void main_loop(const GemmDesc& d, const float2* A, co
   }
 }
 
+// Workgroups per CU the compiler must allow for: two for shapes of up to
+// four waves, three for 3M's (2,2) with 16-byte loads (its LDS admits
+// three; 168 VGPRs each; the 8-byte-load path needs more registers).
+template <template <int, int, int> class OpsT, int WM, int WN, int VW>
+constexpr int min_blocks() {
+  if constexpr (std::is_same_v<OpsT<2, 2, 2>, Ops3M<2, 2, 2>>)
+    if (WM * WN == 4 && VW == 2) return 3;
+  return WM * WN <= 4 ? 2 : 1;
+}
+
 template <template <int, int, int> class OpsT, int WM, int WN, int VW, bool PERM>
-__global__ __launch_bounds__(64 * WM * WN, (WM * WN <= 4) ? 2 : 1) void cgemm_mfma(GemmDesc d, int64_t tiles_m, int64_t tiles_n,
+__global__ __launch_bounds__(64 * WM * WN, (min_blocks<OpsT, WM, WN, VW>())) void cgemm_mfma(GemmDesc d, int64_t tiles_m, int64_t tiles_n,
                                                            int64_t total) {
   using S = Shape<WM, WN, OpsT<WM, WN, VW>::kPW>;
   extern __shared__ __attribute__((aligned(16))) char lds[];
@@ -1013,9 +1054,8 @@ hipError_t ensure_lds_grouped(size_t lds) {
 }
 
 template <template <int, int, int> class OpsT, int WM, int WN, bool GROUPED = true>
-void prepare_shape(bool bf16) {
-  using S = Shape<WM, WN, OpsT<WM, WN, 2>::kPW>;
-  const size_t lds = bf16 ? S::lds_bf16 : S::lds_f32;
+void prepare_shape(bool) {
+  const size_t lds = OpsT<WM, WN, 2>::kLds;
   (void)ensure_lds<OpsT, WM, WN, 2, false>(lds);
   (void)ensure_lds<OpsT, WM, WN, 2, true>(lds);
   if constexpr (GROUPED) (void)ensure_lds_grouped<OpsT, WM, WN>(lds);
@@ -1025,9 +1065,9 @@ void prepare_shape(bool bf16) {
 // than the tiles; at most 512 workgroups (two per compute unit), or 2048
 // waves for the shapes of fewer than four waves.
 template <template <int, int, int> class OpsT, int WM, int WN>
-hipError_t launch_grouped_shape(const GroupedEntry* tab, int n, int64_t total, bool bf16, hipStream_t s) {
+hipError_t launch_grouped_shape(const GroupedEntry* tab, int n, int64_t total, bool, hipStream_t s) {
   using S = Shape<WM, WN, OpsT<WM, WN, 2>::kPW>;
-  const size_t lds = bf16 ? S::lds_bf16 : S::lds_f32;
+  const size_t lds = OpsT<WM, WN, 2>::kLds;
   const hipError_t e = ensure_lds_grouped<OpsT, WM, WN>(lds);
   if (e != hipSuccess) return e;
   constexpr int64_t cap = WM * WN < 4 ? 2048 / (WM * WN) : 512;
@@ -1092,15 +1132,14 @@ void prepare_ops(bool bf16) {
   prepare_shape<OpsT, 1, 2, grouped_ok<OpsT>(4)>(bf16);
   prepare_shape<OpsT, 2, 1, grouped_ok<OpsT>(5)>(bf16);
   prepare_shape<OpsT, 1, 1, grouped_ok<OpsT>(6)>(bf16);
-  const size_t lds = bf16 ? Shape<2, 2>::lds_bf16 : Shape<2, 2>::lds_f32;  // odd-k path
+  const size_t lds = OpsT<2, 2, 1>::kLds;  // odd-k path
   (void)ensure_lds<OpsT, 2, 2, 1, false>(lds);
   (void)ensure_lds<OpsT, 2, 2, 1, true>(lds);
 }
 
 template <template <int, int, int> class OpsT, int WM, int WN>
-hipError_t launch_shape(const GemmDesc& d, bool bf16, hipStream_t s) {
-  using S = Shape<WM, WN, OpsT<WM, WN, 2>::kPW>;
-  const size_t lds = bf16 ? S::lds_bf16 : S::lds_f32;
+hipError_t launch_shape(const GemmDesc& d, bool, hipStream_t s) {
+  const size_t lds = OpsT<WM, WN, 2>::kLds;
   const bool perm = d.offM != nullptr;
   return perm ? launch_one<OpsT, WM, WN, 2, true>(d, lds, s) : launch_one<OpsT, WM, WN, 2, false>(d, lds, s);
 }
@@ -1108,7 +1147,7 @@ hipError_t launch_shape(const GemmDesc& d, bool bf16, hipStream_t s) {
 template <template <int, int, int> class OpsT>
 hipError_t launch_variant(const GemmDesc& d, int variant, bool bf16, hipStream_t s) {
   if ((d.k | row_stride(d)) % 2 != 0) {  // odd k or row stride: 8-byte loads, default shape only
-    const size_t lds = bf16 ? Shape<2, 2>::lds_bf16 : Shape<2, 2>::lds_f32;
+    const size_t lds = OpsT<2, 2, 1>::kLds;
     return d.offM ? launch_one<OpsT, 2, 2, 1, true>(d, lds, s) : launch_one<OpsT, 2, 2, 1, false>(d, lds, s);
   }
   // split precision: the 256 x 128 tile runs as 4x2 wide waves (16 waves of
