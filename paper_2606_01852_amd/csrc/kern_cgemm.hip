@@ -1005,6 +1005,23 @@ __global__ __launch_bounds__(512, 1) void cgemm_bf16x3_presplit(GemmDesc d, cons
   ops.store(d, PERM, tc, wm, wn, lane);
 }
 
+// LDS above 64 KiB for the pre-split kernel, once per device.
+hipError_t ensure_lds_presplit() {
+  static std::atomic<uint64_t> attr_set{0};
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return e;
+  const uint64_t bit = uint64_t{1} << (dev & 63);
+  if (attr_set.load(std::memory_order_acquire) & bit) return hipSuccess;
+  e = hipFuncSetAttribute(reinterpret_cast<const void*>(cgemm_bf16x3_presplit<false>),
+                          hipFuncAttributeMaxDynamicSharedMemorySize, static_cast<int>(PS_LDS));
+  if (e == hipSuccess)
+    e = hipFuncSetAttribute(reinterpret_cast<const void*>(cgemm_bf16x3_presplit<true>),
+                            hipFuncAttributeMaxDynamicSharedMemorySize, static_cast<int>(PS_LDS));
+  if (e == hipSuccess) attr_set.fetch_or(bit, std::memory_order_acq_rel);
+  return e;
+}
+
 // LDS above 64 KiB must be allowed per kernel, once per device (done for
 // every instance when a context is created, so that no first launch inside
 // a graph capture has to do it).
@@ -1173,6 +1190,7 @@ void prepare_gemm_kernels() {
   prepare_ops<Ops3M>(false);
   prepare_ops<OpsBF16x3>(true);
   prepare_shape<OpsBF16x3W, 4, 2, false>(true);
+  (void)ensure_lds_presplit();
 }
 
 void gemm_variant_tile(int variant, int* bm, int* bnc) {
@@ -1220,20 +1238,8 @@ hipError_t launch_gemm_presplit(const GemmDesc& d, void* planes, hipStream_t s) 
   const int64_t nkb = kp / 16;
   // one thread per padded element, counted in 32 bits
   if ((mp > np2 / 2 ? mp : np2 / 2) * kp >= (int64_t{1} << 31)) return hipErrorInvalidValue;
-  static std::atomic<uint64_t> attr_set{0};
-  int dev = 0;
-  hipError_t e = hipGetDevice(&dev);
+  const hipError_t e = ensure_lds_presplit();
   if (e != hipSuccess) return e;
-  const uint64_t bit = uint64_t{1} << (dev & 63);
-  if (!(attr_set.load(std::memory_order_acquire) & bit)) {
-    e = hipFuncSetAttribute(reinterpret_cast<const void*>(cgemm_bf16x3_presplit<false>),
-                            hipFuncAttributeMaxDynamicSharedMemorySize, static_cast<int>(PS_LDS));
-    if (e == hipSuccess)
-      e = hipFuncSetAttribute(reinterpret_cast<const void*>(cgemm_bf16x3_presplit<true>),
-                              hipFuncAttributeMaxDynamicSharedMemorySize, static_cast<int>(PS_LDS));
-    if (e != hipSuccess) return e;
-    attr_set.fetch_or(bit, std::memory_order_acq_rel);
-  }
   uint32_t* Ap = static_cast<uint32_t*>(planes);
   uint32_t* Bp = Ap + mp * 2 * kp;
   const int64_t ld = row_stride(d);

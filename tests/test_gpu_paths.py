@@ -206,7 +206,8 @@ def test_presplit_bf16x3_is_bitwise_the_wide_tile(ctx, order):
     and stage them global -> LDS directly: one GEMM of 4160 x 4224 x 200
     (ragged against the 256 x 128 tile, k padded to 208), stored row-major
     or in an interleaved consumer order.  The result is bitwise that of the
-    wide-wave kernel (variant 3, forced), within 1e-5 of the oracle's split
+    wide-wave kernel (variant 3, forced) and of its hipGraph replays, within
+    1e-5 of the oracle's split
     emulation, and every element within the split bound of the exact
     product."""
     rng = np.random.Generator(np.random.PCG64(4160))
@@ -231,6 +232,11 @@ def test_presplit_bf16x3_is_bitwise_the_wide_tile(ctx, order):
     finally:
         tnc.tnc_ctx_set_gemm_variant(ctx.handle, -1)
     assert np.array_equal(np.asarray(z).view(np.uint64), np.asarray(w).view(np.uint64))
+    # captured as a hipGraph (splits and GEMM in the graph), replayed twice
+    tnc.tnc_plan_set_graph(plan.handle, True)
+    for _ in range(2):
+        g = plan.contract().reshape(np.asarray(z).shape)
+        assert np.array_equal(g.view(np.uint64), np.asarray(z).view(np.uint64))
     emu = oc.contract(net, path, step=osp.split_step)
     err = assert_close(z, emu, tol=1e-5, what="presplit vs emulation")
     # exact product and the split bound 3 * 2^-16 * sum_l (|ar|+|ai|)(|br|+|bi|) per element
