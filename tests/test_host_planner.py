@@ -159,6 +159,56 @@ def test_pair30_structure(hctx):
     assert plan.info.transpose_bytes == 16.0 * (2 ** 30 + 2 ** 28)
 
 
+def test_presplit_steps_and_their_plane_buffer(hctx):
+    """Split precision plans large single GEMMs (h = 1, launch m and n >=
+    4096) on pre-split planes: the step says so, the other precisions and
+    small or batched steps do not, and the planned peak grows by exactly the
+    planes' bytes (A rows padded to 256, B' = 2 rows per complex column
+    padded to 128 columns, k padded to 16, 8 bytes per padded element
+    each)."""
+    def one_gemm(m, n, k, h=1):
+        ext = [h, m, n, k]
+        net = Network([None, None], [(0, 1, 3), (0, 2, 3)], np.array(ext, dtype=np.int64), (0, 1, 2))
+        tn = tnc.Network(hctx, net.labels, net.extents, net.open)
+        return tn, {prec: tnc.Plan(tn, np.array([[0, 1]], dtype=np.int32), (), prec)
+                    for prec in (tnc.PREC_C64, tnc.PREC_BF16X3)}
+    align = 256
+    for (m, n, k, h, expect) in ((4100, 4200, 1000, 1, True), (65536, 16384, 16384, 1, True),
+                                 (4096, 2048, 512, 1, False), (4096, 4096, 512, 2, False)):
+        tn, plans = one_gemm(m, n, k, h)
+        st = {prec: p.step(0) for prec, p in plans.items()}
+        assert st[tnc.PREC_C64].presplit == 0
+        assert st[tnc.PREC_BF16X3].presplit == (1 if expect else 0), (m, n, k, h)
+        grow = plans[tnc.PREC_BF16X3].info.peak_bytes - plans[tnc.PREC_C64].info.peak_bytes
+        if expect:
+            s = st[tnc.PREC_BF16X3]
+            lm, ln = (s.n, s.m) if s.swapped else (s.m, s.n)   # the launch's rows and columns
+            planes = (-(-lm // 256) * 256 + 2 * (-(-ln // 128) * 128)) * (-(-k // 16) * 16) * 8
+            assert grow == -(-planes // align) * align, (m, n, k, grow, planes)
+        else:
+            assert grow == 0
+        for p in plans.values():
+            p.close()
+        tn.close()
+
+
+def test_launch_counts_of_a_run(hctx):
+    """n_launches counts the launches of one eager run: level grouping cuts
+    them, a step-by-step run issues at least one per step plus the
+    reduction."""
+    net, path = configs.circuit12()
+    tn = tnc.Network(hctx, net.labels, net.extents, net.open)
+    counts = {}
+    for grouping in (False, True):
+        p = tnc.Plan(tn, path.pairs)
+        tnc.tnc_plan_set_grouping(p.handle, grouping)
+        counts[grouping] = tnc.tnc_plan_get_info(p.handle).n_launches
+        p.close()
+    assert counts[False] >= len(path.pairs) + 1
+    assert counts[True] < counts[False] // 4, counts
+    tn.close()
+
+
 def test_errors_are_reported_not_raised_across_the_abi(hctx):
     with pytest.raises(tnc.TncError) as e:       # closed hyperedge
         tnc.Network(hctx, [(0, 1), (1, 2), (1, 3)], [2, 2, 2, 2], [0, 2, 3])
