@@ -195,6 +195,10 @@ typedef struct {
                                     split once into bf16 planes (in the plan's
                                     arena) and staged global -> LDS directly;
                                     bitwise the result of variant 3          */
+  int32_t presplit_fused;        /* bit 0 / bit 1: the permute that prepares
+                                    operand A / B' (a leaf) writes its planes
+                                    itself, one pass instead of a permute and
+                                    a split                                  */
 } tnc_step_info;
 tnc_status tnc_plan_get_step(tnc_plan plan, int32_t step, tnc_step_info* out);
 /* The same view for the batch of max_chunk slices the executor runs (h then

@@ -386,6 +386,11 @@ static void step_info(const ChunkPlan& c, int32_t step, tnc_step_info* out) {
   i.hA = s.hA;
   i.hB = s.hB;
   i.presplit = s.presplit ? 1 : 0;
+  for (int side = 1; side <= 2; ++side) {
+    const int id = side == 1 ? s.la : s.lb;
+    if (id >= 0 && id < static_cast<int>(c.leaf.size()) && c.leaf[id].planes_side == side)
+      i.presplit_fused |= side;
+  }
   *out = i;
 }
 

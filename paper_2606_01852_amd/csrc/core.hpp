@@ -150,6 +150,9 @@ struct LeafPrep {
   // a leaf with a per-chunk base offset consumed by a one-thread-per-output
   // GEMM is read in place through the step's operand tables (no gather)
   bool inplace = false;
+  // a tiled permute feeding a pre-split step writes that step's planes
+  // (1: its A, 2: its B') instead of complex64, when the step runs pre-split
+  int planes_side = 0;
 };
 
 struct StepPlan {

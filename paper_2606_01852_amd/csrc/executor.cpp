@@ -174,7 +174,7 @@ namespace {
 // plan's device blob); `bd` points at a per-chunk base offset on the device
 // (null: none).
 hipError_t launch_planned_permute(const PermuteHost& p, const ChunkPlan& cp, const float2* in, float2* out,
-                                  const int64_t* bd, hipStream_t stream) {
+                                  const int64_t* bd, hipStream_t stream, int planes = 0, int64_t pk = 0) {
   const char* blob = static_cast<const char*>(cp.blob.ptr);
   if (p.tiled) {
     PermuteDesc d{};
@@ -193,8 +193,11 @@ hipError_t launch_planned_permute(const PermuteHost& p, const ChunkPlan& cp, con
     d.base = 0;
     d.base_dev = bd;
     d.pairs = p.pairs ? 1 : 0;
+    d.planes = planes;
+    d.pk = pk;
     return launch_permute(d, stream);
   }
+  if (planes) return hipErrorInvalidValue;  // plane output is planned for tiled permutes only
   GatherDesc g = p.plain;
   g.in = in;
   g.out = out;
@@ -204,10 +207,12 @@ hipError_t launch_planned_permute(const PermuteHost& p, const ChunkPlan& cp, con
 }
 
 // Launch the gather-permute of leaf t into `out`; `bd` points at its
-// per-chunk base offset on the device (null: none).
+// per-chunk base offset on the device (null: none).  planes = 1 / 2: out
+// is the consuming step's A / B' planes (rows of pk complex).
 hipError_t launch_leaf_prep(const Net& net, const ChunkPlan& cp, int t, float2* out, const int64_t* bd,
-                            hipStream_t stream) {
-  return launch_planned_permute(cp.leaf[t].perm, cp, static_cast<const float2*>(net.leaf[t].ptr), out, bd, stream);
+                            hipStream_t stream, int planes = 0, int64_t pk = 0) {
+  return launch_planned_permute(cp.leaf[t].perm, cp, static_cast<const float2*>(net.leaf[t].ptr), out, bd, stream,
+                                planes, pk);
 }
 
 // (Re)fill the leaf cache when it is empty or a cached leaf's data has been
@@ -285,11 +290,27 @@ struct ChunkOps {
     if (id == cp.root_id && a.direct_out) return a.direct_out;
     return reinterpret_cast<float2*>(a.arena + cp.buf_off[cp.tensor_buf[id]]);
   }
+  // a forced tile variant (tnc_ctx_set_gemm_variant) runs every MFMA step
+  // on that variant, pre-split steps included
+  bool presplit(const StepPlan& sp) const { return sp.presplit && net.ctx->gemm_variant < 0; }
+  // 1 / 2: leaf t's permute writes its step's A / B' planes this run
+  int planes_of(int t) const {
+    const LeafPrep& lp = cp.leaf[t];
+    return lp.planes_side && presplit(cp.steps[lp.step]) ? lp.planes_side : 0;
+  }
+  // the step's planes: A's, then B''s
+  char* planes(const StepPlan& sp, int side) const {
+    char* p = a.arena + cp.buf_off[sp.presplit_buf];
+    return side == 2 ? p + presplit_rows_a(sp.lm) * presplit_k(sp.k) * 8 : p;
+  }
   void prep(int t) {
     const LeafPrep& lp = cp.leaf[t];
-    float2* out = ptr(t);
+    const int side = planes_of(t);
+    const StepPlan* sp = side ? &cp.steps[lp.step] : nullptr;
+    float2* out = side ? reinterpret_cast<float2*>(planes(*sp, side)) : ptr(t);
     const int64_t* bd = lp.base_slot >= 0 ? bases + lp.base_slot : nullptr;
-    L.run(t_prep, stream, [&] { return launch_leaf_prep(net, cp, t, out, bd, stream); });
+    const int64_t pk = side ? sp->k : 0;
+    L.run(t_prep, stream, [&] { return launch_leaf_prep(net, cp, t, out, bd, stream, side, pk); });
   }
   int variant(const StepPlan& sp) const { return net.ctx->gemm_variant >= 0 ? net.ctx->gemm_variant : sp.variant; }
   // The step's launch descriptor with this run's pointers (the split-K
@@ -321,15 +342,14 @@ struct ChunkOps {
       return launch_splitk_reduce(d.C, c, sp.h, sp.lm, sp.ln, sp.split, sp.dev_offM, sp.dev_offN, stream);
     });
   }
-  // a forced tile variant (tnc_ctx_set_gemm_variant) runs every MFMA step
-  // on that variant, pre-split steps included
-  bool presplit(const StepPlan& sp) const { return sp.presplit && net.ctx->gemm_variant < 0; }
   void step(int s) {
     const StepPlan& sp = cp.steps[s];
     const GemmDesc d = desc(s);
     if (presplit(sp)) {
-      void* planes = a.arena + cp.buf_off[sp.presplit_buf];
-      L.run(s, stream, [&] { return launch_gemm_presplit(d, planes, stream); });
+      void* p = planes(sp, 1);
+      // operands whose permute wrote the planes are not split again
+      const bool have_a = sp.la < n && planes_of(sp.la) == 1, have_b = sp.lb < n && planes_of(sp.lb) == 2;
+      L.run(s, stream, [&] { return launch_gemm_presplit(d, p, have_a, have_b, stream); });
     } else {
       L.run(s, stream, [&] { return launch_gemm(d, sp.kind, variant(sp), form, prec, stream); });
     }

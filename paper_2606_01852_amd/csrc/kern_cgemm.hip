@@ -40,6 +40,7 @@
 #include <atomic>
 #include <type_traits>
 
+#include "bf16_split.hpp"
 #include "gemm_common.hpp"
 
 namespace tnc {
@@ -187,12 +188,7 @@ struct Stage {
   // packed [first | second << 16]; lo = rne(x - hi), x - hi exact in
   // float32).
   __device__ __forceinline__ static void split2(float x, float y, uint32_t& hi, uint32_t& lo) {
-    typedef float fv2 __attribute__((ext_vector_type(2)));
-    typedef __bf16 bv2 __attribute__((ext_vector_type(2)));
-    hi = __builtin_bit_cast(uint32_t, __builtin_convertvector((fv2){x, y}, bv2));
-    const float rx = x - __uint_as_float(hi << 16);
-    const float ry = y - __uint_as_float(hi & 0xFFFF0000u);
-    lo = __builtin_bit_cast(uint32_t, __builtin_convertvector((fv2){rx, ry}, bv2));
+    bf16_split2(x, y, hi, lo);
   }
 
   // A: the staged floats in place (real k index = 2 * complex k + re/im).
@@ -1229,7 +1225,7 @@ hipError_t launch_gemm_grouped(const GroupedEntry* dev, int n, int64_t total, in
   return launch_grouped_variant<Ops4M>(dev, n, total, variant, false, s);
 }
 
-hipError_t launch_gemm_presplit(const GemmDesc& d, void* planes, hipStream_t s) {
+hipError_t launch_gemm_presplit(const GemmDesc& d, void* planes, bool have_a, bool have_b, hipStream_t s) {
   if (d.h <= 0 || d.m <= 0 || d.n <= 0) return hipSuccess;
   if (d.k <= 0 || d.h != 1 || d.rowA || d.kA || d.rowB || d.kB || !planes ||
       reinterpret_cast<uintptr_t>(planes) % 256 != 0)
@@ -1248,10 +1244,12 @@ hipError_t launch_gemm_presplit(const GemmDesc& d, void* planes, hipStream_t s) 
     return static_cast<unsigned>(g < 131072 ? g : 131072);
   };
   const uint32_t blocks_a = static_cast<uint32_t>(mp * nkb), blocks_b = static_cast<uint32_t>(np2 / 2 * nkb);
-  hipLaunchKernelGGL(split_planes_a, dim3(grid(int64_t{blocks_a} * 16)), dim3(256), 0, s, d.A, d.m, d.k, ld,
-                     static_cast<uint32_t>(nkb), blocks_a, kp, Ap);
-  hipLaunchKernelGGL(split_planes_b, dim3(grid(int64_t{blocks_b} * 16)), dim3(256), 0, s, d.B, d.n, d.k, ld,
-                     static_cast<uint32_t>(nkb), blocks_b, kp, Bp);
+  if (!have_a)
+    hipLaunchKernelGGL(split_planes_a, dim3(grid(int64_t{blocks_a} * 16)), dim3(256), 0, s, d.A, d.m, d.k, ld,
+                       static_cast<uint32_t>(nkb), blocks_a, kp, Ap);
+  if (!have_b)
+    hipLaunchKernelGGL(split_planes_b, dim3(grid(int64_t{blocks_b} * 16)), dim3(256), 0, s, d.B, d.n, d.k, ld,
+                       static_cast<uint32_t>(nkb), blocks_b, kp, Bp);
   const int64_t tiles_m = mp / kPresplitBM, tiles_n = np2 / 2 / kPresplitBNC, total = tiles_m * tiles_n;
   if (d.offM)
     hipLaunchKernelGGL(cgemm_bf16x3_presplit<true>, dim3(static_cast<unsigned>(total)), dim3(512), PS_LDS, s, d, Ap,

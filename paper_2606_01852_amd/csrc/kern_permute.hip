@@ -17,7 +17,9 @@
 // 2^30-element operand both together moved the kernel from 5.1 to 5.7 TB/s
 // (a plain copy kernel built the same way: 6.2 TB/s).
 #include <mutex>
+#include <type_traits>
 
+#include "bf16_split.hpp"
 #include "kernels.hpp"
 
 // Table area of the permutes that allocate nothing: the index tables of
@@ -54,7 +56,19 @@ constexpr int kPermThreads = 256;
 
 typedef float f2v __attribute__((ext_vector_type(2)));
 
-template <int EPT>
+// Output element o of a permutation: complex64, or its split into the
+// planes of a split-precision GEMM operand (PermuteDesc::planes).
+template <int PLANES>
+__device__ __forceinline__ void put_out(f2v* __restrict__ out, int64_t o, f2v v, int64_t pk, double inv_pk) {
+  if constexpr (PLANES == 0)
+    __builtin_nontemporal_store(v, out + o);
+  else if constexpr (PLANES == 1)
+    put_planes_a(reinterpret_cast<uint32_t*>(out), o, v.x, v.y);
+  else
+    put_planes_b(reinterpret_cast<uint32_t*>(out), o, pk, inv_pk, v.x, v.y);
+}
+
+template <int EPT, int PLANES>
 __global__ __launch_bounds__(kPermThreads) void permute_tiled(PermuteDesc d) {
   extern __shared__ f2v lds[];
   const f2v* __restrict__ in = reinterpret_cast<const f2v*>(d.in);
@@ -72,6 +86,7 @@ __global__ __launch_bounds__(kPermThreads) void permute_tiled(PermuteDesc d) {
   }
   const int64_t base = d.base + (d.base_dev ? d.base_dev[0] : 0);
   const uint32_t L = static_cast<uint32_t>(d.L);
+  const double inv_pk = PLANES == 2 ? 1.0 / static_cast<double>(d.pk) : 0.0;
   int64_t tile = blockIdx.x;
   if (tile >= d.n_tiles) return;
   f2v v[EPT];
@@ -96,7 +111,7 @@ __global__ __launch_bounds__(kPermThreads) void permute_tiled(PermuteDesc d) {
     if (next < d.n_tiles) load(next);
 #pragma unroll
     for (int e = 0; e < EPT; ++e)
-      if (out_off[e] >= 0) __builtin_nontemporal_store(lds[slot_w[e]], out + ob + out_off[e]);
+      if (out_off[e] >= 0) put_out<PLANES>(out, ob + out_off[e], lds[slot_w[e]], d.pk, inv_pk);
     __syncthreads();
   }
 }
@@ -107,7 +122,7 @@ __global__ __launch_bounds__(kPermThreads) void permute_tiled(PermuteDesc d) {
 // load and one 16-byte store each, through the same LDS slots.
 typedef float f4v __attribute__((ext_vector_type(4)));
 
-template <int PPT>
+template <int PPT, int PLANES>
 __global__ __launch_bounds__(kPermThreads) void permute_pairs(PermuteDesc d) {
   extern __shared__ f2v lds[];
   const f2v* __restrict__ in = reinterpret_cast<const f2v*>(d.in);
@@ -128,6 +143,7 @@ __global__ __launch_bounds__(kPermThreads) void permute_pairs(PermuteDesc d) {
   }
   const int64_t base = d.base;
   const uint32_t L = static_cast<uint32_t>(d.L);
+  const double inv_pk = PLANES == 2 ? 1.0 / static_cast<double>(d.pk) : 0.0;
   int64_t tile = blockIdx.x;
   if (tile >= d.n_tiles) return;
   f4v v[PPT];
@@ -157,7 +173,13 @@ __global__ __launch_bounds__(kPermThreads) void permute_pairs(PermuteDesc d) {
     for (int e = 0; e < PPT; ++e)
       if (out_off[e] >= 0) {
         const f2v a = lds[sw0[e]], b = lds[sw1[e]];
-        __builtin_nontemporal_store(f4v{a.x, a.y, b.x, b.y}, reinterpret_cast<f4v*>(out + ob + out_off[e]));
+        const int64_t o = ob + out_off[e];
+        if constexpr (PLANES == 0)
+          __builtin_nontemporal_store(f4v{a.x, a.y, b.x, b.y}, reinterpret_cast<f4v*>(out + o));
+        else if constexpr (PLANES == 1)
+          put_planes_a2(reinterpret_cast<uint32_t*>(out), o, a.x, a.y, b.x, b.y);
+        else
+          put_planes_b2(reinterpret_cast<uint32_t*>(out), o, d.pk, inv_pk, a.x, a.y, b.x, b.y);
       }
     __syncthreads();
   }
@@ -198,31 +220,38 @@ hipError_t launch_permute(const PermuteDesc& d, hipStream_t s) {
   // ms); pairs per thread follow the element rule (8 pairs where it takes
   // 16 elements)
   const bool aligned = (reinterpret_cast<uintptr_t>(d.in) | reinterpret_cast<uintptr_t>(d.out)) % 16 == 0;
-  if (d.pairs && !d.base_dev && d.base % 2 == 0 && aligned && ept >= 2) {
-    switch (ept / 2) {
+  if (d.planes < 0 || d.planes > 2 || (d.planes && (d.pk <= 0 || d.pk % 16 != 0))) return hipErrorInvalidValue;
+  auto launch = [&](auto plane_tag) -> hipError_t {
+    constexpr int PL = decltype(plane_tag)::value;
+    if (d.pairs && !d.base_dev && d.base % 2 == 0 && aligned && ept >= 2) {
+      switch (ept / 2) {
 #define TNC_PAIR_CASE(E) \
-  case E: hipLaunchKernelGGL(permute_pairs<E>, dim3(grid), dim3(kPermThreads), lds, s, d); return hipGetLastError();
-      TNC_PAIR_CASE(1)
-      TNC_PAIR_CASE(2)
-      TNC_PAIR_CASE(4)
-      TNC_PAIR_CASE(8)
+  case E: hipLaunchKernelGGL((permute_pairs<E, PL>), dim3(grid), dim3(kPermThreads), lds, s, d); return hipGetLastError();
+        TNC_PAIR_CASE(1)
+        TNC_PAIR_CASE(2)
+        TNC_PAIR_CASE(4)
+        TNC_PAIR_CASE(8)
 #undef TNC_PAIR_CASE
-      default: break;
+        default: break;
+      }
     }
-  }
-  switch (ept) {
+    switch (ept) {
 #define TNC_PERM_CASE(E) \
-  case E: hipLaunchKernelGGL(permute_tiled<E>, dim3(grid), dim3(kPermThreads), lds, s, d); break;
-    TNC_PERM_CASE(1)
-    TNC_PERM_CASE(2)
-    TNC_PERM_CASE(4)
-    TNC_PERM_CASE(8)
-    TNC_PERM_CASE(16)
+  case E: hipLaunchKernelGGL((permute_tiled<E, PL>), dim3(grid), dim3(kPermThreads), lds, s, d); break;
+      TNC_PERM_CASE(1)
+      TNC_PERM_CASE(2)
+      TNC_PERM_CASE(4)
+      TNC_PERM_CASE(8)
+      TNC_PERM_CASE(16)
 #undef TNC_PERM_CASE
-    default:
-      return hipErrorInvalidValue;
-  }
-  return hipGetLastError();
+      default:
+        return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+  };
+  if (d.planes == 1) return launch(std::integral_constant<int, 1>{});
+  if (d.planes == 2) return launch(std::integral_constant<int, 2>{});
+  return launch(std::integral_constant<int, 0>{});
 }
 
 hipError_t launch_gather(const GatherDesc& d, hipStream_t s) {

@@ -94,6 +94,11 @@ struct PermuteDesc {
   int64_t base;                // constant input offset
   const int64_t* base_dev;     // optional extra input offset read on device
   int32_t pairs;               // the tables allow 16-byte pairs (PermuteHost::pairs)
+  // 0: write complex64 to out; 1 / 2: write the split planes of a
+  // split-precision GEMM's A / B' operand (out = the planes, rows of pk
+  // complex, pk a multiple of 16)
+  int32_t planes;
+  int64_t pk;
 };
 
 // Plain gather: out[w] = in[base + sum_d digit_d(w) * in_stride[d]] over
@@ -154,7 +159,9 @@ inline size_t presplit_plane_bytes(int64_t m, int64_t n, int64_t k) {
   // per row and 16 complex k: 128 bytes (32 bf16 hi, 32 bf16 lo)
   return static_cast<size_t>((presplit_rows_a(m) + presplit_rows_b(n)) * presplit_k(k) * 8);
 }
-hipError_t launch_gemm_presplit(const GemmDesc& d, void* planes, hipStream_t s);
+// have_a / have_b: that operand's planes are already written (by the
+// permute that produced it) and are not split again.
+hipError_t launch_gemm_presplit(const GemmDesc& d, void* planes, bool have_a, bool have_b, hipStream_t s);
 // Split-K epilogue: C[b, i, j] = sum_{p < S} P[((b * S + p) * m + i) * n + j],
 // p ascending, stored at b * m * n + (offM ? offM[i] + offN[j] : i * n + j).
 hipError_t launch_splitk_reduce(const float2* P, float2* C, int64_t h, int64_t m, int64_t n, int64_t S,

@@ -676,6 +676,15 @@ std::unique_ptr<ChunkPlan> build_chunk(const Plan& plan, int j) {
     // every workgroup that reads it
     sp.presplit = plan.prec == TNC_PREC_BF16X3 && sp.kind == GemmKernel::MFMA && sp.split == 1 && !sp.trans &&
                   d.h == 1 && sp.lm >= 4096 && sp.ln >= 4096;
+    // an operand leaf that is permuted anyway writes the planes itself (the
+    // permute and the split in one pass) when rows are whole 16-k blocks
+    if (sp.presplit && sp.k % 16 == 0 && row_stride(d) == sp.k)
+      for (int side = 1; side <= 2; ++side) {
+        const int id = side == 1 ? sp.la : sp.lb;
+        if (id >= n) continue;
+        LeafPrep& lp = cp->leaf[id];
+        if (!lp.direct && !lp.cached && !lp.inplace && lp.perm.tiled) lp.planes_side = side;
+      }
     cp->flops += 8.0 * static_cast<double>(sp.h) * sp.m * sp.n * sp.k;
     cp->bytes += 8.0 * (static_cast<double>(sp.hA) * sp.m * sp.k + static_cast<double>(sp.hB) * sp.n * sp.k +
                         static_cast<double>(sp.h) * sp.m * sp.n);

@@ -48,7 +48,7 @@ class StepInfo(C.Structure):
                 ("nN", C.c_int32), ("nK", C.c_int32), ("h", C.c_int64), ("m", C.c_int64), ("n", C.c_int64),
                 ("k", C.c_int64), ("natural", C.c_int32), ("kernel", C.c_int32), ("variant", C.c_int32),
                 ("swapped", C.c_int32), ("split", C.c_int32), ("hA", C.c_int64), ("hB", C.c_int64),
-                ("presplit", C.c_int32)]
+                ("presplit", C.c_int32), ("presplit_fused", C.c_int32)]
 
 
 class DistHW(C.Structure):

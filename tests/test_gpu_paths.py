@@ -200,19 +200,23 @@ def test_grid8_bf16x3_wide_tile_permuted_stores(ctx):
     assert abs(z - exact) <= t_exact * abs(exact)
 
 
+@pytest.mark.parametrize("leaves", ["canonical", "permuted"])
 @pytest.mark.parametrize("order", ["natural", "interleaved"])
-def test_presplit_bf16x3_is_bitwise_the_wide_tile(ctx, order):
+def test_presplit_bf16x3_is_bitwise_the_wide_tile(ctx, order, leaves):
     """Large split-bf16x3 steps split their operands once into bf16 planes
     and stage them global -> LDS directly: one GEMM of 4160 x 4224 x 200
     (ragged against the 256 x 128 tile, k padded to 208), stored row-major
-    or in an interleaved consumer order.  The result is bitwise that of the
-    wide-wave kernel (variant 3, forced) and of its hipGraph replays, within
-    1e-5 of the oracle's split
-    emulation, and every element within the split bound of the exact
-    product."""
+    or in an interleaved consumer order.  With permuted leaves (stored K
+    first, M or N labels reversed; 4160 x 4224 x 1024, so that they exceed
+    the 2^22-element leaf cache) the leaf permutes write the planes
+    themselves (one pass), while the forced wide-wave run permutes them to
+    complex64 as usual.  The result is bitwise that of the wide-wave kernel
+    (variant 3, forced) and of its hipGraph replays, within 1e-5 of the
+    oracle's split emulation, and every element within the split bound of
+    the exact product."""
     rng = np.random.Generator(np.random.PCG64(4160))
-    ext = np.array([64, 65, 66, 64, 200], dtype=np.int64)
-    la, lb = (0, 1, 4), (2, 3, 4)
+    ext = np.array([64, 65, 66, 64, 200] if leaves == "canonical" else [64, 65, 64, 66, 1024], dtype=np.int64)
+    la, lb = ((0, 1, 4), (2, 3, 4)) if leaves == "canonical" else ((4, 1, 0), (4, 3, 2))
 
     def cn(lab):
         shape = tuple(int(ext[l]) for l in lab)
@@ -221,11 +225,13 @@ def test_presplit_bf16x3_is_bitwise_the_wide_tile(ctx, order):
     out = (0, 1, 2, 3) if order == "natural" else (0, 2, 1, 3)
     net = Network([cn(la), cn(lb)], [la, lb], ext, out)
     path = Path(np.array([[0, 1]], dtype=np.int32), ())
-    print(f"presplit bf16x3 {order}", flush=True)
+    print(f"presplit bf16x3 {order} {leaves}", flush=True)
     z, plan, _ = run(ctx, net, path, prec=tnc.PREC_BF16X3)
     st = tnc.tnc_plan_get_step(plan.handle, 0)
     assert st.kernel == 0 and st.presplit == 1 and st.split == 1
     assert st.natural == (1 if order == "natural" else 0)
+    assert plan.info.n_permutes == (0 if leaves == "canonical" else 2)
+    assert st.presplit_fused == (0 if leaves == "canonical" else 3)    # both permutes write planes
     tnc.tnc_ctx_set_gemm_variant(ctx.handle, 3)
     try:
         w, _, _ = run(ctx, net, path, prec=tnc.PREC_BF16X3)
@@ -240,16 +246,17 @@ def test_presplit_bf16x3_is_bitwise_the_wide_tile(ctx, order):
     emu = oc.contract(net, path, step=osp.split_step)
     err = assert_close(z, emu, tol=1e-5, what="presplit vs emulation")
     # exact product and the split bound 3 * 2^-16 * sum_l (|ar|+|ai|)(|br|+|bi|) per element
-    A = net.leaves[0].reshape(64 * 65, 200).astype(np.complex128)
-    B = net.leaves[1].reshape(66 * 64, 200).astype(np.complex128)
-    exact = (A @ B.T).reshape(64, 65, 66, 64)
+    e0, e1, e2, e3, kk = (int(x) for x in ext)
+    A = np.transpose(net.leaves[0], [la.index(x) for x in (0, 1, 4)]).reshape(e0 * e1, kk).astype(np.complex128)
+    B = np.transpose(net.leaves[1], [lb.index(x) for x in (2, 3, 4)]).reshape(e2 * e3, kk).astype(np.complex128)
+    exact = (A @ B.T).reshape(e0, e1, e2, e3)
     bound = (3 * 2.0 ** -16 * ((np.abs(A.real) + np.abs(A.imag)) @ (np.abs(B.real) + np.abs(B.imag)).T)
-             .reshape(64, 65, 66, 64))
+             .reshape(e0, e1, e2, e3))
     if order != "natural":
         exact = exact.transpose(0, 2, 1, 3)
         bound = bound.transpose(0, 2, 1, 3)
     assert np.all(np.abs(np.asarray(z) - exact) <= bound + 1e-6 * np.abs(exact))
-    print(f"presplit bf16x3 {order}: err vs emulation {err:.2e}, bitwise = wide tile", flush=True)
+    print(f"presplit bf16x3 {order} {leaves}: err vs emulation {err:.2e}, bitwise = wide tile", flush=True)
 
 
 def interleaved_pair(z, a, b, c, d, k, seed):
