@@ -200,7 +200,15 @@ def test_grid8_bf16x3_wide_tile_permuted_stores(ctx):
     assert abs(z - exact) <= t_exact * abs(exact)
 
 
-@pytest.mark.parametrize("leaves", ["canonical", "permuted"])
+PRESPLIT_LEAVES = {
+    # extents, stored labels of A and of B
+    "canonical": ([64, 65, 66, 64, 200], (0, 1, 4), (2, 3, 4)),
+    "permuted": ([64, 65, 64, 66, 1024], (4, 1, 0), (4, 3, 2)),
+    "permuted_odd": ([66, 63, 63, 66, 1024], (4, 0, 1), (4, 3, 2)),
+}
+
+
+@pytest.mark.parametrize("leaves", list(PRESPLIT_LEAVES))
 @pytest.mark.parametrize("order", ["natural", "interleaved"])
 def test_presplit_bf16x3_is_bitwise_the_wide_tile(ctx, order, leaves):
     """Large split-bf16x3 steps split their operands once into bf16 planes
@@ -210,13 +218,15 @@ def test_presplit_bf16x3_is_bitwise_the_wide_tile(ctx, order, leaves):
     first, M or N labels reversed; 4160 x 4224 x 1024, so that they exceed
     the 2^22-element leaf cache) the leaf permutes write the planes
     themselves (one pass), while the forced wide-wave run permutes them to
-    complex64 as usual.  The result is bitwise that of the wide-wave kernel
-    (variant 3, forced) and of its hipGraph replays, within 1e-5 of the
-    oracle's split emulation, and every element within the split bound of
-    the exact product."""
+    complex64 as usual: "permuted" has even input runs (the 16-byte pair
+    kernel), "permuted_odd" input runs of 63 elements (the element-wise
+    tiled kernel, 4158 x 4158 x 1024).  The result is bitwise that of the
+    wide-wave kernel (variant 3, forced) and of its hipGraph replays,
+    within 1e-5 of the oracle's split emulation, and every element within
+    the split bound of the exact product."""
     rng = np.random.Generator(np.random.PCG64(4160))
-    ext = np.array([64, 65, 66, 64, 200] if leaves == "canonical" else [64, 65, 64, 66, 1024], dtype=np.int64)
-    la, lb = ((0, 1, 4), (2, 3, 4)) if leaves == "canonical" else ((4, 1, 0), (4, 3, 2))
+    ext, la, lb = PRESPLIT_LEAVES[leaves]
+    ext = np.array(ext, dtype=np.int64)
 
     def cn(lab):
         shape = tuple(int(ext[l]) for l in lab)
