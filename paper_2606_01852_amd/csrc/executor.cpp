@@ -263,8 +263,6 @@ struct Launcher {
 
 namespace {
 
-// Enqueue one chunk: leaf permutations, one GEMM per step, the FP64
-// reduction of the root.  `bases` points at this chunk's leaf base offsets.
 // The launches of one chunk of one run, one piece at a time: a leaf's
 // preparation, a step's GEMM, a level's grouped gathers and small GEMMs,
 // the FP64 reduction of the root.  `bases` points at the chunk's leaf base
