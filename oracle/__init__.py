@@ -17,7 +17,8 @@ Contraction on Multiple GPUs"):
   costs        per-step m, n, k and the path costs C_t, C_s, C_m
                (Sec. II-B, Eq. (1)-(3)); 8 real FLOPs per complex MAC
   split        bf16 hi/lo split by round-to-nearest-even bit manipulation and
-               the three-product emulation of a split-precision product
+               the three-product emulation of a split-precision product, in
+               the 4M and the 3M complex form
   distplan     keep-or-redistribute choices along a use-chain by exhaustive
                enumeration under the cost model (Sec. IV-B, Eq. (4)-(7))
 """

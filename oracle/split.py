@@ -6,8 +6,11 @@ Split precision (an extension; the paper itself runs complex64 with FP32
 arithmetic, Sec. V): every float32 value x becomes
     x_hi = bf16_rne(x),  x_lo = bf16_rne(x - x_hi)
 and every real product a*b is replaced by a_hi b_hi + a_hi b_lo + a_lo b_hi.
-A complex product uses four such real products:
-    re = (ar br) - (ai bi),   im = (ar bi) + (ai br).
+A complex product uses four such real products (4M form):
+    re = (ar br) - (ai bi),   im = (ar bi) + (ai br),
+or three (3M form): T1 = ar br, T2 = ai bi, T3 = (ar + ai)(br + bi), with
+the sums formed in float32 like the other float32 planes, re = T1 - T2,
+im = T3 - T1 - T2.
 Each bf16 x bf16 product is exact in float32 and in float64, so the
 emulation below (three-term products summed in float64, then the step
 result rounded to complex64 as the device stores it) differs from the device
@@ -63,6 +66,23 @@ def split_step(x, la, y, lb, keep):
     ir, _ = _real3(xi, la, yr, lb, keep)
     re = (rr - ii).astype(np.float32).astype(np.float64)
     im = (ri + ir).astype(np.float32).astype(np.float64)
+    return re + 1j * im, lz
+
+
+def split_step_3m(x, la, y, lb, keep):
+    """The split-bf16 step in the 3M form: three split real products
+    T1 = ar br, T2 = ai bi, T3 = (ar + ai)(br + bi), the sum planes rounded
+    to float32 before they are split; re = T1 - T2 and im = T3 - T1 - T2
+    in float64, the result stored in complex64 precision."""
+    xr, xi = np.real(x).astype(np.float32), np.imag(x).astype(np.float32)
+    yr, yi = np.real(y).astype(np.float32), np.imag(y).astype(np.float32)
+    xs = xr + xi   # float32 sums
+    ys = yr + yi
+    t1, lz = _real3(xr, la, yr, lb, keep)
+    t2, _ = _real3(xi, la, yi, lb, keep)
+    t3, _ = _real3(xs, la, ys, lb, keep)
+    re = (t1 - t2).astype(np.float32).astype(np.float64)
+    im = (t3 - t1 - t2).astype(np.float32).astype(np.float64)
     return re + 1j * im, lz
 
 

@@ -343,6 +343,63 @@ def test_split_error_bounds():
     assert np.all(np.abs(p3 - exact) <= 3 * 2.0 ** -16 * np.abs(exact) + 1e-300)
 
 
+def _small_integer_pair(rng, shape_a, shape_b):
+    """Complex operands with integer parts in [-100, 100]: every part, every
+    float32 sum of two parts and every product sum below is exact in bf16
+    hi alone (lo = 0) and in float64."""
+    a = rng.integers(-100, 101, shape_a + (2,)).astype(np.float64)
+    b = rng.integers(-100, 101, shape_b + (2,)).astype(np.float64)
+    return a[..., 0] + 1j * a[..., 1], b[..., 0] + 1j * b[..., 1]
+
+
+def test_split_3m_step_is_exact_on_bf16_exact_integers():
+    """3M split form: on operands that bf16 holds exactly the dropped
+    lo * lo term is zero, so the emulation must equal the exact complex
+    product element for element (a dropped or mis-signed T term, a wrong
+    sum plane or swapped re/im fails)."""
+    rng = np.random.Generator(np.random.PCG64(31))
+    x, y = _small_integer_pair(rng, (6, 20), (5, 20))
+    got, lz = osp.split_step_3m(x, (0, 2), y, (1, 2), (0, 1))
+    assert tuple(lz) == (0, 1)
+    assert np.array_equal(got, x @ y.T)
+
+
+def test_split_3m_step_equals_4m_on_real_operands():
+    """With zero imaginary parts T2 = 0 and T3 = T1 exactly, so the 3M
+    split step is the 4M split step (already pinned above) bit for bit."""
+    rng = np.random.Generator(np.random.PCG64(32))
+    x = rng.standard_normal((7, 33)).astype(np.float32).astype(np.complex128)
+    y = rng.standard_normal((9, 33)).astype(np.float32).astype(np.complex128)
+    m3, _ = osp.split_step_3m(x, (0, 2), y, (1, 2), (0, 1))
+    m4, _ = osp.split_step(x, (0, 2), y, (1, 2), (0, 1))
+    assert np.array_equal(m3, m4)
+    assert np.all(m3.imag == 0)
+
+
+def test_split_3m_step_within_its_bound():
+    """Random float32 operands: each element of the 3M split step lies
+    within 3 * 2^-16 of the magnitudes of its three real products (plus
+    the complex64 rounding) of the exact product, and the lo terms matter
+    (hi products alone miss by far more)."""
+    rng = np.random.Generator(np.random.PCG64(33))
+    def c32(shape):
+        return (rng.standard_normal(shape).astype(np.float32)
+                + 1j * rng.standard_normal(shape).astype(np.float32)).astype(np.complex128)
+    x, y = c32((8, 64)), c32((6, 64))
+    got, _ = osp.split_step_3m(x, (0, 2), y, (1, 2), (0, 1))
+    exact = x @ y.T
+    ar, ai, br, bi = np.abs(x.real), np.abs(x.imag), np.abs(y.real), np.abs(y.imag)
+    t1, t2 = ar @ br.T, ai @ bi.T
+    t3 = (ar + ai) @ (br + bi).T
+    bound_re = 3 * 2.0 ** -16 * (t1 + t2) + 2.0 ** -23 * np.abs(exact.real)
+    bound_im = 3 * 2.0 ** -16 * (t1 + t2 + t3) * (1 + 2.0 ** -20) + 2.0 ** -23 * np.abs(exact.imag)
+    assert np.all(np.abs(got.real - exact.real) <= bound_re)
+    assert np.all(np.abs(got.imag - exact.imag) <= bound_im)
+    hi_only = osp.bf16_rne(x.real.astype(np.float32)).astype(np.float64) @ osp.bf16_rne(
+        y.real.astype(np.float32)).astype(np.float64).T
+    assert np.max(np.abs(hi_only - x.real @ y.real.T)) > 4 * np.max(3 * 2.0 ** -16 * t1)
+
+
 def test_split_emulation_tracks_exact_path():
     net, p = configs.circuit12()
     exact = oc.contract(net, p)
@@ -350,3 +407,6 @@ def test_split_emulation_tracks_exact_path():
     c64 = oc.contract(net, p, step=osp.c64_step)
     assert abs(c64 - exact) <= 1e-5 * abs(exact)
     assert 1e-9 < abs(emu - exact) / abs(exact) <= 1e-3
+    emu3 = oc.contract(net, p, step=osp.split_step_3m)
+    assert 1e-9 < abs(emu3 - exact) / abs(exact) <= 1e-3
+    assert emu3 != emu   # a different sequence of roundings
