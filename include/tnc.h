@@ -69,7 +69,10 @@ typedef enum { TNC_PREC_C64 = 0, TNC_PREC_BF16X3 = 1 } tnc_prec;
 /* Complex-GEMM form.  4M: four real products (re = ar*br - ai*bi,
  * im = ar*bi + ai*br), 8 real FLOPs per complex MAC.  3M: three real
  * products (T1 = ar*br, T2 = ai*bi, T3 = (ar+ai)(br+bi); re = T1 - T2,
- * im = T3 - T1 - T2), 6 executed FLOPs per complex MAC. */
+ * im = T3 - T1 - T2), 6 executed FLOPs per complex MAC.  Both compose with
+ * either precision on MFMA steps (BF16X3 + 3M: 9 bf16 products per complex
+ * product instead of 12, the sums ar+ai and br+bi formed in float32 before
+ * their split); the VALU kernels of small steps always use the 4M form. */
 typedef enum { TNC_GEMM_4M = 0, TNC_GEMM_3M = 1 } tnc_cgemm;
 
 /* Element type of host leaf data handed to the library. */
@@ -377,7 +380,8 @@ tnc_status tnc_serve_set_heavy(tnc_ctx ctx, double heavy_flops, int32_t heavy_sl
  * one run: every MFMA step is one grouped launch over the requests' GEMMs
  * of that step (one persistent kernel whose workgroups loop over the tiles
  * of all of them; every tile variant in 4M, all but 3 in 3M, 0 and 4-6 in
- * split precision, other steps one launch per request), and every tree level's small GEMMs and leaf gathers of
+ * split precision's 4M form, all but 3 in its 3M form, other steps one
+ * launch per request), and every tree level's small GEMMs and leaf gathers of
  * all the requests are one launch each.  Only requests that wait on their
  * launches more than on their arithmetic are fused: planned FLOP below
  * flops_per_launch times the launches of the request's own run

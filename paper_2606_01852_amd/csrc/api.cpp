@@ -289,8 +289,6 @@ tnc_status tnc_plan_create(tnc_net net, int32_t n_steps, const int32_t* ssa_pair
     fail(TNC_E_ARG, "bad plan arguments");
   if (prec != TNC_PREC_C64 && prec != TNC_PREC_BF16X3) fail(TNC_E_ARG, "unknown precision");
   if (cgemm != TNC_GEMM_4M && cgemm != TNC_GEMM_3M) fail(TNC_E_ARG, "unknown GEMM form");
-  if (prec == TNC_PREC_BF16X3 && cgemm == TNC_GEMM_3M)
-    fail(TNC_E_UNSUPPORTED, "split precision runs in the 4M form only");
   Net& n = *net->n;
   auto h = std::make_unique<tnc_plan_s>();
   h->p = std::make_shared<Plan>();
@@ -825,7 +823,6 @@ tnc_status tnc_batched_cgemm(tnc_ctx ctx, int64_t h, int64_t m, int64_t n, int64
     fail(TNC_E_ARG, "bad arguments");
   if (prec != TNC_PREC_C64 && prec != TNC_PREC_BF16X3) fail(TNC_E_ARG, "unknown precision");
   if (form != TNC_GEMM_4M && form != TNC_GEMM_3M) fail(TNC_E_ARG, "unknown GEMM form");
-  if (prec == TNC_PREC_BF16X3 && form == TNC_GEMM_3M) fail(TNC_E_UNSUPPORTED, "split precision runs in 4M form");
   Ctx& c = *ctx->c;
   set_device(c);
   GemmDesc d;

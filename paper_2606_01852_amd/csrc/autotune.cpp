@@ -40,8 +40,8 @@ const std::vector<int>& ranking(tnc_prec prec, tnc_cgemm form) {
   static const std::vector<int> r4m = {3, 2, 0, 1, 4, 5, 6};
   static const std::vector<int> r3m = {0, 2, 4, 1, 5, 6};  // 0: three (2,2) workgroups per CU
   static const std::vector<int> rbf = {3, 0, 2, 1, 4, 5, 6};  // 3: the wide-wave 256 x 128 tile
-  if (prec == TNC_PREC_BF16X3) return rbf;
-  return form == TNC_GEMM_3M ? r3m : r4m;
+  if (form == TNC_GEMM_3M) return r3m;  // complex64 and split precision alike
+  return prec == TNC_PREC_BF16X3 ? rbf : r4m;
 }
 
 std::vector<int> candidates(tnc_prec prec, tnc_cgemm form, int64_t h, int64_t m, int64_t n) {

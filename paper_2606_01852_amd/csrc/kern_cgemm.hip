@@ -313,6 +313,52 @@ __device__ __forceinline__ void store_perm_pairs(const GemmDesc& d, const TileCo
     }
 }
 
+// Store of a wave's 64 x 32 complex block from the 3M products (one 32x32
+// accumulator block per 32 rows: T1 = Ar Br, T2 = Ai Bi, T3 = (Ar+Ai)(Br+Bi);
+// Re = T1 - T2, Im = T3 - T1 - T2), row-major or through the offset tables.
+__device__ __forceinline__ void store_3m(const GemmDesc& d, bool perm, const TileCoord& tc, int wm, int wn, int lane,
+                                         const f16v (&t1)[2], const f16v (&t2)[2], const f16v (&t3)[2]) {
+  const int h = lane >> 5, l32 = lane & 31;
+  if (!perm) {  // row-major [M|N]: addresses from the indices alone
+    const int64_t col = tc.col0 + wn * 32 + l32;
+    if (col >= d.n) return;
+    float2* C = d.C + tc.b * d.m * d.n + col;
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+      for (int v = 0; v < 16; ++v) {
+        const int64_t row = tc.row0 + wm * 64 + i * 32 + 8 * (v >> 2) + 4 * h + (v & 3);
+        if (row < d.m) {
+          float2 o;
+          o.x = t1[i][v] - t2[i][v];
+          o.y = t3[i][v] - t1[i][v] - t2[i][v];
+          C[row * d.n] = o;
+        }
+      }
+    return;
+  }
+  const int64_t co = col_offset(d, perm, tc.col0 + wn * 32 + l32);
+  if (co < 0) return;
+  float2* C = d.C + tc.b * d.m * d.n + co;
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int v0 = 0; v0 < 16; v0 += 8) {
+      int64_t ro[8];
+      row_offsets8(d, perm, tc.row0 + wm * 64 + i * 32, h, v0, ro);
+#pragma unroll
+      for (int u = 0; u < 8; ++u) {
+        const int v = v0 + u;
+        if (ro[u] >= 0) {
+          float2 o;
+          o.x = t1[i][v] - t2[i][v];
+          o.y = t3[i][v] - t1[i][v] - t2[i][v];
+          C[ro[u]] = o;
+        }
+      }
+    }
+}
+
 // ------------------------------------------------------------------ 4M, FP32 MFMA
 template <int WM, int WN, int VW>
 struct Ops4M {
@@ -468,45 +514,7 @@ struct Ops3M {
 
   __device__ __forceinline__ void store(const GemmDesc& d, bool perm, const TileCoord& tc, int wm, int wn,
                                         int lane) const {
-    const int h = lane >> 5, l32 = lane & 31;
-    if (!perm) {  // row-major [M|N]: addresses from the indices alone
-      const int64_t col = tc.col0 + wn * 32 + l32;
-      if (col >= d.n) return;
-      float2* C = d.C + tc.b * d.m * d.n + col;
-#pragma unroll
-      for (int i = 0; i < 2; ++i)
-#pragma unroll
-        for (int v = 0; v < 16; ++v) {
-          const int64_t row = tc.row0 + wm * 64 + i * 32 + 8 * (v >> 2) + 4 * h + (v & 3);
-          if (row < d.m) {
-            float2 o;
-            o.x = t1[i][v] - t2[i][v];
-            o.y = t3[i][v] - t1[i][v] - t2[i][v];
-            C[row * d.n] = o;
-          }
-        }
-      return;
-    }
-    const int64_t co = col_offset(d, perm, tc.col0 + wn * 32 + l32);
-    if (co < 0) return;
-    float2* C = d.C + tc.b * d.m * d.n + co;
-#pragma unroll
-    for (int i = 0; i < 2; ++i)
-#pragma unroll
-      for (int v0 = 0; v0 < 16; v0 += 8) {
-        int64_t ro[8];
-        row_offsets8(d, perm, tc.row0 + wm * 64 + i * 32, h, v0, ro);
-#pragma unroll
-        for (int u = 0; u < 8; ++u) {
-          const int v = v0 + u;
-          if (ro[u] >= 0) {
-            float2 o;
-            o.x = t1[i][v] - t2[i][v];
-            o.y = t3[i][v] - t1[i][v] - t2[i][v];
-            C[ro[u]] = o;
-          }
-        }
-      }
+    store_3m(d, perm, tc, wm, wn, lane, t1, t2, t3);
   }
 };
 
@@ -701,6 +709,117 @@ struct OpsBF16x3W {
       return;
     }
     store_perm_pairs<2>(d, tc, wm, wn, lane, [&](int i, int j, int v) { return acc[i][j][v]; });
+  }
+};
+
+// ------------------------------------------------------------------ split BF16x3, 3M form
+// The 3M form's three real products T1 = Ar Br, T2 = Ai Bi, T3 = (Ar+Ai)
+// (Br+Bi), each as a_hi b_lo + a_lo b_hi + a_hi b_hi on bf16 MFMA
+// 32x32x16 into one FP32 accumulator per product: 9 bf16 products per
+// complex product instead of the 4M form's 12.  The sum planes are formed
+// in float32 at staging, then split like the others.  A stage (16 complex
+// k) holds six unpadded bf16 planes per operand (r, i, s, each hi and lo),
+// a row of 16 k in 32 bytes; the row's two 16-byte halves swap places
+// every 8 rows (slot = half ^ ((row >> 3) & 1)), so the fragment reads of
+// 16 lanes (16 rows, one half) and the 4-byte staging stores of a wave (8
+// rows x 8 pairs) hit distinct banks.  The wave tile and the store are the
+// complex64 3M form's.
+template <int WM, int WN, int VW>
+struct Ops3MBF16 {
+  using S = Shape<WM, WN>;
+  static constexpr bool kSwizzle = false;
+  static constexpr int kPW = 1;
+  static constexpr int ROWB = 32;  // bytes per plane row
+  static constexpr int PLANE_A = S::BM * ROWB, PLANE_B = S::BNC * ROWB;
+  static constexpr int STAGE = 6 * (PLANE_A + PLANE_B);
+  static constexpr size_t kLds = 2 * STAGE;
+  f16v t1[2], t2[2], t3[2];
+
+  // byte offset of k (0..15) in plane row `row`
+  __device__ __forceinline__ static int at(int row, int k) {
+    return row * ROWB + ((((k >> 3) ^ ((row >> 3) & 1)) << 4) | ((k & 7) << 1));
+  }
+
+  __device__ __forceinline__ void init() {
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+      for (int v = 0; v < 16; ++v) t1[i][v] = t2[i][v] = t3[i][v] = 0.f;
+  }
+
+  // planes p = 0..5 (r hi, r lo, i hi, i lo, s hi, s lo) at base + p * plane
+  template <class St>
+  __device__ __forceinline__ static void put(char* base, int plane, int row, int idx, const f4& v) {
+    const int off = at(row, (idx % St::PER_ROW) * VW);
+    if constexpr (VW == 2) {  // complex k, k + 1: (re k, im k, re k+1, im k+1)
+      uint32_t rh, rl, ih, il, sh, sl;
+      bf16_split2(v.x, v.z, rh, rl);
+      bf16_split2(v.y, v.w, ih, il);
+      bf16_split2(v.x + v.y, v.z + v.w, sh, sl);
+      *reinterpret_cast<uint32_t*>(base + off) = rh;
+      *reinterpret_cast<uint32_t*>(base + plane + off) = rl;
+      *reinterpret_cast<uint32_t*>(base + 2 * plane + off) = ih;
+      *reinterpret_cast<uint32_t*>(base + 3 * plane + off) = il;
+      *reinterpret_cast<uint32_t*>(base + 4 * plane + off) = sh;
+      *reinterpret_cast<uint32_t*>(base + 5 * plane + off) = sl;
+    } else {  // one complex value: (re, im) split as a pair, the sum alone
+      uint32_t h, l, sh, sl;
+      bf16_split2(v.x, v.y, h, l);
+      bf16_split2(v.x + v.y, 0.f, sh, sl);
+      *reinterpret_cast<uint16_t*>(base + off) = static_cast<uint16_t>(h);
+      *reinterpret_cast<uint16_t*>(base + plane + off) = static_cast<uint16_t>(l);
+      *reinterpret_cast<uint16_t*>(base + 2 * plane + off) = static_cast<uint16_t>(h >> 16);
+      *reinterpret_cast<uint16_t*>(base + 3 * plane + off) = static_cast<uint16_t>(l >> 16);
+      *reinterpret_cast<uint16_t*>(base + 4 * plane + off) = static_cast<uint16_t>(sh);
+      *reinterpret_cast<uint16_t*>(base + 5 * plane + off) = static_cast<uint16_t>(sl);
+    }
+  }
+
+  template <class St>
+  __device__ __forceinline__ void stage(const St& st, char* lds, int buf, int tid) const {
+    char* As = lds + buf * STAGE;
+    char* Bs = As + 6 * PLANE_A;
+#pragma unroll
+    for (int i = 0; i < St::A_LOADS; ++i) put<St>(As, PLANE_A, St::row_a(tid + S::NT * i), tid + S::NT * i, st.a[i]);
+#pragma unroll
+    for (int i = 0; i < St::B_LOADS; ++i) put<St>(Bs, PLANE_B, St::row_b(tid + S::NT * i), tid + S::NT * i, st.b[i]);
+  }
+
+  __device__ __forceinline__ static void mm(f16v& t, const s8v& ah, const s8v& al, const s8v& bh, const s8v& bl) {
+    t = __builtin_amdgcn_mfma_f32_32x32x16_bf16(__builtin_bit_cast(bf8, ah), __builtin_bit_cast(bf8, bl), t, 0, 0, 0);
+    t = __builtin_amdgcn_mfma_f32_32x32x16_bf16(__builtin_bit_cast(bf8, al), __builtin_bit_cast(bf8, bh), t, 0, 0, 0);
+    t = __builtin_amdgcn_mfma_f32_32x32x16_bf16(__builtin_bit_cast(bf8, ah), __builtin_bit_cast(bf8, bh), t, 0, 0, 0);
+  }
+
+  // product p (planes 2p, 2p + 1) of the stage into t
+  __device__ __forceinline__ static void product(f16v (&t)[2], const char* ah, const char* bh, int oa0, int oa1,
+                                                 int ob) {
+    const s8v a0h = *reinterpret_cast<const s8v*>(ah + oa0);
+    const s8v a0l = *reinterpret_cast<const s8v*>(ah + PLANE_A + oa0);
+    const s8v a1h = *reinterpret_cast<const s8v*>(ah + oa1);
+    const s8v a1l = *reinterpret_cast<const s8v*>(ah + PLANE_A + oa1);
+    const s8v b_h = *reinterpret_cast<const s8v*>(bh + ob);
+    const s8v b_l = *reinterpret_cast<const s8v*>(bh + PLANE_B + ob);
+    mm(t[0], a0h, a0l, b_h, b_l);
+    mm(t[1], a1h, a1l, b_h, b_l);
+  }
+
+  // lane (h, r) supplies k = 8h .. 8h + 7 of row r (A) or column r (B);
+  // one product at a time keeps a third of the fragments live
+  __device__ __forceinline__ void compute(const char* lds, int buf, int wm, int wn, int lane) {
+    const char* As = lds + buf * STAGE;
+    const char* Bs = As + 6 * PLANE_A;
+    const int h = lane >> 5, l32 = lane & 31;
+    const int oa0 = at(wm * 64 + l32, 8 * h), oa1 = at(wm * 64 + 32 + l32, 8 * h);
+    const int ob = at(wn * 32 + l32, 8 * h);
+    product(t1, As, Bs, oa0, oa1, ob);
+    product(t2, As + 2 * PLANE_A, Bs + 2 * PLANE_B, oa0, oa1, ob);
+    product(t3, As + 4 * PLANE_A, Bs + 4 * PLANE_B, oa0, oa1, ob);
+  }
+
+  __device__ __forceinline__ void store(const GemmDesc& d, bool perm, const TileCoord& tc, int wm, int wn,
+                                        int lane) const {
+    store_3m(d, perm, tc, wm, wn, lane, t1, t2, t3);
   }
 };
 
@@ -1101,6 +1220,7 @@ constexpr bool grouped_ok(int variant) {
   if (variant < 0 || variant >= kGemmVariants) return false;
   if constexpr (std::is_same_v<OpsT<2, 2, 2>, OpsBF16x3<2, 2, 2>>) return variant == 0 || variant >= 4;
   if constexpr (std::is_same_v<OpsT<2, 2, 2>, Ops3M<2, 2, 2>>) return variant != 3;
+  if constexpr (std::is_same_v<OpsT<2, 2, 2>, Ops3MBF16<2, 2, 2>>) return variant != 3;
   return true;
 }
 
@@ -1120,7 +1240,8 @@ hipError_t launch_grouped_variant(const GroupedEntry* tab, int n, int64_t total,
       case 1: return launch_grouped_shape<OpsT, 4, 2>(tab, n, total, bf16, s);
       case 2: return launch_grouped_shape<OpsT, 2, 4>(tab, n, total, bf16, s);
       case 3:
-        if constexpr (!std::is_same_v<OpsT<2, 2, 2>, Ops3M<2, 2, 2>>) return launch_grouped_shape<OpsT, 4, 4>(tab, n, total, bf16, s);
+        if constexpr (!std::is_same_v<OpsT<2, 2, 2>, Ops3M<2, 2, 2>> && !std::is_same_v<OpsT<2, 2, 2>, Ops3MBF16<2, 2, 2>>)
+          return launch_grouped_shape<OpsT, 4, 4>(tab, n, total, bf16, s);
         break;
       default: break;
     }
@@ -1130,10 +1251,16 @@ hipError_t launch_grouped_variant(const GroupedEntry* tab, int n, int64_t total,
 
 // The narrow split tile has no (4,4) instance: split precision runs that
 // tile size as 4x2 wide waves (the narrow waves' two accumulator sets would
-// spill).
+// spill).  Nor has the 3M split form: its three accumulator sets spill at
+// sixteen waves per workgroup (compiler resource report), so a forced
+// variant 3 runs its (4,2) tile.
 template <template <int, int, int> class OpsT>
 constexpr bool is_split() {
   return std::is_same_v<OpsT<2, 2, 2>, OpsBF16x3<2, 2, 2>>;
+}
+template <template <int, int, int> class OpsT>
+constexpr bool is_split_3m() {
+  return std::is_same_v<OpsT<2, 2, 2>, Ops3MBF16<2, 2, 2>>;
 }
 
 template <template <int, int, int> class OpsT>
@@ -1141,7 +1268,7 @@ void prepare_ops(bool bf16) {
   prepare_shape<OpsT, 2, 2, grouped_ok<OpsT>(0)>(bf16);
   prepare_shape<OpsT, 4, 2, grouped_ok<OpsT>(1)>(bf16);
   prepare_shape<OpsT, 2, 4, grouped_ok<OpsT>(2)>(bf16);
-  if constexpr (!is_split<OpsT>()) prepare_shape<OpsT, 4, 4, grouped_ok<OpsT>(3)>(bf16);
+  if constexpr (!is_split<OpsT>() && !is_split_3m<OpsT>()) prepare_shape<OpsT, 4, 4, grouped_ok<OpsT>(3)>(bf16);
   prepare_shape<OpsT, 1, 2, grouped_ok<OpsT>(4)>(bf16);
   prepare_shape<OpsT, 2, 1, grouped_ok<OpsT>(5)>(bf16);
   prepare_shape<OpsT, 1, 1, grouped_ok<OpsT>(6)>(bf16);
@@ -1171,6 +1298,7 @@ hipError_t launch_variant(const GemmDesc& d, int variant, bool bf16, hipStream_t
     case 2: return launch_shape<OpsT, 2, 4>(d, bf16, s);
     case 3:
       if constexpr (is_split<OpsT>()) return launch_shape<OpsBF16x3W, 4, 2>(d, true, s);
+      else if constexpr (is_split_3m<OpsT>()) return launch_shape<OpsT, 4, 2>(d, true, s);
       else return launch_shape<OpsT, 4, 4>(d, bf16, s);
     case 4: return launch_shape<OpsT, 1, 2>(d, bf16, s);
     case 5: return launch_shape<OpsT, 2, 1>(d, bf16, s);
@@ -1185,6 +1313,7 @@ void prepare_gemm_kernels() {
   prepare_ops<Ops4M>(false);
   prepare_ops<Ops3M>(false);
   prepare_ops<OpsBF16x3>(true);
+  prepare_ops<Ops3MBF16>(true);
   prepare_shape<OpsBF16x3W, 4, 2, false>(true);
   (void)ensure_lds_presplit();
 }
@@ -1213,14 +1342,17 @@ int64_t grouped_layout(GroupedEntry* e, int n, int variant) {
 }
 
 bool grouped_variant_ok(Form form, Prec prec, int variant) {
-  if (prec == Prec::BF16X3) return grouped_ok<OpsBF16x3>(variant);
+  if (prec == Prec::BF16X3)
+    return form == Form::M3 ? grouped_ok<Ops3MBF16>(variant) : grouped_ok<OpsBF16x3>(variant);
   return form == Form::M3 ? grouped_ok<Ops3M>(variant) : grouped_ok<Ops4M>(variant);
 }
 
 hipError_t launch_gemm_grouped(const GroupedEntry* dev, int n, int64_t total, int variant, Form form, Prec prec,
                                hipStream_t s) {
   if (n <= 0 || total <= 0) return hipSuccess;
-  if (prec == Prec::BF16X3) return launch_grouped_variant<OpsBF16x3>(dev, n, total, variant, true, s);
+  if (prec == Prec::BF16X3)
+    return form == Form::M3 ? launch_grouped_variant<Ops3MBF16>(dev, n, total, variant, true, s)
+                            : launch_grouped_variant<OpsBF16x3>(dev, n, total, variant, true, s);
   if (form == Form::M3) return launch_grouped_variant<Ops3M>(dev, n, total, variant, false, s);
   return launch_grouped_variant<Ops4M>(dev, n, total, variant, false, s);
 }
@@ -1264,7 +1396,9 @@ hipError_t launch_gemm(const GemmDesc& d, GemmKernel kind, int variant, Form for
   if (d.h <= 0 || d.m <= 0 || d.n <= 0) return hipSuccess;
   if (d.k <= 0) return hipErrorInvalidValue;
   if (kind != GemmKernel::MFMA) return launch_gemm_valu(d, kind, prec, s);
-  if (prec == Prec::BF16X3) return launch_variant<OpsBF16x3>(d, variant, true, s);
+  if (prec == Prec::BF16X3)
+    return form == Form::M3 ? launch_variant<Ops3MBF16>(d, variant, true, s)
+                            : launch_variant<OpsBF16x3>(d, variant, true, s);
   if (form == Form::M3) return launch_variant<Ops3M>(d, variant, false, s);
   return launch_variant<Ops4M>(d, variant, false, s);
 }

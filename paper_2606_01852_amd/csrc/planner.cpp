@@ -670,12 +670,12 @@ std::unique_ptr<ChunkPlan> build_chunk(const Plan& plan, int j) {
       }
       sp.tperm = build_permute(ext, ist);
     }
-    // split precision on large single GEMMs: split each operand once into
-    // bf16 planes (8 + 8 bytes per element of A, 8 + 16 of B moved: about 1 %
-    // of the GEMM's time from 4096 x 4096 up) rather than in the staging of
-    // every workgroup that reads it
-    sp.presplit = plan.prec == TNC_PREC_BF16X3 && sp.kind == GemmKernel::MFMA && sp.split == 1 && !sp.trans &&
-                  d.h == 1 && sp.lm >= 4096 && sp.ln >= 4096;
+    // split precision (4M form) on large single GEMMs: split each operand
+    // once into bf16 planes (8 + 8 bytes per element of A, 8 + 16 of B
+    // moved: about 1 % of the GEMM's time from 4096 x 4096 up) rather than
+    // in the staging of every workgroup that reads it
+    sp.presplit = plan.prec == TNC_PREC_BF16X3 && plan.form == TNC_GEMM_4M && sp.kind == GemmKernel::MFMA &&
+                  sp.split == 1 && !sp.trans && d.h == 1 && sp.lm >= 4096 && sp.ln >= 4096;
     // an operand leaf that is permuted anyway writes the planes itself (the
     // permute and the split in one pass) when rows are whole 16-k blocks
     if (sp.presplit && sp.k % 16 == 0 && row_stride(d) == sp.k)

@@ -170,12 +170,50 @@ def test_cgemm_bf16x3_matches_split_emulation(ctx, shape):
     assert rel_fro(got, exact) <= 3 * 2.0 ** -16 * 4
 
 
+def split_3m_emulated_gemm(A, B):
+    """The oracle's 3M split step over batch label 0 (A[b, i, l] B[b, j, l])."""
+    z, lz = osp.split_step_3m(A.astype(np.complex128), [0, 1, 3], B.astype(np.complex128), [0, 2, 3], {0, 1, 2})
+    assert lz == [0, 1, 2]
+    return z
+
+
+@pytest.mark.parametrize("shape", [(4, 256, 128, 64), (16, 130, 70, 33), (8, 16, 200, 512), (1, 512, 256, 1000),
+                                   (16, 200, 100, 17)],
+                         ids=["tiles", "ragged_odd_k", "skinny", "long_k", "short_odd_k"])
+def test_cgemm_bf16x3_3m_matches_split_emulation(ctx, shape):
+    """Split precision in the 3M form (three split real products, nine bf16
+    products per complex product) on MFMA steps: within float32 accumulation
+    of the oracle's 3M split emulation, per element, and within twice the
+    split's a-priori bound of the exact product (T3's operands are sums of
+    two parts)."""
+    h, m, n, k = shape
+    rng = np.random.Generator(np.random.PCG64(3 * m + n + k))
+    A, B = cn(rng, (h, m, k)), cn(rng, (h, n, k))
+    print(f"cgemm bf16x3 3M shape={shape}", flush=True)
+    Ad, Bd = to_dev(torch, A), to_dev(torch, B)
+    Cd = torch.empty((h, m, n), dtype=torch.complex64, device="cuda")
+    torch.view_as_real(Cd).fill_(float("nan"))
+    tnc.tnc_batched_cgemm(ctx.handle, h, m, n, k, Ad.data_ptr(), m * k, Bd.data_ptr(), n * k, Cd.data_ptr(),
+                          tnc.PREC_BF16X3, tnc.GEMM_3M)
+    torch.cuda.synchronize()
+    got = from_dev(Cd)
+    emu = split_3m_emulated_gemm(A, B)
+    assert_gemm_close(got, emu, A, B, what=f"bf16x3 3M {shape} vs emulation")
+    exact = ref_gemm(A, B)
+    bound = 2 * split_elem_bound(A, B) + 2 * gemm_elem_bound(A, B)
+    assert np.all(np.abs(got - exact) <= bound)
+    assert rel_fro(got, exact) <= 3 * 2.0 ** -16 * 8
+    # a different sequence of roundings than the 4M split form
+    assert not np.array_equal(got, split_emulated_gemm(A, B).astype(np.complex64))
+
+
 @pytest.mark.parametrize("variant", range(7))
-@pytest.mark.parametrize("kind", ["4M", "3M", "bf16x3"])
+@pytest.mark.parametrize("kind", ["4M", "3M", "bf16x3", "bf16x3_3M"])
 def test_every_tile_variant(ctx, variant, kind):
-    """Each MFMA workgroup shape on an interior-tile shape and a ragged one."""
-    prec = tnc.PREC_BF16X3 if kind == "bf16x3" else tnc.PREC_C64
-    form = tnc.GEMM_3M if kind == "3M" else tnc.GEMM_4M
+    """Each MFMA workgroup shape on an interior-tile shape and a ragged one
+    (the 3M split form runs a forced variant 3 on its (4,2) tile)."""
+    prec = tnc.PREC_BF16X3 if kind.startswith("bf16x3") else tnc.PREC_C64
+    form = tnc.GEMM_3M if kind.endswith("3M") else tnc.GEMM_4M
     tnc.tnc_ctx_set_gemm_variant(ctx.handle, variant)
     try:
         for (h, m, n, k) in ((2, 512, 256, 64), (3, 333, 111, 70)):
@@ -189,7 +227,7 @@ def test_every_tile_variant(ctx, variant, kind):
                                   Cd.data_ptr(), prec, form)
             torch.cuda.synchronize()
             got = from_dev(Cd)
-            ref = split_emulated_gemm(A, B) if kind == "bf16x3" else ref_gemm(A, B)
+            ref = {"bf16x3": split_emulated_gemm, "bf16x3_3M": split_3m_emulated_gemm}.get(kind, ref_gemm)(A, B)
             assert_gemm_close(got, ref, A, B, what=f"variant {variant} {kind} {(h, m, n, k)}")
     finally:
         tnc.tnc_ctx_set_gemm_variant(ctx.handle, -1)

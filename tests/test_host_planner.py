@@ -483,10 +483,11 @@ def test_choice_arguments_are_checked_before_use(hctx):
     pp = pairs.ctypes.data_as(C.POINTER(C.c_int32))
     out = C.c_void_p()
     for prec, form, want in ((9, tnc.GEMM_4M, tnc.E_ARG), (-1, tnc.GEMM_4M, tnc.E_ARG),
-                             (tnc.PREC_C64, 2, tnc.E_ARG), (tnc.PREC_BF16X3, tnc.GEMM_3M, tnc.E_UNSUPPORTED)):
+                             (tnc.PREC_C64, 2, tnc.E_ARG), (tnc.PREC_BF16X3, -3, tnc.E_ARG)):
         assert L.tnc_plan_create(tn.handle, 2, pp, 0, None, prec, form, C.byref(out)) == want
-    assert L.tnc_plan_create(tn.handle, 2, pp, 0, None, tnc.PREC_C64, tnc.GEMM_3M, C.byref(out)) == tnc.OK
-    assert L.tnc_plan_destroy(out) == tnc.OK
+    for prec in (tnc.PREC_C64, tnc.PREC_BF16X3):   # both forms compose with both precisions
+        assert L.tnc_plan_create(tn.handle, 2, pp, 0, None, prec, tnc.GEMM_3M, C.byref(out)) == tnc.OK
+        assert L.tnc_plan_destroy(out) == tnc.OK
     ranks = np.array([1, 1], dtype=np.int32)
     labs = np.array([0, 0], dtype=np.int32)
     ext = np.array([2], dtype=np.int64)
