@@ -434,7 +434,7 @@ def bench_small(args):
     gpath = greedy_path(gs)
     tg = tnc.Network(ctx, gs.labels, gs.extents, gs.open, gs.c64().leaves)
     for name, prec, form in (("c64_4M", tnc.PREC_C64, tnc.GEMM_4M), ("c64_3M", tnc.PREC_C64, tnc.GEMM_3M),
-                             ("bf16x3", tnc.PREC_BF16X3, tnc.GEMM_4M)):
+                             ("bf16x3", tnc.PREC_BF16X3, tnc.GEMM_4M), ("bf16x3_3M", tnc.PREC_BF16X3, tnc.GEMM_3M)):
         p = tnc.Plan(tg, gpath.pairs, (), prec, form)
         tnc.tnc_plan_autotune(p.handle)
         tnc.tnc_plan_set_graph(p.handle, True)
@@ -686,7 +686,7 @@ def record_grid8():
     rec = {"workload": "grid8: closed 8x8 grid, bond 4, CN(0,1)/sqrt(numel) entries (x 2^floor(deg/2), exact), "
                        "greedy path (63 steps)", "forms": {}}
     for name, prec, form in (("c64_4M", tnc.PREC_C64, tnc.GEMM_4M), ("c64_3M", tnc.PREC_C64, tnc.GEMM_3M),
-                             ("bf16x3", tnc.PREC_BF16X3, tnc.GEMM_4M)):
+                             ("bf16x3", tnc.PREC_BF16X3, tnc.GEMM_4M), ("bf16x3_3M", tnc.PREC_BF16X3, tnc.GEMM_3M)):
         p = tnc.Plan(tg, gpath.pairs, (), prec, form)
         tnc.tnc_plan_autotune(p.handle)
         tnc.tnc_plan_set_graph(p.handle, True)
@@ -707,8 +707,13 @@ def record_grid8():
              "error_vs_oracle": abs(z - exact) / abs(exact), "path_roofline_frac": round(roof / dt, 4),
              "dominant_step": dom}
         if prec == tnc.PREC_BF16X3:
-            f["error_vs_split_emulation"] = abs(z - emu) / abs(emu)
-            f["tolerance"] = max(1e-5, 4 * 2.0 ** -16 * depth[-1])
+            e = emu
+            if form == tnc.GEMM_3M:   # MFMA steps in the 3M split form, small (VALU) steps in the 4M one
+                kinds = iter([tnc.tnc_plan_get_step(p.handle, s).kernel for s in range(len(gpath.pairs))])
+                e = complex(oc.contract(gs, gpath, step=lambda *a: (osp.split_step_3m if next(kinds) == 0
+                                                                     else osp.split_step)(*a)))
+            f["error_vs_split_emulation"] = abs(z - e) / abs(e)
+            f["tolerance"] = max(1e-5, (8 if form == tnc.GEMM_3M else 4) * 2.0 ** -16 * depth[-1])
         else:
             f["tolerance"] = 1e-5
         rec["forms"][name] = f
@@ -949,7 +954,7 @@ def main():
     sizes = []
     forms = [(prec, form)]
     if not args.no_forms and args.form == "4M" and args.prec == "c64":
-        forms += [(tnc.PREC_C64, tnc.GEMM_3M), (tnc.PREC_BF16X3, tnc.GEMM_4M)]
+        forms += [(tnc.PREC_C64, tnc.GEMM_3M), (tnc.PREC_BF16X3, tnc.GEMM_4M), (tnc.PREC_BF16X3, tnc.GEMM_3M)]
     for net, path in ((net_a, path_a), (net_b, path_b)):
         tn = tnc.Network(hctx, net.labels, net.extents, net.open)
         for fp, ff in forms:   # split precision also holds its operands' bf16 planes
@@ -1052,7 +1057,8 @@ def main():
         # the same step in the other GEMM forms (same inputs, same arena)
         res["other_forms"] = {}
         for name, fprec, fform, fpeak in (("3M", tnc.PREC_C64, tnc.GEMM_3M, PEAK_FP32_MFMA),
-                                          ("bf16x3", tnc.PREC_BF16X3, tnc.GEMM_4M, PEAK_BF16_MFMA / 3)):
+                                          ("bf16x3", tnc.PREC_BF16X3, tnc.GEMM_4M, PEAK_BF16_MFMA / 3),
+                                          ("bf16x3_3M", tnc.PREC_BF16X3, tnc.GEMM_3M, PEAK_BF16_MFMA / 3)):
             pa = tnc.Plan(tn_a, path_a.pairs, (), fprec, fform)
             pb = tnc.Plan(tn_b, path_b.pairs, (), fprec, fform)
             tnc.tnc_plan_autotune(pa.handle)
@@ -1073,10 +1079,10 @@ def main():
             g_ms, g_n = tnc.tnc_plan_get_profile(pa.handle, 0)
             g_s = g_ms / max(g_n, 1) / 1e3
             gt = plan_a.info.flops_per_slice / g_s / 1e12
-            # executed MFMA work against its own peak: 3M executes 6 of the
-            # 8 FLOPs per complex MAC on FP32 MFMA, split-bf16x3 three bf16
+            # executed MFMA work against its own peak: the 3M forms execute
+            # 6 of the 8 FLOPs per complex MAC, split-bf16x3 three bf16
             # products per real product (peak / 3 in the 8-FLOP convention)
-            executed = gt * 6 / 8 / PEAK_FP32_MFMA if name == "3M" else gt / fpeak
+            executed = gt * (6 / 8 if fform == tnc.GEMM_3M else 1.0) / fpeak
             res["other_forms"][name] = {
                 "tflops": round(flops_step / fdt / 1e12, 3), "ms_per_step": round(fdt * 1e3, 3),
                 "gemm_tflops": round(gt, 3), "gemm_frac_of_executed_mfma_peak": round(executed, 4),

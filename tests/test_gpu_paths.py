@@ -158,19 +158,37 @@ def prescaled_grid(rows, cols, bond, seed):
     return Network(leaves, g.labels, g.extents, ()), int(e.sum())
 
 
-@pytest.mark.parametrize("prec", [tnc.PREC_C64, tnc.PREC_BF16X3], ids=["c64", "bf16x3"])
-def test_grid8_bond4(ctx, prec):
+@pytest.mark.parametrize("prec, form", [(tnc.PREC_C64, tnc.GEMM_4M), (tnc.PREC_BF16X3, tnc.GEMM_4M),
+                                        (tnc.PREC_BF16X3, tnc.GEMM_3M)], ids=["c64", "bf16x3", "bf16x3_3M"])
+def test_grid8_bond4(ctx, prec, form):
+    """grid8 (prescaled, 63 steps).  Split precision in the 3M form runs
+    its MFMA steps as three split real products and its small (VALU) steps
+    in the 4M form: the emulation takes each step's form from the plan.
+    Its tolerance against the emulation is three times the 4M form's: the
+    imaginary part comes from three float32 accumulators (T3's over sums of
+    two parts, up to twice the operand norms) instead of one over 2k terms,
+    about 4 / sqrt(2) times the accumulation error (single GEMMs: 1-5e-7 of
+    the emulation in either form)."""
     net, shift = prescaled_grid(8, 8, 4, seed=1002)
     path = greedy_path(net)
-    print("grid8 prec", prec, flush=True)
-    z, plan, _ = run(ctx, net, path, prec=prec)
+    print("grid8 prec", prec, "form", form, flush=True)
+    z, plan, _ = run(ctx, net, path, prec=prec, form=form)
     exact = complex(oc.contract(net, path))
     if prec == tnc.PREC_C64:
         print(f"grid8 c64: err vs oracle {abs(z - exact) / abs(exact):.2e}")
         assert abs(z - exact) <= 1e-5 * abs(exact)
     else:
-        emu = complex(oc.contract(net, path, step=osp.split_step))
+        kinds = iter([plan.step(s).kernel for s in range(len(path.pairs))])
+        if form == tnc.GEMM_3M:
+            def step(x, la, y, lb, keep):   # steps come in path order
+                return (osp.split_step_3m if next(kinds) == 0 else osp.split_step)(x, la, y, lb, keep)
+        else:
+            step = osp.split_step
+        emu = complex(oc.contract(net, path, step=step))
         t_emu, t_exact = split_tols(net, path)
+        if form == tnc.GEMM_3M:
+            t_emu *= 3
+            t_exact *= 2   # T3's operands are sums of two parts
         print(f"grid8 bf16x3: err vs emulation {abs(z - emu) / abs(emu):.2e} (tol {t_emu:.1e}), "
               f"vs exact {abs(z - exact) / abs(exact):.2e} (tol {t_exact:.1e})")
         assert abs(z - emu) <= t_emu * abs(emu)
