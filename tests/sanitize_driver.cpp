@@ -217,8 +217,11 @@ void malformed(tnc_ctx ctx) {
            "unknown precision", F);
     expect(tnc_plan_create(net, 2, good, 0, nullptr, TNC_PREC_C64, 9, &p) == TNC_E_ARG,
            "unknown form", F);
-    expect(tnc_plan_create(net, 2, good, 0, nullptr, TNC_PREC_BF16X3, TNC_GEMM_3M, &p) == TNC_E_UNSUPPORTED,
-           "split 3M", F);
+    expect(tnc_plan_create(net, 2, good, 0, nullptr, TNC_PREC_BF16X3, -1, &p) == TNC_E_ARG, "negative form", F);
+    p = nullptr;
+    expect(tnc_plan_create(net, 2, good, 0, nullptr, TNC_PREC_BF16X3, TNC_GEMM_3M, &p) == TNC_OK, "split 3M", F);
+    if (p) expect(tnc_plan_destroy(p) == TNC_OK, "split 3M destroy", F);
+    p = nullptr;
     const int32_t sl[1] = {1};
     expect(tnc_plan_create(net, 2, good, 1, sl, TNC_PREC_C64, TNC_GEMM_4M, &p) == TNC_OK, "triangle plan", F);
     if (p) {
