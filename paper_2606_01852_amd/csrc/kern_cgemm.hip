@@ -33,10 +33,14 @@
 // 16-byte fragment reads of 16 lanes hit 16 distinct 4-bank groups).  Each
 // lane reads 4 consecutive real k and feeds them to 4 successive MFMAs; the
 // K order inside a stage is permuted the same way for A and B.  Interior
-// tiles run a copy of the main loop without bounds checks.  Workgroups are
-// remapped so that consecutive tiles land on one XCD (the hardware deals
-// workgroups round-robin over the 8 XCDs, each with its own L2) and tiles
-// sweep N in groups of 8 M-tiles for L2 reuse.
+// tiles run a copy of the main loop without bounds checks.  Tiles sweep N
+// in groups of 8 M-tiles, and workgroups are remapped (the hardware deals
+// them round-robin over the 8 XCDs, each with its own L2) so that the tiles
+// one XCD runs at once form 8 x 4 blocks: 12 operand panels per 32 tiles
+// through its L2.  Where the tile counts allow, the eight XCDs' blocks share
+// their 8 M-tiles, so the memory-side cache serves each A panel to all of
+// them from one HBM read (split precision on pair30: 316.7 -> 314.5 ms,
+// where the chip's power sets its clock; complex64 unchanged).
 #include <atomic>
 #include <type_traits>
 
@@ -99,6 +103,20 @@ __device__ __forceinline__ TileCoord map_tile(int64_t tiles_m, int64_t tiles_n, 
   const int64_t per = total >> 3;
   if (wg < (per << 3)) wg = (wg & 7) * per + (wg >> 3);
   return tile_of<BM, BNC>(wg, tiles_m, tiles_n);
+}
+
+// The same 8 x 4 blocks of tiles per XCD, but the eight XCDs work on the
+// same eight M-tiles at once (XCD x takes N-tiles x, x + 8, ...): the A
+// panels every XCD reads from its own L2 are then shared in the memory-side
+// cache, so HBM serves each once instead of once per XCD.  Needs whole
+// groups of 64 tiles (tiles_n a multiple of 8, GROUP_M M-tiles per group);
+// other shapes keep map_tile's order.
+template <int BM, int BNC>
+__device__ __forceinline__ TileCoord map_tile_shared(int64_t tiles_m, int64_t tiles_n, int64_t total) {
+  const int64_t wg = blockIdx.x;
+  if (tiles_n % 8 != 0 || tiles_m % GROUP_M != 0) return map_tile<BM, BNC>(tiles_m, tiles_n, total);
+  const int64_t g = wg >> 3, x = wg & 7;
+  return tile_of<BM, BNC>(64 * (g >> 3) + 8 * x + (g & 7), tiles_m, tiles_n);
 }
 
 // Global -> register staging of one K stage (VW complex per load).  With
@@ -860,7 +878,7 @@ __global__ __launch_bounds__(64 * WM * WN, (min_blocks<OpsT, WM, WN, VW>())) voi
   const int tid = threadIdx.x;
   const int lane = tid & 63, wave = tid >> 6;
   const int wm = wave / WN, wn = wave % WN;
-  const TileCoord tc = map_tile<S::BM, S::BNC>(tiles_m, tiles_n, total);
+  const TileCoord tc = map_tile_shared<S::BM, S::BNC>(tiles_m, tiles_n, total);
   int64_t oa, ob;
   batch_offsets(d, tc.b, oa, ob);
   const float2* __restrict__ A = d.A + oa;
@@ -1095,7 +1113,7 @@ __global__ __launch_bounds__(512, 1) void cgemm_bf16x3_presplit(GemmDesc d, cons
   const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
   const int wm = wave >> 1, wn = wave & 1;
   const int h = lane >> 5, l32 = lane & 31;
-  const TileCoord tc = map_tile<kPresplitBM, kPresplitBNC>(tiles_m, tiles_n, total);
+  const TileCoord tc = map_tile_shared<kPresplitBM, kPresplitBNC>(tiles_m, tiles_n, total);
   const uint32_t* gA = Ap + tc.row0 * 2 * kp;
   const uint32_t* gB = Bp + 2 * tc.col0 * 2 * kp;
   const int64_t nk = kp / BKC;
