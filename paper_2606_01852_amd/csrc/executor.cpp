@@ -343,7 +343,10 @@ struct ChunkOps {
   void step(int s) {
     const StepPlan& sp = cp.steps[s];
     const GemmDesc d = desc(s);
-    if (presplit(sp)) {
+    if (presplit(sp) && form == Form::M3) {
+      void* p = planes(sp, 1);
+      L.run(s, stream, [&] { return launch_gemm_presplit_3m(d, p, stream); });
+    } else if (presplit(sp)) {
       void* p = planes(sp, 1);
       // operands whose permute wrote the planes are not split again
       const bool have_a = sp.la < n && planes_of(sp.la) == 1, have_b = sp.lb < n && planes_of(sp.lb) == 2;

@@ -42,6 +42,7 @@
 // them from one HBM read (split precision on pair30: 316.7 -> 314.5 ms,
 // where the chip's power sets its clock; complex64 unchanged).
 #include <atomic>
+#include <cstring>
 #include <type_traits>
 
 #include "bf16_split.hpp"
@@ -1014,6 +1015,57 @@ __global__ __launch_bounds__(256) void split_planes_b(const float2* __restrict__
   }
 }
 
+// 3M form: the real parts X_r, X_i and X_s = X_r + X_i (float32 sums) of
+// a complex operand as three real matrices of `rows` x k, each in the
+// planes layout of a real GEMM (blocks of 32 real k, [32 bf16 hi | 32 bf16
+// lo], kp real k pairs per row; padding rows and k zero).  One thread per
+// pair of real k (two complex elements) of a padded row; P points at the
+// r planes, the i and s planes follow at `plane` uint32 apart.
+__global__ __launch_bounds__(256) void split_planes_3m(const float2* __restrict__ X, int64_t rows, int64_t k,
+                                                      int64_t ld, uint32_t kp, uint32_t pairs, int64_t plane,
+                                                      uint32_t* __restrict__ P) {
+  for (uint32_t t = blockIdx.x * 256u + threadIdx.x; t < pairs; t += gridDim.x * 256u) {
+    const int64_t row = t / kp, q = t - row * kp;  // real k 2q, 2q + 1
+    float2 x0 = make_float2(0.f, 0.f), x1 = x0;
+    if (row < rows) {
+      const float2* src = X + row * ld + 2 * q;
+      if (2 * q < k) x0 = src[0];
+      if (2 * q + 1 < k) x1 = src[1];
+    }
+    uint32_t rh, rl, ih, il, sh, sl;
+    ps_split(x0.x, x1.x, rh, rl);
+    ps_split(x0.y, x1.y, ih, il);
+    ps_split(x0.x + x0.y, x1.x + x1.y, sh, sl);
+    const int64_t o = ps_index(row, q, kp);
+    __builtin_nontemporal_store(rh, P + o);
+    __builtin_nontemporal_store(rl, P + o + 16);
+    __builtin_nontemporal_store(ih, P + plane + o);
+    __builtin_nontemporal_store(il, P + plane + o + 16);
+    __builtin_nontemporal_store(sh, P + 2 * plane + o);
+    __builtin_nontemporal_store(sl, P + 2 * plane + o + 16);
+  }
+}
+
+// C from the three real products (rows of `ldt` floats, T2 and T3 `tplane`
+// floats after T1): re = T1 - T2, im = T3 - T1 - T2 in float32, the same
+// expressions as the 3M store; row-major or through the offset tables.
+__global__ __launch_bounds__(256) void combine_3m(const float* __restrict__ T, int64_t tplane, int64_t ldt,
+                                                 GemmDesc d) {
+  const int64_t total = d.m * d.n;
+  const double inv_n = 1.0 / static_cast<double>(d.n);
+  for (int64_t e = static_cast<int64_t>(blockIdx.x) * 256 + threadIdx.x; e < total;
+       e += static_cast<int64_t>(gridDim.x) * 256) {
+    const int64_t row = plane_row(e, d.n, inv_n), col = e - row * d.n;
+    const int64_t o = row * ldt + col;
+    const float t1 = T[o], t2 = T[tplane + o], t3 = T[2 * tplane + o];
+    float2 v;
+    v.x = t1 - t2;
+    v.y = t3 - t1 - t2;
+    const int64_t c = d.offM ? d.offM[row] + d.offN[col] : e;
+    d.C[c] = v;
+  }
+}
+
 struct PsFrag {
   s8v ah[2], al[2], bh[4], bl[4];
 };
@@ -1407,6 +1459,47 @@ hipError_t launch_gemm_presplit(const GemmDesc& d, void* planes, bool have_a, bo
   else
     hipLaunchKernelGGL(cgemm_bf16x3_presplit<false>, dim3(static_cast<unsigned>(total)), dim3(512), PS_LDS, s, d, Ap,
                        Bp, kp, tiles_m, tiles_n, total);
+  return hipGetLastError();
+}
+
+hipError_t launch_gemm_presplit_3m(const GemmDesc& d, void* buf, hipStream_t s) {
+  if (d.h <= 0 || d.m <= 0 || d.n <= 0) return hipSuccess;
+  if (d.k <= 0 || d.h != 1 || d.rowA || d.kA || d.rowB || d.kB || !buf || reinterpret_cast<uintptr_t>(buf) % 256 != 0)
+    return hipErrorInvalidValue;
+  const Presplit3M g = presplit_3m_layout(d.m, d.n, d.k);
+  // one thread per real k pair of a padded row, counted in 32 bits
+  if ((g.mp > g.np ? g.mp : g.np) * g.kp >= (int64_t{1} << 31)) return hipErrorInvalidValue;
+  hipError_t e = ensure_lds_presplit();
+  if (e != hipSuccess) return e;
+  char* base = static_cast<char*>(buf);
+  uint32_t* Ap = reinterpret_cast<uint32_t*>(base);
+  uint32_t* Bp = reinterpret_cast<uint32_t*>(base + g.off_b);
+  float* T = reinterpret_cast<float*>(base + g.off_t);
+  const int64_t ld = row_stride(d);
+  auto grid = [](int64_t threads) {
+    const int64_t q = (threads + 255) / 256;
+    return static_cast<unsigned>(q < 131072 ? q : 131072);
+  };
+  const int64_t plane_a = g.mp * 2 * g.kp, plane_b = g.np * 2 * g.kp;  // uint32 per plane
+  hipLaunchKernelGGL(split_planes_3m, dim3(grid(g.mp * g.kp)), dim3(256), 0, s, d.A, d.m, d.k, ld,
+                     static_cast<uint32_t>(g.kp), static_cast<uint32_t>(g.mp * g.kp), plane_a, Ap);
+  hipLaunchKernelGGL(split_planes_3m, dim3(grid(g.np * g.kp)), dim3(256), 0, s, d.B, d.n, d.k, ld,
+                     static_cast<uint32_t>(g.kp), static_cast<uint32_t>(g.np * g.kp), plane_b, Bp);
+  // T_p = X_p Y_p^T as the pre-split kernel's real GEMM: m rows, np real
+  // columns (nh column pairs), 2 kp real k; stored row-major in pairs
+  const int64_t tiles_m = g.mp / kPresplitBM, tiles_n = g.np / 2 / kPresplitBNC, total = tiles_m * tiles_n;
+  for (int p = 0; p < 3; ++p) {
+    GemmDesc dp;
+    std::memset(&dp, 0, sizeof(dp));
+    dp.C = reinterpret_cast<float2*>(T + p * g.tplane);
+    dp.m = d.m;
+    dp.n = g.nh;
+    dp.k = g.kp;
+    dp.h = 1;
+    hipLaunchKernelGGL(cgemm_bf16x3_presplit<false>, dim3(static_cast<unsigned>(total)), dim3(512), PS_LDS, s, dp,
+                       Ap + p * plane_a, Bp + p * plane_b, g.kp, tiles_m, tiles_n, total);
+  }
+  hipLaunchKernelGGL(combine_3m, dim3(grid(d.m * d.n)), dim3(256), 0, s, T, g.tplane, 2 * g.nh, d);
   return hipGetLastError();
 }
 

@@ -162,6 +162,34 @@ inline size_t presplit_plane_bytes(int64_t m, int64_t n, int64_t k) {
 // have_a / have_b: that operand's planes are already written (by the
 // permute that produced it) and are not split again.
 hipError_t launch_gemm_presplit(const GemmDesc& d, void* planes, bool have_a, bool have_b, hipStream_t s);
+// The 3M form on the same kernel: each operand's real parts X_r, X_i and
+// X_s = X_r + X_i (float32 sums) are split once into the planes of a real
+// GEMM operand (rows of 2 kp real k), the three real products T1 = A_r B_r^T,
+// T2 = A_i B_i^T, T3 = A_s B_s^T run as three launches of the pre-split
+// kernel into float32 matrices of m x 2 nh, and a last pass forms
+// C = (T1 - T2, T3 - T1 - T2) with the step's store.  Bitwise the result
+// of the 3M split tiles (same products in the same order per accumulator).
+// `buf`: presplit_3m_layout(m, n, k).bytes of device memory, 256-aligned.
+struct Presplit3M {
+  int64_t mp, np, kp, nh;      // padded rows of A and B, real k pairs, column pairs of T
+  int64_t off_b, off_t;        // byte offsets of B's planes and of T1 in the buffer
+  int64_t tplane;              // floats from T1 to T2 (and T2 to T3)
+  int64_t bytes;
+};
+inline Presplit3M presplit_3m_layout(int64_t m, int64_t n, int64_t k) {
+  auto al = [](int64_t x) { return (x + 255) / 256 * 256; };
+  Presplit3M g;
+  g.nh = (n + 1) / 2;
+  g.mp = presplit_rows_a(m);
+  g.np = presplit_rows_b(g.nh);      // real rows of B, padded to the tile's 256
+  g.kp = presplit_k((k + 1) / 2);    // real k pairs per row: k padded to 32
+  g.off_b = al(3 * g.mp * g.kp * 8);  // per row 2 kp real k, hi and lo: 8 kp bytes
+  g.off_t = g.off_b + al(3 * g.np * g.kp * 8);
+  g.tplane = m * 2 * g.nh;
+  g.bytes = g.off_t + al(3 * g.tplane * 4);
+  return g;
+}
+hipError_t launch_gemm_presplit_3m(const GemmDesc& d, void* buf, hipStream_t s);
 // Split-K epilogue: C[b, i, j] = sum_{p < S} P[((b * S + p) * m + i) * n + j],
 // p ascending, stored at b * m * n + (offM ? offM[i] + offN[j] : i * n + j).
 hipError_t launch_splitk_reduce(const float2* P, float2* C, int64_t h, int64_t m, int64_t n, int64_t S,

@@ -670,15 +670,18 @@ std::unique_ptr<ChunkPlan> build_chunk(const Plan& plan, int j) {
       }
       sp.tperm = build_permute(ext, ist);
     }
-    // split precision (4M form) on large single GEMMs: split each operand
-    // once into bf16 planes (8 + 8 bytes per element of A, 8 + 16 of B
-    // moved: about 1 % of the GEMM's time from 4096 x 4096 up) rather than
-    // in the staging of every workgroup that reads it
-    sp.presplit = plan.prec == TNC_PREC_BF16X3 && plan.form == TNC_GEMM_4M && sp.kind == GemmKernel::MFMA &&
-                  sp.split == 1 && !sp.trans && d.h == 1 && sp.lm >= 4096 && sp.ln >= 4096;
-    // an operand leaf that is permuted anyway writes the planes itself (the
-    // permute and the split in one pass) when rows are whole 16-k blocks
-    if (sp.presplit && sp.k % 16 == 0 && row_stride(d) == sp.k)
+    // split precision on large single GEMMs: split each operand once into
+    // bf16 planes (4M form: 8 + 8 bytes per element of A, 8 + 16 of B moved,
+    // about 1 % of the GEMM's time from 4096 x 4096 up; 3M form: 8 + 12 per
+    // element of each operand, plus its three float32 products' 12 + 12 + 8
+    // per output element) rather than in the staging of every workgroup
+    // that reads it
+    sp.presplit = plan.prec == TNC_PREC_BF16X3 && sp.kind == GemmKernel::MFMA && sp.split == 1 && !sp.trans &&
+                  d.h == 1 && sp.lm >= 4096 && sp.ln >= 4096;
+    // an operand leaf that is permuted anyway writes the 4M form's planes
+    // itself (the permute and the split in one pass) when rows are whole
+    // 16-k blocks
+    if (sp.presplit && plan.form == TNC_GEMM_4M && sp.k % 16 == 0 && row_stride(d) == sp.k)
       for (int side = 1; side <= 2; ++side) {
         const int id = side == 1 ? sp.la : sp.lb;
         if (id >= n) continue;
@@ -735,9 +738,10 @@ std::unique_ptr<ChunkPlan> build_chunk(const Plan& plan, int j) {
     const StepPlan& sp = cp->steps[s];
     if (sp.split > 1 || sp.trans)  // split-K partials or the untransposed output, live during the step only
       ivs.push_back({align_up(sp.h * sp.split * sp.lm * sp.ln * 8), when(s), when(s), -1 - s});
-    if (sp.presplit)  // the operands' bf16 planes, live during the step only
-      ivs.push_back({align_up(static_cast<int64_t>(presplit_plane_bytes(sp.lm, sp.ln, sp.k))), when(s), when(s),
-                     -1 - ns - s});
+    if (sp.presplit)  // the operands' bf16 planes (and the 3M products), live during the step only
+      ivs.push_back({align_up(plan.form == TNC_GEMM_3M ? presplit_3m_layout(sp.lm, sp.ln, sp.k).bytes
+                                                       : static_cast<int64_t>(presplit_plane_bytes(sp.lm, sp.ln, sp.k))),
+                     when(s), when(s), -1 - ns - s});
   }
   std::vector<int> idx(ivs.size());
   std::iota(idx.begin(), idx.end(), 0);

@@ -287,6 +287,59 @@ def test_presplit_bf16x3_is_bitwise_the_wide_tile(ctx, order, leaves):
     print(f"presplit bf16x3 {order} {leaves}: err vs emulation {err:.2e}, bitwise = wide tile", flush=True)
 
 
+@pytest.mark.parametrize("kk", [200, 201], ids=["even_k", "odd_k"])
+@pytest.mark.parametrize("order", ["natural", "interleaved"])
+def test_presplit_bf16x3_3m_is_bitwise_the_3m_tiles(ctx, order, kk):
+    """Split precision in the 3M form on pre-split planes: one GEMM of
+    4160 x 4224 x kk (ragged against the tile; kk odd pads the last real k
+    pair) splits A and B once into their r, i and s planes, runs the three
+    real products on the pre-split kernel and combines them with the step's
+    store (row-major or interleaved).  The result is bitwise that of the 3M
+    split tiles (variants 0 and 2 forced) and of its hipGraph replays,
+    within 1e-5 of the oracle's 3M split emulation, and every element within
+    twice the split bound of the exact product."""
+    rng = np.random.Generator(np.random.PCG64(4161 + kk))
+    ext = np.array([64, 65, 66, 64, kk], dtype=np.int64)
+    la, lb = (0, 1, 4), (2, 3, 4)
+
+    def cn(lab):
+        shape = tuple(int(ext[l]) for l in lab)
+        x = rng.standard_normal(shape + (2,), dtype=np.float32) * np.float32(np.sqrt(0.5))
+        return x.view(np.complex64).reshape(shape)
+    out = (0, 1, 2, 3) if order == "natural" else (0, 2, 1, 3)
+    net = Network([cn(la), cn(lb)], [la, lb], ext, out)
+    path = Path(np.array([[0, 1]], dtype=np.int32), ())
+    print(f"presplit bf16x3 3M {order} k={kk}", flush=True)
+    z, plan, _ = run(ctx, net, path, prec=tnc.PREC_BF16X3, form=tnc.GEMM_3M)
+    st = tnc.tnc_plan_get_step(plan.handle, 0)
+    assert st.kernel == 0 and st.presplit == 1 and st.split == 1 and st.presplit_fused == 0
+    assert st.natural == (1 if order == "natural" else 0)
+    for v in (0, 2):
+        tnc.tnc_ctx_set_gemm_variant(ctx.handle, v)
+        try:
+            w, _, _ = run(ctx, net, path, prec=tnc.PREC_BF16X3, form=tnc.GEMM_3M)
+        finally:
+            tnc.tnc_ctx_set_gemm_variant(ctx.handle, -1)
+        assert np.array_equal(np.asarray(z).view(np.uint64), np.asarray(w).view(np.uint64)), v
+    tnc.tnc_plan_set_graph(plan.handle, True)
+    for _ in range(2):
+        g = plan.contract().reshape(np.asarray(z).shape)
+        assert np.array_equal(g.view(np.uint64), np.asarray(z).view(np.uint64))
+    emu = oc.contract(net, path, step=osp.split_step_3m)
+    err = assert_close(z, emu, tol=1e-5, what="3M presplit vs emulation")
+    e0, e1, e2, e3, _ = (int(x) for x in ext)
+    A = net.leaves[0].reshape(e0 * e1, kk).astype(np.complex128)
+    B = net.leaves[1].reshape(e2 * e3, kk).astype(np.complex128)
+    exact = (A @ B.T).reshape(e0, e1, e2, e3)
+    bound = (2 * 3 * 2.0 ** -16 * ((np.abs(A.real) + np.abs(A.imag)) @ (np.abs(B.real) + np.abs(B.imag)).T)
+             .reshape(e0, e1, e2, e3))
+    if order != "natural":
+        exact = exact.transpose(0, 2, 1, 3)
+        bound = bound.transpose(0, 2, 1, 3)
+    assert np.all(np.abs(np.asarray(z) - exact) <= bound + 1e-6 * np.abs(exact))
+    print(f"presplit bf16x3 3M {order} k={kk}: err vs emulation {err:.2e}, bitwise = 3M tiles", flush=True)
+
+
 def interleaved_pair(z, a, b, c, d, k, seed):
     """One contraction A[z, a, b, k] B[z, c, d, k] whose result order
     (z, a, c, b, d) interleaves the M labels (a, b) with the N labels (c, d):

@@ -189,6 +189,25 @@ def test_presplit_steps_and_their_plane_buffer(hctx):
             assert grow == 0
         for p in plans.values():
             p.close()
+        # the 3M form: the r, i and s planes of both operands (real k in
+        # blocks of 32, B's real rows padded to 256) and the three float32
+        # products of m x 2 ceil(n / 2), each part 256-byte aligned
+        p3 = {prec: tnc.Plan(tn, np.array([[0, 1]], dtype=np.int32), (), prec, tnc.GEMM_3M)
+              for prec in (tnc.PREC_C64, tnc.PREC_BF16X3)}
+        s3 = p3[tnc.PREC_BF16X3].step(0)
+        assert s3.presplit == (1 if expect else 0) and s3.presplit_fused == 0
+        grow3 = p3[tnc.PREC_BF16X3].info.peak_bytes - p3[tnc.PREC_C64].info.peak_bytes
+        if expect:
+            lm, ln = (s3.n, s3.m) if s3.swapped else (s3.m, s3.n)
+            up = lambda x, a: -(-x // a) * a
+            nh, kp = up(ln, 2) // 2, up(up(k, 2) // 2, 16)
+            mp, np_ = up(lm, 256), 2 * up(nh, 128)
+            want = up(3 * mp * kp * 8, align) + up(3 * np_ * kp * 8, align) + up(3 * lm * 2 * nh * 4, align)
+            assert grow3 == up(want, align), (m, n, k, grow3, want)
+        else:
+            assert grow3 == 0
+        for p in p3.values():
+            p.close()
         tn.close()
 
 
