@@ -197,11 +197,14 @@ typedef struct {
   int32_t presplit;              /* 1 = split-bf16x3 step whose operands are
                                     split once into bf16 planes (in the plan's
                                     arena) and staged global -> LDS directly;
-                                    bitwise the result of variant 3          */
+                                    bitwise the result of variant 3 (4M form)
+                                    or of the 3M form's tiles (its three real
+                                    products as three real GEMMs, then one
+                                    combining pass)                          */
   int32_t presplit_fused;        /* bit 0 / bit 1: the permute that prepares
                                     operand A / B' (a leaf) writes its planes
                                     itself, one pass instead of a permute and
-                                    a split                                  */
+                                    a split (4M form)                        */
 } tnc_step_info;
 tnc_status tnc_plan_get_step(tnc_plan plan, int32_t step, tnc_step_info* out);
 /* The same view for the batch of max_chunk slices the executor runs (h then
