@@ -87,4 +87,49 @@ __device__ __forceinline__ void put_planes_b2(uint32_t* P, int64_t o, int64_t k,
   __builtin_nontemporal_store(u32x2{swap_halves(l0), swap_halves(l1)}, reinterpret_cast<u32x2*>(P + p1 + 16));
 }
 
+// 3M form: the planes of three real GEMM operands X_r, X_i and X_s =
+// X_r + X_i (float32 sums) for an operand stored densely as rows of k
+// complex values, k a multiple of 32 (then a row is k / 32 blocks of 32 real
+// k, [32 bf16 hi | 32 bf16 lo], k uint32 per row with no padding).  Element
+// o = row * k + kc is real k kc of its row: bf16 pair q = kc / 2 of the row,
+// half kc & 1 of it; the i and s planes follow the r planes at `plane`
+// uint32 apart.
+__device__ __forceinline__ int64_t planes_3m_index(int64_t row, int64_t kc, int64_t k) {
+  const int64_t q = kc >> 1;
+  return row * k + 32 * (q >> 4) + (q & 15);
+}
+
+__device__ __forceinline__ void put_planes_3m(uint32_t* P, int64_t o, int64_t k, double inv_k, int64_t plane,
+                                              float re, float im) {
+  const int64_t row = plane_row(o, k, inv_k), kc = o - row * k;
+  const int64_t h = 2 * planes_3m_index(row, kc, k) + (kc & 1);  // bf16 index of the hi half
+  uint16_t* Q = reinterpret_cast<uint16_t*>(P);
+  uint32_t rh, rl, ih, il;
+  bf16_split2(re, im, rh, rl);
+  bf16_split2(re + im, 0.f, ih, il);  // the s plane's pair (its low half)
+  __builtin_nontemporal_store(static_cast<uint16_t>(rh), Q + h);
+  __builtin_nontemporal_store(static_cast<uint16_t>(rl), Q + h + 32);
+  __builtin_nontemporal_store(static_cast<uint16_t>(rh >> 16), Q + 2 * plane + h);
+  __builtin_nontemporal_store(static_cast<uint16_t>(rl >> 16), Q + 2 * plane + h + 32);
+  __builtin_nontemporal_store(static_cast<uint16_t>(ih), Q + 4 * plane + h);
+  __builtin_nontemporal_store(static_cast<uint16_t>(il), Q + 4 * plane + h + 32);
+}
+
+// Two adjacent elements o, o + 1 (o even): one bf16 pair of each plane.
+__device__ __forceinline__ void put_planes_3m2(uint32_t* P, int64_t o, int64_t k, double inv_k, int64_t plane,
+                                               float re0, float im0, float re1, float im1) {
+  const int64_t row = plane_row(o, k, inv_k);
+  const int64_t i = planes_3m_index(row, o - row * k, k);
+  uint32_t rh, rl, ih, il, sh, sl;
+  bf16_split2(re0, re1, rh, rl);
+  bf16_split2(im0, im1, ih, il);
+  bf16_split2(re0 + im0, re1 + im1, sh, sl);
+  __builtin_nontemporal_store(rh, P + i);
+  __builtin_nontemporal_store(rl, P + i + 16);
+  __builtin_nontemporal_store(ih, P + plane + i);
+  __builtin_nontemporal_store(il, P + plane + i + 16);
+  __builtin_nontemporal_store(sh, P + 2 * plane + i);
+  __builtin_nontemporal_store(sl, P + 2 * plane + i + 16);
+}
+
 }  // namespace tnc

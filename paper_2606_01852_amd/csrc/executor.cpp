@@ -174,7 +174,8 @@ namespace {
 // plan's device blob); `bd` points at a per-chunk base offset on the device
 // (null: none).
 hipError_t launch_planned_permute(const PermuteHost& p, const ChunkPlan& cp, const float2* in, float2* out,
-                                  const int64_t* bd, hipStream_t stream, int planes = 0, int64_t pk = 0) {
+                                  const int64_t* bd, hipStream_t stream, int planes = 0, int64_t pk = 0,
+                                  int64_t pplane = 0) {
   const char* blob = static_cast<const char*>(cp.blob.ptr);
   if (p.tiled) {
     PermuteDesc d{};
@@ -195,6 +196,7 @@ hipError_t launch_planned_permute(const PermuteHost& p, const ChunkPlan& cp, con
     d.pairs = p.pairs ? 1 : 0;
     d.planes = planes;
     d.pk = pk;
+    d.pplane = pplane;
     return launch_permute(d, stream);
   }
   if (planes) return hipErrorInvalidValue;  // plane output is planned for tiled permutes only
@@ -210,9 +212,9 @@ hipError_t launch_planned_permute(const PermuteHost& p, const ChunkPlan& cp, con
 // per-chunk base offset on the device (null: none).  planes = 1 / 2: out
 // is the consuming step's A / B' planes (rows of pk complex).
 hipError_t launch_leaf_prep(const Net& net, const ChunkPlan& cp, int t, float2* out, const int64_t* bd,
-                            hipStream_t stream, int planes = 0, int64_t pk = 0) {
+                            hipStream_t stream, int planes = 0, int64_t pk = 0, int64_t pplane = 0) {
   return launch_planned_permute(cp.leaf[t].perm, cp, static_cast<const float2*>(net.leaf[t].ptr), out, bd, stream,
-                                planes, pk);
+                                planes, pk, pplane);
 }
 
 // (Re)fill the leaf cache when it is empty or a cached leaf's data has been
@@ -296,9 +298,11 @@ struct ChunkOps {
     const LeafPrep& lp = cp.leaf[t];
     return lp.planes_side && presplit(cp.steps[lp.step]) ? lp.planes_side : 0;
   }
-  // the step's planes: A's, then B''s
+  // the step's planes: A's, then B''s (in the 3M form each operand's r, i
+  // and s planes)
   char* planes(const StepPlan& sp, int side) const {
     char* p = a.arena + cp.buf_off[sp.presplit_buf];
+    if (form == Form::M3) return side == 2 ? p + presplit_3m_layout(sp.lm, sp.ln, sp.k).off_b : p;
     return side == 2 ? p + presplit_rows_a(sp.lm) * presplit_k(sp.k) * 8 : p;
   }
   void prep(int t) {
@@ -308,7 +312,15 @@ struct ChunkOps {
     float2* out = side ? reinterpret_cast<float2*>(planes(*sp, side)) : ptr(t);
     const int64_t* bd = lp.base_slot >= 0 ? bases + lp.base_slot : nullptr;
     const int64_t pk = side ? sp->k : 0;
-    L.run(t_prep, stream, [&] { return launch_leaf_prep(net, cp, t, out, bd, stream, side, pk); });
+    // 3M form: one plane mode for both operands, planes of padded rows x k
+    int mode = side;
+    int64_t pplane = 0;
+    if (side && form == Form::M3) {
+      const Presplit3M g = presplit_3m_layout(sp->lm, sp->ln, sp->k);
+      mode = 3;
+      pplane = (side == 1 ? g.mp : g.np) * 2 * g.kp;
+    }
+    L.run(t_prep, stream, [&] { return launch_leaf_prep(net, cp, t, out, bd, stream, mode, pk, pplane); });
   }
   int variant(const StepPlan& sp) const { return net.ctx->gemm_variant >= 0 ? net.ctx->gemm_variant : sp.variant; }
   // The step's launch descriptor with this run's pointers (the split-K
@@ -345,7 +357,8 @@ struct ChunkOps {
     const GemmDesc d = desc(s);
     if (presplit(sp) && form == Form::M3) {
       void* p = planes(sp, 1);
-      L.run(s, stream, [&] { return launch_gemm_presplit_3m(d, p, stream); });
+      const bool have_a = sp.la < n && planes_of(sp.la) == 1, have_b = sp.lb < n && planes_of(sp.lb) == 2;
+      L.run(s, stream, [&] { return launch_gemm_presplit_3m(d, p, have_a, have_b, stream); });
     } else if (presplit(sp)) {
       void* p = planes(sp, 1);
       // operands whose permute wrote the planes are not split again

@@ -1462,7 +1462,7 @@ hipError_t launch_gemm_presplit(const GemmDesc& d, void* planes, bool have_a, bo
   return hipGetLastError();
 }
 
-hipError_t launch_gemm_presplit_3m(const GemmDesc& d, void* buf, hipStream_t s) {
+hipError_t launch_gemm_presplit_3m(const GemmDesc& d, void* buf, bool have_a, bool have_b, hipStream_t s) {
   if (d.h <= 0 || d.m <= 0 || d.n <= 0) return hipSuccess;
   if (d.k <= 0 || d.h != 1 || d.rowA || d.kA || d.rowB || d.kB || !buf || reinterpret_cast<uintptr_t>(buf) % 256 != 0)
     return hipErrorInvalidValue;
@@ -1481,10 +1481,12 @@ hipError_t launch_gemm_presplit_3m(const GemmDesc& d, void* buf, hipStream_t s) 
     return static_cast<unsigned>(q < 131072 ? q : 131072);
   };
   const int64_t plane_a = g.mp * 2 * g.kp, plane_b = g.np * 2 * g.kp;  // uint32 per plane
-  hipLaunchKernelGGL(split_planes_3m, dim3(grid(g.mp * g.kp)), dim3(256), 0, s, d.A, d.m, d.k, ld,
-                     static_cast<uint32_t>(g.kp), static_cast<uint32_t>(g.mp * g.kp), plane_a, Ap);
-  hipLaunchKernelGGL(split_planes_3m, dim3(grid(g.np * g.kp)), dim3(256), 0, s, d.B, d.n, d.k, ld,
-                     static_cast<uint32_t>(g.kp), static_cast<uint32_t>(g.np * g.kp), plane_b, Bp);
+  if (!have_a)
+    hipLaunchKernelGGL(split_planes_3m, dim3(grid(g.mp * g.kp)), dim3(256), 0, s, d.A, d.m, d.k, ld,
+                       static_cast<uint32_t>(g.kp), static_cast<uint32_t>(g.mp * g.kp), plane_a, Ap);
+  if (!have_b)
+    hipLaunchKernelGGL(split_planes_3m, dim3(grid(g.np * g.kp)), dim3(256), 0, s, d.B, d.n, d.k, ld,
+                       static_cast<uint32_t>(g.kp), static_cast<uint32_t>(g.np * g.kp), plane_b, Bp);
   // T_p = X_p Y_p^T as the pre-split kernel's real GEMM: m rows, np real
   // columns (nh column pairs), 2 kp real k; stored row-major in pairs
   const int64_t tiles_m = g.mp / kPresplitBM, tiles_n = g.np / 2 / kPresplitBNC, total = tiles_m * tiles_n;

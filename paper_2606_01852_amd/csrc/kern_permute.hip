@@ -59,13 +59,16 @@ typedef float f2v __attribute__((ext_vector_type(2)));
 // Output element o of a permutation: complex64, or its split into the
 // planes of a split-precision GEMM operand (PermuteDesc::planes).
 template <int PLANES>
-__device__ __forceinline__ void put_out(f2v* __restrict__ out, int64_t o, f2v v, int64_t pk, double inv_pk) {
+__device__ __forceinline__ void put_out(f2v* __restrict__ out, int64_t o, f2v v, const PermuteDesc& d,
+                                        double inv_pk) {
   if constexpr (PLANES == 0)
     __builtin_nontemporal_store(v, out + o);
   else if constexpr (PLANES == 1)
     put_planes_a(reinterpret_cast<uint32_t*>(out), o, v.x, v.y);
+  else if constexpr (PLANES == 2)
+    put_planes_b(reinterpret_cast<uint32_t*>(out), o, d.pk, inv_pk, v.x, v.y);
   else
-    put_planes_b(reinterpret_cast<uint32_t*>(out), o, pk, inv_pk, v.x, v.y);
+    put_planes_3m(reinterpret_cast<uint32_t*>(out), o, d.pk, inv_pk, d.pplane, v.x, v.y);
 }
 
 template <int EPT, int PLANES>
@@ -86,7 +89,7 @@ __global__ __launch_bounds__(kPermThreads) void permute_tiled(PermuteDesc d) {
   }
   const int64_t base = d.base + (d.base_dev ? d.base_dev[0] : 0);
   const uint32_t L = static_cast<uint32_t>(d.L);
-  const double inv_pk = PLANES == 2 ? 1.0 / static_cast<double>(d.pk) : 0.0;
+  const double inv_pk = PLANES >= 2 ? 1.0 / static_cast<double>(d.pk) : 0.0;
   int64_t tile = blockIdx.x;
   if (tile >= d.n_tiles) return;
   f2v v[EPT];
@@ -111,7 +114,7 @@ __global__ __launch_bounds__(kPermThreads) void permute_tiled(PermuteDesc d) {
     if (next < d.n_tiles) load(next);
 #pragma unroll
     for (int e = 0; e < EPT; ++e)
-      if (out_off[e] >= 0) put_out<PLANES>(out, ob + out_off[e], lds[slot_w[e]], d.pk, inv_pk);
+      if (out_off[e] >= 0) put_out<PLANES>(out, ob + out_off[e], lds[slot_w[e]], d, inv_pk);
     __syncthreads();
   }
 }
@@ -143,7 +146,7 @@ __global__ __launch_bounds__(kPermThreads) void permute_pairs(PermuteDesc d) {
   }
   const int64_t base = d.base;
   const uint32_t L = static_cast<uint32_t>(d.L);
-  const double inv_pk = PLANES == 2 ? 1.0 / static_cast<double>(d.pk) : 0.0;
+  const double inv_pk = PLANES >= 2 ? 1.0 / static_cast<double>(d.pk) : 0.0;
   int64_t tile = blockIdx.x;
   if (tile >= d.n_tiles) return;
   f4v v[PPT];
@@ -178,8 +181,10 @@ __global__ __launch_bounds__(kPermThreads) void permute_pairs(PermuteDesc d) {
           __builtin_nontemporal_store(f4v{a.x, a.y, b.x, b.y}, reinterpret_cast<f4v*>(out + o));
         else if constexpr (PLANES == 1)
           put_planes_a2(reinterpret_cast<uint32_t*>(out), o, a.x, a.y, b.x, b.y);
-        else
+        else if constexpr (PLANES == 2)
           put_planes_b2(reinterpret_cast<uint32_t*>(out), o, d.pk, inv_pk, a.x, a.y, b.x, b.y);
+        else
+          put_planes_3m2(reinterpret_cast<uint32_t*>(out), o, d.pk, inv_pk, d.pplane, a.x, a.y, b.x, b.y);
       }
     __syncthreads();
   }
@@ -220,7 +225,9 @@ hipError_t launch_permute(const PermuteDesc& d, hipStream_t s) {
   // ms); pairs per thread follow the element rule (8 pairs where it takes
   // 16 elements)
   const bool aligned = (reinterpret_cast<uintptr_t>(d.in) | reinterpret_cast<uintptr_t>(d.out)) % 16 == 0;
-  if (d.planes < 0 || d.planes > 2 || (d.planes && (d.pk <= 0 || d.pk % 16 != 0))) return hipErrorInvalidValue;
+  if (d.planes < 0 || d.planes > 3 || (d.planes && (d.pk <= 0 || d.pk % (d.planes == 3 ? 32 : 16) != 0)) ||
+      (d.planes == 3 && d.pplane <= 0))
+    return hipErrorInvalidValue;
   auto launch = [&](auto plane_tag) -> hipError_t {
     constexpr int PL = decltype(plane_tag)::value;
     if (d.pairs && !d.base_dev && d.base % 2 == 0 && aligned && ept >= 2) {
@@ -251,6 +258,7 @@ hipError_t launch_permute(const PermuteDesc& d, hipStream_t s) {
   };
   if (d.planes == 1) return launch(std::integral_constant<int, 1>{});
   if (d.planes == 2) return launch(std::integral_constant<int, 2>{});
+  if (d.planes == 3) return launch(std::integral_constant<int, 3>{});
   return launch(std::integral_constant<int, 0>{});
 }
 

@@ -96,9 +96,12 @@ struct PermuteDesc {
   int32_t pairs;               // the tables allow 16-byte pairs (PermuteHost::pairs)
   // 0: write complex64 to out; 1 / 2: write the split planes of a
   // split-precision GEMM's A / B' operand (out = the planes, rows of pk
-  // complex, pk a multiple of 16)
+  // complex, pk a multiple of 16); 3: the r, i and s planes of a 3M-form
+  // operand (rows of pk complex, pk a multiple of 32, the i and s planes
+  // pplane uint32 after the r planes)
   int32_t planes;
   int64_t pk;
+  int64_t pplane;
 };
 
 // Plain gather: out[w] = in[base + sum_d digit_d(w) * in_stride[d]] over
@@ -189,7 +192,9 @@ inline Presplit3M presplit_3m_layout(int64_t m, int64_t n, int64_t k) {
   g.bytes = g.off_t + al(3 * g.tplane * 4);
   return g;
 }
-hipError_t launch_gemm_presplit_3m(const GemmDesc& d, void* buf, hipStream_t s);
+// have_a / have_b: as for launch_gemm_presplit (rows of k complex, k a
+// multiple of 32, written by the permute that produced the operand).
+hipError_t launch_gemm_presplit_3m(const GemmDesc& d, void* buf, bool have_a, bool have_b, hipStream_t s);
 // Split-K epilogue: C[b, i, j] = sum_{p < S} P[((b * S + p) * m + i) * n + j],
 // p ascending, stored at b * m * n + (offM ? offM[i] + offN[j] : i * n + j).
 hipError_t launch_splitk_reduce(const float2* P, float2* C, int64_t h, int64_t m, int64_t n, int64_t S,

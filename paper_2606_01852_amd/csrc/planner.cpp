@@ -678,10 +678,10 @@ std::unique_ptr<ChunkPlan> build_chunk(const Plan& plan, int j) {
     // that reads it
     sp.presplit = plan.prec == TNC_PREC_BF16X3 && sp.kind == GemmKernel::MFMA && sp.split == 1 && !sp.trans &&
                   d.h == 1 && sp.lm >= 4096 && sp.ln >= 4096;
-    // an operand leaf that is permuted anyway writes the 4M form's planes
-    // itself (the permute and the split in one pass) when rows are whole
-    // 16-k blocks
-    if (sp.presplit && plan.form == TNC_GEMM_4M && sp.k % 16 == 0 && row_stride(d) == sp.k)
+    // an operand leaf that is permuted anyway writes the planes itself (the
+    // permute and the split in one pass) when rows are whole blocks: 16 k
+    // in the 4M form, 32 real k (2 x 16 pairs) in the 3M form
+    if (sp.presplit && sp.k % (plan.form == TNC_GEMM_3M ? 32 : 16) == 0 && row_stride(d) == sp.k)
       for (int side = 1; side <= 2; ++side) {
         const int id = side == 1 ? sp.la : sp.lb;
         if (id >= n) continue;

@@ -287,20 +287,34 @@ def test_presplit_bf16x3_is_bitwise_the_wide_tile(ctx, order, leaves):
     print(f"presplit bf16x3 {order} {leaves}: err vs emulation {err:.2e}, bitwise = wide tile", flush=True)
 
 
-@pytest.mark.parametrize("kk", [200, 201], ids=["even_k", "odd_k"])
+PRESPLIT_3M_CASES = {
+    # extents, stored labels of A and of B
+    "even_k": ([64, 65, 66, 64, 200], (0, 1, 4), (2, 3, 4)),
+    "odd_k": ([64, 65, 66, 64, 201], (0, 1, 4), (2, 3, 4)),
+    "permuted": ([64, 65, 64, 66, 1024], (4, 1, 0), (4, 3, 2)),
+    "permuted_odd": ([66, 63, 63, 66, 1024], (4, 0, 1), (4, 3, 2)),
+}
+
+
+@pytest.mark.parametrize("case", list(PRESPLIT_3M_CASES))
 @pytest.mark.parametrize("order", ["natural", "interleaved"])
-def test_presplit_bf16x3_3m_is_bitwise_the_3m_tiles(ctx, order, kk):
+def test_presplit_bf16x3_3m_is_bitwise_the_3m_tiles(ctx, order, case):
     """Split precision in the 3M form on pre-split planes: one GEMM of
-    4160 x 4224 x kk (ragged against the tile; kk odd pads the last real k
+    4160 x 4224 x k (ragged against the tile; odd k pads the last real k
     pair) splits A and B once into their r, i and s planes, runs the three
     real products on the pre-split kernel and combines them with the step's
-    store (row-major or interleaved).  The result is bitwise that of the 3M
-    split tiles (variants 0 and 2 forced) and of its hipGraph replays,
-    within 1e-5 of the oracle's 3M split emulation, and every element within
-    twice the split bound of the exact product."""
+    store (row-major or interleaved).  With permuted leaves (k = 1024, over
+    the leaf cache's size) the leaf permutes write the planes themselves:
+    "permuted" through the 16-byte pair kernel, "permuted_odd" (input runs
+    of 63) through the element-wise one.  The result is bitwise that of the
+    3M split tiles (variants 0 and 2 forced, leaves permuted to complex64 as
+    usual) and of its hipGraph replays, within 1e-5 of the oracle's 3M split
+    emulation, and every element within twice the split bound of the exact
+    product."""
+    ext, la, lb = PRESPLIT_3M_CASES[case]
+    kk = ext[4]
     rng = np.random.Generator(np.random.PCG64(4161 + kk))
-    ext = np.array([64, 65, 66, 64, kk], dtype=np.int64)
-    la, lb = (0, 1, 4), (2, 3, 4)
+    ext = np.array(ext, dtype=np.int64)
 
     def cn(lab):
         shape = tuple(int(ext[l]) for l in lab)
@@ -309,10 +323,13 @@ def test_presplit_bf16x3_3m_is_bitwise_the_3m_tiles(ctx, order, kk):
     out = (0, 1, 2, 3) if order == "natural" else (0, 2, 1, 3)
     net = Network([cn(la), cn(lb)], [la, lb], ext, out)
     path = Path(np.array([[0, 1]], dtype=np.int32), ())
-    print(f"presplit bf16x3 3M {order} k={kk}", flush=True)
+    print(f"presplit bf16x3 3M {order} {case}", flush=True)
     z, plan, _ = run(ctx, net, path, prec=tnc.PREC_BF16X3, form=tnc.GEMM_3M)
     st = tnc.tnc_plan_get_step(plan.handle, 0)
-    assert st.kernel == 0 and st.presplit == 1 and st.split == 1 and st.presplit_fused == 0
+    permuted = case.startswith("permuted")
+    assert st.kernel == 0 and st.presplit == 1 and st.split == 1
+    assert st.presplit_fused == (3 if permuted else 0)      # both permutes write planes
+    assert plan.info.n_permutes == (2 if permuted else 0)
     assert st.natural == (1 if order == "natural" else 0)
     for v in (0, 2):
         tnc.tnc_ctx_set_gemm_variant(ctx.handle, v)
@@ -328,8 +345,8 @@ def test_presplit_bf16x3_3m_is_bitwise_the_3m_tiles(ctx, order, kk):
     emu = oc.contract(net, path, step=osp.split_step_3m)
     err = assert_close(z, emu, tol=1e-5, what="3M presplit vs emulation")
     e0, e1, e2, e3, _ = (int(x) for x in ext)
-    A = net.leaves[0].reshape(e0 * e1, kk).astype(np.complex128)
-    B = net.leaves[1].reshape(e2 * e3, kk).astype(np.complex128)
+    A = np.transpose(net.leaves[0], [la.index(x) for x in (0, 1, 4)]).reshape(e0 * e1, kk).astype(np.complex128)
+    B = np.transpose(net.leaves[1], [lb.index(x) for x in (2, 3, 4)]).reshape(e2 * e3, kk).astype(np.complex128)
     exact = (A @ B.T).reshape(e0, e1, e2, e3)
     bound = (2 * 3 * 2.0 ** -16 * ((np.abs(A.real) + np.abs(A.imag)) @ (np.abs(B.real) + np.abs(B.imag)).T)
              .reshape(e0, e1, e2, e3))
@@ -337,7 +354,7 @@ def test_presplit_bf16x3_3m_is_bitwise_the_3m_tiles(ctx, order, kk):
         exact = exact.transpose(0, 2, 1, 3)
         bound = bound.transpose(0, 2, 1, 3)
     assert np.all(np.abs(np.asarray(z) - exact) <= bound + 1e-6 * np.abs(exact))
-    print(f"presplit bf16x3 3M {order} k={kk}: err vs emulation {err:.2e}, bitwise = 3M tiles", flush=True)
+    print(f"presplit bf16x3 3M {order} {case}: err vs emulation {err:.2e}, bitwise = 3M tiles", flush=True)
 
 
 def interleaved_pair(z, a, b, c, d, k, seed):
