@@ -42,12 +42,12 @@ PEAK_HBM = 8000.0        # GB/s
 
 # Memory-side traffic per launch of the dominant kernel (4M GEMM, 4x4-wave
 # tiles, the 2^30-output contraction), from rocprofv3 --pmc FETCH_SIZE
-# (321,777,532 KiB, x2.0) and WRITE_SIZE (8,388,610 KiB, x1.0); the factors
+# (371,296,253 KiB, x2.0) and WRITE_SIZE (8,388,609 KiB, x1.0); the factors
 # are what the same counters read for a 4 GiB device copy.  FETCH_SIZE counts
-# every L2 miss (served by the MALL or HBM): with k = 2^14 the A/B panels of
-# the tiles running at once are re-read per K stage.  Set to None when the
-# kernel changes.
-GEMM_TRAFFIC_BYTES = 667.6e9
+# every L2 miss (served by the memory-side cache or HBM): with k = 2^14 the
+# A/B panels of the tiles running at once are re-read per K stage.  Set to
+# None when the kernel changes.
+GEMM_TRAFFIC_BYTES = 769.0e9
 
 
 def path_roofline_s(tnc, plan, n_runs: int = 1, leaf_permutes: bool = True) -> float:
