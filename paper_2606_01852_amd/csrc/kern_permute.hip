@@ -216,9 +216,18 @@ hipError_t launch_permute(const PermuteDesc& d, hipStream_t s) {
   while (ept * kPermThreads < d.T) ept *= 2;
   if (d.n_tiles >= 1024 && ept < 16) ept = 16;
   const size_t lds = static_cast<size_t>(d.slots) * sizeof(float2);
-  // many short-lived workgroups (a few tiles each); 131072 measured best
-  // among 8192 .. one per tile on pair30's operands
-  const int64_t grid = d.n_tiles < 131072 ? d.n_tiles : 131072;
+  // many short-lived workgroups of about 8192 elements (64 KiB) each: a
+  // few tiles per workgroup, so each loads its next tile while it stores
+  // the current one.  Measured: 131072 workgroups best among 8192 .. one
+  // per tile on pair30's 2^30-element operand (4096-element tiles); 1024-
+  // element tiles of 2^28 elements 0.94 -> 0.85 ms at 32768 instead of
+  // 131072, pair_batch's 64 operand permutes 0.164 -> 0.125 ms.  At least
+  // 1024 workgroups (or one per tile) so that small tensors stay spread
+  // over the chip.
+  int64_t grid = d.n_tiles * d.T / 8192;
+  if (grid < 1024) grid = 1024;
+  if (grid > d.n_tiles) grid = d.n_tiles;
+  if (grid > 131072) grid = 131072;
   // 16-byte pairs where the tables allow them and the base keeps them
   // aligned (standalone repeats of pair30's 2^30-element permutation:
   // 5.77 -> 5.92 TB/s; pair_batch's 64 operand permutes: 0.198 -> 0.165
