@@ -223,6 +223,7 @@ PRESPLIT_LEAVES = {
     "canonical": ([64, 65, 66, 64, 200], (0, 1, 4), (2, 3, 4)),
     "permuted": ([64, 65, 64, 66, 1024], (4, 1, 0), (4, 3, 2)),
     "permuted_odd": ([66, 63, 63, 66, 1024], (4, 0, 1), (4, 3, 2)),
+    "odd_mn": ([64, 65, 65, 65, 256], (0, 1, 4), (2, 3, 4)),   # n = 4225
 }
 
 
@@ -238,7 +239,8 @@ def test_presplit_bf16x3_is_bitwise_the_wide_tile(ctx, order, leaves):
     themselves (one pass), while the forced wide-wave run permutes them to
     complex64 as usual: "permuted" has even input runs (the 16-byte pair
     kernel), "permuted_odd" input runs of 63 elements (the element-wise
-    tiled kernel, 4158 x 4158 x 1024).  The result is bitwise that of the
+    tiled kernel, 4158 x 4158 x 1024); "odd_mn" an odd n (4160 x 4225 x
+    256).  The result is bitwise that of the
     wide-wave kernel (variant 3, forced) and of its hipGraph replays,
     within 1e-5 of the oracle's split emulation, and every element within
     the split bound of the exact product."""
@@ -258,8 +260,9 @@ def test_presplit_bf16x3_is_bitwise_the_wide_tile(ctx, order, leaves):
     st = tnc.tnc_plan_get_step(plan.handle, 0)
     assert st.kernel == 0 and st.presplit == 1 and st.split == 1
     assert st.natural == (1 if order == "natural" else 0)
-    assert plan.info.n_permutes == (0 if leaves == "canonical" else 2)
-    assert st.presplit_fused == (0 if leaves == "canonical" else 3)    # both permutes write planes
+    permuted = leaves.startswith("permuted")
+    assert plan.info.n_permutes == (2 if permuted else 0)
+    assert st.presplit_fused == (3 if permuted else 0)    # both permutes write planes
     tnc.tnc_ctx_set_gemm_variant(ctx.handle, 3)
     try:
         w, _, _ = run(ctx, net, path, prec=tnc.PREC_BF16X3)
@@ -293,6 +296,7 @@ PRESPLIT_3M_CASES = {
     "odd_k": ([64, 65, 66, 64, 201], (0, 1, 4), (2, 3, 4)),
     "permuted": ([64, 65, 64, 66, 1024], (4, 1, 0), (4, 3, 2)),
     "permuted_odd": ([66, 63, 63, 66, 1024], (4, 0, 1), (4, 3, 2)),
+    "odd_n": ([64, 65, 65, 65, 256], (0, 1, 4), (2, 3, 4)),   # n = 4225: T rows end in a padding column
 }
 
 
