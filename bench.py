@@ -1086,6 +1086,9 @@ def main():
             res["other_forms"][name] = {
                 "tflops": round(flops_step / fdt / 1e12, 3), "ms_per_step": round(fdt * 1e3, 3),
                 "gemm_tflops": round(gt, 3), "gemm_frac_of_executed_mfma_peak": round(executed, 4),
+                # the 8-FLOP complex convention against the form's precision
+                # peak (FP32 MFMA, or bf16 MFMA / 3 for split precision)
+                "gemm_frac_of_peak_8flop": round(gt / fpeak, 4),
                 "variant": tnc.tnc_plan_get_step(pa.handle, 0).variant,
                 "presplit": bool(tnc.tnc_plan_get_step(pa.handle, 0).presplit)}
             kept[name] = (out_a[:rows_a].cpu().numpy(), out_b[:rows_b].cpu().numpy())
