@@ -50,18 +50,23 @@ PEAK_HBM = 8000.0        # GB/s
 GEMM_TRAFFIC_BYTES = 769.0e9
 
 
-def path_roofline_s(tnc, plan, n_runs: int = 1, leaf_permutes: bool = True) -> float:
+def path_roofline_s(tnc, plan, n_runs: int = 1, leaf_permutes: bool = True, split: bool = False,
+                    three_m: bool = False) -> float:
     """The Sec. IV cost model as the path's roofline: every step of one
     device batch at max(its algorithmic bytes 8 (hA m k + hB n k + h m n) /
-    8 TB/s, its FLOPs 8 h m n k / 157.3 TFLOP/s), plus the leaf permutes at
-    16 bytes per element / 8 TB/s; times the number of batches run."""
+    8 TB/s, its MFMA work / the precision's peak), plus the leaf permutes at
+    16 bytes per element / 8 TB/s; times the number of batches run.  MFMA
+    work: 8 h m n k FLOP (6 h m n k executed in the 3M form) at 157.3
+    TFLOP/s, or at 2516.6 / 3 for split precision (three bf16 products per
+    real product)."""
     info = tnc.tnc_plan_get_info(plan.handle)
+    peak = (PEAK_BF16_MFMA / 3 if split else PEAK_FP32_MFMA) * 1e12
     t = 0.0
     for s in range(info.n_steps):
         st = tnc.tnc_plan_get_batch_step(plan.handle, s)
-        fl = 8.0 * st.h * st.m * st.n * st.k
+        fl = (6.0 if three_m else 8.0) * st.h * st.m * st.n * st.k
         by = 8.0 * (st.hA * st.m * st.k + st.hB * st.n * st.k + st.h * st.m * st.n)
-        t += max(by / (PEAK_HBM_TBS * 1e12), fl / (PEAK_FP32_MFMA * 1e12))
+        t += max(by / (PEAK_HBM_TBS * 1e12), fl / peak)
     if leaf_permutes:
         t += info.transpose_bytes / (PEAK_HBM_TBS * 1e12)
     return t * n_runs
@@ -548,11 +553,14 @@ def amplitude_query_leg(ctx, n_queries: int = 4096):
     return res
 
 
-def dominant_step(tnc, plan, n_runs: int = 1):
+def dominant_step(tnc, plan, split: bool = False, three_m: bool = False):
     """The step with the most profiled kernel time (profiling on, a run just
     done): its algorithmic bytes 8 (hA m k + hB n k + h m n) and FLOPs
-    8 h m n k per batch, what bounds it at MI355X peaks (HBM 8 TB/s, FP32
-    MFMA 157.3 TFLOP/s) and the achieved fraction of that bound."""
+    8 h m n k per batch, what bounds it at MI355X peaks (HBM 8 TB/s; MFMA:
+    FP32 157.3 TFLOP/s, or bf16 2516.6 / 3 for split precision, three bf16
+    products per real product) and the achieved fraction of that bound; for
+    the 3M form also the fraction in executed MFMA work (6 of the 8 FLOPs
+    per complex MAC)."""
     info = tnc.tnc_plan_get_info(plan.handle)
     best = None
     for s in range(info.n_steps):
@@ -566,13 +574,17 @@ def dominant_step(tnc, plan, n_runs: int = 1):
     per = ms / cnt * 1e-3
     fl = 8.0 * st.h * st.m * st.n * st.k
     by = 8.0 * (st.hA * st.m * st.k + st.hB * st.n * st.k + st.h * st.m * st.n)
-    mfma = fl / (PEAK_FP32_MFMA * 1e12) >= by / (PEAK_HBM_TBS * 1e12)
+    peak_mfma = PEAK_BF16_MFMA / 3 if split else PEAK_FP32_MFMA
+    mfma = fl / (peak_mfma * 1e12) >= by / (PEAK_HBM_TBS * 1e12)
     achieved = fl / per / 1e12 if mfma else by / per / 1e9
-    peak = PEAK_FP32_MFMA if mfma else PEAK_HBM
-    return {"step": s, "h": st.h, "m": st.m, "n": st.n, "k": st.k, "kernel": st.kernel, "variant": st.variant,
-            "ms_per_launch": round(per * 1e3, 4), "launches": cnt, "bound": "mfma" if mfma else "hbm",
-            "achieved": round(achieved, 3), "peak": peak, "unit": "TFLOP/s" if mfma else "GB/s",
-            "frac": round(achieved / peak, 4)}
+    peak = peak_mfma if mfma else PEAK_HBM
+    rec = {"step": s, "h": st.h, "m": st.m, "n": st.n, "k": st.k, "kernel": st.kernel, "variant": st.variant,
+           "ms_per_launch": round(per * 1e3, 4), "launches": cnt, "bound": "mfma" if mfma else "hbm",
+           "achieved": round(achieved, 3), "peak": round(peak, 1), "unit": "TFLOP/s" if mfma else "GB/s",
+           "frac": round(achieved / peak, 4)}
+    if mfma and three_m:
+        rec["frac_executed"] = round(achieved * 6 / 8 / peak, 4)
+    return rec
 
 
 def oracle_time(fn, reps: int = 3) -> float:
@@ -700,8 +712,8 @@ def record_grid8():
         tnc.tnc_plan_autotune(p2.handle)
         tnc.tnc_plan_set_profile(p2.handle, True)
         p2.contract()
-        dom = dominant_step(tnc, p2)
-        roof = path_roofline_s(tnc, p)
+        dom = dominant_step(tnc, p2, prec == tnc.PREC_BF16X3, form == tnc.GEMM_3M)
+        roof = path_roofline_s(tnc, p, split=prec == tnc.PREC_BF16X3, three_m=form == tnc.GEMM_3M)
         flops = p.info.flops_per_slice
         f = {"ms": round(dt * 1e3, 4), "tflops": round(flops / dt / 1e12, 3),
              "error_vs_oracle": abs(z - exact) / abs(exact), "path_roofline_frac": round(roof / dt, 4),
@@ -802,7 +814,7 @@ def circuit40_record(args, steps: int, warmup: int, with_cpu: bool):
         f = 8.0 * st.h * st.m * st.n * st.k * n_chunks
         log(f"  step {s:4d}: {ms:8.2f} ms  h {st.h} m {st.m} n {st.n} k {st.k} kernel {st.kernel} "
             f"variant {st.variant} split {st.split} swapped {st.swapped}: {f / ms / 1e9:.1f} TFLOP/s")
-    dom = dominant_step(tnc, prof)
+    dom = dominant_step(tnc, prof, prec == tnc.PREC_BF16X3, form == tnc.GEMM_3M)
     prof.close()
     exec_flops = info.chunk_flops * n_chunks if n % info.max_chunk == 0 else info.flops_per_slice * n
     value = exec_flops / dt / 1e12
@@ -815,7 +827,8 @@ def circuit40_record(args, steps: int, warmup: int, with_cpu: bool):
         if not st.natural:
             perm_steps += 1
             avoided += 16.0 * st.h * st.m * st.n * n_chunks
-    roof_s = path_roofline_s(tnc, plan, n_chunks, leaf_permutes=False)
+    roof_s = path_roofline_s(tnc, plan, n_chunks, leaf_permutes=False, split=prec == tnc.PREC_BF16X3,
+                             three_m=form == tnc.GEMM_3M)
     log(f"path roofline (GEMM steps of the batched run): {roof_s * 1e3:.1f} ms = {roof_s / dt:.3f} of the measured")
     # the same slices contracted one at a time (a chunk of one slice), the
     # per-slice loop whose cost the paper projects as t_slice * 2^b
@@ -1029,7 +1042,10 @@ def main():
                                "64 x (20 x 18 modes, 10 shared); extents 2; random stored mode orders",
                    "form": args.form, "prec": args.prec, "scale": args.scale,
                    "pct_fp32_mfma_peak": round(100 * value / PEAK_FP32_MFMA, 1),
-                   "path_roofline_frac": round((path_roofline_s(tnc, plan_a) + path_roofline_s(tnc, plan_b))
+                   "path_roofline_frac": round((path_roofline_s(tnc, plan_a, split=prec == tnc.PREC_BF16X3,
+                                                                three_m=form == tnc.GEMM_3M)
+                                                + path_roofline_s(tnc, plan_b, split=prec == tnc.PREC_BF16X3,
+                                                                  three_m=form == tnc.GEMM_3M))
                                                / (dt / args.steps), 4)},
         "roofline": {"bound": "mfma", "achieved": round(achieved, 3), "peak": round(peak, 1),
                      "unit": "TFLOP/s", "frac": round(achieved / peak, 4), "traffic": GEMM_TRAFFIC_BYTES},
