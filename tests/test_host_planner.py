@@ -211,6 +211,23 @@ def test_presplit_steps_and_their_plane_buffer(hctx):
         tn.close()
 
 
+def test_permutes_write_planes_only_for_whole_blocks(hctx):
+    """A pre-split step's permuted leaves (over the leaf cache's size) write
+    its planes themselves when their rows are whole plane blocks: k a
+    multiple of 16 in the 4M form (16 complex k per block), of 32 in the 3M
+    form (32 real k per block); otherwise they permute to complex64 and the
+    step splits them."""
+    for kk, want4, want3 in ((1024, 3, 3), (1040, 3, 0), (1000, 0, 0)):
+        ext = np.array([64, 65, 64, 66, kk], dtype=np.int64)
+        tn = tnc.Network(hctx, [(4, 1, 0), (4, 3, 2)], ext, (0, 1, 2, 3))
+        for form, want in ((tnc.GEMM_4M, want4), (tnc.GEMM_3M, want3)):
+            p = tnc.Plan(tn, np.array([[0, 1]], dtype=np.int32), (), tnc.PREC_BF16X3, form)
+            st = p.step(0)
+            assert (st.presplit, st.presplit_fused, p.info.n_permutes) == (1, want, 2), (kk, form)
+            p.close()
+        tn.close()
+
+
 def test_launch_counts_of_a_run(hctx):
     """n_launches counts the launches of one eager run: level grouping cuts
     them, a step-by-step run issues at least one per step plus the
