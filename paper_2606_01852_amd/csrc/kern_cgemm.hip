@@ -22,8 +22,13 @@
 // BF16x3: each float32 plane is split into bf16 hi/lo (round to nearest
 // even) while it is staged into LDS; every real product becomes
 // a_hi b_hi + (a_hi b_lo + a_lo b_hi) on bf16 MFMA with FP32 accumulation
-// (hi and cross terms in separate accumulators; in the wide-wave variant,
-// one accumulator).
+// (hi and cross terms in separate accumulators; in the wide-wave variant
+// and the 3M form, one accumulator per real product).  It composes with
+// both forms: 12 bf16 products per complex product in the 4M form, 9 in
+// the 3M form (the sum planes Ar+Ai, Br+Bi formed in float32, then split).
+// Large single GEMMs split their operands once into bf16 planes in global
+// memory instead and stage them straight into LDS (the pre-split section
+// below); in the 3M form as three real GEMMs plus a combining pass.
 //
 // Tiling.  A wave64 owns a 64 x 32 complex tile of C (2x2 MFMA 32x32 blocks
 // of the real view, or 2x1 complex blocks in 3M); a workgroup is WM x WN
